@@ -1,0 +1,45 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+Holds no part of the transform's arithmetic: only the input recipes, which
+follow the paper's experiments (Sec. 2.5, 3.1, 4.1 of Hale & Townsend):
+standard normal entries scaled to an algebraic decay (coefficients of the
+forward transform), analytic decay rho^n, and undecayed normal values (the
+inverse transform's input).  Generators are numpy PCG64 streams.
+"""
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def coeffs_algebraic(N: int, seed: int, power: float = 1.0, batch: int = 1) -> np.ndarray:
+    """c_n = s_n (n+1)^(-power), s_n iid N(0,1); shape (batch, N)."""
+    s = rng(seed).standard_normal((batch, N))
+    return s / (np.arange(N, dtype=np.float64) + 1.0) ** power
+
+
+def coeffs_analytic(N: int, seed: int, rho: float = 0.999, batch: int = 1) -> np.ndarray:
+    """c_n = rho^n s_n, s_n iid N(0,1); shape (batch, N)."""
+    s = rng(seed).standard_normal((batch, N))
+    return s * rho ** np.arange(N, dtype=np.float64)
+
+
+def values_normal(N: int, seed: int, batch: int = 1) -> np.ndarray:
+    """f_k iid N(0,1); shape (batch, N)."""
+    return rng(seed).standard_normal((batch, N))
+
+
+def sample_indices(N: int, count: int, seed: int) -> np.ndarray:
+    """Sorted distinct indices in [0, N), always including both ends."""
+    if count >= N:
+        return np.arange(N, dtype=np.int64)
+    idx = rng(seed).choice(N, size=count, replace=False)
+    idx[:2] = [0, N - 1]
+    return np.unique(idx).astype(np.int64)
+
+
+def log_uniform_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """N_i = round(exp(U[ln lo, ln hi])), the ragged-batch size mix."""
+    u = rng(seed).uniform(np.log(lo), np.log(hi), size=count)
+    return np.rint(np.exp(u)).astype(np.int64)
