@@ -1,0 +1,87 @@
+/*
+ * dlt.h -- C ABI of the MI355X (gfx950) fast discrete Legendre transform.
+ *
+ * Implements the transforms of N. Hale and A. Townsend, "A fast FFT-based
+ * discrete Legendre transform" (IMA J. Numer. Anal. 36 (2016)):
+ *
+ *   DLT   (eq. (1))  f_k = sum_{n<N} c_n P_n(x_k),                 0 <= k < N
+ *   IDLT  (eq. (2))  c_n = (n+1/2) sum_{k<N} w_k f_k P_n(x_k),     0 <= n < N
+ *   NDCT  (eq. (3))  f_k = sum_{n<N} chat_n T_n(x_k)
+ *   leg2cheb (Sec. 3, eq. (9))  chat = M c, the Legendre-to-Chebyshev
+ *         coefficient map, so that sum c_n P_n = sum chat_n T_n
+ *
+ * where x_k = cos(theta_k) are the roots of P_N ordered 1 > x_0 > ... >
+ * x_{N-1} > -1 (increasing theta_k) and w_k the Gauss-Legendre weights.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers to double, owned by the caller.
+ *     Inputs are never modified.  Outputs must not overlap inputs.
+ *   - Batched layout: instance b of a batch occupies elements [b*N, (b+1)*N)
+ *     (contiguous, batch-major).
+ *   - Calls are asynchronous on `stream` (0 = default stream); the library
+ *     does not synchronise.  Errors of kernels already enqueued surface as
+ *     DLT_ERR_HIP from a later call or from the caller's own synchronisation.
+ *   - batch == 0 is a no-op returning DLT_OK.
+ *   - Supported sizes: N a power of two with 1 <= N <= DLT_MAX_N (other N
+ *     return DLT_ERR_UNSUPPORTED).
+ *   - The library keeps per-N plans (twiddle and coefficient tables) and a
+ *     per-stream workspace; both are created on first use and live until
+ *     dlt_release() or process exit.
+ *   - FP64 arithmetic throughout.  Accuracy against the direct O(N^2)
+ *     definitions: max_k |f_k - f_k^exact| <= 5e-14 * sum_n |c_n| (DLT, NDCT);
+ *     max_n |c_n - c_n^exact| <= 5e-14 * (n+1/2) sum_k w_k |f_k| (IDLT).
+ *
+ * Status codes (int return value of every call)
+ */
+#ifndef DLT_H_
+#define DLT_H_
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DLT_OK 0
+#define DLT_ERR_INVALID_ARG (-1) /* N < 1, batch < 0, NULL pointer, overlapping in/out */
+#define DLT_ERR_UNSUPPORTED (-2) /* N not a power of two, or N > DLT_MAX_N */
+#define DLT_ERR_HIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define DLT_ERR_NOMEM (-4)       /* device workspace or plan tables could not be allocated */
+
+#define DLT_MAX_N (1LL << 22)
+
+/* Legendre nodes and weights (Sec. 1; theta form, Sec. 2.1-2.2).
+ * theta[k] = arccos(x_k) (increasing), w[k] = w_k, dtheta[k] =
+ * theta_k - (k+1/2) pi/N (offset from the Chebyshev points of the first kind,
+ * computed directly rather than by subtraction).  Any of the three outputs
+ * may be NULL to skip it; `batch` copies of each output are written. */
+int leg_nodes_weights(int64_t N, int64_t batch, double* theta, double* w, double* dtheta, hipStream_t stream);
+
+/* Legendre-to-Chebyshev coefficients chat = M c (Sec. 3, eq. (9)), c and chat
+ * each of length N per instance. */
+int leg2cheb(int64_t N, int64_t batch, const double* c, double* chat, hipStream_t stream);
+
+/* Chebyshev expansion sum_n chat_n T_n evaluated at the N Legendre nodes,
+ * eq. (3) (the "NDCT" of Sec. 2). */
+int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream);
+
+/* Discrete Legendre transform, eq. (1). */
+int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream);
+
+/* Inverse discrete Legendre transform, eq. (2) (Sec. 4). */
+int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream);
+
+/* Human-readable text of a status code (static storage). */
+const char* dlt_status_string(int status);
+
+/* Frees every cached plan and workspace (device memory).  Waits for the
+ * device to finish; the library may be used again afterwards. */
+int dlt_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DLT_H_ */

@@ -8,6 +8,8 @@ discrete Legendre transform":
                       decreasing as in eq. (1)) and Gauss-Legendre weights,
                       Newton's method in theta (Sec. 2.1-2.2).
   dlt(c, theta)       eq. (1)   f = sum_n c_n P_n(cos theta)
+                      (dlt/ndct/idlt accept theta_lo: the angle is then the
+                      two-double sum theta + theta_lo, honoured by prec="l")
   idlt(f, theta, w)   eq. (2)   c_n = (n+1/2) sum_k w_k f_k P_n(cos theta_k)
   ndct(chat, theta)   eq. (3)   f = sum_n chat_n cos(n theta)
   leg2cheb(c)         Sec. 3    chat = M c (dense, corrected M; see the C
@@ -41,9 +43,10 @@ def _load():
         lib = ctypes.CDLL(path)
         for p in ("d", "l"):
             getattr(lib, f"orc_nodes_{p}").argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _f64p, _f64p]
-            getattr(lib, f"orc_dlt_{p}").argtypes = [ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _f64p]
-            getattr(lib, f"orc_ndct_{p}").argtypes = [ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _f64p]
-            getattr(lib, f"orc_idlt_{p}").argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, ctypes.c_int64, _i64p, _f64p]
+            getattr(lib, f"orc_dlt_{p}").argtypes = [ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _f64p, _f64p]
+            getattr(lib, f"orc_ndct_{p}").argtypes = [ctypes.c_int64, _f64p, ctypes.c_int64, _f64p, _f64p, _f64p]
+            getattr(lib, f"orc_idlt_{p}").argtypes = [ctypes.c_int64, _f64p, _f64p, _f64p, _f64p, ctypes.c_int64,
+                                                      _i64p, _f64p]
             getattr(lib, f"orc_leg2cheb_{p}").argtypes = [ctypes.c_int64, _f64p, _f64p]
             getattr(lib, f"orc_leg2cheb_t_{p}").argtypes = [ctypes.c_int64, _f64p, _f64p]
             getattr(lib, f"orc_legendre_{p}").argtypes = [ctypes.c_int64, ctypes.c_double, _f64p]
@@ -81,25 +84,37 @@ def nodes(N, idx=None, prec="d"):
     return th, w
 
 
-def dlt(c, theta, prec="d"):
+def _lo(theta_lo, n):
+    if theta_lo is None:
+        return None, None
+    a, p = _d(theta_lo)
+    if len(a) != n:
+        raise ValueError("theta_lo must match theta")
+    return a, p
+
+
+def dlt(c, theta, prec="d", theta_lo=None):
     c, cp = _d(c)
     theta, tp = _d(theta)
+    lo, lp = _lo(theta_lo, len(theta))
     f = np.empty(len(theta))
-    _check(getattr(_load(), f"orc_dlt_{prec}")(len(c), cp, len(theta), tp, f.ctypes.data_as(_f64p)))
+    _check(getattr(_load(), f"orc_dlt_{prec}")(len(c), cp, len(theta), tp, lp, f.ctypes.data_as(_f64p)))
     return f
 
 
-def ndct(chat, theta, prec="d"):
+def ndct(chat, theta, prec="d", theta_lo=None):
     chat, cp = _d(chat)
     theta, tp = _d(theta)
+    lo, lp = _lo(theta_lo, len(theta))
     f = np.empty(len(theta))
-    _check(getattr(_load(), f"orc_ndct_{prec}")(len(chat), cp, len(theta), tp, f.ctypes.data_as(_f64p)))
+    _check(getattr(_load(), f"orc_ndct_{prec}")(len(chat), cp, len(theta), tp, lp, f.ctypes.data_as(_f64p)))
     return f
 
 
-def idlt(f, theta, w, idx=None, prec="d"):
+def idlt(f, theta, w, idx=None, prec="d", theta_lo=None):
     f, fp = _d(f)
     theta, tp = _d(theta)
+    lo, lp = _lo(theta_lo, len(theta))
     w, wp = _d(w)
     N = len(f)
     if idx is None:
@@ -108,7 +123,7 @@ def idlt(f, theta, w, idx=None, prec="d"):
         idx = np.ascontiguousarray(idx, dtype=np.int64)
         cnt, ip = len(idx), idx.ctypes.data_as(_i64p)
     c = np.empty(cnt)
-    _check(getattr(_load(), f"orc_idlt_{prec}")(N, fp, tp, wp, cnt, ip, c.ctypes.data_as(_f64p)))
+    _check(getattr(_load(), f"orc_idlt_{prec}")(N, fp, tp, lp, wp, cnt, ip, c.ctypes.data_as(_f64p)))
     return c
 
 

@@ -43,7 +43,10 @@
  * in theta from the equispaced guess theta^{cheb*}_k = (k+3/4) pi/(N+1/2) of
  * Sec. 2.2, which Lemma 2 places within 1/(3 pi (2N+1)) of the root, using
  * dP_N/dtheta = N (x P_N - P_{N-1}) / sin(theta), until the step is below
- * one ulp.  Weight w_k = 2/(dP_N/dtheta)^2 = 2 sin^2(theta_k)/(N P_{N-1})^2.
+ * one ulp.  Weight w_k = 2/(dP_N/dtheta)^2 = 2/((1-x^2) P_N'(x)^2), with the
+ * derivative from the same identity evaluated at the final theta (P_N there
+ * is kept rather than set to zero, which keeps the weight well conditioned
+ * near x = +-1 where P_{N-1} is small).
  * Both builds (_d and _l) use the x87 extended-precision recurrence here:
  * the FP64 recurrence loses about N*eps relative accuracy in P_{N-1}, which
  * the weight would inherit.  Results are rounded to double once at the end.
@@ -80,8 +83,9 @@ static void node_half_ld(int64_t N, int64_t k, LD *theta, LD *w) {
     }
     leg_pair_ld(N, t, &pN, &pN1);
     LD st = sinl(t);
+    LD q = (LD)N * (cosl(t) * pN - pN1);
     *theta = t;
-    *w = 2 * st * st / (((LD)N * pN1) * ((LD)N * pN1));
+    *w = 2 * st * st / (q * q);
 }
 
 static int nodes_impl(int64_t N, int64_t nidx, const int64_t *idx, double *theta, double *w) {

@@ -34,6 +34,11 @@
  * x = cos(theta) loses accuracy near x = +-1.  For pi/4 < theta' <= pi/2 the
  * textbook recurrence in x is used, which rounds less there.
  *
+ * Angles are passed as theta (+ optional theta_lo, the low part of a
+ * two-double angle theta + theta_lo; NULL means zero), so an evaluation
+ * point known to better than double precision can be honoured by the
+ * extended build.
+ *
  * Parity status of each routine is recorded in the test-suite; every
  * routine here is pinned by at least one test that does not re-run this
  * code's own formula (closed forms, textbook values, library routines,
@@ -75,11 +80,12 @@ static void FN(leg_row)(int64_t N, REAL t, REAL *P) {
 /* f_i = sum_{n<N} c_n P_n(cos theta_i), eq. (1).  For theta' <= pi/4 the
  * recurrence runs in u = 1 - x (Reinsch form); between pi/4 and pi/2 the
  * textbook form in x is used, which rounds less there. */
-int FN(orc_dlt)(int64_t N, const double *c, int64_t nt, const double *theta, double *f) {
+int FN(orc_dlt)(int64_t N, const double *c, int64_t nt, const double *theta, const double *theta_lo,
+                double *f) {
     if (N < 1) return -1;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < nt; ++i) {
-        REAL t = theta[i];
+        REAL t = (REAL)theta[i] + (theta_lo ? (REAL)theta_lo[i] : (REAL)0);
         int flip = t > PI_R / 2;
         REAL tt = flip ? PI_R - t : t;
         REAL acc = (REAL)c[0];
@@ -113,11 +119,12 @@ int FN(orc_dlt)(int64_t N, const double *c, int64_t nt, const double *theta, dou
 /* f_i = sum_{n<N} chat_n cos(n theta_i), eqs. (3)-(4), by the Chebyshev
  * recurrence T_{n+1} = 2x T_n - T_{n-1}; for theta' <= pi/4 in the form
  * T_{n+1} - T_n = (T_n - T_{n-1}) - 2u T_n with u = 1 - x. */
-int FN(orc_ndct)(int64_t N, const double *chat, int64_t nt, const double *theta, double *f) {
+int FN(orc_ndct)(int64_t N, const double *chat, int64_t nt, const double *theta, const double *theta_lo,
+                 double *f) {
     if (N < 1) return -1;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < nt; ++i) {
-        REAL t = theta[i];
+        REAL t = (REAL)theta[i] + (theta_lo ? (REAL)theta_lo[i] : (REAL)0);
         int flip = t > PI_R / 2;
         REAL tt = flip ? PI_R - t : t;
         REAL acc = (REAL)chat[0];
@@ -155,8 +162,8 @@ int FN(orc_ndct)(int64_t N, const double *chat, int64_t nt, const double *theta,
 /* c_n = (n+1/2) sum_k w_k f_k P_n(cos theta_k), eq. (2), for the requested
  * degrees n (all N if idx == NULL).  One recurrence per node, accumulated
  * per degree ("along rows", Sec. 4.1). */
-int FN(orc_idlt)(int64_t N, const double *f, const double *theta, const double *w,
-                 int64_t nidx, const int64_t *idx, double *c) {
+int FN(orc_idlt)(int64_t N, const double *f, const double *theta, const double *theta_lo,
+                 const double *w, int64_t nidx, const int64_t *idx, double *c) {
     if (N < 1) return -1;
     int64_t cnt = idx ? nidx : N;
     int64_t nmax = 0;
@@ -183,7 +190,7 @@ int FN(orc_idlt)(int64_t N, const double *f, const double *theta, const double *
         int64_t k0 = N * tid / nth, k1 = N * (tid + 1) / nth;
         for (int64_t k = k0; k < k1; ++k) {
             REAL g = (REAL)w[k] * (REAL)f[k];
-            REAL t = theta[k];
+            REAL t = (REAL)theta[k] + (theta_lo ? (REAL)theta_lo[k] : (REAL)0);
             int flip = t > PI_R / 2;
             REAL tt = flip ? PI_R - t : t;
             REAL sg = 1;

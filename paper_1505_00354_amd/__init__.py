@@ -1,0 +1,130 @@
+"""MI355X (gfx950) fast discrete Legendre transform -- Python binding.
+
+Thin ctypes marshalling over the C ABI in include/dlt.h (libdlt.so, built
+in-tree by paper_1505_00354_amd.build).  Every transform runs in the HIP
+kernels of that library; this module only passes device pointers, sizes and
+the current PyTorch stream.  If the library is missing, every call raises.
+
+Tensors are torch.float64 CUDA (ROCm) tensors, contiguous, with the transform
+length N as the last dimension; leading dimensions form the batch.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdlt.so")
+
+DLT_OK = 0
+DLT_ERR_INVALID_ARG = -1
+DLT_ERR_UNSUPPORTED = -2
+DLT_ERR_HIP = -3
+DLT_ERR_NOMEM = -4
+DLT_MAX_N = 1 << 22
+
+_lib = None
+
+
+class DLTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+def lib():
+    """The loaded libdlt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} not found: build the HIP library first "
+                "(python -m paper_1505_00354_amd.build or __graft_entry__.build())"
+            )
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp = ctypes.c_int64, ctypes.c_void_p
+        L.leg_nodes_weights.argtypes = [i64, i64, vp, vp, vp, vp]
+        L.leg2cheb.argtypes = [i64, i64, vp, vp, vp]
+        L.cheb_eval_leggrid.argtypes = [i64, i64, vp, vp, vp]
+        L.dlt_forward.argtypes = [i64, i64, vp, vp, vp]
+        L.dlt_inverse.argtypes = [i64, i64, vp, vp, vp]
+        L.dlt_status_string.argtypes = [ctypes.c_int]
+        L.dlt_status_string.restype = ctypes.c_char_p
+        L.dlt_release.argtypes = []
+        for name in ("leg_nodes_weights", "leg2cheb", "cheb_eval_leggrid", "dlt_forward", "dlt_inverse",
+                     "dlt_release"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st, what):
+    if st != DLT_OK:
+        raise DLTError(st, f"{what}: {lib().dlt_status_string(st).decode()} (status {st})")
+
+
+def _stream(dev=None):
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _vec_args(x, out):
+    import torch
+
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
+        raise TypeError("expected a float64 CUDA tensor")
+    if not x.is_contiguous():
+        raise ValueError("input must be contiguous")
+    N = x.shape[-1]
+    batch = x.numel() // N if N else 0
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must match the input's shape, dtype and device and be contiguous")
+    return N, batch, out
+
+
+def leg_nodes_weights(N, device=None, batch=1, theta=True, w=True, dtheta=True):
+    """(theta, w, dtheta) tensors of shape (batch, N) (None where not asked)."""
+    import torch
+
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    mk = lambda want: torch.empty((batch, N), dtype=torch.float64, device=dev) if want else None
+    t, ww, d = mk(theta), mk(w), mk(dtheta)
+    ptr = lambda a: ctypes.c_void_p(a.data_ptr()) if a is not None else None
+    with torch.cuda.device(dev):
+        _check(lib().leg_nodes_weights(N, batch, ptr(t), ptr(ww), ptr(d), _stream(dev)), "leg_nodes_weights")
+    return t, ww, d
+
+
+def _unary(name, x, out):
+    import torch
+
+    N, batch, out = _vec_args(x, out)
+    with torch.cuda.device(x.device):
+        _check(getattr(lib(), name)(N, batch, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    _stream(x.device)), name)
+    return out
+
+
+def leg2cheb(c, out=None):
+    """Chebyshev coefficients of sum_n c_n P_n (chat = M c)."""
+    return _unary("leg2cheb", c, out)
+
+
+def cheb_eval_leggrid(chat, out=None):
+    """sum_n chat_n T_n at the N Legendre nodes."""
+    return _unary("cheb_eval_leggrid", chat, out)
+
+
+def dlt_forward(c, out=None):
+    """Discrete Legendre transform f_k = sum_n c_n P_n(x_k)."""
+    return _unary("dlt_forward", c, out)
+
+
+def dlt_inverse(f, out=None):
+    """Inverse transform c_n = (n+1/2) sum_k w_k f_k P_n(x_k)."""
+    return _unary("dlt_inverse", f, out)
+
+
+def release():
+    _check(lib().dlt_release(), "dlt_release")

@@ -1,0 +1,234 @@
+// C ABI: argument validation, plan and workspace caches, and the order in
+// which the pipelines are enqueued.  Declared in include/dlt.h.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <utility>
+
+#include "../../include/dlt.h"
+#include "dlt_kernels.hpp"
+
+using namespace dlt;
+
+namespace {
+
+struct Cache {
+    std::mutex mu;
+    std::map<std::pair<int, int64_t>, std::unique_ptr<Plan>> plans;  // (device, N)
+    struct WS {
+        void* ptr = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::pair<int, hipStream_t>, WS> ws;  // (device, stream)
+};
+
+Cache& cache() {
+    static Cache* c = new Cache();  // never destroyed: device memory goes with the process
+    return *c;
+}
+
+const size_t WS_CAP = size_t(6) << 30;  // per-stream workspace bound; larger batches run in slices
+
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int check_size(int64_t N, int64_t batch) {
+    if (N < 1 || batch < 0) return DLT_ERR_INVALID_ARG;
+    if (N > DLT_MAX_N || !is_pow2(N)) return DLT_ERR_UNSUPPORTED;
+    return DLT_OK;
+}
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+int get_plan(int64_t N, Plan** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto key = std::make_pair(dev, N);
+    auto it = c.plans.find(key);
+    if (it != c.plans.end()) {
+        *out = it->second.get();
+        return DLT_OK;
+    }
+    std::unique_ptr<Plan> p(new Plan());
+    int rc = plan_build(N, *p);
+    if (rc != DLT_OK) {
+        plan_free(*p);
+        return rc;
+    }
+    *out = p.get();
+    c.plans[key] = std::move(p);
+    return DLT_OK;
+}
+
+// workspace of at least `bytes` ordered on `s`
+int get_ws(hipStream_t s, size_t bytes, void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    Cache::WS& w = c.ws[std::make_pair(dev, s)];
+    if (w.bytes < bytes) {
+        if (w.ptr) {
+            // earlier work on this stream may still read the old buffer
+            if (hipStreamSynchronize(s) != hipSuccess) return DLT_ERR_HIP;
+            if (hipFree(w.ptr) != hipSuccess) return DLT_ERR_HIP;
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        if (hipMalloc(&w.ptr, bytes) != hipSuccess) {
+            w.ptr = nullptr;
+            return DLT_ERR_NOMEM;
+        }
+        w.bytes = bytes;
+    }
+    *out = w.ptr;
+    return DLT_OK;
+}
+
+// node arrays shared by a call: [theta | w | dtheta] after the per-instance part
+struct CallWS {
+    Work work;
+    double* theta;
+    double* w;
+    double* dth;
+    int64_t nb;  // instances per slice
+};
+
+int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
+    size_t per = p.ws_per_inst;
+    int64_t nb = batch;
+    if (per > 0 && (size_t)nb * per > WS_CAP) nb = (int64_t)(WS_CAP / per);
+    if (nb < 1) nb = 1;
+    size_t shared = p.ws_shared;
+    void* base = nullptr;
+    int rc = get_ws(s, shared + work_bytes(p, nb), &base);
+    if (rc) return rc;
+    size_t vecb = ((size_t)p.N * sizeof(double) + 255) & ~size_t(255);
+    cw.theta = (double*)base;
+    cw.w = (double*)((char*)base + vecb);
+    cw.dth = (double*)((char*)base + 2 * vecb);
+    work_carve(p, nb, (char*)base + shared, cw.work);
+    cw.nb = nb;
+    return DLT_OK;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? DLT_OK : DLT_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+const char* dlt_status_string(int st) {
+    switch (st) {
+        case DLT_OK: return "ok";
+        case DLT_ERR_INVALID_ARG: return "invalid argument";
+        case DLT_ERR_UNSUPPORTED: return "unsupported size";
+        case DLT_ERR_HIP: return "HIP runtime error";
+        case DLT_ERR_NOMEM: return "out of device memory";
+        default: return "unknown status";
+    }
+}
+
+int leg_nodes_weights(int64_t N, int64_t batch, double* theta, double* w, double* dtheta, hipStream_t stream) {
+    int rc = check_size(N, batch);
+    if (rc) return rc;
+    if (batch == 0 || (!theta && !w && !dtheta)) return DLT_OK;
+    size_t bytes = (size_t)N * sizeof(double) * (size_t)batch;
+    if ((theta && w && overlap(theta, w, bytes)) || (theta && dtheta && overlap(theta, dtheta, bytes)) ||
+        (w && dtheta && overlap(w, dtheta, bytes)))
+        return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan(N, &p))) return rc;
+    if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, stream)))) return rc;
+    for (int64_t b = 1; b < batch; ++b) {
+        size_t vb = (size_t)N * sizeof(double);
+        if (theta && hipMemcpyAsync(theta + b * N, theta, vb, hipMemcpyDeviceToDevice, stream)) return DLT_ERR_HIP;
+        if (w && hipMemcpyAsync(w + b * N, w, vb, hipMemcpyDeviceToDevice, stream)) return DLT_ERR_HIP;
+        if (dtheta && hipMemcpyAsync(dtheta + b * N, dtheta, vb, hipMemcpyDeviceToDevice, stream))
+            return DLT_ERR_HIP;
+    }
+    return DLT_OK;
+}
+
+int leg2cheb(int64_t N, int64_t batch, const double* c, double* chat, hipStream_t stream) {
+    int rc = check_size(N, batch);
+    if (rc) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!c || !chat || overlap(c, chat, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan(N, &p))) return rc;
+    CallWS cw;
+    if ((rc = setup_call(*p, batch, stream, cw))) return rc;
+    for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+        int64_t nb = std::min(cw.nb, batch - b0);
+        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, chat + b0 * N, cw.work, stream)))) return rc;
+    }
+    return DLT_OK;
+}
+
+int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream) {
+    int rc = check_size(N, batch);
+    if (rc) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!chat || !f || overlap(chat, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan(N, &p))) return rc;
+    CallWS cw;
+    if ((rc = setup_call(*p, batch, stream, cw))) return rc;
+    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, stream)))) return rc;
+    for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+        int64_t nb = std::min(cw.nb, batch - b0);
+        if ((rc = hip_status(run_ndct(*p, nb, chat + b0 * N, cw.dth, f + b0 * N, cw.work, stream)))) return rc;
+    }
+    return DLT_OK;
+}
+
+int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream) {
+    int rc = check_size(N, batch);
+    if (rc) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!c || !f || overlap(c, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan(N, &p))) return rc;
+    CallWS cw;
+    if ((rc = setup_call(*p, batch, stream, cw))) return rc;
+    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, stream)))) return rc;
+    for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+        int64_t nb = std::min(cw.nb, batch - b0);
+        // Chebyshev coefficients of the slice, stride N, in the workspace
+        double* chat = cw.work.chat;
+        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, chat, cw.work, stream)))) return rc;
+        if ((rc = hip_status(run_ndct(*p, nb, chat, cw.dth, f + b0 * N, cw.work, stream)))) return rc;
+    }
+    return DLT_OK;
+}
+
+int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
+    int rc = check_size(N, batch);
+    if (rc) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!f || !c || overlap(f, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    return DLT_ERR_UNSUPPORTED;
+}
+
+int dlt_release(void) {
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (hipDeviceSynchronize() != hipSuccess) return DLT_ERR_HIP;
+    for (auto& kv : c.plans) plan_free(*kv.second);
+    c.plans.clear();
+    for (auto& kv : c.ws)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    c.ws.clear();
+    return DLT_OK;
+}
+
+}  // extern "C"

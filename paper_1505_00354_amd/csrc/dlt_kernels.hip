@@ -1,0 +1,793 @@
+// Kernels of the fast discrete Legendre transform (Hale & Townsend):
+//   nodes      Legendre nodes/weights and dtheta = theta^leg - theta^cheb1
+//   dense      exact Legendre-to-Chebyshev conversion of the low columns
+//   far A/B    asymptotic (Stieltjes) blocks of the conversion, one length-N
+//              DFT per (block, term), two passes through HBM
+//   near       direct three-term recurrence where the expansion is invalid
+//   dct2 A/B   values on the Chebyshev grid -> Chebyshev coefficients
+//   ndct A/B   Taylor-series evaluation at the Legendre nodes (Sec. 2),
+//              two Taylor terms per complex DFT, Horner combine per node
+// Grid notation: theta_j = (j+1/2) pi / N, j in [0, N).  A length-N complex
+// DFT with + sign, output index m, covers row j(m) = 2m (m < N/2) or
+// 2N-1-2m (m >= N/2); this is how sums over e^{i n theta_j} are formed.
+#include "dlt_kernels.hpp"
+
+namespace dlt {
+
+__device__ __forceinline__ int row_of(int m, int N) { return (2 * m < N) ? 2 * m : 2 * N - 1 - 2 * m; }
+
+// e^{i pi n/(2N)}
+__device__ __forceinline__ cplx half_shift(int64_t n, int N) {
+    double s, c;
+    sincospi((double)n / (2.0 * N), &s, &c);
+    return {c, s};
+}
+
+// ------------------------------------------------------------------ nodes --
+// Interior nodes k in [kb, ceil(N/2)): Newton in delta = theta - theta*_k
+// (theta*_k = (k+1/2)pi/N) on the M-term Stieltjes expansion of P_N(cos theta)
+// with the large phase (N+m+1/2) theta reduced exactly:
+//   (N+m+1/2) theta*_k - (m+1/2) pi/2 = (k+1/2) pi + (m+1/2)(theta*_k - pi/2),
+// so cos(phase) = -(-1)^k sin psi_m, sin(phase) = (-1)^k cos psi_m with
+// psi_m = (m+1/2)(theta - pi/2) + N delta.
+__global__ void k_nodes_interior(NodeParams P, double* __restrict__ theta, double* __restrict__ w,
+                                 double* __restrict__ dth) {
+    const int N = P.N;
+    const int nh = (N + 1) / 2;
+    int k = P.kb + blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nh) return;
+    const double pi = 3.141592653589793;
+    // theta^cheb* - theta^cheb1 = pi (N - 2k - 1) / (4 N (N + 1/2))
+    double delta = pi * (double)(N - 2 * k - 1) / (4.0 * N * (N + 0.5));
+    // theta*_k - pi/2 = pi (2k + 1 - N) / (2N)
+    const double a0 = pi * (double)(2 * k + 1 - N) / (2.0 * N);
+    const double ts = (k + 0.5) * pi / N;
+    double Pv = 0, Dv = 0, s2 = 1;
+    for (int it = 0; it <= 5; ++it) {
+        double th = ts + delta;
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        s2 = 2.0 * sn;
+        double cot = cs / sn;
+        double q = 1.0 / s2;
+        // psi_0 and the per-term increment theta - pi/2
+        double dlt = a0 + delta;  // theta - pi/2
+        double ps, pc, rs, rc;
+        sincos(0.5 * dlt + N * delta, &ps, &pc);
+        sincos(dlt, &rs, &rc);
+        double r = sqrt(q);
+        Pv = 0;
+        Dv = 0;
+#pragma unroll 4
+        for (int m = 0; m < P.Ms; ++m) {
+            double hm = P.h[m] * r;
+            Pv = fma(hm, ps, Pv);
+            Dv = fma(hm, (N + m + 0.5) * pc - (m + 0.5) * ps * cot, Dv);
+            // psi_{m+1} = psi_m + (theta - pi/2)
+            double nps = ps * rc + pc * rs;
+            double npc = pc * rc - ps * rs;
+            ps = nps;
+            pc = npc;
+            r *= q;
+        }
+        if (it < 5) delta -= Pv / Dv;
+    }
+    // dP/dtheta = -(-1)^k C D;  w = 2 / (dP/dtheta)^2
+    double dP = P.C * Dv;
+    double wk = 2.0 / (dP * dP);
+    double th = ts + delta;
+    int k2 = N - 1 - k;
+    if (theta) {
+        theta[k] = th;
+        if (k2 != k) theta[k2] = pi - th;
+    }
+    if (w) {
+        w[k] = wk;
+        if (k2 != k) w[k2] = wk;
+    }
+    if (dth) {
+        dth[k] = delta;
+        if (k2 != k) dth[k2] = -delta;
+    }
+}
+
+// P_N(cos t), P_{N-1}(cos t) and the Christoffel sum K = sum_{n<N} (2n+1) P_n^2
+// for 0 < t <= pi/2, by the recurrence in u = 2 sin^2(t/2),
+//   D_{n+1} = (n D_n - (2n+1) u P_n)/(n+1),  P_{n+1} = P_n + D_{n+1},
+// split over the block: each thread runs its chunk of degrees for the two
+// basis states (P, D) = (1, 0) and (0, 1) (the first chunk from the true
+// start), keeping the chunk's transfer matrix and the quadratic sums
+// sum (2n+1) Pa^2, sum (2n+1) Pa Pb, sum (2n+1) Pb^2; the chunks are then
+// chained in order.  `sh` holds 7*blockDim.x + 3 doubles.
+__device__ void block_legendre_pair(int N, double t, const double* __restrict__ A,
+                                    const double* __restrict__ B, double* sh, double* pN, double* pN1,
+                                    double* kc) {
+    const int T = blockDim.x, tid = threadIdx.x;
+    double s = sin(0.5 * t);
+    double u = 2.0 * s * s;
+    int C = (N + T - 1) / T;
+    int n0 = tid * C, n1 = min(N, n0 + C);
+    double pa = 1, da = 0, pb = 0, db = 1;
+    double saa = 0, sab = 0, sbb = 0;
+    for (int n = n0; n < n1; ++n) {
+        double wgt = 2.0 * n + 1.0;
+        saa = fma(wgt * pa, pa, saa);
+        sab = fma(wgt * pa, pb, sab);
+        sbb = fma(wgt * pb, pb, sbb);
+        double bu = B[n] * u;
+        double dna = fma(A[n], da, -bu * pa);
+        double dnb = fma(A[n], db, -bu * pb);
+        pa += dna;
+        da = dna;
+        pb += dnb;
+        db = dnb;
+    }
+    double* q = sh + 7 * tid;
+    q[0] = pa;
+    q[1] = da;
+    q[2] = pb;
+    q[3] = db;
+    q[4] = saa;
+    q[5] = sab;
+    q[6] = sbb;
+    __syncthreads();
+    if (tid == 0) {
+        double P = 1, D = 0, K = 0;  // state at n = 0 (D_0 does not enter)
+        int nthr = min(T, (N + C - 1) / C);
+        for (int i = 0; i < nthr; ++i) {
+            const double* r = sh + 7 * i;
+            K += P * P * r[4] + 2.0 * P * D * r[5] + D * D * r[6];
+            double Pn = r[0] * P + r[2] * D;
+            double Dn = r[1] * P + r[3] * D;
+            P = Pn;
+            D = Dn;
+        }
+        sh[7 * T] = P;
+        sh[7 * T + 1] = P - D;
+        sh[7 * T + 2] = K;
+    }
+    __syncthreads();
+    *pN = sh[7 * T];
+    *pN1 = sh[7 * T + 1];
+    *kc = sh[7 * T + 2];
+    __syncthreads();
+}
+
+// Boundary nodes k < kb.  The start `guess` (offset from theta*_k) is the
+// Bessel-zero form theta ~ psi + (psi cot psi - 1)/(8 psi nu^2), psi =
+// j_{0,k+1}/nu, nu = N + 1/2, whose error is O(nu^-4) (one ulp from
+// N = 4096 on), or theta^cheb* for small N; `newton_b` Newton steps with the
+// exact recurrence follow (none for large N, where the FP64 recurrence is
+// less accurate than the start).  The weight is the Christoffel number
+// w_k = 2 / sum_{n<N} (2n+1) P_n(x_k)^2, which is well conditioned in x_k.
+__global__ void k_nodes_boundary(NodeParams P, const double* __restrict__ guess, const double* __restrict__ A,
+                                 const double* __restrict__ B, double* __restrict__ theta,
+                                 double* __restrict__ w, double* __restrict__ dth) {
+    extern __shared__ double sh[];
+    const int N = P.N;
+    const int k = blockIdx.x;
+    const double pi = 3.141592653589793;
+    const double ts = (k + 0.5) * pi / N;
+    double delta = guess[k];
+    double pN, pN1, kc;
+    const bool middle = (N & 1) && (k == (N - 1) / 2);
+    if (middle) {
+        delta = 0;  // x = 0 is a root of odd-degree P_N and theta*_k = pi/2 there
+    } else {
+        for (int it = 0; it < P.newton_b; ++it) {
+            double th = ts + delta;
+            block_legendre_pair(N, th, A, B, sh, &pN, &pN1, &kc);
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            double dP = N * (cs * pN - pN1) / sn;
+            double step = pN / dP;
+            delta -= step;
+            if (fabs(step) <= 2.2e-16 * th) break;  // uniform across the block
+        }
+    }
+    double th = ts + delta;
+    block_legendre_pair(N, th, A, B, sh, &pN, &pN1, &kc);
+    if (threadIdx.x == 0) {
+        double wk = 2.0 / kc;
+        int k2 = N - 1 - k;
+        if (theta) {
+            theta[k] = th;
+            if (k2 != k) theta[k2] = pi - th;
+        }
+        if (w) {
+            w[k] = wk;
+            if (k2 != k) w[k2] = wk;
+        }
+        if (dth) {
+            dth[k] = delta;
+            if (k2 != k) dth[k2] = -delta;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ dense --
+// chat_k (k < nd) partial sums over column chunk blockIdx.y:
+//   sum_{n in chunk, n >= k, n+k even} (eps_k/pi) Lam((n-k)/2) Lam((n+k)/2) c_n
+__global__ void k_dense(int N, int nd, int chunk, const double* __restrict__ lam, const double* __restrict__ c,
+                        int64_t c_stride, double* __restrict__ part, int64_t part_stride) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    int ch = blockIdx.y;
+    int b = blockIdx.z;
+    const double* cb = c + b * c_stride;
+    double* pb = part + b * part_stride;
+    if (k >= nd) return;
+    int n0 = ch * chunk, n1 = min(nd, n0 + chunk);
+    double acc = 0;
+    int n = max(n0, k);
+    if ((n - k) & 1) ++n;
+    for (; n < n1; n += 2) acc = fma(lam[(n - k) >> 1] * lam[(n + k) >> 1], cb[n], acc);
+    double e = (k == 0) ? 0.3183098861837907 : 0.6366197723675814;  // eps_k / pi
+    pb[(int64_t)ch * nd + k] = e * acc;
+}
+
+// dense[k] = sum over chunks; written to `out` (stride per instance)
+__global__ void k_dense_reduce(int nd, int nchunk, int chunk, const double* __restrict__ part,
+                               int64_t part_stride, double* __restrict__ out, int64_t out_stride) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.z;
+    if (k >= nd) return;
+    const double* pb = part + b * part_stride;
+    double s = 0;
+    for (int ch = k / chunk; ch < nchunk; ++ch) s += pb[(int64_t)ch * nd + k];
+    out[b * out_stride + k] = s;
+}
+
+// ------------------------------------------------------ FFT pass helpers --
+// Pass A: the block owns columns n_a in [na0, na0+colsA); element e of the
+// tile is (col = e % colsA, n_b = e / colsA), n = na0 + col + N1 n_b.
+// After the in-LDS length-N2 DFTs the tile holds buf[col*N2 + j_b]; it is
+// multiplied by e^{2 pi i n_a j_b / N} and written to X[n_a*N2 + j_b].
+__device__ __forceinline__ void passA_store(const Geo& g, const cplx* buf, int na0, cplx* __restrict__ X) {
+    const int tot = g.colsA * g.N2;
+    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+        int col = e / g.N2, jb = e - col * g.N2;
+        int na = na0 + col;
+        cplx v = buf[e];
+        if (na && jb) v = cmul(v, tw2(g.twHi, g.twLo, (int64_t)na * jb, g.sh));
+        X[(int64_t)na * g.N2 + jb] = v;
+    }
+}
+
+// Pass B: the block owns rows j_b in [jb0, jb0+rowsB); LDS holds
+// buf[r*N1 + n_a]; after the length-N1 DFTs, buf[r*N1 + j_a] is output
+// m = jb0 + r + N2 j_a.
+__device__ __forceinline__ void passB_load(const Geo& g, cplx* buf, int jb0, const cplx* __restrict__ X) {
+    const int tot = g.rowsB * g.N1;
+    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+        int r = e % g.rowsB, na = e / g.rowsB;
+        buf[r * g.N1 + na] = X[(int64_t)na * g.N2 + jb0 + r];
+    }
+}
+
+// ---------------------------------------------------------- far field A --
+// For every term t = (block b, m), in descending m so that
+// h_{m-1,n} = h_{m,n} m (n+m+1/2)/(m-1/2)^2 needs no division, the DFT input
+//   b_n = C_n h_{m,n} c_n e^{i pi n/(2N)} [n >= nlo_b]
+// goes through pass A of the length-N DFT.
+__global__ __launch_bounds__(FFT_THREADS) void k_far_passA(Geo g, FarParams F, const double* __restrict__ c,
+                                                          int64_t c_stride, cplx* __restrict__ X,
+                                                          int64_t x_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int na0 = blockIdx.x * g.colsA;
+    const int b = blockIdx.z;
+    const double* cb = c + b * c_stride;
+    cplx* Xb = X + b * x_stride;
+    const int tot = g.colsA * g.N2;
+    cplx base[FFT_VPT];
+    double h[FFT_VPT];
+    int nn[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        base[s] = {0, 0};
+        h[s] = 0;
+        nn[s] = -1;
+        if (e < tot) {
+            int col = e % g.colsA, nb = e / g.colsA;
+            int n = na0 + col + g.N1 * nb;
+            nn[s] = n;
+            if (n >= F.nd) {
+                double amp = stieltjes_C((double)n) * cb[n];
+                base[s] = cscale(half_shift(n, N), amp);
+                // h_{Mmax-1,n} = prod_{j<Mmax} (j-1/2)^2/(j (n+j+1/2))
+                double hv = 1;
+                for (int j = 1; j < F.Mmax; ++j) hv *= (j - 0.5) * (j - 0.5) / (j * (n + j + 0.5));
+                h[s] = hv;
+            }
+        }
+    }
+    for (int m = F.Mmax - 1; m >= 0; --m) {
+        for (int t = 0; t < F.nterm; ++t) {
+            if (F.term_m[t] != m) continue;
+            const int nlo = F.blk[F.term_blk[t]].nlo;
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) {
+                int e = threadIdx.x + s * FFT_THREADS;
+                if (e < tot) {
+                    int col = e % g.colsA, nb = e / g.colsA;
+                    double f = (nn[s] >= nlo) ? h[s] : 0.0;
+                    buf[col * g.N2 + nb] = cscale(base[s], f);
+                }
+            }
+            __syncthreads();
+            lds_fft(buf, g.N2, g.colsA, g.twN2);
+            passA_store(g, buf, na0, Xb + (int64_t)t * N);
+            __syncthreads();
+        }
+        if (m > 0) {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s)
+                if (nn[s] >= 0) h[s] *= m * (nn[s] + m + 0.5) / ((m - 0.5) * (m - 0.5));
+        }
+    }
+}
+
+// ---------------------------------------------------------- far field B --
+// For every term the z-values z_j = sum_n b_n e^{i n theta_j} (z = V_m or
+// conj(V_m) at row j(m)) are combined into
+//   v_j += Re(e^{i (m+1/2)(theta_j - pi/2)} z_j) / (2 sin theta_j)^{m+1/2}
+// on the rows of the term's block.  Term group blockIdx.y handles terms
+// t = y, y + G, ...; partial values go to v[y].
+__device__ __forceinline__ int row_block(const FarParams& F, int j, int N) {
+    int jj = min(j, N - 1 - j);
+    for (int b = 0; b < F.nblk; ++b)
+        if (jj >= F.blk[b].jlo && jj < F.blk[b].jhi) return b;
+    return -1;
+}
+
+__global__ __launch_bounds__(FFT_THREADS) void k_far_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
+                                                          int64_t x_stride, double* __restrict__ v,
+                                                          int64_t v_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int jb0 = blockIdx.x * g.rowsB;
+    const int grp = blockIdx.y;
+    const int b = blockIdx.z;
+    const cplx* Xb = X + b * x_stride;
+    const int tot = g.rowsB * g.N1;
+    const double pi = 3.141592653589793;
+    cplx gm[FFT_VPT], rq[FFT_VPT];
+    double acc[FFT_VPT];
+    int blk[FFT_VPT];
+    bool cj[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        acc[s] = 0;
+        blk[s] = -1;
+        cj[s] = false;
+        gm[s] = {0, 0};
+        rq[s] = {0, 0};
+        if (e < tot) {
+            int r = e / g.N1, ja = e - r * g.N1;
+            int m = jb0 + r + g.N2 * ja;
+            int j = row_of(m, N);
+            cj[s] = (2 * m >= N);
+            blk[s] = row_block(F, j, N);
+            double d = pi * (double)(2 * j + 1 - N) / (2.0 * N);  // theta_j - pi/2
+            int jj = min(j, N - 1 - j);
+            double sn = sin((jj + 0.5) * pi / N);                 // sin theta_j, full relative accuracy
+            double q = 1.0 / (2.0 * sn);
+            double ps, pc, rs, rc;
+            sincos(0.5 * d, &ps, &pc);
+            sincos(d, &rs, &rc);
+            double r0 = sqrt(q);
+            gm[s] = {pc * r0, ps * r0};
+            rq[s] = {rc * q, rs * q};
+        }
+    }
+    for (int m = 0; m < F.Mmax; ++m) {
+        for (int t = 0; t < F.nterm; ++t) {
+            if (F.term_m[t] != m || (t % G) != grp) continue;
+            const int tb = F.term_blk[t];
+            passB_load(g, buf, jb0, Xb + (int64_t)t * N);
+            __syncthreads();
+            lds_fft(buf, g.N1, g.rowsB, g.twN1);
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) {
+                int e = threadIdx.x + s * FFT_THREADS;
+                if (e < tot && blk[s] == tb) {
+                    cplx z = buf[e];
+                    if (cj[s]) z.im = -z.im;
+                    acc[s] = fma(gm[s].re, z.re, fma(-gm[s].im, z.im, acc[s]));
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) gm[s] = cmul(gm[s], rq[s]);
+    }
+    double* vb = v + b * v_stride + (int64_t)grp * N;
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        if (e < tot) {
+            int r = e / g.N1, ja = e - r * g.N1;
+            int m = jb0 + r + g.N2 * ja;
+            vb[row_of(m, N)] = acc[s];
+        }
+    }
+}
+
+// ------------------------------------------------------------ near field --
+// Item = (row j, degree chunk): the recurrence over the chunk from two basis
+// states (chunk > 0) or the true start (chunk 0), accumulating
+//   S+ = sum c_n P_n(cos theta_j), S- = sum (-1)^n c_n P_n(cos theta_j)
+// over n >= nd; the mirror row N-1-j takes S- since P_n(-x) = (-1)^n P_n(x).
+__global__ void k_near_items(int N, NearParams NP, const double* __restrict__ A, const double* __restrict__ B,
+                             const double* __restrict__ c, int64_t c_stride, double* __restrict__ items,
+                             int64_t it_stride) {
+    int id = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.z;
+    if (id >= NP.nitems) return;
+    int sgi = 0;
+    while (sgi + 1 < NP.nseg && id >= NP.seg[sgi + 1].item_off) ++sgi;
+    const Seg S = NP.seg[sgi];
+    int loc = id - S.item_off;
+    int nrows = S.jhi - S.jlo;
+    int ch = loc / nrows;
+    int j = S.jlo + (loc - ch * nrows);
+    const double* cb = c + b * c_stride;
+    double* out = items + b * it_stride + (int64_t)id * 8;
+    const double pi = 3.141592653589793;
+    double sn = sin(0.5 * (j + 0.5) * pi / N);
+    double u = 2.0 * sn * sn;
+    int n0 = ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
+    if (ch == 0) {
+        double p = 1, d = 0, sp = 0, sm = 0;
+        for (int n = n0; n < n1; ++n) {
+            if (n >= NP.nd) {
+                double cn = cb[n];
+                sp = fma(cn, p, sp);
+                sm = fma((n & 1) ? -cn : cn, p, sm);
+            }
+            double dn = fma(A[n], d, -B[n] * u * p);
+            p += dn;
+            d = dn;
+        }
+        out[0] = p;
+        out[1] = d;
+        out[2] = sp;
+        out[3] = sm;
+    } else {
+        double pa = 1, da = 0, pb = 0, db = 1;
+        double spa = 0, spb = 0, sma = 0, smb = 0;
+        for (int n = n0; n < n1; ++n) {
+            if (n >= NP.nd) {
+                double cn = cb[n];
+                double cm = (n & 1) ? -cn : cn;
+                spa = fma(cn, pa, spa);
+                spb = fma(cn, pb, spb);
+                sma = fma(cm, pa, sma);
+                smb = fma(cm, pb, smb);
+            }
+            double bu = B[n] * u;
+            double dna = fma(A[n], da, -bu * pa);
+            double dnb = fma(A[n], db, -bu * pb);
+            pa += dna;
+            da = dna;
+            pb += dnb;
+            db = dnb;
+        }
+        out[0] = pa;
+        out[1] = da;
+        out[2] = pb;
+        out[3] = db;
+        out[4] = spa;
+        out[5] = spb;
+        out[6] = sma;
+        out[7] = smb;
+    }
+}
+
+// near[j] = S+ for row j < jnear, near[jnear + j] = S- (row N-1-j)
+__global__ void k_near_combine(NearParams NP, const double* __restrict__ items, int64_t it_stride,
+                               double* __restrict__ near, int64_t near_stride) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.z;
+    if (j >= NP.jnear) return;
+    const double* it = items + b * it_stride;
+    double* nb = near + b * near_stride;
+    int sgi = -1;
+    for (int s = 0; s < NP.nseg; ++s)
+        if (j >= NP.seg[s].jlo && j < NP.seg[s].jhi) sgi = s;
+    double sp = 0, sm = 0;
+    if (sgi >= 0) {
+        const Seg S = NP.seg[sgi];
+        int nrows = S.jhi - S.jlo;
+        const double* o = it + (int64_t)(S.item_off + (j - S.jlo)) * 8;
+        double P = o[0], D = o[1];
+        sp = o[2];
+        sm = o[3];
+        for (int ch = 1; ch < S.nchunk; ++ch) {
+            const double* q = it + (int64_t)(S.item_off + ch * nrows + (j - S.jlo)) * 8;
+            sp += P * q[4] + D * q[5];
+            sm += P * q[6] + D * q[7];
+            double Pn = P * q[0] + D * q[2];
+            double Dn = P * q[1] + D * q[3];
+            P = Pn;
+            D = Dn;
+        }
+    }
+    nb[j] = sp;
+    nb[NP.jnear + j] = sm;
+}
+
+// ----------------------------------------------------------------- DCT-II --
+// chat_n = (eps_n/N) sum_j v_j cos(n theta_j) + dense_n:  DFT of
+// p_m = v_{j(m)}, then chat_n = (eps_n/N) Re(e^{i pi n/(2N)} U_n).
+// v_j is the sum of the G far-field partials and the near-field value.
+__global__ __launch_bounds__(FFT_THREADS) void k_dct2_passA(Geo g, int G, const double* __restrict__ v,
+                                                           int64_t v_stride, const double* __restrict__ near,
+                                                           int64_t near_stride, int jnear, cplx* __restrict__ X,
+                                                           int64_t x_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int na0 = blockIdx.x * g.colsA;
+    const int b = blockIdx.z;
+    const double* vb = v + b * v_stride;
+    const double* nb = near + b * near_stride;
+    const int tot = g.colsA * g.N2;
+    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+        int col = e % g.colsA, nbi = e / g.colsA;
+        int m = na0 + col + g.N1 * nbi;
+        int j = row_of(m, N);
+        double x = 0;
+        for (int q = 0; q < G; ++q) x += vb[(int64_t)q * N + j];
+        if (j < jnear) x += nb[j];
+        else if (N - 1 - j < jnear) x += nb[jnear + (N - 1 - j)];
+        buf[col * g.N2 + nbi] = {x, 0.0};
+    }
+    __syncthreads();
+    lds_fft(buf, g.N2, g.colsA, g.twN2);
+    passA_store(g, buf, na0, X + b * x_stride);
+}
+
+__global__ __launch_bounds__(FFT_THREADS) void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ X,
+                                                           int64_t x_stride, const double* __restrict__ dense,
+                                                           int64_t dense_stride, double* __restrict__ chat,
+                                                           int64_t chat_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int jb0 = blockIdx.x * g.rowsB;
+    const int b = blockIdx.z;
+    passB_load(g, buf, jb0, X + b * x_stride);
+    __syncthreads();
+    lds_fft(buf, g.N1, g.rowsB, g.twN1);
+    const int tot = g.rowsB * g.N1;
+    const double* db = dense + b * dense_stride;
+    double* cb = chat + b * chat_stride;
+    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+        int r = e / g.N1, ja = e - r * g.N1;
+        int n = jb0 + r + g.N2 * ja;
+        cplx U = buf[e];
+        cplx t = half_shift(n, N);
+        double val = (t.re * U.re - t.im * U.im) * ((n == 0) ? 1.0 : 2.0) / N;
+        if (n < nd) val += db[n];
+        cb[n] = val;
+    }
+}
+
+// ------------------------------------------------------------------ NDCT --
+// Pair q of Taylor terms (l = 2q: cosine sum of (n/N)^{2q} chat, l = 2q+1:
+// sine sum of (n/N)^{2q+1} chat) as one DFT of the Hermitian-split input
+//   W_n = (e^{i pi n/(2N)}/2) [x^{2q}(1+x) chat_n - i y^{2q} x chat_{N-n}],
+// x = n/N, y = 1 - x (n >= 1), W_0 = chat_0 [q = 0]; then at output m the
+// cosine term is Re U_m and the sine term sigma_m Im U_m, row k = j(m).
+__global__ __launch_bounds__(FFT_THREADS) void k_ndct_passA(Geo g, int Q, int QG, const double* __restrict__ chat,
+                                                           int64_t chat_stride, cplx* __restrict__ X,
+                                                           int64_t x_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int na0 = blockIdx.x * g.colsA;
+    const int grp = blockIdx.y;
+    const int b = blockIdx.z;
+    const double* cb = chat + b * chat_stride;
+    cplx* Xb = X + b * x_stride;
+    const int tot = g.colsA * g.N2;
+    const double invN = 1.0 / N;
+    cplx Av[FFT_VPT], Bv[FFT_VPT];
+    double px[FFT_VPT], py[FFT_VPT];
+    const int q0 = (Q * grp) / QG, q1 = (Q * (grp + 1)) / QG;
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        Av[s] = {0, 0};
+        Bv[s] = {0, 0};
+        px[s] = py[s] = 0;
+        if (e < tot) {
+            int col = e % g.colsA, nbi = e / g.colsA;
+            int n = na0 + col + g.N1 * nbi;
+            if (n == 0) {
+                Av[s] = {cb[0], 0};
+                px[s] = (q0 == 0) ? 1.0 : 0.0;
+            } else {
+                double x = n * invN, y = (N - n) * invN;
+                cplx e2 = cscale(half_shift(n, N), 0.5);
+                Av[s] = cscale(e2, (1.0 + x) * cb[n]);
+                Bv[s] = cscale(cmuli(e2), -x * cb[N - n]);
+                double a = 1, bb = 1;
+                for (int q = 0; q < q0; ++q) {
+                    a *= x * x;
+                    bb *= y * y;
+                }
+                px[s] = a;
+                py[s] = bb;
+            }
+        }
+    }
+    for (int q = q0; q < q1; ++q) {
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            int e = threadIdx.x + s * FFT_THREADS;
+            if (e < tot) {
+                int col = e % g.colsA, nbi = e / g.colsA;
+                int n = na0 + col + g.N1 * nbi;
+                double x = n * invN, y = (N - n) * invN;
+                buf[col * g.N2 + nbi] = cadd(cscale(Av[s], px[s]), cscale(Bv[s], py[s]));
+                px[s] *= x * x;
+                py[s] *= y * y;
+            }
+        }
+        __syncthreads();
+        lds_fft(buf, g.N2, g.colsA, g.twN2);
+        passA_store(g, buf, na0, Xb + (int64_t)q * N);
+        __syncthreads();
+    }
+}
+
+// f_k = sum_l s_l d_k^l/l! F_l[k], s_l = (-1)^floor((l+1)/2), d_k = N dtheta_k,
+// by Horner from the highest pair down.
+__global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X,
+                                                           int64_t x_stride, const double* __restrict__ dth,
+                                                           double* __restrict__ f, int64_t f_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int jb0 = blockIdx.x * g.rowsB;
+    const int b = blockIdx.z;
+    const cplx* Xb = X + b * x_stride;
+    const int tot = g.rowsB * g.N1;
+    double acc[FFT_VPT], d[FFT_VPT];
+    bool hi[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        acc[s] = 0;
+        d[s] = 0;
+        hi[s] = false;
+        if (e < tot) {
+            int r = e / g.N1, ja = e - r * g.N1;
+            int m = jb0 + r + g.N2 * ja;
+            hi[s] = (2 * m >= N);
+            d[s] = (double)N * dth[row_of(m, N)];
+        }
+    }
+    for (int q = Q - 1; q >= 0; --q) {
+        passB_load(g, buf, jb0, Xb + (int64_t)q * N);
+        __syncthreads();
+        lds_fft(buf, g.N1, g.rowsB, g.twN1);
+        const double sc = (q & 1) ? -1.0 : 1.0;  // s_{2q} = (-1)^q, s_{2q+1} = -(-1)^q
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            int e = threadIdx.x + s * FFT_THREADS;
+            if (e < tot) {
+                cplx U = buf[e];
+                double Fc = U.re;
+                double Fs = hi[s] ? -U.im : U.im;
+                double inner = fma(d[s] / (2 * q + 2), acc[s], -sc * Fs);
+                acc[s] = fma(d[s] / (2 * q + 1), inner, sc * Fc);
+            }
+        }
+        __syncthreads();
+    }
+    double* fb = f + b * f_stride;
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        if (e < tot) {
+            int r = e / g.N1, ja = e - r * g.N1;
+            int m = jb0 + r + g.N2 * ja;
+            fb[row_of(m, N)] = acc[s];
+        }
+    }
+}
+
+}  // namespace dlt
+
+// ================================================================ host ====
+namespace dlt {
+
+static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t work_bytes(const Plan& p, int64_t nb) { return (size_t)nb * p.ws_per_inst; }
+
+void work_carve(const Plan& p, int64_t nb, void* base, Work& w) {
+    char* q = (char*)base;
+    auto take = [&](size_t per) {
+        char* r = q;
+        q += al256(per) * nb;
+        return (void*)r;
+    };
+    w.X = (cplx*)take(p.ws_X);
+    w.sX = (int64_t)(al256(p.ws_X) / sizeof(cplx));
+    w.v = (double*)take(p.ws_v);
+    w.sv = (int64_t)(al256(p.ws_v) / sizeof(double));
+    w.items = (double*)take(p.ws_items);
+    w.sitems = (int64_t)(al256(p.ws_items) / sizeof(double));
+    w.near = (double*)take(p.ws_near);
+    w.snear = (int64_t)(al256(p.ws_near) / sizeof(double));
+    w.dense = (double*)take(p.ws_dense);
+    w.sdense = (int64_t)(al256(p.ws_dense) / sizeof(double));
+    w.chat = (double*)take(p.ws_chat);
+    w.schat = (int64_t)(al256(p.ws_chat) / sizeof(double));
+    w.vec = (double*)take(p.ws_vec);
+    w.svec = (int64_t)(al256(p.ws_vec) / sizeof(double));
+}
+
+hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, hipStream_t s) {
+    const NodeParams& P = p.nodes;
+    int nh = (P.N + 1) / 2;
+    if (P.kb > 0) {
+        size_t shm = (7 * 256 + 3) * sizeof(double);
+        k_nodes_boundary<<<P.kb, 256, shm, s>>>(P, p.d_guess, p.d_recA, p.d_recB, theta, w, dth);
+    }
+    int ni = nh - P.kb;
+    if (ni > 0) k_nodes_interior<<<(ni + 255) / 256, 256, 0, s>>>(P, theta, w, dth);
+    return hipGetLastError();
+}
+
+hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, double* chat, Work& w, hipStream_t s) {
+    const int N = (int)p.N;
+    const int nd = p.nd;
+    const Geo& g = p.geo;
+    // dense block: partials then reduction into the last slab of `dense`
+    double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
+    dim3 gd((nd + 255) / 256, p.dense_nchunk, (unsigned)nb);
+    k_dense<<<gd, 256, 0, s>>>(N, nd, p.dense_chunk, p.d_lam, c, N, w.dense, w.sdense);
+    if (N <= nd) {
+        k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                           w.dense, w.sdense, chat, N);
+        return hipGetLastError();
+    }
+    k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                       w.dense, w.sdense, dense_out, w.sdense);
+    // near field
+    const NearParams& NP = p.near;
+    if (NP.nitems > 0)
+        k_near_items<<<dim3((NP.nitems + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(N, NP, p.d_recA, p.d_recB, c, N,
+                                                                                w.items, w.sitems);
+    if (NP.jnear > 0)
+        k_near_combine<<<dim3((NP.jnear + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(NP, w.items, w.sitems, w.near,
+                                                                                 w.snear);
+    // far field
+    const FarParams& F = p.far;
+    k_far_passA<<<dim3(g.N1 / g.colsA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, F, c, N, w.X, w.sX);
+    k_far_passB<<<dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb), FFT_THREADS, 0, s>>>(g, F, p.tgB, w.X, w.sX, w.v,
+                                                                               w.sv);
+    // values on the grid -> coefficients
+    k_dct2_passA<<<dim3(g.N1 / g.colsA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.tgB, w.v, w.sv, w.near, w.snear,
+                                                                            NP.jnear, w.X, w.sX);
+    k_dct2_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, nd, w.X, w.sX, dense_out, w.sdense,
+                                                                            chat, N);
+    return hipGetLastError();
+}
+
+hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, const double* dth, double* f, Work& w,
+                    hipStream_t s) {
+    const Geo& g = p.geo;
+    const int Q = p.L / 2;
+    const int tilesA = g.N1 / g.colsA;
+    // small transforms: split the Taylor pairs over blocks for parallelism
+    int QG = (tilesA * nb >= 256) ? 1 : Q;
+    k_ndct_passA<<<dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, QG, chat, p.N, w.X, w.sX);
+    k_ndct_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, w.X, w.sX, dth, f, p.N);
+    return hipGetLastError();
+}
+
+}  // namespace dlt

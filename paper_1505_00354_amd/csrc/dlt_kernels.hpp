@@ -1,0 +1,31 @@
+// Host-side launchers for the DLT pipelines (implemented with the kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dlt_plan.hpp"
+
+namespace dlt {
+
+// Device scratch for `nb` instances of one plan, carved from one buffer.
+struct Work {
+    cplx* X;          // far-field / DCT / Taylor DFT intermediates
+    double* v;        // far-field partial values (tgB slabs)
+    double* items;    // near-field chunk results
+    double* near;     // near-field values of the endpoint rows
+    double* dense;    // dense-block partials (+ reduced slab at the end)
+    double* chat;     // Chebyshev coefficients
+    double* vec;      // spare length-N vector
+    int64_t sX, sv, sitems, snear, sdense, schat, svec;  // per-instance strides (elements)
+};
+size_t work_bytes(const Plan& p, int64_t nb);
+void work_carve(const Plan& p, int64_t nb, void* base, Work& w);
+
+// theta, w, dtheta (any may be null) for the plan's N
+hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, hipStream_t s);
+// chat = M c for nb instances
+hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, double* chat, Work& w, hipStream_t s);
+// f = sum_n chat_n cos(n theta^leg), dth = theta^leg - theta^cheb1
+hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, const double* dth, double* f, Work& w,
+                    hipStream_t s);
+
+}  // namespace dlt

@@ -1,0 +1,282 @@
+// Plan construction.  Every parameter is derived from an error bound:
+//  * Taylor terms L: smallest even L with (max_k N|dtheta_k|)^L / L! below the
+//    truncation budget, max N|dtheta| <= 0.83845 by Lemma 2 (Corollary 2).
+//  * Far-field blocks of the Legendre-to-Chebyshev conversion: the remainder
+//    of the M-term Stieltjes expansion of P_n(cos theta) is at most
+//    2 C_n h_{M,n} / (2 sin theta)^{M+1/2}; a block's first column nlo and its
+//    rows are chosen so that this bound stays below the far-field budget at
+//    the block's corner (nlo, smallest sin theta), which bounds it everywhere
+//    in the block since the bound decreases in n and in sin theta.
+//  * Columns n < nd go through the exact dense conversion matrix.
+#include "dlt_plan.hpp"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "dlt_status.h"
+
+namespace dlt {
+
+typedef long double LD;
+static const LD PI_L = 3.14159265358979323846264338327950288L;
+
+// Gamma(x+1/2)/Gamma(x), x > 0, in long double: Stirling-type series for
+// x >= 20 and the ratio recurrence R(x) = R(x+1) x/(x+1/2) below.
+static LD gamma_half_ratio(LD x) {
+    static const LD a[] = {-1.0L / 8, 1.0L / 192, -1.0L / 640, 17.0L / 14336, -31.0L / 18432,
+                           691.0L / 180224, -5461.0L / 425984, 929569.0L / 15728640};
+    LD f = 1.0L;
+    while (x < 20) {
+        f *= x / (x + 0.5L);
+        x += 1;
+    }
+    LD r = 1.0L / x, r2 = r * r, s = 0, p = r;
+    for (int k = 0; k < 8; ++k) {
+        s += a[k] * p;
+        p *= r2;
+    }
+    return f * sqrtl(x) * expl(s);
+}
+
+// C_n = sqrt(4/pi) Gamma(n+1)/Gamma(n+3/2)
+static LD stieltjes_C_host(LD n) { return 2.0L / sqrtl(PI_L) / gamma_half_ratio(n + 1); }
+
+// h_{M,n} = prod_{j=1..M} (j-1/2)^2 / (j (n+j+1/2))
+static LD stieltjes_h(int M, LD n) {
+    LD h = 1;
+    for (int j = 1; j <= M; ++j) h *= (j - 0.5L) * (j - 0.5L) / (j * (n + j + 0.5L));
+    return h;
+}
+
+// smallest sin(theta) at which the M-term remainder bound at column n is <= eps
+static LD far_smin(int M, LD n, LD eps) {
+    LD B = 2 * stieltjes_C_host(n) * stieltjes_h(M, n) / eps;
+    return 0.5L * powl(B, 1.0L / (M + 0.5L));
+}
+
+// first row j (0 <= j < N/2) with sin((j+1/2) pi/N) >= s
+static int first_row(int64_t N, LD s) {
+    if (s <= 0) return 0;
+    if (s >= 1) return (int)(N / 2);
+    LD t = asinl(s);
+    int64_t j = (int64_t)floorl(t * N / PI_L - 0.5L);
+    if (j < 0) j = 0;
+    while (j < N / 2 && sinl((j + 0.5L) * PI_L / N) < s) ++j;
+    while (j > 0 && sinl((j - 0.5L) * PI_L / N) >= s) --j;
+    return (int)j;
+}
+
+static int upload(const void* h, size_t bytes, void** d) {
+    if (hipMalloc(d, bytes) != hipSuccess) return DLT_ERR_NOMEM;
+    if (hipMemcpy(*d, h, bytes, hipMemcpyHostToDevice) != hipSuccess) return DLT_ERR_HIP;
+    return 0;
+}
+
+static int twiddle_table(int len, LD denom, int mult, cplx** d) {
+    std::vector<cplx> t(len > 0 ? len : 1);
+    for (int i = 0; i < len; ++i) {
+        LD a = 2 * PI_L * (LD)((int64_t)i * mult) / denom;
+        t[i].re = (double)cosl(a);
+        t[i].im = (double)sinl(a);
+    }
+    return upload(t.data(), t.size() * sizeof(cplx), (void**)d);
+}
+
+// Legendre node parameters: Stieltjes-series Newton for k >= kb, recurrence
+// Newton from a Bessel-zero start for k < kb.
+static double bessel_j0_zero(int k) {
+    // zero k (0-based) of J0: McMahon start, Newton with J0' = -J1
+    double b = (k + 0.75) * M_PI;
+    double x = b + 1.0 / (8 * b) - 124.0 / (3 * 512 * b * b * b);
+    for (int it = 0; it < 8; ++it) x += j0(x) / j1(x);
+    return x;
+}
+
+int plan_build(int64_t N, Plan& p) {
+    memset(&p.geo, 0, sizeof(p.geo));
+    p.N = N;
+    // ---- FFT geometry
+    int lg = 0;
+    while ((int64_t(1) << lg) < N) ++lg;
+    int l2 = lg / 2, l1 = lg - l2;  // N1 = 2^l1 >= N2 = 2^l2
+    int N1 = 1 << l1, N2 = 1 << l2;
+    Geo& g = p.geo;
+    g.N = (int)N;
+    g.N1 = N1;
+    g.N2 = N2;
+    g.colsA = std::min(N1, FFT_CAP / N2);
+    g.rowsB = std::min(N2, FFT_CAP / N1);
+    g.sh = (lg + 1) / 2;
+    int rc;
+    if ((rc = twiddle_table(N1, N1, 1, &p.d_twN1))) return rc;
+    if ((rc = twiddle_table(N2, N2, 1, &p.d_twN2))) return rc;
+    if ((rc = twiddle_table((int)(N >> g.sh) + 1, (LD)N, 1 << g.sh, &p.d_twHi))) return rc;
+    if ((rc = twiddle_table(1 << g.sh, (LD)N, 1, &p.d_twLo))) return rc;
+    g.twN1 = p.d_twN1;
+    g.twN2 = p.d_twN2;
+    g.twHi = p.d_twHi;
+    g.twLo = p.d_twLo;
+
+    // ---- Taylor truncation (Corollary 2 with max N|dtheta| <= 0.83845)
+    {
+        const double tolT = 5e-15;  // 10% of the 5e-14 FP64 budget
+        int L = 1;
+        double f = 0.83845;
+        while (f > tolT) {
+            ++L;
+            f *= 0.83845 / L;
+        }
+        p.L = (L + 1) & ~1;
+    }
+
+    // ---- dense block
+    const int ND_MAX = 8192;
+    p.nd = (int)std::min<int64_t>(N, ND_MAX);
+    p.dense_chunk = 512;
+    p.dense_nchunk = (p.nd + p.dense_chunk - 1) / p.dense_chunk;
+    {
+        std::vector<double> lam(p.nd);
+        for (int z = 0; z < p.nd; ++z) lam[z] = (double)(1.0L / gamma_half_ratio(z + 0.5L));
+        if ((rc = upload(lam.data(), lam.size() * sizeof(double), (void**)&p.d_lam))) return rc;
+    }
+
+    // ---- far field and near field (only when N > nd)
+    FarParams& F = p.far;
+    NearParams& Nr = p.near;
+    memset(&F, 0, sizeof(F));
+    memset(&Nr, 0, sizeof(Nr));
+    F.nd = p.nd;
+    Nr.nd = p.nd;
+    if (N > p.nd) {
+        const LD eps = 1e-15L;
+        const int M1 = 12, M = 12;
+        const double beta = 8.0;
+        int half = (int)(N / 2);
+        // block 0: central rows, columns n >= nd
+        int j0 = first_row(N, far_smin(M1, p.nd, eps));
+        F.blk[0] = {j0, half, p.nd, M1};
+        F.nblk = 1;
+        int jprev = j0;
+        while (jprev > 0 && F.nblk < MAX_BLOCKS) {
+            int jl = (int)floor(jprev / beta);
+            LD s = sinl((jl + 0.5L) * PI_L / N);
+            // smallest column where M terms are within eps at sin = s
+            LD lo = p.nd, hi = (LD)N;
+            if (far_smin(M, hi, eps) > s) break;  // no valid column below N
+            for (int it = 0; it < 80; ++it) {
+                LD mid = 0.5L * (lo + hi);
+                if (far_smin(M, mid, eps) <= s) hi = mid; else lo = mid;
+            }
+            int nlo = (int)ceill(hi);
+            if (nlo >= N) break;
+            F.blk[F.nblk++] = {jl, jprev, nlo, M};
+            jprev = jl;
+        }
+        F.Mmax = 0;
+        F.nterm = 0;
+        for (int b = 0; b < F.nblk; ++b) F.Mmax = std::max(F.Mmax, F.blk[b].M);
+        for (int m = 0; m < F.Mmax; ++m)
+            for (int b = 0; b < F.nblk; ++b)
+                if (m < F.blk[b].M) {
+                    if (F.nterm >= MAX_TERMS) return DLT_ERR_UNSUPPORTED;
+                    F.term_blk[F.nterm] = (unsigned char)b;
+                    F.term_m[F.nterm] = (unsigned char)m;
+                    ++F.nterm;
+                }
+        // near-field segments: blocks b >= 1 need columns [nd, nlo); rows
+        // below the last block need [nd, N)
+        Nr.jnear = jprev;  // rows j < jnear: endpoint rows
+        int items = 0;
+        auto add_seg = [&](int jlo, int jhi, int nend) {
+            if (jhi <= jlo || nend <= p.nd) return;
+            Seg s;
+            s.jlo = jlo;
+            s.jhi = jhi;
+            s.nend = nend;
+            s.nchunk = (nend + NEAR_CHUNK - 1) / NEAR_CHUNK;
+            s.item_off = items;
+            items += (jhi - jlo) * s.nchunk;
+            Nr.seg[Nr.nseg++] = s;
+        };
+        add_seg(0, jprev, (int)N);
+        for (int b = 1; b < F.nblk; ++b) add_seg(F.blk[b].jlo, F.blk[b].jhi, F.blk[b].nlo);
+        Nr.nitems = items;
+        Nr.jnear = (F.nblk > 1) ? F.blk[1].jhi : jprev;  // rows j < jnear may carry near terms
+        if (Nr.nseg == 0) Nr.jnear = 0;
+        // recurrence coefficient tables
+        std::vector<double> A(N), B(N);
+        for (int64_t n = 0; n < N; ++n) {
+            A[n] = (double)((LD)n / (LD)(n + 1));
+            B[n] = (double)((LD)(2 * n + 1) / (LD)(n + 1));
+        }
+        if ((rc = upload(A.data(), N * sizeof(double), (void**)&p.d_recA))) return rc;
+        if ((rc = upload(B.data(), N * sizeof(double), (void**)&p.d_recB))) return rc;
+    } else {
+        // nodes still use the recurrence tables for the boundary nodes
+        std::vector<double> A(N), B(N);
+        for (int64_t n = 0; n < N; ++n) {
+            A[n] = (double)((LD)n / (LD)(n + 1));
+            B[n] = (double)((LD)(2 * n + 1) / (LD)(n + 1));
+        }
+        if ((rc = upload(A.data(), N * sizeof(double), (void**)&p.d_recA))) return rc;
+        if ((rc = upload(B.data(), N * sizeof(double), (void**)&p.d_recB))) return rc;
+    }
+
+    // ---- nodes
+    NodeParams& ndp = p.nodes;
+    memset(&ndp, 0, sizeof(ndp));
+    ndp.N = (int)N;
+    ndp.Ms = MAX_NODE_M;
+    int nh = (int)((N + 1) / 2);
+    ndp.kb = (int)std::min<int64_t>(nh, 6);
+    if (N < 128) ndp.kb = nh;
+    ndp.newton_b = (N >= 4096) ? 0 : (N >= 64) ? 1 : 12;
+    ndp.C = (double)stieltjes_C_host((LD)N);
+    for (int m = 0; m < MAX_NODE_M; ++m) ndp.h[m] = (double)stieltjes_h(m, (LD)N);
+    {
+        // boundary-node starting offsets from theta^cheb1_k = (k+1/2) pi/N:
+        // Bessel-zero form theta ~ psi + (psi cot psi - 1)/(8 psi nu^2),
+        // psi = j_{0,k+1}/nu, nu = N+1/2, for N >= 64; else theta^cheb*.
+        std::vector<double> gsv(ndp.kb > 0 ? ndp.kb : 1);
+        LD nu = (LD)N + 0.5L;
+        for (int k = 0; k < ndp.kb; ++k) {
+            LD th;
+            if (N >= 64) {
+                LD psi = (LD)bessel_j0_zero(k) / nu;
+                th = psi + (psi * cosl(psi) / sinl(psi) - 1) / (8 * psi * nu * nu);
+            } else {
+                th = ((LD)k + 0.75L) * PI_L / nu;
+            }
+            gsv[k] = (double)(th - ((LD)k + 0.5L) * PI_L / (LD)N);
+        }
+        if ((rc = upload(gsv.data(), gsv.size() * sizeof(double), (void**)&p.d_guess))) return rc;
+    }
+
+    // ---- workspace per instance
+    int nX = std::max({F.nterm, p.L / 2, 1});
+    p.tgB = (F.nterm >= 8 && N >= (1 << 16)) ? 2 : 1;
+    p.ws_X = (size_t)nX * N * sizeof(cplx);
+    p.ws_v = (size_t)p.tgB * N * sizeof(double);
+    p.ws_items = (size_t)Nr.nitems * 8 * sizeof(double);
+    p.ws_near = (size_t)2 * std::max(Nr.jnear, 1) * sizeof(double);
+    p.ws_dense = (size_t)(p.dense_nchunk + 1) * p.nd * sizeof(double);
+    p.ws_chat = (size_t)N * sizeof(double);
+    p.ws_vec = (size_t)N * sizeof(double);
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    p.ws_per_inst = al(p.ws_X) + al(p.ws_v) + al(p.ws_items) + al(p.ws_near) + al(p.ws_dense) +
+                    al(p.ws_chat) + al(p.ws_vec);
+    p.ws_shared = 3 * al((size_t)N * sizeof(double));  // theta, w, dtheta
+    return 0;
+}
+
+void plan_free(Plan& p) {
+    void* ptrs[] = {p.d_twN1, p.d_twN2, p.d_twHi, p.d_twLo, p.d_lam, p.d_recA, p.d_recB, p.d_guess};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    p = Plan();
+}
+
+}  // namespace dlt

@@ -1,0 +1,90 @@
+// Host-side plan for one transform size N: FFT geometry, the block split of
+// the Legendre-to-Chebyshev conversion, the Taylor truncation L, node
+// parameters, device tables, and the workspace layout.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "dlt_common.hpp"
+
+namespace dlt {
+
+constexpr int MAX_TERMS = 64;   // far-field (block, m) pairs
+constexpr int MAX_BLOCKS = 8;
+constexpr int MAX_NODE_M = 24;  // terms of the Stieltjes series for nodes
+constexpr int MAX_SEGS = 8;     // near-field row segments
+constexpr int NEAR_CHUNK = 1024;
+constexpr int64_t MAX_N = int64_t(1) << 22;
+
+// FFT geometry of the length-N DFT (N power of two): N = N1*N2.  Pass A runs
+// length-N2 DFTs over the slow input index for tiles of colsA columns; pass B
+// runs length-N1 DFTs over the fast input index for tiles of rowsB rows.
+struct Geo {
+    int N, N1, N2, colsA, rowsB, sh;
+    const cplx* twN1;  // e^{2 pi i t/N1}
+    const cplx* twN2;  // e^{2 pi i t/N2}
+    const cplx* twHi;  // e^{2 pi i (t<<sh)/N}
+    const cplx* twLo;  // e^{2 pi i t/N}, t < 2^sh
+};
+
+// Far-field block b: rows j in [jlo, jhi) and the mirrored rows
+// [N-jhi, N-jlo); columns n >= nlo; M terms of the Stieltjes series.
+struct Block {
+    int jlo, jhi, nlo, M;
+};
+
+// Near-field segment: rows j in [jlo, jhi) (and mirrors), recurrence over
+// n in [0, nend), contributions accumulated for n >= nd.
+struct Seg {
+    int jlo, jhi, nend, nchunk;
+    int item_off;  // first item of this segment
+};
+
+struct FarParams {
+    int nblk, nterm, Mmax, nd;
+    Block blk[MAX_BLOCKS];
+    unsigned char term_blk[MAX_TERMS], term_m[MAX_TERMS];
+    // row -> block lookup: rows j < blk_edge[b] (and mirrors) are outside
+    // blocks 0..b-1; block 0 is the central one.
+};
+
+struct NearParams {
+    int nseg, nitems, jnear, nd;
+    Seg seg[MAX_SEGS];
+};
+
+struct NodeParams {
+    int N, kb, Ms, newton_b;   // boundary nodes k < kb use the recurrence
+    double C;                  // C_N of the Stieltjes series
+    double h[MAX_NODE_M];      // h_{m,N}
+};
+
+struct Plan {
+    int64_t N = 0;
+    int L = 16;        // Taylor terms (even)
+    int nd = 0;        // columns n < nd handled by the dense block
+    int dense_chunk = 1024, dense_nchunk = 0;
+    Geo geo{};
+    FarParams far{};
+    NearParams near{};
+    NodeParams nodes{};
+    // device tables
+    cplx *d_twN1 = nullptr, *d_twN2 = nullptr, *d_twHi = nullptr, *d_twLo = nullptr;
+    double* d_lam = nullptr;     // Lambda(z), z < nd
+    double* d_recA = nullptr;    // n/(n+1)
+    double* d_recB = nullptr;    // (2n+1)/(n+1)
+    double* d_guess = nullptr;   // boundary-node initial offsets from theta^cheb1
+    // workspace sizes per transform instance (bytes)
+    size_t ws_X = 0, ws_v = 0, ws_items = 0, ws_near = 0, ws_dense = 0, ws_chat = 0, ws_vec = 0;
+    size_t ws_per_inst = 0, ws_shared = 0;
+    int tgB = 1;       // far-field pass-B term groups
+};
+
+// Builds the plan for size N (power of two, 1 <= N <= MAX_N); returns 0 or a
+// DLT status code.  Allocates the device tables.
+int plan_build(int64_t N, Plan& p);
+void plan_free(Plan& p);
+
+}  // namespace dlt

@@ -103,6 +103,23 @@ def test_nodes_invariants_and_lemma2(orc, N):
     assert 3 * np.pi * (2 * N + 1) * np.max(np.abs(th - chebstar(N))) > 0.9
 
 
+def test_boundary_weights_mpmath(orc):
+    # nodes next to x = +-1 at a size where the weight formula's conditioning
+    # matters; the root is bracketed with Lemma 2 (theta^cheb* < theta^leg <=
+    # theta^cheb* + 1/(3 pi (2N+1))), independently of the oracle
+    mp.mp.dps = 40
+    N = 1024
+    idx = np.array([0, 1, 2, 5])
+    th, w = orc.nodes(N, idx=idx)
+    g = lambda t: mp.legendre(N, mp.cos(t))
+    for i, k in enumerate(idx):
+        a = mp.mpf(k + 0.75) * mp.pi / (N + mp.mpf(1) / 2)
+        r = mp.findroot(g, (a, a + 1.01 / (3 * mp.pi * (2 * N + 1))), solver="illinois")
+        assert abs(float(r) - th[i]) <= 1 * ULP * float(r)
+        wk = 2 / mp.diff(g, r) ** 2
+        assert abs(float(wk) / w[i] - 1) <= 4 * ULP
+
+
 def test_nodes_residual_mpmath(orc):
     mp.mp.dps = 30
     N = 1000
