@@ -216,7 +216,16 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
     if (rc) return rc;
     if (batch == 0) return DLT_OK;
     if (!f || !c || overlap(f, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
-    return DLT_ERR_UNSUPPORTED;
+    Plan* p;
+    if ((rc = get_plan(N, &p))) return rc;
+    CallWS cw;
+    if ((rc = setup_call(*p, batch, stream, cw))) return rc;
+    if ((rc = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, stream)))) return rc;
+    for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+        int64_t nb = std::min(cw.nb, batch - b0);
+        if ((rc = hip_status(run_inverse(*p, nb, f + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, stream)))) return rc;
+    }
+    return DLT_OK;
 }
 
 int dlt_release(void) {

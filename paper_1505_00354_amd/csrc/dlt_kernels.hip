@@ -433,7 +433,7 @@ __global__ void k_near_items(int N, NearParams NP, const double* __restrict__ A,
     int nrows = S.jhi - S.jlo;
     int ch = loc / nrows;
     int j = S.jlo + (loc - ch * nrows);
-    const double* cb = c + b * c_stride;
+    const double* cb = c ? c + b * c_stride : nullptr;
     double* out = items + b * it_stride + (int64_t)id * 8;
     const double pi = 3.141592653589793;
     double sn = sin(0.5 * (j + 0.5) * pi / N);
@@ -442,7 +442,7 @@ __global__ void k_near_items(int N, NearParams NP, const double* __restrict__ A,
     if (ch == 0) {
         double p = 1, d = 0, sp = 0, sm = 0;
         for (int n = n0; n < n1; ++n) {
-            if (n >= NP.nd) {
+            if (cb && n >= NP.nd) {
                 double cn = cb[n];
                 sp = fma(cn, p, sp);
                 sm = fma((n & 1) ? -cn : cn, p, sm);
@@ -459,7 +459,7 @@ __global__ void k_near_items(int N, NearParams NP, const double* __restrict__ A,
         double pa = 1, da = 0, pb = 0, db = 1;
         double spa = 0, spb = 0, sma = 0, smb = 0;
         for (int n = n0; n < n1; ++n) {
-            if (n >= NP.nd) {
+            if (cb && n >= NP.nd) {
                 double cn = cb[n];
                 double cm = (n & 1) ? -cn : cn;
                 spa = fma(cn, pa, spa);
@@ -698,6 +698,469 @@ __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const 
     }
 }
 
+
+// ============================================================== inverse ===
+// c = D_s M^T T^T D_w f (Sec. 4): g = w f; y = T^T g by the transposed Taylor
+// series; c_n = (n+1/2) (M^T y)_n with M^T = P^T C D_eps on the grid.
+
+// Transposed Taylor pair q: DFT input at m (row k = j(m)):
+//   g_k d_k^{2q} (1 + i sigma_m d_k),  sigma_m = +1 (2m < N), -1 otherwise.
+__global__ __launch_bounds__(FFT_THREADS) void k_tndct_passA(Geo g, int Q, int QG, const double* __restrict__ fv,
+                                                            int64_t f_stride, const double* __restrict__ wts,
+                                                            const double* __restrict__ dth, cplx* __restrict__ X,
+                                                            int64_t x_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int na0 = blockIdx.x * g.colsA;
+    const int grp = blockIdx.y;
+    const int b = blockIdx.z;
+    const double* fb = fv + b * f_stride;
+    cplx* Xb = X + b * x_stride;
+    const int tot = g.colsA * g.N2;
+    double gv[FFT_VPT], dv[FFT_VPT], pw[FFT_VPT];
+    const int q0 = (Q * grp) / QG, q1 = (Q * (grp + 1)) / QG;
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        gv[s] = dv[s] = pw[s] = 0;
+        if (e < tot) {
+            int col = e % g.colsA, nbi = e / g.colsA;
+            int m = na0 + col + g.N1 * nbi;
+            int kk = row_of(m, N);
+            gv[s] = wts[kk] * fb[kk];
+            dv[s] = (double)N * dth[kk];
+            double p = 1;
+            for (int q = 0; q < q0; ++q) p *= dv[s] * dv[s];
+            pw[s] = p;
+        }
+    }
+    for (int q = q0; q < q1; ++q) {
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            int e = threadIdx.x + s * FFT_THREADS;
+            if (e < tot) {
+                int col = e % g.colsA, nbi = e / g.colsA;
+                int m = na0 + col + g.N1 * nbi;
+                double a = gv[s] * pw[s];
+                double sg = (2 * m < N) ? 1.0 : -1.0;
+                buf[col * g.N2 + nbi] = {a, sg * a * dv[s]};
+                pw[s] *= dv[s] * dv[s];
+            }
+        }
+        __syncthreads();
+        lds_fft(buf, g.N2, g.colsA, g.twN2);
+        passA_store(g, buf, na0, Xb + (int64_t)q * N);
+        __syncthreads();
+    }
+}
+
+// Pass-B tiles closed under n -> N-n: local rows [0, h) are r = tile*h + i
+// (r < N2/2) and rows [h, 2h) their partners p(r) = N2 - r (p(0) = N2/2).
+__device__ __forceinline__ int pair_row(int tile, int i, int rowsB, int N2) {
+    if (N2 == 1) return 0;
+    int h = rowsB / 2;
+    if (i < h) return tile * h + i;
+    int r = tile * h + (i - h);
+    return (r == 0) ? N2 / 2 : N2 - r;
+}
+
+__device__ __forceinline__ void passB_load_rows(const Geo& g, cplx* buf, int tile, const cplx* __restrict__ X) {
+    const int tot = g.rowsB * g.N1;
+    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+        int i = e % g.rowsB, na = e / g.rowsB;
+        buf[i * g.N1 + na] = X[(int64_t)na * g.N2 + pair_row(tile, i, g.rowsB, g.N2)];
+    }
+}
+
+// y_n = sum_l s_l (n/N)^l / l! Z_l[n]; Z_{2q} = Re(e_n A_n), Z_{2q+1} = Im(e_n B_n),
+// A = (U_n + conj U_{N-n})/2, B = (U_n - conj U_{N-n})/(2i), e_n = e^{i pi n/(2N)}.
+__global__ __launch_bounds__(FFT_THREADS) void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ X,
+                                                            int64_t x_stride, double* __restrict__ y,
+                                                            int64_t y_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int tile = blockIdx.x;
+    const int b = blockIdx.z;
+    const cplx* Xb = X + b * x_stride;
+    const int tot = g.rowsB * g.N1;
+    const int nrows = (g.N2 == 1) ? 1 : g.rowsB;
+    const int h = g.rowsB / 2;
+    double acc[FFT_VPT], xs[FFT_VPT];
+    cplx en[FFT_VPT];
+    int part[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        acc[s] = 0;
+        xs[s] = 0;
+        en[s] = {0, 0};
+        part[s] = 0;
+        if (e < tot && e / g.N1 < nrows) {
+            int i = e / g.N1, ja = e - i * g.N1;
+            int r = pair_row(tile, i, g.rowsB, g.N2);
+            int n = r + g.N2 * ja;
+            xs[s] = (double)n / N;
+            en[s] = half_shift(n, N);
+            int ip, jp;
+            if (r == 0) {
+                ip = i;
+                jp = (g.N1 - ja) & (g.N1 - 1);
+            } else {
+                ip = (g.N2 == 1) ? i : (i < h ? i + h : i - h);
+                if (r == g.N2 / 2) ip = i;
+                jp = g.N1 - 1 - ja;
+            }
+            part[s] = ip * g.N1 + jp;
+        }
+    }
+    for (int q = Q - 1; q >= 0; --q) {
+        passB_load_rows(g, buf, tile, Xb + (int64_t)q * N);
+        __syncthreads();
+        lds_fft(buf, g.N1, g.rowsB, g.twN1);
+        const double sc = (q & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            int e = threadIdx.x + s * FFT_THREADS;
+            if (e < tot && e / g.N1 < nrows) {
+                cplx U = buf[e], V = buf[part[s]];
+                cplx A = {0.5 * (U.re + V.re), 0.5 * (U.im - V.im)};
+                cplx Bm = {0.5 * (U.im + V.im), -0.5 * (U.re - V.re)};  // (U - conj V)/(2i)
+                double Zc = en[s].re * A.re - en[s].im * A.im;
+                double Zs = en[s].re * Bm.im + en[s].im * Bm.re;
+                double inner = fma(xs[s] / (2 * q + 2), acc[s], -sc * Zs);
+                acc[s] = fma(xs[s] / (2 * q + 1), inner, sc * Zc);
+            }
+        }
+        __syncthreads();
+    }
+    double* yb = y + b * y_stride;
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        if (e < tot && e / g.N1 < nrows) {
+            int i = e / g.N1, ja = e - i * g.N1;
+            int r = pair_row(tile, i, g.rowsB, g.N2);
+            yb[r + g.N2 * ja] = acc[s];
+        }
+    }
+}
+
+// (M^T y)_n for n < nd, chunk blockIdx.y of rows k:
+//   sum_{k in chunk, k <= n, k+n even} (eps_k/pi) Lam((n-k)/2) Lam((n+k)/2) y_k
+__global__ void k_dense_t(int nd, int chunk, const double* __restrict__ lam, const double* __restrict__ y,
+                          int64_t y_stride, double* __restrict__ part, int64_t part_stride) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    int ch = blockIdx.y;
+    int b = blockIdx.z;
+    if (n >= nd) return;
+    const double* yb = y + b * y_stride;
+    int k0 = ch * chunk, k1 = min(n + 1, k0 + chunk);
+    int k = k0;
+    if ((n - k) & 1) ++k;
+    double acc = 0;
+    for (; k < k1; k += 2) {
+        double e = (k == 0) ? 0.3183098861837907 : 0.6366197723675814;
+        acc = fma(e * lam[(n - k) >> 1] * lam[(n + k) >> 1], yb[k], acc);
+    }
+    part[b * part_stride + (int64_t)ch * nd + n] = acc;
+}
+
+__global__ void k_dense_t_reduce(int nd, int nchunk, int chunk, const double* __restrict__ part,
+                                 int64_t part_stride, double* __restrict__ out, int64_t out_stride) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.z;
+    if (n >= nd) return;
+    const double* pb = part + b * part_stride;
+    double s = 0;
+    int last = min(nchunk - 1, n / chunk);
+    for (int ch = 0; ch <= last; ++ch) s += pb[(int64_t)ch * nd + n];
+    out[b * out_stride + n] = s;
+}
+
+// u_j = sum_k (eps_k/N) y_k cos(k theta_j): DFT of (eps_k/N) y_k e^{i pi k/(2N)},
+// u at row j(m) = Re V_m.
+__global__ __launch_bounds__(FFT_THREADS) void k_dct3_passA(Geo g, const double* __restrict__ y, int64_t y_stride,
+                                                           cplx* __restrict__ X, int64_t x_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int na0 = blockIdx.x * g.colsA;
+    const int b = blockIdx.z;
+    const double* yb = y + b * y_stride;
+    const int tot = g.colsA * g.N2;
+    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+        int col = e % g.colsA, nbi = e / g.colsA;
+        int n = na0 + col + g.N1 * nbi;
+        double a = yb[n] * ((n == 0) ? 1.0 : 2.0) / N;
+        buf[col * g.N2 + nbi] = cscale(half_shift(n, N), a);
+    }
+    __syncthreads();
+    lds_fft(buf, g.N2, g.colsA, g.twN2);
+    passA_store(g, buf, na0, X + b * x_stride);
+}
+
+__global__ __launch_bounds__(FFT_THREADS) void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64_t x_stride,
+                                                           double* __restrict__ u, int64_t u_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int jb0 = blockIdx.x * g.rowsB;
+    const int b = blockIdx.z;
+    passB_load(g, buf, jb0, X + b * x_stride);
+    __syncthreads();
+    lds_fft(buf, g.N1, g.rowsB, g.twN1);
+    const int tot = g.rowsB * g.N1;
+    double* ub = u + b * u_stride;
+    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+        int r = e / g.N1, ja = e - r * g.N1;
+        int m = jb0 + r + g.N2 * ja;
+        ub[row_of(m, N)] = buf[e].re;
+    }
+}
+
+// Transposed far field, pass A: for every term (b, m), ascending m, the DFT
+// input at m is rho at row j = j(m) (conjugated when 2m >= N) with
+//   rho_j = u_j e^{i (m+1/2)(theta_j - pi/2)} (2 sin theta_j)^{-m-1/2} [j in block b].
+__global__ __launch_bounds__(FFT_THREADS) void k_tfar_passA(Geo g, FarParams F, const double* __restrict__ u,
+                                                           int64_t u_stride, cplx* __restrict__ X,
+                                                           int64_t x_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int na0 = blockIdx.x * g.colsA;
+    const int b = blockIdx.z;
+    const double* ub = u + b * u_stride;
+    cplx* Xb = X + b * x_stride;
+    const int tot = g.colsA * g.N2;
+    const double pi = 3.141592653589793;
+    cplx gm[FFT_VPT], rq[FFT_VPT];
+    int blk[FFT_VPT];
+    bool cj[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        gm[s] = rq[s] = {0, 0};
+        blk[s] = -1;
+        cj[s] = false;
+        if (e < tot) {
+            int col = e % g.colsA, nbi = e / g.colsA;
+            int m = na0 + col + g.N1 * nbi;
+            int j = row_of(m, N);
+            cj[s] = (2 * m >= N);
+            blk[s] = row_block(F, j, N);
+            double d = pi * (double)(2 * j + 1 - N) / (2.0 * N);
+            int jj = min(j, N - 1 - j);
+            double sn = sin((jj + 0.5) * pi / N);
+            double q = 1.0 / (2.0 * sn);
+            double ps, pc, rs, rc;
+            sincos(0.5 * d, &ps, &pc);
+            sincos(d, &rs, &rc);
+            double r0 = sqrt(q) * ub[j];
+            gm[s] = {pc * r0, ps * r0};
+            rq[s] = {rc * q, rs * q};
+        }
+    }
+    for (int m = 0; m < F.Mmax; ++m) {
+        for (int t = 0; t < F.nterm; ++t) {
+            if (F.term_m[t] != m) continue;
+            const int tb = F.term_blk[t];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) {
+                int e = threadIdx.x + s * FFT_THREADS;
+                if (e < tot) {
+                    int col = e % g.colsA, nbi = e / g.colsA;
+                    cplx v = (blk[s] == tb) ? gm[s] : cplx{0, 0};
+                    if (cj[s]) v.im = -v.im;
+                    buf[col * g.N2 + nbi] = v;
+                }
+            }
+            __syncthreads();
+            lds_fft(buf, g.N2, g.colsA, g.twN2);
+            passA_store(g, buf, na0, Xb + (int64_t)t * N);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) gm[s] = cmul(gm[s], rq[s]);
+    }
+}
+
+// Transposed far field, pass B: out_n = sum_terms C_n h_{m,n} [n >= nlo_b]
+// Re(e^{i pi n/(2N)} U_n), descending m (h by multiplication only).
+__global__ __launch_bounds__(FFT_THREADS) void k_tfar_passB(Geo g, FarParams F, const cplx* __restrict__ X,
+                                                           int64_t x_stride, double* __restrict__ out,
+                                                           int64_t out_stride) {
+    __shared__ cplx buf[FFT_CAP];
+    const int N = g.N;
+    const int jb0 = blockIdx.x * g.rowsB;
+    const int b = blockIdx.z;
+    const cplx* Xb = X + b * x_stride;
+    const int tot = g.rowsB * g.N1;
+    double acc[FFT_VPT], h[FFT_VPT];
+    cplx en[FFT_VPT];
+    int nn[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        acc[s] = 0;
+        h[s] = 0;
+        en[s] = {0, 0};
+        nn[s] = -1;
+        if (e < tot) {
+            int r = e / g.N1, ja = e - r * g.N1;
+            int n = jb0 + r + g.N2 * ja;
+            nn[s] = n;
+            if (n >= F.nd) {
+                en[s] = cscale(half_shift(n, N), stieltjes_C((double)n));
+                double hv = 1;
+                for (int j = 1; j < F.Mmax; ++j) hv *= (j - 0.5) * (j - 0.5) / (j * (n + j + 0.5));
+                h[s] = hv;
+            }
+        }
+    }
+    for (int m = F.Mmax - 1; m >= 0; --m) {
+        for (int t = 0; t < F.nterm; ++t) {
+            if (F.term_m[t] != m) continue;
+            const int nlo = F.blk[F.term_blk[t]].nlo;
+            passB_load(g, buf, jb0, Xb + (int64_t)t * N);
+            __syncthreads();
+            lds_fft(buf, g.N1, g.rowsB, g.twN1);
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) {
+                int e = threadIdx.x + s * FFT_THREADS;
+                if (e < tot && nn[s] >= nlo) {
+                    cplx U = buf[e];
+                    acc[s] = fma(h[s], en[s].re * U.re - en[s].im * U.im, acc[s]);
+                }
+            }
+            __syncthreads();
+        }
+        if (m > 0) {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s)
+                if (nn[s] >= 0) h[s] *= m * (nn[s] + m + 0.5) / ((m - 0.5) * (m - 0.5));
+        }
+    }
+    double* ob = out + b * out_stride;
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        if (e < tot) ob[nn[s]] = acc[s];
+    }
+}
+
+// Transposed near field.  (1) k_near_items with c == null gives each
+// (row, chunk) transfer matrix; (2) k_tnear_scan chains them per row into the
+// state (P, D) at every chunk start; (3) k_tnear_accum reruns each chunk from
+// its true state for 256 rows of one segment and sums over the rows
+//   out_n += P_n(x_j) (u_j + (-1)^n u_{N-1-j})
+// through an LDS tile, 32 degrees at a time.
+__global__ void k_tnear_scan(NearParams NP, const double* __restrict__ items, int64_t it_stride,
+                             double* __restrict__ st, int64_t st_stride) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.z;
+    if (j >= NP.jnear) return;
+    int sgi = -1;
+    for (int s = 0; s < NP.nseg; ++s)
+        if (j >= NP.seg[s].jlo && j < NP.seg[s].jhi) sgi = s;
+    if (sgi < 0) return;
+    const Seg S = NP.seg[sgi];
+    const double* it = items + b * it_stride;
+    double* so = st + b * st_stride;
+    int nrows = S.jhi - S.jlo;
+    double P = 1, D = 0;
+    for (int ch = 0; ch < S.nchunk; ++ch) {
+        int id = S.item_off + ch * nrows + (j - S.jlo);
+        so[2 * id] = P;
+        so[2 * id + 1] = D;
+        const double* q = it + (int64_t)id * 8;
+        if (ch == 0) {
+            P = q[0];
+            D = q[1];
+        } else {
+            double Pn = P * q[0] + D * q[2];
+            double Dn = P * q[1] + D * q[3];
+            P = Pn;
+            D = Dn;
+        }
+    }
+}
+
+constexpr int TN_ROWS = 256;
+constexpr int TN_STEPS = 32;
+
+// grid.x enumerates (segment, chunk, row group) with the table from the plan
+__global__ __launch_bounds__(TN_ROWS) void k_tnear_accum(int N, NearParams NP, const int* __restrict__ wg_seg,
+                                                          const int* __restrict__ wg_rg_off,
+                                                          const double* __restrict__ A,
+                                                          const double* __restrict__ B, const double* __restrict__ u,
+                                                          int64_t u_stride, const double* __restrict__ st,
+                                                          int64_t st_stride, double* __restrict__ part,
+                                                          int64_t part_stride) {
+    __shared__ double tile[TN_STEPS][TN_ROWS + 1];
+    const int wgid = blockIdx.x;
+    const int b = blockIdx.z;
+    const int sgi = wg_seg[wgid];
+    const Seg S = NP.seg[sgi];
+    const int nrows = S.jhi - S.jlo;
+    const int ngroups = (nrows + TN_ROWS - 1) / TN_ROWS;
+    // local index inside the segment: chunk-major over row groups
+    int loc = wgid - wg_rg_off[2 * sgi];
+    int ch = loc / ngroups;
+    int grp = loc - ch * ngroups;
+    int rg_global = wg_rg_off[2 * sgi + 1] + grp;
+    int row = grp * TN_ROWS + threadIdx.x;
+    bool act = row < nrows;
+    int j = S.jlo + (act ? row : 0);
+    const double* ub = u + b * u_stride;
+    const double* so = st + b * st_stride;
+    double uj = act ? ub[j] : 0.0, um = act ? ub[N - 1 - j] : 0.0;
+    const double pi = 3.141592653589793;
+    double sn = sin(0.5 * (j + 0.5) * pi / N);
+    double uu = 2.0 * sn * sn;
+    int id = S.item_off + ch * nrows + (act ? row : 0);
+    double p = act ? so[2 * id] : 0.0, d = act ? so[2 * id + 1] : 0.0;
+    int n0 = ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
+    double* pb = part + b * part_stride + (int64_t)rg_global * N;
+    for (int nb0 = n0; nb0 < n1; nb0 += TN_STEPS) {
+        int cnt = min(TN_STEPS, n1 - nb0);
+        for (int i = 0; i < cnt; ++i) {
+            int n = nb0 + i;
+            tile[i][threadIdx.x] = p * ((n & 1) ? uj - um : uj + um);
+            double dn = fma(A[n], d, -B[n] * uu * p);
+            p += dn;
+            d = dn;
+        }
+        __syncthreads();
+        // 8 threads per degree column, 32 rows each, then a butterfly of 8
+        int col = threadIdx.x >> 3, prt = threadIdx.x & 7;
+        double s = 0;
+        if (col < cnt)
+            for (int r = 0; r < TN_ROWS / 8; ++r) s += tile[col][prt * (TN_ROWS / 8) + r];
+        s += __shfl_xor(s, 1, 8);
+        s += __shfl_xor(s, 2, 8);
+        s += __shfl_xor(s, 4, 8);
+        if (prt == 0 && col < cnt) pb[nb0 + col] = s;
+        __syncthreads();
+    }
+}
+
+// c_n = (n + 1/2) (dense_n [n < nd] + far_n + sum_rg near parts [nd <= n < nend(rg)])
+__global__ void k_idlt_final(int N, int nd, int nrg, const int* __restrict__ rg_nend, const double* __restrict__ dense,
+                             int64_t dense_stride, const double* __restrict__ far, int64_t far_stride,
+                             const double* __restrict__ part, int64_t part_stride, double* __restrict__ c,
+                             int64_t c_stride) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.z;
+    if (n >= N) return;
+    double s;
+    if (n < nd) {
+        s = dense[b * dense_stride + n];
+    } else {
+        s = far ? far[b * far_stride + n] : 0.0;
+        const double* pb = part + b * part_stride;
+        for (int r = 0; r < nrg; ++r)
+            if (n < rg_nend[r]) s += pb[(int64_t)r * N + n];
+    }
+    c[b * c_stride + n] = (n + 0.5) * s;
+}
+
 }  // namespace dlt
 
 // ================================================================ host ====
@@ -728,6 +1191,10 @@ void work_carve(const Plan& p, int64_t nb, void* base, Work& w) {
     w.schat = (int64_t)(al256(p.ws_chat) / sizeof(double));
     w.vec = (double*)take(p.ws_vec);
     w.svec = (int64_t)(al256(p.ws_vec) / sizeof(double));
+    w.states = (double*)take(p.ws_states);
+    w.sstates = (int64_t)(al256(p.ws_states) / sizeof(double));
+    w.part = (double*)take(p.ws_part);
+    w.spart = (int64_t)(al256(p.ws_part) / sizeof(double));
 }
 
 hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, hipStream_t s) {
@@ -787,6 +1254,52 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, const double*
     int QG = (tilesA * nb >= 256) ? 1 : Q;
     k_ndct_passA<<<dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, QG, chat, p.N, w.X, w.sX);
     k_ndct_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, w.X, w.sX, dth, f, p.N);
+    return hipGetLastError();
+}
+
+hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double* wts, const double* dth,
+                       double* c, Work& w, hipStream_t s) {
+    const int N = (int)p.N;
+    const int nd = p.nd;
+    const Geo& g = p.geo;
+    const int Q = p.L / 2;
+    const int tilesA = g.N1 / g.colsA;
+    int QG = (tilesA * nb >= 256) ? 1 : Q;
+    double* y = w.chat;  // T^T D_w f, stride w.schat
+    // transposed Taylor series: y = T^T (w f)
+    k_tndct_passA<<<dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, QG, f, N, wts, dth, w.X, w.sX);
+    int tilesB = (g.N2 == 1) ? 1 : g.N2 / g.rowsB;
+    k_tndct_passB<<<dim3(tilesB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, w.X, w.sX, y, w.schat);
+    // dense block of M^T for n < nd
+    double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
+    k_dense_t<<<dim3((nd + 255) / 256, p.dense_nchunk, (unsigned)nb), 256, 0, s>>>(nd, p.dense_chunk, p.d_lam, y,
+                                                                                 w.schat, w.dense, w.sdense);
+    k_dense_t_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                         w.dense, w.sdense, dense_out, w.sdense);
+    const double* far = nullptr;
+    const NearParams& NP = p.near;
+    if (N > nd) {
+        // u = C D_eps y on the grid
+        double* u = w.vec;
+        k_dct3_passA<<<dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, y, w.schat, w.X, w.sX);
+        k_dct3_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, w.X, w.sX, u, w.svec);
+        // transposed far field
+        k_tfar_passA<<<dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.far, u, w.svec, w.X, w.sX);
+        k_tfar_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.far, w.X, w.sX, w.v, w.sv);
+        far = w.v;
+        // transposed near field
+        if (NP.nitems > 0) {
+            k_near_items<<<dim3((NP.nitems + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(
+                N, NP, p.d_recA, p.d_recB, nullptr, 0, w.items, w.sitems);
+            k_tnear_scan<<<dim3((NP.jnear + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(NP, w.items, w.sitems,
+                                                                                    w.states, w.sstates);
+            k_tnear_accum<<<dim3(p.tn_wg, 1, (unsigned)nb), TN_ROWS, 0, s>>>(
+                N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_recA, p.d_recB, u, w.svec, w.states, w.sstates, w.part,
+                w.spart);
+        }
+    }
+    k_idlt_final<<<dim3((N + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(
+        N, nd, (N > nd) ? p.tn_nrg : 0, p.d_tn_rgnend, dense_out, w.sdense, far, w.sv, w.part, w.spart, c, N);
     return hipGetLastError();
 }
 

@@ -15,7 +15,9 @@ struct Work {
     double* dense;    // dense-block partials (+ reduced slab at the end)
     double* chat;     // Chebyshev coefficients
     double* vec;      // spare length-N vector
-    int64_t sX, sv, sitems, snear, sdense, schat, svec;  // per-instance strides (elements)
+    double* states;   // near-field states at chunk starts (inverse)
+    double* part;     // near-field per-row-group sums over degrees (inverse)
+    int64_t sX, sv, sitems, snear, sdense, schat, svec, sstates, spart;  // per-instance strides (elements)
 };
 size_t work_bytes(const Plan& p, int64_t nb);
 void work_carve(const Plan& p, int64_t nb, void* base, Work& w);
@@ -27,5 +29,9 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, double* chat
 // f = sum_n chat_n cos(n theta^leg), dth = theta^leg - theta^cheb1
 hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, const double* dth, double* f, Work& w,
                     hipStream_t s);
+
+// c = D_s M^T T^T D_w f (inverse transform), wts/dth from the nodes
+hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double* wts, const double* dth,
+                       double* c, Work& w, hipStream_t s);
 
 }  // namespace dlt

@@ -204,6 +204,28 @@ int plan_build(int64_t N, Plan& p) {
         add_seg(0, jprev, (int)N);
         for (int b = 1; b < F.nblk; ++b) add_seg(F.blk[b].jlo, F.blk[b].jhi, F.blk[b].nlo);
         Nr.nitems = items;
+        // work-group tables of the transposed near field (256 rows x one chunk)
+        {
+            std::vector<int> wgseg, segoff(2 * MAX_SEGS, 0), rgnend;
+            int wg = 0, rg = 0;
+            for (int s = 0; s < Nr.nseg; ++s) {
+                const Seg& S = Nr.seg[s];
+                int ng = (S.jhi - S.jlo + 255) / 256;
+                segoff[2 * s] = wg;
+                segoff[2 * s + 1] = rg;
+                for (int i = 0; i < S.nchunk * ng; ++i) wgseg.push_back(s);
+                for (int i = 0; i < ng; ++i) rgnend.push_back(S.nend);
+                wg += S.nchunk * ng;
+                rg += ng;
+            }
+            p.tn_wg = wg;
+            p.tn_nrg = rg;
+            if (wg > 0) {
+                if ((rc = upload(wgseg.data(), wgseg.size() * sizeof(int), (void**)&p.d_tn_wgseg))) return rc;
+                if ((rc = upload(rgnend.data(), rgnend.size() * sizeof(int), (void**)&p.d_tn_rgnend))) return rc;
+            }
+            if ((rc = upload(segoff.data(), segoff.size() * sizeof(int), (void**)&p.d_tn_segoff))) return rc;
+        }
         Nr.jnear = (F.nblk > 1) ? F.blk[1].jhi : jprev;  // rows j < jnear may carry near terms
         if (Nr.nseg == 0) Nr.jnear = 0;
         // recurrence coefficient tables
@@ -265,15 +287,18 @@ int plan_build(int64_t N, Plan& p) {
     p.ws_dense = (size_t)(p.dense_nchunk + 1) * p.nd * sizeof(double);
     p.ws_chat = (size_t)N * sizeof(double);
     p.ws_vec = (size_t)N * sizeof(double);
+    p.ws_states = (size_t)Nr.nitems * 2 * sizeof(double);
+    p.ws_part = (size_t)p.tn_nrg * N * sizeof(double);
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     p.ws_per_inst = al(p.ws_X) + al(p.ws_v) + al(p.ws_items) + al(p.ws_near) + al(p.ws_dense) +
-                    al(p.ws_chat) + al(p.ws_vec);
+                    al(p.ws_chat) + al(p.ws_vec) + al(p.ws_states) + al(p.ws_part);
     p.ws_shared = 3 * al((size_t)N * sizeof(double));  // theta, w, dtheta
     return 0;
 }
 
 void plan_free(Plan& p) {
-    void* ptrs[] = {p.d_twN1, p.d_twN2, p.d_twHi, p.d_twLo, p.d_lam, p.d_recA, p.d_recB, p.d_guess};
+    void* ptrs[] = {p.d_twN1, p.d_twN2, p.d_twHi,     p.d_twLo,       p.d_lam,       p.d_recA,
+                    p.d_recB, p.d_guess, p.d_tn_wgseg, p.d_tn_segoff, p.d_tn_rgnend};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();

@@ -76,8 +76,15 @@ struct Plan {
     double* d_recA = nullptr;    // n/(n+1)
     double* d_recB = nullptr;    // (2n+1)/(n+1)
     double* d_guess = nullptr;   // boundary-node initial offsets from theta^cheb1
+    // transposed near field: work-group -> segment table, per-segment
+    // (first work-group, first row group), and nend of every row group
+    int* d_tn_wgseg = nullptr;
+    int* d_tn_segoff = nullptr;
+    int* d_tn_rgnend = nullptr;
+    int tn_wg = 0, tn_nrg = 0;
     // workspace sizes per transform instance (bytes)
     size_t ws_X = 0, ws_v = 0, ws_items = 0, ws_near = 0, ws_dense = 0, ws_chat = 0, ws_vec = 0;
+    size_t ws_states = 0, ws_part = 0;
     size_t ws_per_inst = 0, ws_shared = 0;
     int tgB = 1;       // far-field pass-B term groups
 };
