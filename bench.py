@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput of the fast discrete Legendre transform on one MI355X.
+
+One step = the hot path of the paper's method on one batch of synthetic
+input at N = 2^20 (plain FP64): a forward DLT (nodes, Legendre-to-Chebyshev
+conversion, Taylor-series Chebyshev evaluation), an inverse DLT (the
+transposed pipeline) and a standalone Chebyshev-at-Legendre-grid evaluation.
+Inputs are resident in HBM before timing starts.  `value` counts transforms
+(3 per instance per step) per second.
+
+Prints one JSON line; diagnostics go to stderr.  Options:
+  --gpus N      must be 1 (this build runs on one GPU)
+  --steps K     timed steps (default 20)
+  --warmup W    untimed steps first (default 3)
+  --n N         transform length (default 2^20)
+  --batch B     instances per step (default 1)
+  --cpu-sample K  output indices the CPU oracle evaluates for cpu_baseline
+  --no-cpu      skip the CPU baseline
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name, N, info, nb):
+    """Algorithmic HBM bytes of one launch of `name` (inputs read once,
+    outputs and DFT intermediates written once): the per-kernel byte model."""
+    T, Q, G = info["far_terms"], info["L"] // 2, info["tgB"]
+    per = {
+        "k_far_passA": 8 * N + 16 * N * T,
+        "k_far_passB": 16 * N * T + 8 * N * G,
+        "k_tfar_passA": 8 * N + 16 * N * T,
+        "k_tfar_passB": 16 * N * T + 8 * N,
+        "k_ndct_passA": 8 * N + 16 * N * Q,
+        "k_ndct_passB": 16 * N * Q + 16 * N,
+        "k_tndct_passA": 24 * N + 16 * N * Q,
+        "k_tndct_passB": 16 * N * Q + 8 * N,
+        "k_dct2_passA": 8 * N * G + 16 * N,
+        "k_dct2_passB": 16 * N + 8 * N,
+        "k_dct3_passA": 8 * N + 16 * N,
+        "k_dct3_passB": 16 * N + 8 * N,
+    }
+    return per.get(name, None) if name in per else None, nb
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        sys.exit("bench.py: this build runs on a single GPU; --gpus must be 1 "
+                 "(a batch would shard across GPUs with no exchange, see DESIGN.md)")
+
+    import numpy as np
+    import torch
+
+    import paper_1505_00354_amd as pk
+    from paper_1505_00354_amd import workloads as wl
+
+    N, B = args.n, args.batch
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pk.lib()
+    info = pk.plan_info(N)
+    log("plan", info)
+    c = torch.from_numpy(wl.coeffs_algebraic(N, 2, batch=B)).to(dev)
+    fin = torch.from_numpy(wl.values_normal(N, 4, batch=B)).to(dev)
+    chat = torch.from_numpy(wl.coeffs_algebraic(N, 3, batch=B)).to(dev)
+    f = torch.empty_like(c)
+    c2 = torch.empty_like(c)
+    g = torch.empty_like(c)
+
+    def step():
+        pk.dlt_forward(c, out=f)
+        pk.dlt_inverse(fin, out=c2)
+        pk.cheb_eval_leggrid(chat, out=g)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K steps bracketed by synchronisations and events on the
+    # current stream; the kernel trace records per-launch events on the same
+    # stream throughout
+    pk.trace_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pk.trace_enable(False)
+    kern = pk.trace_collect()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = 3 * B * 1000.0 / ms_step
+    log(f"ms/step {ms_step:.4f} (wall {1000 * wall / args.steps:.4f})")
+    tot = sum(v[0] for v in kern.values())
+    for k, (ms, cnt) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
+        log(f"  {k:20s} {ms / cnt * 1000:10.2f} us/launch  x{cnt:4d}  {100 * ms / tot:5.1f}%")
+
+    # roofline of the dominant kernel with a byte model
+    roof = None
+    ranked = sorted(kern.items(), key=lambda kv: -kv[1][0])
+    for name, (ms, cnt) in ranked:
+        by, _ = kernel_bytes(name, N, info, B)
+        if by is not None:
+            avg_s = ms / cnt / 1000.0
+            ach = by * B / avg_s / 1e9
+            roof = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": by * B, "avg_launch_us": round(avg_s * 1e6, 2),
+                    "share_of_step": round(ms / tot, 3)}
+            break
+    dominant = ranked[0][0] if ranked else None
+
+    out = {
+        "metric": "DLT transforms/s + HBM GB/s at N=2^16..2^20, plain FP64 vs batched/FP32-bulk",
+        "value": round(value, 2),
+        "unit": "transforms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"single plain FP64 DLT + IDLT + Chebyshev-at-Legendre-grid evaluation, N={N}",
+                   "N": N, "batch": B, "transforms_per_step": 3 * B,
+                   "inputs": "c_n=N(0,1)/(n+1) seed 2; IDLT f_k=N(0,1) seed 4; chat_n=N(0,1)/(n+1) seed 3"},
+        "dominant_kernel": dominant,
+        "roofline": roof,
+        "kernel_us": {k: round(v[0] / v[1] * 1000, 2) for k, v in kern.items()},
+    }
+
+    if not args.no_cpu:
+        import oracle
+
+        cores = oracle.set_threads(0)
+        K = min(args.cpu_sample, N)
+        idx = wl.sample_indices(N, K, 5)
+        cc = wl.coeffs_algebraic(N, 2)[0]
+        t0 = time.perf_counter()
+        th, _ = oracle.nodes(N, idx=idx)
+        oracle.dlt(cc, th)
+        dt = time.perf_counter() - t0
+        per_transform = dt * N / len(idx)
+        out["cpu_baseline"] = {
+            "value": round(1.0 / per_transform, 6), "unit": "transforms/s", "cores": cores, "kind": "oracle",
+            "sample": f"forward DLT at N={N}: {len(idx)} of {N} outputs (Newton nodes + direct recurrence sum, "
+                      f"FP64 build) in {dt:.2f} s, extrapolated x{N / len(idx):.0f} to one transform"}
+        log("cpu baseline", out["cpu_baseline"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -76,6 +76,26 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
 /* Human-readable text of a status code (static storage). */
 const char* dlt_status_string(int status);
 
+/* Plan parameters for size N (creates the plan if needed).  Writes up to
+ * max_fields of: L (Taylor terms), nd (dense columns), far-field terms,
+ * far-field blocks, max terms per block, near-field chunk items, near rows
+ * per end, N1, N2, pass-A tile columns, pass-B tile rows, pass-B term groups,
+ * transposed-near work-groups, transposed-near row groups, near-field
+ * recurrence steps (rows x degrees, one end), boundary nodes, workspace bytes
+ * per instance.  Returns the number of fields available or a status < 0. */
+int dlt_plan_query(int64_t N, int64_t* out, int max_fields);
+
+/* Kernel trace.  While enabled, every kernel the library launches is
+ * bracketed by two hipEvents recorded on the launch stream (no host
+ * synchronisation at launch time).  dlt_trace_collect waits for the recorded
+ * events, writes at most max_kernels entries -- kernel name (NUL-terminated,
+ * truncated to name_len-1 bytes, at names + i*name_len), total milliseconds
+ * and launch count, summed over launches -- clears the record and returns the
+ * number of entries written (>= 0) or a negative status.  Intended for
+ * measurement runs; tracing is off by default. */
+int dlt_trace_enable(int on);
+int dlt_trace_collect(int max_kernels, char* names, int name_len, double* total_ms, int64_t* counts);
+
 /* Frees every cached plan and workspace (device memory).  Waits for the
  * device to finish; the library may be used again afterwards. */
 int dlt_release(void);

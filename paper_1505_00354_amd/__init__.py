@@ -49,8 +49,12 @@ def lib():
         L.dlt_status_string.argtypes = [ctypes.c_int]
         L.dlt_status_string.restype = ctypes.c_char_p
         L.dlt_release.argtypes = []
+        L.dlt_plan_query.argtypes = [i64, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        L.dlt_trace_enable.argtypes = [ctypes.c_int]
+        L.dlt_trace_collect.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         for name in ("leg_nodes_weights", "leg2cheb", "cheb_eval_leggrid", "dlt_forward", "dlt_inverse",
-                     "dlt_release"):
+                     "dlt_release", "dlt_plan_query", "dlt_trace_enable", "dlt_trace_collect"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -128,3 +132,36 @@ def dlt_inverse(f, out=None):
 
 def release():
     _check(lib().dlt_release(), "dlt_release")
+
+
+PLAN_FIELDS = ("L", "nd", "far_terms", "far_blocks", "far_mmax", "near_items", "near_rows", "N1", "N2",
+               "colsA", "rowsB", "tgB", "tnear_wg", "tnear_rg", "near_steps", "boundary_nodes", "ws_bytes")
+
+
+def plan_info(N):
+    """The library's plan parameters for size N, as a dict."""
+    buf = (ctypes.c_int64 * 32)()
+    n = lib().dlt_plan_query(N, buf, 32)
+    if n < 0:
+        _check(n, "dlt_plan_query")
+    return {k: int(buf[i]) for i, k in enumerate(PLAN_FIELDS[:n])}
+
+
+def trace_enable(on=True):
+    _check(lib().dlt_trace_enable(1 if on else 0), "dlt_trace_enable")
+
+
+def trace_collect(max_kernels=64):
+    """{kernel name: (total ms, launches)} since the last collect; waits for
+    the recorded events."""
+    names = ctypes.create_string_buffer(max_kernels * 48)
+    ms = (ctypes.c_double * max_kernels)()
+    cnt = (ctypes.c_int64 * max_kernels)()
+    n = lib().dlt_trace_collect(max_kernels, names, 48, ms, cnt)
+    if n < 0:
+        _check(n, "dlt_trace_collect")
+    out = {}
+    for i in range(n):
+        nm = names.raw[i * 48:(i + 1) * 48].split(b"\0", 1)[0].decode()
+        out[nm] = (ms[i], int(cnt[i]))
+    return out

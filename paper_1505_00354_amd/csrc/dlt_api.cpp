@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string.h>
+
 #include <algorithm>
 #include <map>
 #include <memory>
@@ -226,6 +228,45 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
         if ((rc = hip_status(run_inverse(*p, nb, f + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, stream)))) return rc;
     }
     return DLT_OK;
+}
+
+int dlt_plan_query(int64_t N, int64_t* out, int max_fields) {
+    int rc = check_size(N, 1);
+    if (rc) return rc;
+    if (!out || max_fields < 0) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan(N, &p))) return rc;
+    int64_t steps = 0;
+    for (int s = 0; s < p->near.nseg; ++s)
+        steps += (int64_t)(p->near.seg[s].jhi - p->near.seg[s].jlo) * p->near.seg[s].nend;
+    const int64_t v[] = {p->L, p->nd, p->far.nterm, p->far.nblk, p->far.Mmax, p->near.nitems, p->near.jnear,
+                         p->geo.N1, p->geo.N2, p->geo.colsA, p->geo.rowsB, p->tgB, p->tn_wg, p->tn_nrg, steps,
+                         p->nodes.kb, (int64_t)p->ws_per_inst};
+    int n = (int)(sizeof(v) / sizeof(v[0]));
+    for (int i = 0; i < n && i < max_fields; ++i) out[i] = v[i];
+    return n;
+}
+
+int dlt_trace_enable(int on) {
+    trace_set(on != 0);
+    return DLT_OK;
+}
+
+int dlt_trace_collect(int max_kernels, char* names, int name_len, double* total_ms, int64_t* counts) {
+    if (max_kernels < 0 || name_len < 1 || (max_kernels > 0 && (!names || !total_ms || !counts)))
+        return DLT_ERR_INVALID_ARG;
+    std::vector<std::pair<std::string, std::pair<double, int64_t>>> v;
+    if (trace_collect(v) != 0) return DLT_ERR_HIP;
+    int n = 0;
+    for (auto& kv : v) {
+        if (n >= max_kernels) break;
+        std::string s = kv.first.substr(0, (size_t)name_len - 1);
+        memcpy(names + (size_t)n * name_len, s.c_str(), s.size() + 1);
+        total_ms[n] = kv.second.first;
+        counts[n] = kv.second.second;
+        ++n;
+    }
+    return n;
 }
 
 int dlt_release(void) {

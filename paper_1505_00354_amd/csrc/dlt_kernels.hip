@@ -12,6 +12,11 @@
 // 2N-1-2m (m >= N/2); this is how sums over e^{i n theta_j} are formed.
 #include "dlt_kernels.hpp"
 
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 namespace dlt {
 
 __device__ __forceinline__ int row_of(int m, int N) { return (2 * m < N) ? 2 * m : 2 * N - 1 - 2 * m; }
@@ -1166,6 +1171,70 @@ __global__ void k_idlt_final(int N, int nd, int nrg, const int* __restrict__ rg_
 // ================================================================ host ====
 namespace dlt {
 
+// ---- kernel trace: start/stop events around every launch while enabled
+namespace trace {
+struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+};
+static std::mutex mu;
+static bool on = false;
+static std::vector<Rec> recs;
+static std::vector<hipEvent_t> pool;
+
+static hipEvent_t take() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+}  // namespace trace
+
+bool trace_on() { return trace::on; }
+
+void trace_set(bool enable) {
+    std::lock_guard<std::mutex> lk(trace::mu);
+    trace::on = enable;
+}
+
+// launches `fn` bracketed by events when tracing
+template <class F>
+static void traced(const char* name, hipStream_t s, F&& fn) {
+    if (!trace::on) {
+        fn();
+        return;
+    }
+    std::lock_guard<std::mutex> lk(trace::mu);
+    trace::Rec r{name, trace::take(), trace::take()};
+    (void)hipEventRecord(r.a, s);
+    fn();
+    (void)hipEventRecord(r.b, s);
+    trace::recs.push_back(r);
+}
+
+int trace_collect(std::vector<std::pair<std::string, std::pair<double, int64_t>>>& out) {
+    std::lock_guard<std::mutex> lk(trace::mu);
+    std::map<std::string, std::pair<double, int64_t>> acc;
+    for (auto& r : trace::recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return -3;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return -3;
+        auto& a = acc[r.name];
+        a.first += ms;
+        a.second += 1;
+        trace::pool.push_back(r.a);
+        trace::pool.push_back(r.b);
+    }
+    trace::recs.clear();
+    out.assign(acc.begin(), acc.end());
+    return 0;
+}
+
+
 static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t work_bytes(const Plan& p, int64_t nb) { return (size_t)nb * p.ws_per_inst; }
@@ -1202,10 +1271,11 @@ hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, hipSt
     int nh = (P.N + 1) / 2;
     if (P.kb > 0) {
         size_t shm = (7 * 256 + 3) * sizeof(double);
-        k_nodes_boundary<<<P.kb, 256, shm, s>>>(P, p.d_guess, p.d_recA, p.d_recB, theta, w, dth);
+        traced("k_nodes_boundary", s, [&] { k_nodes_boundary<<<P.kb, 256, shm, s>>>(P, p.d_guess, p.d_recA, p.d_recB, theta, w, dth); });
     }
     int ni = nh - P.kb;
-    if (ni > 0) k_nodes_interior<<<(ni + 255) / 256, 256, 0, s>>>(P, theta, w, dth);
+    if (ni > 0)
+        traced("k_nodes_interior", s, [&] { k_nodes_interior<<<(ni + 255) / 256, 256, 0, s>>>(P, theta, w, dth); });
     return hipGetLastError();
 }
 
@@ -1216,32 +1286,32 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, double* chat
     // dense block: partials then reduction into the last slab of `dense`
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
     dim3 gd((nd + 255) / 256, p.dense_nchunk, (unsigned)nb);
-    k_dense<<<gd, 256, 0, s>>>(N, nd, p.dense_chunk, p.d_lam, c, N, w.dense, w.sdense);
+    traced("k_dense", s, [&] { k_dense<<<gd, 256, 0, s>>>(N, nd, p.dense_chunk, p.d_lam, c, N, w.dense, w.sdense); });
     if (N <= nd) {
-        k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
-                                                                           w.dense, w.sdense, chat, N);
+        traced("k_dense_reduce", s, [&] { k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                           w.dense, w.sdense, chat, N); });
         return hipGetLastError();
     }
-    k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
-                                                                       w.dense, w.sdense, dense_out, w.sdense);
+    traced("k_dense_reduce", s, [&] { k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                       w.dense, w.sdense, dense_out, w.sdense); });
     // near field
     const NearParams& NP = p.near;
     if (NP.nitems > 0)
-        k_near_items<<<dim3((NP.nitems + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(N, NP, p.d_recA, p.d_recB, c, N,
-                                                                                w.items, w.sitems);
+        traced("k_near_items", s, [&] { k_near_items<<<dim3((NP.nitems + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(N, NP, p.d_recA, p.d_recB, c, N,
+                                                                                w.items, w.sitems); });
     if (NP.jnear > 0)
-        k_near_combine<<<dim3((NP.jnear + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(NP, w.items, w.sitems, w.near,
-                                                                                 w.snear);
+        traced("k_near_combine", s, [&] { k_near_combine<<<dim3((NP.jnear + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(NP, w.items, w.sitems, w.near,
+                                                                                 w.snear); });
     // far field
     const FarParams& F = p.far;
-    k_far_passA<<<dim3(g.N1 / g.colsA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, F, c, N, w.X, w.sX);
-    k_far_passB<<<dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb), FFT_THREADS, 0, s>>>(g, F, p.tgB, w.X, w.sX, w.v,
-                                                                               w.sv);
+    traced("k_far_passA", s, [&] { k_far_passA<<<dim3(g.N1 / g.colsA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, F, c, N, w.X, w.sX); });
+    traced("k_far_passB", s, [&] { k_far_passB<<<dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb), FFT_THREADS, 0, s>>>(g, F, p.tgB, w.X, w.sX, w.v,
+                                                                               w.sv); });
     // values on the grid -> coefficients
-    k_dct2_passA<<<dim3(g.N1 / g.colsA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.tgB, w.v, w.sv, w.near, w.snear,
-                                                                            NP.jnear, w.X, w.sX);
-    k_dct2_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, nd, w.X, w.sX, dense_out, w.sdense,
-                                                                            chat, N);
+    traced("k_dct2_passA", s, [&] { k_dct2_passA<<<dim3(g.N1 / g.colsA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.tgB, w.v, w.sv, w.near, w.snear,
+                                                                            NP.jnear, w.X, w.sX); });
+    traced("k_dct2_passB", s, [&] { k_dct2_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, nd, w.X, w.sX, dense_out, w.sdense,
+                                                                            chat, N); });
     return hipGetLastError();
 }
 
@@ -1252,8 +1322,8 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, const double*
     const int tilesA = g.N1 / g.colsA;
     // small transforms: split the Taylor pairs over blocks for parallelism
     int QG = (tilesA * nb >= 256) ? 1 : Q;
-    k_ndct_passA<<<dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, QG, chat, p.N, w.X, w.sX);
-    k_ndct_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, w.X, w.sX, dth, f, p.N);
+    traced("k_ndct_passA", s, [&] { k_ndct_passA<<<dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, QG, chat, p.N, w.X, w.sX); });
+    traced("k_ndct_passB", s, [&] { k_ndct_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, w.X, w.sX, dth, f, p.N); });
     return hipGetLastError();
 }
 
@@ -1267,39 +1337,39 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
     int QG = (tilesA * nb >= 256) ? 1 : Q;
     double* y = w.chat;  // T^T D_w f, stride w.schat
     // transposed Taylor series: y = T^T (w f)
-    k_tndct_passA<<<dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, QG, f, N, wts, dth, w.X, w.sX);
+    traced("k_tndct_passA", s, [&] { k_tndct_passA<<<dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, QG, f, N, wts, dth, w.X, w.sX); });
     int tilesB = (g.N2 == 1) ? 1 : g.N2 / g.rowsB;
-    k_tndct_passB<<<dim3(tilesB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, w.X, w.sX, y, w.schat);
+    traced("k_tndct_passB", s, [&] { k_tndct_passB<<<dim3(tilesB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, w.X, w.sX, y, w.schat); });
     // dense block of M^T for n < nd
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
-    k_dense_t<<<dim3((nd + 255) / 256, p.dense_nchunk, (unsigned)nb), 256, 0, s>>>(nd, p.dense_chunk, p.d_lam, y,
-                                                                                 w.schat, w.dense, w.sdense);
-    k_dense_t_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
-                                                                         w.dense, w.sdense, dense_out, w.sdense);
+    traced("k_dense_t", s, [&] { k_dense_t<<<dim3((nd + 255) / 256, p.dense_nchunk, (unsigned)nb), 256, 0, s>>>(nd, p.dense_chunk, p.d_lam, y,
+                                                                                 w.schat, w.dense, w.sdense); });
+    traced("k_dense_t_reduce", s, [&] { k_dense_t_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                         w.dense, w.sdense, dense_out, w.sdense); });
     const double* far = nullptr;
     const NearParams& NP = p.near;
     if (N > nd) {
         // u = C D_eps y on the grid
         double* u = w.vec;
-        k_dct3_passA<<<dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, y, w.schat, w.X, w.sX);
-        k_dct3_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, w.X, w.sX, u, w.svec);
+        traced("k_dct3_passA", s, [&] { k_dct3_passA<<<dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, y, w.schat, w.X, w.sX); });
+        traced("k_dct3_passB", s, [&] { k_dct3_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, w.X, w.sX, u, w.svec); });
         // transposed far field
-        k_tfar_passA<<<dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.far, u, w.svec, w.X, w.sX);
-        k_tfar_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.far, w.X, w.sX, w.v, w.sv);
+        traced("k_tfar_passA", s, [&] { k_tfar_passA<<<dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.far, u, w.svec, w.X, w.sX); });
+        traced("k_tfar_passB", s, [&] { k_tfar_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.far, w.X, w.sX, w.v, w.sv); });
         far = w.v;
         // transposed near field
         if (NP.nitems > 0) {
-            k_near_items<<<dim3((NP.nitems + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(
-                N, NP, p.d_recA, p.d_recB, nullptr, 0, w.items, w.sitems);
-            k_tnear_scan<<<dim3((NP.jnear + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(NP, w.items, w.sitems,
-                                                                                    w.states, w.sstates);
-            k_tnear_accum<<<dim3(p.tn_wg, 1, (unsigned)nb), TN_ROWS, 0, s>>>(
+            traced("k_near_items", s, [&] { k_near_items<<<dim3((NP.nitems + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(
+                N, NP, p.d_recA, p.d_recB, nullptr, 0, w.items, w.sitems); });
+            traced("k_tnear_scan", s, [&] { k_tnear_scan<<<dim3((NP.jnear + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(NP, w.items, w.sitems,
+                                                                                    w.states, w.sstates); });
+            traced("k_tnear_accum", s, [&] { k_tnear_accum<<<dim3(p.tn_wg, 1, (unsigned)nb), TN_ROWS, 0, s>>>(
                 N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_recA, p.d_recB, u, w.svec, w.states, w.sstates, w.part,
-                w.spart);
+                w.spart); });
         }
     }
-    k_idlt_final<<<dim3((N + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(
-        N, nd, (N > nd) ? p.tn_nrg : 0, p.d_tn_rgnend, dense_out, w.sdense, far, w.sv, w.part, w.spart, c, N);
+    traced("k_idlt_final", s, [&] { k_idlt_final<<<dim3((N + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(
+        N, nd, (N > nd) ? p.tn_nrg : 0, p.d_tn_rgnend, dense_out, w.sdense, far, w.sv, w.part, w.spart, c, N); });
     return hipGetLastError();
 }
 

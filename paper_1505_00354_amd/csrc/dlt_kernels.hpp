@@ -2,6 +2,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
+#include <utility>
+#include <vector>
+
 #include "dlt_plan.hpp"
 
 namespace dlt {
@@ -33,5 +37,10 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, const double*
 // c = D_s M^T T^T D_w f (inverse transform), wts/dth from the nodes
 hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double* wts, const double* dth,
                        double* c, Work& w, hipStream_t s);
+
+// kernel trace (events around every launch while enabled)
+bool trace_on();
+void trace_set(bool enable);
+int trace_collect(std::vector<std::pair<std::string, std::pair<double, int64_t>>>& out);
 
 }  // namespace dlt
