@@ -114,7 +114,7 @@ def main():
     log(f"ms/step {ms_step:.4f} (wall {1000 * wall / args.steps:.4f})")
     tot = sum(v[0] for v in kern.values())
     for k, (ms, cnt) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
-        log(f"  {k:20s} {ms / cnt * 1000:10.2f} us/launch  x{cnt:4d}  {100 * ms / tot:5.1f}%")
+        log(f"  {k:26s} {ms / cnt * 1000:10.2f} us/launch  x{cnt:4d}  {100 * ms / tot:5.1f}%")
 
     # roofline of the dominant kernel with a byte model
     roof = None

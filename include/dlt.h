@@ -50,7 +50,7 @@ extern "C" {
 #define DLT_ERR_HIP (-3)         /* a HIP runtime call or kernel launch failed */
 #define DLT_ERR_NOMEM (-4)       /* device workspace or plan tables could not be allocated */
 
-#define DLT_MAX_N (1LL << 22)
+#define DLT_MAX_N (1LL << 20)
 
 /* Legendre nodes and weights (Sec. 1; theta form, Sec. 2.1-2.2).
  * theta[k] = arccos(x_k) (increasing), w[k] = w_k, dtheta[k] =

@@ -19,7 +19,7 @@ DLT_ERR_INVALID_ARG = -1
 DLT_ERR_UNSUPPORTED = -2
 DLT_ERR_HIP = -3
 DLT_ERR_NOMEM = -4
-DLT_MAX_N = 1 << 22
+DLT_MAX_N = 1 << 20
 
 _lib = None
 

@@ -101,6 +101,7 @@ struct CallWS {
     double* theta;
     double* w;
     double* dth;
+    double* nscr;  // node scratch
     int64_t nb;  // instances per slice
 };
 
@@ -108,8 +109,8 @@ int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
     size_t per = p.ws_per_inst;
     int64_t nb = batch;
     if (per > 0 && (size_t)nb * per > WS_CAP) nb = (int64_t)(WS_CAP / per);
-    if (nb < 1) nb = 1;
-    size_t shared = p.ws_shared;
+    if (batch > 0 && nb < 1) nb = 1;
+    size_t shared = p.ws_shared + (size_t)64 * NODE_PARTS_MAX * 8 * sizeof(double);
     void* base = nullptr;
     int rc = get_ws(s, shared + work_bytes(p, nb), &base);
     if (rc) return rc;
@@ -117,6 +118,7 @@ int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
     cw.theta = (double*)base;
     cw.w = (double*)((char*)base + vecb);
     cw.dth = (double*)((char*)base + 2 * vecb);
+    cw.nscr = (double*)((char*)base + 3 * vecb);
     work_carve(p, nb, (char*)base + shared, cw.work);
     cw.nb = nb;
     return DLT_OK;
@@ -149,7 +151,9 @@ int leg_nodes_weights(int64_t N, int64_t batch, double* theta, double* w, double
         return DLT_ERR_INVALID_ARG;
     Plan* p;
     if ((rc = get_plan(N, &p))) return rc;
-    if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, stream)))) return rc;
+    CallWS cw;
+    if ((rc = setup_call(*p, 0, stream, cw))) return rc;
+    if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, cw.nscr, stream)))) return rc;
     for (int64_t b = 1; b < batch; ++b) {
         size_t vb = (size_t)N * sizeof(double);
         if (theta && hipMemcpyAsync(theta + b * N, theta, vb, hipMemcpyDeviceToDevice, stream)) return DLT_ERR_HIP;
@@ -171,7 +175,7 @@ int leg2cheb(int64_t N, int64_t batch, const double* c, double* chat, hipStream_
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
         int64_t nb = std::min(cw.nb, batch - b0);
-        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, chat + b0 * N, cw.work, stream)))) return rc;
+        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat + b0 * N, N, cw.work, stream)))) return rc;
     }
     return DLT_OK;
 }
@@ -185,10 +189,10 @@ int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, h
     if ((rc = get_plan(N, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, stream)))) return rc;
+    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, stream)))) return rc;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
         int64_t nb = std::min(cw.nb, batch - b0);
-        if ((rc = hip_status(run_ndct(*p, nb, chat + b0 * N, cw.dth, f + b0 * N, cw.work, stream)))) return rc;
+        if ((rc = hip_status(run_ndct(*p, nb, chat + b0 * N, N, cw.dth, f + b0 * N, cw.work, stream)))) return rc;
     }
     return DLT_OK;
 }
@@ -202,13 +206,13 @@ int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_
     if ((rc = get_plan(N, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, stream)))) return rc;
+    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, stream)))) return rc;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
         int64_t nb = std::min(cw.nb, batch - b0);
         // Chebyshev coefficients of the slice, stride N, in the workspace
         double* chat = cw.work.chat;
-        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, chat, cw.work, stream)))) return rc;
-        if ((rc = hip_status(run_ndct(*p, nb, chat, cw.dth, f + b0 * N, cw.work, stream)))) return rc;
+        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat, cw.work.schat, cw.work, stream)))) return rc;
+        if ((rc = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, f + b0 * N, cw.work, stream)))) return rc;
     }
     return DLT_OK;
 }
@@ -222,7 +226,7 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
     if ((rc = get_plan(N, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, stream)))) return rc;
+    if ((rc = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, stream)))) return rc;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
         int64_t nb = std::min(cw.nb, batch - b0);
         if ((rc = hip_status(run_inverse(*p, nb, f + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, stream)))) return rc;

@@ -22,9 +22,9 @@ __device__ __forceinline__ cplx cconj(cplx a) { return {a.re, -a.im}; }
 __device__ __forceinline__ cplx cmuli(cplx a) { return {-a.im, a.re}; }
 
 // Threads per block of every FFT-carrying kernel, and the LDS capacity in
-// complex doubles one block uses for its tile (64 KiB).
-constexpr int FFT_THREADS = 512;
-constexpr int FFT_CAP = 4096;
+// complex doubles one block uses for its tile (32 KiB).
+constexpr int FFT_THREADS = 256;
+constexpr int FFT_CAP = 2048;
 constexpr int FFT_VPT = FFT_CAP / FFT_THREADS;  // values per thread per stage
 
 // e^{+2 pi i t / len} from a table tw[t] = e^{+2 pi i t / len}, t < len.
@@ -123,6 +123,98 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
             __syncthreads();
         }
         p *= r;
+    }
+}
+
+// Same transform with the length known at compile time (L > 0) so that the
+// stage loop unrolls and index arithmetic becomes shifts; L == 0 falls back
+// to the run-time length `len`.
+template <int L>
+__device__ __forceinline__ void lds_fft_t(cplx* buf, int len, int cols, const cplx* __restrict__ tw) {
+    if constexpr (L == 0) {
+        lds_fft(buf, len, cols, tw);
+    } else {
+        constexpr int LOG = __builtin_ctz(L);
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int st = 0; st < (LOG + 1) / 2; ++st) {
+            // radix 4 while two or more bits remain, radix 2 for a last odd bit
+            const int p = 1 << (2 * st);
+            const int r = ((LOG - 2 * st) >= 2) ? 4 : 2;
+            const int nb = L / r;
+            const int total = nb * cols;
+            const int tstride = L / (p * r);
+            cplx v[FFT_VPT];
+            int dst[FFT_VPT / 2];
+            if (r == 4) {
+#pragma unroll
+                for (int b = 0; b < FFT_VPT / 4; ++b) {
+                    int t = tid + b * FFT_THREADS;
+                    if (t < total) {
+                        int col = t / nb;
+                        int i = t - col * nb;
+                        int k = i & (p - 1);
+                        cplx* base = buf + col * L;
+                        cplx x0 = base[i], x1 = base[i + nb], x2 = base[i + 2 * nb], x3 = base[i + 3 * nb];
+                        if (p > 1) {
+                            cplx w1 = tw[k * tstride];
+                            cplx w2 = cmul(w1, w1);
+                            cplx w3 = cmul(w2, w1);
+                            x1 = cmul(x1, w1);
+                            x2 = cmul(x2, w2);
+                            x3 = cmul(x3, w3);
+                        }
+                        cplx s02 = cadd(x0, x2), d02 = csub(x0, x2);
+                        cplx s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
+                        v[4 * b + 0] = cadd(s02, s13);
+                        v[4 * b + 1] = cadd(d02, d13);
+                        v[4 * b + 2] = csub(s02, s13);
+                        v[4 * b + 3] = csub(d02, d13);
+                        dst[b] = col * L + (i - k) * 4 + k;
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int b = 0; b < FFT_VPT / 4; ++b) {
+                    int t = tid + b * FFT_THREADS;
+                    if (t < total) {
+                        int d = dst[b];
+                        buf[d] = v[4 * b + 0];
+                        buf[d + p] = v[4 * b + 1];
+                        buf[d + 2 * p] = v[4 * b + 2];
+                        buf[d + 3 * p] = v[4 * b + 3];
+                    }
+                }
+                __syncthreads();
+            } else {
+#pragma unroll
+                for (int b = 0; b < FFT_VPT / 2; ++b) {
+                    int t = tid + b * FFT_THREADS;
+                    if (t < total) {
+                        int col = t / nb;
+                        int i = t - col * nb;
+                        int k = i & (p - 1);
+                        cplx* base = buf + col * L;
+                        cplx x0 = base[i], x1 = base[i + nb];
+                        if (p > 1) x1 = cmul(x1, tw[k * tstride]);
+                        v[2 * b + 0] = cadd(x0, x1);
+                        v[2 * b + 1] = csub(x0, x1);
+                        dst[b] = col * L + (i - k) * 2 + k;
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int b = 0; b < FFT_VPT / 2; ++b) {
+                    int t = tid + b * FFT_THREADS;
+                    if (t < total) {
+                        int d = dst[b];
+                        buf[d] = v[2 * b + 0];
+                        buf[d + p] = v[2 * b + 1];
+                    }
+                }
+                __syncthreads();
+            }
+        }
     }
 }
 

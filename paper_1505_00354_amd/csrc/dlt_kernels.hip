@@ -42,20 +42,22 @@ __global__ void k_nodes_interior(NodeParams P, double* __restrict__ theta, doubl
     int k = P.kb + blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nh) return;
     const double pi = 3.141592653589793;
-    // theta^cheb* - theta^cheb1 = pi (N - 2k - 1) / (4 N (N + 1/2))
-    double delta = pi * (double)(N - 2 * k - 1) / (4.0 * N * (N + 0.5));
+    const double nu = N + 0.5;
+    // start: psi + cot(psi)/(8 nu^2), psi = (k+3/4) pi/nu (two terms of the
+    // classical expansion of the zeros; relative error below 4e-7 for k >= 6),
+    // as an offset from theta*_k: psi - theta*_k = pi (N - 2k - 1)/(4 N nu)
+    const double psi = (k + 0.75) * pi / nu;
+    double delta = pi * (double)(N - 2 * k - 1) / (4.0 * N * nu) + 1.0 / (8.0 * nu * nu * tan(psi));
     // theta*_k - pi/2 = pi (2k + 1 - N) / (2N)
     const double a0 = pi * (double)(2 * k + 1 - N) / (2.0 * N);
     const double ts = (k + 0.5) * pi / N;
-    double Pv = 0, Dv = 0, s2 = 1;
-    for (int it = 0; it <= 5; ++it) {
+    double Pv = 0, Dv = 0;
+    for (int it = 0; it <= 3; ++it) {
         double th = ts + delta;
         double sn, cs;
         sincos(th, &sn, &cs);
-        s2 = 2.0 * sn;
         double cot = cs / sn;
-        double q = 1.0 / s2;
-        // psi_0 and the per-term increment theta - pi/2
+        double q = 1.0 / (2.0 * sn);
         double dlt = a0 + delta;  // theta - pi/2
         double ps, pc, rs, rc;
         sincos(0.5 * dlt + N * delta, &ps, &pc);
@@ -63,19 +65,18 @@ __global__ void k_nodes_interior(NodeParams P, double* __restrict__ theta, doubl
         double r = sqrt(q);
         Pv = 0;
         Dv = 0;
-#pragma unroll 4
         for (int m = 0; m < P.Ms; ++m) {
             double hm = P.h[m] * r;
             Pv = fma(hm, ps, Pv);
             Dv = fma(hm, (N + m + 0.5) * pc - (m + 0.5) * ps * cot, Dv);
-            // psi_{m+1} = psi_m + (theta - pi/2)
+            if (hm < 1e-18 * P.h[0] * sqrt(q)) break;  // remaining terms below rounding
             double nps = ps * rc + pc * rs;
             double npc = pc * rc - ps * rs;
             ps = nps;
             pc = npc;
             r *= q;
         }
-        if (it < 5) delta -= Pv / Dv;
+        if (it < 3) delta -= Pv / Dv;
     }
     // dP/dtheta = -(-1)^k C D;  w = 2 / (dP/dtheta)^2
     double dP = P.C * Dv;
@@ -96,17 +97,55 @@ __global__ void k_nodes_interior(NodeParams P, double* __restrict__ theta, doubl
     }
 }
 
+// One step n -> n+1 of the Legendre recurrence in u = 2 sin^2(theta/2)
+// (Reinsch's form), with r = 1/(n+1):
+//   D_{n+1} = (n D_n - (2n+1) u P_n)/(n+1) = e - t - r e,  e = D_n - t, t = u P_n,
+//   P_{n+1} = P_n + D_{n+1}.
+__device__ __forceinline__ void reinsch_step(double u, double r, double& P, double& D) {
+    double t = u * P;
+    double e = D - t;
+    double Dn = fma(-r, e, e - t);
+    P += Dn;
+    D = Dn;
+}
+
+// 1/(n+1) to full precision: hardware reciprocal plus one Newton step
+__device__ __forceinline__ double recip_np1(int n) {
+    double x = (double)(n + 1);
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * fma(-x, r, 2.0);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Transfer data of a run of recurrence steps: the 2x2 map of the state
+// (P, D) and the quadratic form Q of sum (2n+1) P_n^2 in the start state.
+struct Xfer {
+    double a, b, c, d;     // (P, D)_end = [[a, c], [b, d]] (P, D)_start
+    double qaa, qab, qbb;  // sum = qaa P^2 + 2 qab P D + qbb D^2
+};
+
+// (first x, then y): T = Ty Tx, Q = Qx + Tx^T Qy Tx
+__device__ __forceinline__ Xfer xfer_then(const Xfer& x, const Xfer& y) {
+    Xfer o;
+    o.a = y.a * x.a + y.c * x.b;
+    o.b = y.b * x.a + y.d * x.b;
+    o.c = y.a * x.c + y.c * x.d;
+    o.d = y.b * x.c + y.d * x.d;
+    // Tx^T Qy Tx with Tx columns (a, b) and (c, d)
+    double pa = y.qaa * x.a + y.qab * x.b, pb = y.qab * x.a + y.qbb * x.b;  // Qy (a, b)
+    double qa = y.qaa * x.c + y.qab * x.d, qb = y.qab * x.c + y.qbb * x.d;  // Qy (c, d)
+    o.qaa = x.qaa + x.a * pa + x.b * pb;
+    o.qab = x.qab + x.c * pa + x.d * pb;
+    o.qbb = x.qbb + x.c * qa + x.d * qb;
+    return o;
+}
+
 // P_N(cos t), P_{N-1}(cos t) and the Christoffel sum K = sum_{n<N} (2n+1) P_n^2
-// for 0 < t <= pi/2, by the recurrence in u = 2 sin^2(t/2),
-//   D_{n+1} = (n D_n - (2n+1) u P_n)/(n+1),  P_{n+1} = P_n + D_{n+1},
-// split over the block: each thread runs its chunk of degrees for the two
-// basis states (P, D) = (1, 0) and (0, 1) (the first chunk from the true
-// start), keeping the chunk's transfer matrix and the quadratic sums
-// sum (2n+1) Pa^2, sum (2n+1) Pa Pb, sum (2n+1) Pb^2; the chunks are then
-// chained in order.  `sh` holds 7*blockDim.x + 3 doubles.
-__device__ void block_legendre_pair(int N, double t, const double* __restrict__ A,
-                                    const double* __restrict__ B, double* sh, double* pN, double* pN1,
-                                    double* kc) {
+// for 0 < t <= pi/2: each thread of the block runs its chunk of degrees from
+// the two basis states (1, 0) and (0, 1), then the chunks' transfer data are
+// combined by a tree in LDS (`sh` holds 7*blockDim.x doubles, blockDim a power
+// of two) and applied to the true start (P_0, D_0) = (1, 0).
+__device__ void block_legendre_pair(int N, double t, double* sh, double* pN, double* pN1, double* kc) {
     const int T = blockDim.x, tid = threadIdx.x;
     double s = sin(0.5 * t);
     double u = 2.0 * s * s;
@@ -119,42 +158,33 @@ __device__ void block_legendre_pair(int N, double t, const double* __restrict__ 
         saa = fma(wgt * pa, pa, saa);
         sab = fma(wgt * pa, pb, sab);
         sbb = fma(wgt * pb, pb, sbb);
-        double bu = B[n] * u;
-        double dna = fma(A[n], da, -bu * pa);
-        double dnb = fma(A[n], db, -bu * pb);
-        pa += dna;
-        da = dna;
-        pb += dnb;
-        db = dnb;
+        double r = recip_np1(n);
+        reinsch_step(u, r, pa, da);
+        reinsch_step(u, r, pb, db);
     }
-    double* q = sh + 7 * tid;
-    q[0] = pa;
-    q[1] = da;
-    q[2] = pb;
-    q[3] = db;
-    q[4] = saa;
-    q[5] = sab;
-    q[6] = sbb;
-    __syncthreads();
-    if (tid == 0) {
-        double P = 1, D = 0, K = 0;  // state at n = 0 (D_0 does not enter)
-        int nthr = min(T, (N + C - 1) / C);
-        for (int i = 0; i < nthr; ++i) {
-            const double* r = sh + 7 * i;
-            K += P * P * r[4] + 2.0 * P * D * r[5] + D * D * r[6];
-            double Pn = r[0] * P + r[2] * D;
-            double Dn = r[1] * P + r[3] * D;
-            P = Pn;
-            D = Dn;
+    Xfer x{pa, da, pb, db, saa, sab, sbb};
+    for (int span = 1; span < T; span *= 2) {
+        // threads tid = k*2*span hold the combined data of [k*2*span, (k*2+1)*span)
+        double* q = sh + 7 * tid;
+        q[0] = x.a; q[1] = x.b; q[2] = x.c; q[3] = x.d; q[4] = x.qaa; q[5] = x.qab; q[6] = x.qbb;
+        __syncthreads();
+        if ((tid & (2 * span - 1)) == 0 && tid + span < T) {
+            const double* r = sh + 7 * (tid + span);
+            Xfer y{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+            x = xfer_then(x, y);
         }
-        sh[7 * T] = P;
-        sh[7 * T + 1] = P - D;
-        sh[7 * T + 2] = K;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        // start state (P_0, D_0) = (1, 0): P = a, D = b, K = qaa
+        sh[0] = x.a;
+        sh[1] = x.a - x.b;
+        sh[2] = x.qaa;
     }
     __syncthreads();
-    *pN = sh[7 * T];
-    *pN1 = sh[7 * T + 1];
-    *kc = sh[7 * T + 2];
+    *pN = sh[0];
+    *pN1 = sh[1];
+    *kc = sh[2];
     __syncthreads();
 }
 
@@ -165,9 +195,9 @@ __device__ void block_legendre_pair(int N, double t, const double* __restrict__ 
 // exact recurrence follow (none for large N, where the FP64 recurrence is
 // less accurate than the start).  The weight is the Christoffel number
 // w_k = 2 / sum_{n<N} (2n+1) P_n(x_k)^2, which is well conditioned in x_k.
-__global__ void k_nodes_boundary(NodeParams P, const double* __restrict__ guess, const double* __restrict__ A,
-                                 const double* __restrict__ B, double* __restrict__ theta,
-                                 double* __restrict__ w, double* __restrict__ dth) {
+__global__ __launch_bounds__(1024) void k_nodes_boundary(NodeParams P, const double* __restrict__ guess,
+                                                        double* __restrict__ theta, double* __restrict__ w,
+                                                        double* __restrict__ dth) {
     extern __shared__ double sh[];
     const int N = P.N;
     const int k = blockIdx.x;
@@ -181,7 +211,7 @@ __global__ void k_nodes_boundary(NodeParams P, const double* __restrict__ guess,
     } else {
         for (int it = 0; it < P.newton_b; ++it) {
             double th = ts + delta;
-            block_legendre_pair(N, th, A, B, sh, &pN, &pN1, &kc);
+            block_legendre_pair(N, th, sh, &pN, &pN1, &kc);
             double sn, cs;
             sincos(th, &sn, &cs);
             double dP = N * (cs * pN - pN1) / sn;
@@ -191,7 +221,7 @@ __global__ void k_nodes_boundary(NodeParams P, const double* __restrict__ guess,
         }
     }
     double th = ts + delta;
-    block_legendre_pair(N, th, A, B, sh, &pN, &pN1, &kc);
+    block_legendre_pair(N, th, sh, &pN, &pN1, &kc);
     if (threadIdx.x == 0) {
         double wk = 2.0 / kc;
         int k2 = N - 1 - k;
@@ -210,22 +240,122 @@ __global__ void k_nodes_boundary(NodeParams P, const double* __restrict__ guess,
     }
 }
 
+
+// Boundary nodes for large N (no Newton step: the Bessel-zero start is
+// within an ulp): block (k, part) produces the transfer data of degrees
+// [part*N/P, (part+1)*N/P) at theta_k; k_nodes_bfin chains the P parts.
+__global__ __launch_bounds__(1024) void k_nodes_bpart(NodeParams P, const double* __restrict__ guess, int parts,
+                                                     double* __restrict__ scratch) {
+    __shared__ double sh[7 * 1024];
+    const int N = P.N;
+    const int k = blockIdx.x, part = blockIdx.y;
+    const double pi = 3.141592653589793;
+    const double t = (k + 0.5) * pi / N + guess[k];
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int lo = (int)((int64_t)N * part / parts), hi = (int)((int64_t)N * (part + 1) / parts);
+    double s = sin(0.5 * t);
+    double u = 2.0 * s * s;
+    int C = (hi - lo + T - 1) / T;
+    int n0 = lo + tid * C, n1 = min(hi, n0 + C);
+    double pa = 1, da = 0, pb = 0, db = 1;
+    double saa = 0, sab = 0, sbb = 0;
+    for (int n = n0; n < n1; ++n) {
+        double wgt = 2.0 * n + 1.0;
+        saa = fma(wgt * pa, pa, saa);
+        sab = fma(wgt * pa, pb, sab);
+        sbb = fma(wgt * pb, pb, sbb);
+        double r = recip_np1(n);
+        reinsch_step(u, r, pa, da);
+        reinsch_step(u, r, pb, db);
+    }
+    Xfer x{pa, da, pb, db, saa, sab, sbb};
+    for (int span = 1; span < T; span *= 2) {
+        double* q = sh + 7 * tid;
+        q[0] = x.a; q[1] = x.b; q[2] = x.c; q[3] = x.d; q[4] = x.qaa; q[5] = x.qab; q[6] = x.qbb;
+        __syncthreads();
+        if ((tid & (2 * span - 1)) == 0 && tid + span < T) {
+            const double* r = sh + 7 * (tid + span);
+            Xfer y{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+            x = xfer_then(x, y);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double* o = scratch + ((int64_t)k * parts + part) * 8;
+        o[0] = x.a; o[1] = x.b; o[2] = x.c; o[3] = x.d; o[4] = x.qaa; o[5] = x.qab; o[6] = x.qbb;
+    }
+}
+
+__global__ void k_nodes_bfin(NodeParams P, const double* __restrict__ guess, int parts,
+                             const double* __restrict__ scratch, double* __restrict__ theta, double* __restrict__ w,
+                             double* __restrict__ dth) {
+    const int N = P.N;
+    const int k = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    const double pi = 3.141592653589793;
+    Xfer x{1, 0, 0, 1, 0, 0, 0};
+    for (int part = 0; part < parts; ++part) {
+        const double* o = scratch + ((int64_t)k * parts + part) * 8;
+        Xfer y{o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
+        x = xfer_then(x, y);
+    }
+    double delta = guess[k];
+    double th = (k + 0.5) * pi / N + delta;
+    double wk = 2.0 / x.qaa;  // Christoffel number from the true start (1, 0)
+    int k2 = N - 1 - k;
+    if (theta) {
+        theta[k] = th;
+        if (k2 != k) theta[k2] = pi - th;
+    }
+    if (w) {
+        w[k] = wk;
+        if (k2 != k) w[k2] = wk;
+    }
+    if (dth) {
+        dth[k] = delta;
+        if (k2 != k) dth[k2] = -delta;
+    }
+}
+
 // ------------------------------------------------------------------ dense --
 // chat_k (k < nd) partial sums over column chunk blockIdx.y:
 //   sum_{n in chunk, n >= k, n+k even} (eps_k/pi) Lam((n-k)/2) Lam((n+k)/2) c_n
-__global__ void k_dense(int N, int nd, int chunk, const double* __restrict__ lam, const double* __restrict__ c,
-                        int64_t c_stride, double* __restrict__ part, int64_t part_stride) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    int ch = blockIdx.y;
-    int b = blockIdx.z;
+// Block = 256 rows of one parity, k = kb0 + 2i + par, so every lane walks the
+// same columns n (same parity); the Lam windows and c of the chunk are staged
+// in LDS.  DENSE_CH columns per chunk.
+constexpr int DENSE_CH = 512;
+
+__global__ __launch_bounds__(256) void k_dense(int N, int nd, int chunk, const double* __restrict__ lam,
+                                               const double* __restrict__ c, int64_t c_stride,
+                                               double* __restrict__ part, int64_t part_stride) {
+    __shared__ double sc[DENSE_CH], slm[DENSE_CH / 2 + 256], slp[DENSE_CH / 2 + 256];
+    const int par = blockIdx.x & 1;
+    const int kb0 = (blockIdx.x >> 1) * 512;
+    const int ch = blockIdx.y;
+    const int b = blockIdx.z;
     const double* cb = c + b * c_stride;
     double* pb = part + b * part_stride;
+    const int n0 = ch * DENSE_CH, n1 = min(nd, n0 + DENSE_CH);
+    const int k = kb0 + 2 * threadIdx.x + par;
+    // windows: (n-k)/2 in [zm0, zm0 + CH/2 + 256), (n+k)/2 in [zp0, ...)
+    const int kmax = kb0 + 511;
+    const int zm0 = (n0 - kmax) >> 1;  // may be negative (unused entries)
+    const int zp0 = (n0 + kb0) >> 1;
+    for (int i = threadIdx.x; i < DENSE_CH; i += 256) sc[i] = (n0 + i < n1) ? cb[n0 + i] : 0.0;
+    for (int i = threadIdx.x; i < DENSE_CH / 2 + 256; i += 256) {
+        int zm = zm0 + i, zp = zp0 + i;
+        slm[i] = (zm >= 0 && zm < nd) ? lam[zm] : 0.0;
+        slp[i] = (zp >= 0 && zp < nd) ? lam[zp] : 0.0;
+    }
+    __syncthreads();
     if (k >= nd) return;
-    int n0 = ch * chunk, n1 = min(nd, n0 + chunk);
     double acc = 0;
     int n = max(n0, k);
     if ((n - k) & 1) ++n;
-    for (; n < n1; n += 2) acc = fma(lam[(n - k) >> 1] * lam[(n + k) >> 1], cb[n], acc);
+    for (; n < n1; n += 2) {
+        int im = ((n - k) >> 1) - zm0, ip = ((n + k) >> 1) - zp0;
+        acc = fma(slm[im] * slp[ip], sc[n - n0], acc);
+    }
     double e = (k == 0) ? 0.3183098861837907 : 0.6366197723675814;  // eps_k / pi
     pb[(int64_t)ch * nd + k] = e * acc;
 }
@@ -243,29 +373,60 @@ __global__ void k_dense_reduce(int nd, int nchunk, int chunk, const double* __re
 }
 
 // ------------------------------------------------------ FFT pass helpers --
+// Intermediate layout between the passes ("blocked"): DFT output (n_a, j_b)
+// of pass A sits at X[(v >> lrB) * (N1 << lrB) + n_a * rowsB + (v & (rowsB-1))]
+// with v = j_b, or for kernels whose pass B pairs row r with N2 - r, the
+// virtual row v(j_b) that places the pair next to each other:
+// v(0) = 0, v(N2/2) = 1, v(r) = 2r, v(N2-r) = 2r+1 (0 < r < N2/2).
+// A pass-B tile of rowsB (virtual) rows is one contiguous block.
+__device__ __forceinline__ int virt_row(int jb, int N2) {
+    if (N2 <= 2) return jb;
+    if (jb == 0) return 0;
+    if (jb == N2 / 2) return 1;
+    return (jb < N2 / 2) ? 2 * jb : 2 * (N2 - jb) + 1;
+}
+__device__ __forceinline__ int actual_row(int v, int N2) {
+    if (N2 <= 2) return v;
+    if (v == 1) return N2 / 2;
+    return (v & 1) ? N2 - (v >> 1) : (v >> 1);
+}
+
+// blocks are dispatched round-robin to the 8 XCDs; give each XCD a
+// contiguous range of tiles so neighbouring tiles share an L2
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+    if (ntiles & 7) return bid;
+    return (bid & 7) * (ntiles >> 3) + (bid >> 3);
+}
+
 // Pass A: the block owns columns n_a in [na0, na0+colsA); element e of the
-// tile is (col = e % colsA, n_b = e / colsA), n = na0 + col + N1 n_b.
-// After the in-LDS length-N2 DFTs the tile holds buf[col*N2 + j_b]; it is
-// multiplied by e^{2 pi i n_a j_b / N} and written to X[n_a*N2 + j_b].
-__device__ __forceinline__ void passA_store(const Geo& g, const cplx* buf, int na0, cplx* __restrict__ X) {
-    const int tot = g.colsA * g.N2;
+// tile is (col = e % colsA, n_b = e / colsA), n = na0 + col + N1 n_b.  After
+// the length-N2 DFTs the tile holds buf[col*N2 + j_b]; it is multiplied by
+// e^{2 pi i n_a j_b / N} and stored in the blocked layout.
+template <bool VIRT>
+__device__ __forceinline__ void passA_store(const Geo& g, int N2, int colsA, const cplx* buf, int na0,
+                                            cplx* __restrict__ X) {
+    const int tot = colsA * N2;
+    const int rB = g.rowsB, lrB = g.lrB;
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int col = e / g.N2, jb = e - col * g.N2;
+        int col = e / N2, jb = e - col * N2;
         int na = na0 + col;
         cplx v = buf[e];
         if (na && jb) v = cmul(v, tw2(g.twHi, g.twLo, (int64_t)na * jb, g.sh));
-        X[(int64_t)na * g.N2 + jb] = v;
+        int vr = VIRT ? virt_row(jb, N2) : jb;
+        X[(int64_t)(vr >> lrB) * ((int64_t)g.N1 << lrB) + (int64_t)na * rB + (vr & (rB - 1))] = v;
     }
 }
 
-// Pass B: the block owns rows j_b in [jb0, jb0+rowsB); LDS holds
-// buf[r*N1 + n_a]; after the length-N1 DFTs, buf[r*N1 + j_a] is output
-// m = jb0 + r + N2 j_a.
-__device__ __forceinline__ void passB_load(const Geo& g, cplx* buf, int jb0, const cplx* __restrict__ X) {
-    const int tot = g.rowsB * g.N1;
+// Pass B: the block owns (virtual) rows [vb0, vb0+rowsB): one contiguous
+// block of the intermediate; LDS gets buf[r*N1 + n_a]; after the length-N1
+// DFTs buf[r*N1 + j_a] is output m = jb(r) + N2 j_a.
+__device__ __forceinline__ void passB_load(const Geo& g, int N1, int rowsB, cplx* buf, int vb0,
+                                           const cplx* __restrict__ X) {
+    const int tot = rowsB * N1;
+    const cplx* src = X + (int64_t)(vb0 >> g.lrB) * ((int64_t)N1 << g.lrB);
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int r = e % g.rowsB, na = e / g.rowsB;
-        buf[r * g.N1 + na] = X[(int64_t)na * g.N2 + jb0 + r];
+        int r = e & (rowsB - 1), na = e / rowsB;
+        buf[r * N1 + na] = src[e];
     }
 }
 
@@ -274,16 +435,19 @@ __device__ __forceinline__ void passB_load(const Geo& g, cplx* buf, int jb0, con
 // h_{m-1,n} = h_{m,n} m (n+m+1/2)/(m-1/2)^2 needs no division, the DFT input
 //   b_n = C_n h_{m,n} c_n e^{i pi n/(2N)} [n >= nlo_b]
 // goes through pass A of the length-N DFT.
-__global__ __launch_bounds__(FFT_THREADS) void k_far_passA(Geo g, FarParams F, const double* __restrict__ c,
+template <int LA>
+__global__ __launch_bounds__(FFT_THREADS) void k_far_passA(Geo g, FarParams F, int G, const double* __restrict__ c,
                                                           int64_t c_stride, cplx* __restrict__ X,
                                                           int64_t x_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N2 = LA ? LA : g.N2;
+    const int colsA = LA ? FFT_CAP / LA : g.colsA;
     const int N = g.N;
-    const int na0 = blockIdx.x * g.colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int b = blockIdx.z;
     const double* cb = c + b * c_stride;
     cplx* Xb = X + b * x_stride;
-    const int tot = g.colsA * g.N2;
+    const int tot = colsA * N2;
     cplx base[FFT_VPT];
     double h[FFT_VPT];
     int nn[FFT_VPT];
@@ -294,35 +458,36 @@ __global__ __launch_bounds__(FFT_THREADS) void k_far_passA(Geo g, FarParams F, c
         h[s] = 0;
         nn[s] = -1;
         if (e < tot) {
-            int col = e % g.colsA, nb = e / g.colsA;
+            int col = e % colsA, nb = e / colsA;
             int n = na0 + col + g.N1 * nb;
             nn[s] = n;
             if (n >= F.nd) {
                 double amp = stieltjes_C((double)n) * cb[n];
                 base[s] = cscale(half_shift(n, N), amp);
                 // h_{Mmax-1,n} = prod_{j<Mmax} (j-1/2)^2/(j (n+j+1/2))
-                double hv = 1;
-                for (int j = 1; j < F.Mmax; ++j) hv *= (j - 0.5) * (j - 0.5) / (j * (n + j + 0.5));
-                h[s] = hv;
+                // h_{Mmax-1,n} = K / prod_{j<Mmax} (n+j+1/2),  K = prod_{j<Mmax} (j-1/2)^2/j
+                double den = 1;
+                for (int j = 1; j < F.Mmax; ++j) den *= (n + j + 0.5);
+                h[s] = F.hK / den;
             }
         }
     }
     for (int m = F.Mmax - 1; m >= 0; --m) {
         for (int t = 0; t < F.nterm; ++t) {
-            if (F.term_m[t] != m) continue;
+            if (F.term_m[t] != m || (t % G) != (int)blockIdx.y) continue;
             const int nlo = F.blk[F.term_blk[t]].nlo;
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) {
                 int e = threadIdx.x + s * FFT_THREADS;
                 if (e < tot) {
-                    int col = e % g.colsA, nb = e / g.colsA;
+                    int col = e % colsA, nb = e / colsA;
                     double f = (nn[s] >= nlo) ? h[s] : 0.0;
-                    buf[col * g.N2 + nb] = cscale(base[s], f);
+                    buf[col * N2 + nb] = cscale(base[s], f);
                 }
             }
             __syncthreads();
-            lds_fft(buf, g.N2, g.colsA, g.twN2);
-            passA_store(g, buf, na0, Xb + (int64_t)t * N);
+            lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+            passA_store<false>(g, N2, colsA, buf, na0, Xb + (int64_t)t * N);
             __syncthreads();
         }
         if (m > 0) {
@@ -346,16 +511,19 @@ __device__ __forceinline__ int row_block(const FarParams& F, int j, int N) {
     return -1;
 }
 
+template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_far_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
                                                           int64_t x_stride, double* __restrict__ v,
                                                           int64_t v_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N1 = LB ? LB : g.N1;
+    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     const int N = g.N;
-    const int jb0 = blockIdx.x * g.rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const cplx* Xb = X + b * x_stride;
-    const int tot = g.rowsB * g.N1;
+    const int tot = rowsB * N1;
     const double pi = 3.141592653589793;
     cplx gm[FFT_VPT], rq[FFT_VPT];
     double acc[FFT_VPT];
@@ -370,7 +538,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_far_passB(Geo g, FarParams F, i
         gm[s] = {0, 0};
         rq[s] = {0, 0};
         if (e < tot) {
-            int r = e / g.N1, ja = e - r * g.N1;
+            int r = e / N1, ja = e - r * N1;
             int m = jb0 + r + g.N2 * ja;
             int j = row_of(m, N);
             cj[s] = (2 * m >= N);
@@ -391,9 +559,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_far_passB(Geo g, FarParams F, i
         for (int t = 0; t < F.nterm; ++t) {
             if (F.term_m[t] != m || (t % G) != grp) continue;
             const int tb = F.term_blk[t];
-            passB_load(g, buf, jb0, Xb + (int64_t)t * N);
+            passB_load(g, N1, rowsB, buf, jb0, Xb + (int64_t)t * N);
             __syncthreads();
-            lds_fft(buf, g.N1, g.rowsB, g.twN1);
+            lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) {
                 int e = threadIdx.x + s * FFT_THREADS;
@@ -413,7 +581,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_far_passB(Geo g, FarParams F, i
     for (int s = 0; s < FFT_VPT; ++s) {
         int e = threadIdx.x + s * FFT_THREADS;
         if (e < tot) {
-            int r = e / g.N1, ja = e - r * g.N1;
+            int r = e / N1, ja = e - r * N1;
             int m = jb0 + r + g.N2 * ja;
             vb[row_of(m, N)] = acc[s];
         }
@@ -421,155 +589,258 @@ __global__ __launch_bounds__(FFT_THREADS) void k_far_passB(Geo g, FarParams F, i
 }
 
 // ------------------------------------------------------------ near field --
-// Item = (row j, degree chunk): the recurrence over the chunk from two basis
-// states (chunk > 0) or the true start (chunk 0), accumulating
-//   S+ = sum c_n P_n(cos theta_j), S- = sum (-1)^n c_n P_n(cos theta_j)
-// over n >= nd; the mirror row N-1-j takes S- since P_n(-x) = (-1)^n P_n(x).
-__global__ void k_near_items(int N, NearParams NP, const double* __restrict__ A, const double* __restrict__ B,
-                             const double* __restrict__ c, int64_t c_stride, double* __restrict__ items,
-                             int64_t it_stride) {
-    int id = blockIdx.x * blockDim.x + threadIdx.x;
-    int b = blockIdx.z;
-    if (id >= NP.nitems) return;
-    int sgi = 0;
-    while (sgi + 1 < NP.nseg && id >= NP.seg[sgi + 1].item_off) ++sgi;
-    const Seg S = NP.seg[sgi];
-    int loc = id - S.item_off;
-    int nrows = S.jhi - S.jlo;
-    int ch = loc / nrows;
-    int j = S.jlo + (loc - ch * nrows);
-    const double* cb = c ? c + b * c_stride : nullptr;
-    double* out = items + b * it_stride + (int64_t)id * 8;
+// Work-group = one wave = 64 consecutive rows of one segment and one degree
+// chunk [n0, n1) (NEAR_CHUNK degrees); the plan's table maps blockIdx.x to
+// its segment.  Item (row, chunk) stores, for chunk 0 (true start P_0 = 1),
+// the end state and the even/odd-degree sums
+//   E = sum_{n even, n >= nd} c_n P_n(x_j),  O = sum_{n odd, n >= nd} c_n P_n(x_j)
+// (S+ = E + O is row j, S- = E - O the mirror row N-1-j, since
+// P_n(-x) = (-1)^n P_n(x)); for later chunks the same from the two basis
+// states (1, 0) and (0, 1), i.e. the chunk's transfer matrix and sums.
+// With c == null only the transfer data are produced (inverse transform).
+// Degrees, c_n and 1/(n+1) are uniform across the wave.
+struct NearWG {
+    int seg, ch, grp;
+};
+
+__device__ __forceinline__ NearWG near_wg(const NearParams& NP, const int* __restrict__ wg_seg,
+                                          const int* __restrict__ segoff, int wgid) {
+    NearWG w;
+    w.seg = wg_seg[wgid];
+    const Seg& S = NP.seg[w.seg];
+    int ng = (S.jhi - S.jlo + 63) >> 6;
+    int loc = wgid - segoff[2 * w.seg];
+    w.ch = loc / ng;
+    w.grp = loc - w.ch * ng;
+    return w;
+}
+
+__global__ __launch_bounds__(64) void k_near_items(int N, NearParams NP, const int* __restrict__ wg_seg,
+                                                   const int* __restrict__ segoff, const double* __restrict__ rcp,
+                                                   const double* __restrict__ c, int64_t c_stride,
+                                                   double* __restrict__ items, int64_t it_stride) {
+    const NearWG W = near_wg(NP, wg_seg, segoff, blockIdx.x);
+    const Seg S = NP.seg[W.seg];
+    const int b = blockIdx.z;
+    const int nrows = S.jhi - S.jlo;
+    const int row = W.grp * 64 + threadIdx.x;
+    const bool act = row < nrows;
+    const int j = S.jlo + (act ? row : nrows - 1);
     const double pi = 3.141592653589793;
     double sn = sin(0.5 * (j + 0.5) * pi / N);
-    double u = 2.0 * sn * sn;
-    int n0 = ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
-    if (ch == 0) {
-        double p = 1, d = 0, sp = 0, sm = 0;
-        for (int n = n0; n < n1; ++n) {
-            if (cb && n >= NP.nd) {
-                double cn = cb[n];
-                sp = fma(cn, p, sp);
-                sm = fma((n & 1) ? -cn : cn, p, sm);
+    const double u = 2.0 * sn * sn;
+    const int n0 = W.ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
+    const double* cb = (c && n0 >= NP.nd) ? c + b * c_stride : nullptr;
+    double* out = items + b * it_stride + (int64_t)(S.item_off + W.ch * nrows + row) * 8;
+    if (W.ch == 0) {
+        double p = 1, d = 0, E = 0, O = 0;
+        int n = n0;
+        if (cb) {
+            for (; n + 1 < n1; n += 2) {
+                E = fma(cb[n], p, E);
+                reinsch_step(u, rcp[n], p, d);
+                O = fma(cb[n + 1], p, O);
+                reinsch_step(u, rcp[n + 1], p, d);
             }
-            double dn = fma(A[n], d, -B[n] * u * p);
-            p += dn;
-            d = dn;
+            if (n < n1) {
+                E = fma(cb[n], p, E);
+                reinsch_step(u, rcp[n], p, d);
+            }
+        } else {
+#pragma unroll 4
+            for (; n < n1; ++n) reinsch_step(u, rcp[n], p, d);
         }
-        out[0] = p;
-        out[1] = d;
-        out[2] = sp;
-        out[3] = sm;
+        if (act) {
+            out[0] = p;
+            out[1] = d;
+            out[2] = E;
+            out[3] = O;
+        }
     } else {
         double pa = 1, da = 0, pb = 0, db = 1;
-        double spa = 0, spb = 0, sma = 0, smb = 0;
-        for (int n = n0; n < n1; ++n) {
-            if (cb && n >= NP.nd) {
-                double cn = cb[n];
-                double cm = (n & 1) ? -cn : cn;
-                spa = fma(cn, pa, spa);
-                spb = fma(cn, pb, spb);
-                sma = fma(cm, pa, sma);
-                smb = fma(cm, pb, smb);
+        double Ea = 0, Eb = 0, Oa = 0, Ob = 0;
+        int n = n0;
+        if (cb) {
+            for (; n + 1 < n1; n += 2) {
+                double ce = cb[n], co = cb[n + 1], r0 = rcp[n], r1 = rcp[n + 1];
+                Ea = fma(ce, pa, Ea);
+                Eb = fma(ce, pb, Eb);
+                reinsch_step(u, r0, pa, da);
+                reinsch_step(u, r0, pb, db);
+                Oa = fma(co, pa, Oa);
+                Ob = fma(co, pb, Ob);
+                reinsch_step(u, r1, pa, da);
+                reinsch_step(u, r1, pb, db);
             }
-            double bu = B[n] * u;
-            double dna = fma(A[n], da, -bu * pa);
-            double dnb = fma(A[n], db, -bu * pb);
-            pa += dna;
-            da = dna;
-            pb += dnb;
-            db = dnb;
+            if (n < n1) {
+                Ea = fma(cb[n], pa, Ea);
+                Eb = fma(cb[n], pb, Eb);
+                reinsch_step(u, rcp[n], pa, da);
+                reinsch_step(u, rcp[n], pb, db);
+            }
+        } else {
+#pragma unroll 4
+            for (; n < n1; ++n) {
+                double r = rcp[n];
+                reinsch_step(u, r, pa, da);
+                reinsch_step(u, r, pb, db);
+            }
         }
-        out[0] = pa;
-        out[1] = da;
-        out[2] = pb;
-        out[3] = db;
-        out[4] = spa;
-        out[5] = spb;
-        out[6] = sma;
-        out[7] = smb;
+        if (act) {
+            out[0] = pa;
+            out[1] = da;
+            out[2] = pb;
+            out[3] = db;
+            out[4] = Ea;
+            out[5] = Eb;
+            out[6] = Oa;
+            out[7] = Ob;
+        }
     }
 }
 
-// near[j] = S+ for row j < jnear, near[jnear + j] = S- (row N-1-j)
-__global__ void k_near_combine(NearParams NP, const double* __restrict__ items, int64_t it_stride,
-                               double* __restrict__ near, int64_t near_stride) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    int b = blockIdx.z;
-    if (j >= NP.jnear) return;
-    const double* it = items + b * it_stride;
-    double* nb = near + b * near_stride;
+// Linear data of a run of chunks acting on the start state s = (P, D):
+// end state T s and the even/odd sums eE . s, eO . s.
+struct ChunkMap {
+    double a, b, c, d;  // T = [[a, c], [b, d]]
+    double ea, eb, oa, ob;
+};
+
+// first x, then y
+__device__ __forceinline__ ChunkMap cmap_then(const ChunkMap& x, const ChunkMap& y) {
+    ChunkMap o;
+    o.a = y.a * x.a + y.c * x.b;
+    o.b = y.b * x.a + y.d * x.b;
+    o.c = y.a * x.c + y.c * x.d;
+    o.d = y.b * x.c + y.d * x.d;
+    o.ea = x.ea + y.ea * x.a + y.eb * x.b;
+    o.eb = x.eb + y.ea * x.c + y.eb * x.d;
+    o.oa = x.oa + y.oa * x.a + y.ob * x.b;
+    o.ob = x.ob + y.oa * x.c + y.ob * x.d;
+    return o;
+}
+
+__device__ __forceinline__ ChunkMap cmap_identity() { return {1, 0, 0, 1, 0, 0, 0, 0}; }
+
+__device__ __forceinline__ ChunkMap cmap_shfl_down(const ChunkMap& x, int d) {
+    ChunkMap o;
+    o.a = __shfl_down(x.a, d);
+    o.b = __shfl_down(x.b, d);
+    o.c = __shfl_down(x.c, d);
+    o.d = __shfl_down(x.d, d);
+    o.ea = __shfl_down(x.ea, d);
+    o.eb = __shfl_down(x.eb, d);
+    o.oa = __shfl_down(x.oa, d);
+    o.ob = __shfl_down(x.ob, d);
+    return o;
+}
+
+__device__ __forceinline__ ChunkMap cmap_load(const double* q) {
+    return {q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7]};
+}
+
+__device__ __forceinline__ int near_seg_of(const NearParams& NP, int j) {
     int sgi = -1;
     for (int s = 0; s < NP.nseg; ++s)
         if (j >= NP.seg[s].jlo && j < NP.seg[s].jhi) sgi = s;
-    double sp = 0, sm = 0;
-    if (sgi >= 0) {
-        const Seg S = NP.seg[sgi];
-        int nrows = S.jhi - S.jlo;
-        const double* o = it + (int64_t)(S.item_off + (j - S.jlo)) * 8;
-        double P = o[0], D = o[1];
-        sp = o[2];
-        sm = o[3];
-        for (int ch = 1; ch < S.nchunk; ++ch) {
-            const double* q = it + (int64_t)(S.item_off + ch * nrows + (j - S.jlo)) * 8;
-            sp += P * q[4] + D * q[5];
-            sm += P * q[6] + D * q[7];
-            double Pn = P * q[0] + D * q[2];
-            double Dn = P * q[1] + D * q[3];
-            P = Pn;
-            D = Dn;
+    return sgi;
+}
+
+// One wave per row j < jnear: every lane chains a contiguous run of chunks
+// 1.., the runs are chained in order by a shuffle tree, and lane 0 applies
+// the result to the state after chunk 0.  near[j] = E + O (row j),
+// near[jnear + j] = E - O (row N-1-j).
+__global__ __launch_bounds__(64) void k_near_combine(NearParams NP, const double* __restrict__ items,
+                                                     int64_t it_stride, double* __restrict__ near,
+                                                     int64_t near_stride) {
+    const int j = blockIdx.x;
+    const int b = blockIdx.z;
+    const int lane = threadIdx.x;
+    const double* it = items + b * it_stride;
+    double* nb = near + b * near_stride;
+    const int sgi = near_seg_of(NP, j);
+    if (sgi < 0) {
+        if (lane == 0) {
+            nb[j] = 0;
+            nb[NP.jnear + j] = 0;
         }
+        return;
     }
-    nb[j] = sp;
-    nb[NP.jnear + j] = sm;
+    const Seg S = NP.seg[sgi];
+    const int nrows = S.jhi - S.jlo;
+    const int64_t base = (int64_t)(S.item_off + (j - S.jlo)) * 8;
+    const int64_t step = (int64_t)nrows * 8;
+    const int rest = S.nchunk - 1;
+    const int per = (rest + 63) / 64;
+    const int c0 = 1 + lane * per, c1 = min(S.nchunk, c0 + per);
+    ChunkMap x = cmap_identity();
+    for (int ch = c0; ch < c1; ++ch) x = cmap_then(x, cmap_load(it + base + ch * step));
+    for (int d = 1; d < 64; d *= 2) {
+        ChunkMap y = cmap_shfl_down(x, d);
+        if ((lane & (2 * d - 1)) == 0) x = cmap_then(x, y);
+    }
+    if (lane == 0) {
+        const double* o = it + base;
+        double P = o[0], D = o[1];
+        double E = o[2] + x.ea * P + x.eb * D;
+        double O = o[3] + x.oa * P + x.ob * D;
+        nb[j] = E + O;
+        nb[NP.jnear + j] = E - O;
+    }
 }
 
 // ----------------------------------------------------------------- DCT-II --
 // chat_n = (eps_n/N) sum_j v_j cos(n theta_j) + dense_n:  DFT of
 // p_m = v_{j(m)}, then chat_n = (eps_n/N) Re(e^{i pi n/(2N)} U_n).
 // v_j is the sum of the G far-field partials and the near-field value.
+template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) void k_dct2_passA(Geo g, int G, const double* __restrict__ v,
                                                            int64_t v_stride, const double* __restrict__ near,
                                                            int64_t near_stride, int jnear, cplx* __restrict__ X,
                                                            int64_t x_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N2 = LA ? LA : g.N2;
+    const int colsA = LA ? FFT_CAP / LA : g.colsA;
     const int N = g.N;
-    const int na0 = blockIdx.x * g.colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int b = blockIdx.z;
     const double* vb = v + b * v_stride;
     const double* nb = near + b * near_stride;
-    const int tot = g.colsA * g.N2;
+    const int tot = colsA * N2;
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int col = e % g.colsA, nbi = e / g.colsA;
+        int col = e % colsA, nbi = e / colsA;
         int m = na0 + col + g.N1 * nbi;
         int j = row_of(m, N);
         double x = 0;
         for (int q = 0; q < G; ++q) x += vb[(int64_t)q * N + j];
         if (j < jnear) x += nb[j];
         else if (N - 1 - j < jnear) x += nb[jnear + (N - 1 - j)];
-        buf[col * g.N2 + nbi] = {x, 0.0};
+        buf[col * N2 + nbi] = {x, 0.0};
     }
     __syncthreads();
-    lds_fft(buf, g.N2, g.colsA, g.twN2);
-    passA_store(g, buf, na0, X + b * x_stride);
+    lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+    passA_store<false>(g, N2, colsA, buf, na0, X + b * x_stride);
 }
 
+template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ X,
                                                            int64_t x_stride, const double* __restrict__ dense,
                                                            int64_t dense_stride, double* __restrict__ chat,
                                                            int64_t chat_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N1 = LB ? LB : g.N1;
+    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     const int N = g.N;
-    const int jb0 = blockIdx.x * g.rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int b = blockIdx.z;
-    passB_load(g, buf, jb0, X + b * x_stride);
+    passB_load(g, N1, rowsB, buf, jb0, X + b * x_stride);
     __syncthreads();
-    lds_fft(buf, g.N1, g.rowsB, g.twN1);
-    const int tot = g.rowsB * g.N1;
+    lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
+    const int tot = rowsB * N1;
     const double* db = dense + b * dense_stride;
     double* cb = chat + b * chat_stride;
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int r = e / g.N1, ja = e - r * g.N1;
+        int r = e / N1, ja = e - r * N1;
         int n = jb0 + r + g.N2 * ja;
         cplx U = buf[e];
         cplx t = half_shift(n, N);
@@ -585,17 +856,20 @@ __global__ __launch_bounds__(FFT_THREADS) void k_dct2_passB(Geo g, int nd, const
 //   W_n = (e^{i pi n/(2N)}/2) [x^{2q}(1+x) chat_n - i y^{2q} x chat_{N-n}],
 // x = n/N, y = 1 - x (n >= 1), W_0 = chat_0 [q = 0]; then at output m the
 // cosine term is Re U_m and the sine term sigma_m Im U_m, row k = j(m).
+template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passA(Geo g, int Q, int QG, const double* __restrict__ chat,
                                                            int64_t chat_stride, cplx* __restrict__ X,
                                                            int64_t x_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N2 = LA ? LA : g.N2;
+    const int colsA = LA ? FFT_CAP / LA : g.colsA;
     const int N = g.N;
-    const int na0 = blockIdx.x * g.colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const double* cb = chat + b * chat_stride;
     cplx* Xb = X + b * x_stride;
-    const int tot = g.colsA * g.N2;
+    const int tot = colsA * N2;
     const double invN = 1.0 / N;
     cplx Av[FFT_VPT], Bv[FFT_VPT];
     double px[FFT_VPT], py[FFT_VPT];
@@ -607,7 +881,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passA(Geo g, int Q, int QG
         Bv[s] = {0, 0};
         px[s] = py[s] = 0;
         if (e < tot) {
-            int col = e % g.colsA, nbi = e / g.colsA;
+            int col = e % colsA, nbi = e / colsA;
             int n = na0 + col + g.N1 * nbi;
             if (n == 0) {
                 Av[s] = {cb[0], 0};
@@ -632,32 +906,35 @@ __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passA(Geo g, int Q, int QG
         for (int s = 0; s < FFT_VPT; ++s) {
             int e = threadIdx.x + s * FFT_THREADS;
             if (e < tot) {
-                int col = e % g.colsA, nbi = e / g.colsA;
+                int col = e % colsA, nbi = e / colsA;
                 int n = na0 + col + g.N1 * nbi;
                 double x = n * invN, y = (N - n) * invN;
-                buf[col * g.N2 + nbi] = cadd(cscale(Av[s], px[s]), cscale(Bv[s], py[s]));
+                buf[col * N2 + nbi] = cadd(cscale(Av[s], px[s]), cscale(Bv[s], py[s]));
                 px[s] *= x * x;
                 py[s] *= y * y;
             }
         }
         __syncthreads();
-        lds_fft(buf, g.N2, g.colsA, g.twN2);
-        passA_store(g, buf, na0, Xb + (int64_t)q * N);
+        lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+        passA_store<false>(g, N2, colsA, buf, na0, Xb + (int64_t)q * N);
         __syncthreads();
     }
 }
 
 // f_k = sum_l s_l d_k^l/l! F_l[k], s_l = (-1)^floor((l+1)/2), d_k = N dtheta_k,
 // by Horner from the highest pair down.
+template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X,
                                                            int64_t x_stride, const double* __restrict__ dth,
                                                            double* __restrict__ f, int64_t f_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N1 = LB ? LB : g.N1;
+    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     const int N = g.N;
-    const int jb0 = blockIdx.x * g.rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int b = blockIdx.z;
     const cplx* Xb = X + b * x_stride;
-    const int tot = g.rowsB * g.N1;
+    const int tot = rowsB * N1;
     double acc[FFT_VPT], d[FFT_VPT];
     bool hi[FFT_VPT];
 #pragma unroll
@@ -667,16 +944,16 @@ __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const 
         d[s] = 0;
         hi[s] = false;
         if (e < tot) {
-            int r = e / g.N1, ja = e - r * g.N1;
+            int r = e / N1, ja = e - r * N1;
             int m = jb0 + r + g.N2 * ja;
             hi[s] = (2 * m >= N);
             d[s] = (double)N * dth[row_of(m, N)];
         }
     }
     for (int q = Q - 1; q >= 0; --q) {
-        passB_load(g, buf, jb0, Xb + (int64_t)q * N);
+        passB_load(g, N1, rowsB, buf, jb0, Xb + (int64_t)q * N);
         __syncthreads();
-        lds_fft(buf, g.N1, g.rowsB, g.twN1);
+        lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
         const double sc = (q & 1) ? -1.0 : 1.0;  // s_{2q} = (-1)^q, s_{2q+1} = -(-1)^q
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
@@ -696,7 +973,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const 
     for (int s = 0; s < FFT_VPT; ++s) {
         int e = threadIdx.x + s * FFT_THREADS;
         if (e < tot) {
-            int r = e / g.N1, ja = e - r * g.N1;
+            int r = e / N1, ja = e - r * N1;
             int m = jb0 + r + g.N2 * ja;
             fb[row_of(m, N)] = acc[s];
         }
@@ -710,18 +987,21 @@ __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const 
 
 // Transposed Taylor pair q: DFT input at m (row k = j(m)):
 //   g_k d_k^{2q} (1 + i sigma_m d_k),  sigma_m = +1 (2m < N), -1 otherwise.
+template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passA(Geo g, int Q, int QG, const double* __restrict__ fv,
                                                             int64_t f_stride, const double* __restrict__ wts,
                                                             const double* __restrict__ dth, cplx* __restrict__ X,
                                                             int64_t x_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N2 = LA ? LA : g.N2;
+    const int colsA = LA ? FFT_CAP / LA : g.colsA;
     const int N = g.N;
-    const int na0 = blockIdx.x * g.colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const double* fb = fv + b * f_stride;
     cplx* Xb = X + b * x_stride;
-    const int tot = g.colsA * g.N2;
+    const int tot = colsA * N2;
     double gv[FFT_VPT], dv[FFT_VPT], pw[FFT_VPT];
     const int q0 = (Q * grp) / QG, q1 = (Q * (grp + 1)) / QG;
 #pragma unroll
@@ -729,7 +1009,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passA(Geo g, int Q, int Q
         int e = threadIdx.x + s * FFT_THREADS;
         gv[s] = dv[s] = pw[s] = 0;
         if (e < tot) {
-            int col = e % g.colsA, nbi = e / g.colsA;
+            int col = e % colsA, nbi = e / colsA;
             int m = na0 + col + g.N1 * nbi;
             int kk = row_of(m, N);
             gv[s] = wts[kk] * fb[kk];
@@ -744,52 +1024,36 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passA(Geo g, int Q, int Q
         for (int s = 0; s < FFT_VPT; ++s) {
             int e = threadIdx.x + s * FFT_THREADS;
             if (e < tot) {
-                int col = e % g.colsA, nbi = e / g.colsA;
+                int col = e % colsA, nbi = e / colsA;
                 int m = na0 + col + g.N1 * nbi;
                 double a = gv[s] * pw[s];
                 double sg = (2 * m < N) ? 1.0 : -1.0;
-                buf[col * g.N2 + nbi] = {a, sg * a * dv[s]};
+                buf[col * N2 + nbi] = {a, sg * a * dv[s]};
                 pw[s] *= dv[s] * dv[s];
             }
         }
         __syncthreads();
-        lds_fft(buf, g.N2, g.colsA, g.twN2);
-        passA_store(g, buf, na0, Xb + (int64_t)q * N);
+        lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+        passA_store<true>(g, N2, colsA, buf, na0, Xb + (int64_t)q * N);
         __syncthreads();
-    }
-}
-
-// Pass-B tiles closed under n -> N-n: local rows [0, h) are r = tile*h + i
-// (r < N2/2) and rows [h, 2h) their partners p(r) = N2 - r (p(0) = N2/2).
-__device__ __forceinline__ int pair_row(int tile, int i, int rowsB, int N2) {
-    if (N2 == 1) return 0;
-    int h = rowsB / 2;
-    if (i < h) return tile * h + i;
-    int r = tile * h + (i - h);
-    return (r == 0) ? N2 / 2 : N2 - r;
-}
-
-__device__ __forceinline__ void passB_load_rows(const Geo& g, cplx* buf, int tile, const cplx* __restrict__ X) {
-    const int tot = g.rowsB * g.N1;
-    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int i = e % g.rowsB, na = e / g.rowsB;
-        buf[i * g.N1 + na] = X[(int64_t)na * g.N2 + pair_row(tile, i, g.rowsB, g.N2)];
     }
 }
 
 // y_n = sum_l s_l (n/N)^l / l! Z_l[n]; Z_{2q} = Re(e_n A_n), Z_{2q+1} = Im(e_n B_n),
 // A = (U_n + conj U_{N-n})/2, B = (U_n - conj U_{N-n})/(2i), e_n = e^{i pi n/(2N)}.
+template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ X,
                                                             int64_t x_stride, double* __restrict__ y,
                                                             int64_t y_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N1 = LB ? LB : g.N1;
+    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     const int N = g.N;
-    const int tile = blockIdx.x;
+    const int N2 = g.N2;
+    const int vb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int b = blockIdx.z;
     const cplx* Xb = X + b * x_stride;
-    const int tot = g.rowsB * g.N1;
-    const int nrows = (g.N2 == 1) ? 1 : g.rowsB;
-    const int h = g.rowsB / 2;
+    const int tot = rowsB * N1;
     double acc[FFT_VPT], xs[FFT_VPT];
     cplx en[FFT_VPT];
     int part[FFT_VPT];
@@ -800,33 +1064,37 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passB(Geo g, int Q, const
         xs[s] = 0;
         en[s] = {0, 0};
         part[s] = 0;
-        if (e < tot && e / g.N1 < nrows) {
-            int i = e / g.N1, ja = e - i * g.N1;
-            int r = pair_row(tile, i, g.rowsB, g.N2);
-            int n = r + g.N2 * ja;
+        if (e < tot) {
+            int i = e / N1, ja = e - i * N1;
+            int r = actual_row(vb0 + i, N2);
+            int n = r + N2 * ja;
             xs[s] = (double)n / N;
             en[s] = half_shift(n, N);
+            // U_{N-n}: row 0 pairs with itself at (N1 - ja) mod N1, row N2/2
+            // with itself at N1-1-ja, row r with its neighbour N2 - r at N1-1-ja
             int ip, jp;
             if (r == 0) {
                 ip = i;
-                jp = (g.N1 - ja) & (g.N1 - 1);
+                jp = (N1 - ja) & (N1 - 1);
+            } else if (2 * r == N2) {
+                ip = i;
+                jp = N1 - 1 - ja;
             } else {
-                ip = (g.N2 == 1) ? i : (i < h ? i + h : i - h);
-                if (r == g.N2 / 2) ip = i;
-                jp = g.N1 - 1 - ja;
+                ip = i ^ 1;
+                jp = N1 - 1 - ja;
             }
-            part[s] = ip * g.N1 + jp;
+            part[s] = ip * N1 + jp;
         }
     }
     for (int q = Q - 1; q >= 0; --q) {
-        passB_load_rows(g, buf, tile, Xb + (int64_t)q * N);
+        passB_load(g, N1, rowsB, buf, vb0, Xb + (int64_t)q * N);
         __syncthreads();
-        lds_fft(buf, g.N1, g.rowsB, g.twN1);
+        lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
         const double sc = (q & 1) ? -1.0 : 1.0;
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
             int e = threadIdx.x + s * FFT_THREADS;
-            if (e < tot && e / g.N1 < nrows) {
+            if (e < tot) {
                 cplx U = buf[e], V = buf[part[s]];
                 cplx A = {0.5 * (U.re + V.re), 0.5 * (U.im - V.im)};
                 cplx Bm = {0.5 * (U.im + V.im), -0.5 * (U.re - V.re)};  // (U - conj V)/(2i)
@@ -842,36 +1110,55 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passB(Geo g, int Q, const
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         int e = threadIdx.x + s * FFT_THREADS;
-        if (e < tot && e / g.N1 < nrows) {
-            int i = e / g.N1, ja = e - i * g.N1;
-            int r = pair_row(tile, i, g.rowsB, g.N2);
-            yb[r + g.N2 * ja] = acc[s];
+        if (e < tot) {
+            int i = e / N1, ja = e - i * N1;
+            int r = actual_row(vb0 + i, N2);
+            yb[r + N2 * ja] = acc[s];
         }
     }
 }
 
 // (M^T y)_n for n < nd, chunk blockIdx.y of rows k:
 //   sum_{k in chunk, k <= n, k+n even} (eps_k/pi) Lam((n-k)/2) Lam((n+k)/2) y_k
-__global__ void k_dense_t(int nd, int chunk, const double* __restrict__ lam, const double* __restrict__ y,
-                          int64_t y_stride, double* __restrict__ part, int64_t part_stride) {
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
-    int ch = blockIdx.y;
-    int b = blockIdx.z;
-    if (n >= nd) return;
+// Same blocking as k_dense with the roles of rows and columns exchanged.
+__global__ __launch_bounds__(256) void k_dense_t(int nd, int chunk, const double* __restrict__ lam,
+                                                 const double* __restrict__ y, int64_t y_stride,
+                                                 double* __restrict__ part, int64_t part_stride) {
+    __shared__ double sy[DENSE_CH], slm[DENSE_CH / 2 + 256], slp[DENSE_CH / 2 + 256];
+    const int par = blockIdx.x & 1;
+    const int nb0 = (blockIdx.x >> 1) * 512;
+    const int ch = blockIdx.y;
+    const int b = blockIdx.z;
     const double* yb = y + b * y_stride;
-    int k0 = ch * chunk, k1 = min(n + 1, k0 + chunk);
-    int k = k0;
-    if ((n - k) & 1) ++k;
+    const int k0 = ch * DENSE_CH, k1 = min(nd, k0 + DENSE_CH);
+    const int n = nb0 + 2 * threadIdx.x + par;
+    // (n-k)/2 in [zm0, ...): n - k >= nb0 - (k0 + CH - 1); (n+k)/2 >= (nb0 + k0)/2
+    const int zm0 = (nb0 - (k0 + DENSE_CH - 1)) >> 1;
+    const int zp0 = (nb0 + k0) >> 1;
+    for (int i = threadIdx.x; i < DENSE_CH; i += 256) {
+        int kk = k0 + i;
+        sy[i] = (kk < k1) ? yb[kk] * ((kk == 0) ? 0.3183098861837907 : 0.6366197723675814) : 0.0;
+    }
+    for (int i = threadIdx.x; i < DENSE_CH / 2 + 256; i += 256) {
+        int zm = zm0 + i, zp = zp0 + i;
+        slm[i] = (zm >= 0 && zm < nd) ? lam[zm] : 0.0;
+        slp[i] = (zp >= 0 && zp < nd) ? lam[zp] : 0.0;
+    }
+    __syncthreads();
+    if (n >= nd) return;
     double acc = 0;
-    for (; k < k1; k += 2) {
-        double e = (k == 0) ? 0.3183098861837907 : 0.6366197723675814;
-        acc = fma(e * lam[(n - k) >> 1] * lam[(n + k) >> 1], yb[k], acc);
+    int kk = k0;
+    if ((n - kk) & 1) ++kk;
+    int kend = min(k1, n + 1);
+    for (; kk < kend; kk += 2) {
+        int im = ((n - kk) >> 1) - zm0, ip = ((n + kk) >> 1) - zp0;
+        acc = fma(slm[im] * slp[ip], sy[kk - k0], acc);
     }
     part[b * part_stride + (int64_t)ch * nd + n] = acc;
 }
 
 __global__ void k_dense_t_reduce(int nd, int nchunk, int chunk, const double* __restrict__ part,
-                                 int64_t part_stride, double* __restrict__ out, int64_t out_stride) {
+                                 int64_t part_stride, double* __restrict__ out, int64_t out_stride, int half) {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     int b = blockIdx.z;
     if (n >= nd) return;
@@ -879,43 +1166,49 @@ __global__ void k_dense_t_reduce(int nd, int nchunk, int chunk, const double* __
     double s = 0;
     int last = min(nchunk - 1, n / chunk);
     for (int ch = 0; ch <= last; ++ch) s += pb[(int64_t)ch * nd + n];
-    out[b * out_stride + n] = s;
+    out[b * out_stride + n] = half ? (n + 0.5) * s : s;
 }
 
 // u_j = sum_k (eps_k/N) y_k cos(k theta_j): DFT of (eps_k/N) y_k e^{i pi k/(2N)},
 // u at row j(m) = Re V_m.
+template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) void k_dct3_passA(Geo g, const double* __restrict__ y, int64_t y_stride,
                                                            cplx* __restrict__ X, int64_t x_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N2 = LA ? LA : g.N2;
+    const int colsA = LA ? FFT_CAP / LA : g.colsA;
     const int N = g.N;
-    const int na0 = blockIdx.x * g.colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int b = blockIdx.z;
     const double* yb = y + b * y_stride;
-    const int tot = g.colsA * g.N2;
+    const int tot = colsA * N2;
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int col = e % g.colsA, nbi = e / g.colsA;
+        int col = e % colsA, nbi = e / colsA;
         int n = na0 + col + g.N1 * nbi;
         double a = yb[n] * ((n == 0) ? 1.0 : 2.0) / N;
-        buf[col * g.N2 + nbi] = cscale(half_shift(n, N), a);
+        buf[col * N2 + nbi] = cscale(half_shift(n, N), a);
     }
     __syncthreads();
-    lds_fft(buf, g.N2, g.colsA, g.twN2);
-    passA_store(g, buf, na0, X + b * x_stride);
+    lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+    passA_store<false>(g, N2, colsA, buf, na0, X + b * x_stride);
 }
 
+template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64_t x_stride,
                                                            double* __restrict__ u, int64_t u_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N1 = LB ? LB : g.N1;
+    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     const int N = g.N;
-    const int jb0 = blockIdx.x * g.rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int b = blockIdx.z;
-    passB_load(g, buf, jb0, X + b * x_stride);
+    passB_load(g, N1, rowsB, buf, jb0, X + b * x_stride);
     __syncthreads();
-    lds_fft(buf, g.N1, g.rowsB, g.twN1);
-    const int tot = g.rowsB * g.N1;
+    lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
+    const int tot = rowsB * N1;
     double* ub = u + b * u_stride;
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int r = e / g.N1, ja = e - r * g.N1;
+        int r = e / N1, ja = e - r * N1;
         int m = jb0 + r + g.N2 * ja;
         ub[row_of(m, N)] = buf[e].re;
     }
@@ -924,16 +1217,19 @@ __global__ __launch_bounds__(FFT_THREADS) void k_dct3_passB(Geo g, const cplx* _
 // Transposed far field, pass A: for every term (b, m), ascending m, the DFT
 // input at m is rho at row j = j(m) (conjugated when 2m >= N) with
 //   rho_j = u_j e^{i (m+1/2)(theta_j - pi/2)} (2 sin theta_j)^{-m-1/2} [j in block b].
-__global__ __launch_bounds__(FFT_THREADS) void k_tfar_passA(Geo g, FarParams F, const double* __restrict__ u,
+template <int LA>
+__global__ __launch_bounds__(FFT_THREADS) void k_tfar_passA(Geo g, FarParams F, int G, const double* __restrict__ u,
                                                            int64_t u_stride, cplx* __restrict__ X,
                                                            int64_t x_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N2 = LA ? LA : g.N2;
+    const int colsA = LA ? FFT_CAP / LA : g.colsA;
     const int N = g.N;
-    const int na0 = blockIdx.x * g.colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int b = blockIdx.z;
     const double* ub = u + b * u_stride;
     cplx* Xb = X + b * x_stride;
-    const int tot = g.colsA * g.N2;
+    const int tot = colsA * N2;
     const double pi = 3.141592653589793;
     cplx gm[FFT_VPT], rq[FFT_VPT];
     int blk[FFT_VPT];
@@ -945,7 +1241,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passA(Geo g, FarParams F, 
         blk[s] = -1;
         cj[s] = false;
         if (e < tot) {
-            int col = e % g.colsA, nbi = e / g.colsA;
+            int col = e % colsA, nbi = e / colsA;
             int m = na0 + col + g.N1 * nbi;
             int j = row_of(m, N);
             cj[s] = (2 * m >= N);
@@ -964,21 +1260,21 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passA(Geo g, FarParams F, 
     }
     for (int m = 0; m < F.Mmax; ++m) {
         for (int t = 0; t < F.nterm; ++t) {
-            if (F.term_m[t] != m) continue;
+            if (F.term_m[t] != m || (t % G) != (int)blockIdx.y) continue;
             const int tb = F.term_blk[t];
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) {
                 int e = threadIdx.x + s * FFT_THREADS;
                 if (e < tot) {
-                    int col = e % g.colsA, nbi = e / g.colsA;
+                    int col = e % colsA, nbi = e / colsA;
                     cplx v = (blk[s] == tb) ? gm[s] : cplx{0, 0};
                     if (cj[s]) v.im = -v.im;
-                    buf[col * g.N2 + nbi] = v;
+                    buf[col * N2 + nbi] = v;
                 }
             }
             __syncthreads();
-            lds_fft(buf, g.N2, g.colsA, g.twN2);
-            passA_store(g, buf, na0, Xb + (int64_t)t * N);
+            lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+            passA_store<false>(g, N2, colsA, buf, na0, Xb + (int64_t)t * N);
             __syncthreads();
         }
 #pragma unroll
@@ -988,15 +1284,18 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passA(Geo g, FarParams F, 
 
 // Transposed far field, pass B: out_n = sum_terms C_n h_{m,n} [n >= nlo_b]
 // Re(e^{i pi n/(2N)} U_n), descending m (h by multiplication only).
-__global__ __launch_bounds__(FFT_THREADS) void k_tfar_passB(Geo g, FarParams F, const cplx* __restrict__ X,
+template <int LB>
+__global__ __launch_bounds__(FFT_THREADS) void k_tfar_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
                                                            int64_t x_stride, double* __restrict__ out,
                                                            int64_t out_stride) {
     __shared__ cplx buf[FFT_CAP];
+    const int N1 = LB ? LB : g.N1;
+    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     const int N = g.N;
-    const int jb0 = blockIdx.x * g.rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int b = blockIdx.z;
     const cplx* Xb = X + b * x_stride;
-    const int tot = g.rowsB * g.N1;
+    const int tot = rowsB * N1;
     double acc[FFT_VPT], h[FFT_VPT];
     cplx en[FFT_VPT];
     int nn[FFT_VPT];
@@ -1008,24 +1307,25 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passB(Geo g, FarParams F, 
         en[s] = {0, 0};
         nn[s] = -1;
         if (e < tot) {
-            int r = e / g.N1, ja = e - r * g.N1;
+            int r = e / N1, ja = e - r * N1;
             int n = jb0 + r + g.N2 * ja;
             nn[s] = n;
             if (n >= F.nd) {
                 en[s] = cscale(half_shift(n, N), stieltjes_C((double)n));
-                double hv = 1;
-                for (int j = 1; j < F.Mmax; ++j) hv *= (j - 0.5) * (j - 0.5) / (j * (n + j + 0.5));
-                h[s] = hv;
+                // h_{Mmax-1,n} = K / prod_{j<Mmax} (n+j+1/2),  K = prod_{j<Mmax} (j-1/2)^2/j
+                double den = 1;
+                for (int j = 1; j < F.Mmax; ++j) den *= (n + j + 0.5);
+                h[s] = F.hK / den;
             }
         }
     }
     for (int m = F.Mmax - 1; m >= 0; --m) {
         for (int t = 0; t < F.nterm; ++t) {
-            if (F.term_m[t] != m) continue;
+            if (F.term_m[t] != m || (t % G) != (int)blockIdx.y) continue;
             const int nlo = F.blk[F.term_blk[t]].nlo;
-            passB_load(g, buf, jb0, Xb + (int64_t)t * N);
+            passB_load(g, N1, rowsB, buf, jb0, Xb + (int64_t)t * N);
             __syncthreads();
-            lds_fft(buf, g.N1, g.rowsB, g.twN1);
+            lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) {
                 int e = threadIdx.x + s * FFT_THREADS;
@@ -1042,7 +1342,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passB(Geo g, FarParams F, 
                 if (nn[s] >= 0) h[s] *= m * (nn[s] + m + 0.5) / ((m - 0.5) * (m - 0.5));
         }
     }
-    double* ob = out + b * out_stride;
+    double* ob = out + b * out_stride + (int64_t)blockIdx.y * N;
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         int e = threadIdx.x + s * FFT_THREADS;
@@ -1053,104 +1353,138 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passB(Geo g, FarParams F, 
 // Transposed near field.  (1) k_near_items with c == null gives each
 // (row, chunk) transfer matrix; (2) k_tnear_scan chains them per row into the
 // state (P, D) at every chunk start; (3) k_tnear_accum reruns each chunk from
-// its true state for 256 rows of one segment and sums over the rows
+// its true state for the 64 rows of one wave and sums over the rows
 //   out_n += P_n(x_j) (u_j + (-1)^n u_{N-1-j})
-// through an LDS tile, 32 degrees at a time.
-__global__ void k_tnear_scan(NearParams NP, const double* __restrict__ items, int64_t it_stride,
-                             double* __restrict__ st, int64_t st_stride) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    int b = blockIdx.z;
-    if (j >= NP.jnear) return;
-    int sgi = -1;
-    for (int s = 0; s < NP.nseg; ++s)
-        if (j >= NP.seg[s].jlo && j < NP.seg[s].jhi) sgi = s;
+// through an LDS tile, 32 degrees at a time; partial sums per row group.
+// One wave per row: states (P, D) at every chunk start.  Lane runs of chunks
+// are chained into transfer matrices, an exclusive scan over lanes gives each
+// run's start state, and every lane then walks its run.
+__global__ __launch_bounds__(64) void k_tnear_scan(NearParams NP, const double* __restrict__ items,
+                                                   int64_t it_stride, double* __restrict__ st, int64_t st_stride) {
+    const int j = blockIdx.x;
+    const int b = blockIdx.z;
+    const int lane = threadIdx.x;
+    const int sgi = near_seg_of(NP, j);
     if (sgi < 0) return;
     const Seg S = NP.seg[sgi];
     const double* it = items + b * it_stride;
     double* so = st + b * st_stride;
-    int nrows = S.jhi - S.jlo;
-    double P = 1, D = 0;
-    for (int ch = 0; ch < S.nchunk; ++ch) {
-        int id = S.item_off + ch * nrows + (j - S.jlo);
+    const int nrows = S.jhi - S.jlo;
+    const int id0 = S.item_off + (j - S.jlo);
+    const int rest = S.nchunk - 1;
+    const int per = (rest + 63) / 64;
+    const int c0 = 1 + lane * per, c1 = min(S.nchunk, c0 + per);
+    // this lane's run as a transfer matrix [[a, c], [b, d]]
+    double a = 1, bb = 0, c = 0, d = 1;
+    for (int ch = c0; ch < c1; ++ch) {
+        const double* q = it + (int64_t)(id0 + ch * nrows) * 8;
+        double na = q[0] * a + q[2] * bb, nbv = q[1] * a + q[3] * bb;
+        double nc = q[0] * c + q[2] * d, nd = q[1] * c + q[3] * d;
+        a = na;
+        bb = nbv;
+        c = nc;
+        d = nd;
+    }
+    // inclusive scan: T_l <- T_l T_{l-k}
+    for (int k2 = 1; k2 < 64; k2 *= 2) {
+        double pa = __shfl_up(a, k2), pb = __shfl_up(bb, k2), pc = __shfl_up(c, k2), pd = __shfl_up(d, k2);
+        if (lane >= k2) {
+            double na = a * pa + c * pb, nbv = bb * pa + d * pb;
+            double nc = a * pc + c * pd, nd = bb * pc + d * pd;
+            a = na;
+            bb = nbv;
+            c = nc;
+            d = nd;
+        }
+    }
+    // exclusive prefix = inclusive of lane-1
+    double ea = __shfl_up(a, 1), eb = __shfl_up(bb, 1), ec = __shfl_up(c, 1), ed = __shfl_up(d, 1);
+    if (lane == 0) {
+        ea = 1;
+        eb = 0;
+        ec = 0;
+        ed = 1;
+    }
+    const double* o = it + (int64_t)id0 * 8;
+    double P1 = o[0], D1 = o[1];  // state after chunk 0
+    double P = ea * P1 + ec * D1, D = eb * P1 + ed * D1;
+    if (lane == 0) {
+        so[2 * id0] = 1;
+        so[2 * id0 + 1] = 0;
+    }
+    for (int ch = c0; ch < c1; ++ch) {
+        int id = id0 + ch * nrows;
         so[2 * id] = P;
         so[2 * id + 1] = D;
         const double* q = it + (int64_t)id * 8;
-        if (ch == 0) {
-            P = q[0];
-            D = q[1];
-        } else {
-            double Pn = P * q[0] + D * q[2];
-            double Dn = P * q[1] + D * q[3];
-            P = Pn;
-            D = Dn;
-        }
+        double Pn = q[0] * P + q[2] * D;
+        double Dn = q[1] * P + q[3] * D;
+        P = Pn;
+        D = Dn;
     }
 }
 
-constexpr int TN_ROWS = 256;
 constexpr int TN_STEPS = 32;
 
-// grid.x enumerates (segment, chunk, row group) with the table from the plan
-__global__ __launch_bounds__(TN_ROWS) void k_tnear_accum(int N, NearParams NP, const int* __restrict__ wg_seg,
-                                                          const int* __restrict__ wg_rg_off,
-                                                          const double* __restrict__ A,
-                                                          const double* __restrict__ B, const double* __restrict__ u,
-                                                          int64_t u_stride, const double* __restrict__ st,
-                                                          int64_t st_stride, double* __restrict__ part,
-                                                          int64_t part_stride) {
-    __shared__ double tile[TN_STEPS][TN_ROWS + 1];
-    const int wgid = blockIdx.x;
+__global__ __launch_bounds__(64) void k_tnear_accum(int N, NearParams NP, const int* __restrict__ wg_seg,
+                                                    const int* __restrict__ segoff, const double* __restrict__ rcp,
+                                                    const double* __restrict__ u, int64_t u_stride,
+                                                    const double* __restrict__ st, int64_t st_stride,
+                                                    double* __restrict__ part, int64_t part_stride) {
+    __shared__ double tile[TN_STEPS][64 + 1];
+    const NearWG W = near_wg(NP, wg_seg, segoff, blockIdx.x);
+    const Seg S = NP.seg[W.seg];
     const int b = blockIdx.z;
-    const int sgi = wg_seg[wgid];
-    const Seg S = NP.seg[sgi];
     const int nrows = S.jhi - S.jlo;
-    const int ngroups = (nrows + TN_ROWS - 1) / TN_ROWS;
-    // local index inside the segment: chunk-major over row groups
-    int loc = wgid - wg_rg_off[2 * sgi];
-    int ch = loc / ngroups;
-    int grp = loc - ch * ngroups;
-    int rg_global = wg_rg_off[2 * sgi + 1] + grp;
-    int row = grp * TN_ROWS + threadIdx.x;
-    bool act = row < nrows;
-    int j = S.jlo + (act ? row : 0);
+    const int row = W.grp * 64 + threadIdx.x;
+    const bool act = row < nrows;
+    const int j = S.jlo + (act ? row : 0);
+    const int rg_global = segoff[2 * W.seg + 1] + W.grp;
     const double* ub = u + b * u_stride;
     const double* so = st + b * st_stride;
-    double uj = act ? ub[j] : 0.0, um = act ? ub[N - 1 - j] : 0.0;
+    const double uj = act ? ub[j] : 0.0, um = act ? ub[N - 1 - j] : 0.0;
     const double pi = 3.141592653589793;
     double sn = sin(0.5 * (j + 0.5) * pi / N);
-    double uu = 2.0 * sn * sn;
-    int id = S.item_off + ch * nrows + (act ? row : 0);
+    const double uu = 2.0 * sn * sn;
+    const int id = S.item_off + W.ch * nrows + (act ? row : 0);
     double p = act ? so[2 * id] : 0.0, d = act ? so[2 * id + 1] : 0.0;
-    int n0 = ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
+    const int n0 = W.ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
     double* pb = part + b * part_stride + (int64_t)rg_global * N;
+    const double we = uj + um, wo = uj - um;  // weights of even / odd degrees
     for (int nb0 = n0; nb0 < n1; nb0 += TN_STEPS) {
-        int cnt = min(TN_STEPS, n1 - nb0);
-        for (int i = 0; i < cnt; ++i) {
-            int n = nb0 + i;
-            tile[i][threadIdx.x] = p * ((n & 1) ? uj - um : uj + um);
-            double dn = fma(A[n], d, -B[n] * uu * p);
-            p += dn;
-            d = dn;
+        const int cnt = min(TN_STEPS, n1 - nb0);
+        if (cnt == TN_STEPS) {
+#pragma unroll
+            for (int i = 0; i < TN_STEPS; i += 2) {
+                tile[i][threadIdx.x] = p * we;
+                reinsch_step(uu, rcp[nb0 + i], p, d);
+                tile[i + 1][threadIdx.x] = p * wo;
+                reinsch_step(uu, rcp[nb0 + i + 1], p, d);
+            }
+        } else {
+            for (int i = 0; i < cnt; ++i) {
+                tile[i][threadIdx.x] = p * (((nb0 + i) & 1) ? wo : we);
+                reinsch_step(uu, rcp[nb0 + i], p, d);
+            }
         }
         __syncthreads();
-        // 8 threads per degree column, 32 rows each, then a butterfly of 8
-        int col = threadIdx.x >> 3, prt = threadIdx.x & 7;
+        // two lanes per degree column, 32 rows each
+        const int col = threadIdx.x >> 1, half = threadIdx.x & 1;
         double s = 0;
-        if (col < cnt)
-            for (int r = 0; r < TN_ROWS / 8; ++r) s += tile[col][prt * (TN_ROWS / 8) + r];
-        s += __shfl_xor(s, 1, 8);
-        s += __shfl_xor(s, 2, 8);
-        s += __shfl_xor(s, 4, 8);
-        if (prt == 0 && col < cnt) pb[nb0 + col] = s;
+#pragma unroll 8
+        for (int r = 0; r < 32; ++r) s += tile[col][half * 32 + r];
+        s += __shfl_xor(s, 1, 2);
+        if (half == 0 && col < cnt) pb[nb0 + col] = s;
         __syncthreads();
     }
 }
 
-// c_n = (n + 1/2) (dense_n [n < nd] + far_n + sum_rg near parts [nd <= n < nend(rg)])
+// (M^T y)_n = dense_n [n < nd] + far_n + sum_rg near parts [nd <= n < nend(rg)],
+// times n + 1/2 when `half` (the D_s of the inverse transform)
 __global__ void k_idlt_final(int N, int nd, int nrg, const int* __restrict__ rg_nend, const double* __restrict__ dense,
-                             int64_t dense_stride, const double* __restrict__ far, int64_t far_stride,
+                             int64_t dense_stride, int G, const double* __restrict__ far, int64_t far_stride,
                              const double* __restrict__ part, int64_t part_stride, double* __restrict__ c,
-                             int64_t c_stride) {
+                             int64_t c_stride, int half) {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     int b = blockIdx.z;
     if (n >= N) return;
@@ -1158,23 +1492,39 @@ __global__ void k_idlt_final(int N, int nd, int nrg, const int* __restrict__ rg_
     if (n < nd) {
         s = dense[b * dense_stride + n];
     } else {
-        s = far ? far[b * far_stride + n] : 0.0;
+        s = 0.0;
+        for (int q = 0; q < G; ++q) s += far[b * far_stride + (int64_t)q * N + n];
         const double* pb = part + b * part_stride;
         for (int r = 0; r < nrg; ++r)
             if (n < rg_nend[r]) s += pb[(int64_t)r * N + n];
     }
-    c[b * c_stride + n] = (n + 0.5) * s;
+    c[b * c_stride + n] = half ? (n + 0.5) * s : s;
 }
 
 }  // namespace dlt
 
 // ================================================================ host ====
+// Launch a length-templated pass kernel: the compile-time length is used
+// when the tile is full (N >= FFT_CAP), the run-time path otherwise.
+#define LEN_LAUNCH(FULL, LEN, KER, GRID, BLK, SHM, STR, ...)                      \
+    do {                                                                          \
+        int L_ = (FULL) ? (LEN) : 0;                                              \
+        switch (L_) {                                                             \
+            case 64: KER<64><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;         \
+            case 128: KER<128><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;       \
+            case 256: KER<256><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;       \
+            case 512: KER<512><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;       \
+            case 1024: KER<1024><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;     \
+            case 2048: KER<2048><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;     \
+            default: KER<0><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;          \
+        }                                                                         \
+    } while (0)
 namespace dlt {
 
 // ---- kernel trace: start/stop events around every launch while enabled
 namespace trace {
 struct Rec {
-    const char* name;
+    std::string name;
     hipEvent_t a, b;
 };
 static std::mutex mu;
@@ -1202,6 +1552,9 @@ void trace_set(bool enable) {
 }
 
 // launches `fn` bracketed by events when tracing
+// current transform size, appended to trace names ("kernel/N")
+static thread_local int64_t trace_n = 0;
+
 template <class F>
 static void traced(const char* name, hipStream_t s, F&& fn) {
     if (!trace::on) {
@@ -1209,7 +1562,7 @@ static void traced(const char* name, hipStream_t s, F&& fn) {
         return;
     }
     std::lock_guard<std::mutex> lk(trace::mu);
-    trace::Rec r{name, trace::take(), trace::take()};
+    trace::Rec r{std::string(name) + "/" + std::to_string(trace_n), trace::take(), trace::take()};
     (void)hipEventRecord(r.a, s);
     fn();
     (void)hipEventRecord(r.b, s);
@@ -1266,12 +1619,26 @@ void work_carve(const Plan& p, int64_t nb, void* base, Work& w) {
     w.spart = (int64_t)(al256(p.ws_part) / sizeof(double));
 }
 
-hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, hipStream_t s) {
+hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, hipStream_t s) {
+    trace_n = p.N;
     const NodeParams& P = p.nodes;
     int nh = (P.N + 1) / 2;
     if (P.kb > 0) {
-        size_t shm = (7 * 256 + 3) * sizeof(double);
-        traced("k_nodes_boundary", s, [&] { k_nodes_boundary<<<P.kb, 256, shm, s>>>(P, p.d_guess, p.d_recA, p.d_recB, theta, w, dth); });
+        if (P.newton_b == 0 && P.N >= (1 << 16)) {
+            int parts = P.N >> 16;
+            if (parts > NODE_PARTS_MAX) parts = NODE_PARTS_MAX;
+            traced("k_nodes_bpart", s, [&] {
+                k_nodes_bpart<<<dim3(P.kb, parts), 1024, 0, s>>>(P, p.d_guess, parts, scratch);
+            });
+            traced("k_nodes_bfin", s, [&] {
+                k_nodes_bfin<<<P.kb, 64, 0, s>>>(P, p.d_guess, parts, scratch, theta, w, dth);
+            });
+        } else {
+            int T = 64;
+            while (T < 1024 && T * 256 < P.N) T *= 2;
+            size_t shm = (size_t)7 * T * sizeof(double);
+            traced("k_nodes_boundary", s, [&] { k_nodes_boundary<<<P.kb, T, shm, s>>>(P, p.d_guess, theta, w, dth); });
+        }
     }
     int ni = nh - P.kb;
     if (ni > 0)
@@ -1279,98 +1646,169 @@ hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, hipSt
     return hipGetLastError();
 }
 
-hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, double* chat, Work& w, hipStream_t s) {
+// Scratch of a sub-plan's run, carved from the parent's DFT-intermediate slab
+// (not yet in use when the low-degree block is computed).
+static Work sub_work(const Plan& sub, int64_t nb, const Work& w) {
+    Work sw;
+    work_carve(sub, nb, (void*)w.X, sw);
+    return sw;
+}
+
+// chat = M c.  Columns n < nd: the exact conversion (dense for nd <= 8192,
+// otherwise the same algorithm at size nd, recursively); columns n >= nd:
+// values on the Chebyshev grid from the near and far fields, then DCT-II.
+hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, double* chat, int64_t hs, Work& w,
+                        hipStream_t s) {
+    trace_n = p.N;
     const int N = (int)p.N;
     const int nd = p.nd;
     const Geo& g = p.geo;
-    // dense block: partials then reduction into the last slab of `dense`
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
-    dim3 gd((nd + 255) / 256, p.dense_nchunk, (unsigned)nb);
-    traced("k_dense", s, [&] { k_dense<<<gd, 256, 0, s>>>(N, nd, p.dense_chunk, p.d_lam, c, N, w.dense, w.sdense); });
-    if (N <= nd) {
-        traced("k_dense_reduce", s, [&] { k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
-                                                                           w.dense, w.sdense, chat, N); });
-        return hipGetLastError();
+    if (!p.sub) {
+        dim3 gd(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb);
+        traced("k_dense", s, [&] { k_dense<<<gd, 256, 0, s>>>(N, nd, p.dense_chunk, p.d_lam, c, cs, w.dense, w.sdense); });
+        double* dst = (N <= nd) ? chat : dense_out;
+        int64_t ds = (N <= nd) ? hs : w.sdense;
+        traced("k_dense_reduce", s, [&] {
+            k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                               w.dense, w.sdense, dst, ds);
+        });
+        if (N <= nd) return hipGetLastError();
+    } else {
+        Work sw = sub_work(*p.sub, nb, w);
+        hipError_t e = run_leg2cheb(*p.sub, nb, c, cs, dense_out, w.sdense, sw, s);
+        trace_n = p.N;
+        if (e != hipSuccess) return e;
     }
-    traced("k_dense_reduce", s, [&] { k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
-                                                                       w.dense, w.sdense, dense_out, w.sdense); });
     // near field
     const NearParams& NP = p.near;
     if (NP.nitems > 0)
-        traced("k_near_items", s, [&] { k_near_items<<<dim3((NP.nitems + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(N, NP, p.d_recA, p.d_recB, c, N,
-                                                                                w.items, w.sitems); });
+        traced("k_near_items", s, [&] {
+            k_near_items<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, s>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, c,
+                                                                      cs, w.items, w.sitems);
+        });
     if (NP.jnear > 0)
-        traced("k_near_combine", s, [&] { k_near_combine<<<dim3((NP.jnear + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(NP, w.items, w.sitems, w.near,
-                                                                                 w.snear); });
+        traced("k_near_combine", s, [&] {
+            k_near_combine<<<dim3(NP.jnear, 1, (unsigned)nb), 64, 0, s>>>(NP, w.items, w.sitems, w.near, w.snear);
+        });
     // far field
     const FarParams& F = p.far;
-    traced("k_far_passA", s, [&] { k_far_passA<<<dim3(g.N1 / g.colsA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, F, c, N, w.X, w.sX); });
-    traced("k_far_passB", s, [&] { k_far_passB<<<dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb), FFT_THREADS, 0, s>>>(g, F, p.tgB, w.X, w.sX, w.v,
-                                                                               w.sv); });
+    traced("k_far_passA", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_far_passA, (dim3(g.N1 / g.colsA, p.tgA, (unsigned)nb)), FFT_THREADS, 0, s, g, F, p.tgA, c, cs, w.X, w.sX);
+    });
+    traced("k_far_passB", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_far_passB, (dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb)), FFT_THREADS, 0, s, g, F, p.tgB, w.X, w.sX, w.v, w.sv);
+    });
     // values on the grid -> coefficients
-    traced("k_dct2_passA", s, [&] { k_dct2_passA<<<dim3(g.N1 / g.colsA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.tgB, w.v, w.sv, w.near, w.snear,
-                                                                            NP.jnear, w.X, w.sX); });
-    traced("k_dct2_passB", s, [&] { k_dct2_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, nd, w.X, w.sX, dense_out, w.sdense,
-                                                                            chat, N); });
+    traced("k_dct2_passA", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_dct2_passA, (dim3(g.N1 / g.colsA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, p.tgB, w.v, w.sv, w.near, w.snear,
+                                                                                NP.jnear, w.X, w.sX);
+    });
+    traced("k_dct2_passB", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_dct2_passB, (dim3(g.N2 / g.rowsB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, nd, w.X, w.sX, dense_out, w.sdense,
+                                                                                chat, hs);
+    });
     return hipGetLastError();
 }
 
-hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, const double* dth, double* f, Work& w,
-                    hipStream_t s) {
+// out = M^T y (times n + 1/2 when `half`): rows n < nd from the exact
+// conversion (dense or recursive), rows n >= nd as P^T C D_eps y on the grid.
+hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys, double* out, int64_t os, int half,
+                          Work& w, hipStream_t s) {
+    trace_n = p.N;
+    const int N = (int)p.N;
+    const int nd = p.nd;
+    const Geo& g = p.geo;
+    const int tilesA = g.N1 / g.colsA;
+    double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
+    if (!p.sub) {
+        traced("k_dense_t", s, [&] {
+            k_dense_t<<<dim3(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb), 256, 0, s>>>(nd, p.dense_chunk, p.d_lam, y,
+                                                                                         ys, w.dense, w.sdense);
+        });
+        double* dst = (N <= nd) ? out : dense_out;
+        int64_t ds = (N <= nd) ? os : w.sdense;
+        int hf = (N <= nd) ? half : 0;
+        traced("k_dense_t_reduce", s, [&] {
+            k_dense_t_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                                 w.dense, w.sdense, dst, ds, hf);
+        });
+        if (N <= nd) return hipGetLastError();
+    } else {
+        Work sw = sub_work(*p.sub, nb, w);
+        hipError_t e = run_leg2cheb_t(*p.sub, nb, y, ys, dense_out, w.sdense, 0, sw, s);
+        trace_n = p.N;
+        if (e != hipSuccess) return e;
+    }
+    const NearParams& NP = p.near;
+    // u = C D_eps y on the grid
+    double* u = w.vec;
+    traced("k_dct3_passA", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_dct3_passA, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, y, ys, w.X, w.sX);
+    });
+    traced("k_dct3_passB", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_dct3_passB, (dim3(g.N2 / g.rowsB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, w.X, w.sX, u, w.svec);
+    });
+    // transposed far field
+    traced("k_tfar_passA", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_tfar_passA, (dim3(tilesA, p.tgA, (unsigned)nb)), FFT_THREADS, 0, s, g, p.far, p.tgA, u, w.svec, w.X, w.sX);
+    });
+    traced("k_tfar_passB", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_tfar_passB, (dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb)), FFT_THREADS, 0, s, g, p.far, p.tgB, w.X, w.sX, w.v, w.sv);
+    });
+    // transposed near field
+    if (NP.nitems > 0) {
+        traced("k_near_items", s, [&] {
+            k_near_items<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, s>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp,
+                                                                      nullptr, 0, w.items, w.sitems);
+        });
+        traced("k_tnear_scan", s, [&] {
+            k_tnear_scan<<<dim3(NP.jnear, 1, (unsigned)nb), 64, 0, s>>>(NP, w.items, w.sitems, w.states, w.sstates);
+        });
+        traced("k_tnear_accum", s, [&] {
+            k_tnear_accum<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, s>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, u,
+                                                                       w.svec, w.states, w.sstates, w.part, w.spart);
+        });
+    }
+    traced("k_idlt_final", s, [&] {
+        k_idlt_final<<<dim3((N + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(N, nd, (NP.nitems > 0) ? p.tn_nrg : 0,
+                                                                          p.d_tn_rgnend, dense_out, w.sdense, p.tgB, w.v,
+                                                                          w.sv, w.part, w.spart, out, os, half);
+    });
+    return hipGetLastError();
+}
+
+hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
+                    Work& w, hipStream_t s) {
+    trace_n = p.N;
     const Geo& g = p.geo;
     const int Q = p.L / 2;
     const int tilesA = g.N1 / g.colsA;
     // small transforms: split the Taylor pairs over blocks for parallelism
     int QG = (tilesA * nb >= 256) ? 1 : Q;
-    traced("k_ndct_passA", s, [&] { k_ndct_passA<<<dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, QG, chat, p.N, w.X, w.sX); });
-    traced("k_ndct_passB", s, [&] { k_ndct_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, w.X, w.sX, dth, f, p.N); });
+    traced("k_ndct_passA", s, [&] { LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_ndct_passA, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, Q, QG, chat, hs, w.X, w.sX); });
+    traced("k_ndct_passB", s, [&] { LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_ndct_passB, (dim3(g.N2 / g.rowsB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, Q, w.X, w.sX, dth, f, p.N); });
     return hipGetLastError();
 }
 
 hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double* wts, const double* dth,
                        double* c, Work& w, hipStream_t s) {
+    trace_n = p.N;
     const int N = (int)p.N;
-    const int nd = p.nd;
     const Geo& g = p.geo;
     const int Q = p.L / 2;
     const int tilesA = g.N1 / g.colsA;
     int QG = (tilesA * nb >= 256) ? 1 : Q;
     double* y = w.chat;  // T^T D_w f, stride w.schat
-    // transposed Taylor series: y = T^T (w f)
-    traced("k_tndct_passA", s, [&] { k_tndct_passA<<<dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, QG, f, N, wts, dth, w.X, w.sX); });
+    traced("k_tndct_passA", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_tndct_passA, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, Q, QG, f, N, wts, dth, w.X, w.sX);
+    });
     int tilesB = (g.N2 == 1) ? 1 : g.N2 / g.rowsB;
-    traced("k_tndct_passB", s, [&] { k_tndct_passB<<<dim3(tilesB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, Q, w.X, w.sX, y, w.schat); });
-    // dense block of M^T for n < nd
-    double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
-    traced("k_dense_t", s, [&] { k_dense_t<<<dim3((nd + 255) / 256, p.dense_nchunk, (unsigned)nb), 256, 0, s>>>(nd, p.dense_chunk, p.d_lam, y,
-                                                                                 w.schat, w.dense, w.sdense); });
-    traced("k_dense_t_reduce", s, [&] { k_dense_t_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
-                                                                         w.dense, w.sdense, dense_out, w.sdense); });
-    const double* far = nullptr;
-    const NearParams& NP = p.near;
-    if (N > nd) {
-        // u = C D_eps y on the grid
-        double* u = w.vec;
-        traced("k_dct3_passA", s, [&] { k_dct3_passA<<<dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, y, w.schat, w.X, w.sX); });
-        traced("k_dct3_passB", s, [&] { k_dct3_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, w.X, w.sX, u, w.svec); });
-        // transposed far field
-        traced("k_tfar_passA", s, [&] { k_tfar_passA<<<dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.far, u, w.svec, w.X, w.sX); });
-        traced("k_tfar_passB", s, [&] { k_tfar_passB<<<dim3(g.N2 / g.rowsB, 1, (unsigned)nb), FFT_THREADS, 0, s>>>(g, p.far, w.X, w.sX, w.v, w.sv); });
-        far = w.v;
-        // transposed near field
-        if (NP.nitems > 0) {
-            traced("k_near_items", s, [&] { k_near_items<<<dim3((NP.nitems + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(
-                N, NP, p.d_recA, p.d_recB, nullptr, 0, w.items, w.sitems); });
-            traced("k_tnear_scan", s, [&] { k_tnear_scan<<<dim3((NP.jnear + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(NP, w.items, w.sitems,
-                                                                                    w.states, w.sstates); });
-            traced("k_tnear_accum", s, [&] { k_tnear_accum<<<dim3(p.tn_wg, 1, (unsigned)nb), TN_ROWS, 0, s>>>(
-                N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_recA, p.d_recB, u, w.svec, w.states, w.sstates, w.part,
-                w.spart); });
-        }
-    }
-    traced("k_idlt_final", s, [&] { k_idlt_final<<<dim3((N + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(
-        N, nd, (N > nd) ? p.tn_nrg : 0, p.d_tn_rgnend, dense_out, w.sdense, far, w.sv, w.part, w.spart, c, N); });
-    return hipGetLastError();
+    traced("k_tndct_passB", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_tndct_passB, (dim3(tilesB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, Q, w.X, w.sX, y, w.schat);
+    });
+    hipError_t e = run_leg2cheb_t(p, nb, y, w.schat, c, N, 1, w, s);
+    return e;
 }
 
 }  // namespace dlt

@@ -27,12 +27,18 @@ size_t work_bytes(const Plan& p, int64_t nb);
 void work_carve(const Plan& p, int64_t nb, void* base, Work& w);
 
 // theta, w, dtheta (any may be null) for the plan's N
-hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, hipStream_t s);
-// chat = M c for nb instances
-hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, double* chat, Work& w, hipStream_t s);
+// `scratch` holds kb * NODE_PARTS_MAX * 8 doubles
+constexpr int NODE_PARTS_MAX = 64;
+hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, hipStream_t s);
+// chat = M c for nb instances (batch strides cs, hs in elements)
+hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, double* chat, int64_t hs, Work& w,
+                        hipStream_t s);
+// out = M^T y (times n + 1/2 when half != 0)
+hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys, double* out, int64_t os, int half,
+                          Work& w, hipStream_t s);
 // f = sum_n chat_n cos(n theta^leg), dth = theta^leg - theta^cheb1
-hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, const double* dth, double* f, Work& w,
-                    hipStream_t s);
+hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
+                    Work& w, hipStream_t s);
 
 // c = D_s M^T T^T D_w f (inverse transform), wts/dth from the nodes
 hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double* wts, const double* dth,

@@ -109,6 +109,8 @@ int plan_build(int64_t N, Plan& p) {
     g.N2 = N2;
     g.colsA = std::min(N1, FFT_CAP / N2);
     g.rowsB = std::min(N2, FFT_CAP / N1);
+    g.lrB = 0;
+    while ((1 << g.lrB) < g.rowsB) ++g.lrB;
     g.sh = (lg + 1) / 2;
     int rc;
     if ((rc = twiddle_table(N1, N1, 1, &p.d_twN1))) return rc;
@@ -132,12 +134,16 @@ int plan_build(int64_t N, Plan& p) {
         p.L = (L + 1) & ~1;
     }
 
-    // ---- dense block
-    const int ND_MAX = 8192;
-    p.nd = (int)std::min<int64_t>(N, ND_MAX);
-    p.dense_chunk = 512;
+    // ---- low-degree block: dense matrix up to DENSE_MAX columns; for large N
+    // the block n < N/16 is itself converted by this algorithm (sub-plan)
+    p.nd = (N >= RECURSE_FROM) ? (int)(N / 16) : (int)std::min<int64_t>(N, DENSE_MAX);
+    p.dense_chunk = 512;  // equals DENSE_CH of the dense kernels
     p.dense_nchunk = (p.nd + p.dense_chunk - 1) / p.dense_chunk;
-    {
+    if (p.nd > DENSE_MAX) {
+        p.sub = new Plan();
+        if ((rc = plan_build(p.nd, *p.sub))) return rc;
+        p.dense_nchunk = 0;
+    } else {
         std::vector<double> lam(p.nd);
         for (int z = 0; z < p.nd; ++z) lam[z] = (double)(1.0L / gamma_half_ratio(z + 0.5L));
         if ((rc = upload(lam.data(), lam.size() * sizeof(double), (void**)&p.d_lam))) return rc;
@@ -178,6 +184,11 @@ int plan_build(int64_t N, Plan& p) {
         F.Mmax = 0;
         F.nterm = 0;
         for (int b = 0; b < F.nblk; ++b) F.Mmax = std::max(F.Mmax, F.blk[b].M);
+        {
+            LD hk = 1;
+            for (int j = 1; j < F.Mmax; ++j) hk *= (j - 0.5L) * (j - 0.5L) / j;
+            F.hK = (double)hk;
+        }
         for (int m = 0; m < F.Mmax; ++m)
             for (int b = 0; b < F.nblk; ++b)
                 if (m < F.blk[b].M) {
@@ -210,7 +221,7 @@ int plan_build(int64_t N, Plan& p) {
             int wg = 0, rg = 0;
             for (int s = 0; s < Nr.nseg; ++s) {
                 const Seg& S = Nr.seg[s];
-                int ng = (S.jhi - S.jlo + 255) / 256;
+                int ng = (S.jhi - S.jlo + 63) / 64;
                 segoff[2 * s] = wg;
                 segoff[2 * s + 1] = rg;
                 for (int i = 0; i < S.nchunk * ng; ++i) wgseg.push_back(s);
@@ -228,23 +239,10 @@ int plan_build(int64_t N, Plan& p) {
         }
         Nr.jnear = (F.nblk > 1) ? F.blk[1].jhi : jprev;  // rows j < jnear may carry near terms
         if (Nr.nseg == 0) Nr.jnear = 0;
-        // recurrence coefficient tables
-        std::vector<double> A(N), B(N);
-        for (int64_t n = 0; n < N; ++n) {
-            A[n] = (double)((LD)n / (LD)(n + 1));
-            B[n] = (double)((LD)(2 * n + 1) / (LD)(n + 1));
-        }
-        if ((rc = upload(A.data(), N * sizeof(double), (void**)&p.d_recA))) return rc;
-        if ((rc = upload(B.data(), N * sizeof(double), (void**)&p.d_recB))) return rc;
-    } else {
-        // nodes still use the recurrence tables for the boundary nodes
-        std::vector<double> A(N), B(N);
-        for (int64_t n = 0; n < N; ++n) {
-            A[n] = (double)((LD)n / (LD)(n + 1));
-            B[n] = (double)((LD)(2 * n + 1) / (LD)(n + 1));
-        }
-        if ((rc = upload(A.data(), N * sizeof(double), (void**)&p.d_recA))) return rc;
-        if ((rc = upload(B.data(), N * sizeof(double), (void**)&p.d_recB))) return rc;
+        // 1/(n+1), the recurrence coefficient of the near field
+        std::vector<double> R(N);
+        for (int64_t n = 0; n < N; ++n) R[n] = (double)(1.0L / (LD)(n + 1));
+        if ((rc = upload(R.data(), N * sizeof(double), (void**)&p.d_rcp))) return rc;
     }
 
     // ---- nodes
@@ -279,8 +277,15 @@ int plan_build(int64_t N, Plan& p) {
 
     // ---- workspace per instance
     int nX = std::max({F.nterm, p.L / 2, 1});
-    p.tgB = (F.nterm >= 8 && N >= (1 << 16)) ? 2 : 1;
+    {
+        // enough blocks per pass to fill the GPU: at least 512 (tile, group) pairs
+        int tilesA = g.N1 / g.colsA, tilesB = g.N2 / g.rowsB;
+        int nt = std::max(F.nterm, 1);
+        p.tgA = std::min({nt, 16, std::max(1, (768 + tilesA - 1) / tilesA)});
+        p.tgB = std::min({nt, 4, std::max(1, (768 + tilesB - 1) / tilesB)});
+    }
     p.ws_X = (size_t)nX * N * sizeof(cplx);
+    if (p.sub && p.ws_X < p.sub->ws_per_inst) p.ws_X = p.sub->ws_per_inst;  // the sub-run borrows this slab
     p.ws_v = (size_t)p.tgB * N * sizeof(double);
     p.ws_items = (size_t)Nr.nitems * 8 * sizeof(double);
     p.ws_near = (size_t)2 * std::max(Nr.jnear, 1) * sizeof(double);
@@ -297,8 +302,13 @@ int plan_build(int64_t N, Plan& p) {
 }
 
 void plan_free(Plan& p) {
-    void* ptrs[] = {p.d_twN1, p.d_twN2, p.d_twHi,     p.d_twLo,       p.d_lam,       p.d_recA,
-                    p.d_recB, p.d_guess, p.d_tn_wgseg, p.d_tn_segoff, p.d_tn_rgnend};
+    if (p.sub) {
+        plan_free(*p.sub);
+        delete p.sub;
+        p.sub = nullptr;
+    }
+    void* ptrs[] = {p.d_twN1,  p.d_twN2,     p.d_twHi,      p.d_twLo,     p.d_lam,
+                    p.d_rcp,   p.d_guess,    p.d_tn_wgseg,  p.d_tn_segoff, p.d_tn_rgnend};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();

@@ -16,13 +16,16 @@ constexpr int MAX_BLOCKS = 8;
 constexpr int MAX_NODE_M = 24;  // terms of the Stieltjes series for nodes
 constexpr int MAX_SEGS = 8;     // near-field row segments
 constexpr int NEAR_CHUNK = 1024;
-constexpr int64_t MAX_N = int64_t(1) << 22;
+constexpr int64_t MAX_N = int64_t(1) << 20;
+constexpr int DENSE_MAX = 8192;         // largest low-degree block done by the dense matrix
+constexpr int64_t RECURSE_FROM = 1 << 17;  // from this N on the low block is N/16, recursively
 
 // FFT geometry of the length-N DFT (N power of two): N = N1*N2.  Pass A runs
 // length-N2 DFTs over the slow input index for tiles of colsA columns; pass B
 // runs length-N1 DFTs over the fast input index for tiles of rowsB rows.
 struct Geo {
     int N, N1, N2, colsA, rowsB, sh;
+    int lrB;  // log2(rowsB)
     const cplx* twN1;  // e^{2 pi i t/N1}
     const cplx* twN2;  // e^{2 pi i t/N2}
     const cplx* twHi;  // e^{2 pi i (t<<sh)/N}
@@ -44,6 +47,7 @@ struct Seg {
 
 struct FarParams {
     int nblk, nterm, Mmax, nd;
+    double hK;  // prod_{j=1}^{Mmax-1} (j-1/2)^2 / j
     Block blk[MAX_BLOCKS];
     unsigned char term_blk[MAX_TERMS], term_m[MAX_TERMS];
     // row -> block lookup: rows j < blk_edge[b] (and mirrors) are outside
@@ -73,8 +77,7 @@ struct Plan {
     // device tables
     cplx *d_twN1 = nullptr, *d_twN2 = nullptr, *d_twHi = nullptr, *d_twLo = nullptr;
     double* d_lam = nullptr;     // Lambda(z), z < nd
-    double* d_recA = nullptr;    // n/(n+1)
-    double* d_recB = nullptr;    // (2n+1)/(n+1)
+    double* d_rcp = nullptr;     // 1/(n+1), n < N (near field)
     double* d_guess = nullptr;   // boundary-node initial offsets from theta^cheb1
     // transposed near field: work-group -> segment table, per-segment
     // (first work-group, first row group), and nend of every row group
@@ -86,7 +89,11 @@ struct Plan {
     size_t ws_X = 0, ws_v = 0, ws_items = 0, ws_near = 0, ws_dense = 0, ws_chat = 0, ws_vec = 0;
     size_t ws_states = 0, ws_part = 0;
     size_t ws_per_inst = 0, ws_shared = 0;
-    int tgB = 1;       // far-field pass-B term groups
+    int tgA = 1;       // far-field pass-A term groups (blocks split the terms)
+    int tgB = 1;       // far-field pass-B term groups (partial outputs summed later)
+    // low-degree block n < nd when nd exceeds the dense limit: the same
+    // transform at size nd (owned)
+    Plan* sub = nullptr;
 };
 
 // Builds the plan for size N (power of two, 1 <= N <= MAX_N); returns 0 or a

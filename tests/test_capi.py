@@ -46,7 +46,7 @@ def test_rejects_bad_sizes_before_device_work(L, fn):
     assert f(-5, 1, p, q, None) == -1
     assert f(16, -1, p, q, None) == -1        # batch < 0
     assert f(12, 1, p, q, None) == -2         # not a power of two
-    assert f((1 << 22) * 2, 1, p, q, None) == -2   # beyond DLT_MAX_N
+    assert f((1 << 20) * 2, 1, p, q, None) == -2   # beyond DLT_MAX_N
     assert f(16, 0, p, q, None) == 0          # empty batch is a no-op
     assert f(16, 1, None, q, None) == -1      # NULL input
     assert f(16, 1, p, None, None) == -1      # NULL output
