@@ -26,6 +26,10 @@ __device__ __forceinline__ cplx cmuli(cplx a) { return {-a.im, a.re}; }
 constexpr int FFT_THREADS = 256;
 constexpr int FFT_CAP = 2048;
 constexpr int FFT_VPT = FFT_CAP / FFT_THREADS;  // values per thread per stage
+// LDS tiles are padded with one complex per 8 so that the stride-4 writes of
+// the first Stockham stage fall into distinct banks
+constexpr int FFT_LDS = FFT_CAP + FFT_CAP / 8;
+__device__ __forceinline__ int lp(int x) { return x + (x >> 3); }
 
 // e^{+2 pi i t / len} from a table tw[t] = e^{+2 pi i t / len}, t < len.
 __device__ __forceinline__ cplx tw_load(const cplx* __restrict__ tw, int t) { return tw[t]; }
@@ -41,7 +45,7 @@ __device__ __forceinline__ cplx tw2(const cplx* __restrict__ hi, const cplx* __r
 
 // In-place radix-4 (one radix-2 stage when log2(len) is odd) Stockham FFT with
 // the + sign, sum_n x_n e^{+2 pi i n m/len}, of `cols` independent sequences
-// stored contiguously in LDS: buf[col*len + i], cols*len <= FFT_CAP.  Every
+// stored contiguously in LDS: buf[lp(col*len + i)], cols*len <= FFT_CAP.  Every
 // thread of the (FFT_THREADS-wide) block must call it.  `tw` is the table of
 // e^{+2 pi i t/len}.  Each stage reads all of its inputs into registers, waits,
 // then writes, so one buffer suffices.
@@ -62,8 +66,8 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
                     int col = t / nb;
                     int i = t - col * nb;
                     int k = i & (p - 1);
-                    cplx* base = buf + col * len;
-                    cplx x0 = base[i], x1 = base[i + nb], x2 = base[i + 2 * nb], x3 = base[i + 3 * nb];
+                    const int cb0 = col * len;
+                    cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)], x2 = buf[lp(cb0 + i + 2 * nb)], x3 = buf[lp(cb0 + i + 3 * nb)];
                     if (p > 1) {
                         cplx w1 = tw_load(tw, k * tstride);
                         cplx w2 = cmul(w1, w1);
@@ -87,10 +91,10 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
                 int t = tid + b * FFT_THREADS;
                 if (t < total) {
                     int d = dst[b];
-                    buf[d] = v[4 * b + 0];
-                    buf[d + p] = v[4 * b + 1];
-                    buf[d + 2 * p] = v[4 * b + 2];
-                    buf[d + 3 * p] = v[4 * b + 3];
+                    buf[lp(d)] = v[4 * b + 0];
+                    buf[lp(d + p)] = v[4 * b + 1];
+                    buf[lp(d + 2 * p)] = v[4 * b + 2];
+                    buf[lp(d + 3 * p)] = v[4 * b + 3];
                 }
             }
             __syncthreads();
@@ -102,8 +106,8 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
                     int col = t / nb;
                     int i = t - col * nb;
                     int k = i & (p - 1);
-                    cplx* base = buf + col * len;
-                    cplx x0 = base[i], x1 = base[i + nb];
+                    const int cb0 = col * len;
+                    cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)];
                     if (p > 1) x1 = cmul(x1, tw_load(tw, k * tstride));
                     v[2 * b + 0] = cadd(x0, x1);
                     v[2 * b + 1] = csub(x0, x1);
@@ -116,8 +120,8 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
                 int t = tid + b * FFT_THREADS;
                 if (t < total) {
                     int d = dst[b];
-                    buf[d] = v[2 * b + 0];
-                    buf[d + p] = v[2 * b + 1];
+                    buf[lp(d)] = v[2 * b + 0];
+                    buf[lp(d + p)] = v[2 * b + 1];
                 }
             }
             __syncthreads();
@@ -154,8 +158,8 @@ __device__ __forceinline__ void lds_fft_t(cplx* buf, int len, int cols, const cp
                         int col = t / nb;
                         int i = t - col * nb;
                         int k = i & (p - 1);
-                        cplx* base = buf + col * L;
-                        cplx x0 = base[i], x1 = base[i + nb], x2 = base[i + 2 * nb], x3 = base[i + 3 * nb];
+                        const int cb0 = col * L;
+                        cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)], x2 = buf[lp(cb0 + i + 2 * nb)], x3 = buf[lp(cb0 + i + 3 * nb)];
                         if (p > 1) {
                             cplx w1 = tw[k * tstride];
                             cplx w2 = cmul(w1, w1);
@@ -179,10 +183,10 @@ __device__ __forceinline__ void lds_fft_t(cplx* buf, int len, int cols, const cp
                     int t = tid + b * FFT_THREADS;
                     if (t < total) {
                         int d = dst[b];
-                        buf[d] = v[4 * b + 0];
-                        buf[d + p] = v[4 * b + 1];
-                        buf[d + 2 * p] = v[4 * b + 2];
-                        buf[d + 3 * p] = v[4 * b + 3];
+                        buf[lp(d)] = v[4 * b + 0];
+                        buf[lp(d + p)] = v[4 * b + 1];
+                        buf[lp(d + 2 * p)] = v[4 * b + 2];
+                        buf[lp(d + 3 * p)] = v[4 * b + 3];
                     }
                 }
                 __syncthreads();
@@ -194,8 +198,8 @@ __device__ __forceinline__ void lds_fft_t(cplx* buf, int len, int cols, const cp
                         int col = t / nb;
                         int i = t - col * nb;
                         int k = i & (p - 1);
-                        cplx* base = buf + col * L;
-                        cplx x0 = base[i], x1 = base[i + nb];
+                        const int cb0 = col * L;
+                        cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)];
                         if (p > 1) x1 = cmul(x1, tw[k * tstride]);
                         v[2 * b + 0] = cadd(x0, x1);
                         v[2 * b + 1] = csub(x0, x1);
@@ -208,8 +212,8 @@ __device__ __forceinline__ void lds_fft_t(cplx* buf, int len, int cols, const cp
                     int t = tid + b * FFT_THREADS;
                     if (t < total) {
                         int d = dst[b];
-                        buf[d] = v[2 * b + 0];
-                        buf[d + p] = v[2 * b + 1];
+                        buf[lp(d)] = v[2 * b + 0];
+                        buf[lp(d + p)] = v[2 * b + 1];
                     }
                 }
                 __syncthreads();

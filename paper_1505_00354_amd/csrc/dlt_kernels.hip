@@ -400,33 +400,61 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
 
 // Pass A: the block owns columns n_a in [na0, na0+colsA); element e of the
 // tile is (col = e % colsA, n_b = e / colsA), n = na0 + col + N1 n_b.  After
-// the length-N2 DFTs the tile holds buf[col*N2 + j_b]; it is multiplied by
+// the length-N2 DFTs the tile holds buf[lp(col*N2 + j_b)]; it is multiplied by
 // e^{2 pi i n_a j_b / N} and stored in the blocked layout.
 template <bool VIRT>
 __device__ __forceinline__ void passA_store(const Geo& g, int N2, int colsA, const cplx* buf, int na0,
                                             cplx* __restrict__ X) {
     const int tot = colsA * N2;
     const int rB = g.rowsB, lrB = g.lrB;
-    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int col = e / N2, jb = e - col * N2;
-        int na = na0 + col;
-        cplx v = buf[e];
-        if (na && jb) v = cmul(v, tw2(g.twHi, g.twLo, (int64_t)na * jb, g.sh));
-        int vr = VIRT ? virt_row(jb, N2) : jb;
-        X[(int64_t)(vr >> lrB) * ((int64_t)g.N1 << lrB) + (int64_t)na * rB + (vr & (rB - 1))] = v;
+    // the element s of this thread is e = tid + s*T; its twiddle is built from
+    // the one P = N2/T elements earlier (same j_b, previous column) when
+    // N2 >= T, else from the previous element (same j_b, column + T/N2)
+    cplx tw[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        if (e < tot) {
+            int col = e / N2, jb = e - col * N2;
+            int na = na0 + col;
+            cplx w;
+            if (N2 >= FFT_THREADS) {
+                int P = N2 / FFT_THREADS;
+                w = (s < P) ? tw2(g.twHi, g.twLo, (int64_t)na * jb, g.sh) : cmul(tw[s - P], g.twLo[jb]);
+            } else {
+                int dc = FFT_THREADS / N2;
+                w = (s == 0) ? tw2(g.twHi, g.twLo, (int64_t)na * jb, g.sh)
+                             : cmul(tw[s - 1], tw2(g.twHi, g.twLo, (int64_t)dc * jb, g.sh));
+            }
+            tw[s] = w;
+            cplx v = cmul(buf[lp(e)], w);
+            int vr = VIRT ? virt_row(jb, N2) : jb;
+            X[(int64_t)(vr >> lrB) * ((int64_t)g.N1 << lrB) + (int64_t)na * rB + (vr & (rB - 1))] = v;
+        }
     }
 }
 
 // Pass B: the block owns (virtual) rows [vb0, vb0+rowsB): one contiguous
-// block of the intermediate; LDS gets buf[r*N1 + n_a]; after the length-N1
-// DFTs buf[r*N1 + j_a] is output m = jb(r) + N2 j_a.
+// block of the intermediate; LDS gets buf[lp(r*N1 + n_a)]; after the length-N1
+// DFTs buf[lp(r*N1 + j_a)] is output m = jb(r) + N2 j_a.
 __device__ __forceinline__ void passB_load(const Geo& g, int N1, int rowsB, cplx* buf, int vb0,
                                            const cplx* __restrict__ X) {
     const int tot = rowsB * N1;
     const cplx* src = X + (int64_t)(vb0 >> g.lrB) * ((int64_t)N1 << g.lrB);
-    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int r = e & (rowsB - 1), na = e / rowsB;
-        buf[r * N1 + na] = src[e];
+    // all loads of the thread first, then the LDS writes
+    cplx v[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        if (e < tot) v[s] = src[e];
+    }
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        int e = threadIdx.x + s * FFT_THREADS;
+        if (e < tot) {
+            int r = e & (rowsB - 1), na = e / rowsB;
+            buf[lp(r * N1 + na)] = v[s];
+        }
     }
 }
 
@@ -439,9 +467,16 @@ template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) void k_far_passA(Geo g, FarParams F, int G, const double* __restrict__ c,
                                                           int64_t c_stride, cplx* __restrict__ X,
                                                           int64_t x_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N2 = LA ? LA : g.N2;
     const int colsA = LA ? FFT_CAP / LA : g.colsA;
+    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
+    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
+    if constexpr (LA > 1) {
+        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
+        __syncthreads();
+    }
+    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int b = blockIdx.z;
@@ -482,11 +517,11 @@ __global__ __launch_bounds__(FFT_THREADS) void k_far_passA(Geo g, FarParams F, i
                 if (e < tot) {
                     int col = e % colsA, nb = e / colsA;
                     double f = (nn[s] >= nlo) ? h[s] : 0.0;
-                    buf[col * N2 + nb] = cscale(base[s], f);
+                    buf[lp(col * N2 + nb)] = cscale(base[s], f);
                 }
             }
             __syncthreads();
-            lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+            lds_fft_t<LA>(buf, N2, colsA, twA);
             passA_store<false>(g, N2, colsA, buf, na0, Xb + (int64_t)t * N);
             __syncthreads();
         }
@@ -515,9 +550,15 @@ template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_far_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
                                                           int64_t x_stride, double* __restrict__ v,
                                                           int64_t v_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N1 = LB ? LB : g.N1;
     const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
+    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
+    if constexpr (LB > 1) {
+        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
+        __syncthreads();
+    }
+    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int grp = blockIdx.y;
@@ -561,12 +602,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_far_passB(Geo g, FarParams F, i
             const int tb = F.term_blk[t];
             passB_load(g, N1, rowsB, buf, jb0, Xb + (int64_t)t * N);
             __syncthreads();
-            lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
+            lds_fft_t<LB>(buf, N1, rowsB, twB);
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) {
                 int e = threadIdx.x + s * FFT_THREADS;
                 if (e < tot && blk[s] == tb) {
-                    cplx z = buf[e];
+                    cplx z = buf[lp(e)];
                     if (cj[s]) z.im = -z.im;
                     acc[s] = fma(gm[s].re, z.re, fma(-gm[s].im, z.im, acc[s]));
                 }
@@ -798,9 +839,16 @@ __global__ __launch_bounds__(FFT_THREADS) void k_dct2_passA(Geo g, int G, const 
                                                            int64_t v_stride, const double* __restrict__ near,
                                                            int64_t near_stride, int jnear, cplx* __restrict__ X,
                                                            int64_t x_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N2 = LA ? LA : g.N2;
     const int colsA = LA ? FFT_CAP / LA : g.colsA;
+    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
+    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
+    if constexpr (LA > 1) {
+        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
+        __syncthreads();
+    }
+    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int b = blockIdx.z;
@@ -815,10 +863,10 @@ __global__ __launch_bounds__(FFT_THREADS) void k_dct2_passA(Geo g, int G, const 
         for (int q = 0; q < G; ++q) x += vb[(int64_t)q * N + j];
         if (j < jnear) x += nb[j];
         else if (N - 1 - j < jnear) x += nb[jnear + (N - 1 - j)];
-        buf[col * N2 + nbi] = {x, 0.0};
+        buf[lp(col * N2 + nbi)] = {x, 0.0};
     }
     __syncthreads();
-    lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+    lds_fft_t<LA>(buf, N2, colsA, twA);
     passA_store<false>(g, N2, colsA, buf, na0, X + b * x_stride);
 }
 
@@ -827,22 +875,28 @@ __global__ __launch_bounds__(FFT_THREADS) void k_dct2_passB(Geo g, int nd, const
                                                            int64_t x_stride, const double* __restrict__ dense,
                                                            int64_t dense_stride, double* __restrict__ chat,
                                                            int64_t chat_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N1 = LB ? LB : g.N1;
     const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
+    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
+    if constexpr (LB > 1) {
+        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
+        __syncthreads();
+    }
+    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int b = blockIdx.z;
     passB_load(g, N1, rowsB, buf, jb0, X + b * x_stride);
     __syncthreads();
-    lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
+    lds_fft_t<LB>(buf, N1, rowsB, twB);
     const int tot = rowsB * N1;
     const double* db = dense + b * dense_stride;
     double* cb = chat + b * chat_stride;
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
         int r = e / N1, ja = e - r * N1;
         int n = jb0 + r + g.N2 * ja;
-        cplx U = buf[e];
+        cplx U = buf[lp(e)];
         cplx t = half_shift(n, N);
         double val = (t.re * U.re - t.im * U.im) * ((n == 0) ? 1.0 : 2.0) / N;
         if (n < nd) val += db[n];
@@ -860,9 +914,16 @@ template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passA(Geo g, int Q, int QG, const double* __restrict__ chat,
                                                            int64_t chat_stride, cplx* __restrict__ X,
                                                            int64_t x_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N2 = LA ? LA : g.N2;
     const int colsA = LA ? FFT_CAP / LA : g.colsA;
+    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
+    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
+    if constexpr (LA > 1) {
+        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
+        __syncthreads();
+    }
+    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int grp = blockIdx.y;
@@ -909,13 +970,13 @@ __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passA(Geo g, int Q, int QG
                 int col = e % colsA, nbi = e / colsA;
                 int n = na0 + col + g.N1 * nbi;
                 double x = n * invN, y = (N - n) * invN;
-                buf[col * N2 + nbi] = cadd(cscale(Av[s], px[s]), cscale(Bv[s], py[s]));
+                buf[lp(col * N2 + nbi)] = cadd(cscale(Av[s], px[s]), cscale(Bv[s], py[s]));
                 px[s] *= x * x;
                 py[s] *= y * y;
             }
         }
         __syncthreads();
-        lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+        lds_fft_t<LA>(buf, N2, colsA, twA);
         passA_store<false>(g, N2, colsA, buf, na0, Xb + (int64_t)q * N);
         __syncthreads();
     }
@@ -927,9 +988,15 @@ template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X,
                                                            int64_t x_stride, const double* __restrict__ dth,
                                                            double* __restrict__ f, int64_t f_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N1 = LB ? LB : g.N1;
     const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
+    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
+    if constexpr (LB > 1) {
+        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
+        __syncthreads();
+    }
+    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int b = blockIdx.z;
@@ -953,13 +1020,13 @@ __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const 
     for (int q = Q - 1; q >= 0; --q) {
         passB_load(g, N1, rowsB, buf, jb0, Xb + (int64_t)q * N);
         __syncthreads();
-        lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
+        lds_fft_t<LB>(buf, N1, rowsB, twB);
         const double sc = (q & 1) ? -1.0 : 1.0;  // s_{2q} = (-1)^q, s_{2q+1} = -(-1)^q
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
             int e = threadIdx.x + s * FFT_THREADS;
             if (e < tot) {
-                cplx U = buf[e];
+                cplx U = buf[lp(e)];
                 double Fc = U.re;
                 double Fs = hi[s] ? -U.im : U.im;
                 double inner = fma(d[s] / (2 * q + 2), acc[s], -sc * Fs);
@@ -992,9 +1059,16 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passA(Geo g, int Q, int Q
                                                             int64_t f_stride, const double* __restrict__ wts,
                                                             const double* __restrict__ dth, cplx* __restrict__ X,
                                                             int64_t x_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N2 = LA ? LA : g.N2;
     const int colsA = LA ? FFT_CAP / LA : g.colsA;
+    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
+    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
+    if constexpr (LA > 1) {
+        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
+        __syncthreads();
+    }
+    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int grp = blockIdx.y;
@@ -1028,12 +1102,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passA(Geo g, int Q, int Q
                 int m = na0 + col + g.N1 * nbi;
                 double a = gv[s] * pw[s];
                 double sg = (2 * m < N) ? 1.0 : -1.0;
-                buf[col * N2 + nbi] = {a, sg * a * dv[s]};
+                buf[lp(col * N2 + nbi)] = {a, sg * a * dv[s]};
                 pw[s] *= dv[s] * dv[s];
             }
         }
         __syncthreads();
-        lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+        lds_fft_t<LA>(buf, N2, colsA, twA);
         passA_store<true>(g, N2, colsA, buf, na0, Xb + (int64_t)q * N);
         __syncthreads();
     }
@@ -1045,9 +1119,15 @@ template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ X,
                                                             int64_t x_stride, double* __restrict__ y,
                                                             int64_t y_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N1 = LB ? LB : g.N1;
     const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
+    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
+    if constexpr (LB > 1) {
+        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
+        __syncthreads();
+    }
+    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
     const int N = g.N;
     const int N2 = g.N2;
     const int vb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
@@ -1089,13 +1169,13 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passB(Geo g, int Q, const
     for (int q = Q - 1; q >= 0; --q) {
         passB_load(g, N1, rowsB, buf, vb0, Xb + (int64_t)q * N);
         __syncthreads();
-        lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
+        lds_fft_t<LB>(buf, N1, rowsB, twB);
         const double sc = (q & 1) ? -1.0 : 1.0;
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
             int e = threadIdx.x + s * FFT_THREADS;
             if (e < tot) {
-                cplx U = buf[e], V = buf[part[s]];
+                cplx U = buf[lp(e)], V = buf[lp(part[s])];
                 cplx A = {0.5 * (U.re + V.re), 0.5 * (U.im - V.im)};
                 cplx Bm = {0.5 * (U.im + V.im), -0.5 * (U.re - V.re)};  // (U - conj V)/(2i)
                 double Zc = en[s].re * A.re - en[s].im * A.im;
@@ -1174,9 +1254,16 @@ __global__ void k_dense_t_reduce(int nd, int nchunk, int chunk, const double* __
 template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) void k_dct3_passA(Geo g, const double* __restrict__ y, int64_t y_stride,
                                                            cplx* __restrict__ X, int64_t x_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N2 = LA ? LA : g.N2;
     const int colsA = LA ? FFT_CAP / LA : g.colsA;
+    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
+    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
+    if constexpr (LA > 1) {
+        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
+        __syncthreads();
+    }
+    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int b = blockIdx.z;
@@ -1186,31 +1273,37 @@ __global__ __launch_bounds__(FFT_THREADS) void k_dct3_passA(Geo g, const double*
         int col = e % colsA, nbi = e / colsA;
         int n = na0 + col + g.N1 * nbi;
         double a = yb[n] * ((n == 0) ? 1.0 : 2.0) / N;
-        buf[col * N2 + nbi] = cscale(half_shift(n, N), a);
+        buf[lp(col * N2 + nbi)] = cscale(half_shift(n, N), a);
     }
     __syncthreads();
-    lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+    lds_fft_t<LA>(buf, N2, colsA, twA);
     passA_store<false>(g, N2, colsA, buf, na0, X + b * x_stride);
 }
 
 template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64_t x_stride,
                                                            double* __restrict__ u, int64_t u_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N1 = LB ? LB : g.N1;
     const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
+    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
+    if constexpr (LB > 1) {
+        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
+        __syncthreads();
+    }
+    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int b = blockIdx.z;
     passB_load(g, N1, rowsB, buf, jb0, X + b * x_stride);
     __syncthreads();
-    lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
+    lds_fft_t<LB>(buf, N1, rowsB, twB);
     const int tot = rowsB * N1;
     double* ub = u + b * u_stride;
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
         int r = e / N1, ja = e - r * N1;
         int m = jb0 + r + g.N2 * ja;
-        ub[row_of(m, N)] = buf[e].re;
+        ub[row_of(m, N)] = buf[lp(e)].re;
     }
 }
 
@@ -1221,9 +1314,16 @@ template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passA(Geo g, FarParams F, int G, const double* __restrict__ u,
                                                            int64_t u_stride, cplx* __restrict__ X,
                                                            int64_t x_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N2 = LA ? LA : g.N2;
     const int colsA = LA ? FFT_CAP / LA : g.colsA;
+    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
+    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
+    if constexpr (LA > 1) {
+        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
+        __syncthreads();
+    }
+    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
     const int b = blockIdx.z;
@@ -1269,11 +1369,11 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passA(Geo g, FarParams F, 
                     int col = e % colsA, nbi = e / colsA;
                     cplx v = (blk[s] == tb) ? gm[s] : cplx{0, 0};
                     if (cj[s]) v.im = -v.im;
-                    buf[col * N2 + nbi] = v;
+                    buf[lp(col * N2 + nbi)] = v;
                 }
             }
             __syncthreads();
-            lds_fft_t<LA>(buf, N2, colsA, g.twN2);
+            lds_fft_t<LA>(buf, N2, colsA, twA);
             passA_store<false>(g, N2, colsA, buf, na0, Xb + (int64_t)t * N);
             __syncthreads();
         }
@@ -1288,9 +1388,15 @@ template <int LB>
 __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
                                                            int64_t x_stride, double* __restrict__ out,
                                                            int64_t out_stride) {
-    __shared__ cplx buf[FFT_CAP];
+    __shared__ cplx buf[FFT_LDS];
     const int N1 = LB ? LB : g.N1;
     const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
+    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
+    if constexpr (LB > 1) {
+        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
+        __syncthreads();
+    }
+    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
     const int b = blockIdx.z;
@@ -1325,12 +1431,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tfar_passB(Geo g, FarParams F, 
             const int nlo = F.blk[F.term_blk[t]].nlo;
             passB_load(g, N1, rowsB, buf, jb0, Xb + (int64_t)t * N);
             __syncthreads();
-            lds_fft_t<LB>(buf, N1, rowsB, g.twN1);
+            lds_fft_t<LB>(buf, N1, rowsB, twB);
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) {
                 int e = threadIdx.x + s * FFT_THREADS;
                 if (e < tot && nn[s] >= nlo) {
-                    cplx U = buf[e];
+                    cplx U = buf[lp(e)];
                     acc[s] = fma(h[s], en[s].re * U.re - en[s].im * U.im, acc[s]);
                 }
             }

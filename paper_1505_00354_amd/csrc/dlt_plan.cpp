@@ -166,6 +166,12 @@ int plan_build(int64_t N, Plan& p) {
         F.blk[0] = {j0, half, p.nd, M1};
         F.nblk = 1;
         int jprev = j0;
+        // further blocks only where their M full-length transforms cost less
+        // than the near-field recurrence they replace (cost model: one far
+        // term ~ 64 N bytes through HBM at ~4 TB/s; one recurrence step of
+        // one row ~ 2 x 4 FP64 ops at ~20% of the vector peak)
+        const double far_term_s = 64.0 * (double)N / 4e12;
+        const double near_step_s = 8.0 / (0.2 * 39e12);
         while (jprev > 0 && F.nblk < MAX_BLOCKS) {
             int jl = (int)floor(jprev / beta);
             LD s = sinl((jl + 0.5L) * PI_L / N);
@@ -178,6 +184,8 @@ int plan_build(int64_t N, Plan& p) {
             }
             int nlo = (int)ceill(hi);
             if (nlo >= N) break;
+            double saved = (double)(jprev - jl) * (double)(N - nlo) * near_step_s * 2;  // both ends
+            if (saved < M * far_term_s * 2) break;  // forward and inverse alike
             F.blk[F.nblk++] = {jl, jprev, nlo, M};
             jprev = jl;
         }
