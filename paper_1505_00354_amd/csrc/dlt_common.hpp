@@ -21,18 +21,14 @@ __device__ __forceinline__ cplx cconj(cplx a) { return {a.re, -a.im}; }
 // multiply by +i
 __device__ __forceinline__ cplx cmuli(cplx a) { return {-a.im, a.re}; }
 
-// Threads per block of every FFT-carrying kernel, and the LDS capacity in
-// complex doubles one block uses for its tile (32 KiB).
+// Threads per block of every FFT-carrying kernel, and the number of complex
+// values in one block's tile (32 KiB).
 constexpr int FFT_THREADS = 256;
 constexpr int FFT_CAP = 2048;
-constexpr int FFT_VPT = FFT_CAP / FFT_THREADS;  // values per thread per stage
-// LDS tiles are padded with one complex per 8 so that the stride-4 writes of
-// the first Stockham stage fall into distinct banks
-constexpr int FFT_LDS = FFT_CAP + FFT_CAP / 8;
+constexpr int FFT_VPT = FFT_CAP / FFT_THREADS;  // tile elements per thread
+// LDS slots of a tile: one pad slot per 8 values plus a per-sequence skew
+constexpr int FFT_LDS = FFT_CAP + FFT_CAP / 8 + 32;
 __device__ __forceinline__ int lp(int x) { return x + (x >> 3); }
-
-// e^{+2 pi i t / len} from a table tw[t] = e^{+2 pi i t / len}, t < len.
-__device__ __forceinline__ cplx tw_load(const cplx* __restrict__ tw, int t) { return tw[t]; }
 
 // e^{+2 pi i t / N}, 0 <= t < N, from a two-level table:
 //   hi[t >> sh] = e^{2 pi i (t >> sh) 2^sh / N},  lo[t & mask] = e^{2 pi i (t & mask)/N}.
@@ -48,7 +44,7 @@ __device__ __forceinline__ cplx tw2(const cplx* __restrict__ hi, const cplx* __r
 // stored contiguously in LDS: buf[lp(col*len + i)], cols*len <= FFT_CAP.  Every
 // thread of the (FFT_THREADS-wide) block must call it.  `tw` is the table of
 // e^{+2 pi i t/len}.  Each stage reads all of its inputs into registers, waits,
-// then writes, so one buffer suffices.
+// then writes, so one buffer suffices.  Used for lengths below 64 only.
 __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restrict__ tw) {
     const int tid = threadIdx.x;
     for (int p = 1; p < len;) {
@@ -67,9 +63,10 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
                     int i = t - col * nb;
                     int k = i & (p - 1);
                     const int cb0 = col * len;
-                    cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)], x2 = buf[lp(cb0 + i + 2 * nb)], x3 = buf[lp(cb0 + i + 3 * nb)];
+                    cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)], x2 = buf[lp(cb0 + i + 2 * nb)],
+                         x3 = buf[lp(cb0 + i + 3 * nb)];
                     if (p > 1) {
-                        cplx w1 = tw_load(tw, k * tstride);
+                        cplx w1 = tw[k * tstride];
                         cplx w2 = cmul(w1, w1);
                         cplx w3 = cmul(w2, w1);
                         x1 = cmul(x1, w1);
@@ -108,7 +105,7 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
                     int k = i & (p - 1);
                     const int cb0 = col * len;
                     cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)];
-                    if (p > 1) x1 = cmul(x1, tw_load(tw, k * tstride));
+                    if (p > 1) x1 = cmul(x1, tw[k * tstride]);
                     v[2 * b + 0] = cadd(x0, x1);
                     v[2 * b + 1] = csub(x0, x1);
                     dst[b] = col * len + (i - k) * 2 + k;
@@ -130,95 +127,171 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
     }
 }
 
-// Same transform with the length known at compile time (L > 0) so that the
-// stage loop unrolls and index arithmetic becomes shifts; L == 0 falls back
-// to the run-time length `len`.
+// In-place length-8 DFT with the + sign, a_q <- sum_j a_j e^{2 pi i j q/8}:
+// one radix-2 split (a_j +- a_{j+4}, the difference turned by e^{2 pi i j/8})
+// followed by two length-4 DFTs giving the even and the odd outputs.
+__device__ __forceinline__ void dft8(cplx* a) {
+    const double h = 0.70710678118654752440;  // 1/sqrt(2)
+    cplx b0 = cadd(a[0], a[4]), b1 = cadd(a[1], a[5]), b2 = cadd(a[2], a[6]), b3 = cadd(a[3], a[7]);
+    cplx c0 = csub(a[0], a[4]), c1 = csub(a[1], a[5]), c2 = csub(a[2], a[6]), c3 = csub(a[3], a[7]);
+    c1 = {(c1.re - c1.im) * h, (c1.re + c1.im) * h};     // * e^{i pi/4}
+    c2 = cmuli(c2);                                       // * e^{i pi/2}
+    c3 = {-(c3.re + c3.im) * h, (c3.re - c3.im) * h};    // * e^{3 i pi/4}
+    cplx s02 = cadd(b0, b2), d02 = csub(b0, b2), s13 = cadd(b1, b3), d13 = cmuli(csub(b1, b3));
+    cplx t02 = cadd(c0, c2), e02 = csub(c0, c2), t13 = cadd(c1, c3), e13 = cmuli(csub(c1, c3));
+    a[0] = cadd(s02, s13);
+    a[2] = cadd(d02, d13);
+    a[4] = csub(s02, s13);
+    a[6] = csub(d02, d13);
+    a[1] = cadd(t02, t13);
+    a[3] = cadd(e02, e13);
+    a[5] = csub(t02, t13);
+    a[7] = csub(e02, e13);
+}
+
+// Ownership of the elements of an FFT tile (FFT_CAP values: `cols` sequences
+// of length `len`, cols*len = FFT_CAP) among the FFT_THREADS threads.
+// Compile-time length L >= 64: thread t owns sequence col = t % cols and the
+// 8 indices i0 + s*L/8 (i0 = t / cols), which are exactly the inputs of one
+// radix-8 butterfly of the first Stockham stage and the outputs of one
+// butterfly of the last, so both stages run in registers.  L == 0 (lengths
+// below 64, tiles smaller than FFT_CAP): element e = t + s*FFT_THREADS is
+// (e % cols, e / cols) and may lie beyond the tile (live() false).
 template <int L>
-__device__ __forceinline__ void lds_fft_t(cplx* buf, int len, int cols, const cplx* __restrict__ tw) {
+struct Tile {
+    static constexpr int LOG = __builtin_ctz(L);
+    static constexpr int COLS = FFT_CAP / L;
+    // per-sequence skew so that the lanes of one column group hit distinct banks
+    static constexpr int SK = COLS >= 8 ? 1 : 8 / COLS;
+    static constexpr int STRIDE = L / 8;
+    int col_, i0_;
+    __device__ __forceinline__ Tile(int /*cols*/, int /*len*/)
+        : col_((int)threadIdx.x % COLS), i0_((int)threadIdx.x / COLS) {}
+    __device__ __forceinline__ int col(int) const { return col_; }
+    __device__ __forceinline__ int idx(int s) const { return i0_ + s * STRIDE; }
+    __device__ __forceinline__ bool live(int) const { return true; }
+    __device__ __forceinline__ int cols() const { return COLS; }
+    __device__ __forceinline__ int len() const { return L; }
+    __device__ __forceinline__ static int pad(int x) { return x + (x >> 3) + (x >> LOG) * SK; }
+    __device__ __forceinline__ int slot(int s) const { return pad(col_ * L + idx(s)); }
+};
+
+template <>
+struct Tile<0> {
+    int cols_, len_;
+    __device__ __forceinline__ Tile(int cols, int len) : cols_(cols), len_(len) {}
+    __device__ __forceinline__ int e(int s) const { return (int)threadIdx.x + s * FFT_THREADS; }
+    __device__ __forceinline__ int col(int s) const { return e(s) % cols_; }
+    __device__ __forceinline__ int idx(int s) const { return e(s) / cols_; }
+    __device__ __forceinline__ bool live(int s) const { return e(s) < cols_ * len_; }
+    __device__ __forceinline__ int cols() const { return cols_; }
+    __device__ __forceinline__ int len() const { return len_; }
+    __device__ __forceinline__ static int pad(int x) { return lp(x); }
+    __device__ __forceinline__ int slot(int s) const { return lp(col(s) * len_ + idx(s)); }
+};
+
+// Multiplies a[1..7] by w^1..w^7, w = tw[t] (e^{2 pi i t/L}); the powers up to
+// 4 come from the table (indices below L/2), the rest as w^4 w^j.
+__device__ __forceinline__ void twiddle8(cplx* a, const cplx* __restrict__ tw, int t) {
+    cplx w1 = tw[t], w2 = tw[2 * t], w3 = tw[3 * t], w4 = tw[4 * t];
+    a[1] = cmul(a[1], w1);
+    a[2] = cmul(a[2], w2);
+    a[3] = cmul(a[3], w3);
+    a[4] = cmul(a[4], w4);
+    a[5] = cmul(a[5], cmul(w4, w1));
+    a[6] = cmul(a[6], cmul(w4, w2));
+    a[7] = cmul(a[7], cmul(w4, w3));
+}
+
+// DFT with the + sign of every sequence of the tile, v[s] holding the element
+// (col(s), idx(s)) on entry and the transform at the same position on exit.
+// `buf` is FFT_LDS slots of LDS, `tw` the table e^{2 pi i t/L}, t < L/2.
+// Stockham stages: radix 8 in registers, radix 8 through LDS, and a last
+// radix-8/4/2 stage in registers; all threads of the block must call it.  On
+// return `buf` is free for reuse (the last LDS reads are behind a barrier).
+template <int L>
+__device__ __forceinline__ void tile_fft(cplx* v, cplx* buf, const cplx* __restrict__ tw, const Tile<L>& T) {
     if constexpr (L == 0) {
-        lds_fft(buf, len, cols, tw);
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s)
+            if (T.live(s)) buf[T.slot(s)] = v[s];
+        __syncthreads();
+        lds_fft(buf, T.len(), T.cols(), tw);
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s)
+            if (T.live(s)) v[s] = buf[T.slot(s)];
+        __syncthreads();
     } else {
-        constexpr int LOG = __builtin_ctz(L);
-        const int tid = threadIdx.x;
+        using TT = Tile<L>;
+        constexpr int LOG = TT::LOG;
+        constexpr int ST = TT::STRIDE;
+        constexpr int RL = ((LOG - 3) % 3) ? (LOG - 3) % 3 : 3;  // log2 of the last radix
+        constexpr int NMID = (LOG - 3 - RL) / 3;
+        const int cb = T.col_ * L;
+        const int i0 = T.i0_;
+        // first stage (p = 1): no twiddles, outputs to 8 i0 + q
+        dft8(v);
 #pragma unroll
-        for (int st = 0; st < (LOG + 1) / 2; ++st) {
-            // radix 4 while two or more bits remain, radix 2 for a last odd bit
-            const int p = 1 << (2 * st);
-            const int r = ((LOG - 2 * st) >= 2) ? 4 : 2;
-            const int nb = L / r;
-            const int total = nb * cols;
-            const int tstride = L / (p * r);
-            cplx v[FFT_VPT];
-            int dst[FFT_VPT / 2];
-            if (r == 4) {
+        for (int q = 0; q < 8; ++q) buf[TT::pad(cb + 8 * i0 + q)] = v[q];
+        __syncthreads();
 #pragma unroll
-                for (int b = 0; b < FFT_VPT / 4; ++b) {
-                    int t = tid + b * FFT_THREADS;
-                    if (t < total) {
-                        int col = t / nb;
-                        int i = t - col * nb;
-                        int k = i & (p - 1);
-                        const int cb0 = col * L;
-                        cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)], x2 = buf[lp(cb0 + i + 2 * nb)], x3 = buf[lp(cb0 + i + 3 * nb)];
-                        if (p > 1) {
-                            cplx w1 = tw[k * tstride];
-                            cplx w2 = cmul(w1, w1);
-                            cplx w3 = cmul(w2, w1);
-                            x1 = cmul(x1, w1);
-                            x2 = cmul(x2, w2);
-                            x3 = cmul(x3, w3);
-                        }
-                        cplx s02 = cadd(x0, x2), d02 = csub(x0, x2);
-                        cplx s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
-                        v[4 * b + 0] = cadd(s02, s13);
-                        v[4 * b + 1] = cadd(d02, d13);
-                        v[4 * b + 2] = csub(s02, s13);
-                        v[4 * b + 3] = csub(d02, d13);
-                        dst[b] = col * L + (i - k) * 4 + k;
-                    }
-                }
-                __syncthreads();
+        for (int st = 0; st < NMID; ++st) {
+            const int p = 8 << (3 * st);
+            const int k = i0 & (p - 1);
+            cplx a[8];
 #pragma unroll
-                for (int b = 0; b < FFT_VPT / 4; ++b) {
-                    int t = tid + b * FFT_THREADS;
-                    if (t < total) {
-                        int d = dst[b];
-                        buf[lp(d)] = v[4 * b + 0];
-                        buf[lp(d + p)] = v[4 * b + 1];
-                        buf[lp(d + 2 * p)] = v[4 * b + 2];
-                        buf[lp(d + 3 * p)] = v[4 * b + 3];
-                    }
-                }
-                __syncthreads();
-            } else {
+            for (int j = 0; j < 8; ++j) a[j] = buf[TT::pad(cb + i0 + j * ST)];
+            twiddle8(a, tw, k * (L / (8 * p)));
+            dft8(a);
+            __syncthreads();
+            const int d = cb + (i0 - k) * 8 + k;
 #pragma unroll
-                for (int b = 0; b < FFT_VPT / 2; ++b) {
-                    int t = tid + b * FFT_THREADS;
-                    if (t < total) {
-                        int col = t / nb;
-                        int i = t - col * nb;
-                        int k = i & (p - 1);
-                        const int cb0 = col * L;
-                        cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)];
-                        if (p > 1) x1 = cmul(x1, tw[k * tstride]);
-                        v[2 * b + 0] = cadd(x0, x1);
-                        v[2 * b + 1] = csub(x0, x1);
-                        dst[b] = col * L + (i - k) * 2 + k;
-                    }
-                }
-                __syncthreads();
+            for (int q = 0; q < 8; ++q) buf[TT::pad(d + q * p)] = a[q];
+            __syncthreads();
+        }
 #pragma unroll
-                for (int b = 0; b < FFT_VPT / 2; ++b) {
-                    int t = tid + b * FFT_THREADS;
-                    if (t < total) {
-                        int d = dst[b];
-                        buf[lp(d)] = v[2 * b + 0];
-                        buf[lp(d + p)] = v[2 * b + 1];
-                    }
-                }
-                __syncthreads();
+        for (int s = 0; s < 8; ++s) v[s] = buf[TT::pad(cb + i0 + s * ST)];
+        __syncthreads();
+        // last stage, p = L / radix: butterfly index k = i < p
+        if constexpr (RL == 3) {
+            twiddle8(v, tw, i0);
+            dft8(v);
+        } else if constexpr (RL == 2) {
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp) {
+                const int i = i0 + sp * ST;
+                cplx w1 = tw[i], w2 = tw[2 * i];
+                cplx w3 = cmul(w1, w2);
+                cplx x0 = v[sp], x1 = cmul(v[sp + 2], w1), x2 = cmul(v[sp + 4], w2), x3 = cmul(v[sp + 6], w3);
+                cplx s02 = cadd(x0, x2), d02 = csub(x0, x2);
+                cplx s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
+                v[sp] = cadd(s02, s13);
+                v[sp + 2] = cadd(d02, d13);
+                v[sp + 4] = csub(s02, s13);
+                v[sp + 6] = csub(d02, d13);
+            }
+        } else {
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                cplx x1 = cmul(v[sp + 4], tw[i0 + sp * ST]);
+                cplx x0 = v[sp];
+                v[sp] = cadd(x0, x1);
+                v[sp + 4] = csub(x0, x1);
             }
         }
+    }
+}
+
+// Stage twiddles e^{2 pi i t/L}, t < L/2, copied into the LDS array `stw` of
+// a compile-time length; the run-time path reads the global table.
+template <int L>
+__device__ __forceinline__ const cplx* stage_twiddles(cplx* stw, const cplx* __restrict__ src) {
+    if constexpr (L > 1) {
+        for (int i = threadIdx.x; i < L / 2; i += FFT_THREADS) stw[i] = src[i];
+        __syncthreads();
+        return stw;
+    } else {
+        return src;
     }
 }
 

@@ -373,6 +373,12 @@ __global__ void k_dense_reduce(int nd, int nchunk, int chunk, const double* __re
 }
 
 // ------------------------------------------------------ FFT pass helpers --
+// Every FFT-carrying kernel: FFT_THREADS threads, and registers capped so that
+// FFT_WAVES waves of it share a SIMD (the LDS tile allows three blocks per CU)
+#ifndef FFT_WAVES
+#define FFT_WAVES 2
+#endif
+#define FFT_BOUNDS __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES)))
 // Intermediate layout between the passes ("blocked"): DFT output (n_a, j_b)
 // of pass A sits at X[(v >> lrB) * (N1 << lrB) + n_a * rowsB + (v & (rowsB-1))]
 // with v = j_b, or for kernels whose pass B pairs row r with N2 - r, the
@@ -398,138 +404,127 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
     return (bid & 7) * (ntiles >> 3) + (bid >> 3);
 }
 
-// Pass A: the block owns columns n_a in [na0, na0+colsA); element e of the
-// tile is (col = e % colsA, n_b = e / colsA), n = na0 + col + N1 n_b.  After
-// the length-N2 DFTs the tile holds buf[lp(col*N2 + j_b)]; it is multiplied by
-// e^{2 pi i n_a j_b / N} and stored in the blocked layout.
-template <bool VIRT>
-__device__ __forceinline__ void passA_store(const Geo& g, int N2, int colsA, const cplx* buf, int na0,
-                                            cplx* __restrict__ X) {
-    const int tot = colsA * N2;
-    const int rB = g.rowsB, lrB = g.lrB;
-    // the element s of this thread is e = tid + s*T; its twiddle is built from
-    // the one P = N2/T elements earlier (same j_b, previous column) when
-    // N2 >= T, else from the previous element (same j_b, column + T/N2)
-    cplx tw[FFT_VPT];
-#pragma unroll
-    for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        if (e < tot) {
-            int col = e / N2, jb = e - col * N2;
-            int na = na0 + col;
-            cplx w;
-            if (N2 >= FFT_THREADS) {
-                int P = N2 / FFT_THREADS;
-                w = (s < P) ? tw2(g.twHi, g.twLo, (int64_t)na * jb, g.sh) : cmul(tw[s - P], g.twLo[jb]);
-            } else {
-                int dc = FFT_THREADS / N2;
-                w = (s == 0) ? tw2(g.twHi, g.twLo, (int64_t)na * jb, g.sh)
-                             : cmul(tw[s - 1], tw2(g.twHi, g.twLo, (int64_t)dc * jb, g.sh));
-            }
-            tw[s] = w;
-            cplx v = cmul(buf[lp(e)], w);
-            int vr = VIRT ? virt_row(jb, N2) : jb;
-            X[(int64_t)(vr >> lrB) * ((int64_t)g.N1 << lrB) + (int64_t)na * rB + (vr & (rB - 1))] = v;
-        }
-    }
+// Pass A: the block owns columns n_a in [na0, na0+colsA) and runs the
+// length-N2 DFTs over n_b (element (col, idx) of the tile is n_a = na0 + col,
+// n_b = idx, input index n = n_a + N1 n_b).  Output j_b = idx of the same
+// element is multiplied by e^{2 pi i n_a j_b / N} and stored in the blocked
+// layout.  With a compile-time length the thread's column is fixed and its
+// j_b are i0 + s L/8, so the twiddles are e^{2 pi i n_a i0/N} times powers
+// of e^{2 pi i n_a L/(8N)}, kept as that start value and the 1st, 2nd and 4th
+// powers (every twiddle is at most three products away from table values).
+__device__ __forceinline__ int passA_offset(const Geo& g, int na, int jb, bool virt) {
+    const int vr = virt ? virt_row(jb, g.N2) : jb;
+    return (vr >> g.lrB) * (g.N1 << g.lrB) + na * g.rowsB + (vr & (g.rowsB - 1));
 }
 
-// Pass B: the block owns (virtual) rows [vb0, vb0+rowsB): one contiguous
-// block of the intermediate; LDS gets buf[lp(r*N1 + n_a)]; after the length-N1
-// DFTs buf[lp(r*N1 + j_a)] is output m = jb(r) + N2 j_a.
-__device__ __forceinline__ void passB_load(const Geo& g, int N1, int rowsB, cplx* buf, int vb0,
-                                           const cplx* __restrict__ X) {
-    const int tot = rowsB * N1;
-    const cplx* src = X + (int64_t)(vb0 >> g.lrB) * ((int64_t)N1 << g.lrB);
-    // all loads of the thread first, then the LDS writes
-    cplx v[FFT_VPT];
-#pragma unroll
-    for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        if (e < tot) v[s] = src[e];
+template <int L, bool VIRT>
+struct PassAOut {
+    cplx w0, p1, p2, p4;
+    int na;
+    __device__ __forceinline__ PassAOut(const Geo& g, const Tile<L>& T, int na0) {
+        na = na0 + T.col(0);
+        w0 = tw2(g.twHi, g.twLo, (int64_t)na * T.idx(0), g.sh);
+        p1 = tw2(g.twHi, g.twLo, (int64_t)na * (L / 8), g.sh);
+        p2 = tw2(g.twHi, g.twLo, (int64_t)na * (L / 4), g.sh);
+        p4 = tw2(g.twHi, g.twLo, (int64_t)na * (L / 2), g.sh);
     }
+    __device__ __forceinline__ void put(const Geo& g, const cplx* v, cplx* __restrict__ Xt, const Tile<L>& T) const {
+        cplx w[8];
+        w[0] = w0;
+        w[1] = cmul(w0, p1);
+        w[2] = cmul(w0, p2);
+        w[3] = cmul(w[1], p2);
+        w[4] = cmul(w0, p4);
+        w[5] = cmul(w[1], p4);
+        w[6] = cmul(w[2], p4);
+        w[7] = cmul(w[3], p4);
 #pragma unroll
-    for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        if (e < tot) {
-            int r = e & (rowsB - 1), na = e / rowsB;
-            buf[lp(r * N1 + na)] = v[s];
-        }
+        for (int s = 0; s < FFT_VPT; ++s) Xt[passA_offset(g, na, T.idx(s), VIRT)] = cmul(v[s], w[s]);
     }
+};
+
+template <bool VIRT>
+struct PassAOut<0, VIRT> {
+    cplx w[FFT_VPT];
+    int na0;
+    __device__ __forceinline__ PassAOut(const Geo& g, const Tile<0>& T, int na0_) : na0(na0_) {
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s)
+            if (T.live(s)) w[s] = tw2(g.twHi, g.twLo, (int64_t)(na0 + T.col(s)) * T.idx(s), g.sh);
+    }
+    __device__ __forceinline__ void put(const Geo& g, const cplx* v, cplx* __restrict__ Xt, const Tile<0>& T) const {
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s)
+            if (T.live(s)) Xt[passA_offset(g, na0 + T.col(s), T.idx(s), VIRT)] = cmul(v[s], w[s]);
+    }
+};
+
+// Pass B: the block owns (virtual) rows [vb0, vb0+rowsB) of the blocked
+// intermediate, one contiguous run of rowsB*N1 values in which element
+// (row, n_a) = (col, idx) of the tile sits at n_a*rowsB + row, which is
+// thread + s*FFT_THREADS for the thread's element s.  After the length-N1 DFTs
+// element (row, j_a) is output m = jb(row) + N2 j_a.
+template <int L>
+__device__ __forceinline__ void passB_load(const Geo& g, int vb0, const cplx* __restrict__ X, cplx* v,
+                                           const Tile<L>& T) {
+    const cplx* src = X + (int64_t)(vb0 >> g.lrB) * ((int64_t)g.N1 << g.lrB);
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s)
+        if (T.live(s)) v[s] = src[threadIdx.x + s * FFT_THREADS];
 }
 
 // ---------------------------------------------------------- far field A --
-// For every term t = (block b, m), in descending m so that
-// h_{m-1,n} = h_{m,n} m (n+m+1/2)/(m-1/2)^2 needs no division, the DFT input
+// Terms t are ordered by ascending m.  For every term, taken in descending m
+// so that h_{m-1,n} = h_{m,n} m (n+m+1/2)/(m-1/2)^2 needs no division, the
+// DFT input
 //   b_n = C_n h_{m,n} c_n e^{i pi n/(2N)} [n >= nlo_b]
-// goes through pass A of the length-N DFT.
+// goes through pass A of the length-N DFT.  Term group blockIdx.y takes the
+// terms nterm-1-y, nterm-1-y-G, ...
 template <int LA>
-__global__ __launch_bounds__(FFT_THREADS) void k_far_passA(Geo g, FarParams F, int G, const double* __restrict__ c,
+__global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const double* __restrict__ c,
                                                           int64_t c_stride, cplx* __restrict__ X,
                                                           int64_t x_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N2 = LA ? LA : g.N2;
-    const int colsA = LA ? FFT_CAP / LA : g.colsA;
-    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
     __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    if constexpr (LA > 1) {
-        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
-        __syncthreads();
-    }
-    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
+    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
-    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const double* cb = c + b * c_stride;
     cplx* Xb = X + b * x_stride;
-    const int tot = colsA * N2;
-    cplx base[FFT_VPT];
-    double h[FFT_VPT];
+    const PassAOut<LA, false> out(g, T, na0);
+    cplx bh[FFT_VPT];  // C_n h_{m,n} c_n e^{i pi n/(2N)} at the current m
     int nn[FFT_VPT];
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        base[s] = {0, 0};
-        h[s] = 0;
+        bh[s] = {0, 0};
         nn[s] = -1;
-        if (e < tot) {
-            int col = e % colsA, nb = e / colsA;
-            int n = na0 + col + g.N1 * nb;
+        if (T.live(s)) {
+            const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             nn[s] = n;
             if (n >= F.nd) {
-                double amp = stieltjes_C((double)n) * cb[n];
-                base[s] = cscale(half_shift(n, N), amp);
-                // h_{Mmax-1,n} = prod_{j<Mmax} (j-1/2)^2/(j (n+j+1/2))
                 // h_{Mmax-1,n} = K / prod_{j<Mmax} (n+j+1/2),  K = prod_{j<Mmax} (j-1/2)^2/j
                 double den = 1;
                 for (int j = 1; j < F.Mmax; ++j) den *= (n + j + 0.5);
-                h[s] = F.hK / den;
+                bh[s] = cscale(half_shift(n, N), stieltjes_C((double)n) * cb[n] * (F.hK / den));
             }
         }
     }
-    for (int m = F.Mmax - 1; m >= 0; --m) {
-        for (int t = 0; t < F.nterm; ++t) {
-            if (F.term_m[t] != m || (t % G) != (int)blockIdx.y) continue;
-            const int nlo = F.blk[F.term_blk[t]].nlo;
+    int mcur = F.Mmax - 1;
+    for (int t = F.nterm - 1 - (int)blockIdx.y; t >= 0; t -= G) {
+        const int m = F.term_m[t];
+        for (; mcur > m; --mcur) {
+            const double fm = (double)mcur / ((mcur - 0.5) * (mcur - 0.5));
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) {
-                int e = threadIdx.x + s * FFT_THREADS;
-                if (e < tot) {
-                    int col = e % colsA, nb = e / colsA;
-                    double f = (nn[s] >= nlo) ? h[s] : 0.0;
-                    buf[lp(col * N2 + nb)] = cscale(base[s], f);
-                }
-            }
-            __syncthreads();
-            lds_fft_t<LA>(buf, N2, colsA, twA);
-            passA_store<false>(g, N2, colsA, buf, na0, Xb + (int64_t)t * N);
-            __syncthreads();
+            for (int s = 0; s < FFT_VPT; ++s) bh[s] = cscale(bh[s], fm * (nn[s] + mcur + 0.5));
         }
-        if (m > 0) {
+        const int nlo = F.blk[F.term_blk[t]].nlo;
+        cplx v[FFT_VPT];
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s)
-                if (nn[s] >= 0) h[s] *= m * (nn[s] + m + 0.5) / ((m - 0.5) * (m - 0.5));
-        }
+        for (int s = 0; s < FFT_VPT; ++s) v[s] = (nn[s] >= nlo) ? bh[s] : cplx{0, 0};
+        tile_fft<LA>(v, buf, twA, T);
+        out.put(g, v, Xb + (int64_t)t * N, T);
     }
 }
 
@@ -538,7 +533,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_far_passA(Geo g, FarParams F, i
 // conj(V_m) at row j(m)) are combined into
 //   v_j += Re(e^{i (m+1/2)(theta_j - pi/2)} z_j) / (2 sin theta_j)^{m+1/2}
 // on the rows of the term's block.  Term group blockIdx.y handles terms
-// t = y, y + G, ...; partial values go to v[y].
+// t = y, y + G, ... (ascending m); partial values go to v[y].  The next
+// term's tile is loaded while the current one is transformed.
 __device__ __forceinline__ int row_block(const FarParams& F, int j, int N) {
     int jj = min(j, N - 1 - j);
     for (int b = 0; b < F.nblk; ++b)
@@ -546,85 +542,80 @@ __device__ __forceinline__ int row_block(const FarParams& F, int j, int N) {
     return -1;
 }
 
+// e^{i (theta_j - pi/2)/2} (2 sin theta_j)^{-1/2} and e^{i (theta_j - pi/2)} / (2 sin theta_j)
+__device__ __forceinline__ void far_row_factors(int j, int N, cplx& g0, cplx& rq) {
+    const double pi = 3.141592653589793;
+    double d = pi * (double)(2 * j + 1 - N) / (2.0 * N);  // theta_j - pi/2
+    int jj = min(j, N - 1 - j);
+    double sn = sin((jj + 0.5) * pi / N);                 // sin theta_j, full relative accuracy
+    double q = 1.0 / (2.0 * sn);
+    double ps, pc, rs, rc;
+    sincos(0.5 * d, &ps, &pc);
+    sincos(d, &rs, &rc);
+    double r0 = sqrt(q);
+    g0 = {pc * r0, ps * r0};
+    rq = {rc * q, rs * q};
+}
+
 template <int LB>
-__global__ __launch_bounds__(FFT_THREADS) void k_far_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
+__global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
                                                           int64_t x_stride, double* __restrict__ v,
                                                           int64_t v_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N1 = LB ? LB : g.N1;
-    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    if constexpr (LB > 1) {
-        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
-        __syncthreads();
-    }
-    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
+    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
-    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const cplx* Xb = X + b * x_stride;
-    const int tot = rowsB * N1;
-    const double pi = 3.141592653589793;
     cplx gm[FFT_VPT], rq[FFT_VPT];
     double acc[FFT_VPT];
-    int blk[FFT_VPT];
-    bool cj[FFT_VPT];
+    int key[FFT_VPT];  // 2 * block + (conjugated output), -1 outside
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
         acc[s] = 0;
-        blk[s] = -1;
-        cj[s] = false;
-        gm[s] = {0, 0};
-        rq[s] = {0, 0};
-        if (e < tot) {
-            int r = e / N1, ja = e - r * N1;
-            int m = jb0 + r + g.N2 * ja;
-            int j = row_of(m, N);
-            cj[s] = (2 * m >= N);
-            blk[s] = row_block(F, j, N);
-            double d = pi * (double)(2 * j + 1 - N) / (2.0 * N);  // theta_j - pi/2
-            int jj = min(j, N - 1 - j);
-            double sn = sin((jj + 0.5) * pi / N);                 // sin theta_j, full relative accuracy
-            double q = 1.0 / (2.0 * sn);
-            double ps, pc, rs, rc;
-            sincos(0.5 * d, &ps, &pc);
-            sincos(d, &rs, &rc);
-            double r0 = sqrt(q);
-            gm[s] = {pc * r0, ps * r0};
-            rq[s] = {rc * q, rs * q};
+        key[s] = -1;
+        gm[s] = rq[s] = {0, 0};
+        if (T.live(s)) {
+            const int mo = jb0 + T.col(s) + g.N2 * T.idx(s);
+            const int j = row_of(mo, N);
+            const int blk = row_block(F, j, N);
+            if (blk >= 0) key[s] = 2 * blk + (2 * mo >= N ? 1 : 0);
+            far_row_factors(j, N, gm[s], rq[s]);
         }
     }
-    for (int m = 0; m < F.Mmax; ++m) {
-        for (int t = 0; t < F.nterm; ++t) {
-            if (F.term_m[t] != m || (t % G) != grp) continue;
-            const int tb = F.term_blk[t];
-            passB_load(g, N1, rowsB, buf, jb0, Xb + (int64_t)t * N);
-            __syncthreads();
-            lds_fft_t<LB>(buf, N1, rowsB, twB);
+    int mcur = 0;
+    int t = grp;
+    cplx nx[FFT_VPT] = {};
+    if (t < F.nterm) passB_load<LB>(g, jb0, Xb + (int64_t)t * N, nx, T);
+    for (; t < F.nterm; t += G) {
+        const int m = F.term_m[t];
+        const int tb = F.term_blk[t];
+        cplx z[FFT_VPT];
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) {
-                int e = threadIdx.x + s * FFT_THREADS;
-                if (e < tot && blk[s] == tb) {
-                    cplx z = buf[lp(e)];
-                    if (cj[s]) z.im = -z.im;
-                    acc[s] = fma(gm[s].re, z.re, fma(-gm[s].im, z.im, acc[s]));
-                }
-            }
-            __syncthreads();
+        for (int s = 0; s < FFT_VPT; ++s) z[s] = nx[s];
+        if (t + G < F.nterm) passB_load<LB>(g, jb0, Xb + (int64_t)(t + G) * N, nx, T);
+        for (; mcur < m; ++mcur) {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) gm[s] = cmul(gm[s], rq[s]);
         }
+        tile_fft<LB>(z, buf, twB, T);
 #pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s) gm[s] = cmul(gm[s], rq[s]);
+        for (int s = 0; s < FFT_VPT; ++s) {
+            if ((key[s] >> 1) == tb) {
+                const double zi = (key[s] & 1) ? -z[s].im : z[s].im;
+                acc[s] = fma(gm[s].re, z[s].re, fma(-gm[s].im, zi, acc[s]));
+            }
+        }
     }
     double* vb = v + b * v_stride + (int64_t)grp * N;
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        if (e < tot) {
-            int r = e / N1, ja = e - r * N1;
-            int m = jb0 + r + g.N2 * ja;
-            vb[row_of(m, N)] = acc[s];
+        if (T.live(s)) {
+            const int mo = jb0 + T.col(s) + g.N2 * T.idx(s);
+            vb[row_of(mo, N)] = acc[s];
         }
     }
 }
@@ -835,72 +826,63 @@ __global__ __launch_bounds__(64) void k_near_combine(NearParams NP, const double
 // p_m = v_{j(m)}, then chat_n = (eps_n/N) Re(e^{i pi n/(2N)} U_n).
 // v_j is the sum of the G far-field partials and the near-field value.
 template <int LA>
-__global__ __launch_bounds__(FFT_THREADS) void k_dct2_passA(Geo g, int G, const double* __restrict__ v,
+__global__ FFT_BOUNDS void k_dct2_passA(Geo g, int G, const double* __restrict__ v,
                                                            int64_t v_stride, const double* __restrict__ near,
                                                            int64_t near_stride, int jnear, cplx* __restrict__ X,
                                                            int64_t x_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N2 = LA ? LA : g.N2;
-    const int colsA = LA ? FFT_CAP / LA : g.colsA;
-    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
     __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    if constexpr (LA > 1) {
-        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
-        __syncthreads();
-    }
-    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
+    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
-    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const double* vb = v + b * v_stride;
     const double* nb = near + b * near_stride;
-    const int tot = colsA * N2;
-    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int col = e % colsA, nbi = e / colsA;
-        int m = na0 + col + g.N1 * nbi;
-        int j = row_of(m, N);
-        double x = 0;
-        for (int q = 0; q < G; ++q) x += vb[(int64_t)q * N + j];
-        if (j < jnear) x += nb[j];
-        else if (N - 1 - j < jnear) x += nb[jnear + (N - 1 - j)];
-        buf[lp(col * N2 + nbi)] = {x, 0.0};
+    const PassAOut<LA, false> out(g, T, na0);
+    cplx x[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        if (T.live(s)) {
+            const int m = na0 + T.col(s) + g.N1 * T.idx(s);
+            const int j = row_of(m, N);
+            double a = 0;
+            for (int q = 0; q < G; ++q) a += vb[(int64_t)q * N + j];
+            if (j < jnear) a += nb[j];
+            else if (N - 1 - j < jnear) a += nb[jnear + (N - 1 - j)];
+            x[s] = {a, 0.0};
+        }
     }
-    __syncthreads();
-    lds_fft_t<LA>(buf, N2, colsA, twA);
-    passA_store<false>(g, N2, colsA, buf, na0, X + b * x_stride);
+    tile_fft<LA>(x, buf, twA, T);
+    out.put(g, x, X + b * x_stride, T);
 }
 
 template <int LB>
-__global__ __launch_bounds__(FFT_THREADS) void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ X,
+__global__ FFT_BOUNDS void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ X,
                                                            int64_t x_stride, const double* __restrict__ dense,
                                                            int64_t dense_stride, double* __restrict__ chat,
                                                            int64_t chat_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N1 = LB ? LB : g.N1;
-    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    if constexpr (LB > 1) {
-        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
-        __syncthreads();
-    }
-    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
+    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
-    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
-    passB_load(g, N1, rowsB, buf, jb0, X + b * x_stride);
-    __syncthreads();
-    lds_fft_t<LB>(buf, N1, rowsB, twB);
-    const int tot = rowsB * N1;
+    cplx z[FFT_VPT];
+    passB_load<LB>(g, jb0, X + b * x_stride, z, T);
+    tile_fft<LB>(z, buf, twB, T);
     const double* db = dense + b * dense_stride;
     double* cb = chat + b * chat_stride;
-    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int r = e / N1, ja = e - r * N1;
-        int n = jb0 + r + g.N2 * ja;
-        cplx U = buf[lp(e)];
-        cplx t = half_shift(n, N);
-        double val = (t.re * U.re - t.im * U.im) * ((n == 0) ? 1.0 : 2.0) / N;
-        if (n < nd) val += db[n];
-        cb[n] = val;
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        if (T.live(s)) {
+            const int n = jb0 + T.col(s) + g.N2 * T.idx(s);
+            const cplx t = half_shift(n, N);
+            double val = (t.re * z[s].re - t.im * z[s].im) * ((n == 0) ? 1.0 : 2.0) / N;
+            if (n < nd) val += db[n];
+            cb[n] = val;
+        }
     }
 }
 
@@ -910,138 +892,110 @@ __global__ __launch_bounds__(FFT_THREADS) void k_dct2_passB(Geo g, int nd, const
 //   W_n = (e^{i pi n/(2N)}/2) [x^{2q}(1+x) chat_n - i y^{2q} x chat_{N-n}],
 // x = n/N, y = 1 - x (n >= 1), W_0 = chat_0 [q = 0]; then at output m the
 // cosine term is Re U_m and the sine term sigma_m Im U_m, row k = j(m).
+// Block row blockIdx.y handles the pairs [Q y / QG, Q (y+1) / QG).
 template <int LA>
-__global__ __launch_bounds__(FFT_THREADS) void k_ndct_passA(Geo g, int Q, int QG, const double* __restrict__ chat,
+__global__ FFT_BOUNDS void k_ndct_passA(Geo g, int Q, int QG, const double* __restrict__ chat,
                                                            int64_t chat_stride, cplx* __restrict__ X,
                                                            int64_t x_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N2 = LA ? LA : g.N2;
-    const int colsA = LA ? FFT_CAP / LA : g.colsA;
-    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
     __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    if constexpr (LA > 1) {
-        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
-        __syncthreads();
-    }
-    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
+    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
-    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const double* cb = chat + b * chat_stride;
     cplx* Xb = X + b * x_stride;
-    const int tot = colsA * N2;
+    const PassAOut<LA, false> out(g, T, na0);
     const double invN = 1.0 / N;
-    cplx Av[FFT_VPT], Bv[FFT_VPT];
-    double px[FFT_VPT], py[FFT_VPT];
+    // W = A x^{2q} + B y^{2q} with A = e (1+x) chat_n / 2, B = -i e x chat_{N-n} / 2;
+    // Ap = A x^{2q} and Bp = B y^{2q} are carried from pair to pair
+    cplx Ap[FFT_VPT], Bp[FFT_VPT];
     const int q0 = (Q * grp) / QG, q1 = (Q * (grp + 1)) / QG;
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        Av[s] = {0, 0};
-        Bv[s] = {0, 0};
-        px[s] = py[s] = 0;
-        if (e < tot) {
-            int col = e % colsA, nbi = e / colsA;
-            int n = na0 + col + g.N1 * nbi;
+        Ap[s] = Bp[s] = {0, 0};
+        if (T.live(s)) {
+            const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             if (n == 0) {
-                Av[s] = {cb[0], 0};
-                px[s] = (q0 == 0) ? 1.0 : 0.0;
+                if (q0 == 0) Ap[s] = {cb[0], 0};
             } else {
-                double x = n * invN, y = (N - n) * invN;
-                cplx e2 = cscale(half_shift(n, N), 0.5);
-                Av[s] = cscale(e2, (1.0 + x) * cb[n]);
-                Bv[s] = cscale(cmuli(e2), -x * cb[N - n]);
+                const double x = n * invN, y = (N - n) * invN;
+                const cplx e2 = cscale(half_shift(n, N), 0.5);
                 double a = 1, bb = 1;
                 for (int q = 0; q < q0; ++q) {
                     a *= x * x;
                     bb *= y * y;
                 }
-                px[s] = a;
-                py[s] = bb;
+                Ap[s] = cscale(e2, (1.0 + x) * cb[n] * a);
+                Bp[s] = cscale(cmuli(e2), -x * cb[N - n] * bb);
             }
         }
     }
     for (int q = q0; q < q1; ++q) {
+        cplx v[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
-            int e = threadIdx.x + s * FFT_THREADS;
-            if (e < tot) {
-                int col = e % colsA, nbi = e / colsA;
-                int n = na0 + col + g.N1 * nbi;
-                double x = n * invN, y = (N - n) * invN;
-                buf[lp(col * N2 + nbi)] = cadd(cscale(Av[s], px[s]), cscale(Bv[s], py[s]));
-                px[s] *= x * x;
-                py[s] *= y * y;
-            }
+            const int n = na0 + T.col(s) + g.N1 * T.idx(s);
+            const double x = n * invN, y = (N - n) * invN;
+            v[s] = cadd(Ap[s], Bp[s]);
+            Ap[s] = cscale(Ap[s], (n == 0) ? 0.0 : x * x);
+            Bp[s] = cscale(Bp[s], y * y);
         }
-        __syncthreads();
-        lds_fft_t<LA>(buf, N2, colsA, twA);
-        passA_store<false>(g, N2, colsA, buf, na0, Xb + (int64_t)q * N);
-        __syncthreads();
+        tile_fft<LA>(v, buf, twA, T);
+        out.put(g, v, Xb + (int64_t)q * N, T);
     }
 }
 
 // f_k = sum_l s_l d_k^l/l! F_l[k], s_l = (-1)^floor((l+1)/2), d_k = N dtheta_k,
-// by Horner from the highest pair down.
+// by Horner from the highest pair down; the next pair's tile is loaded while
+// the current one is transformed.
 template <int LB>
-__global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X,
+__global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X,
                                                            int64_t x_stride, const double* __restrict__ dth,
                                                            double* __restrict__ f, int64_t f_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N1 = LB ? LB : g.N1;
-    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    if constexpr (LB > 1) {
-        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
-        __syncthreads();
-    }
-    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
+    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
-    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const cplx* Xb = X + b * x_stride;
-    const int tot = rowsB * N1;
     double acc[FFT_VPT], d[FFT_VPT];
-    bool hi[FFT_VPT];
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
         acc[s] = 0;
         d[s] = 0;
-        hi[s] = false;
-        if (e < tot) {
-            int r = e / N1, ja = e - r * N1;
-            int m = jb0 + r + g.N2 * ja;
-            hi[s] = (2 * m >= N);
+        if (T.live(s)) {
+            const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
             d[s] = (double)N * dth[row_of(m, N)];
         }
     }
+    cplx nx[FFT_VPT] = {};
+    if (Q > 0) passB_load<LB>(g, jb0, Xb + (int64_t)(Q - 1) * N, nx, T);
     for (int q = Q - 1; q >= 0; --q) {
-        passB_load(g, N1, rowsB, buf, jb0, Xb + (int64_t)q * N);
-        __syncthreads();
-        lds_fft_t<LB>(buf, N1, rowsB, twB);
+        cplx z[FFT_VPT];
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) z[s] = nx[s];
+        if (q > 0) passB_load<LB>(g, jb0, Xb + (int64_t)(q - 1) * N, nx, T);
+        tile_fft<LB>(z, buf, twB, T);
         const double sc = (q & 1) ? -1.0 : 1.0;  // s_{2q} = (-1)^q, s_{2q+1} = -(-1)^q
+        const double r1 = 1.0 / (2 * q + 1), r2 = 1.0 / (2 * q + 2);
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
-            int e = threadIdx.x + s * FFT_THREADS;
-            if (e < tot) {
-                cplx U = buf[lp(e)];
-                double Fc = U.re;
-                double Fs = hi[s] ? -U.im : U.im;
-                double inner = fma(d[s] / (2 * q + 2), acc[s], -sc * Fs);
-                acc[s] = fma(d[s] / (2 * q + 1), inner, sc * Fc);
-            }
+            const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
+            const double Fs = (2 * m >= N) ? -z[s].im : z[s].im;
+            const double inner = fma(d[s] * r2, acc[s], -sc * Fs);
+            acc[s] = fma(d[s] * r1, inner, sc * z[s].re);
         }
-        __syncthreads();
     }
     double* fb = f + b * f_stride;
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        if (e < tot) {
-            int r = e / N1, ja = e - r * N1;
-            int m = jb0 + r + g.N2 * ja;
+        if (T.live(s)) {
+            const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
             fb[row_of(m, N)] = acc[s];
         }
     }
@@ -1054,104 +1008,86 @@ __global__ __launch_bounds__(FFT_THREADS) void k_ndct_passB(Geo g, int Q, const 
 
 // Transposed Taylor pair q: DFT input at m (row k = j(m)):
 //   g_k d_k^{2q} (1 + i sigma_m d_k),  sigma_m = +1 (2m < N), -1 otherwise.
+// Block row blockIdx.y handles the pairs [Q y / QG, Q (y+1) / QG).
 template <int LA>
-__global__ __launch_bounds__(FFT_THREADS) void k_tndct_passA(Geo g, int Q, int QG, const double* __restrict__ fv,
+__global__ FFT_BOUNDS void k_tndct_passA(Geo g, int Q, int QG, const double* __restrict__ fv,
                                                             int64_t f_stride, const double* __restrict__ wts,
                                                             const double* __restrict__ dth, cplx* __restrict__ X,
                                                             int64_t x_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N2 = LA ? LA : g.N2;
-    const int colsA = LA ? FFT_CAP / LA : g.colsA;
-    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
     __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    if constexpr (LA > 1) {
-        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
-        __syncthreads();
-    }
-    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
+    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
-    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const double* fb = fv + b * f_stride;
     cplx* Xb = X + b * x_stride;
-    const int tot = colsA * N2;
-    double gv[FFT_VPT], dv[FFT_VPT], pw[FFT_VPT];
+    const PassAOut<LA, true> out(g, T, na0);
+    double gv[FFT_VPT], dv[FFT_VPT], d2[FFT_VPT];
     const int q0 = (Q * grp) / QG, q1 = (Q * (grp + 1)) / QG;
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        gv[s] = dv[s] = pw[s] = 0;
-        if (e < tot) {
-            int col = e % colsA, nbi = e / colsA;
-            int m = na0 + col + g.N1 * nbi;
-            int kk = row_of(m, N);
-            gv[s] = wts[kk] * fb[kk];
-            dv[s] = (double)N * dth[kk];
-            double p = 1;
-            for (int q = 0; q < q0; ++q) p *= dv[s] * dv[s];
-            pw[s] = p;
+        gv[s] = dv[s] = d2[s] = 0;
+        if (T.live(s)) {
+            const int m = na0 + T.col(s) + g.N1 * T.idx(s);
+            const int kk = row_of(m, N);
+            const double d = (double)N * dth[kk];
+            double p = wts[kk] * fb[kk];
+            for (int q = 0; q < q0; ++q) p *= d * d;
+            gv[s] = p;  // g_k d_k^{2q}
+            d2[s] = d * d;
+            dv[s] = (2 * m < N) ? d : -d;  // sigma_m d_k
         }
     }
     for (int q = q0; q < q1; ++q) {
+        cplx v[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
-            int e = threadIdx.x + s * FFT_THREADS;
-            if (e < tot) {
-                int col = e % colsA, nbi = e / colsA;
-                int m = na0 + col + g.N1 * nbi;
-                double a = gv[s] * pw[s];
-                double sg = (2 * m < N) ? 1.0 : -1.0;
-                buf[lp(col * N2 + nbi)] = {a, sg * a * dv[s]};
-                pw[s] *= dv[s] * dv[s];
-            }
+            v[s] = {gv[s], gv[s] * dv[s]};
+            gv[s] *= d2[s];
         }
-        __syncthreads();
-        lds_fft_t<LA>(buf, N2, colsA, twA);
-        passA_store<true>(g, N2, colsA, buf, na0, Xb + (int64_t)q * N);
-        __syncthreads();
+        tile_fft<LA>(v, buf, twA, T);
+        out.put(g, v, Xb + (int64_t)q * N, T);
     }
 }
 
 // y_n = sum_l s_l (n/N)^l / l! Z_l[n]; Z_{2q} = Re(e_n A_n), Z_{2q+1} = Im(e_n B_n),
 // A = (U_n + conj U_{N-n})/2, B = (U_n - conj U_{N-n})/(2i), e_n = e^{i pi n/(2N)}.
+// U_{N-n} of (virtual) row i, column j_a sits in the same tile: row 0 pairs
+// with itself at (N1 - j_a) mod N1, row N2/2 with itself at N1-1-j_a, row r
+// with its neighbour N2 - r (virtual row i ^ 1) at N1-1-j_a; the transform
+// goes through LDS once more to reach it.
 template <int LB>
-__global__ __launch_bounds__(FFT_THREADS) void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ X,
+__global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ X,
                                                             int64_t x_stride, double* __restrict__ y,
                                                             int64_t y_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N1 = LB ? LB : g.N1;
-    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    if constexpr (LB > 1) {
-        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
-        __syncthreads();
-    }
-    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
+    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
+    const int N1 = T.len();
     const int N2 = g.N2;
-    const int vb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
+    const int vb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const cplx* Xb = X + b * x_stride;
-    const int tot = rowsB * N1;
     double acc[FFT_VPT], xs[FFT_VPT];
     cplx en[FFT_VPT];
     int part[FFT_VPT];
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
         acc[s] = 0;
         xs[s] = 0;
         en[s] = {0, 0};
         part[s] = 0;
-        if (e < tot) {
-            int i = e / N1, ja = e - i * N1;
-            int r = actual_row(vb0 + i, N2);
-            int n = r + N2 * ja;
+        if (T.live(s)) {
+            const int i = T.col(s), ja = T.idx(s);
+            const int r = actual_row(vb0 + i, N2);
+            const int n = r + N2 * ja;
             xs[s] = (double)n / N;
             en[s] = half_shift(n, N);
-            // U_{N-n}: row 0 pairs with itself at (N1 - ja) mod N1, row N2/2
-            // with itself at N1-1-ja, row r with its neighbour N2 - r at N1-1-ja
             int ip, jp;
             if (r == 0) {
                 ip = i;
@@ -1163,25 +1099,33 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passB(Geo g, int Q, const
                 ip = i ^ 1;
                 jp = N1 - 1 - ja;
             }
-            part[s] = ip * N1 + jp;
+            part[s] = Tile<LB>::pad(ip * N1 + jp);
         }
     }
+    cplx nx[FFT_VPT] = {};
+    if (Q > 0) passB_load<LB>(g, vb0, Xb + (int64_t)(Q - 1) * N, nx, T);
     for (int q = Q - 1; q >= 0; --q) {
-        passB_load(g, N1, rowsB, buf, vb0, Xb + (int64_t)q * N);
+        cplx U[FFT_VPT];
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
+        if (q > 0) passB_load<LB>(g, vb0, Xb + (int64_t)(q - 1) * N, nx, T);
+        tile_fft<LB>(U, buf, twB, T);
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s)
+            if (T.live(s)) buf[T.slot(s)] = U[s];
         __syncthreads();
-        lds_fft_t<LB>(buf, N1, rowsB, twB);
         const double sc = (q & 1) ? -1.0 : 1.0;
+        const double r1 = 1.0 / (2 * q + 1), r2 = 1.0 / (2 * q + 2);
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
-            int e = threadIdx.x + s * FFT_THREADS;
-            if (e < tot) {
-                cplx U = buf[lp(e)], V = buf[lp(part[s])];
-                cplx A = {0.5 * (U.re + V.re), 0.5 * (U.im - V.im)};
-                cplx Bm = {0.5 * (U.im + V.im), -0.5 * (U.re - V.re)};  // (U - conj V)/(2i)
-                double Zc = en[s].re * A.re - en[s].im * A.im;
-                double Zs = en[s].re * Bm.im + en[s].im * Bm.re;
-                double inner = fma(xs[s] / (2 * q + 2), acc[s], -sc * Zs);
-                acc[s] = fma(xs[s] / (2 * q + 1), inner, sc * Zc);
+            if (T.live(s)) {
+                const cplx V = buf[part[s]];
+                const cplx A = {0.5 * (U[s].re + V.re), 0.5 * (U[s].im - V.im)};
+                const cplx Bm = {0.5 * (U[s].im + V.im), -0.5 * (U[s].re - V.re)};  // (U - conj V)/(2i)
+                const double Zc = en[s].re * A.re - en[s].im * A.im;
+                const double Zs = en[s].re * Bm.im + en[s].im * Bm.re;
+                const double inner = fma(xs[s] * r2, acc[s], -sc * Zs);
+                acc[s] = fma(xs[s] * r1, inner, sc * Zc);
             }
         }
         __syncthreads();
@@ -1189,11 +1133,9 @@ __global__ __launch_bounds__(FFT_THREADS) void k_tndct_passB(Geo g, int Q, const
     double* yb = y + b * y_stride;
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        if (e < tot) {
-            int i = e / N1, ja = e - i * N1;
-            int r = actual_row(vb0 + i, N2);
-            yb[r + N2 * ja] = acc[s];
+        if (T.live(s)) {
+            const int r = actual_row(vb0 + T.col(s), N2);
+            yb[r + N2 * T.idx(s)] = acc[s];
         }
     }
 }
@@ -1252,208 +1194,166 @@ __global__ void k_dense_t_reduce(int nd, int nchunk, int chunk, const double* __
 // u_j = sum_k (eps_k/N) y_k cos(k theta_j): DFT of (eps_k/N) y_k e^{i pi k/(2N)},
 // u at row j(m) = Re V_m.
 template <int LA>
-__global__ __launch_bounds__(FFT_THREADS) void k_dct3_passA(Geo g, const double* __restrict__ y, int64_t y_stride,
+__global__ FFT_BOUNDS void k_dct3_passA(Geo g, const double* __restrict__ y, int64_t y_stride,
                                                            cplx* __restrict__ X, int64_t x_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N2 = LA ? LA : g.N2;
-    const int colsA = LA ? FFT_CAP / LA : g.colsA;
-    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
     __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    if constexpr (LA > 1) {
-        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
-        __syncthreads();
-    }
-    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
+    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
-    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const double* yb = y + b * y_stride;
-    const int tot = colsA * N2;
-    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int col = e % colsA, nbi = e / colsA;
-        int n = na0 + col + g.N1 * nbi;
-        double a = yb[n] * ((n == 0) ? 1.0 : 2.0) / N;
-        buf[lp(col * N2 + nbi)] = cscale(half_shift(n, N), a);
+    const PassAOut<LA, false> out(g, T, na0);
+    cplx x[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        if (T.live(s)) {
+            const int n = na0 + T.col(s) + g.N1 * T.idx(s);
+            const double a = yb[n] * ((n == 0) ? 1.0 : 2.0) / N;
+            x[s] = cscale(half_shift(n, N), a);
+        }
     }
-    __syncthreads();
-    lds_fft_t<LA>(buf, N2, colsA, twA);
-    passA_store<false>(g, N2, colsA, buf, na0, X + b * x_stride);
+    tile_fft<LA>(x, buf, twA, T);
+    out.put(g, x, X + b * x_stride, T);
 }
 
 template <int LB>
-__global__ __launch_bounds__(FFT_THREADS) void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64_t x_stride,
+__global__ FFT_BOUNDS void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64_t x_stride,
                                                            double* __restrict__ u, int64_t u_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N1 = LB ? LB : g.N1;
-    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    if constexpr (LB > 1) {
-        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
-        __syncthreads();
-    }
-    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
+    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
-    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
-    passB_load(g, N1, rowsB, buf, jb0, X + b * x_stride);
-    __syncthreads();
-    lds_fft_t<LB>(buf, N1, rowsB, twB);
-    const int tot = rowsB * N1;
+    cplx z[FFT_VPT];
+    passB_load<LB>(g, jb0, X + b * x_stride, z, T);
+    tile_fft<LB>(z, buf, twB, T);
     double* ub = u + b * u_stride;
-    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-        int r = e / N1, ja = e - r * N1;
-        int m = jb0 + r + g.N2 * ja;
-        ub[row_of(m, N)] = buf[lp(e)].re;
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        if (T.live(s)) {
+            const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
+            ub[row_of(m, N)] = z[s].re;
+        }
     }
 }
 
 // Transposed far field, pass A: for every term (b, m), ascending m, the DFT
 // input at m is rho at row j = j(m) (conjugated when 2m >= N) with
 //   rho_j = u_j e^{i (m+1/2)(theta_j - pi/2)} (2 sin theta_j)^{-m-1/2} [j in block b].
+// Term group blockIdx.y takes the terms y, y + G, ...
 template <int LA>
-__global__ __launch_bounds__(FFT_THREADS) void k_tfar_passA(Geo g, FarParams F, int G, const double* __restrict__ u,
+__global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const double* __restrict__ u,
                                                            int64_t u_stride, cplx* __restrict__ X,
                                                            int64_t x_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N2 = LA ? LA : g.N2;
-    const int colsA = LA ? FFT_CAP / LA : g.colsA;
-    // stage twiddles e^{2 pi i t/N2}, t < N2/2 (all the radix-4/2 stages use)
     __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    if constexpr (LA > 1) {
-        for (int i = threadIdx.x; i < LA / 2; i += FFT_THREADS) stw[i] = g.twN2[i];
-        __syncthreads();
-    }
-    const cplx* twA = (LA > 1) ? (const cplx*)stw : g.twN2;
+    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
-    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * colsA;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const double* ub = u + b * u_stride;
     cplx* Xb = X + b * x_stride;
-    const int tot = colsA * N2;
-    const double pi = 3.141592653589793;
+    const PassAOut<LA, false> out(g, T, na0);
     cplx gm[FFT_VPT], rq[FFT_VPT];
-    int blk[FFT_VPT];
-    bool cj[FFT_VPT];
+    int key[FFT_VPT];  // 2 * block + (conjugated input), -1 outside
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
         gm[s] = rq[s] = {0, 0};
-        blk[s] = -1;
-        cj[s] = false;
-        if (e < tot) {
-            int col = e % colsA, nbi = e / colsA;
-            int m = na0 + col + g.N1 * nbi;
-            int j = row_of(m, N);
-            cj[s] = (2 * m >= N);
-            blk[s] = row_block(F, j, N);
-            double d = pi * (double)(2 * j + 1 - N) / (2.0 * N);
-            int jj = min(j, N - 1 - j);
-            double sn = sin((jj + 0.5) * pi / N);
-            double q = 1.0 / (2.0 * sn);
-            double ps, pc, rs, rc;
-            sincos(0.5 * d, &ps, &pc);
-            sincos(d, &rs, &rc);
-            double r0 = sqrt(q) * ub[j];
-            gm[s] = {pc * r0, ps * r0};
-            rq[s] = {rc * q, rs * q};
+        key[s] = -1;
+        if (T.live(s)) {
+            const int mo = na0 + T.col(s) + g.N1 * T.idx(s);
+            const int j = row_of(mo, N);
+            const int blk = row_block(F, j, N);
+            if (blk >= 0) key[s] = 2 * blk + (2 * mo >= N ? 1 : 0);
+            cplx g0;
+            far_row_factors(j, N, g0, rq[s]);
+            gm[s] = cscale(g0, ub[j]);
         }
     }
-    for (int m = 0; m < F.Mmax; ++m) {
-        for (int t = 0; t < F.nterm; ++t) {
-            if (F.term_m[t] != m || (t % G) != (int)blockIdx.y) continue;
-            const int tb = F.term_blk[t];
+    int mcur = 0;
+    for (int t = blockIdx.y; t < F.nterm; t += G) {
+        const int m = F.term_m[t];
+        const int tb = F.term_blk[t];
+        for (; mcur < m; ++mcur) {
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) {
-                int e = threadIdx.x + s * FFT_THREADS;
-                if (e < tot) {
-                    int col = e % colsA, nbi = e / colsA;
-                    cplx v = (blk[s] == tb) ? gm[s] : cplx{0, 0};
-                    if (cj[s]) v.im = -v.im;
-                    buf[lp(col * N2 + nbi)] = v;
-                }
-            }
-            __syncthreads();
-            lds_fft_t<LA>(buf, N2, colsA, twA);
-            passA_store<false>(g, N2, colsA, buf, na0, Xb + (int64_t)t * N);
-            __syncthreads();
+            for (int s = 0; s < FFT_VPT; ++s) gm[s] = cmul(gm[s], rq[s]);
         }
+        cplx v[FFT_VPT];
 #pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s) gm[s] = cmul(gm[s], rq[s]);
+        for (int s = 0; s < FFT_VPT; ++s) {
+            v[s] = ((key[s] >> 1) == tb) ? gm[s] : cplx{0, 0};
+            if (key[s] & 1) v[s].im = -v[s].im;
+        }
+        tile_fft<LA>(v, buf, twA, T);
+        out.put(g, v, Xb + (int64_t)t * N, T);
     }
 }
 
 // Transposed far field, pass B: out_n = sum_terms C_n h_{m,n} [n >= nlo_b]
-// Re(e^{i pi n/(2N)} U_n), descending m (h by multiplication only).
+// Re(e^{i pi n/(2N)} U_n), descending m (h by multiplication only); term
+// group blockIdx.y takes the terms nterm-1-y, nterm-1-y-G, ... and writes
+// partial sums to out[y].
 template <int LB>
-__global__ __launch_bounds__(FFT_THREADS) void k_tfar_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
+__global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
                                                            int64_t x_stride, double* __restrict__ out,
                                                            int64_t out_stride) {
     __shared__ cplx buf[FFT_LDS];
-    const int N1 = LB ? LB : g.N1;
-    const int rowsB = LB ? FFT_CAP / LB : g.rowsB;
     __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    if constexpr (LB > 1) {
-        for (int i = threadIdx.x; i < LB / 2; i += FFT_THREADS) stw[i] = g.twN1[i];
-        __syncthreads();
-    }
-    const cplx* twB = (LB > 1) ? (const cplx*)stw : g.twN1;
+    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
-    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * rowsB;
+    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const cplx* Xb = X + b * x_stride;
-    const int tot = rowsB * N1;
-    double acc[FFT_VPT], h[FFT_VPT];
-    cplx en[FFT_VPT];
+    double acc[FFT_VPT];
+    cplx eh[FFT_VPT];  // C_n h_{m,n} e^{i pi n/(2N)} at the current m
     int nn[FFT_VPT];
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
         acc[s] = 0;
-        h[s] = 0;
-        en[s] = {0, 0};
+        eh[s] = {0, 0};
         nn[s] = -1;
-        if (e < tot) {
-            int r = e / N1, ja = e - r * N1;
-            int n = jb0 + r + g.N2 * ja;
+        if (T.live(s)) {
+            const int n = jb0 + T.col(s) + g.N2 * T.idx(s);
             nn[s] = n;
             if (n >= F.nd) {
-                en[s] = cscale(half_shift(n, N), stieltjes_C((double)n));
                 // h_{Mmax-1,n} = K / prod_{j<Mmax} (n+j+1/2),  K = prod_{j<Mmax} (j-1/2)^2/j
                 double den = 1;
                 for (int j = 1; j < F.Mmax; ++j) den *= (n + j + 0.5);
-                h[s] = F.hK / den;
+                eh[s] = cscale(half_shift(n, N), stieltjes_C((double)n) * (F.hK / den));
             }
         }
     }
-    for (int m = F.Mmax - 1; m >= 0; --m) {
-        for (int t = 0; t < F.nterm; ++t) {
-            if (F.term_m[t] != m || (t % G) != (int)blockIdx.y) continue;
-            const int nlo = F.blk[F.term_blk[t]].nlo;
-            passB_load(g, N1, rowsB, buf, jb0, Xb + (int64_t)t * N);
-            __syncthreads();
-            lds_fft_t<LB>(buf, N1, rowsB, twB);
+    int mcur = F.Mmax - 1;
+    int t = F.nterm - 1 - (int)blockIdx.y;
+    cplx nx[FFT_VPT] = {};
+    if (t >= 0) passB_load<LB>(g, jb0, Xb + (int64_t)t * N, nx, T);
+    for (; t >= 0; t -= G) {
+        const int m = F.term_m[t];
+        const int nlo = F.blk[F.term_blk[t]].nlo;
+        cplx U[FFT_VPT];
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) {
-                int e = threadIdx.x + s * FFT_THREADS;
-                if (e < tot && nn[s] >= nlo) {
-                    cplx U = buf[lp(e)];
-                    acc[s] = fma(h[s], en[s].re * U.re - en[s].im * U.im, acc[s]);
-                }
-            }
-            __syncthreads();
-        }
-        if (m > 0) {
+        for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
+        if (t - G >= 0) passB_load<LB>(g, jb0, Xb + (int64_t)(t - G) * N, nx, T);
+        for (; mcur > m; --mcur) {
+            const double fm = (double)mcur / ((mcur - 0.5) * (mcur - 0.5));
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s)
-                if (nn[s] >= 0) h[s] *= m * (nn[s] + m + 0.5) / ((m - 0.5) * (m - 0.5));
+            for (int s = 0; s < FFT_VPT; ++s) eh[s] = cscale(eh[s], fm * (nn[s] + mcur + 0.5));
         }
+        tile_fft<LB>(U, buf, twB, T);
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s)
+            if (nn[s] >= nlo) acc[s] = fma(eh[s].re, U[s].re, fma(-eh[s].im, U[s].im, acc[s]));
     }
     double* ob = out + b * out_stride + (int64_t)blockIdx.y * N;
 #pragma unroll
-    for (int s = 0; s < FFT_VPT; ++s) {
-        int e = threadIdx.x + s * FFT_THREADS;
-        if (e < tot) ob[nn[s]] = acc[s];
-    }
+    for (int s = 0; s < FFT_VPT; ++s)
+        if (T.live(s)) ob[nn[s]] = acc[s];
 }
 
 // Transposed near field.  (1) k_near_items with c == null gives each

@@ -201,8 +201,8 @@ int plan_build(int64_t N, Plan& p) {
             for (int b = 0; b < F.nblk; ++b)
                 if (m < F.blk[b].M) {
                     if (F.nterm >= MAX_TERMS) return DLT_ERR_UNSUPPORTED;
-                    F.term_blk[F.nterm] = (unsigned char)b;
-                    F.term_m[F.nterm] = (unsigned char)m;
+                    F.term_blk[F.nterm] = b;
+                    F.term_m[F.nterm] = m;
                     ++F.nterm;
                 }
         // near-field segments: blocks b >= 1 need columns [nd, nlo); rows

@@ -49,7 +49,8 @@ struct FarParams {
     int nblk, nterm, Mmax, nd;
     double hK;  // prod_{j=1}^{Mmax-1} (j-1/2)^2 / j
     Block blk[MAX_BLOCKS];
-    unsigned char term_blk[MAX_TERMS], term_m[MAX_TERMS];
+    // int (not byte) entries so that kernels read them with scalar loads
+    int term_blk[MAX_TERMS], term_m[MAX_TERMS];  // ordered by ascending m
     // row -> block lookup: rows j < blk_edge[b] (and mirrors) are outside
     // blocks 0..b-1; block 0 is the central one.
 };
