@@ -61,6 +61,7 @@ int get_plan(int64_t N, Plan** out) {
     }
     std::unique_ptr<Plan> p(new Plan());
     int rc = plan_build(N, *p);
+    if (rc == DLT_OK && plan_prepare(*p) != hipSuccess) rc = DLT_ERR_HIP;
     if (rc != DLT_OK) {
         plan_free(*p);
         return rc;

@@ -287,6 +287,7 @@ __device__ __forceinline__ void tile_fft(cplx* v, cplx* buf, const cplx* __restr
 template <int L>
 __device__ __forceinline__ const cplx* stage_twiddles(cplx* stw, const cplx* __restrict__ src) {
     if constexpr (L > 1) {
+#pragma unroll
         for (int i = threadIdx.x; i < L / 2; i += FFT_THREADS) stw[i] = src[i];
         __syncthreads();
         return stw;

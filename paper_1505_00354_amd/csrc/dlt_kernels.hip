@@ -341,7 +341,9 @@ __global__ __launch_bounds__(256) void k_dense(int N, int nd, int chunk, const d
     const int kmax = kb0 + 511;
     const int zm0 = (n0 - kmax) >> 1;  // may be negative (unused entries)
     const int zp0 = (n0 + kb0) >> 1;
+#pragma unroll
     for (int i = threadIdx.x; i < DENSE_CH; i += 256) sc[i] = (n0 + i < n1) ? cb[n0 + i] : 0.0;
+#pragma unroll
     for (int i = threadIdx.x; i < DENSE_CH / 2 + 256; i += 256) {
         int zm = zm0 + i, zp = zp0 + i;
         slm[i] = (zm >= 0 && zm < nd) ? lam[zm] : 0.0;
@@ -621,16 +623,11 @@ __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __
 }
 
 // ------------------------------------------------------------ near field --
-// Work-group = one wave = 64 consecutive rows of one segment and one degree
-// chunk [n0, n1) (NEAR_CHUNK degrees); the plan's table maps blockIdx.x to
-// its segment.  Item (row, chunk) stores, for chunk 0 (true start P_0 = 1),
-// the end state and the even/odd-degree sums
-//   E = sum_{n even, n >= nd} c_n P_n(x_j),  O = sum_{n odd, n >= nd} c_n P_n(x_j)
-// (S+ = E + O is row j, S- = E - O the mirror row N-1-j, since
-// P_n(-x) = (-1)^n P_n(x)); for later chunks the same from the two basis
-// states (1, 0) and (0, 1), i.e. the chunk's transfer matrix and sums.
-// With c == null only the transfer data are produced (inverse transform).
-// Degrees, c_n and 1/(n+1) are uniform across the wave.
+// Rows j < jnear (and their mirrors N-1-j) take the direct recurrence over
+// degrees [nd, nend) of their segment, split into chunks of NEAR_CHUNK
+// degrees.  Work-group = one wave = 64 consecutive rows of one segment and
+// one chunk; the plan's table maps blockIdx.x to (segment, chunk, row group).
+// Degrees and 1/(n+1) are uniform across the wave.
 struct NearWG {
     int seg, ch, grp;
 };
@@ -647,13 +644,15 @@ __device__ __forceinline__ NearWG near_wg(const NearParams& NP, const int* __res
     return w;
 }
 
+// Transfer data of item (row, chunk), used once per plan: for chunk 0 the
+// state (P, D) at its end from the true start (P_0, D_0) = (1, 0); for later
+// chunks the images of the basis states (1, 0) and (0, 1), i.e. the chunk's
+// 2x2 transfer matrix.  Item record: 8 doubles (end state | matrix).
 __global__ __launch_bounds__(64) void k_near_items(int N, NearParams NP, const int* __restrict__ wg_seg,
                                                    const int* __restrict__ segoff, const double* __restrict__ rcp,
-                                                   const double* __restrict__ c, int64_t c_stride,
-                                                   double* __restrict__ items, int64_t it_stride) {
+                                                   double* __restrict__ items) {
     const NearWG W = near_wg(NP, wg_seg, segoff, blockIdx.x);
     const Seg S = NP.seg[W.seg];
-    const int b = blockIdx.z;
     const int nrows = S.jhi - S.jlo;
     const int row = W.grp * 64 + threadIdx.x;
     const bool act = row < nrows;
@@ -662,113 +661,168 @@ __global__ __launch_bounds__(64) void k_near_items(int N, NearParams NP, const i
     double sn = sin(0.5 * (j + 0.5) * pi / N);
     const double u = 2.0 * sn * sn;
     const int n0 = W.ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
-    const double* cb = (c && n0 >= NP.nd) ? c + b * c_stride : nullptr;
-    double* out = items + b * it_stride + (int64_t)(S.item_off + W.ch * nrows + row) * 8;
+    double* out = items + (int64_t)(S.item_off + W.ch * nrows + row) * 8;
     if (W.ch == 0) {
-        double p = 1, d = 0, E = 0, O = 0;
-        int n = n0;
-        if (cb) {
-            for (; n + 1 < n1; n += 2) {
-                E = fma(cb[n], p, E);
-                reinsch_step(u, rcp[n], p, d);
-                O = fma(cb[n + 1], p, O);
-                reinsch_step(u, rcp[n + 1], p, d);
-            }
-            if (n < n1) {
-                E = fma(cb[n], p, E);
-                reinsch_step(u, rcp[n], p, d);
-            }
-        } else {
-#pragma unroll 4
-            for (; n < n1; ++n) reinsch_step(u, rcp[n], p, d);
-        }
+        double p = 1, d = 0;
+        for (int n = n0; n < n1; ++n) reinsch_step(u, rcp[n], p, d);
         if (act) {
             out[0] = p;
             out[1] = d;
-            out[2] = E;
-            out[3] = O;
         }
     } else {
         double pa = 1, da = 0, pb = 0, db = 1;
-        double Ea = 0, Eb = 0, Oa = 0, Ob = 0;
-        int n = n0;
-        if (cb) {
-            for (; n + 1 < n1; n += 2) {
-                double ce = cb[n], co = cb[n + 1], r0 = rcp[n], r1 = rcp[n + 1];
-                Ea = fma(ce, pa, Ea);
-                Eb = fma(ce, pb, Eb);
-                reinsch_step(u, r0, pa, da);
-                reinsch_step(u, r0, pb, db);
-                Oa = fma(co, pa, Oa);
-                Ob = fma(co, pb, Ob);
-                reinsch_step(u, r1, pa, da);
-                reinsch_step(u, r1, pb, db);
-            }
-            if (n < n1) {
-                Ea = fma(cb[n], pa, Ea);
-                Eb = fma(cb[n], pb, Eb);
-                reinsch_step(u, rcp[n], pa, da);
-                reinsch_step(u, rcp[n], pb, db);
-            }
-        } else {
-#pragma unroll 4
-            for (; n < n1; ++n) {
-                double r = rcp[n];
-                reinsch_step(u, r, pa, da);
-                reinsch_step(u, r, pb, db);
-            }
+        for (int n = n0; n < n1; ++n) {
+            double r = rcp[n];
+            reinsch_step(u, r, pa, da);
+            reinsch_step(u, r, pb, db);
         }
         if (act) {
             out[0] = pa;
             out[1] = da;
             out[2] = pb;
             out[3] = db;
-            out[4] = Ea;
-            out[5] = Eb;
-            out[6] = Oa;
-            out[7] = Ob;
         }
     }
 }
 
-// Linear data of a run of chunks acting on the start state s = (P, D):
-// end state T s and the even/odd sums eE . s, eO . s.
-struct ChunkMap {
-    double a, b, c, d;  // T = [[a, c], [b, d]]
-    double ea, eb, oa, ob;
-};
-
-// first x, then y
-__device__ __forceinline__ ChunkMap cmap_then(const ChunkMap& x, const ChunkMap& y) {
-    ChunkMap o;
-    o.a = y.a * x.a + y.c * x.b;
-    o.b = y.b * x.a + y.d * x.b;
-    o.c = y.a * x.c + y.c * x.d;
-    o.d = y.b * x.c + y.d * x.d;
-    o.ea = x.ea + y.ea * x.a + y.eb * x.b;
-    o.eb = x.eb + y.ea * x.c + y.eb * x.d;
-    o.oa = x.oa + y.oa * x.a + y.ob * x.b;
-    o.ob = x.ob + y.oa * x.c + y.ob * x.d;
-    return o;
+// Plan time: from the state at each chunk start (2 doubles per item), the
+// states every NEAR_SUB degrees inside the chunk (2 * NEAR_NSUB per item).
+// The recurrence may run past the segment's last degree; such states are
+// never weighted.
+__global__ __launch_bounds__(64) void k_near_substates(int N, NearParams NP, const int* __restrict__ wg_seg,
+                                                       const int* __restrict__ segoff,
+                                                       const double* __restrict__ rcp,
+                                                       const double* __restrict__ st1, double* __restrict__ st) {
+    const NearWG W = near_wg(NP, wg_seg, segoff, blockIdx.x);
+    const Seg S = NP.seg[W.seg];
+    const int nrows = S.jhi - S.jlo;
+    const int row = W.grp * 64 + threadIdx.x;
+    if (row >= nrows) return;
+    const int j = S.jlo + row;
+    const double pi = 3.141592653589793;
+    const double sn = sin(0.5 * (j + 0.5) * pi / N);
+    const double u = 2.0 * sn * sn;
+    const int id = S.item_off + W.ch * nrows + row;
+    double p = st1[2 * id], d = st1[2 * id + 1];
+    const int n0 = W.ch * NEAR_CHUNK;
+    for (int k = 0; k < NEAR_NSUB; ++k) {
+        st[(int64_t)id * 2 * NEAR_NSUB + 2 * k] = p;
+        st[(int64_t)id * 2 * NEAR_NSUB + 2 * k + 1] = d;
+        if (k + 1 < NEAR_NSUB)
+            for (int n = n0 + k * NEAR_SUB; n < n0 + (k + 1) * NEAR_SUB; ++n) reinsch_step(u, rcp[n], p, d);
+    }
 }
 
-__device__ __forceinline__ ChunkMap cmap_identity() { return {1, 0, 0, 1, 0, 0, 0, 0}; }
-
-__device__ __forceinline__ ChunkMap cmap_shfl_down(const ChunkMap& x, int d) {
-    ChunkMap o;
-    o.a = __shfl_down(x.a, d);
-    o.b = __shfl_down(x.b, d);
-    o.c = __shfl_down(x.c, d);
-    o.d = __shfl_down(x.d, d);
-    o.ea = __shfl_down(x.ea, d);
-    o.eb = __shfl_down(x.eb, d);
-    o.oa = __shfl_down(x.oa, d);
-    o.ob = __shfl_down(x.ob, d);
-    return o;
+// Forward near field from the plan's states: work-group = 64 consecutive
+// rows of one segment and one degree chunk [n0, n1); each lane runs the
+// NEAR_NSUB sub-chunks of its row as independent recurrences (from the
+// stored states) side by side and forms
+//   E = sum_{n even, n >= nd} c_n P_n(x_j),  O = sum_{n odd, n >= nd} c_n P_n(x_j)
+// over the chunk.  Chunks that end at or below nd have nothing to add.
+__global__ __launch_bounds__(64) void k_near_sums(int N, NearParams NP, const int* __restrict__ wg_seg,
+                                                  const int* __restrict__ segoff, const double* __restrict__ rcp,
+                                                  const double* __restrict__ st, const double* __restrict__ c,
+                                                  int64_t c_stride, double* __restrict__ sums, int64_t s_stride) {
+    const NearWG W = near_wg(NP, wg_seg, segoff, blockIdx.x);
+    const Seg S = NP.seg[W.seg];
+    const int n0 = W.ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
+    if (n1 <= NP.nd) return;
+    const int b = blockIdx.z;
+    const int nrows = S.jhi - S.jlo;
+    const int row = W.grp * 64 + threadIdx.x;
+    const bool act = row < nrows;
+    const int rr = act ? row : nrows - 1;
+    const int j = S.jlo + rr;
+    const double pi = 3.141592653589793;
+    const double sn = sin(0.5 * (j + 0.5) * pi / N);
+    const double u = 2.0 * sn * sn;
+    const int id = S.item_off + W.ch * nrows + rr;
+    // the chunk's 1/(n+1) and c_n (zero below nd and from n1 on) in LDS;
+    // the recurrences run the whole chunk (rcp covers n < N, a multiple of
+    // NEAR_CHUNK)
+    __shared__ double sr[NEAR_CHUNK], sc[NEAR_CHUNK];
+    const double* cb = c + b * c_stride;
+    {
+        // all loads first, then the LDS stores
+        double lr[NEAR_CHUNK / 64], lc[NEAR_CHUNK / 64];
+#pragma unroll
+        for (int q = 0; q < NEAR_CHUNK / 64; ++q) {
+            const int n = n0 + (int)threadIdx.x + 64 * q;
+            lr[q] = rcp[n];
+            lc[q] = (n >= NP.nd && n < n1) ? cb[n] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NEAR_CHUNK / 64; ++q) {
+            sr[threadIdx.x + 64 * q] = lr[q];
+            sc[threadIdx.x + 64 * q] = lc[q];
+        }
+    }
+    __syncthreads();
+    double p[NEAR_NSUB], d[NEAR_NSUB], E[NEAR_NSUB], O[NEAR_NSUB];
+#pragma unroll
+    for (int k = 0; k < NEAR_NSUB; ++k) {
+        p[k] = st[(int64_t)id * 2 * NEAR_NSUB + 2 * k];
+        d[k] = st[(int64_t)id * 2 * NEAR_NSUB + 2 * k + 1];
+        E[k] = O[k] = 0;
+    }
+    // sub-chunk starts are even, so even offsets are even degrees
+#pragma unroll 2
+    for (int i = 0; i < NEAR_SUB; i += 2) {
+#pragma unroll
+        for (int k = 0; k < NEAR_NSUB; ++k) {
+            const int o = k * NEAR_SUB + i;
+            E[k] = fma(sc[o], p[k], E[k]);
+            reinsch_step(u, sr[o], p[k], d[k]);
+            O[k] = fma(sc[o + 1], p[k], O[k]);
+            reinsch_step(u, sr[o + 1], p[k], d[k]);
+        }
+    }
+    if (act) {
+        double Es = 0, Os = 0;
+#pragma unroll
+        for (int k = 0; k < NEAR_NSUB; ++k) {
+            Es += E[k];
+            Os += O[k];
+        }
+        double* o = sums + b * s_stride + 2 * (int64_t)id;
+        o[0] = Es;
+        o[1] = Os;
+    }
 }
 
-__device__ __forceinline__ ChunkMap cmap_load(const double* q) {
-    return {q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7]};
+// One wave per endpoint row j < jnear: sums the chunk results of the row;
+// near[j] = E + O (row j), near[jnear + j] = E - O (row N-1-j), since
+// P_n(-x) = (-1)^n P_n(x).
+__global__ __launch_bounds__(64) void k_near_reduce(NearParams NP, const double* __restrict__ sums,
+                                                    int64_t s_stride, double* __restrict__ near,
+                                                    int64_t near_stride) {
+    const int j = blockIdx.x;
+    const int b = blockIdx.z;
+    const int lane = threadIdx.x;
+    double E = 0, O = 0;
+    int sgi = -1;
+    for (int q = 0; q < NP.nseg; ++q)
+        if (j >= NP.seg[q].jlo && j < NP.seg[q].jhi) sgi = q;
+    if (sgi >= 0) {
+        const Seg S = NP.seg[sgi];
+        const int nrows = S.jhi - S.jlo;
+        const int id0 = S.item_off + (j - S.jlo);
+        const double* sb = sums + b * s_stride;
+        for (int ch = NP.nd / NEAR_CHUNK + lane; ch < S.nchunk; ch += 64) {
+            const double* o = sb + 2 * (int64_t)(id0 + ch * nrows);
+            E += o[0];
+            O += o[1];
+        }
+    }
+    for (int k = 32; k >= 1; k >>= 1) {
+        E += __shfl_xor(E, k);
+        O += __shfl_xor(O, k);
+    }
+    if (lane == 0) {
+        double* nb = near + b * near_stride;
+        nb[j] = E + O;
+        nb[NP.jnear + j] = E - O;
+    }
 }
 
 __device__ __forceinline__ int near_seg_of(const NearParams& NP, int j) {
@@ -776,49 +830,6 @@ __device__ __forceinline__ int near_seg_of(const NearParams& NP, int j) {
     for (int s = 0; s < NP.nseg; ++s)
         if (j >= NP.seg[s].jlo && j < NP.seg[s].jhi) sgi = s;
     return sgi;
-}
-
-// One wave per row j < jnear: every lane chains a contiguous run of chunks
-// 1.., the runs are chained in order by a shuffle tree, and lane 0 applies
-// the result to the state after chunk 0.  near[j] = E + O (row j),
-// near[jnear + j] = E - O (row N-1-j).
-__global__ __launch_bounds__(64) void k_near_combine(NearParams NP, const double* __restrict__ items,
-                                                     int64_t it_stride, double* __restrict__ near,
-                                                     int64_t near_stride) {
-    const int j = blockIdx.x;
-    const int b = blockIdx.z;
-    const int lane = threadIdx.x;
-    const double* it = items + b * it_stride;
-    double* nb = near + b * near_stride;
-    const int sgi = near_seg_of(NP, j);
-    if (sgi < 0) {
-        if (lane == 0) {
-            nb[j] = 0;
-            nb[NP.jnear + j] = 0;
-        }
-        return;
-    }
-    const Seg S = NP.seg[sgi];
-    const int nrows = S.jhi - S.jlo;
-    const int64_t base = (int64_t)(S.item_off + (j - S.jlo)) * 8;
-    const int64_t step = (int64_t)nrows * 8;
-    const int rest = S.nchunk - 1;
-    const int per = (rest + 63) / 64;
-    const int c0 = 1 + lane * per, c1 = min(S.nchunk, c0 + per);
-    ChunkMap x = cmap_identity();
-    for (int ch = c0; ch < c1; ++ch) x = cmap_then(x, cmap_load(it + base + ch * step));
-    for (int d = 1; d < 64; d *= 2) {
-        ChunkMap y = cmap_shfl_down(x, d);
-        if ((lane & (2 * d - 1)) == 0) x = cmap_then(x, y);
-    }
-    if (lane == 0) {
-        const double* o = it + base;
-        double P = o[0], D = o[1];
-        double E = o[2] + x.ea * P + x.eb * D;
-        double O = o[3] + x.oa * P + x.ob * D;
-        nb[j] = E + O;
-        nb[NP.jnear + j] = E - O;
-    }
 }
 
 // ----------------------------------------------------------------- DCT-II --
@@ -1157,10 +1168,12 @@ __global__ __launch_bounds__(256) void k_dense_t(int nd, int chunk, const double
     // (n-k)/2 in [zm0, ...): n - k >= nb0 - (k0 + CH - 1); (n+k)/2 >= (nb0 + k0)/2
     const int zm0 = (nb0 - (k0 + DENSE_CH - 1)) >> 1;
     const int zp0 = (nb0 + k0) >> 1;
+#pragma unroll
     for (int i = threadIdx.x; i < DENSE_CH; i += 256) {
         int kk = k0 + i;
         sy[i] = (kk < k1) ? yb[kk] * ((kk == 0) ? 0.3183098861837907 : 0.6366197723675814) : 0.0;
     }
+#pragma unroll
     for (int i = threadIdx.x; i < DENSE_CH / 2 + 256; i += 256) {
         int zm = zm0 + i, zp = zp0 + i;
         slm[i] = (zm >= 0 && zm < nd) ? lam[zm] : 0.0;
@@ -1356,10 +1369,10 @@ __global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplx* _
         if (T.live(s)) ob[nn[s]] = acc[s];
 }
 
-// Transposed near field.  (1) k_near_items with c == null gives each
-// (row, chunk) transfer matrix; (2) k_tnear_scan chains them per row into the
-// state (P, D) at every chunk start; (3) k_tnear_accum reruns each chunk from
-// its true state for the 64 rows of one wave and sums over the rows
+// Chunk-start states (once per plan): k_near_items gives each (row, chunk)
+// transfer matrix and k_tnear_scan chains them per row into the state (P, D)
+// at every chunk start.  Transposed near field: k_tnear_accum reruns each
+// chunk from its true state for the 64 rows of one wave and sums over the rows
 //   out_n += P_n(x_j) (u_j + (-1)^n u_{N-1-j})
 // through an LDS tile, 32 degrees at a time; partial sums per row group.
 // One wave per row: states (P, D) at every chunk start.  Lane runs of chunks
@@ -1430,16 +1443,25 @@ __global__ __launch_bounds__(64) void k_tnear_scan(NearParams NP, const double* 
     }
 }
 
-constexpr int TN_STEPS = 32;
+constexpr int TN_STEPS = 16;             // degrees per LDS tile and chain
+constexpr int TN_CH = 2;                 // independent recurrences per lane
+constexpr int TN_LEN = NEAR_CHUNK / TN_CH;
 
+// Work-group = 64 rows of one segment and one degree chunk; each lane runs
+// its row over the chunk as TN_CH recurrences of TN_LEN degrees side by side
+// from the plan's states, the products P_n(x_j) w_j go through an LDS tile
+// and pairs of lanes sum a degree's column; partial sums per row group.
 __global__ __launch_bounds__(64) void k_tnear_accum(int N, NearParams NP, const int* __restrict__ wg_seg,
                                                     const int* __restrict__ segoff, const double* __restrict__ rcp,
                                                     const double* __restrict__ u, int64_t u_stride,
-                                                    const double* __restrict__ st, int64_t st_stride,
-                                                    double* __restrict__ part, int64_t part_stride) {
-    __shared__ double tile[TN_STEPS][64 + 1];
+                                                    const double* __restrict__ st, double* __restrict__ part,
+                                                    int64_t part_stride) {
+    __shared__ double tile[TN_CH][TN_STEPS][64 + 1];
+    __shared__ double sr[NEAR_CHUNK];
     const NearWG W = near_wg(NP, wg_seg, segoff, blockIdx.x);
     const Seg S = NP.seg[W.seg];
+    const int n0 = W.ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
+    if (n1 <= NP.nd) return;  // degrees below nd come from the exact low block
     const int b = blockIdx.z;
     const int nrows = S.jhi - S.jlo;
     const int row = W.grp * 64 + threadIdx.x;
@@ -1447,40 +1469,51 @@ __global__ __launch_bounds__(64) void k_tnear_accum(int N, NearParams NP, const 
     const int j = S.jlo + (act ? row : 0);
     const int rg_global = segoff[2 * W.seg + 1] + W.grp;
     const double* ub = u + b * u_stride;
-    const double* so = st + b * st_stride;
     const double uj = act ? ub[j] : 0.0, um = act ? ub[N - 1 - j] : 0.0;
     const double pi = 3.141592653589793;
-    double sn = sin(0.5 * (j + 0.5) * pi / N);
+    const double sn = sin(0.5 * (j + 0.5) * pi / N);
     const double uu = 2.0 * sn * sn;
     const int id = S.item_off + W.ch * nrows + (act ? row : 0);
-    double p = act ? so[2 * id] : 0.0, d = act ? so[2 * id + 1] : 0.0;
-    const int n0 = W.ch * NEAR_CHUNK, n1 = min(S.nend, n0 + NEAR_CHUNK);
+    double p[TN_CH], d[TN_CH];
+#pragma unroll
+    for (int k = 0; k < TN_CH; ++k) {
+        const int q = k * (NEAR_NSUB / TN_CH);
+        p[k] = st[(int64_t)id * 2 * NEAR_NSUB + 2 * q];
+        d[k] = st[(int64_t)id * 2 * NEAR_NSUB + 2 * q + 1];
+    }
+    {
+        double lr[NEAR_CHUNK / 64];
+#pragma unroll
+        for (int q = 0; q < NEAR_CHUNK / 64; ++q) lr[q] = rcp[n0 + (int)threadIdx.x + 64 * q];
+#pragma unroll
+        for (int q = 0; q < NEAR_CHUNK / 64; ++q) sr[threadIdx.x + 64 * q] = lr[q];
+    }
+    __syncthreads();
     double* pb = part + b * part_stride + (int64_t)rg_global * N;
     const double we = uj + um, wo = uj - um;  // weights of even / odd degrees
-    for (int nb0 = n0; nb0 < n1; nb0 += TN_STEPS) {
-        const int cnt = min(TN_STEPS, n1 - nb0);
-        if (cnt == TN_STEPS) {
+    // reduction lanes: column c = lane % 32 = (chain, degree), rows of half h = lane / 32
+    const int cidx = threadIdx.x & 31, kc = cidx / TN_STEPS, col = cidx % TN_STEPS, half = threadIdx.x >> 5;
+    for (int nb = 0; nb < TN_LEN; nb += TN_STEPS) {
 #pragma unroll
-            for (int i = 0; i < TN_STEPS; i += 2) {
-                tile[i][threadIdx.x] = p * we;
-                reinsch_step(uu, rcp[nb0 + i], p, d);
-                tile[i + 1][threadIdx.x] = p * wo;
-                reinsch_step(uu, rcp[nb0 + i + 1], p, d);
-            }
-        } else {
-            for (int i = 0; i < cnt; ++i) {
-                tile[i][threadIdx.x] = p * (((nb0 + i) & 1) ? wo : we);
-                reinsch_step(uu, rcp[nb0 + i], p, d);
+        for (int i = 0; i < TN_STEPS; i += 2) {
+#pragma unroll
+            for (int k = 0; k < TN_CH; ++k) {
+                const int o = k * TN_LEN + nb + i;
+                tile[k][i][threadIdx.x] = p[k] * we;
+                reinsch_step(uu, sr[o], p[k], d[k]);
+                tile[k][i + 1][threadIdx.x] = p[k] * wo;
+                reinsch_step(uu, sr[o + 1], p[k], d[k]);
             }
         }
         __syncthreads();
-        // two lanes per degree column, 32 rows each
-        const int col = threadIdx.x >> 1, half = threadIdx.x & 1;
+        // lanes c and c + 32 sum column c over 32 rows each (consecutive
+        // lanes read consecutive columns: distinct banks with the odd row pitch)
         double s = 0;
 #pragma unroll 8
-        for (int r = 0; r < 32; ++r) s += tile[col][half * 32 + r];
-        s += __shfl_xor(s, 1, 2);
-        if (half == 0 && col < cnt) pb[nb0 + col] = s;
+        for (int r = 0; r < 32; ++r) s += tile[kc][col][half * 32 + r];
+        s += __shfl_xor(s, 32);
+        const int n = n0 + kc * TN_LEN + nb + col;
+        if (half == 0 && n < n1) pb[n] = s;
         __syncthreads();
     }
 }
@@ -1619,10 +1652,36 @@ void work_carve(const Plan& p, int64_t nb, void* base, Work& w) {
     w.schat = (int64_t)(al256(p.ws_chat) / sizeof(double));
     w.vec = (double*)take(p.ws_vec);
     w.svec = (int64_t)(al256(p.ws_vec) / sizeof(double));
-    w.states = (double*)take(p.ws_states);
-    w.sstates = (int64_t)(al256(p.ws_states) / sizeof(double));
     w.part = (double*)take(p.ws_part);
     w.spart = (int64_t)(al256(p.ws_part) / sizeof(double));
+}
+
+// Near-field chunk-start states of the plan: the transfer data of every
+// (row, chunk) item (k_near_items without an input), then a per-row scan.
+hipError_t plan_prepare(Plan& p) {
+    if (p.sub) {
+        hipError_t e = plan_prepare(*p.sub);
+        if (e != hipSuccess) return e;
+    }
+    const NearParams& NP = p.near;
+    if (NP.nitems <= 0) return hipSuccess;
+    const int N = (int)p.N;
+    // items: 8 doubles per item, later reused for the chunk-start states
+    double* items = nullptr;
+    hipError_t e = hipMalloc(&items, (size_t)NP.nitems * 10 * sizeof(double));
+    if (e != hipSuccess) return e;
+    double* st1 = items + (size_t)NP.nitems * 8;
+    e = hipMalloc(&p.d_near_st, (size_t)NP.nitems * 2 * NEAR_NSUB * sizeof(double));
+    if (e == hipSuccess) {
+        k_near_items<<<dim3(p.tn_wg, 1, 1), 64, 0, 0>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, items);
+        k_tnear_scan<<<dim3(NP.jnear, 1, 1), 64, 0, 0>>>(NP, items, 0, st1, 0);
+        k_near_substates<<<dim3(p.tn_wg, 1, 1), 64, 0, 0>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, st1,
+                                                           p.d_near_st);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    hipError_t e2 = hipFree(items);
+    return (e != hipSuccess) ? e : e2;
 }
 
 hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, hipStream_t s) {
@@ -1689,13 +1748,13 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
     // near field
     const NearParams& NP = p.near;
     if (NP.nitems > 0)
-        traced("k_near_items", s, [&] {
-            k_near_items<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, s>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, c,
-                                                                      cs, w.items, w.sitems);
+        traced("k_near_sums", s, [&] {
+            k_near_sums<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, s>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp,
+                                                                     p.d_near_st, c, cs, w.items, w.sitems);
         });
     if (NP.jnear > 0)
-        traced("k_near_combine", s, [&] {
-            k_near_combine<<<dim3(NP.jnear, 1, (unsigned)nb), 64, 0, s>>>(NP, w.items, w.sitems, w.near, w.snear);
+        traced("k_near_reduce", s, [&] {
+            k_near_reduce<<<dim3(NP.jnear, 1, (unsigned)nb), 64, 0, s>>>(NP, w.items, w.sitems, w.near, w.snear);
         });
     // far field
     const FarParams& F = p.far;
@@ -1764,16 +1823,9 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     });
     // transposed near field
     if (NP.nitems > 0) {
-        traced("k_near_items", s, [&] {
-            k_near_items<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, s>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp,
-                                                                      nullptr, 0, w.items, w.sitems);
-        });
-        traced("k_tnear_scan", s, [&] {
-            k_tnear_scan<<<dim3(NP.jnear, 1, (unsigned)nb), 64, 0, s>>>(NP, w.items, w.sitems, w.states, w.sstates);
-        });
         traced("k_tnear_accum", s, [&] {
             k_tnear_accum<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, s>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, u,
-                                                                       w.svec, w.states, w.sstates, w.part, w.spart);
+                                                                       w.svec, p.d_near_st, w.part, w.spart);
         });
     }
     traced("k_idlt_final", s, [&] {

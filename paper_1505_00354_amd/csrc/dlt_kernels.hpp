@@ -14,14 +14,13 @@ namespace dlt {
 struct Work {
     cplx* X;          // far-field / DCT / Taylor DFT intermediates
     double* v;        // far-field partial values (tgB slabs)
-    double* items;    // near-field chunk results
+    double* items;    // near-field (even, odd) degree sums per (row, chunk)
     double* near;     // near-field values of the endpoint rows
     double* dense;    // dense-block partials (+ reduced slab at the end)
     double* chat;     // Chebyshev coefficients
     double* vec;      // spare length-N vector
-    double* states;   // near-field states at chunk starts (inverse)
     double* part;     // near-field per-row-group sums over degrees (inverse)
-    int64_t sX, sv, sitems, snear, sdense, schat, svec, sstates, spart;  // per-instance strides (elements)
+    int64_t sX, sv, sitems, snear, sdense, schat, svec, spart;  // per-instance strides (elements)
 };
 size_t work_bytes(const Plan& p, int64_t nb);
 void work_carve(const Plan& p, int64_t nb, void* base, Work& w);
@@ -30,6 +29,9 @@ void work_carve(const Plan& p, int64_t nb, void* base, Work& w);
 // `scratch` holds kb * NODE_PARTS_MAX * 8 doubles
 constexpr int NODE_PARTS_MAX = 64;
 hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, hipStream_t s);
+// Input-independent plan data formed on the device once per plan (and its
+// sub-plans): the near-field states at every chunk start.  Synchronous.
+hipError_t plan_prepare(Plan& p);
 // chat = M c for nb instances (batch strides cs, hs in elements)
 hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, double* chat, int64_t hs, Work& w,
                         hipStream_t s);

@@ -295,16 +295,15 @@ int plan_build(int64_t N, Plan& p) {
     p.ws_X = (size_t)nX * N * sizeof(cplx);
     if (p.sub && p.ws_X < p.sub->ws_per_inst) p.ws_X = p.sub->ws_per_inst;  // the sub-run borrows this slab
     p.ws_v = (size_t)p.tgB * N * sizeof(double);
-    p.ws_items = (size_t)Nr.nitems * 8 * sizeof(double);
+    p.ws_items = (size_t)Nr.nitems * 2 * sizeof(double);
     p.ws_near = (size_t)2 * std::max(Nr.jnear, 1) * sizeof(double);
     p.ws_dense = (size_t)(p.dense_nchunk + 1) * p.nd * sizeof(double);
     p.ws_chat = (size_t)N * sizeof(double);
     p.ws_vec = (size_t)N * sizeof(double);
-    p.ws_states = (size_t)Nr.nitems * 2 * sizeof(double);
     p.ws_part = (size_t)p.tn_nrg * N * sizeof(double);
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     p.ws_per_inst = al(p.ws_X) + al(p.ws_v) + al(p.ws_items) + al(p.ws_near) + al(p.ws_dense) +
-                    al(p.ws_chat) + al(p.ws_vec) + al(p.ws_states) + al(p.ws_part);
+                    al(p.ws_chat) + al(p.ws_vec) + al(p.ws_part);
     p.ws_shared = 3 * al((size_t)N * sizeof(double));  // theta, w, dtheta
     return 0;
 }
@@ -316,7 +315,7 @@ void plan_free(Plan& p) {
         p.sub = nullptr;
     }
     void* ptrs[] = {p.d_twN1,  p.d_twN2,     p.d_twHi,      p.d_twLo,     p.d_lam,
-                    p.d_rcp,   p.d_guess,    p.d_tn_wgseg,  p.d_tn_segoff, p.d_tn_rgnend};
+                    p.d_rcp,   p.d_guess,    p.d_tn_wgseg,  p.d_tn_segoff, p.d_tn_rgnend, p.d_near_st};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();

@@ -15,7 +15,9 @@ constexpr int MAX_TERMS = 64;   // far-field (block, m) pairs
 constexpr int MAX_BLOCKS = 8;
 constexpr int MAX_NODE_M = 24;  // terms of the Stieltjes series for nodes
 constexpr int MAX_SEGS = 8;     // near-field row segments
-constexpr int NEAR_CHUNK = 1024;
+constexpr int NEAR_CHUNK = 512;
+constexpr int NEAR_SUB = 128;   // near-field states are kept every NEAR_SUB degrees
+constexpr int NEAR_NSUB = NEAR_CHUNK / NEAR_SUB;
 constexpr int64_t MAX_N = int64_t(1) << 20;
 constexpr int DENSE_MAX = 8192;         // largest low-degree block done by the dense matrix
 constexpr int64_t RECURSE_FROM = 1 << 17;  // from this N on the low block is N/16, recursively
@@ -86,9 +88,13 @@ struct Plan {
     int* d_tn_segoff = nullptr;
     int* d_tn_rgnend = nullptr;
     int tn_wg = 0, tn_nrg = 0;
+    // near-field recurrence state (P_n, D_n) at the start of every (row,
+    // chunk) item and every NEAR_SUB degrees inside it: it does not depend on
+    // the input, so it is formed once per plan (2 * NEAR_NSUB doubles per item)
+    double* d_near_st = nullptr;
     // workspace sizes per transform instance (bytes)
     size_t ws_X = 0, ws_v = 0, ws_items = 0, ws_near = 0, ws_dense = 0, ws_chat = 0, ws_vec = 0;
-    size_t ws_states = 0, ws_part = 0;
+    size_t ws_part = 0;
     size_t ws_per_inst = 0, ws_shared = 0;
     int tgA = 1;       // far-field pass-A term groups (blocks split the terms)
     int tgB = 1;       // far-field pass-B term groups (partial outputs summed later)
