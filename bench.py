@@ -16,6 +16,9 @@ Prints one JSON line; diagnostics go to stderr.  Options:
   --batch B     instances per step (default 1)
   --cpu-sample K  output indices the CPU oracle evaluates for cpu_baseline
   --no-cpu      skip the CPU baseline
+  --copy-probe BYTES  only run one plain copy kernel (read BYTES, write
+                BYTES) and exit: the reference for calibrating the HBM byte
+                counters FETCH_SIZE / WRITE_SIZE
 """
 import argparse
 import json
@@ -31,25 +34,77 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name, N, info, nb):
-    """Algorithmic HBM bytes of one launch of `name` (inputs read once,
-    outputs and DFT intermediates written once): the per-kernel byte model."""
-    T, Q, G = info["far_terms"], info["L"] // 2, info["tgB"]
-    per = {
+def kernel_model(name, N, info):
+    """Algorithmic work of one launch of `name` at transform size N for one
+    instance: ("hbm", bytes) -- inputs read once, outputs and DFT
+    intermediates written once -- or ("alu", FP64 flops).  None if the kernel
+    has no model."""
+    T, Q = info["far_terms"], info["L"] // 2
+    GA, GB = info["tgA"], info["tgB"]
+    hbm = {
         "k_far_passA": 8 * N + 16 * N * T,
-        "k_far_passB": 16 * N * T + 8 * N * G,
+        "k_far_passB": 16 * N * T + 8 * N * GB,
         "k_tfar_passA": 8 * N + 16 * N * T,
-        "k_tfar_passB": 16 * N * T + 8 * N,
+        "k_tfar_passB": 16 * N * T + 8 * N * GB,
         "k_ndct_passA": 8 * N + 16 * N * Q,
         "k_ndct_passB": 16 * N * Q + 16 * N,
         "k_tndct_passA": 24 * N + 16 * N * Q,
         "k_tndct_passB": 16 * N * Q + 8 * N,
-        "k_dct2_passA": 8 * N * G + 16 * N,
+        "k_dct2_passA": 8 * N * GB + 16 * N,
         "k_dct2_passB": 16 * N + 8 * N,
         "k_dct3_passA": 8 * N + 16 * N,
         "k_dct3_passB": 16 * N + 8 * N,
     }
-    return per.get(name, None) if name in per else None, nb
+    # near field: per (row, degree >= nd) one recurrence step (3 FMA + 1 add
+    # = 7 flops) and one weighted accumulation (FMA, or multiply + add)
+    alu = {
+        "k_near_sums": 9 * info["near_work"],
+        "k_tnear_accum": 9 * info["near_work"],
+    }
+    if name in hbm:
+        return "hbm", hbm[name]
+    if name in alu:
+        return "alu", alu[name]
+    return None
+
+
+def source_digest():
+    """Digest of the kernel sources, to tell whether stored counter data
+    still describe the kernels that run."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in ("dlt_kernels.hip", "dlt_common.hpp", "dlt_plan.cpp", "dlt_plan.hpp"):
+        with open(os.path.join(here, "paper_1505_00354_amd", "csrc", f), "rb") as fh:
+            data = fh.read()
+        if f == "dlt_kernels.hip":  # device code only: the launch code may change freely
+            cut = data.find(b"// ================================================================ host ====")
+            data = data[:cut] if cut >= 0 else data
+        h.update(data)
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` ("name/N") from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when absent or
+    taken on other kernel sources."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "hbm_traffic_dlt_step_n1048576.md")
+    if not os.path.exists(path):
+        return None
+    digest, rows = None, {}
+    for line in open(path):
+        if line.startswith("source digest:"):
+            digest = line.split(":", 1)[1].strip().strip("`")
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0].startswith("k_"):
+            try:
+                rows[cells[0]] = float(cells[4])
+            except ValueError:
+                pass
+    if digest != source_digest() or kernel not in rows:
+        return None
+    return rows[kernel]
 
 
 def main():
@@ -61,6 +116,7 @@ def main():
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py: this build runs on a single GPU; --gpus must be 1 "
@@ -72,9 +128,18 @@ def main():
     import paper_1505_00354_amd as pk
     from paper_1505_00354_amd import workloads as wl
 
-    N, B = args.n, args.batch
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        a = torch.ones(args.copy_probe // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 1.0, out=b)  # one elementwise kernel: reads and writes BYTES
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe} bytes read and written")
+        return
+
+    N, B = args.n, args.batch
     pk.lib()
     info = pk.plan_info(N)
     log("plan", info)
@@ -116,20 +181,41 @@ def main():
     for k, (ms, cnt) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
         log(f"  {k:26s} {ms / cnt * 1000:10.2f} us/launch  x{cnt:4d}  {100 * ms / tot:5.1f}%")
 
-    # roofline of the dominant kernel with a byte model
-    roof = None
+    # roofline of the dominant kernel (largest share of the step): its
+    # algorithmic bytes or flops per launch over its average launch time
+    infos = {}
+
+    def model(key):
+        name, n = key.split("/")
+        n = int(n)
+        if n not in infos:
+            infos[n] = pk.plan_info(n)
+        return kernel_model(name, n, infos[n])
+
     ranked = sorted(kern.items(), key=lambda kv: -kv[1][0])
-    for name, (ms, cnt) in ranked:
-        by, _ = kernel_bytes(name, N, info, B)
-        if by is not None:
-            avg_s = ms / cnt / 1000.0
-            ach = by * B / avg_s / 1e9
-            roof = {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                    "bytes_per_launch": by * B, "avg_launch_us": round(avg_s * 1e6, 2),
-                    "share_of_step": round(ms / tot, 3)}
-            break
+    per_kernel = {}
+    for key, (ms, cnt) in ranked:
+        m = model(key)
+        if m is None:
+            continue
+        bound, work = m
+        avg_s = ms / cnt / 1000.0
+        if bound == "hbm":
+            ach, peak, unit = work * B / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            ach, peak, unit = work * B / avg_s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+        per_kernel[key] = {"bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit,
+                           "frac": round(ach / peak, 4), "work_per_launch": work * B,
+                           "avg_launch_us": round(avg_s * 1e6, 2), "share_of_step": round(ms / tot, 4)}
     dominant = ranked[0][0] if ranked else None
+    roof = None
+    if dominant in per_kernel:
+        r = per_kernel[dominant]
+        traffic = stored_traffic(dominant) if B == 1 else None
+        roof = {"kernel": dominant, "bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"],
+                "unit": r["unit"], "frac": r["frac"], "traffic": traffic,
+                ("bytes_per_launch" if r["bound"] == "hbm" else "flops_per_launch"): r["work_per_launch"],
+                "avg_launch_us": r["avg_launch_us"], "share_of_step": r["share_of_step"]}
 
     out = {
         "metric": "DLT transforms/s + HBM GB/s at N=2^16..2^20, plain FP64 vs batched/FP32-bulk",
@@ -149,6 +235,7 @@ def main():
                    "inputs": "c_n=N(0,1)/(n+1) seed 2; IDLT f_k=N(0,1) seed 4; chat_n=N(0,1)/(n+1) seed 3"},
         "dominant_kernel": dominant,
         "roofline": roof,
+        "roofline_by_kernel": per_kernel,
         "kernel_us": {k: round(v[0] / v[1] * 1000, 2) for k, v in kern.items()},
     }
 

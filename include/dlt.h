@@ -24,9 +24,12 @@
  *   - batch == 0 is a no-op returning DLT_OK.
  *   - Supported sizes: N a power of two with 1 <= N <= DLT_MAX_N (other N
  *     return DLT_ERR_UNSUPPORTED).
- *   - The library keeps per-N plans (twiddle and coefficient tables) and a
- *     per-stream workspace; both are created on first use and live until
- *     dlt_release() or process exit.
+ *   - The library keeps per-N plans (twiddle and coefficient tables, and the
+ *     input-independent near-field recurrence states, formed on the device)
+ *     and a per-stream workspace; both are created on first use and live
+ *     until dlt_release() or process exit.  The first call for a given N on
+ *     a device builds its plan and synchronises the device (so it must not
+ *     be made inside stream capture); later calls never synchronise.
  *   - FP64 arithmetic throughout.  Accuracy against the direct O(N^2)
  *     definitions: max_k |f_k - f_k^exact| <= 5e-14 * sum_n |c_n| (DLT, NDCT);
  *     max_n |c_n - c_n^exact| <= 5e-14 * (n+1/2) sum_k w_k |f_k| (IDLT).
@@ -82,7 +85,9 @@ const char* dlt_status_string(int status);
  * per end, N1, N2, pass-A tile columns, pass-B tile rows, pass-B term groups,
  * transposed-near work-groups, transposed-near row groups, near-field
  * recurrence steps (rows x degrees, one end), boundary nodes, workspace bytes
- * per instance.  Returns the number of fields available or a status < 0. */
+ * per instance, near-field steps that carry weights (rows x degrees >= nd),
+ * pass-A term groups.  Returns the number of fields available or a
+ * status < 0. */
 int dlt_plan_query(int64_t N, int64_t* out, int max_fields);
 
 /* Kernel trace.  While enabled, every kernel the library launches is

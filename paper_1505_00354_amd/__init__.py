@@ -135,7 +135,8 @@ def release():
 
 
 PLAN_FIELDS = ("L", "nd", "far_terms", "far_blocks", "far_mmax", "near_items", "near_rows", "N1", "N2",
-               "colsA", "rowsB", "tgB", "tnear_wg", "tnear_rg", "near_steps", "boundary_nodes", "ws_bytes")
+               "colsA", "rowsB", "tgB", "tnear_wg", "tnear_rg", "near_steps", "boundary_nodes", "ws_bytes",
+               "near_work", "tgA")
 
 
 def plan_info(N):

@@ -241,12 +241,15 @@ int dlt_plan_query(int64_t N, int64_t* out, int max_fields) {
     if (!out || max_fields < 0) return DLT_ERR_INVALID_ARG;
     Plan* p;
     if ((rc = get_plan(N, &p))) return rc;
-    int64_t steps = 0;
-    for (int s = 0; s < p->near.nseg; ++s)
-        steps += (int64_t)(p->near.seg[s].jhi - p->near.seg[s].jlo) * p->near.seg[s].nend;
+    int64_t steps = 0, work = 0;
+    for (int s = 0; s < p->near.nseg; ++s) {
+        const int64_t rows = p->near.seg[s].jhi - p->near.seg[s].jlo;
+        steps += rows * p->near.seg[s].nend;
+        work += rows * std::max<int64_t>(0, p->near.seg[s].nend - p->nd);
+    }
     const int64_t v[] = {p->L, p->nd, p->far.nterm, p->far.nblk, p->far.Mmax, p->near.nitems, p->near.jnear,
                          p->geo.N1, p->geo.N2, p->geo.colsA, p->geo.rowsB, p->tgB, p->tn_wg, p->tn_nrg, steps,
-                         p->nodes.kb, (int64_t)p->ws_per_inst};
+                         p->nodes.kb, (int64_t)p->ws_per_inst, work, p->tgA};
     int n = (int)(sizeof(v) / sizeof(v[0]));
     for (int i = 0; i < n && i < max_fields; ++i) out[i] = v[i];
     return n;
