@@ -26,6 +26,7 @@ struct Cache {
         size_t bytes = 0;
     };
     std::map<std::pair<int, hipStream_t>, WS> ws;  // (device, stream)
+    std::map<std::pair<int, hipStream_t>, Lanes> lanes;  // (device, stream): side streams, events
 };
 
 Cache& cache() {
@@ -96,6 +97,28 @@ int get_ws(hipStream_t s, size_t bytes, void** out) {
     return DLT_OK;
 }
 
+// Side streams (default priority, non-blocking) and events for calls on
+// stream s of the current device, created on first use.
+int get_lanes(hipStream_t s, Lanes* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto key = std::make_pair(dev, s);
+    auto it = c.lanes.find(key);
+    if (it == c.lanes.end()) {
+        Lanes l;
+        for (int i = 0; i < LANE_SIDES; ++i)
+            if (hipStreamCreateWithFlags(&l.side[i], hipStreamNonBlocking) != hipSuccess) return DLT_ERR_HIP;
+        for (int i = 0; i < LANE_EVENTS; ++i)
+            if (hipEventCreateWithFlags(&l.ev[i], hipEventDisableTiming) != hipSuccess) return DLT_ERR_HIP;
+        it = c.lanes.emplace(key, l).first;
+    }
+    *out = it->second;
+    out->s = s;
+    return DLT_OK;
+}
+
 // node arrays shared by a call: [theta | w | dtheta] after the per-instance part
 struct CallWS {
     Work work;
@@ -104,6 +127,7 @@ struct CallWS {
     double* dth;
     double* nscr;  // node scratch
     int64_t nb;  // instances per slice
+    Lanes lanes;
 };
 
 int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
@@ -122,7 +146,7 @@ int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
     cw.nscr = (double*)((char*)base + 3 * vecb);
     work_carve(p, nb, (char*)base + shared, cw.work);
     cw.nb = nb;
-    return DLT_OK;
+    return get_lanes(s, &cw.lanes);
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? DLT_OK : DLT_ERR_HIP; }
@@ -154,7 +178,7 @@ int leg_nodes_weights(int64_t N, int64_t batch, double* theta, double* w, double
     if ((rc = get_plan(N, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, 0, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, cw.nscr, stream)))) return rc;
+    if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, cw.nscr, cw.lanes)))) return rc;
     for (int64_t b = 1; b < batch; ++b) {
         size_t vb = (size_t)N * sizeof(double);
         if (theta && hipMemcpyAsync(theta + b * N, theta, vb, hipMemcpyDeviceToDevice, stream)) return DLT_ERR_HIP;
@@ -176,7 +200,7 @@ int leg2cheb(int64_t N, int64_t batch, const double* c, double* chat, hipStream_
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
         int64_t nb = std::min(cw.nb, batch - b0);
-        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat + b0 * N, N, cw.work, stream)))) return rc;
+        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat + b0 * N, N, cw.work, cw.lanes)))) return rc;
     }
     return DLT_OK;
 }
@@ -190,10 +214,10 @@ int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, h
     if ((rc = get_plan(N, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, stream)))) return rc;
+    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, cw.lanes)))) return rc;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
         int64_t nb = std::min(cw.nb, batch - b0);
-        if ((rc = hip_status(run_ndct(*p, nb, chat + b0 * N, N, cw.dth, f + b0 * N, cw.work, stream)))) return rc;
+        if ((rc = hip_status(run_ndct(*p, nb, chat + b0 * N, N, cw.dth, f + b0 * N, cw.work, cw.lanes)))) return rc;
     }
     return DLT_OK;
 }
@@ -207,13 +231,21 @@ int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_
     if ((rc = get_plan(N, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, stream)))) return rc;
+    // the nodes are needed only by the Taylor evaluation: they run on the
+    // first side stream beside the conversion of the first slice
+    const Lanes& L = cw.lanes;
+    const hipStream_t sn = L.aux(0);
+    if (hipEventRecord(L.ev[10], stream) != hipSuccess || hipStreamWaitEvent(sn, L.ev[10], 0) != hipSuccess)
+        return DLT_ERR_HIP;
+    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, L.on(sn))))) return rc;
+    if (hipEventRecord(L.ev[11], sn) != hipSuccess) return DLT_ERR_HIP;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
         int64_t nb = std::min(cw.nb, batch - b0);
         // Chebyshev coefficients of the slice, stride N, in the workspace
         double* chat = cw.work.chat;
-        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat, cw.work.schat, cw.work, stream)))) return rc;
-        if ((rc = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, f + b0 * N, cw.work, stream)))) return rc;
+        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat, cw.work.schat, cw.work, L)))) return rc;
+        if (b0 == 0 && hipStreamWaitEvent(stream, L.ev[11], 0) != hipSuccess) return DLT_ERR_HIP;
+        if ((rc = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, f + b0 * N, cw.work, L)))) return rc;
     }
     return DLT_OK;
 }
@@ -227,10 +259,10 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
     if ((rc = get_plan(N, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, stream)))) return rc;
+    if ((rc = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes)))) return rc;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
         int64_t nb = std::min(cw.nb, batch - b0);
-        if ((rc = hip_status(run_inverse(*p, nb, f + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, stream)))) return rc;
+        if ((rc = hip_status(run_inverse(*p, nb, f + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, cw.lanes)))) return rc;
     }
     return DLT_OK;
 }
@@ -286,6 +318,13 @@ int dlt_release(void) {
     for (auto& kv : c.ws)
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     c.ws.clear();
+    for (auto& kv : c.lanes) {
+        for (int i = 0; i < LANE_SIDES; ++i)
+            if (kv.second.side[i]) (void)hipStreamDestroy(kv.second.side[i]);
+        for (int i = 0; i < LANE_EVENTS; ++i)
+            if (kv.second.ev[i]) (void)hipEventDestroy(kv.second.ev[i]);
+    }
+    c.lanes.clear();
     return DLT_OK;
 }
 

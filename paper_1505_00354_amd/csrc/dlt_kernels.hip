@@ -1654,6 +1654,7 @@ void work_carve(const Plan& p, int64_t nb, void* base, Work& w) {
     w.svec = (int64_t)(al256(p.ws_vec) / sizeof(double));
     w.part = (double*)take(p.ws_part);
     w.spart = (int64_t)(al256(p.ws_part) / sizeof(double));
+    w.sub = (char*)take(p.ws_sub);
 }
 
 // Near-field chunk-start states of the plan: the transfer data of every
@@ -1684,77 +1685,102 @@ hipError_t plan_prepare(Plan& p) {
     return (e != hipSuccess) ? e : e2;
 }
 
-hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, hipStream_t s) {
+// Makes `to` wait for everything enqueued on `from` so far.
+static hipError_t dep(hipStream_t from, hipStream_t to, hipEvent_t e) {
+    if (from == to) return hipSuccess;
+    hipError_t r = hipEventRecord(e, from);
+    if (r != hipSuccess) return r;
+    return hipStreamWaitEvent(to, e, 0);
+}
+
+#define DLT_TRY(x)                            \
+    do {                                      \
+        hipError_t e_ = (x);                  \
+        if (e_ != hipSuccess) return e_;      \
+    } while (0)
+
+// Boundary nodes (few, recurrence-based) and interior nodes (one thread
+// each) are independent: with side streams they run side by side.
+hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, const Lanes& L) {
     trace_n = p.N;
     const NodeParams& P = p.nodes;
+    const hipStream_t s = L.s, sb = L.aux(0);
     int nh = (P.N + 1) / 2;
+    int ni = nh - P.kb;
     if (P.kb > 0) {
+        DLT_TRY(dep(s, sb, L.ev[0]));
         if (P.newton_b == 0 && P.N >= (1 << 16)) {
             int parts = P.N >> 16;
             if (parts > NODE_PARTS_MAX) parts = NODE_PARTS_MAX;
-            traced("k_nodes_bpart", s, [&] {
-                k_nodes_bpart<<<dim3(P.kb, parts), 1024, 0, s>>>(P, p.d_guess, parts, scratch);
+            traced("k_nodes_bpart", sb, [&] {
+                k_nodes_bpart<<<dim3(P.kb, parts), 1024, 0, sb>>>(P, p.d_guess, parts, scratch);
             });
-            traced("k_nodes_bfin", s, [&] {
-                k_nodes_bfin<<<P.kb, 64, 0, s>>>(P, p.d_guess, parts, scratch, theta, w, dth);
+            traced("k_nodes_bfin", sb, [&] {
+                k_nodes_bfin<<<P.kb, 64, 0, sb>>>(P, p.d_guess, parts, scratch, theta, w, dth);
             });
         } else {
             int T = 64;
             while (T < 1024 && T * 256 < P.N) T *= 2;
             size_t shm = (size_t)7 * T * sizeof(double);
-            traced("k_nodes_boundary", s, [&] { k_nodes_boundary<<<P.kb, T, shm, s>>>(P, p.d_guess, theta, w, dth); });
+            traced("k_nodes_boundary", sb, [&] { k_nodes_boundary<<<P.kb, T, shm, sb>>>(P, p.d_guess, theta, w, dth); });
         }
     }
-    int ni = nh - P.kb;
     if (ni > 0)
         traced("k_nodes_interior", s, [&] { k_nodes_interior<<<(ni + 255) / 256, 256, 0, s>>>(P, theta, w, dth); });
+    if (P.kb > 0) DLT_TRY(dep(sb, s, L.ev[1]));
     return hipGetLastError();
 }
 
-// Scratch of a sub-plan's run, carved from the parent's DFT-intermediate slab
-// (not yet in use when the low-degree block is computed).
+// Scratch of a sub-plan's run: the parent's sub region.
 static Work sub_work(const Plan& sub, int64_t nb, const Work& w) {
     Work sw;
-    work_carve(sub, nb, (void*)w.X, sw);
+    work_carve(sub, nb, (void*)w.sub, sw);
     return sw;
 }
 
 // chat = M c.  Columns n < nd: the exact conversion (dense for nd <= 8192,
 // otherwise the same algorithm at size nd, recursively); columns n >= nd:
 // values on the Chebyshev grid from the near and far fields, then DCT-II.
+// With side streams the low block and the near field run beside the far
+// field and join before the DCT-II passes that read them.
 hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, double* chat, int64_t hs, Work& w,
-                        hipStream_t s) {
+                        const Lanes& L) {
     trace_n = p.N;
     const int N = (int)p.N;
     const int nd = p.nd;
     const Geo& g = p.geo;
+    const hipStream_t s = L.s;
+    const bool last = (N <= nd);  // the dense block is the whole conversion
+    const hipStream_t sl = last ? s : L.aux(1), sn = L.aux(2);
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
+    // low block
+    DLT_TRY(dep(s, sl, L.ev[2]));
     if (!p.sub) {
         dim3 gd(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb);
-        traced("k_dense", s, [&] { k_dense<<<gd, 256, 0, s>>>(N, nd, p.dense_chunk, p.d_lam, c, cs, w.dense, w.sdense); });
-        double* dst = (N <= nd) ? chat : dense_out;
-        int64_t ds = (N <= nd) ? hs : w.sdense;
-        traced("k_dense_reduce", s, [&] {
-            k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
-                                                                               w.dense, w.sdense, dst, ds);
+        traced("k_dense", sl, [&] { k_dense<<<gd, 256, 0, sl>>>(N, nd, p.dense_chunk, p.d_lam, c, cs, w.dense, w.sdense); });
+        double* dst = last ? chat : dense_out;
+        int64_t ds = last ? hs : w.sdense;
+        traced("k_dense_reduce", sl, [&] {
+            k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, sl>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                                w.dense, w.sdense, dst, ds);
         });
-        if (N <= nd) return hipGetLastError();
+        if (last) return hipGetLastError();
     } else {
         Work sw = sub_work(*p.sub, nb, w);
-        hipError_t e = run_leg2cheb(*p.sub, nb, c, cs, dense_out, w.sdense, sw, s);
+        DLT_TRY(run_leg2cheb(*p.sub, nb, c, cs, dense_out, w.sdense, sw, L.on(sl)));
         trace_n = p.N;
-        if (e != hipSuccess) return e;
     }
     // near field
     const NearParams& NP = p.near;
+    DLT_TRY(dep(s, sn, L.ev[3]));
     if (NP.nitems > 0)
-        traced("k_near_sums", s, [&] {
-            k_near_sums<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, s>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp,
-                                                                     p.d_near_st, c, cs, w.items, w.sitems);
+        traced("k_near_sums", sn, [&] {
+            k_near_sums<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, sn>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp,
+                                                                      p.d_near_st, c, cs, w.items, w.sitems);
         });
     if (NP.jnear > 0)
-        traced("k_near_reduce", s, [&] {
-            k_near_reduce<<<dim3(NP.jnear, 1, (unsigned)nb), 64, 0, s>>>(NP, w.items, w.sitems, w.near, w.snear);
+        traced("k_near_reduce", sn, [&] {
+            k_near_reduce<<<dim3(NP.jnear, 1, (unsigned)nb), 64, 0, sn>>>(NP, w.items, w.sitems, w.near, w.snear);
         });
     // far field
     const FarParams& F = p.far;
@@ -1765,10 +1791,12 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
         LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_far_passB, (dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb)), FFT_THREADS, 0, s, g, F, p.tgB, w.X, w.sX, w.v, w.sv);
     });
     // values on the grid -> coefficients
+    DLT_TRY(dep(sn, s, L.ev[4]));
     traced("k_dct2_passA", s, [&] {
         LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_dct2_passA, (dim3(g.N1 / g.colsA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, p.tgB, w.v, w.sv, w.near, w.snear,
                                                                                 NP.jnear, w.X, w.sX);
     });
+    DLT_TRY(dep(sl, s, L.ev[5]));
     traced("k_dct2_passB", s, [&] {
         LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_dct2_passB, (dim3(g.N2 / g.rowsB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, nd, w.X, w.sX, dense_out, w.sdense,
                                                                                 chat, hs);
@@ -1778,32 +1806,37 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
 
 // out = M^T y (times n + 1/2 when `half`): rows n < nd from the exact
 // conversion (dense or recursive), rows n >= nd as P^T C D_eps y on the grid.
+// With side streams the low block runs beside everything else and the
+// transposed near field beside the transposed far field.
 hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys, double* out, int64_t os, int half,
-                          Work& w, hipStream_t s) {
+                          Work& w, const Lanes& L) {
     trace_n = p.N;
     const int N = (int)p.N;
     const int nd = p.nd;
     const Geo& g = p.geo;
     const int tilesA = g.N1 / g.colsA;
+    const hipStream_t s = L.s;
+    const bool last = (N <= nd);
+    const hipStream_t sl = last ? s : L.aux(1), sn = L.aux(2);
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
+    DLT_TRY(dep(s, sl, L.ev[6]));
     if (!p.sub) {
-        traced("k_dense_t", s, [&] {
-            k_dense_t<<<dim3(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb), 256, 0, s>>>(nd, p.dense_chunk, p.d_lam, y,
-                                                                                         ys, w.dense, w.sdense);
+        traced("k_dense_t", sl, [&] {
+            k_dense_t<<<dim3(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb), 256, 0, sl>>>(nd, p.dense_chunk, p.d_lam,
+                                                                                          y, ys, w.dense, w.sdense);
         });
-        double* dst = (N <= nd) ? out : dense_out;
-        int64_t ds = (N <= nd) ? os : w.sdense;
-        int hf = (N <= nd) ? half : 0;
-        traced("k_dense_t_reduce", s, [&] {
-            k_dense_t_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(nd, p.dense_nchunk, p.dense_chunk,
-                                                                                 w.dense, w.sdense, dst, ds, hf);
+        double* dst = last ? out : dense_out;
+        int64_t ds = last ? os : w.sdense;
+        int hf = last ? half : 0;
+        traced("k_dense_t_reduce", sl, [&] {
+            k_dense_t_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, sl>>>(nd, p.dense_nchunk, p.dense_chunk,
+                                                                                  w.dense, w.sdense, dst, ds, hf);
         });
-        if (N <= nd) return hipGetLastError();
+        if (last) return hipGetLastError();
     } else {
         Work sw = sub_work(*p.sub, nb, w);
-        hipError_t e = run_leg2cheb_t(*p.sub, nb, y, ys, dense_out, w.sdense, 0, sw, s);
+        DLT_TRY(run_leg2cheb_t(*p.sub, nb, y, ys, dense_out, w.sdense, 0, sw, L.on(sl)));
         trace_n = p.N;
-        if (e != hipSuccess) return e;
     }
     const NearParams& NP = p.near;
     // u = C D_eps y on the grid
@@ -1814,6 +1847,14 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     traced("k_dct3_passB", s, [&] {
         LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_dct3_passB, (dim3(g.N2 / g.rowsB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, w.X, w.sX, u, w.svec);
     });
+    // transposed near field
+    DLT_TRY(dep(s, sn, L.ev[7]));
+    if (NP.nitems > 0) {
+        traced("k_tnear_accum", sn, [&] {
+            k_tnear_accum<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, sn>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, u,
+                                                                        w.svec, p.d_near_st, w.part, w.spart);
+        });
+    }
     // transposed far field
     traced("k_tfar_passA", s, [&] {
         LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_tfar_passA, (dim3(tilesA, p.tgA, (unsigned)nb)), FFT_THREADS, 0, s, g, p.far, p.tgA, u, w.svec, w.X, w.sX);
@@ -1821,13 +1862,8 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     traced("k_tfar_passB", s, [&] {
         LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_tfar_passB, (dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb)), FFT_THREADS, 0, s, g, p.far, p.tgB, w.X, w.sX, w.v, w.sv);
     });
-    // transposed near field
-    if (NP.nitems > 0) {
-        traced("k_tnear_accum", s, [&] {
-            k_tnear_accum<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, s>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, u,
-                                                                       w.svec, p.d_near_st, w.part, w.spart);
-        });
-    }
+    DLT_TRY(dep(sn, s, L.ev[8]));
+    DLT_TRY(dep(sl, s, L.ev[9]));
     traced("k_idlt_final", s, [&] {
         k_idlt_final<<<dim3((N + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(N, nd, (NP.nitems > 0) ? p.tn_nrg : 0,
                                                                           p.d_tn_rgnend, dense_out, w.sdense, p.tgB, w.v,
@@ -1837,9 +1873,10 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
 }
 
 hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
-                    Work& w, hipStream_t s) {
+                    Work& w, const Lanes& L) {
     trace_n = p.N;
     const Geo& g = p.geo;
+    const hipStream_t s = L.s;
     const int Q = p.L / 2;
     const int tilesA = g.N1 / g.colsA;
     // small transforms: split the Taylor pairs over blocks for parallelism
@@ -1850,10 +1887,11 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
 }
 
 hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double* wts, const double* dth,
-                       double* c, Work& w, hipStream_t s) {
+                       double* c, Work& w, const Lanes& L) {
     trace_n = p.N;
     const int N = (int)p.N;
     const Geo& g = p.geo;
+    const hipStream_t s = L.s;
     const int Q = p.L / 2;
     const int tilesA = g.N1 / g.colsA;
     int QG = (tilesA * nb >= 256) ? 1 : Q;
@@ -1865,8 +1903,7 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
     traced("k_tndct_passB", s, [&] {
         LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_tndct_passB, (dim3(tilesB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, Q, w.X, w.sX, y, w.schat);
     });
-    hipError_t e = run_leg2cheb_t(p, nb, y, w.schat, c, N, 1, w, s);
-    return e;
+    return run_leg2cheb_t(p, nb, y, w.schat, c, N, 1, w, L);
 }
 
 }  // namespace dlt

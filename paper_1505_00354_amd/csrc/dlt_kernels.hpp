@@ -20,7 +20,27 @@ struct Work {
     double* chat;     // Chebyshev coefficients
     double* vec;      // spare length-N vector
     double* part;     // near-field per-row-group sums over degrees (inverse)
+    char* sub;        // scratch of the low-degree sub-run (nb instances of the sub-plan)
     int64_t sX, sv, sitems, snear, sdense, schat, svec, spart;  // per-instance strides (elements)
+};
+
+// Streams of one call: work is enqueued on `s`; independent parts may go to
+// the side streams (default priority) and are joined back through events.
+// With no side streams everything runs on `s`.
+constexpr int LANE_SIDES = 3;
+constexpr int LANE_EVENTS = 16;
+struct Lanes {
+    hipStream_t s = nullptr;
+    hipStream_t side[LANE_SIDES] = {};
+    hipEvent_t ev[LANE_EVENTS] = {};
+    bool forks() const { return side[0] != nullptr; }
+    hipStream_t aux(int i) const { return side[i] ? side[i] : s; }
+    // the same call on one stream only (used for nested runs)
+    Lanes on(hipStream_t st) const {
+        Lanes l;
+        l.s = st;
+        return l;
+    }
 };
 size_t work_bytes(const Plan& p, int64_t nb);
 void work_carve(const Plan& p, int64_t nb, void* base, Work& w);
@@ -28,23 +48,23 @@ void work_carve(const Plan& p, int64_t nb, void* base, Work& w);
 // theta, w, dtheta (any may be null) for the plan's N
 // `scratch` holds kb * NODE_PARTS_MAX * 8 doubles
 constexpr int NODE_PARTS_MAX = 64;
-hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, hipStream_t s);
+hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, const Lanes& L);
 // Input-independent plan data formed on the device once per plan (and its
 // sub-plans): the near-field states at every chunk start.  Synchronous.
 hipError_t plan_prepare(Plan& p);
 // chat = M c for nb instances (batch strides cs, hs in elements)
 hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, double* chat, int64_t hs, Work& w,
-                        hipStream_t s);
+                        const Lanes& L);
 // out = M^T y (times n + 1/2 when half != 0)
 hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys, double* out, int64_t os, int half,
-                          Work& w, hipStream_t s);
+                          Work& w, const Lanes& L);
 // f = sum_n chat_n cos(n theta^leg), dth = theta^leg - theta^cheb1
 hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
-                    Work& w, hipStream_t s);
+                    Work& w, const Lanes& L);
 
 // c = D_s M^T T^T D_w f (inverse transform), wts/dth from the nodes
 hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double* wts, const double* dth,
-                       double* c, Work& w, hipStream_t s);
+                       double* c, Work& w, const Lanes& L);
 
 // kernel trace (events around every launch while enabled)
 bool trace_on();

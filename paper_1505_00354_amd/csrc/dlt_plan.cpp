@@ -293,7 +293,8 @@ int plan_build(int64_t N, Plan& p) {
         p.tgB = std::min({nt, 4, std::max(1, (768 + tilesB - 1) / tilesB)});
     }
     p.ws_X = (size_t)nX * N * sizeof(cplx);
-    if (p.sub && p.ws_X < p.sub->ws_per_inst) p.ws_X = p.sub->ws_per_inst;  // the sub-run borrows this slab
+    // the low-degree sub-run has its own region: it runs beside the far field
+    p.ws_sub = p.sub ? p.sub->ws_per_inst : 0;
     p.ws_v = (size_t)p.tgB * N * sizeof(double);
     p.ws_items = (size_t)Nr.nitems * 2 * sizeof(double);
     p.ws_near = (size_t)2 * std::max(Nr.jnear, 1) * sizeof(double);
@@ -303,7 +304,7 @@ int plan_build(int64_t N, Plan& p) {
     p.ws_part = (size_t)p.tn_nrg * N * sizeof(double);
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     p.ws_per_inst = al(p.ws_X) + al(p.ws_v) + al(p.ws_items) + al(p.ws_near) + al(p.ws_dense) +
-                    al(p.ws_chat) + al(p.ws_vec) + al(p.ws_part);
+                    al(p.ws_chat) + al(p.ws_vec) + al(p.ws_part) + al(p.ws_sub);
     p.ws_shared = 3 * al((size_t)N * sizeof(double));  // theta, w, dtheta
     return 0;
 }

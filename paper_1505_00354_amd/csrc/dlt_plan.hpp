@@ -94,7 +94,7 @@ struct Plan {
     double* d_near_st = nullptr;
     // workspace sizes per transform instance (bytes)
     size_t ws_X = 0, ws_v = 0, ws_items = 0, ws_near = 0, ws_dense = 0, ws_chat = 0, ws_vec = 0;
-    size_t ws_part = 0;
+    size_t ws_part = 0, ws_sub = 0;
     size_t ws_per_inst = 0, ws_shared = 0;
     int tgA = 1;       // far-field pass-A term groups (blocks split the terms)
     int tgB = 1;       // far-field pass-B term groups (partial outputs summed later)
