@@ -16,6 +16,12 @@ Prints one JSON line; diagnostics go to stderr.  Options:
   --batch B     instances per step (default 1)
   --cpu-sample K  output indices the CPU oracle evaluates for cpu_baseline
   --no-cpu      skip the CPU baseline
+  --prec P      arithmetic of the headline run: fp64 (default), fp32bulk
+                (FP32 bulk transforms, 5e-6 budget) or fp64relaxed (FP64 with
+                the 5e-6 parameters)
+  --no-modes    skip the short runs of the other modes (reported under
+                "modes": step time, speedup at equal stated accuracy,
+                FP32-bulk at batch 64, error against the oracle)
   --copy-probe BYTES  only run one plain copy kernel (read BYTES, write
                 BYTES) and exit: the reference for calibrating the HBM byte
                 counters FETCH_SIZE / WRITE_SIZE
@@ -34,11 +40,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_model(name, N, info):
+def kernel_model(name, N, info, f32=False, bulk=False):
     """Algorithmic work of one launch of `name` at transform size N for one
     instance: ("hbm", bytes) -- inputs read once, outputs and DFT
     intermediates written once -- or ("alu", FP64 flops).  None if the kernel
-    has no model."""
+    has no model.  f32: an FP32 launch of the FP32-bulk mode (complex
+    intermediates of 8 bytes; its Taylor launches cover pairs 1..Q-1); bulk:
+    an FP64 launch of that mode (its Taylor pass A covers pair 0 only)."""
     T, Q = info["far_terms"], info["L"] // 2
     GA, GB = info["tgA"], info["tgB"]
     hbm = {
@@ -61,6 +69,20 @@ def kernel_model(name, N, info):
         "k_near_sums": 9 * info["near_work"],
         "k_tnear_accum": 9 * info["near_work"],
     }
+    if f32:
+        hbm = {
+            "k_far_passA": 8 * N + 8 * N * T,
+            "k_far_passB": 8 * N * T + 8 * N * GB,
+            "k_tfar_passA": 8 * N + 8 * N * T,
+            "k_tfar_passB": 8 * N * T + 8 * N * GB,
+            "k_ndct_passA": 8 * N + 8 * N * (Q - 1),
+            "k_ndct_passB": 16 * N + 8 * N * (Q - 1) + 16 * N,
+            "k_tndct_passA": 24 * N + 8 * N * (Q - 1),
+            "k_tndct_passB": 16 * N + 8 * N * (Q - 1) + 8 * N,
+        }
+    elif bulk:
+        hbm["k_ndct_passA"] = 8 * N + 16 * N
+        hbm["k_tndct_passA"] = 24 * N + 16 * N
     if name in hbm:
         return "hbm", hbm[name]
     if name in alu:
@@ -117,6 +139,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32bulk", "fp64relaxed"])
+    ap.add_argument("--no-modes", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py: this build runs on a single GPU; --gpus must be 1 "
@@ -141,8 +165,9 @@ def main():
 
     N, B = args.n, args.batch
     pk.lib()
-    info = pk.plan_info(N)
-    log("plan", info)
+    prec = args.prec
+    info = pk.plan_info(N, prec)
+    log("plan", prec, info)
     c = torch.from_numpy(wl.coeffs_algebraic(N, 2, batch=B)).to(dev)
     fin = torch.from_numpy(wl.values_normal(N, 4, batch=B)).to(dev)
     chat = torch.from_numpy(wl.coeffs_algebraic(N, 3, batch=B)).to(dev)
@@ -150,19 +175,29 @@ def main():
     c2 = torch.empty_like(c)
     g = torch.empty_like(c)
 
-    def step():
-        pk.dlt_forward(c, out=f)
-        pk.dlt_inverse(fin, out=c2)
-        pk.cheb_eval_leggrid(chat, out=g)
+    def step(mode=prec, c=c, fin=fin, chat=chat, f=f, c2=c2, g=g):
+        pk.dlt_forward(c, out=f, prec=mode)
+        pk.dlt_inverse(fin, out=c2, prec=mode)
+        pk.cheb_eval_leggrid(chat, out=g, prec=mode)
+
+    def timed(mode, steps, **kw):
+        for _ in range(2):
+            step(mode, **kw)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            step(mode, **kw)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
     # timed region: K steps bracketed by synchronisations and events on the
-    # current stream; the kernel trace records per-launch events on the same
-    # stream throughout
-    pk.trace_enable(True)
+    # current stream (this gives `value`)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -172,11 +207,24 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    pk.trace_enable(False)
-    kern = pk.trace_collect()
     ms_step = e0.elapsed_time(e1) / args.steps
     value = 3 * B * 1000.0 / ms_step
     log(f"ms/step {ms_step:.4f} (wall {1000 * wall / args.steps:.4f})")
+    # the same K steps again with the library's kernel trace on: HIP events
+    # around every launch, on the stream it is launched on.  The events hold
+    # each launch until the previous one has finished, so this region runs
+    # slower; it gives the per-kernel launch times only.
+    pk.trace_enable(True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    pk.trace_enable(False)
+    kern = pk.trace_collect()
+    ms_traced = e0.elapsed_time(e1) / args.steps
+    log(f"ms/step with the kernel trace {ms_traced:.4f}")
     tot = sum(v[0] for v in kern.values())
     for k, (ms, cnt) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
         log(f"  {k:26s} {ms / cnt * 1000:10.2f} us/launch  x{cnt:4d}  {100 * ms / tot:5.1f}%")
@@ -189,8 +237,9 @@ def main():
         name, n = key.split("/")
         n = int(n)
         if n not in infos:
-            infos[n] = pk.plan_info(n)
-        return kernel_model(name, n, infos[n])
+            infos[n] = pk.plan_info(n, prec)
+        return kernel_model(name.replace("_f32", ""), n, infos[n], f32=name.endswith("_f32"),
+                            bulk=(prec == "fp32bulk"))
 
     ranked = sorted(kern.items(), key=lambda kv: -kv[1][0])
     per_kernel = {}
@@ -225,19 +274,63 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 5),
+        "ms_per_step_traced": round(ms_traced, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec != "fp32bulk" else "f32-bulk+f64",
         "data": "synthetic",
-        "config": {"workload": f"single plain FP64 DLT + IDLT + Chebyshev-at-Legendre-grid evaluation, N={N}",
-                   "N": N, "batch": B, "transforms_per_step": 3 * B,
+        "config": {"workload": f"single {'plain FP64' if prec == 'fp64' else prec} DLT + IDLT + "
+                               f"Chebyshev-at-Legendre-grid evaluation, N={N}",
+                   "N": N, "batch": B, "prec": prec, "transforms_per_step": 3 * B,
                    "inputs": "c_n=N(0,1)/(n+1) seed 2; IDLT f_k=N(0,1) seed 4; chat_n=N(0,1)/(n+1) seed 3"},
         "dominant_kernel": dominant,
         "roofline": roof,
         "roofline_by_kernel": per_kernel,
         "kernel_us": {k: round(v[0] / v[1] * 1000, 2) for k, v in kern.items()},
     }
+
+    # the other arithmetic modes, briefly: step time and speedups at equal
+    # stated accuracy (FP32-bulk against FP64 with the same 5e-6 budget), and
+    # FP32-bulk forward + inverse at batch 64
+    modes = {}
+    if not args.no_modes:
+        for m in ("fp64", "fp32bulk", "fp64relaxed"):
+            ms = ms_step if m == prec else timed(m, args.steps)
+            pi = pk.plan_info(N, m)
+            modes[m] = {"ms_per_step": round(ms, 5), "transforms_per_s": round(3 * B * 1000.0 / ms, 2),
+                        "budget": 5e-14 if m == "fp64" else 5e-6, "L": pi["L"], "far_terms": pi["far_terms"],
+                        "near_rows": pi["near_rows"]}
+            log(f"mode {m}: {ms:.4f} ms/step")
+        modes["fp32bulk"]["speedup_vs_fp64"] = round(modes["fp64"]["ms_per_step"] / modes["fp32bulk"]["ms_per_step"], 3)
+        modes["fp32bulk"]["speedup_vs_fp64relaxed_equal_accuracy"] = round(
+            modes["fp64relaxed"]["ms_per_step"] / modes["fp32bulk"]["ms_per_step"], 3)
+        if B == 1:
+            BB = 64
+            cb = torch.from_numpy(np.concatenate([wl.coeffs_algebraic(N, 100 + i) for i in range(BB)])).to(dev)
+            fb, cb2 = torch.empty_like(cb), torch.empty_like(cb)
+            for m in ("fp32bulk", "fp64relaxed"):
+                def bstep():
+                    pk.dlt_forward(cb, out=fb, prec=m)
+                    pk.dlt_inverse(fb, out=cb2, prec=m)
+
+                bstep()
+                torch.cuda.synchronize()
+                a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(3):
+                    bstep()
+                b2.record()
+                torch.cuda.synchronize()
+                bms = a.elapsed_time(b2) / 3
+                modes[m + "_batch64"] = {"ms_per_step": round(bms, 3), "transforms_per_s": round(2 * BB * 1000.0 / bms, 2),
+                                         "step": "forward DLT + inverse DLT of 64 instances (c_n = N(0,1)/(n+1), "
+                                                 "seeds 100..163)"}
+                log(f"{m} batch 64: {bms:.3f} ms per forward+inverse")
+            modes["fp32bulk_batch64"]["speedup_vs_fp64relaxed_equal_accuracy"] = round(
+                modes["fp64relaxed_batch64"]["ms_per_step"] / modes["fp32bulk_batch64"]["ms_per_step"], 3)
+            del cb, fb, cb2
+        out["modes"] = modes
 
     if not args.no_cpu:
         import oracle
@@ -248,7 +341,7 @@ def main():
         cc = wl.coeffs_algebraic(N, 2)[0]
         t0 = time.perf_counter()
         th, _ = oracle.nodes(N, idx=idx)
-        oracle.dlt(cc, th)
+        fo = oracle.dlt(cc, th)
         dt = time.perf_counter() - t0
         per_transform = dt * N / len(idx)
         out["cpu_baseline"] = {
@@ -256,6 +349,14 @@ def main():
             "sample": f"forward DLT at N={N}: {len(idx)} of {N} outputs (Newton nodes + direct recurrence sum, "
                       f"FP64 build) in {dt:.2f} s, extrapolated x{N / len(idx):.0f} to one transform"}
         log("cpu baseline", out["cpu_baseline"])
+        # end-to-end error of every mode against the FP64 oracle on the same
+        # sampled outputs (the oracle with its own nodes), in ||.||_inf/||c||_1
+        if modes:
+            c1 = torch.from_numpy(cc[None, :]).to(dev)
+            for m in ("fp64", "fp32bulk", "fp64relaxed"):
+                fg = pk.dlt_forward(c1, prec=m).cpu().numpy()[0]
+                modes[m]["forward_error_vs_oracle"] = float(np.max(np.abs(fg[idx] - fo)) / np.sum(np.abs(cc)))
+            log("errors", {m: modes[m]["forward_error_vs_oracle"] for m in ("fp64", "fp32bulk", "fp64relaxed")})
     print(json.dumps(out), flush=True)
 
 

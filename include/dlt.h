@@ -76,6 +76,33 @@ int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_
 /* Inverse discrete Legendre transform, eq. (2) (Sec. 4). */
 int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream);
 
+/* Arithmetic of the _ex entry points (FP64 inputs and outputs in both).
+ *   DLT_PREC_FP64       the plain method in FP64 (what the entry points above
+ *                       use): accuracy as stated at the top of this file.
+ *   DLT_PREC_FP32_BULK  the far-field terms and the Taylor pairs l >= 2 are
+ *                       stored and transformed in FP32 (half the bytes of
+ *                       those intermediates), with the method's parameters
+ *                       chosen for a 5e-6 budget (fewer far-field terms,
+ *                       L = 10 Taylor terms); nodes, dtheta, the asymptotic
+ *                       amplitudes, the near field, the low-degree block, the
+ *                       l = 0, 1 Taylor pair, the Horner sums and the
+ *                       DCT-II/III stay FP64.  Accuracy: the norms above
+ *                       within 5e-6 instead of 5e-14.
+ *   DLT_PREC_FP64_RELAXED  FP64 arithmetic with the FP32-bulk parameters
+ *                       (same 5e-6 budget): the plain method at equal stated
+ *                       accuracy, for comparisons with DLT_PREC_FP32_BULK.
+ * Any other value returns DLT_ERR_INVALID_ARG. */
+#define DLT_PREC_FP64 0
+#define DLT_PREC_FP32_BULK 1
+#define DLT_PREC_FP64_RELAXED 2
+
+/* leg2cheb, cheb_eval_leggrid, dlt_forward and dlt_inverse with a precision
+ * mode (DLT_PREC_*); same arguments and behaviour otherwise. */
+int leg2cheb_ex(int64_t N, int64_t batch, const double* c, double* chat, int prec, hipStream_t stream);
+int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f, int prec, hipStream_t stream);
+int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int prec, hipStream_t stream);
+int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int prec, hipStream_t stream);
+
 /* Human-readable text of a status code (static storage). */
 const char* dlt_status_string(int status);
 
@@ -89,6 +116,8 @@ const char* dlt_status_string(int status);
  * pass-A term groups.  Returns the number of fields available or a
  * status < 0. */
 int dlt_plan_query(int64_t N, int64_t* out, int max_fields);
+/* The same for the plan of precision mode `prec` (DLT_PREC_*). */
+int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields);
 
 /* Kernel trace.  While enabled, every kernel the library launches is
  * bracketed by two hipEvents recorded on the launch stream (no host

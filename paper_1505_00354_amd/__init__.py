@@ -20,6 +20,10 @@ DLT_ERR_UNSUPPORTED = -2
 DLT_ERR_HIP = -3
 DLT_ERR_NOMEM = -4
 DLT_MAX_N = 1 << 20
+DLT_PREC_FP64 = 0
+DLT_PREC_FP32_BULK = 1
+DLT_PREC_FP64_RELAXED = 2
+PRECISIONS = {"fp64": DLT_PREC_FP64, "fp32bulk": DLT_PREC_FP32_BULK, "fp64relaxed": DLT_PREC_FP64_RELAXED}
 
 _lib = None
 
@@ -46,6 +50,11 @@ def lib():
         L.cheb_eval_leggrid.argtypes = [i64, i64, vp, vp, vp]
         L.dlt_forward.argtypes = [i64, i64, vp, vp, vp]
         L.dlt_inverse.argtypes = [i64, i64, vp, vp, vp]
+        for name in ("leg2cheb_ex", "cheb_eval_leggrid_ex", "dlt_forward_ex", "dlt_inverse_ex"):
+            getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_int, vp]
+            getattr(L, name).restype = ctypes.c_int
+        L.dlt_plan_query_ex.argtypes = [i64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        L.dlt_plan_query_ex.restype = ctypes.c_int
         L.dlt_status_string.argtypes = [ctypes.c_int]
         L.dlt_status_string.restype = ctypes.c_char_p
         L.dlt_release.argtypes = []
@@ -100,34 +109,45 @@ def leg_nodes_weights(N, device=None, batch=1, theta=True, w=True, dtheta=True):
     return t, ww, d
 
 
-def _unary(name, x, out):
+def _prec(prec):
+    if prec not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+    return PRECISIONS[prec]
+
+
+def _unary(name, x, out, prec="fp64"):
     import torch
 
     N, batch, out = _vec_args(x, out)
+    args = (N, batch, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()))
     with torch.cuda.device(x.device):
-        _check(getattr(lib(), name)(N, batch, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                    _stream(x.device)), name)
+        if prec == "fp64":
+            _check(getattr(lib(), name)(*args, _stream(x.device)), name)
+        else:
+            _check(getattr(lib(), name + "_ex")(*args, _prec(prec), _stream(x.device)), name + "_ex")
     return out
 
 
-def leg2cheb(c, out=None):
+def leg2cheb(c, out=None, prec="fp64"):
     """Chebyshev coefficients of sum_n c_n P_n (chat = M c)."""
-    return _unary("leg2cheb", c, out)
+    return _unary("leg2cheb", c, out, prec)
 
 
-def cheb_eval_leggrid(chat, out=None):
+def cheb_eval_leggrid(chat, out=None, prec="fp64"):
     """sum_n chat_n T_n at the N Legendre nodes."""
-    return _unary("cheb_eval_leggrid", chat, out)
+    return _unary("cheb_eval_leggrid", chat, out, prec)
 
 
-def dlt_forward(c, out=None):
-    """Discrete Legendre transform f_k = sum_n c_n P_n(x_k)."""
-    return _unary("dlt_forward", c, out)
+def dlt_forward(c, out=None, prec="fp64"):
+    """Discrete Legendre transform f_k = sum_n c_n P_n(x_k).  prec: "fp64",
+    "fp32bulk" (FP32 bulk transforms, 5e-6 budget) or "fp64relaxed" (FP64
+    with the 5e-6 parameters)."""
+    return _unary("dlt_forward", c, out, prec)
 
 
-def dlt_inverse(f, out=None):
+def dlt_inverse(f, out=None, prec="fp64"):
     """Inverse transform c_n = (n+1/2) sum_k w_k f_k P_n(x_k)."""
-    return _unary("dlt_inverse", f, out)
+    return _unary("dlt_inverse", f, out, prec)
 
 
 def release():
@@ -139,12 +159,12 @@ PLAN_FIELDS = ("L", "nd", "far_terms", "far_blocks", "far_mmax", "near_items", "
                "near_work", "tgA")
 
 
-def plan_info(N):
-    """The library's plan parameters for size N, as a dict."""
+def plan_info(N, prec="fp64"):
+    """The library's plan parameters for size N (and precision), as a dict."""
     buf = (ctypes.c_int64 * 32)()
-    n = lib().dlt_plan_query(N, buf, 32)
+    n = lib().dlt_plan_query_ex(N, _prec(prec), buf, 32)
     if n < 0:
-        _check(n, "dlt_plan_query")
+        _check(n, "dlt_plan_query_ex")
     return {k: int(buf[i]) for i, k in enumerate(PLAN_FIELDS[:n])}
 
 

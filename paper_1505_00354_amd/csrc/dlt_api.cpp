@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <utility>
 
 #include "../../include/dlt.h"
@@ -20,7 +21,7 @@ namespace {
 
 struct Cache {
     std::mutex mu;
-    std::map<std::pair<int, int64_t>, std::unique_ptr<Plan>> plans;  // (device, N)
+    std::map<std::tuple<int, int64_t, int>, std::unique_ptr<Plan>> plans;  // (device, N, precision)
     struct WS {
         void* ptr = nullptr;
         size_t bytes = 0;
@@ -49,19 +50,28 @@ bool overlap(const void* a, const void* b, size_t bytes) {
     return x < y + bytes && y < x + bytes;
 }
 
-int get_plan(int64_t N, Plan** out) {
+int check_prec(int prec) {
+    return (prec == DLT_PREC_FP64 || prec == DLT_PREC_FP32_BULK || prec == DLT_PREC_FP64_RELAXED) ? DLT_OK
+                                                                                                : DLT_ERR_INVALID_ARG;
+}
+
+int get_plan(int64_t N, int prec, Plan** out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
     Cache& c = cache();
     std::lock_guard<std::mutex> lk(c.mu);
-    auto key = std::make_pair(dev, N);
+    auto key = std::make_tuple(dev, N, prec);
     auto it = c.plans.find(key);
     if (it != c.plans.end()) {
         *out = it->second.get();
         return DLT_OK;
     }
     std::unique_ptr<Plan> p(new Plan());
-    int rc = plan_build(N, *p);
+    int rc = plan_build(N,
+                        prec == DLT_PREC_FP32_BULK   ? PREC_FP32_BULK
+                        : prec == DLT_PREC_FP64_RELAXED ? PREC_FP64_RELAXED
+                                                        : PREC_FP64,
+                        *p);
     if (rc == DLT_OK && plan_prepare(*p) != hipSuccess) rc = DLT_ERR_HIP;
     if (rc != DLT_OK) {
         plan_free(*p);
@@ -175,7 +185,7 @@ int leg_nodes_weights(int64_t N, int64_t batch, double* theta, double* w, double
         (w && dtheta && overlap(w, dtheta, bytes)))
         return DLT_ERR_INVALID_ARG;
     Plan* p;
-    if ((rc = get_plan(N, &p))) return rc;
+    if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, 0, stream, cw))) return rc;
     if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, cw.nscr, cw.lanes)))) return rc;
@@ -190,12 +200,17 @@ int leg_nodes_weights(int64_t N, int64_t batch, double* theta, double* w, double
 }
 
 int leg2cheb(int64_t N, int64_t batch, const double* c, double* chat, hipStream_t stream) {
+    return leg2cheb_ex(N, batch, c, chat, DLT_PREC_FP64, stream);
+}
+
+int leg2cheb_ex(int64_t N, int64_t batch, const double* c, double* chat, int prec, hipStream_t stream) {
     int rc = check_size(N, batch);
     if (rc) return rc;
+    if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
     if (!c || !chat || overlap(c, chat, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
     Plan* p;
-    if ((rc = get_plan(N, &p))) return rc;
+    if ((rc = get_plan(N, prec, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
@@ -206,12 +221,17 @@ int leg2cheb(int64_t N, int64_t batch, const double* c, double* chat, hipStream_
 }
 
 int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream) {
+    return cheb_eval_leggrid_ex(N, batch, chat, f, DLT_PREC_FP64, stream);
+}
+
+int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f, int prec, hipStream_t stream) {
     int rc = check_size(N, batch);
     if (rc) return rc;
+    if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
     if (!chat || !f || overlap(chat, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
     Plan* p;
-    if ((rc = get_plan(N, &p))) return rc;
+    if ((rc = get_plan(N, prec, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
     if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, cw.lanes)))) return rc;
@@ -223,12 +243,17 @@ int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, h
 }
 
 int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream) {
+    return dlt_forward_ex(N, batch, c, f, DLT_PREC_FP64, stream);
+}
+
+int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int prec, hipStream_t stream) {
     int rc = check_size(N, batch);
     if (rc) return rc;
+    if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
     if (!c || !f || overlap(c, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
     Plan* p;
-    if ((rc = get_plan(N, &p))) return rc;
+    if ((rc = get_plan(N, prec, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
     // the nodes are needed only by the Taylor evaluation: they run on the
@@ -251,12 +276,17 @@ int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_
 }
 
 int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
+    return dlt_inverse_ex(N, batch, f, c, DLT_PREC_FP64, stream);
+}
+
+int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int prec, hipStream_t stream) {
     int rc = check_size(N, batch);
     if (rc) return rc;
+    if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
     if (!f || !c || overlap(f, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
     Plan* p;
-    if ((rc = get_plan(N, &p))) return rc;
+    if ((rc = get_plan(N, prec, &p))) return rc;
     CallWS cw;
     if ((rc = setup_call(*p, batch, stream, cw))) return rc;
     if ((rc = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes)))) return rc;
@@ -267,12 +297,15 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
     return DLT_OK;
 }
 
-int dlt_plan_query(int64_t N, int64_t* out, int max_fields) {
+int dlt_plan_query(int64_t N, int64_t* out, int max_fields) { return dlt_plan_query_ex(N, DLT_PREC_FP64, out, max_fields); }
+
+int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields) {
     int rc = check_size(N, 1);
     if (rc) return rc;
+    if ((rc = check_prec(prec))) return rc;
     if (!out || max_fields < 0) return DLT_ERR_INVALID_ARG;
     Plan* p;
-    if ((rc = get_plan(N, &p))) return rc;
+    if ((rc = get_plan(N, prec, &p))) return rc;
     int64_t steps = 0, work = 0;
     for (int s = 0; s < p->near.nseg; ++s) {
         const int64_t rows = p->near.seg[s].jhi - p->near.seg[s].jlo;

@@ -7,19 +7,48 @@
 
 namespace dlt {
 
-struct cplx {
-    double re, im;
+// Complex value in precision R (double, or float for the FP32-bulk passes).
+template <class R>
+struct cplxT {
+    R re, im;
 };
+using cplx = cplxT<double>;
+using cplxf = cplxT<float>;
 
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+template <class R>
+__device__ __forceinline__ cplxT<R> cmul(cplxT<R> a, cplxT<R> b) {
     return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
 }
-__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
-__device__ __forceinline__ cplx cconj(cplx a) { return {a.re, -a.im}; }
+template <class R>
+__device__ __forceinline__ cplxT<R> cadd(cplxT<R> a, cplxT<R> b) {
+    return {a.re + b.re, a.im + b.im};
+}
+template <class R>
+__device__ __forceinline__ cplxT<R> csub(cplxT<R> a, cplxT<R> b) {
+    return {a.re - b.re, a.im - b.im};
+}
+template <class R>
+__device__ __forceinline__ cplxT<R> cscale(cplxT<R> a, R s) {
+    return {a.re * s, a.im * s};
+}
+template <class R>
+__device__ __forceinline__ cplxT<R> cconj(cplxT<R> a) {
+    return {a.re, -a.im};
+}
 // multiply by +i
-__device__ __forceinline__ cplx cmuli(cplx a) { return {-a.im, a.re}; }
+template <class R>
+__device__ __forceinline__ cplxT<R> cmuli(cplxT<R> a) {
+    return {-a.im, a.re};
+}
+// precision changes (round to nearest)
+template <class R>
+__device__ __forceinline__ cplxT<R> cto(cplx a) {
+    return {(R)a.re, (R)a.im};
+}
+template <class R>
+__device__ __forceinline__ cplx cwide(cplxT<R> a) {
+    return {(double)a.re, (double)a.im};
+}
 
 // Threads per block of every FFT-carrying kernel, and the number of complex
 // values in one block's tile (32 KiB).
@@ -45,14 +74,15 @@ __device__ __forceinline__ cplx tw2(const cplx* __restrict__ hi, const cplx* __r
 // thread of the (FFT_THREADS-wide) block must call it.  `tw` is the table of
 // e^{+2 pi i t/len}.  Each stage reads all of its inputs into registers, waits,
 // then writes, so one buffer suffices.  Used for lengths below 64 only.
-__device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restrict__ tw) {
+template <class R>
+__device__ inline void lds_fft(cplxT<R>* buf, int len, int cols, const cplxT<R>* __restrict__ tw) {
     const int tid = threadIdx.x;
     for (int p = 1; p < len;) {
         const int r = ((len / p) & 3) == 0 ? 4 : 2;
         const int nb = len / r;
         const int total = nb * cols;
         const int tstride = len / (p * r);
-        cplx v[FFT_VPT];
+        cplxT<R> v[FFT_VPT];
         int dst[FFT_VPT / 2];
         if (r == 4) {
 #pragma unroll
@@ -63,18 +93,18 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
                     int i = t - col * nb;
                     int k = i & (p - 1);
                     const int cb0 = col * len;
-                    cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)], x2 = buf[lp(cb0 + i + 2 * nb)],
+                    cplxT<R> x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)], x2 = buf[lp(cb0 + i + 2 * nb)],
                          x3 = buf[lp(cb0 + i + 3 * nb)];
                     if (p > 1) {
-                        cplx w1 = tw[k * tstride];
-                        cplx w2 = cmul(w1, w1);
-                        cplx w3 = cmul(w2, w1);
+                        cplxT<R> w1 = tw[k * tstride];
+                        cplxT<R> w2 = cmul(w1, w1);
+                        cplxT<R> w3 = cmul(w2, w1);
                         x1 = cmul(x1, w1);
                         x2 = cmul(x2, w2);
                         x3 = cmul(x3, w3);
                     }
-                    cplx s02 = cadd(x0, x2), d02 = csub(x0, x2);
-                    cplx s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
+                    cplxT<R> s02 = cadd(x0, x2), d02 = csub(x0, x2);
+                    cplxT<R> s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
                     v[4 * b + 0] = cadd(s02, s13);
                     v[4 * b + 1] = cadd(d02, d13);
                     v[4 * b + 2] = csub(s02, s13);
@@ -104,7 +134,7 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
                     int i = t - col * nb;
                     int k = i & (p - 1);
                     const int cb0 = col * len;
-                    cplx x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)];
+                    cplxT<R> x0 = buf[lp(cb0 + i)], x1 = buf[lp(cb0 + i + nb)];
                     if (p > 1) x1 = cmul(x1, tw[k * tstride]);
                     v[2 * b + 0] = cadd(x0, x1);
                     v[2 * b + 1] = csub(x0, x1);
@@ -130,15 +160,16 @@ __device__ inline void lds_fft(cplx* buf, int len, int cols, const cplx* __restr
 // In-place length-8 DFT with the + sign, a_q <- sum_j a_j e^{2 pi i j q/8}:
 // one radix-2 split (a_j +- a_{j+4}, the difference turned by e^{2 pi i j/8})
 // followed by two length-4 DFTs giving the even and the odd outputs.
-__device__ __forceinline__ void dft8(cplx* a) {
-    const double h = 0.70710678118654752440;  // 1/sqrt(2)
-    cplx b0 = cadd(a[0], a[4]), b1 = cadd(a[1], a[5]), b2 = cadd(a[2], a[6]), b3 = cadd(a[3], a[7]);
-    cplx c0 = csub(a[0], a[4]), c1 = csub(a[1], a[5]), c2 = csub(a[2], a[6]), c3 = csub(a[3], a[7]);
+template <class R>
+__device__ __forceinline__ void dft8(cplxT<R>* a) {
+    const R h = (R)0.70710678118654752440;  // 1/sqrt(2)
+    cplxT<R> b0 = cadd(a[0], a[4]), b1 = cadd(a[1], a[5]), b2 = cadd(a[2], a[6]), b3 = cadd(a[3], a[7]);
+    cplxT<R> c0 = csub(a[0], a[4]), c1 = csub(a[1], a[5]), c2 = csub(a[2], a[6]), c3 = csub(a[3], a[7]);
     c1 = {(c1.re - c1.im) * h, (c1.re + c1.im) * h};     // * e^{i pi/4}
     c2 = cmuli(c2);                                       // * e^{i pi/2}
     c3 = {-(c3.re + c3.im) * h, (c3.re - c3.im) * h};    // * e^{3 i pi/4}
-    cplx s02 = cadd(b0, b2), d02 = csub(b0, b2), s13 = cadd(b1, b3), d13 = cmuli(csub(b1, b3));
-    cplx t02 = cadd(c0, c2), e02 = csub(c0, c2), t13 = cadd(c1, c3), e13 = cmuli(csub(c1, c3));
+    cplxT<R> s02 = cadd(b0, b2), d02 = csub(b0, b2), s13 = cadd(b1, b3), d13 = cmuli(csub(b1, b3));
+    cplxT<R> t02 = cadd(c0, c2), e02 = csub(c0, c2), t13 = cadd(c1, c3), e13 = cmuli(csub(c1, c3));
     a[0] = cadd(s02, s13);
     a[2] = cadd(d02, d13);
     a[4] = csub(s02, s13);
@@ -192,8 +223,9 @@ struct Tile<0> {
 
 // Multiplies a[1..7] by w^1..w^7, w = tw[t] (e^{2 pi i t/L}); the powers up to
 // 4 come from the table (indices below L/2), the rest as w^4 w^j.
-__device__ __forceinline__ void twiddle8(cplx* a, const cplx* __restrict__ tw, int t) {
-    cplx w1 = tw[t], w2 = tw[2 * t], w3 = tw[3 * t], w4 = tw[4 * t];
+template <class R>
+__device__ __forceinline__ void twiddle8(cplxT<R>* a, const cplxT<R>* __restrict__ tw, int t) {
+    cplxT<R> w1 = tw[t], w2 = tw[2 * t], w3 = tw[3 * t], w4 = tw[4 * t];
     a[1] = cmul(a[1], w1);
     a[2] = cmul(a[2], w2);
     a[3] = cmul(a[3], w3);
@@ -209,8 +241,8 @@ __device__ __forceinline__ void twiddle8(cplx* a, const cplx* __restrict__ tw, i
 // Stockham stages: radix 8 in registers, radix 8 through LDS, and a last
 // radix-8/4/2 stage in registers; all threads of the block must call it.  On
 // return `buf` is free for reuse (the last LDS reads are behind a barrier).
-template <int L>
-__device__ __forceinline__ void tile_fft(cplx* v, cplx* buf, const cplx* __restrict__ tw, const Tile<L>& T) {
+template <int L, class R>
+__device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT<R>* __restrict__ tw, const Tile<L>& T) {
     if constexpr (L == 0) {
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s)
@@ -238,7 +270,7 @@ __device__ __forceinline__ void tile_fft(cplx* v, cplx* buf, const cplx* __restr
         for (int st = 0; st < NMID; ++st) {
             const int p = 8 << (3 * st);
             const int k = i0 & (p - 1);
-            cplx a[8];
+            cplxT<R> a[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) a[j] = buf[TT::pad(cb + i0 + j * ST)];
             twiddle8(a, tw, k * (L / (8 * p)));
@@ -260,11 +292,11 @@ __device__ __forceinline__ void tile_fft(cplx* v, cplx* buf, const cplx* __restr
 #pragma unroll
             for (int sp = 0; sp < 2; ++sp) {
                 const int i = i0 + sp * ST;
-                cplx w1 = tw[i], w2 = tw[2 * i];
-                cplx w3 = cmul(w1, w2);
-                cplx x0 = v[sp], x1 = cmul(v[sp + 2], w1), x2 = cmul(v[sp + 4], w2), x3 = cmul(v[sp + 6], w3);
-                cplx s02 = cadd(x0, x2), d02 = csub(x0, x2);
-                cplx s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
+                cplxT<R> w1 = tw[i], w2 = tw[2 * i];
+                cplxT<R> w3 = cmul(w1, w2);
+                cplxT<R> x0 = v[sp], x1 = cmul(v[sp + 2], w1), x2 = cmul(v[sp + 4], w2), x3 = cmul(v[sp + 6], w3);
+                cplxT<R> s02 = cadd(x0, x2), d02 = csub(x0, x2);
+                cplxT<R> s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
                 v[sp] = cadd(s02, s13);
                 v[sp + 2] = cadd(d02, d13);
                 v[sp + 4] = csub(s02, s13);
@@ -273,8 +305,8 @@ __device__ __forceinline__ void tile_fft(cplx* v, cplx* buf, const cplx* __restr
         } else {
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp) {
-                cplx x1 = cmul(v[sp + 4], tw[i0 + sp * ST]);
-                cplx x0 = v[sp];
+                cplxT<R> x1 = cmul(v[sp + 4], tw[i0 + sp * ST]);
+                cplxT<R> x0 = v[sp];
                 v[sp] = cadd(x0, x1);
                 v[sp + 4] = csub(x0, x1);
             }
@@ -282,17 +314,25 @@ __device__ __forceinline__ void tile_fft(cplx* v, cplx* buf, const cplx* __restr
     }
 }
 
-// Stage twiddles e^{2 pi i t/L}, t < L/2, copied into the LDS array `stw` of
-// a compile-time length; the run-time path reads the global table.
-template <int L>
-__device__ __forceinline__ const cplx* stage_twiddles(cplx* stw, const cplx* __restrict__ src) {
+// Stage twiddles e^{2 pi i t/len}, t < len/2, in the LDS array `stw` of the
+// kernel (declared with STAGE_TW) when the length is a compile-time L; the
+// FP32 table is the FP64 one rounded.  A run-time length (L == 0) reads the
+// global FP64 table directly, or copies len/2 rounded values for FP32.
+#define STAGE_TW(name, L, R) \
+    __shared__ cplxT<R> name[(L) > 1 ? (L) / 2 : (sizeof(R) == sizeof(double) ? 1 : FFT_CAP / 2)]
+template <int L, class R>
+__device__ __forceinline__ const cplxT<R>* stage_twiddles(cplxT<R>* stw, const cplx* __restrict__ src, int len) {
     if constexpr (L > 1) {
 #pragma unroll
-        for (int i = threadIdx.x; i < L / 2; i += FFT_THREADS) stw[i] = src[i];
+        for (int i = threadIdx.x; i < L / 2; i += FFT_THREADS) stw[i] = cto<R>(src[i]);
         __syncthreads();
         return stw;
+    } else if constexpr (sizeof(R) == sizeof(double)) {
+        return (const cplxT<R>*)src;
     } else {
-        return src;
+        for (int i = threadIdx.x; i < len / 2; i += FFT_THREADS) stw[i] = cto<R>(src[i]);
+        __syncthreads();
+        return stw;
     }
 }
 

@@ -430,7 +430,9 @@ struct PassAOut {
         p2 = tw2(g.twHi, g.twLo, (int64_t)na * (L / 4), g.sh);
         p4 = tw2(g.twHi, g.twLo, (int64_t)na * (L / 2), g.sh);
     }
-    __device__ __forceinline__ void put(const Geo& g, const cplx* v, cplx* __restrict__ Xt, const Tile<L>& T) const {
+    template <class R>
+    __device__ __forceinline__ void put(const Geo& g, const cplxT<R>* v, cplxT<R>* __restrict__ Xt,
+                                        const Tile<L>& T) const {
         cplx w[8];
         w[0] = w0;
         w[1] = cmul(w0, p1);
@@ -441,7 +443,7 @@ struct PassAOut {
         w[6] = cmul(w[2], p4);
         w[7] = cmul(w[3], p4);
 #pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s) Xt[passA_offset(g, na, T.idx(s), VIRT)] = cmul(v[s], w[s]);
+        for (int s = 0; s < FFT_VPT; ++s) Xt[passA_offset(g, na, T.idx(s), VIRT)] = cto<R>(cmul(cwide(v[s]), w[s]));
     }
 };
 
@@ -454,10 +456,12 @@ struct PassAOut<0, VIRT> {
         for (int s = 0; s < FFT_VPT; ++s)
             if (T.live(s)) w[s] = tw2(g.twHi, g.twLo, (int64_t)(na0 + T.col(s)) * T.idx(s), g.sh);
     }
-    __device__ __forceinline__ void put(const Geo& g, const cplx* v, cplx* __restrict__ Xt, const Tile<0>& T) const {
+    template <class R>
+    __device__ __forceinline__ void put(const Geo& g, const cplxT<R>* v, cplxT<R>* __restrict__ Xt,
+                                        const Tile<0>& T) const {
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s)
-            if (T.live(s)) Xt[passA_offset(g, na0 + T.col(s), T.idx(s), VIRT)] = cmul(v[s], w[s]);
+            if (T.live(s)) Xt[passA_offset(g, na0 + T.col(s), T.idx(s), VIRT)] = cto<R>(cmul(cwide(v[s]), w[s]));
     }
 };
 
@@ -466,10 +470,10 @@ struct PassAOut<0, VIRT> {
 // (row, n_a) = (col, idx) of the tile sits at n_a*rowsB + row, which is
 // thread + s*FFT_THREADS for the thread's element s.  After the length-N1 DFTs
 // element (row, j_a) is output m = jb(row) + N2 j_a.
-template <int L>
-__device__ __forceinline__ void passB_load(const Geo& g, int vb0, const cplx* __restrict__ X, cplx* v,
+template <int L, class R>
+__device__ __forceinline__ void passB_load(const Geo& g, int vb0, const cplxT<R>* __restrict__ X, cplxT<R>* v,
                                            const Tile<L>& T) {
-    const cplx* src = X + (int64_t)(vb0 >> g.lrB) * ((int64_t)g.N1 << g.lrB);
+    const cplxT<R>* src = X + (int64_t)(vb0 >> g.lrB) * ((int64_t)g.N1 << g.lrB);
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s)
         if (T.live(s)) v[s] = src[threadIdx.x + s * FFT_THREADS];
@@ -482,19 +486,19 @@ __device__ __forceinline__ void passB_load(const Geo& g, int vb0, const cplx* __
 //   b_n = C_n h_{m,n} c_n e^{i pi n/(2N)} [n >= nlo_b]
 // goes through pass A of the length-N DFT.  Term group blockIdx.y takes the
 // terms nterm-1-y, nterm-1-y-G, ...
-template <int LA>
+template <int LA, class R>
 __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const double* __restrict__ c,
-                                                          int64_t c_stride, cplx* __restrict__ X,
+                                                          int64_t c_stride, cplxT<R>* __restrict__ X,
                                                           int64_t x_stride) {
-    __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    __shared__ cplxT<R> buf[FFT_LDS];
+    STAGE_TW(stw, LA, R);
+    const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const double* cb = c + b * c_stride;
-    cplx* Xb = X + b * x_stride;
+    cplxT<R>* Xb = X + b * x_stride;
     const PassAOut<LA, false> out(g, T, na0);
     cplx bh[FFT_VPT];  // C_n h_{m,n} c_n e^{i pi n/(2N)} at the current m
     int nn[FFT_VPT];
@@ -522,9 +526,9 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const double* 
             for (int s = 0; s < FFT_VPT; ++s) bh[s] = cscale(bh[s], fm * (nn[s] + mcur + 0.5));
         }
         const int nlo = F.blk[F.term_blk[t]].nlo;
-        cplx v[FFT_VPT];
+        cplxT<R> v[FFT_VPT];
 #pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s) v[s] = (nn[s] >= nlo) ? bh[s] : cplx{0, 0};
+        for (int s = 0; s < FFT_VPT; ++s) v[s] = (nn[s] >= nlo) ? cto<R>(bh[s]) : cplxT<R>{0, 0};
         tile_fft<LA>(v, buf, twA, T);
         out.put(g, v, Xb + (int64_t)t * N, T);
     }
@@ -559,19 +563,19 @@ __device__ __forceinline__ void far_row_factors(int j, int N, cplx& g0, cplx& rq
     rq = {rc * q, rs * q};
 }
 
-template <int LB>
-__global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
+template <int LB, class R>
+__global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplxT<R>* __restrict__ X,
                                                           int64_t x_stride, double* __restrict__ v,
                                                           int64_t v_stride) {
-    __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    __shared__ cplxT<R> buf[FFT_LDS];
+    STAGE_TW(stw, LB, R);
+    const cplxT<R>* twB = stage_twiddles<LB, R>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
-    const cplx* Xb = X + b * x_stride;
+    const cplxT<R>* Xb = X + b * x_stride;
     cplx gm[FFT_VPT], rq[FFT_VPT];
     double acc[FFT_VPT];
     int key[FFT_VPT];  // 2 * block + (conjugated output), -1 outside
@@ -590,15 +594,15 @@ __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __
     }
     int mcur = 0;
     int t = grp;
-    cplx nx[FFT_VPT] = {};
-    if (t < F.nterm) passB_load<LB>(g, jb0, Xb + (int64_t)t * N, nx, T);
+    cplxT<R> nx[FFT_VPT] = {};
+    if (t < F.nterm) passB_load<LB, R>(g, jb0, Xb + (int64_t)t * N, nx, T);
     for (; t < F.nterm; t += G) {
         const int m = F.term_m[t];
         const int tb = F.term_blk[t];
-        cplx z[FFT_VPT];
+        cplxT<R> z[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) z[s] = nx[s];
-        if (t + G < F.nterm) passB_load<LB>(g, jb0, Xb + (int64_t)(t + G) * N, nx, T);
+        if (t + G < F.nterm) passB_load<LB, R>(g, jb0, Xb + (int64_t)(t + G) * N, nx, T);
         for (; mcur < m; ++mcur) {
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) gm[s] = cmul(gm[s], rq[s]);
@@ -607,8 +611,8 @@ __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
             if ((key[s] >> 1) == tb) {
-                const double zi = (key[s] & 1) ? -z[s].im : z[s].im;
-                acc[s] = fma(gm[s].re, z[s].re, fma(-gm[s].im, zi, acc[s]));
+                const double zr = (double)z[s].re, zi = (key[s] & 1) ? -(double)z[s].im : (double)z[s].im;
+                acc[s] = fma(gm[s].re, zr, fma(-gm[s].im, zi, acc[s]));
             }
         }
     }
@@ -842,8 +846,8 @@ __global__ FFT_BOUNDS void k_dct2_passA(Geo g, int G, const double* __restrict__
                                                            int64_t near_stride, int jnear, cplx* __restrict__ X,
                                                            int64_t x_stride) {
     __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    STAGE_TW(stw, LA, double);
+    const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
@@ -874,14 +878,14 @@ __global__ FFT_BOUNDS void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ 
                                                            int64_t dense_stride, double* __restrict__ chat,
                                                            int64_t chat_stride) {
     __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    STAGE_TW(stw, LB, double);
+    const cplx* twB = stage_twiddles<LB, double>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     cplx z[FFT_VPT];
-    passB_load<LB>(g, jb0, X + b * x_stride, z, T);
+    passB_load<LB, double>(g, jb0, X + b * x_stride, z, T);
     tile_fft<LB>(z, buf, twB, T);
     const double* db = dense + b * dense_stride;
     double* cb = chat + b * chat_stride;
@@ -903,27 +907,27 @@ __global__ FFT_BOUNDS void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ 
 //   W_n = (e^{i pi n/(2N)}/2) [x^{2q}(1+x) chat_n - i y^{2q} x chat_{N-n}],
 // x = n/N, y = 1 - x (n >= 1), W_0 = chat_0 [q = 0]; then at output m the
 // cosine term is Re U_m and the sine term sigma_m Im U_m, row k = j(m).
-// Block row blockIdx.y handles the pairs [Q y / QG, Q (y+1) / QG).
-template <int LA>
-__global__ FFT_BOUNDS void k_ndct_passA(Geo g, int Q, int QG, const double* __restrict__ chat,
-                                                           int64_t chat_stride, cplx* __restrict__ X,
-                                                           int64_t x_stride) {
-    __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+// One launch covers the pairs [qa, qb) (slab q - qa of X, precision R);
+// block row blockIdx.y takes an equal share of them.
+template <int LA, class R>
+__global__ FFT_BOUNDS void k_ndct_passA(Geo g, int qa, int qb, int QG, const double* __restrict__ chat,
+                                        int64_t chat_stride, cplxT<R>* __restrict__ X, int64_t x_stride) {
+    __shared__ cplxT<R> buf[FFT_LDS];
+    STAGE_TW(stw, LA, R);
+    const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const double* cb = chat + b * chat_stride;
-    cplx* Xb = X + b * x_stride;
+    cplxT<R>* Xb = X + b * x_stride;
     const PassAOut<LA, false> out(g, T, na0);
     const double invN = 1.0 / N;
     // W = A x^{2q} + B y^{2q} with A = e (1+x) chat_n / 2, B = -i e x chat_{N-n} / 2;
     // Ap = A x^{2q} and Bp = B y^{2q} are carried from pair to pair
     cplx Ap[FFT_VPT], Bp[FFT_VPT];
-    const int q0 = (Q * grp) / QG, q1 = (Q * (grp + 1)) / QG;
+    const int q0 = qa + ((qb - qa) * grp) / QG, q1 = qa + ((qb - qa) * (grp + 1)) / QG;
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         Ap[s] = Bp[s] = {0, 0};
@@ -945,35 +949,45 @@ __global__ FFT_BOUNDS void k_ndct_passA(Geo g, int Q, int QG, const double* __re
         }
     }
     for (int q = q0; q < q1; ++q) {
-        cplx v[FFT_VPT];
+        cplxT<R> v[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
             const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             const double x = n * invN, y = (N - n) * invN;
-            v[s] = cadd(Ap[s], Bp[s]);
+            v[s] = cto<R>(cadd(Ap[s], Bp[s]));
             Ap[s] = cscale(Ap[s], (n == 0) ? 0.0 : x * x);
             Bp[s] = cscale(Bp[s], y * y);
         }
         tile_fft<LA>(v, buf, twA, T);
-        out.put(g, v, Xb + (int64_t)q * N, T);
+        out.put(g, v, Xb + (int64_t)(q - qa) * N, T);
     }
 }
 
 // f_k = sum_l s_l d_k^l/l! F_l[k], s_l = (-1)^floor((l+1)/2), d_k = N dtheta_k,
-// by Horner from the highest pair down; the next pair's tile is loaded while
-// the current one is transformed.
-template <int LB>
-__global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X,
-                                                           int64_t x_stride, const double* __restrict__ dth,
-                                                           double* __restrict__ f, int64_t f_stride) {
-    __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+// by Horner from the highest pair down, in FP64.  Pairs q >= 1 come from X1
+// (slab q - 1, precision R), pair 0 from X0 (FP64); the next pair's tile is
+// loaded while the current one is transformed.
+template <int LB, class R>
+__global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X0, int64_t x0_stride,
+                                        const cplxT<R>* __restrict__ X1, int64_t x1_stride,
+                                        const double* __restrict__ dth, double* __restrict__ f, int64_t f_stride) {
+    __shared__ cplx bufd[FFT_LDS];
+    cplxT<R>* bufr = reinterpret_cast<cplxT<R>*>(bufd);
+    STAGE_TW(stwd, LB, double);
+    const cplx* twd = stage_twiddles<LB, double>(stwd, g.twN1, g.N1);
+    const cplxT<R>* twr;
+    if constexpr (sizeof(R) == sizeof(double)) {
+        twr = (const cplxT<R>*)twd;
+    } else {
+        STAGE_TW(stwr, LB, R);
+        twr = stage_twiddles<LB, R>(stwr, g.twN1, g.N1);
+    }
     const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
-    const cplx* Xb = X + b * x_stride;
+    const cplx* X0b = X0 + b * x0_stride;
+    const cplxT<R>* X1b = X1 + b * x1_stride;
     double acc[FFT_VPT], d[FFT_VPT];
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
@@ -984,23 +998,48 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
             d[s] = (double)N * dth[row_of(m, N)];
         }
     }
-    cplx nx[FFT_VPT] = {};
-    if (Q > 0) passB_load<LB>(g, jb0, Xb + (int64_t)(Q - 1) * N, nx, T);
-    for (int q = Q - 1; q >= 0; --q) {
-        cplx z[FFT_VPT];
-#pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s) z[s] = nx[s];
-        if (q > 0) passB_load<LB>(g, jb0, Xb + (int64_t)(q - 1) * N, nx, T);
-        tile_fft<LB>(z, buf, twB, T);
+    auto horner = [&](int q, const cplx* U) {
         const double sc = (q & 1) ? -1.0 : 1.0;  // s_{2q} = (-1)^q, s_{2q+1} = -(-1)^q
         const double r1 = 1.0 / (2 * q + 1), r2 = 1.0 / (2 * q + 2);
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
             const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
-            const double Fs = (2 * m >= N) ? -z[s].im : z[s].im;
+            const double Fs = (2 * m >= N) ? -U[s].im : U[s].im;
             const double inner = fma(d[s] * r2, acc[s], -sc * Fs);
-            acc[s] = fma(d[s] * r1, inner, sc * z[s].re);
+            acc[s] = fma(d[s] * r1, inner, sc * U[s].re);
         }
+    };
+    if constexpr (sizeof(R) == sizeof(double)) {
+        // all pairs FP64 and contiguous (X1 = X0 + N): one prefetch buffer
+        cplx nx[FFT_VPT] = {};
+        passB_load<LB, double>(g, jb0, X0b + (int64_t)(Q - 1) * N, nx, T);
+        for (int q = Q - 1; q >= 0; --q) {
+            cplx z[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) z[s] = nx[s];
+            if (q > 0) passB_load<LB, double>(g, jb0, X0b + (int64_t)(q - 1) * N, nx, T);
+            tile_fft<LB>(z, bufd, twd, T);
+            horner(q, z);
+        }
+    } else {
+        cplxT<R> nx[FFT_VPT] = {};
+        cplx n0[FFT_VPT] = {};
+        if (Q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(Q - 2) * N, nx, T);
+        else passB_load<LB, double>(g, jb0, X0b, n0, T);
+        for (int q = Q - 1; q >= 1; --q) {
+            cplxT<R> z[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) z[s] = nx[s];
+            if (q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 2) * N, nx, T);
+            else passB_load<LB, double>(g, jb0, X0b, n0, T);
+            tile_fft<LB>(z, bufr, twr, T);
+            cplx U[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
+            horner(q, U);
+        }
+        tile_fft<LB>(n0, bufd, twd, T);
+        horner(0, n0);
     }
     double* fb = f + b * f_stride;
 #pragma unroll
@@ -1019,25 +1058,25 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
 
 // Transposed Taylor pair q: DFT input at m (row k = j(m)):
 //   g_k d_k^{2q} (1 + i sigma_m d_k),  sigma_m = +1 (2m < N), -1 otherwise.
-// Block row blockIdx.y handles the pairs [Q y / QG, Q (y+1) / QG).
-template <int LA>
-__global__ FFT_BOUNDS void k_tndct_passA(Geo g, int Q, int QG, const double* __restrict__ fv,
-                                                            int64_t f_stride, const double* __restrict__ wts,
-                                                            const double* __restrict__ dth, cplx* __restrict__ X,
-                                                            int64_t x_stride) {
-    __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+// One launch covers the pairs [qa, qb) (slab q - qa of X, precision R);
+// block row blockIdx.y takes an equal share of them.
+template <int LA, class R>
+__global__ FFT_BOUNDS void k_tndct_passA(Geo g, int qa, int qb, int QG, const double* __restrict__ fv,
+                                         int64_t f_stride, const double* __restrict__ wts,
+                                         const double* __restrict__ dth, cplxT<R>* __restrict__ X, int64_t x_stride) {
+    __shared__ cplxT<R> buf[FFT_LDS];
+    STAGE_TW(stw, LA, R);
+    const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const double* fb = fv + b * f_stride;
-    cplx* Xb = X + b * x_stride;
+    cplxT<R>* Xb = X + b * x_stride;
     const PassAOut<LA, true> out(g, T, na0);
     double gv[FFT_VPT], dv[FFT_VPT], d2[FFT_VPT];
-    const int q0 = (Q * grp) / QG, q1 = (Q * (grp + 1)) / QG;
+    const int q0 = qa + ((qb - qa) * grp) / QG, q1 = qa + ((qb - qa) * (grp + 1)) / QG;
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         gv[s] = dv[s] = d2[s] = 0;
@@ -1053,14 +1092,14 @@ __global__ FFT_BOUNDS void k_tndct_passA(Geo g, int Q, int QG, const double* __r
         }
     }
     for (int q = q0; q < q1; ++q) {
-        cplx v[FFT_VPT];
+        cplxT<R> v[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
-            v[s] = {gv[s], gv[s] * dv[s]};
+            v[s] = cto<R>(cplx{gv[s], gv[s] * dv[s]});
             gv[s] *= d2[s];
         }
         tile_fft<LA>(v, buf, twA, T);
-        out.put(g, v, Xb + (int64_t)q * N, T);
+        out.put(g, v, Xb + (int64_t)(q - qa) * N, T);
     }
 }
 
@@ -1069,21 +1108,31 @@ __global__ FFT_BOUNDS void k_tndct_passA(Geo g, int Q, int QG, const double* __r
 // U_{N-n} of (virtual) row i, column j_a sits in the same tile: row 0 pairs
 // with itself at (N1 - j_a) mod N1, row N2/2 with itself at N1-1-j_a, row r
 // with its neighbour N2 - r (virtual row i ^ 1) at N1-1-j_a; the transform
-// goes through LDS once more to reach it.
-template <int LB>
-__global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ X,
-                                                            int64_t x_stride, double* __restrict__ y,
-                                                            int64_t y_stride) {
-    __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+// goes through LDS once more to reach it.  Pairs q >= 1 come from X1 (slab
+// q - 1, precision R), pair 0 from X0 (FP64); Horner in FP64.
+template <int LB, class R>
+__global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ X0, int64_t x0_stride,
+                                         const cplxT<R>* __restrict__ X1, int64_t x1_stride, double* __restrict__ y,
+                                         int64_t y_stride) {
+    __shared__ cplx bufd[FFT_LDS];
+    cplxT<R>* bufr = reinterpret_cast<cplxT<R>*>(bufd);
+    STAGE_TW(stwd, LB, double);
+    const cplx* twd = stage_twiddles<LB, double>(stwd, g.twN1, g.N1);
+    const cplxT<R>* twr;
+    if constexpr (sizeof(R) == sizeof(double)) {
+        twr = (const cplxT<R>*)twd;
+    } else {
+        STAGE_TW(stwr, LB, R);
+        twr = stage_twiddles<LB, R>(stwr, g.twN1, g.N1);
+    }
     const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
     const int N1 = T.len();
     const int N2 = g.N2;
     const int vb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
-    const cplx* Xb = X + b * x_stride;
+    const cplx* X0b = X0 + b * x0_stride;
+    const cplxT<R>* X1b = X1 + b * x1_stride;
     double acc[FFT_VPT], xs[FFT_VPT];
     cplx en[FFT_VPT];
     int part[FFT_VPT];
@@ -1113,26 +1162,21 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
             part[s] = Tile<LB>::pad(ip * N1 + jp);
         }
     }
-    cplx nx[FFT_VPT] = {};
-    if (Q > 0) passB_load<LB>(g, vb0, Xb + (int64_t)(Q - 1) * N, nx, T);
-    for (int q = Q - 1; q >= 0; --q) {
-        cplx U[FFT_VPT];
-#pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
-        if (q > 0) passB_load<LB>(g, vb0, Xb + (int64_t)(q - 1) * N, nx, T);
-        tile_fft<LB>(U, buf, twB, T);
+    // transformed tile in buffer `bb` (precision P): pair each value with its
+    // partner and take one Horner step
+    auto combine = [&](int q, auto* bb, const auto* U) {
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s)
-            if (T.live(s)) buf[T.slot(s)] = U[s];
+            if (T.live(s)) bb[T.slot(s)] = U[s];
         __syncthreads();
         const double sc = (q & 1) ? -1.0 : 1.0;
         const double r1 = 1.0 / (2 * q + 1), r2 = 1.0 / (2 * q + 2);
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
             if (T.live(s)) {
-                const cplx V = buf[part[s]];
-                const cplx A = {0.5 * (U[s].re + V.re), 0.5 * (U[s].im - V.im)};
-                const cplx Bm = {0.5 * (U[s].im + V.im), -0.5 * (U[s].re - V.re)};  // (U - conj V)/(2i)
+                const cplx u = cwide(U[s]), V = cwide(bb[part[s]]);
+                const cplx A = {0.5 * (u.re + V.re), 0.5 * (u.im - V.im)};
+                const cplx Bm = {0.5 * (u.im + V.im), -0.5 * (u.re - V.re)};  // (U - conj V)/(2i)
                 const double Zc = en[s].re * A.re - en[s].im * A.im;
                 const double Zs = en[s].re * Bm.im + en[s].im * Bm.re;
                 const double inner = fma(xs[s] * r2, acc[s], -sc * Zs);
@@ -1140,6 +1184,35 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
             }
         }
         __syncthreads();
+    };
+    if constexpr (sizeof(R) == sizeof(double)) {
+        // all pairs FP64 and contiguous (X1 = X0 + N): one prefetch buffer
+        cplx nx[FFT_VPT] = {};
+        passB_load<LB, double>(g, vb0, X0b + (int64_t)(Q - 1) * N, nx, T);
+        for (int q = Q - 1; q >= 0; --q) {
+            cplx U[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
+            if (q > 0) passB_load<LB, double>(g, vb0, X0b + (int64_t)(q - 1) * N, nx, T);
+            tile_fft<LB>(U, bufd, twd, T);
+            combine(q, bufd, U);
+        }
+    } else {
+        cplxT<R> nx[FFT_VPT] = {};
+        cplx n0[FFT_VPT] = {};
+        if (Q > 1) passB_load<LB, R>(g, vb0, X1b + (int64_t)(Q - 2) * N, nx, T);
+        else passB_load<LB, double>(g, vb0, X0b, n0, T);
+        for (int q = Q - 1; q >= 1; --q) {
+            cplxT<R> U[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
+            if (q > 1) passB_load<LB, R>(g, vb0, X1b + (int64_t)(q - 2) * N, nx, T);
+            else passB_load<LB, double>(g, vb0, X0b, n0, T);
+            tile_fft<LB>(U, bufr, twr, T);
+            combine(q, bufr, U);
+        }
+        tile_fft<LB>(n0, bufd, twd, T);
+        combine(0, bufd, n0);
     }
     double* yb = y + b * y_stride;
 #pragma unroll
@@ -1210,8 +1283,8 @@ template <int LA>
 __global__ FFT_BOUNDS void k_dct3_passA(Geo g, const double* __restrict__ y, int64_t y_stride,
                                                            cplx* __restrict__ X, int64_t x_stride) {
     __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    STAGE_TW(stw, LA, double);
+    const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
@@ -1235,14 +1308,14 @@ template <int LB>
 __global__ FFT_BOUNDS void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64_t x_stride,
                                                            double* __restrict__ u, int64_t u_stride) {
     __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    STAGE_TW(stw, LB, double);
+    const cplx* twB = stage_twiddles<LB, double>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     cplx z[FFT_VPT];
-    passB_load<LB>(g, jb0, X + b * x_stride, z, T);
+    passB_load<LB, double>(g, jb0, X + b * x_stride, z, T);
     tile_fft<LB>(z, buf, twB, T);
     double* ub = u + b * u_stride;
 #pragma unroll
@@ -1258,19 +1331,19 @@ __global__ FFT_BOUNDS void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64
 // input at m is rho at row j = j(m) (conjugated when 2m >= N) with
 //   rho_j = u_j e^{i (m+1/2)(theta_j - pi/2)} (2 sin theta_j)^{-m-1/2} [j in block b].
 // Term group blockIdx.y takes the terms y, y + G, ...
-template <int LA>
+template <int LA, class R>
 __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const double* __restrict__ u,
-                                                           int64_t u_stride, cplx* __restrict__ X,
+                                                           int64_t u_stride, cplxT<R>* __restrict__ X,
                                                            int64_t x_stride) {
-    __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LA > 1 ? LA / 2 : 1];
-    const cplx* twA = stage_twiddles<LA>(stw, g.twN2);
+    __shared__ cplxT<R> buf[FFT_LDS];
+    STAGE_TW(stw, LA, R);
+    const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const double* ub = u + b * u_stride;
-    cplx* Xb = X + b * x_stride;
+    cplxT<R>* Xb = X + b * x_stride;
     const PassAOut<LA, false> out(g, T, na0);
     cplx gm[FFT_VPT], rq[FFT_VPT];
     int key[FFT_VPT];  // 2 * block + (conjugated input), -1 outside
@@ -1296,10 +1369,10 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const double*
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) gm[s] = cmul(gm[s], rq[s]);
         }
-        cplx v[FFT_VPT];
+        cplxT<R> v[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
-            v[s] = ((key[s] >> 1) == tb) ? gm[s] : cplx{0, 0};
+            v[s] = ((key[s] >> 1) == tb) ? cto<R>(gm[s]) : cplxT<R>{0, 0};
             if (key[s] & 1) v[s].im = -v[s].im;
         }
         tile_fft<LA>(v, buf, twA, T);
@@ -1311,18 +1384,18 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const double*
 // Re(e^{i pi n/(2N)} U_n), descending m (h by multiplication only); term
 // group blockIdx.y takes the terms nterm-1-y, nterm-1-y-G, ... and writes
 // partial sums to out[y].
-template <int LB>
-__global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplx* __restrict__ X,
+template <int LB, class R>
+__global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplxT<R>* __restrict__ X,
                                                            int64_t x_stride, double* __restrict__ out,
                                                            int64_t out_stride) {
-    __shared__ cplx buf[FFT_LDS];
-    __shared__ cplx stw[LB > 1 ? LB / 2 : 1];
-    const cplx* twB = stage_twiddles<LB>(stw, g.twN1);
+    __shared__ cplxT<R> buf[FFT_LDS];
+    STAGE_TW(stw, LB, R);
+    const cplxT<R>* twB = stage_twiddles<LB, R>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
-    const cplx* Xb = X + b * x_stride;
+    const cplxT<R>* Xb = X + b * x_stride;
     double acc[FFT_VPT];
     cplx eh[FFT_VPT];  // C_n h_{m,n} e^{i pi n/(2N)} at the current m
     int nn[FFT_VPT];
@@ -1344,15 +1417,15 @@ __global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplx* _
     }
     int mcur = F.Mmax - 1;
     int t = F.nterm - 1 - (int)blockIdx.y;
-    cplx nx[FFT_VPT] = {};
-    if (t >= 0) passB_load<LB>(g, jb0, Xb + (int64_t)t * N, nx, T);
+    cplxT<R> nx[FFT_VPT] = {};
+    if (t >= 0) passB_load<LB, R>(g, jb0, Xb + (int64_t)t * N, nx, T);
     for (; t >= 0; t -= G) {
         const int m = F.term_m[t];
         const int nlo = F.blk[F.term_blk[t]].nlo;
-        cplx U[FFT_VPT];
+        cplxT<R> U[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
-        if (t - G >= 0) passB_load<LB>(g, jb0, Xb + (int64_t)(t - G) * N, nx, T);
+        if (t - G >= 0) passB_load<LB, R>(g, jb0, Xb + (int64_t)(t - G) * N, nx, T);
         for (; mcur > m; --mcur) {
             const double fm = (double)mcur / ((mcur - 0.5) * (mcur - 0.5));
 #pragma unroll
@@ -1361,7 +1434,7 @@ __global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplx* _
         tile_fft<LB>(U, buf, twB, T);
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s)
-            if (nn[s] >= nlo) acc[s] = fma(eh[s].re, U[s].re, fma(-eh[s].im, U[s].im, acc[s]));
+            if (nn[s] >= nlo) acc[s] = fma(eh[s].re, (double)U[s].re, fma(-eh[s].im, (double)U[s].im, acc[s]));
     }
     double* ob = out + b * out_stride + (int64_t)blockIdx.y * N;
 #pragma unroll
@@ -1556,6 +1629,20 @@ __global__ void k_idlt_final(int N, int nd, int nrg, const int* __restrict__ rg_
             case 1024: KER<1024><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;     \
             case 2048: KER<2048><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;     \
             default: KER<0><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;          \
+        }                                                                         \
+    } while (0)
+// The same for kernels with a precision parameter R (double or float).
+#define LEN_LAUNCH_R(FULL, LEN, KER, R, GRID, BLK, SHM, STR, ...)                  \
+    do {                                                                          \
+        int L_ = (FULL) ? (LEN) : 0;                                              \
+        switch (L_) {                                                             \
+            case 64: KER<64, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;      \
+            case 128: KER<128, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;    \
+            case 256: KER<256, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;    \
+            case 512: KER<512, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;    \
+            case 1024: KER<1024, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;  \
+            case 2048: KER<2048, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;  \
+            default: KER<0, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;       \
         }                                                                         \
     } while (0)
 namespace dlt {
@@ -1784,12 +1871,24 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
         });
     // far field
     const FarParams& F = p.far;
-    traced("k_far_passA", s, [&] {
-        LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_far_passA, (dim3(g.N1 / g.colsA, p.tgA, (unsigned)nb)), FFT_THREADS, 0, s, g, F, p.tgA, c, cs, w.X, w.sX);
-    });
-    traced("k_far_passB", s, [&] {
-        LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_far_passB, (dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb)), FFT_THREADS, 0, s, g, F, p.tgB, w.X, w.sX, w.v, w.sv);
-    });
+    const dim3 gA(g.N1 / g.colsA, p.tgA, (unsigned)nb), gB(g.N2 / g.rowsB, p.tgB, (unsigned)nb);
+    if (p.prec == PREC_FP32_BULK) {
+        cplxf* X = (cplxf*)w.X;
+        const int64_t sX = 2 * w.sX;
+        traced("k_far_passA_f32", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_far_passA, float, gA, FFT_THREADS, 0, s, g, F, p.tgA, c, cs, X, sX);
+        });
+        traced("k_far_passB_f32", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_far_passB, float, gB, FFT_THREADS, 0, s, g, F, p.tgB, X, sX, w.v, w.sv);
+        });
+    } else {
+        traced("k_far_passA", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_far_passA, double, gA, FFT_THREADS, 0, s, g, F, p.tgA, c, cs, w.X, w.sX);
+        });
+        traced("k_far_passB", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_far_passB, double, gB, FFT_THREADS, 0, s, g, F, p.tgB, w.X, w.sX, w.v, w.sv);
+        });
+    }
     // values on the grid -> coefficients
     DLT_TRY(dep(sn, s, L.ev[4]));
     traced("k_dct2_passA", s, [&] {
@@ -1856,12 +1955,24 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
         });
     }
     // transposed far field
-    traced("k_tfar_passA", s, [&] {
-        LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_tfar_passA, (dim3(tilesA, p.tgA, (unsigned)nb)), FFT_THREADS, 0, s, g, p.far, p.tgA, u, w.svec, w.X, w.sX);
-    });
-    traced("k_tfar_passB", s, [&] {
-        LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_tfar_passB, (dim3(g.N2 / g.rowsB, p.tgB, (unsigned)nb)), FFT_THREADS, 0, s, g, p.far, p.tgB, w.X, w.sX, w.v, w.sv);
-    });
+    const dim3 gA(tilesA, p.tgA, (unsigned)nb), gB(g.N2 / g.rowsB, p.tgB, (unsigned)nb);
+    if (p.prec == PREC_FP32_BULK) {
+        cplxf* X = (cplxf*)w.X;
+        const int64_t sX = 2 * w.sX;
+        traced("k_tfar_passA_f32", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tfar_passA, float, gA, FFT_THREADS, 0, s, g, p.far, p.tgA, u, w.svec, X, sX);
+        });
+        traced("k_tfar_passB_f32", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tfar_passB, float, gB, FFT_THREADS, 0, s, g, p.far, p.tgB, X, sX, w.v, w.sv);
+        });
+    } else {
+        traced("k_tfar_passA", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tfar_passA, double, gA, FFT_THREADS, 0, s, g, p.far, p.tgA, u, w.svec, w.X, w.sX);
+        });
+        traced("k_tfar_passB", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tfar_passB, double, gB, FFT_THREADS, 0, s, g, p.far, p.tgB, w.X, w.sX, w.v, w.sv);
+        });
+    }
     DLT_TRY(dep(sn, s, L.ev[8]));
     DLT_TRY(dep(sl, s, L.ev[9]));
     traced("k_idlt_final", s, [&] {
@@ -1879,10 +1990,33 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
     const hipStream_t s = L.s;
     const int Q = p.L / 2;
     const int tilesA = g.N1 / g.colsA;
-    // small transforms: split the Taylor pairs over blocks for parallelism
-    int QG = (tilesA * nb >= 256) ? 1 : Q;
-    traced("k_ndct_passA", s, [&] { LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_ndct_passA, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, Q, QG, chat, hs, w.X, w.sX); });
-    traced("k_ndct_passB", s, [&] { LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_ndct_passB, (dim3(g.N2 / g.rowsB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, Q, w.X, w.sX, dth, f, p.N); });
+    const int N = (int)p.N;
+    const dim3 gB(g.N2 / g.rowsB, 1, (unsigned)nb);
+    if (p.prec == PREC_FP32_BULK) {
+        // pair 0 in FP64 (slab 0 of X), pairs 1..Q-1 in FP32 behind it
+        cplxf* X1 = (cplxf*)(w.X + N);
+        const int64_t s1 = 2 * w.sX;
+        const int QG = (tilesA * nb >= 256) ? 1 : std::max(Q - 1, 1);
+        traced("k_ndct_passA", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_ndct_passA, double, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, 1, 1, chat, hs, w.X, w.sX);
+        });
+        if (Q > 1)
+            traced("k_ndct_passA_f32", s, [&] {
+                LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_ndct_passA, float, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 1, Q, QG, chat, hs, X1, s1);
+            });
+        traced("k_ndct_passB_f32", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_ndct_passB, float, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, X1, s1, dth, f, p.N);
+        });
+    } else {
+        // small transforms: split the Taylor pairs over blocks for parallelism
+        const int QG = (tilesA * nb >= 256) ? 1 : Q;
+        traced("k_ndct_passA", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_ndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, chat, hs, w.X, w.sX);
+        });
+        traced("k_ndct_passB", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_ndct_passB, double, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, w.X + N, w.sX, dth, f, p.N);
+        });
+    }
     return hipGetLastError();
 }
 
@@ -1894,15 +2028,32 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
     const hipStream_t s = L.s;
     const int Q = p.L / 2;
     const int tilesA = g.N1 / g.colsA;
-    int QG = (tilesA * nb >= 256) ? 1 : Q;
     double* y = w.chat;  // T^T D_w f, stride w.schat
-    traced("k_tndct_passA", s, [&] {
-        LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_tndct_passA, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, Q, QG, f, N, wts, dth, w.X, w.sX);
-    });
-    int tilesB = (g.N2 == 1) ? 1 : g.N2 / g.rowsB;
-    traced("k_tndct_passB", s, [&] {
-        LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_tndct_passB, (dim3(tilesB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, Q, w.X, w.sX, y, w.schat);
-    });
+    const int tilesB = (g.N2 == 1) ? 1 : g.N2 / g.rowsB;
+    const dim3 gB(tilesB, 1, (unsigned)nb);
+    if (p.prec == PREC_FP32_BULK) {
+        cplxf* X1 = (cplxf*)(w.X + N);
+        const int64_t s1 = 2 * w.sX;
+        const int QG = (tilesA * nb >= 256) ? 1 : std::max(Q - 1, 1);
+        traced("k_tndct_passA", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, 1, 1, f, N, wts, dth, w.X, w.sX);
+        });
+        if (Q > 1)
+            traced("k_tndct_passA_f32", s, [&] {
+                LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, float, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 1, Q, QG, f, N, wts, dth, X1, s1);
+            });
+        traced("k_tndct_passB_f32", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tndct_passB, float, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, X1, s1, y, w.schat);
+        });
+    } else {
+        const int QG = (tilesA * nb >= 256) ? 1 : Q;
+        traced("k_tndct_passA", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, f, N, wts, dth, w.X, w.sX);
+        });
+        traced("k_tndct_passB", s, [&] {
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tndct_passB, double, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, w.X + N, w.sX, y, w.schat);
+        });
+    }
     return run_leg2cheb_t(p, nb, y, w.schat, c, N, 1, w, L);
 }
 

@@ -95,9 +95,12 @@ static double bessel_j0_zero(int k) {
     return x;
 }
 
-int plan_build(int64_t N, Plan& p) {
+int plan_build(int64_t N, int prec, Plan& p) {
     memset(&p.geo, 0, sizeof(p.geo));
     p.N = N;
+    p.prec = prec;
+    const bool bulk = (prec != PREC_FP64);  // parameters for the 5e-6 budget
+    const bool f32 = (prec == PREC_FP32_BULK);
     // ---- FFT geometry
     int lg = 0;
     while ((int64_t(1) << lg) < N) ++lg;
@@ -124,7 +127,8 @@ int plan_build(int64_t N, Plan& p) {
 
     // ---- Taylor truncation (Corollary 2 with max N|dtheta| <= 0.83845)
     {
-        const double tolT = 5e-15;  // 10% of the 5e-14 FP64 budget
+        // 10% of the budget: 5e-14 (FP64) or 5e-6 (FP32-bulk)
+        const double tolT = bulk ? 5e-7 : 5e-15;
         int L = 1;
         double f = 0.83845;
         while (f > tolT) {
@@ -141,7 +145,7 @@ int plan_build(int64_t N, Plan& p) {
     p.dense_nchunk = (p.nd + p.dense_chunk - 1) / p.dense_chunk;
     if (p.nd > DENSE_MAX) {
         p.sub = new Plan();
-        if ((rc = plan_build(p.nd, *p.sub))) return rc;
+        if ((rc = plan_build(p.nd, prec, *p.sub))) return rc;
         p.dense_nchunk = 0;
     } else {
         std::vector<double> lam(p.nd);
@@ -157,8 +161,32 @@ int plan_build(int64_t N, Plan& p) {
     F.nd = p.nd;
     Nr.nd = p.nd;
     if (N > p.nd) {
-        const LD eps = 1e-15L;
-        const int M1 = 12, M = 12;
+        // truncation of the asymptotic series per row, relative to ||c||_1
+        const LD eps = bulk ? 5e-7L : 1e-15L;
+        // cost model (forward + inverse, calibrated on MI355X at N = 2^20):
+        // one far term (both passes) ~ 24 us per 2^20 points in FP64, 3/4 of
+        // that with FP32 storage; the near field runs 64 rows per wave, so it
+        // costs by groups of 64 rows, ~0.8 ps per row-degree in all
+        const double far_term_s = (f32 ? 18e-6 : 24e-6) * (double)N / (double)(1 << 20);
+        const double near_step_s = 0.8e-12;
+        auto near_cost = [&](int rows, int64_t degrees) {
+            return (double)(((rows + 63) / 64) * 64) * (double)degrees * near_step_s;
+        };
+        // terms of the central block: fewest total cost, rows near the ends
+        // go to the recurrence
+        int M1 = 12;
+        {
+            double best = 1e300;
+            for (int m = bulk ? 3 : 8; m <= (bulk ? 12 : 16); ++m) {
+                int j = first_row(N, far_smin(m, p.nd, eps));
+                double cost = m * far_term_s + near_cost(j, N - p.nd);
+                if (cost < best) {
+                    best = cost;
+                    M1 = m;
+                }
+            }
+        }
+        const int M = M1;
         const double beta = 8.0;
         int half = (int)(N / 2);
         // block 0: central rows, columns n >= nd
@@ -167,11 +195,7 @@ int plan_build(int64_t N, Plan& p) {
         F.nblk = 1;
         int jprev = j0;
         // further blocks only where their M full-length transforms cost less
-        // than the near-field recurrence they replace (cost model: one far
-        // term ~ 64 N bytes through HBM at ~4 TB/s; one recurrence step of
-        // one row ~ 2 x 4 FP64 ops at ~20% of the vector peak)
-        const double far_term_s = 64.0 * (double)N / 4e12;
-        const double near_step_s = 8.0 / (0.2 * 39e12);
+        // than the near-field recurrence they replace
         while (jprev > 0 && F.nblk < MAX_BLOCKS) {
             int jl = (int)floor(jprev / beta);
             LD s = sinl((jl + 0.5L) * PI_L / N);
@@ -184,8 +208,9 @@ int plan_build(int64_t N, Plan& p) {
             }
             int nlo = (int)ceill(hi);
             if (nlo >= N) break;
-            double saved = (double)(jprev - jl) * (double)(N - nlo) * near_step_s * 2;  // both ends
-            if (saved < M * far_term_s * 2) break;  // forward and inverse alike
+            // rows [jl, jprev) keep only degrees [nd, nlo) in the recurrence
+            double saved = (double)(jprev - jl) * (double)(N - nlo) * near_step_s;
+            if (saved < M * far_term_s) break;
             F.blk[F.nblk++] = {jl, jprev, nlo, M};
             jprev = jl;
         }
@@ -293,6 +318,9 @@ int plan_build(int64_t N, Plan& p) {
         p.tgB = std::min({nt, 4, std::max(1, (768 + tilesB - 1) / tilesB)});
     }
     p.ws_X = (size_t)nX * N * sizeof(cplx);
+    if (f32)  // FP32 far terms; or the FP64 Taylor pair 0 + FP32 pairs 1..Q-1
+        p.ws_X = std::max((size_t)std::max(F.nterm, 1) * N * sizeof(cplxf),
+                          (size_t)N * sizeof(cplx) + (size_t)(p.L / 2 - 1) * N * sizeof(cplxf));
     // the low-degree sub-run has its own region: it runs beside the far field
     p.ws_sub = p.sub ? p.sub->ws_per_inst : 0;
     p.ws_v = (size_t)p.tgB * N * sizeof(double);

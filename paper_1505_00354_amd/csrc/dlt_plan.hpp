@@ -68,8 +68,18 @@ struct NodeParams {
     double h[MAX_NODE_M];      // h_{m,N}
 };
 
+// Arithmetic of a plan: FP64 throughout (5e-14 budget); FP32-bulk (the
+// far-field terms and Taylor pairs q >= 1 stored and transformed in FP32,
+// parameters for a 5e-6 budget; nodes, amplitudes, near field, pair 0,
+// Horner and the DCT-II/III stay FP64); or FP64 with the 5e-6 parameters
+// (the equal-accuracy FP64 reference for FP32-bulk).
+constexpr int PREC_FP64 = 0;
+constexpr int PREC_FP32_BULK = 1;
+constexpr int PREC_FP64_RELAXED = 2;
+
 struct Plan {
     int64_t N = 0;
+    int prec = PREC_FP64;
     int L = 16;        // Taylor terms (even)
     int nd = 0;        // columns n < nd handled by the dense block
     int dense_chunk = 1024, dense_nchunk = 0;
@@ -103,9 +113,9 @@ struct Plan {
     Plan* sub = nullptr;
 };
 
-// Builds the plan for size N (power of two, 1 <= N <= MAX_N); returns 0 or a
-// DLT status code.  Allocates the device tables.
-int plan_build(int64_t N, Plan& p);
+// Builds the plan for size N (power of two, 1 <= N <= MAX_N) and precision
+// `prec`; returns 0 or a DLT status code.  Allocates the device tables.
+int plan_build(int64_t N, int prec, Plan& p);
 void plan_free(Plan& p);
 
 }  // namespace dlt
