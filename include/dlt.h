@@ -22,8 +22,11 @@
  *     does not synchronise.  Errors of kernels already enqueued surface as
  *     DLT_ERR_HIP from a later call or from the caller's own synchronisation.
  *   - batch == 0 is a no-op returning DLT_OK.
- *   - Supported sizes: N a power of two with 1 <= N <= DLT_MAX_N (other N
- *     return DLT_ERR_UNSUPPORTED).
+ *   - Supported sizes: 1 <= N <= DLT_MAX_N (larger N return
+ *     DLT_ERR_UNSUPPORTED).  Powers of two run on the Chebyshev grid of the
+ *     same size; other N run on the next power-of-two grid, with the inputs
+ *     zero-padded and every Legendre node paired with its nearest grid point
+ *     (more Taylor terms, same accuracy).
  *   - The library keeps per-N plans (twiddle and coefficient tables, and the
  *     input-independent near-field recurrence states, formed on the device)
  *     and a per-stream workspace; both are created on first use and live
@@ -49,7 +52,7 @@ extern "C" {
 
 #define DLT_OK 0
 #define DLT_ERR_INVALID_ARG (-1) /* N < 1, batch < 0, NULL pointer, overlapping in/out */
-#define DLT_ERR_UNSUPPORTED (-2) /* N not a power of two, or N > DLT_MAX_N */
+#define DLT_ERR_UNSUPPORTED (-2) /* N > DLT_MAX_N (plan queries: N not a power of two) */
 #define DLT_ERR_HIP (-3)         /* a HIP runtime call or kernel launch failed */
 #define DLT_ERR_NOMEM (-4)       /* device workspace or plan tables could not be allocated */
 
@@ -102,6 +105,27 @@ int leg2cheb_ex(int64_t N, int64_t batch, const double* c, double* chat, int pre
 int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f, int prec, hipStream_t stream);
 int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int prec, hipStream_t stream);
 int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int prec, hipStream_t stream);
+
+/* Ragged batch: `count` independent transforms of uneven sizes in one call
+ * (many transforms of different N, forward and inverse mixed).
+ *   Ns[i]       size of instance i (1 <= Ns[i] <= DLT_MAX_N), host array
+ *   offsets[i]  element offset of instance i in `in` and in `out` (host array;
+ *               instance i reads in[offsets[i] .. offsets[i]+Ns[i]) and writes
+ *               out[offsets[i] .. offsets[i]+Ns[i]))
+ *   inverse[i]  0: DLT (eq. (1)), 1: IDLT (eq. (2)); host array, NULL = all 0
+ *   in, out     device arrays; the spans they cover must not overlap
+ *   prec        DLT_PREC_* as for the _ex entry points
+ * Instances are grouped by direction and padded power-of-two size; each group
+ * runs as one batched pipeline (in slices bounded by the workspace).  The
+ * first call with a given descriptor (count, Ns, offsets, inverse, prec, in,
+ * out, stream) times the candidate grid sizes of each group (autotuner, once
+ * per group shape), builds the device descriptors and captures the whole
+ * sequence into a HIP graph; it synchronises the device.  Later calls with the
+ * same descriptor launch the cached graph on `stream` and do not
+ * synchronise.  Graphs, descriptors and their workspaces live until
+ * dlt_release(). */
+int dlt_batch_ex(int64_t count, const int64_t* Ns, const int64_t* offsets, const int8_t* inverse,
+                 const double* in, double* out, int prec, hipStream_t stream);
 
 /* Human-readable text of a status code (static storage). */
 const char* dlt_status_string(int status);

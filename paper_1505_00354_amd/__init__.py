@@ -55,6 +55,8 @@ def lib():
             getattr(L, name).restype = ctypes.c_int
         L.dlt_plan_query_ex.argtypes = [i64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         L.dlt_plan_query_ex.restype = ctypes.c_int
+        L.dlt_batch_ex.argtypes = [i64, vp, vp, vp, vp, vp, ctypes.c_int, vp]
+        L.dlt_batch_ex.restype = ctypes.c_int
         L.dlt_status_string.argtypes = [ctypes.c_int]
         L.dlt_status_string.restype = ctypes.c_char_p
         L.dlt_release.argtypes = []
@@ -148,6 +150,47 @@ def dlt_forward(c, out=None, prec="fp64"):
 def dlt_inverse(f, out=None, prec="fp64"):
     """Inverse transform c_n = (n+1/2) sum_k w_k f_k P_n(x_k)."""
     return _unary("dlt_inverse", f, out, prec)
+
+
+def dlt_batch(x, sizes, offsets=None, inverse=None, out=None, prec="fp64"):
+    """Ragged batch of transforms of uneven sizes in one call (dlt_batch_ex).
+
+    x: 1-D float64 CUDA tensor holding every instance; instance i is
+    x[offsets[i] : offsets[i] + sizes[i]] (offsets default to the packed
+    layout).  inverse[i] true: IDLT of that instance, else DLT.  Returns (or
+    fills) a tensor like x with each instance's result at the same place.
+    The first call with a given layout and buffers tunes, captures and
+    synchronises; repeated calls replay a cached HIP graph."""
+    import numpy as np
+    import torch
+
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.dim() == 1):
+        raise TypeError("expected a 1-D float64 CUDA tensor")
+    if not x.is_contiguous():
+        raise ValueError("input must be contiguous")
+    Ns = np.ascontiguousarray(sizes, dtype=np.int64)
+    if offsets is None:
+        offs = np.zeros(len(Ns), dtype=np.int64)
+        if len(Ns) > 1:
+            offs[1:] = np.cumsum(Ns)[:-1]
+    else:
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    if len(offs) != len(Ns):
+        raise ValueError("sizes and offsets differ in length")
+    if len(Ns) and int((offs + Ns).max()) > x.numel():
+        raise ValueError("an instance reaches beyond the input")
+    inv = np.zeros(len(Ns), dtype=np.int8) if inverse is None else np.ascontiguousarray(inverse, dtype=np.int8)
+    if len(inv) != len(Ns):
+        raise ValueError("inverse flags and sizes differ in length")
+    if out is None:
+        out = torch.zeros_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must match the input's shape, dtype and device and be contiguous")
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+    with torch.cuda.device(x.device):
+        _check(lib().dlt_batch_ex(len(Ns), ptr(Ns), ptr(offs), ptr(inv), ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), _prec(prec), _stream(x.device)), "dlt_batch_ex")
+    return out
 
 
 def release():

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <tuple>
 #include <utility>
+#include <vector>
 
 #include "../../include/dlt.h"
 #include "dlt_kernels.hpp"
@@ -18,6 +19,45 @@
 using namespace dlt;
 
 namespace {
+
+// Device arrays describing nb instances: node parameters, offsets in the
+// caller's arrays, prefix sums of interior and boundary node counts.
+struct RDesc {
+    RNode* R = nullptr;
+    int64_t* offs = nullptr;
+    int* ioff = nullptr;
+    int* boff = nullptr;
+    int nb = 0, ni = 0, nbd = 0;
+    ~RDesc() {
+        void* q[] = {R, offs, ioff, boff};
+        for (void* x : q)
+            if (x) (void)hipFree(x);
+    }
+};
+
+// One slice of a ragged batch: instances of one direction on one grid.
+struct RSlice {
+    int dir = 0;  // 0: forward DLT, 1: inverse DLT, 2: leg2cheb, 3: Chebyshev evaluation, 4: nodes
+    int64_t Ng = 0;
+    int Q = 0;
+    Plan* plan = nullptr;
+    std::unique_ptr<RDesc> d;
+};
+
+struct BatchEntry {
+    std::vector<RSlice> slices;
+    void* ws = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchEntry() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (ws) (void)hipFree(ws);
+    }
+};
+
+struct SingleEntry {
+    std::vector<RSlice> slices;
+    size_t ws_bytes = 0;
+};
 
 struct Cache {
     std::mutex mu;
@@ -28,6 +68,12 @@ struct Cache {
     };
     std::map<std::pair<int, hipStream_t>, WS> ws;  // (device, stream)
     std::map<std::pair<int, hipStream_t>, Lanes> lanes;  // (device, stream): side streams, events
+    std::map<int64_t, RNode> rnodes;                     // host node parameters per N
+    std::map<std::pair<int, hipStream_t>, hipStream_t> capture;  // (device, stream) -> private capture stream
+    // equal-size batches of a size that is not a power of two: (device, N, batch, direction, precision)
+    std::map<std::tuple<int, int64_t, int64_t, int, int>, std::unique_ptr<SingleEntry>> single;
+    std::map<std::vector<int64_t>, std::unique_ptr<BatchEntry>> graphs;  // descriptor -> graph
+    std::map<std::tuple<int, int, int64_t, int>, int64_t> tuned;  // (device, direction, P, prec) -> grid
 };
 
 Cache& cache() {
@@ -161,9 +207,393 @@ int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? DLT_OK : DLT_ERR_HIP; }
 
+// ------------------------------------------------------------ ragged sizes --
+// Sizes that are not powers of two, and batches of uneven sizes, run on the
+// power-of-two grid Ng >= N of the Chebyshev points (j+1/2) pi/Ng: inputs are
+// zero-padded to Ng (the Legendre-to-Chebyshev map and the DCTs are exact on
+// the finer grid), and every Legendre node is paired with its nearest grid
+// row (the Taylor series then runs with |Ng dtheta| <= pi/2, so more terms).
+
+int64_t next_pow2(int64_t n) {
+    int64_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Taylor pairs for sizes Ns on the grid Ng: the smallest L with
+// r^L / L! <= tol, r = max over the sizes of |Ng dtheta| * N/Ng (<= 0.83845
+// when N = Ng, Lemma 2; <= (pi/2) N/Ng otherwise).
+int ragged_Q(int prec, const int64_t* Ns, const std::vector<int64_t>& idx, int64_t Ng) {
+    double r = 0;
+    for (int64_t i : idx)
+        r = std::max(r, Ns[i] == Ng ? 0.83845 : 1.5707963267948966 * (double)Ns[i] / (double)Ng);
+    const double tol = (prec == DLT_PREC_FP64) ? 5e-15 : 5e-7;
+    int L = 1;
+    double f = r;
+    while (f > tol && L < 64) {
+        ++L;
+        f *= r / L;
+    }
+    return std::max(1, (L + 1) / 2);
+}
+
+// node parameters of size N (host, cached; caller holds the cache lock)
+const RNode& rnode_of(Cache& c, int64_t N) {
+    auto it = c.rnodes.find(N);
+    if (it == c.rnodes.end()) {
+        RNode r;
+        rnode_build(N, r);
+        it = c.rnodes.emplace(N, r).first;
+    }
+    return it->second;
+}
+
+// Builds the device descriptor of instances idx (sizes Ns, offsets offs).
+// Synchronous (host-to-device copies).
+int rdesc_build(const int64_t* Ns, const int64_t* offs, const std::vector<int64_t>& idx, RDesc& d) {
+    const int nb = (int)idx.size();
+    std::vector<RNode> R(nb);
+    std::vector<int64_t> o(nb);
+    std::vector<int> io(nb + 1, 0), bo(nb + 1, 0);
+    {
+        Cache& c = cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        for (int b = 0; b < nb; ++b) {
+            R[b] = rnode_of(c, Ns[idx[b]]);
+            o[b] = offs[idx[b]];
+            const int nh = (int)((Ns[idx[b]] + 1) / 2);
+            io[b + 1] = io[b] + (nh - R[b].P.kb);
+            bo[b + 1] = bo[b] + R[b].P.kb;
+        }
+    }
+    d.nb = nb;
+    d.ni = io[nb];
+    d.nbd = bo[nb];
+    auto up = [](const void* h, size_t bytes, void** dst) {
+        if (hipMalloc(dst, bytes) != hipSuccess) return DLT_ERR_NOMEM;
+        return hipMemcpy(*dst, h, bytes, hipMemcpyHostToDevice) == hipSuccess ? DLT_OK : DLT_ERR_HIP;
+    };
+    int rc;
+    if ((rc = up(R.data(), R.size() * sizeof(RNode), (void**)&d.R))) return rc;
+    if ((rc = up(o.data(), o.size() * sizeof(int64_t), (void**)&d.offs))) return rc;
+    if ((rc = up(io.data(), io.size() * sizeof(int), (void**)&d.ioff))) return rc;
+    return up(bo.data(), bo.size() * sizeof(int), (void**)&d.boff);
+}
+
+size_t al256z(size_t x) { return (x + 255) & ~size_t(255); }
+
+// workspace of a slice: the plan's per-instance work, the staging vectors
+// and the node tables on the grid
+size_t rslice_bytes(const Plan& p, int64_t nb) {
+    const size_t v = (size_t)nb * (size_t)p.N;
+    return work_bytes(p, nb) + al256z(v * sizeof(double)) + al256z(v * sizeof(int)) + 2 * al256z(v * sizeof(double));
+}
+
+// Enqueues slice S (in/out: the caller's arrays, indexed through the offsets).
+hipError_t rslice_run(const RSlice& S, const double* in, double* out, void* ws, const Lanes& L) {
+    const Plan& p = *S.plan;
+    const int nb = S.d->nb, Ng = (int)S.Ng;
+    Work w;
+    work_carve(p, nb, ws, w);
+    char* q = (char*)ws + work_bytes(p, nb);
+    const size_t v = (size_t)nb * (size_t)Ng;
+    double* stage = (double*)q;
+    q += al256z(v * sizeof(double));
+    int* gk = (int*)q;
+    q += al256z(v * sizeof(int));
+    double* dg = (double*)q;
+    q += al256z(v * sizeof(double));
+    double* wg = (double*)q;
+    const RaggedNodes rn{S.d->R, S.d->ioff, S.d->boff, nb, S.d->ni, S.d->nbd};
+    const RaggedRows rr{gk, dg, wg, S.d->offs};
+    hipError_t e;
+    if (S.dir == 0) {
+        // nodes on the first side stream, beside the conversion
+        const hipStream_t sn = L.aux(0);
+        if (sn != L.s) {
+            if ((e = hipEventRecord(L.ev[12], L.s)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(sn, L.ev[12], 0)) != hipSuccess) return e;
+        }
+        if ((e = run_rnodes(rn, Ng, gk, dg, nullptr, nullptr, nullptr, nullptr, sn)) != hipSuccess) return e;
+        if (sn != L.s && (e = hipEventRecord(L.ev[13], sn)) != hipSuccess) return e;
+        if ((e = run_rgather(in, S.d->R, S.d->offs, nb, Ng, Ng, stage, L.s)) != hipSuccess) return e;
+        if ((e = run_leg2cheb(p, nb, stage, Ng, w.chat, w.schat, w, L)) != hipSuccess) return e;
+        if (sn != L.s && (e = hipStreamWaitEvent(L.s, L.ev[13], 0)) != hipSuccess) return e;
+        return run_ndct(p, nb, w.chat, w.schat, nullptr, out, w, L, &rr, S.Q);
+    }
+    if (S.dir == 2) {  // Legendre-to-Chebyshev coefficients, the first N_b of each
+        if ((e = run_rgather(in, S.d->R, S.d->offs, nb, Ng, Ng, stage, L.s)) != hipSuccess) return e;
+        if ((e = run_leg2cheb(p, nb, stage, Ng, w.chat, w.schat, w, L)) != hipSuccess) return e;
+        return run_rscatter(w.chat, w.schat, S.d->R, S.d->offs, nb, Ng, out, L.s);
+    }
+    if (S.dir == 3) {  // Chebyshev expansion (zero-padded) at the Legendre nodes
+        if ((e = run_rnodes(rn, Ng, gk, dg, nullptr, nullptr, nullptr, nullptr, L.s)) != hipSuccess) return e;
+        if ((e = run_rgather(in, S.d->R, S.d->offs, nb, Ng, Ng, stage, L.s)) != hipSuccess) return e;
+        return run_ndct(p, nb, stage, Ng, nullptr, out, w, L, &rr, S.Q);
+    }
+    if ((e = run_rnodes(rn, Ng, gk, dg, wg, nullptr, nullptr, nullptr, L.s)) != hipSuccess) return e;
+    if ((e = run_inverse(p, nb, in, nullptr, nullptr, stage, w, L, &rr, S.Q)) != hipSuccess) return e;
+    return run_rscatter(stage, Ng, S.d->R, S.d->offs, nb, Ng, out, L.s);
+}
+
+// Splits instances idx (one direction, one grid) into slices whose
+// workspace fits WS_CAP; builds their descriptors.
+int rslices_build(int dir, int64_t Ng, int prec, const int64_t* Ns, const int64_t* offs,
+                  const std::vector<int64_t>& idx, std::vector<RSlice>& out, size_t* ws_max) {
+    Plan* p;
+    int rc;
+    if ((rc = get_plan(Ng, prec, &p))) return rc;
+    int64_t per = std::max<int64_t>(1, (int64_t)(WS_CAP / std::max<size_t>(1, rslice_bytes(*p, 1))));
+    per = std::min<int64_t>(per, 32768);  // grid y limit of the gather kernels
+    for (size_t a = 0; a < idx.size(); a += (size_t)per) {
+        std::vector<int64_t> part(idx.begin() + a, idx.begin() + std::min(idx.size(), a + (size_t)per));
+        RSlice S;
+        S.dir = dir;
+        S.Ng = Ng;
+        S.plan = p;
+        S.Q = ragged_Q(prec, Ns, part, Ng);
+        S.d.reset(new RDesc());
+        if ((rc = rdesc_build(Ns, offs, part, *S.d))) return rc;
+        *ws_max = std::max(*ws_max, rslice_bytes(*p, (int64_t)part.size()));
+        out.push_back(std::move(S));
+    }
+    return DLT_OK;
+}
+
+// Equal-size instances of a size that is not a power of two (batch
+// instances at stride N): run directly on the caller's stream; the slices
+// are built once per (device, size, batch, direction, precision).
+int single_entry(int64_t N, int64_t batch, int dir, int prec, SingleEntry** out);
+
+int ragged_equal(int64_t N, int64_t batch, int dir, const double* in, double* out, int prec, hipStream_t s) {
+    SingleEntry* E = nullptr;
+    int rc;
+    if ((rc = single_entry(N, batch, dir, prec, &E))) return rc;
+    void* ws = nullptr;
+    if ((rc = get_ws(s, E->ws_bytes, &ws))) return rc;
+    Lanes L;
+    if ((rc = get_lanes(s, &L))) return rc;
+    for (auto& S : E->slices)
+        if ((rc = hip_status(rslice_run(S, in, out, ws, L)))) return rc;
+    return DLT_OK;
+}
+
+int single_entry(int64_t N, int64_t batch, int dir, int prec, SingleEntry** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    const auto key = std::make_tuple(dev, N, batch, dir, prec);
+    SingleEntry* E = nullptr;
+    {
+        Cache& c = cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.single.find(key);
+        if (it != c.single.end()) E = it->second.get();
+    }
+    int rc;
+    if (!E) {
+        std::unique_ptr<SingleEntry> e(new SingleEntry());
+        std::vector<int64_t> Ns(batch, N), offs(batch), idx(batch);
+        for (int64_t b = 0; b < batch; ++b) {
+            offs[b] = b * N;
+            idx[b] = b;
+        }
+        if ((rc = rslices_build(dir, next_pow2(N), prec, Ns.data(), offs.data(), idx, e->slices, &e->ws_bytes)))
+            return rc;
+        Cache& c = cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        E = c.single.emplace(key, std::move(e)).first->second.get();
+    }
+    *out = E;
+    return DLT_OK;
+}
+
+// Private stream on which batch graphs are captured (one per device and
+// caller stream; capture cannot run on the legacy default stream).
+int capture_stream(hipStream_t user, hipStream_t* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto key = std::make_pair(dev, user);
+    auto it = c.capture.find(key);
+    if (it == c.capture.end()) {
+        hipStream_t cs = nullptr;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return DLT_ERR_HIP;
+        it = c.capture.emplace(key, cs).first;
+    }
+    *out = it->second;
+    return DLT_OK;
+}
+
+// Autotuner: for the instances idx of one direction with largest padded
+// size P, time the grid Ng = P against Ng = 2P (fewer Taylor terms on a
+// twice larger grid) on up to 64 of them (inputs copied to a compact
+// scratch layout, outputs to scratch), once per (device, direction, P,
+// precision).  Synchronous; runs before any capture.
+int tune_grid(int dir, int64_t P, int prec, const int64_t* Ns, const int64_t* offs,
+              const std::vector<int64_t>& idx, const double* in, hipStream_t s, int64_t* Ng) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    const auto key = std::make_tuple(dev, dir, P, prec);
+    {
+        Cache& c = cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.tuned.find(key);
+        if (it != c.tuned.end()) {
+            *Ng = it->second;
+            return DLT_OK;
+        }
+    }
+    *Ng = P;
+    if (2 * P > DLT_MAX_N) return DLT_OK;
+    // compact copy of a sample of the instances
+    std::vector<int64_t> sub(idx.begin(), idx.begin() + std::min<size_t>(idx.size(), 64));
+    std::vector<int64_t> sN(sub.size()), so(sub.size()), sidx(sub.size());
+    int64_t tot = 0;
+    for (size_t i = 0; i < sub.size(); ++i) {
+        sN[i] = Ns[sub[i]];
+        so[i] = tot;
+        sidx[i] = (int64_t)i;
+        tot += sN[i];
+    }
+    double *din = nullptr, *dout = nullptr;
+    if (hipMalloc(&din, tot * sizeof(double)) != hipSuccess) return DLT_ERR_NOMEM;
+    if (hipMalloc(&dout, tot * sizeof(double)) != hipSuccess) {
+        (void)hipFree(din);
+        return DLT_ERR_NOMEM;
+    }
+    int rc = DLT_OK;
+    for (size_t i = 0; i < sub.size() && rc == DLT_OK; ++i)
+        if (hipMemcpyAsync(din + so[i], in + offs[sub[i]], sN[i] * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
+            rc = DLT_ERR_HIP;
+    Lanes L;
+    if (rc == DLT_OK) rc = get_lanes(s, &L);
+    float best = 1e30f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == DLT_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = DLT_ERR_HIP;
+    for (int64_t cand = P; cand <= 2 * P && rc == DLT_OK; cand *= 2) {
+        std::vector<RSlice> sl;
+        size_t wmax = 0;
+        if ((rc = rslices_build(dir, cand, prec, sN.data(), so.data(), sidx, sl, &wmax))) break;
+        void* ws = nullptr;
+        if ((rc = get_ws(s, wmax, &ws))) break;
+        float ms = 0;
+        for (int rep = 0; rep < 3 && rc == DLT_OK; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) rc = DLT_ERR_HIP;
+            for (auto& S : sl)
+                if (rc == DLT_OK) rc = hip_status(rslice_run(S, din, dout, ws, L));
+        }
+        if (rc == DLT_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = DLT_ERR_HIP;
+        if (rc == DLT_OK && ms < best) {
+            best = ms;
+            *Ng = cand;
+        }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && rc == DLT_OK) rc = DLT_ERR_HIP;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(din);
+    (void)hipFree(dout);
+    if (rc != DLT_OK) return rc;
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.tuned[key] = *Ng;
+    return DLT_OK;
+}
+
+bool is_pow2_n(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// arguments of the single-size entry points: power-of-two sizes take the
+// plain path; other sizes up to DLT_MAX_N the padded-grid path
+int check_any_size(int64_t N, int64_t batch) {
+    if (N < 1 || batch < 0) return DLT_ERR_INVALID_ARG;
+    if (N > DLT_MAX_N) return DLT_ERR_UNSUPPORTED;
+    return DLT_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int dlt_batch_ex(int64_t count, const int64_t* Ns, const int64_t* offsets, const int8_t* inverse,
+                 const double* in, double* out, int prec, hipStream_t stream) {
+    if (count < 0) return DLT_ERR_INVALID_ARG;
+    if (count == 0) return DLT_OK;
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    if (!Ns || !offsets || !in || !out) return DLT_ERR_INVALID_ARG;
+    int64_t lo = INT64_MAX, hi = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        if (Ns[i] < 1 || offsets[i] < 0) return DLT_ERR_INVALID_ARG;
+        if (Ns[i] > DLT_MAX_N) return DLT_ERR_UNSUPPORTED;
+        if (inverse && inverse[i] != 0 && inverse[i] != 1) return DLT_ERR_INVALID_ARG;
+        lo = std::min(lo, offsets[i]);
+        hi = std::max(hi, offsets[i] + Ns[i]);
+    }
+    if (overlap(in + lo, out + lo, (size_t)(hi - lo) * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    std::vector<int64_t> key;
+    key.reserve(3 * count + 6);
+    key.push_back(dev);
+    key.push_back(prec);
+    key.push_back((int64_t)(uintptr_t)in);
+    key.push_back((int64_t)(uintptr_t)out);
+    key.push_back((int64_t)(uintptr_t)stream);
+    key.push_back(count);
+    for (int64_t i = 0; i < count; ++i) {
+        key.push_back(Ns[i]);
+        key.push_back(offsets[i]);
+        key.push_back(inverse ? inverse[i] : 0);
+    }
+    BatchEntry* E = nullptr;
+    {
+        Cache& c = cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.graphs.find(key);
+        if (it != c.graphs.end()) E = it->second.get();
+    }
+    if (!E) {
+        std::unique_ptr<BatchEntry> e(new BatchEntry());
+        // size classes: direction and padded size
+        std::map<std::pair<int, int64_t>, std::vector<int64_t>> cls;
+        for (int64_t i = 0; i < count; ++i) cls[{inverse ? (int)inverse[i] : 0, next_pow2(Ns[i])}].push_back(i);
+        size_t wmax = 0;
+        for (auto& kv : cls) {
+            int64_t Ng = kv.first.second;
+            if ((rc = tune_grid(kv.first.first, kv.first.second, prec, Ns, offsets, kv.second, in, stream, &Ng)))
+                return rc;
+            if ((rc = rslices_build(kv.first.first, Ng, prec, Ns, offsets, kv.second, e->slices, &wmax))) return rc;
+        }
+        if (hipMalloc(&e->ws, wmax) != hipSuccess) return DLT_ERR_NOMEM;
+        // capture every slice into one graph on a private stream
+        hipStream_t cs;
+        if ((rc = capture_stream(stream, &cs))) return rc;
+        Lanes L;
+        if ((rc = get_lanes(cs, &L))) return rc;
+        const bool tr = trace_on();
+        trace_set(false);
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) rc = DLT_ERR_HIP;
+        for (auto& S : e->slices)
+            if (rc == DLT_OK) rc = hip_status(rslice_run(S, in, out, e->ws, L));
+        hipError_t ce = hipStreamEndCapture(cs, &g);
+        trace_set(tr);
+        if (rc == DLT_OK && ce != hipSuccess) rc = DLT_ERR_HIP;
+        if (rc == DLT_OK && hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0) != hipSuccess) rc = DLT_ERR_HIP;
+        if (g) (void)hipGraphDestroy(g);
+        if (rc) return rc;
+        Cache& c = cache();
+        std::lock_guard<std::mutex> lk(c.mu);
+        E = c.graphs.emplace(key, std::move(e)).first->second.get();
+    }
+    return hip_status(hipGraphLaunch(E->exec, stream));
+}
+
+
 
 const char* dlt_status_string(int st) {
     switch (st) {
@@ -177,18 +607,26 @@ const char* dlt_status_string(int st) {
 }
 
 int leg_nodes_weights(int64_t N, int64_t batch, double* theta, double* w, double* dtheta, hipStream_t stream) {
-    int rc = check_size(N, batch);
+    int rc = check_any_size(N, batch);
     if (rc) return rc;
     if (batch == 0 || (!theta && !w && !dtheta)) return DLT_OK;
     size_t bytes = (size_t)N * sizeof(double) * (size_t)batch;
     if ((theta && w && overlap(theta, w, bytes)) || (theta && dtheta && overlap(theta, dtheta, bytes)) ||
         (w && dtheta && overlap(w, dtheta, bytes)))
         return DLT_ERR_INVALID_ARG;
-    Plan* p;
-    if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
-    CallWS cw;
-    if ((rc = setup_call(*p, 0, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, cw.nscr, cw.lanes)))) return rc;
+    if (!is_pow2_n(N)) {
+        SingleEntry* E;
+        if ((rc = single_entry(N, 1, 4, DLT_PREC_FP64, &E))) return rc;
+        const RDesc& d = *E->slices[0].d;
+        const RaggedNodes rn{d.R, d.ioff, d.boff, d.nb, d.ni, d.nbd};
+        if ((rc = hip_status(run_rnodes(rn, 0, nullptr, nullptr, nullptr, theta, w, dtheta, stream)))) return rc;
+    } else {
+        Plan* p;
+        if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
+        CallWS cw;
+        if ((rc = setup_call(*p, 0, stream, cw))) return rc;
+        if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, cw.nscr, cw.lanes)))) return rc;
+    }
     for (int64_t b = 1; b < batch; ++b) {
         size_t vb = (size_t)N * sizeof(double);
         if (theta && hipMemcpyAsync(theta + b * N, theta, vb, hipMemcpyDeviceToDevice, stream)) return DLT_ERR_HIP;
@@ -204,11 +642,12 @@ int leg2cheb(int64_t N, int64_t batch, const double* c, double* chat, hipStream_
 }
 
 int leg2cheb_ex(int64_t N, int64_t batch, const double* c, double* chat, int prec, hipStream_t stream) {
-    int rc = check_size(N, batch);
+    int rc = check_any_size(N, batch);
     if (rc) return rc;
     if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
     if (!c || !chat || overlap(c, chat, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    if (!is_pow2_n(N)) return ragged_equal(N, batch, 2, c, chat, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
     CallWS cw;
@@ -225,11 +664,12 @@ int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, h
 }
 
 int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f, int prec, hipStream_t stream) {
-    int rc = check_size(N, batch);
+    int rc = check_any_size(N, batch);
     if (rc) return rc;
     if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
     if (!chat || !f || overlap(chat, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    if (!is_pow2_n(N)) return ragged_equal(N, batch, 3, chat, f, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
     CallWS cw;
@@ -247,11 +687,12 @@ int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_
 }
 
 int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int prec, hipStream_t stream) {
-    int rc = check_size(N, batch);
+    int rc = check_any_size(N, batch);
     if (rc) return rc;
     if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
     if (!c || !f || overlap(c, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    if (!is_pow2_n(N)) return ragged_equal(N, batch, 0, c, f, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
     CallWS cw;
@@ -280,11 +721,12 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
 }
 
 int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int prec, hipStream_t stream) {
-    int rc = check_size(N, batch);
+    int rc = check_any_size(N, batch);
     if (rc) return rc;
     if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
     if (!f || !c || overlap(f, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    if (!is_pow2_n(N)) return ragged_equal(N, batch, 1, f, c, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
     CallWS cw;
@@ -358,6 +800,11 @@ int dlt_release(void) {
             if (kv.second.ev[i]) (void)hipEventDestroy(kv.second.ev[i]);
     }
     c.lanes.clear();
+    c.graphs.clear();  // graph executables, their workspaces and descriptors
+    c.single.clear();
+    c.tuned.clear();
+    for (auto& kv : c.capture) (void)hipStreamDestroy(kv.second);
+    c.capture.clear();
     return DLT_OK;
 }
 

@@ -35,12 +35,9 @@ __device__ __forceinline__ cplx half_shift(int64_t n, int N) {
 //   (N+m+1/2) theta*_k - (m+1/2) pi/2 = (k+1/2) pi + (m+1/2)(theta*_k - pi/2),
 // so cos(phase) = -(-1)^k sin psi_m, sin(phase) = (-1)^k cos psi_m with
 // psi_m = (m+1/2)(theta - pi/2) + N delta.
-__global__ void k_nodes_interior(NodeParams P, double* __restrict__ theta, double* __restrict__ w,
-                                 double* __restrict__ dth) {
+// theta_k - theta*_k (delta) and w_k of interior node k of P_N.
+__device__ void node_interior(const NodeParams& P, int k, double& delta_out, double& w_out) {
     const int N = P.N;
-    const int nh = (N + 1) / 2;
-    int k = P.kb + blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nh) return;
     const double pi = 3.141592653589793;
     const double nu = N + 0.5;
     // start: psi + cot(psi)/(8 nu^2), psi = (k+3/4) pi/nu (two terms of the
@@ -80,9 +77,16 @@ __global__ void k_nodes_interior(NodeParams P, double* __restrict__ theta, doubl
     }
     // dP/dtheta = -(-1)^k C D;  w = 2 / (dP/dtheta)^2
     double dP = P.C * Dv;
-    double wk = 2.0 / (dP * dP);
-    double th = ts + delta;
-    int k2 = N - 1 - k;
+    delta_out = delta;
+    w_out = 2.0 / (dP * dP);
+}
+
+// node k (k < ceil(N/2)) and its mirror N-1-k into theta, w, dtheta
+__device__ __forceinline__ void emit_node(int N, int k, double delta, double wk, double* __restrict__ theta,
+                                          double* __restrict__ w, double* __restrict__ dth) {
+    const double pi = 3.141592653589793;
+    const double th = (k + 0.5) * pi / N + delta;
+    const int k2 = N - 1 - k;
     if (theta) {
         theta[k] = th;
         if (k2 != k) theta[k2] = pi - th;
@@ -95,6 +99,17 @@ __global__ void k_nodes_interior(NodeParams P, double* __restrict__ theta, doubl
         dth[k] = delta;
         if (k2 != k) dth[k2] = -delta;
     }
+}
+
+__global__ void k_nodes_interior(NodeParams P, double* __restrict__ theta, double* __restrict__ w,
+                                 double* __restrict__ dth) {
+    const int N = P.N;
+    const int nh = (N + 1) / 2;
+    int k = P.kb + blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nh) return;
+    double delta, wk;
+    node_interior(P, k, delta, wk);
+    emit_node(N, k, delta, wk, theta, w, dth);
 }
 
 // One step n -> n+1 of the Legendre recurrence in u = 2 sin^2(theta/2)
@@ -190,20 +205,20 @@ __device__ void block_legendre_pair(int N, double t, double* sh, double* pN, dou
 
 // Boundary nodes k < kb.  The start `guess` (offset from theta*_k) is the
 // Bessel-zero form theta ~ psi + (psi cot psi - 1)/(8 psi nu^2), psi =
-// j_{0,k+1}/nu, nu = N + 1/2, whose error is O(nu^-4) (one ulp from
-// N = 4096 on), or theta^cheb* for small N; `newton_b` Newton steps with the
+// j_{0,k+1}/nu, nu = N + 1/2, whose error is O(nu^-4) (2.5 ulp or less from
+// N = 2048 on), or theta^cheb* for small N; `newton_b` Newton steps with the
 // exact recurrence follow (none for large N, where the FP64 recurrence is
 // less accurate than the start).  The weight is the Christoffel number
 // w_k = 2 / sum_{n<N} (2n+1) P_n(x_k)^2, which is well conditioned in x_k.
-__global__ __launch_bounds__(1024) void k_nodes_boundary(NodeParams P, const double* __restrict__ guess,
-                                                        double* __restrict__ theta, double* __restrict__ w,
-                                                        double* __restrict__ dth) {
-    extern __shared__ double sh[];
+// Boundary node k: Newton steps from the start `guess0` with the exact
+// recurrence (all threads of the block take part; `sh` holds 7*blockDim.x
+// doubles), then the Christoffel weight.  Results valid in every thread.
+__device__ void node_boundary(const NodeParams& P, double guess0, int k, double* sh, double& delta_out,
+                              double& w_out) {
     const int N = P.N;
-    const int k = blockIdx.x;
     const double pi = 3.141592653589793;
     const double ts = (k + 0.5) * pi / N;
-    double delta = guess[k];
+    double delta = guess0;
     double pN, pN1, kc;
     const bool middle = (N & 1) && (k == (N - 1) / 2);
     if (middle) {
@@ -220,26 +235,20 @@ __global__ __launch_bounds__(1024) void k_nodes_boundary(NodeParams P, const dou
             if (fabs(step) <= 2.2e-16 * th) break;  // uniform across the block
         }
     }
-    double th = ts + delta;
-    block_legendre_pair(N, th, sh, &pN, &pN1, &kc);
-    if (threadIdx.x == 0) {
-        double wk = 2.0 / kc;
-        int k2 = N - 1 - k;
-        if (theta) {
-            theta[k] = th;
-            if (k2 != k) theta[k2] = pi - th;
-        }
-        if (w) {
-            w[k] = wk;
-            if (k2 != k) w[k2] = wk;
-        }
-        if (dth) {
-            dth[k] = delta;
-            if (k2 != k) dth[k2] = -delta;
-        }
-    }
+    block_legendre_pair(N, ts + delta, sh, &pN, &pN1, &kc);
+    delta_out = delta;
+    w_out = 2.0 / kc;
 }
 
+__global__ __launch_bounds__(1024) void k_nodes_boundary(NodeParams P, const double* __restrict__ guess,
+                                                        double* __restrict__ theta, double* __restrict__ w,
+                                                        double* __restrict__ dth) {
+    extern __shared__ double sh[];
+    const int k = blockIdx.x;
+    double delta, wk;
+    node_boundary(P, guess[k], k, sh, delta, wk);
+    if (threadIdx.x == 0) emit_node(P.N, k, delta, wk, theta, w, dth);
+}
 
 // Boundary nodes for large N (no Newton step: the Bessel-zero start is
 // within an ulp): block (k, part) produces the transfer data of degrees
@@ -315,6 +324,98 @@ __global__ void k_nodes_bfin(NodeParams P, const double* __restrict__ guess, int
         dth[k] = delta;
         if (k2 != k) dth[k2] = -delta;
     }
+}
+
+// --------------------------------------------------------- ragged batches --
+// Instances of uneven size N_b share one power-of-two grid of size Ng >= N_b
+// (the Chebyshev points (j+1/2) pi/Ng).  Every node of P_{N_b} is paired with
+// its nearest grid row j; since the node spacing exceeds pi/Ng when Ng > N_b
+// the pairing is one-to-one, and |Ng (theta_k - theta*_j)| <= pi/2 (for
+// Ng = N_b it is the identity and Lemma 2 applies).  The Taylor series then
+// runs about theta*_j with d = Ng (theta_k - theta*_j).
+__device__ __forceinline__ int ragged_find(const int* __restrict__ off, int nb, int t) {
+    int lo = 0, hi = nb;  // largest b with off[b] <= t
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void map_node(int N, int Ng, int k, double delta, double wk, int* __restrict__ gk,
+                                         double* __restrict__ dg, double* __restrict__ wg) {
+    const double pi = 3.141592653589793;
+    for (int side = 0; side < 2; ++side) {
+        const int kk = side ? N - 1 - k : k;
+        if (side && kk == k) break;
+        const double dd = side ? -delta : delta;
+        int j = (int)rint((2.0 * kk + 1.0) * Ng / (2.0 * N) + dd * Ng / pi - 0.5);
+        j = min(max(j, 0), Ng - 1);
+        const int64_t I = (int64_t)(2 * kk + 1) * Ng - (int64_t)(2 * j + 1) * N;
+        gk[j] = kk;
+        dg[j] = Ng * dd + pi * (double)I / (2.0 * N);
+        if (wg) wg[j] = wk;
+    }
+}
+
+// Interior nodes of every instance, one thread each (ioff: prefix sums of
+// the instances' interior node counts).  Writes the grid tables, and theta,
+// w, dtheta of instance 0 when given (single non-power-of-two size).
+__global__ void k_rnodes_interior(const RNode* __restrict__ R, const int* __restrict__ ioff, int nb, int Ng,
+                                  int* __restrict__ gk, double* __restrict__ dg, double* __restrict__ wg,
+                                  double* __restrict__ theta, double* __restrict__ w, double* __restrict__ dth) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ioff[nb]) return;
+    const int b = ragged_find(ioff, nb, t);
+    const NodeParams& P = R[b].P;
+    const int k = P.kb + (t - ioff[b]);
+    double delta, wk;
+    node_interior(P, k, delta, wk);
+    if (gk) map_node(P.N, Ng, k, delta, wk, gk + (int64_t)b * Ng, dg + (int64_t)b * Ng, wg ? wg + (int64_t)b * Ng : nullptr);
+    if (theta || w || dth) emit_node(P.N, k, delta, wk, theta, w, dth);
+}
+
+// Boundary nodes of every instance, one block of 256 threads each (boff:
+// prefix sums of the boundary node counts).
+__global__ __launch_bounds__(256) void k_rnodes_boundary(const RNode* __restrict__ R, const int* __restrict__ boff,
+                                                         int nb, int Ng, int* __restrict__ gk,
+                                                         double* __restrict__ dg, double* __restrict__ wg,
+                                                         double* __restrict__ theta, double* __restrict__ w,
+                                                         double* __restrict__ dth) {
+    __shared__ double sh[7 * 256];
+    const int t = blockIdx.x;
+    if (t >= boff[nb]) return;  // uniform per block
+    const int b = ragged_find(boff, nb, t);
+    const int k = t - boff[b];
+    double delta, wk;
+    node_boundary(R[b].P, R[b].guess[k], k, sh, delta, wk);
+    if (threadIdx.x == 0) {
+        const int N = R[b].P.N;
+        if (gk) map_node(N, Ng, k, delta, wk, gk + (int64_t)b * Ng, dg + (int64_t)b * Ng, wg ? wg + (int64_t)b * Ng : nullptr);
+        if (theta || w || dth) emit_node(N, k, delta, wk, theta, w, dth);
+    }
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int64_t n, int v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// out[b*stride + n] = in[offs[b] + n] for n < N_b, 0 up to Ng (zero padding)
+__global__ void k_rgather(const double* __restrict__ in, const RNode* __restrict__ R,
+                          const int64_t* __restrict__ offs, int Ng, int64_t stride, double* __restrict__ out) {
+    const int b = blockIdx.y;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= Ng) return;
+    out[(int64_t)b * stride + n] = (n < R[b].P.N) ? in[offs[b] + n] : 0.0;
+}
+
+// out[offs[b] + n] = in[b*stride + n] for n < N_b
+__global__ void k_rscatter(const double* __restrict__ in, int64_t stride, const RNode* __restrict__ R,
+                           const int64_t* __restrict__ offs, double* __restrict__ out) {
+    const int b = blockIdx.y;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < R[b].P.N) out[offs[b] + n] = in[(int64_t)b * stride + n];
 }
 
 // ------------------------------------------------------------------ dense --
@@ -970,7 +1071,8 @@ __global__ FFT_BOUNDS void k_ndct_passA(Geo g, int qa, int qb, int QG, const dou
 template <int LB, class R>
 __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X0, int64_t x0_stride,
                                         const cplxT<R>* __restrict__ X1, int64_t x1_stride,
-                                        const double* __restrict__ dth, double* __restrict__ f, int64_t f_stride) {
+                                        const double* __restrict__ dth, double* __restrict__ f, int64_t f_stride,
+                                        RaggedRows RR) {
     __shared__ cplx bufd[FFT_LDS];
     cplxT<R>* bufr = reinterpret_cast<cplxT<R>*>(bufd);
     STAGE_TW(stwd, LB, double);
@@ -989,13 +1091,22 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
     const cplx* X0b = X0 + b * x0_stride;
     const cplxT<R>* X1b = X1 + b * x1_stride;
     double acc[FFT_VPT], d[FFT_VPT];
+    int kn[FFT_VPT];  // output index: grid row, or the node paired with it (-1: none)
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         acc[s] = 0;
         d[s] = 0;
+        kn[s] = -1;
         if (T.live(s)) {
             const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
-            d[s] = (double)N * dth[row_of(m, N)];
+            const int r = row_of(m, N);
+            if (RR.gk) {
+                kn[s] = RR.gk[(int64_t)b * N + r];
+                d[s] = (kn[s] >= 0) ? RR.dg[(int64_t)b * N + r] : 0.0;
+            } else {
+                kn[s] = r;
+                d[s] = (double)N * dth[r];
+            }
         }
     }
     auto horner = [&](int q, const cplx* U) {
@@ -1041,14 +1152,10 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
         tile_fft<LB>(n0, bufd, twd, T);
         horner(0, n0);
     }
-    double* fb = f + b * f_stride;
+    double* fb = RR.gk ? f + RR.offs[b] : f + b * f_stride;
 #pragma unroll
-    for (int s = 0; s < FFT_VPT; ++s) {
-        if (T.live(s)) {
-            const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
-            fb[row_of(m, N)] = acc[s];
-        }
-    }
+    for (int s = 0; s < FFT_VPT; ++s)
+        if (kn[s] >= 0) fb[kn[s]] = acc[s];
 }
 
 
@@ -1063,7 +1170,8 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
 template <int LA, class R>
 __global__ FFT_BOUNDS void k_tndct_passA(Geo g, int qa, int qb, int QG, const double* __restrict__ fv,
                                          int64_t f_stride, const double* __restrict__ wts,
-                                         const double* __restrict__ dth, cplxT<R>* __restrict__ X, int64_t x_stride) {
+                                         const double* __restrict__ dth, cplxT<R>* __restrict__ X, int64_t x_stride,
+                                         RaggedRows RR) {
     __shared__ cplxT<R> buf[FFT_LDS];
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
@@ -1082,9 +1190,16 @@ __global__ FFT_BOUNDS void k_tndct_passA(Geo g, int qa, int qb, int QG, const do
         gv[s] = dv[s] = d2[s] = 0;
         if (T.live(s)) {
             const int m = na0 + T.col(s) + g.N1 * T.idx(s);
-            const int kk = row_of(m, N);
-            const double d = (double)N * dth[kk];
-            double p = wts[kk] * fb[kk];
+            const int r = row_of(m, N);
+            double d, p;
+            if (RR.gk) {
+                const int kk = RR.gk[(int64_t)b * N + r];
+                d = (kk >= 0) ? RR.dg[(int64_t)b * N + r] : 0.0;
+                p = (kk >= 0) ? RR.wg[(int64_t)b * N + r] * fv[RR.offs[b] + kk] : 0.0;
+            } else {
+                d = (double)N * dth[r];
+                p = wts[r] * fb[r];
+            }
             for (int q = 0; q < q0; ++q) p *= d * d;
             gv[s] = p;  // g_k d_k^{2q}
             d2[s] = d * d;
@@ -1984,11 +2099,12 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
 }
 
 hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
-                    Work& w, const Lanes& L) {
+                    Work& w, const Lanes& L, const RaggedRows* rr, int Qo) {
     trace_n = p.N;
     const Geo& g = p.geo;
     const hipStream_t s = L.s;
-    const int Q = p.L / 2;
+    const int Q = Qo > 0 ? Qo : p.L / 2;
+    const RaggedRows RR = rr ? *rr : RaggedRows{nullptr, nullptr, nullptr, nullptr};
     const int tilesA = g.N1 / g.colsA;
     const int N = (int)p.N;
     const dim3 gB(g.N2 / g.rowsB, 1, (unsigned)nb);
@@ -2005,7 +2121,7 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
                 LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_ndct_passA, float, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 1, Q, QG, chat, hs, X1, s1);
             });
         traced("k_ndct_passB_f32", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_ndct_passB, float, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, X1, s1, dth, f, p.N);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_ndct_passB, float, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, X1, s1, dth, f, p.N, RR);
         });
     } else {
         // small transforms: split the Taylor pairs over blocks for parallelism
@@ -2014,19 +2130,20 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_ndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, chat, hs, w.X, w.sX);
         });
         traced("k_ndct_passB", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_ndct_passB, double, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, w.X + N, w.sX, dth, f, p.N);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_ndct_passB, double, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, w.X + N, w.sX, dth, f, p.N, RR);
         });
     }
     return hipGetLastError();
 }
 
 hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double* wts, const double* dth,
-                       double* c, Work& w, const Lanes& L) {
+                       double* c, Work& w, const Lanes& L, const RaggedRows* rr, int Qo) {
     trace_n = p.N;
     const int N = (int)p.N;
     const Geo& g = p.geo;
     const hipStream_t s = L.s;
-    const int Q = p.L / 2;
+    const int Q = Qo > 0 ? Qo : p.L / 2;
+    const RaggedRows RR = rr ? *rr : RaggedRows{nullptr, nullptr, nullptr, nullptr};
     const int tilesA = g.N1 / g.colsA;
     double* y = w.chat;  // T^T D_w f, stride w.schat
     const int tilesB = (g.N2 == 1) ? 1 : g.N2 / g.rowsB;
@@ -2036,11 +2153,11 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
         const int64_t s1 = 2 * w.sX;
         const int QG = (tilesA * nb >= 256) ? 1 : std::max(Q - 1, 1);
         traced("k_tndct_passA", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, 1, 1, f, N, wts, dth, w.X, w.sX);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, 1, 1, f, N, wts, dth, w.X, w.sX, RR);
         });
         if (Q > 1)
             traced("k_tndct_passA_f32", s, [&] {
-                LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, float, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 1, Q, QG, f, N, wts, dth, X1, s1);
+                LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, float, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 1, Q, QG, f, N, wts, dth, X1, s1, RR);
             });
         traced("k_tndct_passB_f32", s, [&] {
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tndct_passB, float, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, X1, s1, y, w.schat);
@@ -2048,13 +2165,46 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
     } else {
         const int QG = (tilesA * nb >= 256) ? 1 : Q;
         traced("k_tndct_passA", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, f, N, wts, dth, w.X, w.sX);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, f, N, wts, dth, w.X, w.sX, RR);
         });
         traced("k_tndct_passB", s, [&] {
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tndct_passB, double, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, w.X + N, w.sX, y, w.schat);
         });
     }
     return run_leg2cheb_t(p, nb, y, w.schat, c, N, 1, w, L);
+}
+
+hipError_t run_rnodes(const RaggedNodes& rn, int Ng, int* gk, double* dg, double* wg, double* theta, double* w,
+                      double* dth, hipStream_t s) {
+    trace_n = Ng;
+    if (gk) {
+        const int64_t n = (int64_t)rn.nb * Ng;
+        traced("k_fill_int", s, [&] { k_fill_int<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(gk, n, -1); });
+    }
+    if (rn.nbnd_total > 0)
+        traced("k_rnodes_boundary", s, [&] {
+            k_rnodes_boundary<<<rn.nbnd_total, 256, 0, s>>>(rn.R, rn.boff, rn.nb, Ng, gk, dg, wg, theta, w, dth);
+        });
+    if (rn.ni_total > 0)
+        traced("k_rnodes_interior", s, [&] {
+            k_rnodes_interior<<<(rn.ni_total + 255) / 256, 256, 0, s>>>(rn.R, rn.ioff, rn.nb, Ng, gk, dg, wg, theta, w,
+                                                                       dth);
+        });
+    return hipGetLastError();
+}
+
+hipError_t run_rgather(const double* in, const RNode* R, const int64_t* offs, int nb, int Ng, int64_t stride,
+                       double* out, hipStream_t s) {
+    trace_n = Ng;
+    traced("k_rgather", s, [&] { k_rgather<<<dim3((Ng + 255) / 256, nb), 256, 0, s>>>(in, R, offs, Ng, stride, out); });
+    return hipGetLastError();
+}
+
+hipError_t run_rscatter(const double* in, int64_t stride, const RNode* R, const int64_t* offs, int nb, int Ng,
+                        double* out, hipStream_t s) {
+    trace_n = Ng;
+    traced("k_rscatter", s, [&] { k_rscatter<<<dim3((Ng + 255) / 256, nb), 256, 0, s>>>(in, stride, R, offs, out); });
+    return hipGetLastError();
 }
 
 }  // namespace dlt

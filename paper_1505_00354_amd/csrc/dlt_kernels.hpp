@@ -58,13 +58,33 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
 // out = M^T y (times n + 1/2 when half != 0)
 hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys, double* out, int64_t os, int half,
                           Work& w, const Lanes& L);
-// f = sum_n chat_n cos(n theta^leg), dth = theta^leg - theta^cheb1
+// f = sum_n chat_n cos(n theta^leg), dth = theta^leg - theta^cheb1.  With
+// per-row tables `rr` (ragged batch) the nodes come from rr, outputs go to
+// f + rr->offs[b] and dth is unused; Q > 0 overrides the plan's Taylor pairs.
 hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
-                    Work& w, const Lanes& L);
+                    Work& w, const Lanes& L, const RaggedRows* rr = nullptr, int Q = 0);
 
-// c = D_s M^T T^T D_w f (inverse transform), wts/dth from the nodes
+// c = D_s M^T T^T D_w f (inverse transform), wts/dth from the nodes; with
+// `rr` the inputs are f + rr->offs[b] paired through rr (wts, dth unused) and
+// c has stride p.N.
 hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double* wts, const double* dth,
-                       double* c, Work& w, const Lanes& L);
+                       double* c, Work& w, const Lanes& L, const RaggedRows* rr = nullptr, int Q = 0);
+
+// Ragged batches: node tables on the grid of size Ng for nb instances
+// (R, ioff, boff device arrays; totals of interior and boundary nodes), and
+// the zero-padded gather / scatter between the caller's layout and the grid.
+struct RaggedNodes {
+    const RNode* R;
+    const int* ioff;
+    const int* boff;
+    int nb, ni_total, nbnd_total;
+};
+hipError_t run_rnodes(const RaggedNodes& rn, int Ng, int* gk, double* dg, double* wg, double* theta, double* w,
+                      double* dth, hipStream_t s);
+hipError_t run_rgather(const double* in, const RNode* R, const int64_t* offs, int nb, int Ng, int64_t stride,
+                       double* out, hipStream_t s);
+hipError_t run_rscatter(const double* in, int64_t stride, const RNode* R, const int64_t* offs, int nb, int Ng,
+                        double* out, hipStream_t s);
 
 // kernel trace (events around every launch while enabled)
 bool trace_on();

@@ -95,6 +95,35 @@ static double bessel_j0_zero(int k) {
     return x;
 }
 
+void rnode_build(int64_t N, RNode& r) {
+    memset(&r, 0, sizeof(r));
+    NodeParams& ndp = r.P;
+    ndp.N = (int)N;
+    ndp.Ms = MAX_NODE_M;
+    int nh = (int)((N + 1) / 2);
+    ndp.kb = (int)std::min<int64_t>(nh, 6);
+    if (N < 128) ndp.kb = nh;
+    // the Bessel-zero start is within 2.5 ulp from N = 2048 on (one FP64
+    // recurrence Newton step there would add several ulp); below, one step
+    ndp.newton_b = (N >= 2048) ? 0 : (N >= 64) ? 1 : 12;
+    ndp.C = (double)stieltjes_C_host((LD)N);
+    for (int m = 0; m < MAX_NODE_M; ++m) ndp.h[m] = (double)stieltjes_h(m, (LD)N);
+    // boundary-node starting offsets from theta^cheb1_k = (k+1/2) pi/N:
+    // Bessel-zero form theta ~ psi + (psi cot psi - 1)/(8 psi nu^2),
+    // psi = j_{0,k+1}/nu, nu = N+1/2, for N >= 64; else theta^cheb*.
+    LD nu = (LD)N + 0.5L;
+    for (int k = 0; k < ndp.kb; ++k) {
+        LD th;
+        if (N >= 64) {
+            LD psi = (LD)bessel_j0_zero(k) / nu;
+            th = psi + (psi * cosl(psi) / sinl(psi) - 1) / (8 * psi * nu * nu);
+        } else {
+            th = ((LD)k + 0.75L) * PI_L / nu;
+        }
+        r.guess[k] = (double)(th - ((LD)k + 0.5L) * PI_L / (LD)N);
+    }
+}
+
 int plan_build(int64_t N, int prec, Plan& p) {
     memset(&p.geo, 0, sizeof(p.geo));
     p.N = N;
@@ -279,37 +308,18 @@ int plan_build(int64_t N, int prec, Plan& p) {
     }
 
     // ---- nodes
-    NodeParams& ndp = p.nodes;
-    memset(&ndp, 0, sizeof(ndp));
-    ndp.N = (int)N;
-    ndp.Ms = MAX_NODE_M;
-    int nh = (int)((N + 1) / 2);
-    ndp.kb = (int)std::min<int64_t>(nh, 6);
-    if (N < 128) ndp.kb = nh;
-    ndp.newton_b = (N >= 4096) ? 0 : (N >= 64) ? 1 : 12;
-    ndp.C = (double)stieltjes_C_host((LD)N);
-    for (int m = 0; m < MAX_NODE_M; ++m) ndp.h[m] = (double)stieltjes_h(m, (LD)N);
     {
-        // boundary-node starting offsets from theta^cheb1_k = (k+1/2) pi/N:
-        // Bessel-zero form theta ~ psi + (psi cot psi - 1)/(8 psi nu^2),
-        // psi = j_{0,k+1}/nu, nu = N+1/2, for N >= 64; else theta^cheb*.
-        std::vector<double> gsv(ndp.kb > 0 ? ndp.kb : 1);
-        LD nu = (LD)N + 0.5L;
-        for (int k = 0; k < ndp.kb; ++k) {
-            LD th;
-            if (N >= 64) {
-                LD psi = (LD)bessel_j0_zero(k) / nu;
-                th = psi + (psi * cosl(psi) / sinl(psi) - 1) / (8 * psi * nu * nu);
-            } else {
-                th = ((LD)k + 0.75L) * PI_L / nu;
-            }
-            gsv[k] = (double)(th - ((LD)k + 0.5L) * PI_L / (LD)N);
-        }
-        if ((rc = upload(gsv.data(), gsv.size() * sizeof(double), (void**)&p.d_guess))) return rc;
+        RNode rn;
+        rnode_build(N, rn);
+        p.nodes = rn.P;
+        if ((rc = upload(rn.guess, (size_t)std::max(rn.P.kb, 1) * sizeof(double), (void**)&p.d_guess))) return rc;
     }
 
     // ---- workspace per instance
-    int nX = std::max({F.nterm, p.L / 2, 1});
+    // Taylor pairs: the plan's, or up to RAGGED_Q_MAX for grids shared by
+    // smaller sizes (nodes up to half a grid step from their rows)
+    const int qmax = bulk ? RAGGED_Q_MAX_BULK : RAGGED_Q_MAX;
+    int nX = std::max({F.nterm, p.L / 2, qmax, 1});
     {
         // enough blocks per pass to fill the GPU: at least 512 (tile, group) pairs
         int tilesA = g.N1 / g.colsA, tilesB = g.N2 / g.rowsB;
@@ -320,7 +330,7 @@ int plan_build(int64_t N, int prec, Plan& p) {
     p.ws_X = (size_t)nX * N * sizeof(cplx);
     if (f32)  // FP32 far terms; or the FP64 Taylor pair 0 + FP32 pairs 1..Q-1
         p.ws_X = std::max((size_t)std::max(F.nterm, 1) * N * sizeof(cplxf),
-                          (size_t)N * sizeof(cplx) + (size_t)(p.L / 2 - 1) * N * sizeof(cplxf));
+                          (size_t)N * sizeof(cplx) + (size_t)(qmax - 1) * N * sizeof(cplxf));
     // the low-degree sub-run has its own region: it runs beside the far field
     p.ws_sub = p.sub ? p.sub->ws_per_inst : 0;
     p.ws_v = (size_t)p.tgB * N * sizeof(double);

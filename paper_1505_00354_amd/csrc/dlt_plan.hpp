@@ -21,6 +21,10 @@ constexpr int NEAR_NSUB = NEAR_CHUNK / NEAR_SUB;
 constexpr int64_t MAX_N = int64_t(1) << 20;
 constexpr int DENSE_MAX = 8192;         // largest low-degree block done by the dense matrix
 constexpr int64_t RECURSE_FROM = 1 << 17;  // from this N on the low block is N/16, recursively
+// Taylor pairs a grid may run for sizes padded to it (|d| n/Ng <= pi/2):
+// L = 20 for 5e-15, L = 12 for 5e-7
+constexpr int RAGGED_Q_MAX = 10;
+constexpr int RAGGED_Q_MAX_BULK = 6;
 
 // FFT geometry of the length-N DFT (N power of two): N = N1*N2.  Pass A runs
 // length-N2 DFTs over the slow input index for tiles of colsA columns; pass B
@@ -66,6 +70,27 @@ struct NodeParams {
     int N, kb, Ms, newton_b;   // boundary nodes k < kb use the recurrence
     double C;                  // C_N of the Stieltjes series
     double h[MAX_NODE_M];      // h_{m,N}
+};
+
+// Node parameters of one instance of a ragged batch: its NodeParams and the
+// starting offsets of its boundary nodes (kb <= RNODE_GUESS).
+constexpr int RNODE_GUESS = 64;
+struct RNode {
+    NodeParams P;
+    double guess[RNODE_GUESS];
+};
+// Fills `r` for size N (any N >= 1); host only.
+void rnode_build(int64_t N, RNode& r);
+
+// Per-instance tables of a ragged batch on the power-of-two grid of size Ng
+// (instance b at b*Ng): the node paired with grid row j (or -1), Ng times its
+// offset from that row's angle, its weight; and each instance's offset in the
+// caller's arrays.  gk == nullptr: the plain layout (node k on row k).
+struct RaggedRows {
+    const int* gk;
+    const double* dg;
+    const double* wg;
+    const int64_t* offs;
 };
 
 // Arithmetic of a plan: FP64 throughout (5e-14 budget); FP32-bulk (the

@@ -45,7 +45,6 @@ def test_rejects_bad_sizes_before_device_work(L, fn):
     assert f(0, 1, p, q, None) == -1          # N < 1
     assert f(-5, 1, p, q, None) == -1
     assert f(16, -1, p, q, None) == -1        # batch < 0
-    assert f(12, 1, p, q, None) == -2         # not a power of two
     assert f((1 << 20) * 2, 1, p, q, None) == -2   # beyond DLT_MAX_N
     assert f(16, 0, p, q, None) == 0          # empty batch is a no-op
     assert f(16, 1, None, q, None) == -1      # NULL input
@@ -56,7 +55,44 @@ def test_rejects_bad_sizes_before_device_work(L, fn):
 
 def test_nodes_rejects(L):
     assert L.leg_nodes_weights(0, 1, None, None, None, None) == -1
-    assert L.leg_nodes_weights(24, 1, None, None, None, None) == -2
+    assert L.leg_nodes_weights((1 << 20) + 1, 1, None, None, None, None) == -2
     assert L.leg_nodes_weights(16, 1, None, None, None, None) == 0   # nothing requested
+    assert L.leg_nodes_weights(24, 1, None, None, None, None) == 0   # any size; nothing requested
+
+
+@pytest.mark.parametrize("fn", ["leg2cheb_ex", "cheb_eval_leggrid_ex", "dlt_forward_ex", "dlt_inverse_ex"])
+def test_ex_rejects_bad_precision(L, fn):
+    f = getattr(L, fn)
+    p, q = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000)
+    for prec in (-1, 3, 99):
+        assert f(16, 1, p, q, prec, None) == -1
+    assert f(0, 1, p, q, 0, None) == -1
+    assert f(16, 0, p, q, 1, None) == 0
+
+
+def test_batch_rejects_bad_descriptors(L):
+    import numpy as np
+
+    i64p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    Ns = np.array([16, 100, 7], dtype=np.int64)
+    offs = np.array([0, 16, 116], dtype=np.int64)
+    inv = np.array([0, 1, 0], dtype=np.int8)
+    x, y = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000000)
+    f = L.dlt_batch_ex
+    assert f(-1, i64p(Ns), i64p(offs), i64p(inv), x, y, 0, None) == -1
+    assert f(0, i64p(Ns), i64p(offs), i64p(inv), x, y, 0, None) == 0      # nothing to do
+    assert f(3, i64p(Ns), i64p(offs), i64p(inv), x, y, 7, None) == -1     # precision
+    assert f(3, None, i64p(offs), i64p(inv), x, y, 0, None) == -1
+    assert f(3, i64p(Ns), i64p(offs), i64p(inv), None, y, 0, None) == -1
+    bad = Ns.copy(); bad[1] = 0
+    assert f(3, i64p(bad), i64p(offs), i64p(inv), x, y, 0, None) == -1   # size 0
+    bad[1] = (1 << 20) + 1
+    assert f(3, i64p(bad), i64p(offs), i64p(inv), x, y, 0, None) == -2   # too large
+    bo = offs.copy(); bo[2] = -4
+    assert f(3, i64p(Ns), i64p(bo), i64p(inv), x, y, 0, None) == -1      # negative offset
+    bi = inv.copy(); bi[0] = 2
+    assert f(3, i64p(Ns), i64p(offs), i64p(bi), x, y, 0, None) == -1     # direction flag
+    # output overlapping the input span
+    assert f(3, i64p(Ns), i64p(offs), i64p(inv), x, ctypes.c_void_p(0x1000 + 8 * 50), 0, None) == -1
     a = ctypes.c_void_p(0x1000)
     assert L.leg_nodes_weights(16, 1, a, a, None, None) == -1        # overlapping outputs
