@@ -19,6 +19,11 @@ Prints one JSON line; diagnostics go to stderr.  Options:
   --prec P      arithmetic of the headline run: fp64 (default), fp32bulk
                 (FP32 bulk transforms, 5e-6 budget) or fp64relaxed (FP64 with
                 the 5e-6 parameters)
+  --no-ragged   skip the ragged-batch runs (reported under "ragged": 4096
+                FP64 DLTs of sizes log-uniform in [64, 16384] as one cached
+                graph launch against one call per transform; 16384 FP32-bulk
+                transforms of sizes log-uniform in [256, 2^18], half of them
+                inverse, with errors per octave against the oracle)
   --no-modes    skip the short runs of the other modes (reported under
                 "modes": step time, speedup at equal stated accuracy,
                 FP32-bulk at batch 64, error against the oracle)
@@ -129,6 +134,100 @@ def stored_traffic(kernel):
     return rows[kernel]
 
 
+def ragged_runs(pk, wl, torch, np, dev, with_oracle=True):
+    """The two ragged-batch workloads; see --no-ragged."""
+    res = {}
+
+    def timed_calls(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    # batched plain FP64 DLT: 4096 sizes log-uniform in [64, 16384]
+    sizes = wl.log_uniform_sizes(4096, 64, 16384, 6)
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)[:-1]
+    x = torch.from_numpy(wl.ragged_inputs(sizes, 6)).to(dev)
+    y = torch.zeros_like(x)
+    t0 = time.perf_counter()
+    pk.dlt_batch(x, sizes, offs, out=y)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ms_graph = timed_calls(lambda: pk.dlt_batch(x, sizes, offs, out=y), 5)
+    views = [(x[o:o + n], y[o:o + n]) for n, o in zip(sizes.tolist(), offs.tolist())]
+
+    def one_by_one():
+        for xi, yi in views:
+            pk.dlt_forward(xi, out=yi)
+
+    ms_single = timed_calls(one_by_one, 1)
+    res["fp64_4096_sizes_64_16384"] = {
+        "transforms": 4096, "ms_per_batch_graph": round(ms_graph, 3),
+        "transforms_per_s_graph": round(4096 * 1000.0 / ms_graph, 1),
+        "ms_per_batch_one_call_each": round(ms_single, 3),
+        "speedup_graph_vs_one_call_each": round(ms_single / ms_graph, 2),
+        "first_call_s": round(setup_s, 2),
+        "inputs": "c_n = N(0,1)/(n+1), sizes round(exp(U[ln 64, ln 16384])) seed 6, values seed 6"}
+    log("ragged fp64 4096:", res["fp64_4096_sizes_64_16384"])
+    del x, y, views
+
+    # mixed stream: 16384 sizes in [256, 2^18], half inverse, FP32-bulk
+    cnt = 16384
+    sizes = wl.log_uniform_sizes(cnt, 256, 1 << 18, 7)
+    r = wl.rng(8)
+    inv = (np.arange(cnt) % 2 == 1).astype(np.int8)
+    analytic = (r.random(cnt) < 0.1) & (inv == 0)
+    offs = np.zeros(cnt, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)[:-1]
+    xh = wl.ragged_inputs(sizes, 9, inverse=inv, analytic=analytic)
+    x = torch.from_numpy(xh).to(dev)
+    y = torch.zeros_like(x)
+    t0 = time.perf_counter()
+    pk.dlt_batch(x, sizes, offs, inv, out=y, prec="fp32bulk")
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ms = timed_calls(lambda: pk.dlt_batch(x, sizes, offs, inv, out=y, prec="fp32bulk"), 2)
+    entry = {"transforms": cnt, "ms_per_batch_graph": round(ms, 2), "transforms_per_s": round(cnt * 1000.0 / ms, 1),
+             "gbytes_in_out": round(2 * 8 * int(sizes.sum()) / 1e9, 2), "first_call_s": round(setup_s, 2),
+             "inputs": "sizes round(exp(U[ln 256, ln 2^18])) seed 7; odd instances inverse (values N(0,1)); "
+                       "10% of forward instances c_n = 0.99^n N(0,1), others N(0,1)/(n+1); values seed 9"}
+    if with_oracle:
+        import oracle
+
+        yh = y.cpu().numpy()
+        errs = {}
+        for octave in range(8, 18):
+            lo, hi = 1 << octave, 1 << (octave + 1)
+            members = [i for i in range(cnt) if lo <= sizes[i] < hi]
+            worst = 0.0
+            for i in members[:2] + [i for i in members if inv[i]][:1]:
+                n, o = int(sizes[i]), int(offs[i])
+                xi, yi = xh[o:o + n], yh[o:o + n]
+                th, w, d = (t.cpu().numpy()[0] for t in pk.leg_nodes_weights(n))
+                if inv[i]:
+                    idx = np.arange(min(n, 64))
+                    ref = oracle.idlt(xi, th, w, idx=idx)
+                    err = np.max(np.abs(yi[idx] - ref) / ((idx + 0.5) * np.sum(w * np.abs(xi))))
+                else:
+                    idx = wl.sample_indices(n, 64, 10 + i)
+                    ref = oracle.dlt(xi, th[idx])
+                    err = np.max(np.abs(yi[idx] - ref)) / np.sum(np.abs(xi))
+                worst = max(worst, float(err))
+            errs[f"[2^{octave}, 2^{octave + 1})"] = worst
+        entry["max_error_vs_oracle_by_octave"] = errs
+        entry["error_budget"] = 5e-6
+    res["fp32bulk_16384_sizes_256_262144_mixed"] = entry
+    log("ragged fp32bulk 16384:", {k: v for k, v in entry.items() if k != "max_error_vs_oracle_by_octave"})
+    del x, y
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +240,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32bulk", "fp64relaxed"])
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py: this build runs on a single GPU; --gpus must be 1 "
@@ -331,6 +431,9 @@ def main():
                 modes["fp64relaxed_batch64"]["ms_per_step"] / modes["fp32bulk_batch64"]["ms_per_step"], 3)
             del cb, fb, cb2
         out["modes"] = modes
+
+    if not args.no_ragged and B == 1:
+        out["ragged"] = ragged_runs(pk, wl, torch, np, dev, with_oracle=not args.no_cpu)
 
     if not args.no_cpu:
         import oracle
