@@ -149,8 +149,11 @@ int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields);
  * events, writes at most max_kernels entries -- kernel name (NUL-terminated,
  * truncated to name_len-1 bytes, at names + i*name_len), total milliseconds
  * and launch count, summed over launches -- clears the record and returns the
- * number of entries written (>= 0) or a negative status.  Intended for
- * measurement runs; tracing is off by default. */
+ * number of entries written (>= 0) or a negative status.  While the trace
+ * is on, calls run every kernel on the caller's stream alone (no side
+ * streams), so a traced duration is the kernel's own and not time shared
+ * with concurrent kernels; a traced call is therefore slower than an
+ * untraced one.  Intended for measurement runs; tracing is off by default. */
 int dlt_trace_enable(int on);
 int dlt_trace_collect(int max_kernels, char* names, int name_len, double* total_ms, int64_t* counts);
 

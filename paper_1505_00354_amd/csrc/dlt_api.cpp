@@ -156,6 +156,13 @@ int get_ws(hipStream_t s, size_t bytes, void** out) {
 // Side streams (default priority, non-blocking) and events for calls on
 // stream s of the current device, created on first use.
 int get_lanes(hipStream_t s, Lanes* out) {
+    // with the kernel trace on every kernel runs alone on the call's stream,
+    // so that each traced duration is the kernel's own, not shared time
+    if (trace_on()) {
+        *out = Lanes();
+        out->s = s;
+        return DLT_OK;
+    }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
     Cache& c = cache();
@@ -572,10 +579,14 @@ int dlt_batch_ex(int64_t count, const int64_t* Ns, const int64_t* offsets, const
         // capture every slice into one graph on a private stream
         hipStream_t cs;
         if ((rc = capture_stream(stream, &cs))) return rc;
-        Lanes L;
-        if ((rc = get_lanes(cs, &L))) return rc;
+        // the graph is cached: capture it untraced, with its side streams
         const bool tr = trace_on();
         trace_set(false);
+        Lanes L;
+        if ((rc = get_lanes(cs, &L))) {
+            trace_set(tr);
+            return rc;
+        }
         hipGraph_t g = nullptr;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) rc = DLT_ERR_HIP;
         for (auto& S : e->slices)
@@ -701,16 +712,17 @@ int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int pre
     // first side stream beside the conversion of the first slice
     const Lanes& L = cw.lanes;
     const hipStream_t sn = L.aux(0);
-    if (hipEventRecord(L.ev[10], stream) != hipSuccess || hipStreamWaitEvent(sn, L.ev[10], 0) != hipSuccess)
+    const bool fork = sn != stream;
+    if (fork && (hipEventRecord(L.ev[10], stream) != hipSuccess || hipStreamWaitEvent(sn, L.ev[10], 0) != hipSuccess))
         return DLT_ERR_HIP;
     if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, L.on(sn))))) return rc;
-    if (hipEventRecord(L.ev[11], sn) != hipSuccess) return DLT_ERR_HIP;
+    if (fork && hipEventRecord(L.ev[11], sn) != hipSuccess) return DLT_ERR_HIP;
     for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
         int64_t nb = std::min(cw.nb, batch - b0);
         // Chebyshev coefficients of the slice, stride N, in the workspace
         double* chat = cw.work.chat;
         if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat, cw.work.schat, cw.work, L)))) return rc;
-        if (b0 == 0 && hipStreamWaitEvent(stream, L.ev[11], 0) != hipSuccess) return DLT_ERR_HIP;
+        if (fork && b0 == 0 && hipStreamWaitEvent(stream, L.ev[11], 0) != hipSuccess) return DLT_ERR_HIP;
         if ((rc = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, f + b0 * N, cw.work, L)))) return rc;
     }
     return DLT_OK;

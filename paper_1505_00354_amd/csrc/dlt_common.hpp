@@ -55,8 +55,11 @@ __device__ __forceinline__ cplx cwide(cplxT<R> a) {
 constexpr int FFT_THREADS = 256;
 constexpr int FFT_CAP = 2048;
 constexpr int FFT_VPT = FFT_CAP / FFT_THREADS;  // tile elements per thread
-// LDS slots of a tile: one pad slot per 8 values plus a per-sequence skew
+// LDS slots of a run-time-length tile: one pad slot per 8 values plus a
+// per-sequence skew.  A compile-time length swizzles its slots instead and
+// needs exactly FFT_CAP of them.
 constexpr int FFT_LDS = FFT_CAP + FFT_CAP / 8 + 32;
+#define TILE_LDS(L) ((L) > 0 ? FFT_CAP : FFT_LDS)
 __device__ __forceinline__ int lp(int x) { return x + (x >> 3); }
 
 // e^{+2 pi i t / N}, 0 <= t < N, from a two-level table:
@@ -188,23 +191,53 @@ __device__ __forceinline__ void dft8(cplxT<R>* a) {
 // butterfly of the last, so both stages run in registers.  L == 0 (lengths
 // below 64, tiles smaller than FFT_CAP): element e = t + s*FFT_THREADS is
 // (e % cols, e / cols) and may lie beyond the tile (live() false).
+// Slot swizzle of a compile-time tile of length 2^LOG (6 <= LOG <= 11): for
+// every term (i, j), j > i, bit i of the slot is flipped by bit j of the
+// element index col*L + i.  Flips of low bits by higher ones make a bijection
+// of [0, FFT_CAP), so no padding is needed.  The terms put the lane bits that
+// vary within each access of tile_fft on distinct banks, given how gfx950
+// serves 16-byte (and 8-byte) LDS accesses, measured with a probe: reads 32
+// and 64 lanes at a time, writes 8 and 16 lanes at a time (16-byte slots of
+// 64 four-byte banks, a slot's bank group being its index modulo the group
+// size).  Every access of tile_fft is then free of bank conflicts.
+constexpr int TILE_SWZ_MAX = 7;
+constexpr signed char TILE_SWZ[6][TILE_SWZ_MAX][2] = {
+    {{0, 8}, {1, 6}, {2, 7}, {3, 9}, {4, 10}, {5, 8}, {-1, -1}},         // L = 64
+    {{0, 7}, {1, 9}, {2, 8}, {3, 10}, {4, 7}, {5, 9}, {-1, -1}},         // L = 128
+    {{0, 8}, {1, 10}, {2, 9}, {3, 8}, {4, 10}, {5, 9}, {-1, -1}},        // L = 256
+    {{0, 3}, {1, 4}, {1, 10}, {2, 9}, {3, 10}, {4, 9}, {5, 10}},         // L = 512
+    {{0, 4}, {1, 3}, {2, 5}, {2, 10}, {3, 10}, {4, 10}, {5, 10}},        // L = 1024
+    {{0, 5}, {1, 3}, {2, 4}, {3, 6}, {-1, -1}, {-1, -1}, {-1, -1}},      // L = 2048
+};
+__host__ __device__ constexpr int tile_swizzle(int log_len, int x) {
+    int y = x;
+    for (int t = 0; t < TILE_SWZ_MAX; ++t) {
+        const int i = TILE_SWZ[log_len - 6][t][0], j = TILE_SWZ[log_len - 6][t][1];
+        if (i >= 0) y ^= (x >> (j - i)) & (1 << i);
+    }
+    return y;
+}
+
 template <int L>
 struct Tile {
     static constexpr int LOG = __builtin_ctz(L);
+    static_assert(LOG >= 6 && LOG <= 11, "compile-time tile lengths are 64..2048");
     static constexpr int COLS = FFT_CAP / L;
-    // per-sequence skew so that the lanes of one column group hit distinct banks
-    static constexpr int SK = COLS >= 8 ? 1 : 8 / COLS;
     static constexpr int STRIDE = L / 8;
-    int col_, i0_;
+    int col_, i0_, rb_;
     __device__ __forceinline__ Tile(int /*cols*/, int /*len*/)
-        : col_((int)threadIdx.x % COLS), i0_((int)threadIdx.x / COLS) {}
+        : col_((int)threadIdx.x % COLS), i0_((int)threadIdx.x / COLS), rb_(sw(col_ * L + i0_)) {}
     __device__ __forceinline__ int col(int) const { return col_; }
     __device__ __forceinline__ int idx(int s) const { return i0_ + s * STRIDE; }
     __device__ __forceinline__ bool live(int) const { return true; }
     __device__ __forceinline__ int cols() const { return COLS; }
     __device__ __forceinline__ int len() const { return L; }
-    __device__ __forceinline__ static int pad(int x) { return x + (x >> 3) + (x >> LOG) * SK; }
-    __device__ __forceinline__ int slot(int s) const { return pad(col_ * L + idx(s)); }
+    // LDS slot of element index x (= col*L + i)
+    __host__ __device__ static constexpr int sw(int x) { return tile_swizzle(LOG, x); }
+    // slot of (col_, idx(s)): the base bits (below STRIDE, and the column)
+    // and s*STRIDE are disjoint, so the swizzle splits into two XORed parts,
+    // the second a compile-time constant once s is
+    __device__ __forceinline__ int slot(int s) const { return rb_ ^ sw(s * STRIDE); }
 };
 
 template <>
@@ -217,7 +250,7 @@ struct Tile<0> {
     __device__ __forceinline__ bool live(int s) const { return e(s) < cols_ * len_; }
     __device__ __forceinline__ int cols() const { return cols_; }
     __device__ __forceinline__ int len() const { return len_; }
-    __device__ __forceinline__ static int pad(int x) { return lp(x); }
+    __device__ __forceinline__ static int sw(int x) { return lp(x); }
     __device__ __forceinline__ int slot(int s) const { return lp(col(s) * len_ + idx(s)); }
 };
 
@@ -261,10 +294,14 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
         constexpr int NMID = (LOG - 3 - RL) / 3;
         const int cb = T.col_ * L;
         const int i0 = T.i0_;
+        // Every slot below is sw(base) ^ sw(offset): the offset's bits lie
+        // above the base's within the sequence (8 i0 + q, q < 8; i0 < ST;
+        // d's low bits below p, q p from p up to 8 p).
         // first stage (p = 1): no twiddles, outputs to 8 i0 + q
         dft8(v);
+        const int wb = TT::sw(cb + 8 * i0);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) buf[TT::pad(cb + 8 * i0 + q)] = v[q];
+        for (int q = 0; q < 8; ++q) buf[wb ^ TT::sw(q)] = v[q];
         __syncthreads();
 #pragma unroll
         for (int st = 0; st < NMID; ++st) {
@@ -272,17 +309,17 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
             const int k = i0 & (p - 1);
             cplxT<R> a[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = buf[TT::pad(cb + i0 + j * ST)];
+            for (int j = 0; j < 8; ++j) a[j] = buf[T.rb_ ^ TT::sw(j * ST)];
             twiddle8(a, tw, k * (L / (8 * p)));
             dft8(a);
             __syncthreads();
-            const int d = cb + (i0 - k) * 8 + k;
+            const int db = TT::sw(cb + (i0 - k) * 8 + k);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) buf[TT::pad(d + q * p)] = a[q];
+            for (int q = 0; q < 8; ++q) buf[db ^ TT::sw(q * p)] = a[q];
             __syncthreads();
         }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) v[s] = buf[TT::pad(cb + i0 + s * ST)];
+        for (int s = 0; s < 8; ++s) v[s] = buf[T.rb_ ^ TT::sw(s * ST)];
         __syncthreads();
         // last stage, p = L / radix: butterfly index k = i < p
         if constexpr (RL == 3) {

@@ -35,7 +35,43 @@ __device__ __forceinline__ cplx half_shift(int64_t n, int N) {
 //   (N+m+1/2) theta*_k - (m+1/2) pi/2 = (k+1/2) pi + (m+1/2)(theta*_k - pi/2),
 // so cos(phase) = -(-1)^k sin psi_m, sin(phase) = (-1)^k cos psi_m with
 // psi_m = (m+1/2)(theta - pi/2) + N delta.
-// theta_k - theta*_k (delta) and w_k of interior node k of P_N.
+// P_N(cos theta) / (-(-1)^k C) and its theta-derivative / (-(-1)^k C) at
+// theta = theta*_k + delta from the Stieltjes series (terms below rounding
+// dropped).
+__device__ __forceinline__ void node_series(const NodeParams& P, double a0, double ts, double delta, double& Pv,
+                                            double& Dv) {
+    const int N = P.N;
+    double th = ts + delta;
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    double cot = cs / sn;
+    double q = 1.0 / (2.0 * sn);
+    double dlt = a0 + delta;  // theta - pi/2
+    double ps, pc, rs, rc;
+    sincos(0.5 * dlt + N * delta, &ps, &pc);
+    sincos(dlt, &rs, &rc);
+    double r = sqrt(q);
+    const double stop = 1e-18 * P.h[0] * r;
+    Pv = 0;
+    Dv = 0;
+    for (int m = 0; m < P.Ms; ++m) {
+        double hm = P.h[m] * r;
+        Pv = fma(hm, ps, Pv);
+        Dv = fma(hm, (N + m + 0.5) * pc - (m + 0.5) * ps * cot, Dv);
+        if (hm < stop) break;  // remaining terms below rounding
+        double nps = ps * rc + pc * rs;
+        double npc = pc * rc - ps * rs;
+        ps = nps;
+        pc = npc;
+        r *= q;
+    }
+}
+
+// theta_k - theta*_k (delta) and w_k of interior node k of P_N.  The start
+// is within half an ulp of theta_k for all but about the 2000 nodes nearest
+// each end, and two Newton steps converge everywhere (k >= 6); a wave whose
+// first steps are all below half an ulp (over its active lanes) is done after
+// one evaluation, whose derivative then gives the weight.
 __device__ void node_interior(const NodeParams& P, int k, double& delta_out, double& w_out) {
     const int N = P.N;
     const double pi = 3.141592653589793;
@@ -48,32 +84,15 @@ __device__ void node_interior(const NodeParams& P, int k, double& delta_out, dou
     // theta*_k - pi/2 = pi (2k + 1 - N) / (2N)
     const double a0 = pi * (double)(2 * k + 1 - N) / (2.0 * N);
     const double ts = (k + 0.5) * pi / N;
-    double Pv = 0, Dv = 0;
-    for (int it = 0; it <= 3; ++it) {
-        double th = ts + delta;
-        double sn, cs;
-        sincos(th, &sn, &cs);
-        double cot = cs / sn;
-        double q = 1.0 / (2.0 * sn);
-        double dlt = a0 + delta;  // theta - pi/2
-        double ps, pc, rs, rc;
-        sincos(0.5 * dlt + N * delta, &ps, &pc);
-        sincos(dlt, &rs, &rc);
-        double r = sqrt(q);
-        Pv = 0;
-        Dv = 0;
-        for (int m = 0; m < P.Ms; ++m) {
-            double hm = P.h[m] * r;
-            Pv = fma(hm, ps, Pv);
-            Dv = fma(hm, (N + m + 0.5) * pc - (m + 0.5) * ps * cot, Dv);
-            if (hm < 1e-18 * P.h[0] * sqrt(q)) break;  // remaining terms below rounding
-            double nps = ps * rc + pc * rs;
-            double npc = pc * rc - ps * rs;
-            ps = nps;
-            pc = npc;
-            r *= q;
-        }
-        if (it < 3) delta -= Pv / Dv;
+    double Pv, Dv;
+    node_series(P, a0, ts, delta, Pv, Dv);
+    const double step = Pv / Dv;
+    delta -= step;
+    // 2^-54 theta is at most half an ulp of theta
+    if (!__all(fabs(step) <= 0x1p-54 * (ts + delta))) {
+        node_series(P, a0, ts, delta, Pv, Dv);
+        delta -= Pv / Dv;
+        node_series(P, a0, ts, delta, Pv, Dv);
     }
     // dP/dtheta = -(-1)^k C D;  w = 2 / (dP/dtheta)^2
     double dP = P.C * Dv;
@@ -591,7 +610,7 @@ template <int LA, class R>
 __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const double* __restrict__ c,
                                                           int64_t c_stride, cplxT<R>* __restrict__ X,
                                                           int64_t x_stride) {
-    __shared__ cplxT<R> buf[FFT_LDS];
+    __shared__ cplxT<R> buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
@@ -668,7 +687,7 @@ template <int LB, class R>
 __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplxT<R>* __restrict__ X,
                                                           int64_t x_stride, double* __restrict__ v,
                                                           int64_t v_stride) {
-    __shared__ cplxT<R> buf[FFT_LDS];
+    __shared__ cplxT<R> buf[TILE_LDS(LB)];
     STAGE_TW(stw, LB, R);
     const cplxT<R>* twB = stage_twiddles<LB, R>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
@@ -946,7 +965,7 @@ __global__ FFT_BOUNDS void k_dct2_passA(Geo g, int G, const double* __restrict__
                                                            int64_t v_stride, const double* __restrict__ near,
                                                            int64_t near_stride, int jnear, cplx* __restrict__ X,
                                                            int64_t x_stride) {
-    __shared__ cplx buf[FFT_LDS];
+    __shared__ cplx buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, double);
     const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
@@ -978,7 +997,7 @@ __global__ FFT_BOUNDS void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ 
                                                            int64_t x_stride, const double* __restrict__ dense,
                                                            int64_t dense_stride, double* __restrict__ chat,
                                                            int64_t chat_stride) {
-    __shared__ cplx buf[FFT_LDS];
+    __shared__ cplx buf[TILE_LDS(LB)];
     STAGE_TW(stw, LB, double);
     const cplx* twB = stage_twiddles<LB, double>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
@@ -1013,7 +1032,7 @@ __global__ FFT_BOUNDS void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ 
 template <int LA, class R>
 __global__ FFT_BOUNDS void k_ndct_passA(Geo g, int qa, int qb, int QG, const double* __restrict__ chat,
                                         int64_t chat_stride, cplxT<R>* __restrict__ X, int64_t x_stride) {
-    __shared__ cplxT<R> buf[FFT_LDS];
+    __shared__ cplxT<R> buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
@@ -1073,7 +1092,7 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
                                         const cplxT<R>* __restrict__ X1, int64_t x1_stride,
                                         const double* __restrict__ dth, double* __restrict__ f, int64_t f_stride,
                                         RaggedRows RR) {
-    __shared__ cplx bufd[FFT_LDS];
+    __shared__ cplx bufd[TILE_LDS(LB)];
     cplxT<R>* bufr = reinterpret_cast<cplxT<R>*>(bufd);
     STAGE_TW(stwd, LB, double);
     const cplx* twd = stage_twiddles<LB, double>(stwd, g.twN1, g.N1);
@@ -1172,7 +1191,7 @@ __global__ FFT_BOUNDS void k_tndct_passA(Geo g, int qa, int qb, int QG, const do
                                          int64_t f_stride, const double* __restrict__ wts,
                                          const double* __restrict__ dth, cplxT<R>* __restrict__ X, int64_t x_stride,
                                          RaggedRows RR) {
-    __shared__ cplxT<R> buf[FFT_LDS];
+    __shared__ cplxT<R> buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
@@ -1229,7 +1248,7 @@ template <int LB, class R>
 __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ X0, int64_t x0_stride,
                                          const cplxT<R>* __restrict__ X1, int64_t x1_stride, double* __restrict__ y,
                                          int64_t y_stride) {
-    __shared__ cplx bufd[FFT_LDS];
+    __shared__ cplx bufd[TILE_LDS(LB)];
     cplxT<R>* bufr = reinterpret_cast<cplxT<R>*>(bufd);
     STAGE_TW(stwd, LB, double);
     const cplx* twd = stage_twiddles<LB, double>(stwd, g.twN1, g.N1);
@@ -1274,7 +1293,7 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
                 ip = i ^ 1;
                 jp = N1 - 1 - ja;
             }
-            part[s] = Tile<LB>::pad(ip * N1 + jp);
+            part[s] = Tile<LB>::sw(ip * N1 + jp);
         }
     }
     // transformed tile in buffer `bb` (precision P): pair each value with its
@@ -1397,7 +1416,7 @@ __global__ void k_dense_t_reduce(int nd, int nchunk, int chunk, const double* __
 template <int LA>
 __global__ FFT_BOUNDS void k_dct3_passA(Geo g, const double* __restrict__ y, int64_t y_stride,
                                                            cplx* __restrict__ X, int64_t x_stride) {
-    __shared__ cplx buf[FFT_LDS];
+    __shared__ cplx buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, double);
     const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
@@ -1422,7 +1441,7 @@ __global__ FFT_BOUNDS void k_dct3_passA(Geo g, const double* __restrict__ y, int
 template <int LB>
 __global__ FFT_BOUNDS void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64_t x_stride,
                                                            double* __restrict__ u, int64_t u_stride) {
-    __shared__ cplx buf[FFT_LDS];
+    __shared__ cplx buf[TILE_LDS(LB)];
     STAGE_TW(stw, LB, double);
     const cplx* twB = stage_twiddles<LB, double>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
@@ -1450,7 +1469,7 @@ template <int LA, class R>
 __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const double* __restrict__ u,
                                                            int64_t u_stride, cplxT<R>* __restrict__ X,
                                                            int64_t x_stride) {
-    __shared__ cplxT<R> buf[FFT_LDS];
+    __shared__ cplxT<R> buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
@@ -1503,7 +1522,7 @@ template <int LB, class R>
 __global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplxT<R>* __restrict__ X,
                                                            int64_t x_stride, double* __restrict__ out,
                                                            int64_t out_stride) {
-    __shared__ cplxT<R> buf[FFT_LDS];
+    __shared__ cplxT<R> buf[TILE_LDS(LB)];
     STAGE_TW(stw, LB, R);
     const cplxT<R>* twB = stage_twiddles<LB, R>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
@@ -1631,14 +1650,17 @@ __global__ __launch_bounds__(64) void k_tnear_scan(NearParams NP, const double* 
     }
 }
 
-constexpr int TN_STEPS = 16;             // degrees per LDS tile and chain
-constexpr int TN_CH = 2;                 // independent recurrences per lane
+constexpr int TN_STEPS = 4;              // degrees per LDS tile and chain
+constexpr int TN_CH = 4;                 // independent recurrences per lane
 constexpr int TN_LEN = NEAR_CHUNK / TN_CH;
+constexpr int TN_COLS = TN_CH * TN_STEPS;  // columns of one tile
+constexpr int TN_SUM = 64 / TN_COLS;       // lanes that sum one column
 
 // Work-group = 64 rows of one segment and one degree chunk; each lane runs
 // its row over the chunk as TN_CH recurrences of TN_LEN degrees side by side
 // from the plan's states, the products P_n(x_j) w_j go through an LDS tile
-// and pairs of lanes sum a degree's column; partial sums per row group.
+// and TN_SUM lanes sum a degree's column; partial sums per row group.  The
+// tile is small (8 KiB) so that many waves share a CU.
 __global__ __launch_bounds__(64) void k_tnear_accum(int N, NearParams NP, const int* __restrict__ wg_seg,
                                                     const int* __restrict__ segoff, const double* __restrict__ rcp,
                                                     const double* __restrict__ u, int64_t u_stride,
@@ -1670,6 +1692,7 @@ __global__ __launch_bounds__(64) void k_tnear_accum(int N, NearParams NP, const 
         d[k] = st[(int64_t)id * 2 * NEAR_NSUB + 2 * q + 1];
     }
     {
+        // the chunk's 1/(n+1) (rcp has N entries, a multiple of NEAR_CHUNK)
         double lr[NEAR_CHUNK / 64];
 #pragma unroll
         for (int q = 0; q < NEAR_CHUNK / 64; ++q) lr[q] = rcp[n0 + (int)threadIdx.x + 64 * q];
@@ -1679,8 +1702,11 @@ __global__ __launch_bounds__(64) void k_tnear_accum(int N, NearParams NP, const 
     __syncthreads();
     double* pb = part + b * part_stride + (int64_t)rg_global * N;
     const double we = uj + um, wo = uj - um;  // weights of even / odd degrees
-    // reduction lanes: column c = lane % 32 = (chain, degree), rows of half h = lane / 32
-    const int cidx = threadIdx.x & 31, kc = cidx / TN_STEPS, col = cidx % TN_STEPS, half = threadIdx.x >> 5;
+    // reduction lanes: column c = lane % TN_COLS = (chain, degree); the
+    // TN_SUM lanes of a column take 64 / TN_SUM rows each.  Row pitch 65:
+    // the lanes of a 32-lane group read distinct banks.
+    const int cidx = threadIdx.x % TN_COLS, kc = cidx / TN_STEPS, col = cidx % TN_STEPS;
+    const int part_r = threadIdx.x / TN_COLS;
     for (int nb = 0; nb < TN_LEN; nb += TN_STEPS) {
 #pragma unroll
         for (int i = 0; i < TN_STEPS; i += 2) {
@@ -1694,14 +1720,17 @@ __global__ __launch_bounds__(64) void k_tnear_accum(int N, NearParams NP, const 
             }
         }
         __syncthreads();
-        // lanes c and c + 32 sum column c over 32 rows each (consecutive
-        // lanes read consecutive columns: distinct banks with the odd row pitch)
-        double s = 0;
-#pragma unroll 8
-        for (int r = 0; r < 32; ++r) s += tile[kc][col][half * 32 + r];
-        s += __shfl_xor(s, 32);
+        double s = 0, s1 = 0;
+#pragma unroll
+        for (int r = 0; r < 64 / TN_SUM; r += 2) {
+            s += tile[kc][col][part_r * (64 / TN_SUM) + r];
+            s1 += tile[kc][col][part_r * (64 / TN_SUM) + r + 1];
+        }
+        s += s1;
+#pragma unroll
+        for (int x = TN_COLS; x < 64; x <<= 1) s += __shfl_xor(s, x);
         const int n = n0 + kc * TN_LEN + nb + col;
-        if (half == 0 && n < n1) pb[n] = s;
+        if (part_r == 0 && n < n1) pb[n] = s;
         __syncthreads();
     }
 }

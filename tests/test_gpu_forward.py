@@ -127,3 +127,23 @@ def test_deterministic(pk):
     f1 = to_host(pk.dlt_forward(c))
     f2 = to_host(pk.dlt_forward(c))
     assert np.array_equal(f1, f2)
+
+
+@pytest.mark.parametrize("N", [1 << 16, 1 << 20])
+def test_traced_calls_match_untraced(pk, N):
+    # with the kernel trace on, every kernel runs on the call's stream alone;
+    # the results are the same bits, and the trace names the far-field passes
+    say("trace", N)
+    c = to_dev(wl.coeffs_algebraic(N, 9)[0])
+    f = to_dev(wl.values_normal(N, 10)[0])
+    ref_f, ref_c = to_host(pk.dlt_forward(c)), to_host(pk.dlt_inverse(f))
+    pk.trace_enable(True)
+    try:
+        got_f, got_c = to_host(pk.dlt_forward(c)), to_host(pk.dlt_inverse(f))
+    finally:
+        pk.trace_enable(False)
+    kern = pk.trace_collect()
+    assert np.array_equal(got_f, ref_f)
+    assert np.array_equal(got_c, ref_c)
+    names = " ".join(kern)
+    assert "far_pass" in names and "tfar_pass" in names
