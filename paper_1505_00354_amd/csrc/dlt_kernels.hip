@@ -607,9 +607,9 @@ __device__ __forceinline__ void passB_load(const Geo& g, int vb0, const cplxT<R>
 // goes through pass A of the length-N DFT.  Term group blockIdx.y takes the
 // terms nterm-1-y, nterm-1-y-G, ...
 template <int LA, class R>
-__global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const double* __restrict__ c,
-                                                          int64_t c_stride, cplxT<R>* __restrict__ X,
-                                                          int64_t x_stride) {
+__global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __restrict__ amp,
+                                                          const double* __restrict__ c, int64_t c_stride,
+                                                          cplxT<R>* __restrict__ X, int64_t x_stride) {
     __shared__ cplxT<R> buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
@@ -629,12 +629,7 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const double* 
         if (T.live(s)) {
             const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             nn[s] = n;
-            if (n >= F.nd) {
-                // h_{Mmax-1,n} = K / prod_{j<Mmax} (n+j+1/2),  K = prod_{j<Mmax} (j-1/2)^2/j
-                double den = 1;
-                for (int j = 1; j < F.Mmax; ++j) den *= (n + j + 0.5);
-                bh[s] = cscale(half_shift(n, N), stieltjes_C((double)n) * cb[n] * (F.hK / den));
-            }
+            if (n >= F.nd) bh[s] = cscale(amp[n], cb[n]);
         }
     }
     int mcur = F.Mmax - 1;
@@ -683,10 +678,29 @@ __device__ __forceinline__ void far_row_factors(int j, int N, cplx& g0, cplx& rq
     rq = {rc * q, rs * q};
 }
 
+// Plan time: the far-field tables (see Plan::d_amp, Plan::d_rowf), one
+// thread per index.
+__global__ void k_far_tables(int N, FarParams F, cplx* __restrict__ amp, cplx* __restrict__ rowf) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    cplx a = {0, 0};
+    if (n >= F.nd) {
+        // h_{Mmax-1,n} = K / prod_{j<Mmax} (n+j+1/2),  K = prod_{j<Mmax} (j-1/2)^2/j
+        double den = 1;
+        for (int j = 1; j < F.Mmax; ++j) den *= (n + j + 0.5);
+        a = cscale(half_shift(n, N), stieltjes_C((double)n) * (F.hK / den));
+    }
+    amp[n] = a;
+    cplx g0, rq;
+    far_row_factors(n, N, g0, rq);
+    rowf[2 * n] = g0;
+    rowf[2 * n + 1] = rq;
+}
+
 template <int LB, class R>
-__global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplxT<R>* __restrict__ X,
-                                                          int64_t x_stride, double* __restrict__ v,
-                                                          int64_t v_stride) {
+__global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __restrict__ rowf,
+                                                          const cplxT<R>* __restrict__ X, int64_t x_stride,
+                                                          double* __restrict__ v, int64_t v_stride) {
     __shared__ cplxT<R> buf[TILE_LDS(LB)];
     STAGE_TW(stw, LB, R);
     const cplxT<R>* twB = stage_twiddles<LB, R>(stw, g.twN1, g.N1);
@@ -709,7 +723,8 @@ __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplxT<R>
             const int j = row_of(mo, N);
             const int blk = row_block(F, j, N);
             if (blk >= 0) key[s] = 2 * blk + (2 * mo >= N ? 1 : 0);
-            far_row_factors(j, N, gm[s], rq[s]);
+            gm[s] = rowf[2 * j];
+            rq[s] = rowf[2 * j + 1];
         }
     }
     int mcur = 0;
@@ -1466,9 +1481,9 @@ __global__ FFT_BOUNDS void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64
 //   rho_j = u_j e^{i (m+1/2)(theta_j - pi/2)} (2 sin theta_j)^{-m-1/2} [j in block b].
 // Term group blockIdx.y takes the terms y, y + G, ...
 template <int LA, class R>
-__global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const double* __restrict__ u,
-                                                           int64_t u_stride, cplxT<R>* __restrict__ X,
-                                                           int64_t x_stride) {
+__global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const cplx* __restrict__ rowf,
+                                                           const double* __restrict__ u, int64_t u_stride,
+                                                           cplxT<R>* __restrict__ X, int64_t x_stride) {
     __shared__ cplxT<R> buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
@@ -1490,9 +1505,8 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const double*
             const int j = row_of(mo, N);
             const int blk = row_block(F, j, N);
             if (blk >= 0) key[s] = 2 * blk + (2 * mo >= N ? 1 : 0);
-            cplx g0;
-            far_row_factors(j, N, g0, rq[s]);
-            gm[s] = cscale(g0, ub[j]);
+            rq[s] = rowf[2 * j + 1];
+            gm[s] = cscale(rowf[2 * j], ub[j]);
         }
     }
     int mcur = 0;
@@ -1519,9 +1533,9 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const double*
 // group blockIdx.y takes the terms nterm-1-y, nterm-1-y-G, ... and writes
 // partial sums to out[y].
 template <int LB, class R>
-__global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplxT<R>* __restrict__ X,
-                                                           int64_t x_stride, double* __restrict__ out,
-                                                           int64_t out_stride) {
+__global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplx* __restrict__ amp,
+                                                           const cplxT<R>* __restrict__ X, int64_t x_stride,
+                                                           double* __restrict__ out, int64_t out_stride) {
     __shared__ cplxT<R> buf[TILE_LDS(LB)];
     STAGE_TW(stw, LB, R);
     const cplxT<R>* twB = stage_twiddles<LB, R>(stw, g.twN1, g.N1);
@@ -1541,12 +1555,7 @@ __global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplxT<R
         if (T.live(s)) {
             const int n = jb0 + T.col(s) + g.N2 * T.idx(s);
             nn[s] = n;
-            if (n >= F.nd) {
-                // h_{Mmax-1,n} = K / prod_{j<Mmax} (n+j+1/2),  K = prod_{j<Mmax} (j-1/2)^2/j
-                double den = 1;
-                for (int j = 1; j < F.Mmax; ++j) den *= (n + j + 0.5);
-                eh[s] = cscale(half_shift(n, N), stieltjes_C((double)n) * (F.hK / den));
-            }
+            if (n >= F.nd) eh[s] = amp[n];
         }
     }
     int mcur = F.Mmax - 1;
@@ -1895,6 +1904,16 @@ hipError_t plan_prepare(Plan& p) {
         hipError_t e = plan_prepare(*p.sub);
         if (e != hipSuccess) return e;
     }
+    if (p.far.nterm > 0) {
+        const int N = (int)p.N;
+        hipError_t e = hipMalloc(&p.d_amp, (size_t)N * sizeof(cplx));
+        if (e == hipSuccess) e = hipMalloc(&p.d_rowf, (size_t)N * 2 * sizeof(cplx));
+        if (e != hipSuccess) return e;
+        k_far_tables<<<(N + 255) / 256, 256, 0, 0>>>(N, p.far, p.d_amp, p.d_rowf);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+    }
     const NearParams& NP = p.near;
     if (NP.nitems <= 0) return hipSuccess;
     const int N = (int)p.N;
@@ -2020,17 +2039,17 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
         cplxf* X = (cplxf*)w.X;
         const int64_t sX = 2 * w.sX;
         traced("k_far_passA_f32", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_far_passA, float, gA, FFT_THREADS, 0, s, g, F, p.tgA, c, cs, X, sX);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_far_passA, float, gA, FFT_THREADS, 0, s, g, F, p.tgA, p.d_amp, c, cs, X, sX);
         });
         traced("k_far_passB_f32", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_far_passB, float, gB, FFT_THREADS, 0, s, g, F, p.tgB, X, sX, w.v, w.sv);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_far_passB, float, gB, FFT_THREADS, 0, s, g, F, p.tgB, p.d_rowf, X, sX, w.v, w.sv);
         });
     } else {
         traced("k_far_passA", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_far_passA, double, gA, FFT_THREADS, 0, s, g, F, p.tgA, c, cs, w.X, w.sX);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_far_passA, double, gA, FFT_THREADS, 0, s, g, F, p.tgA, p.d_amp, c, cs, w.X, w.sX);
         });
         traced("k_far_passB", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_far_passB, double, gB, FFT_THREADS, 0, s, g, F, p.tgB, w.X, w.sX, w.v, w.sv);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_far_passB, double, gB, FFT_THREADS, 0, s, g, F, p.tgB, p.d_rowf, w.X, w.sX, w.v, w.sv);
         });
     }
     // values on the grid -> coefficients
@@ -2104,17 +2123,17 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
         cplxf* X = (cplxf*)w.X;
         const int64_t sX = 2 * w.sX;
         traced("k_tfar_passA_f32", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tfar_passA, float, gA, FFT_THREADS, 0, s, g, p.far, p.tgA, u, w.svec, X, sX);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tfar_passA, float, gA, FFT_THREADS, 0, s, g, p.far, p.tgA, p.d_rowf, u, w.svec, X, sX);
         });
         traced("k_tfar_passB_f32", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tfar_passB, float, gB, FFT_THREADS, 0, s, g, p.far, p.tgB, X, sX, w.v, w.sv);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tfar_passB, float, gB, FFT_THREADS, 0, s, g, p.far, p.tgB, p.d_amp, X, sX, w.v, w.sv);
         });
     } else {
         traced("k_tfar_passA", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tfar_passA, double, gA, FFT_THREADS, 0, s, g, p.far, p.tgA, u, w.svec, w.X, w.sX);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tfar_passA, double, gA, FFT_THREADS, 0, s, g, p.far, p.tgA, p.d_rowf, u, w.svec, w.X, w.sX);
         });
         traced("k_tfar_passB", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tfar_passB, double, gB, FFT_THREADS, 0, s, g, p.far, p.tgB, w.X, w.sX, w.v, w.sv);
+            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tfar_passB, double, gB, FFT_THREADS, 0, s, g, p.far, p.tgB, p.d_amp, w.X, w.sX, w.v, w.sv);
         });
     }
     DLT_TRY(dep(sn, s, L.ev[8]));

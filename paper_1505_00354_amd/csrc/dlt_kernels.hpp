@@ -50,7 +50,8 @@ void work_carve(const Plan& p, int64_t nb, void* base, Work& w);
 constexpr int NODE_PARTS_MAX = 64;
 hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, const Lanes& L);
 // Input-independent plan data formed on the device once per plan (and its
-// sub-plans): the near-field states at every chunk start.  Synchronous.
+// sub-plans): the far-field amplitude and row-factor tables and the
+// near-field states at every chunk start.  Synchronous.
 hipError_t plan_prepare(Plan& p);
 // chat = M c for nb instances (batch strides cs, hs in elements)
 hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, double* chat, int64_t hs, Work& w,

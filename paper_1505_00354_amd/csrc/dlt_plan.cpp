@@ -354,7 +354,8 @@ void plan_free(Plan& p) {
         p.sub = nullptr;
     }
     void* ptrs[] = {p.d_twN1,  p.d_twN2,     p.d_twHi,      p.d_twLo,     p.d_lam,
-                    p.d_rcp,   p.d_guess,    p.d_tn_wgseg,  p.d_tn_segoff, p.d_tn_rgnend, p.d_near_st};
+                    p.d_rcp,   p.d_guess,    p.d_tn_wgseg,  p.d_tn_segoff, p.d_tn_rgnend, p.d_near_st,
+                    p.d_amp,   p.d_rowf};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();

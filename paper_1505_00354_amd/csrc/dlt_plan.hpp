@@ -127,6 +127,12 @@ struct Plan {
     // chunk) item and every NEAR_SUB degrees inside it: it does not depend on
     // the input, so it is formed once per plan (2 * NEAR_NSUB doubles per item)
     double* d_near_st = nullptr;
+    // far-field tables, input-independent, formed once per plan on the
+    // device: amp[n] = C_n h_{Mmax-1,n} e^{i pi n/(2N)} (zero for n < nd) and
+    // rowf[2j], rowf[2j+1] = e^{i(theta_j-pi/2)/2} (2 sin theta_j)^{-1/2},
+    // e^{i(theta_j-pi/2)} / (2 sin theta_j) on the Chebyshev grid
+    cplx* d_amp = nullptr;
+    cplx* d_rowf = nullptr;
     // workspace sizes per transform instance (bytes)
     size_t ws_X = 0, ws_v = 0, ws_items = 0, ws_near = 0, ws_dense = 0, ws_chat = 0, ws_vec = 0;
     size_t ws_part = 0, ws_sub = 0;
