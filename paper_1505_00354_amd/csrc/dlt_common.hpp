@@ -224,6 +224,10 @@ struct Tile {
     static_assert(LOG >= 6 && LOG <= 11, "compile-time tile lengths are 64..2048");
     static constexpr int COLS = FFT_CAP / L;
     static constexpr int STRIDE = L / 8;
+    // Stockham stages: radix 8 in registers, NMID radix-8 stages through
+    // LDS (p = 8, 64, ...), a last radix-2^RL stage in registers
+    static constexpr int RL = ((LOG - 3) % 3) ? (LOG - 3) % 3 : 3;
+    static constexpr int NMID = (LOG - 3 - RL) / 3;
     int col_, i0_, rb_;
     __device__ __forceinline__ Tile(int /*cols*/, int /*len*/)
         : col_((int)threadIdx.x % COLS), i0_((int)threadIdx.x / COLS), rb_(sw(col_ * L + i0_)) {}
@@ -254,6 +258,42 @@ struct Tile<0> {
     __device__ __forceinline__ int slot(int s) const { return lp(col(s) * len_ + idx(s)); }
 };
 
+// Twiddles of the LDS stages of a compile-time length L, stored after the
+// L/2 entries e^{2 pi i t/L} of the staged table: for the stage with span p,
+// 4p entries [j][k] = e^{2 pi i (j+1) k L/(8p) / L}, j < 4, k < p.  Lanes of
+// a stage read consecutive k, free of bank conflicts (the plain table's
+// indices j k L/(8p) are multiples of a large power of two).
+template <int L>
+constexpr int tw_mid_size() {
+    if constexpr (L < 64) {
+        return 0;
+    } else {
+        int n = 0;
+        for (int st = 0, p = 8; st < Tile<L>::NMID; ++st, p *= 8) n += 4 * p;
+        return n;
+    }
+}
+template <int L>
+constexpr int tw_mid_off(int st) {
+    int n = 0;
+    for (int i = 0, p = 8; i < st; ++i, p *= 8) n += 4 * p;
+    return n;
+}
+
+// Multiplies a[1..7] by w^1..w^7 with w^1..w^4 = w4[0], w4[p], w4[2p], w4[3p]
+// and the rest as w^4 w^j.
+template <class R>
+__device__ __forceinline__ void twiddle8_tab(cplxT<R>* a, const cplxT<R>* __restrict__ w4, int p) {
+    cplxT<R> w1 = w4[0], w2 = w4[p], w3 = w4[2 * p], w4v = w4[3 * p];
+    a[1] = cmul(a[1], w1);
+    a[2] = cmul(a[2], w2);
+    a[3] = cmul(a[3], w3);
+    a[4] = cmul(a[4], w4v);
+    a[5] = cmul(a[5], cmul(w4v, w1));
+    a[6] = cmul(a[6], cmul(w4v, w2));
+    a[7] = cmul(a[7], cmul(w4v, w3));
+}
+
 // Multiplies a[1..7] by w^1..w^7, w = tw[t] (e^{2 pi i t/L}); the powers up to
 // 4 come from the table (indices below L/2), the rest as w^4 w^j.
 template <class R>
@@ -270,7 +310,9 @@ __device__ __forceinline__ void twiddle8(cplxT<R>* a, const cplxT<R>* __restrict
 
 // DFT with the + sign of every sequence of the tile, v[s] holding the element
 // (col(s), idx(s)) on entry and the transform at the same position on exit.
-// `buf` is FFT_LDS slots of LDS, `tw` the table e^{2 pi i t/L}, t < L/2.
+// `buf` is TILE_LDS(L) slots of LDS, `tw` the table e^{2 pi i t/L}, t < L/2,
+// followed (compile-time L) by the stage table of tw_mid_size<L>() entries
+// (both as staged by stage_twiddles).
 // Stockham stages: radix 8 in registers, radix 8 through LDS, and a last
 // radix-8/4/2 stage in registers; all threads of the block must call it.  On
 // return `buf` is free for reuse (the last LDS reads are behind a barrier).
@@ -288,10 +330,9 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
         __syncthreads();
     } else {
         using TT = Tile<L>;
-        constexpr int LOG = TT::LOG;
         constexpr int ST = TT::STRIDE;
-        constexpr int RL = ((LOG - 3) % 3) ? (LOG - 3) % 3 : 3;  // log2 of the last radix
-        constexpr int NMID = (LOG - 3 - RL) / 3;
+        constexpr int RL = TT::RL;  // log2 of the last radix
+        constexpr int NMID = TT::NMID;
         const int cb = T.col_ * L;
         const int i0 = T.i0_;
         // Every slot below is sw(base) ^ sw(offset): the offset's bits lie
@@ -310,7 +351,7 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
             cplxT<R> a[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) a[j] = buf[T.rb_ ^ TT::sw(j * ST)];
-            twiddle8(a, tw, k * (L / (8 * p)));
+            twiddle8_tab(a, tw + L / 2 + tw_mid_off<L>(st) + k, p);
             dft8(a);
             __syncthreads();
             const int db = TT::sw(cb + (i0 - k) * 8 + k);
@@ -356,12 +397,24 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
 // FP32 table is the FP64 one rounded.  A run-time length (L == 0) reads the
 // global FP64 table directly, or copies len/2 rounded values for FP32.
 #define STAGE_TW(name, L, R) \
-    __shared__ cplxT<R> name[(L) > 1 ? (L) / 2 : (sizeof(R) == sizeof(double) ? 1 : FFT_CAP / 2)]
+    __shared__ cplxT<R> name[(L) > 1 ? (L) / 2 + tw_mid_size<L>() : (sizeof(R) == sizeof(double) ? 1 : FFT_CAP / 2)]
 template <int L, class R>
 __device__ __forceinline__ const cplxT<R>* stage_twiddles(cplxT<R>* stw, const cplx* __restrict__ src, int len) {
     if constexpr (L > 1) {
 #pragma unroll
         for (int i = threadIdx.x; i < L / 2; i += FFT_THREADS) stw[i] = cto<R>(src[i]);
+        // stage tables: entry (st, j, k) is e^{2 pi i (j+1) k (L/(8p))/L}, an
+        // index below L/2 of the plain table
+        for (int i = threadIdx.x; i < tw_mid_size<L>(); i += FFT_THREADS) {
+            int st = 0, p = 8, r = i;
+            while (r >= 4 * p) {
+                r -= 4 * p;
+                p *= 8;
+                ++st;
+            }
+            const int j = r / p, k = r % p;
+            stw[L / 2 + i] = cto<R>(src[(j + 1) * k * (L / (8 * p))]);
+        }
         __syncthreads();
         return stw;
     } else if constexpr (sizeof(R) == sizeof(double)) {

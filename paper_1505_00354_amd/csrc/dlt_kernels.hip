@@ -599,6 +599,25 @@ __device__ __forceinline__ void passB_load(const Geo& g, int vb0, const cplxT<R>
         if (T.live(s)) v[s] = src[threadIdx.x + s * FFT_THREADS];
 }
 
+// The far-field term list, entry l in lane l (MAX_TERMS = wave size): the
+// loops over terms take a term's fields with readlane, a register operation,
+// instead of a scalar load from the kernel arguments and its wait (which also
+// drains the outstanding LDS operations) in every iteration.
+static_assert(MAX_TERMS <= 64, "one term per lane");
+struct FarTerms {
+    int m_, blk_, nlo_;
+    __device__ __forceinline__ explicit FarTerms(const FarParams& F) {
+        const int l = (int)threadIdx.x & 63;
+        const bool in = l < F.nterm;
+        m_ = in ? F.term_m[l] : 0;
+        blk_ = in ? F.term_blk[l] : 0;
+        nlo_ = in ? F.blk[blk_].nlo : 0;
+    }
+    __device__ __forceinline__ int m(int t) const { return __builtin_amdgcn_readlane(m_, t); }
+    __device__ __forceinline__ int blk(int t) const { return __builtin_amdgcn_readlane(blk_, t); }
+    __device__ __forceinline__ int nlo(int t) const { return __builtin_amdgcn_readlane(nlo_, t); }
+};
+
 // ---------------------------------------------------------- far field A --
 // Terms t are ordered by ascending m.  For every term, taken in descending m
 // so that h_{m-1,n} = h_{m,n} m (n+m+1/2)/(m-1/2)^2 needs no division, the
@@ -614,6 +633,7 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
+    const FarTerms FT(F);
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
@@ -634,13 +654,13 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __
     }
     int mcur = F.Mmax - 1;
     for (int t = F.nterm - 1 - (int)blockIdx.y; t >= 0; t -= G) {
-        const int m = F.term_m[t];
+        const int m = FT.m(t);
         for (; mcur > m; --mcur) {
             const double fm = (double)mcur / ((mcur - 0.5) * (mcur - 0.5));
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) bh[s] = cscale(bh[s], fm * (nn[s] + mcur + 0.5));
         }
-        const int nlo = F.blk[F.term_blk[t]].nlo;
+        const int nlo = FT.nlo(t);
         cplxT<R> v[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) v[s] = (nn[s] >= nlo) ? cto<R>(bh[s]) : cplxT<R>{0, 0};
@@ -705,6 +725,7 @@ __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __
     STAGE_TW(stw, LB, R);
     const cplxT<R>* twB = stage_twiddles<LB, R>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
+    const FarTerms FT(F);
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int grp = blockIdx.y;
@@ -732,8 +753,8 @@ __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __
     cplxT<R> nx[FFT_VPT] = {};
     if (t < F.nterm) passB_load<LB, R>(g, jb0, Xb + (int64_t)t * N, nx, T);
     for (; t < F.nterm; t += G) {
-        const int m = F.term_m[t];
-        const int tb = F.term_blk[t];
+        const int m = FT.m(t);
+        const int tb = FT.blk(t);
         cplxT<R> z[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) z[s] = nx[s];
@@ -1488,6 +1509,7 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const cplx* _
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
+    const FarTerms FT(F);
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
@@ -1511,8 +1533,8 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const cplx* _
     }
     int mcur = 0;
     for (int t = blockIdx.y; t < F.nterm; t += G) {
-        const int m = F.term_m[t];
-        const int tb = F.term_blk[t];
+        const int m = FT.m(t);
+        const int tb = FT.blk(t);
         for (; mcur < m; ++mcur) {
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) gm[s] = cmul(gm[s], rq[s]);
@@ -1540,6 +1562,7 @@ __global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplx* _
     STAGE_TW(stw, LB, R);
     const cplxT<R>* twB = stage_twiddles<LB, R>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
+    const FarTerms FT(F);
     const int N = g.N;
     const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
@@ -1563,8 +1586,8 @@ __global__ FFT_BOUNDS void k_tfar_passB(Geo g, FarParams F, int G, const cplx* _
     cplxT<R> nx[FFT_VPT] = {};
     if (t >= 0) passB_load<LB, R>(g, jb0, Xb + (int64_t)t * N, nx, T);
     for (; t >= 0; t -= G) {
-        const int m = F.term_m[t];
-        const int nlo = F.blk[F.term_blk[t]].nlo;
+        const int m = FT.m(t);
+        const int nlo = FT.nlo(t);
         cplxT<R> U[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];

@@ -321,11 +321,15 @@ int plan_build(int64_t N, int prec, Plan& p) {
     const int qmax = bulk ? RAGGED_Q_MAX_BULK : RAGGED_Q_MAX;
     int nX = std::max({F.nterm, p.L / 2, qmax, 1});
     {
-        // enough blocks per pass to fill the GPU: at least 512 (tile, group) pairs
+        // about 512 (tile, term group) blocks per pass, one round of two per
+        // CU: every term group repeats its tiles' per-block set-up (twiddle
+        // staging, amplitude or row-factor reads, the first tile), so more
+        // groups than needed to fill the GPU cost time (measured at N = 2^20:
+        // one group per pass is fastest)
         int tilesA = g.N1 / g.colsA, tilesB = g.N2 / g.rowsB;
         int nt = std::max(F.nterm, 1);
-        p.tgA = std::min({nt, 16, std::max(1, (768 + tilesA - 1) / tilesA)});
-        p.tgB = std::min({nt, 4, std::max(1, (768 + tilesB - 1) / tilesB)});
+        p.tgA = std::min({nt, 16, std::max(1, (512 + tilesA - 1) / tilesA)});
+        p.tgB = std::min({nt, 4, std::max(1, (512 + tilesB - 1) / tilesB)});
     }
     p.ws_X = (size_t)nX * N * sizeof(cplx);
     if (f32)  // FP32 far terms; or the FP64 Taylor pair 0 + FP32 pairs 1..Q-1
