@@ -272,14 +272,15 @@ __global__ __launch_bounds__(1024) void k_nodes_boundary(NodeParams P, const dou
 // Boundary nodes for large N (no Newton step: the Bessel-zero start is
 // within an ulp): block (k, part) produces the transfer data of degrees
 // [part*N/P, (part+1)*N/P) at theta_k; k_nodes_bfin chains the P parts.
-__global__ __launch_bounds__(1024) void k_nodes_bpart(NodeParams P, const double* __restrict__ guess, int parts,
-                                                     double* __restrict__ scratch) {
-    __shared__ double sh[7 * 1024];
+constexpr int NODE_PART_THREADS = 256;
+__global__ __launch_bounds__(NODE_PART_THREADS) void k_nodes_bpart(NodeParams P, const double* __restrict__ guess,
+                                                                  int parts, double* __restrict__ scratch) {
+    __shared__ double sh[7 * NODE_PART_THREADS];
     const int N = P.N;
     const int k = blockIdx.x, part = blockIdx.y;
     const double pi = 3.141592653589793;
     const double t = (k + 0.5) * pi / N + guess[k];
-    const int T = blockDim.x, tid = threadIdx.x;
+    const int T = NODE_PART_THREADS, tid = threadIdx.x;
     const int lo = (int)((int64_t)N * part / parts), hi = (int)((int64_t)N * (part + 1) / parts);
     double s = sin(0.5 * t);
     double u = 2.0 * s * s;
@@ -314,19 +315,33 @@ __global__ __launch_bounds__(1024) void k_nodes_bpart(NodeParams P, const double
     }
 }
 
-__global__ void k_nodes_bfin(NodeParams P, const double* __restrict__ guess, int parts,
-                             const double* __restrict__ scratch, double* __restrict__ theta, double* __restrict__ w,
-                             double* __restrict__ dth) {
+// One wave per boundary node: lane i takes the transfer data of part i
+// (parts <= 64), and a shuffle tree combines them in order (each level joins
+// a run with the run after it).
+__global__ __launch_bounds__(64) void k_nodes_bfin(NodeParams P, const double* __restrict__ guess, int parts,
+                                                   const double* __restrict__ scratch, double* __restrict__ theta,
+                                                   double* __restrict__ w, double* __restrict__ dth) {
     const int N = P.N;
     const int k = blockIdx.x;
-    if (threadIdx.x != 0) return;
+    const int lane = threadIdx.x;
     const double pi = 3.141592653589793;
     Xfer x{1, 0, 0, 1, 0, 0, 0};
-    for (int part = 0; part < parts; ++part) {
-        const double* o = scratch + ((int64_t)k * parts + part) * 8;
-        Xfer y{o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
-        x = xfer_then(x, y);
+    if (lane < parts) {
+        const double* o = scratch + ((int64_t)k * parts + lane) * 8;
+        x = Xfer{o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
     }
+    for (int span = 1; span < 64; span *= 2) {
+        Xfer y;
+        y.a = __shfl_down(x.a, span);
+        y.b = __shfl_down(x.b, span);
+        y.c = __shfl_down(x.c, span);
+        y.d = __shfl_down(x.d, span);
+        y.qaa = __shfl_down(x.qaa, span);
+        y.qab = __shfl_down(x.qab, span);
+        y.qbb = __shfl_down(x.qbb, span);
+        if ((lane & (2 * span - 1)) == 0) x = xfer_then(x, y);
+    }
+    if (lane != 0) return;
     double delta = guess[k];
     double th = (k + 0.5) * pi / N + delta;
     double wk = 2.0 / x.qaa;  // Christoffel number from the true start (1, 0)
@@ -1682,23 +1697,48 @@ __global__ __launch_bounds__(64) void k_tnear_scan(NearParams NP, const double* 
     }
 }
 
-constexpr int TN_STEPS = 4;              // degrees per LDS tile and chain
+constexpr int TN_STEPS = 8;              // degrees per LDS tile and chain
 constexpr int TN_CH = 4;                 // independent recurrences per lane
 constexpr int TN_LEN = NEAR_CHUNK / TN_CH;
-constexpr int TN_COLS = TN_CH * TN_STEPS;  // columns of one tile
-constexpr int TN_SUM = 64 / TN_COLS;       // lanes that sum one column
+constexpr int TN_QUADS = TN_STEPS / 4;   // 4-degree groups per tile and chain
+constexpr int TN_PITCH = 65;             // LDS pitch of one (chain, group) slot
+
+// Lane sums of two doubles by exchanging wave halves or 16-lane rows
+// (v_permlane32_swap / v_permlane16_swap, register operations):
+//   sum32(x, y): lanes l < 32 get x_l + x_{l+32}, lanes l >= 32 get
+//                y_{l-32} + y_l;
+//   sum16(x, y): in rows R (16 lanes) 0, 1, 2, 3 the lanes get the sums of
+//                lanes l, l+16 of x (row 0), of y (row 1), of x (row 2) and of
+//                y (row 3), pairing rows 0/1 and 2/3.
+__device__ __forceinline__ double lane_sum32(double x, double y) {
+    const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
+    const unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
+    const auto rl = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
+}
+__device__ __forceinline__ double lane_sum16(double x, double y) {
+    const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
+    const unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
+    const auto rl = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
+}
 
 // Work-group = 64 rows of one segment and one degree chunk; each lane runs
 // its row over the chunk as TN_CH recurrences of TN_LEN degrees side by side
-// from the plan's states, the products P_n(x_j) w_j go through an LDS tile
-// and TN_SUM lanes sum a degree's column; partial sums per row group.  The
-// tile is small (8 KiB) so that many waves share a CU.
+// from the plan's states.  The products P_n(x_j) w_j of 4 consecutive degrees
+// are first summed over 4 rows in registers (lane_sum32 on degree pairs, then
+// lane_sum16): lane l then holds degree offset {0, 2, 1, 3}[l / 16] summed
+// over rows l % 16 + {0, 16, 32, 48}.  These partials go through an LDS tile
+// (a quarter of the products) where two lanes sum a degree's 16 partials;
+// partial sums per row group.
 __global__ __launch_bounds__(64) void k_tnear_accum(int N, NearParams NP, const int* __restrict__ wg_seg,
                                                     const int* __restrict__ segoff, const double* __restrict__ rcp,
                                                     const double* __restrict__ u, int64_t u_stride,
                                                     const double* __restrict__ st, double* __restrict__ part,
                                                     int64_t part_stride) {
-    __shared__ double tile[TN_CH][TN_STEPS][64 + 1];
+    __shared__ double tile[TN_CH * TN_QUADS * TN_PITCH];
     __shared__ double sr[NEAR_CHUNK];
     const NearWG W = near_wg(NP, wg_seg, segoff, blockIdx.x);
     const Seg S = NP.seg[W.seg];
@@ -1734,35 +1774,42 @@ __global__ __launch_bounds__(64) void k_tnear_accum(int N, NearParams NP, const 
     __syncthreads();
     double* pb = part + b * part_stride + (int64_t)rg_global * N;
     const double we = uj + um, wo = uj - um;  // weights of even / odd degrees
-    // reduction lanes: column c = lane % TN_COLS = (chain, degree); the
-    // TN_SUM lanes of a column take 64 / TN_SUM rows each.  Row pitch 65:
-    // the lanes of a 32-lane group read distinct banks.
-    const int cidx = threadIdx.x % TN_COLS, kc = cidx / TN_STEPS, col = cidx % TN_STEPS;
-    const int part_r = threadIdx.x / TN_COLS;
+    // reduction: lane L sums column c = L % 32 = (chain, degree of the tile)
+    // over 8 of its 16 partials, the other 8 in lane L + 32.  Lanes of rows
+    // 2, 3 start half a row on, which with the odd pitch keeps each 32-lane
+    // group on distinct banks.
+    const int c = threadIdx.x & 31, half = threadIdx.x >> 5;
+    const int kc = c / TN_STEPS, dcol = c % TN_STEPS;
+    const int rsel = (dcol & 3) == 1 ? 2 : (dcol & 3) == 2 ? 1 : (dcol & 3);  // row of the degree offset
+    const int rbase = (kc * TN_QUADS + (dcol >> 2)) * TN_PITCH + rsel * 16;
+    const int p0 = half * 8 + (rsel >> 1) * 8;
     for (int nb = 0; nb < TN_LEN; nb += TN_STEPS) {
 #pragma unroll
-        for (int i = 0; i < TN_STEPS; i += 2) {
+        for (int qd = 0; qd < TN_QUADS; ++qd) {
+            double v[TN_CH][4];
 #pragma unroll
-            for (int k = 0; k < TN_CH; ++k) {
-                const int o = k * TN_LEN + nb + i;
-                tile[k][i][threadIdx.x] = p[k] * we;
-                reinsch_step(uu, sr[o], p[k], d[k]);
-                tile[k][i + 1][threadIdx.x] = p[k] * wo;
-                reinsch_step(uu, sr[o + 1], p[k], d[k]);
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                for (int k = 0; k < TN_CH; ++k) {
+                    v[k][i] = p[k] * ((i & 1) ? wo : we);
+                    reinsch_step(uu, sr[k * TN_LEN + nb + 4 * qd + i], p[k], d[k]);
+                }
             }
+#pragma unroll
+            for (int k = 0; k < TN_CH; ++k)
+                tile[(k * TN_QUADS + qd) * TN_PITCH + threadIdx.x] =
+                    lane_sum16(lane_sum32(v[k][0], v[k][1]), lane_sum32(v[k][2], v[k][3]));
         }
         __syncthreads();
-        double s = 0, s1 = 0;
+        double s0 = 0, s1 = 0;
 #pragma unroll
-        for (int r = 0; r < 64 / TN_SUM; r += 2) {
-            s += tile[kc][col][part_r * (64 / TN_SUM) + r];
-            s1 += tile[kc][col][part_r * (64 / TN_SUM) + r + 1];
+        for (int i = 0; i < 8; i += 2) {
+            s0 += tile[rbase + ((p0 + i) & 15)];
+            s1 += tile[rbase + ((p0 + i + 1) & 15)];
         }
-        s += s1;
-#pragma unroll
-        for (int x = TN_COLS; x < 64; x <<= 1) s += __shfl_xor(s, x);
-        const int n = n0 + kc * TN_LEN + nb + col;
-        if (part_r == 0 && n < n1) pb[n] = s;
+        const double s = lane_sum32(s0 + s1, s0 + s1);
+        const int n = n0 + kc * TN_LEN + nb + dcol;
+        if (half == 0 && n < n1) pb[n] = s;
         __syncthreads();
     }
 }
@@ -1983,10 +2030,11 @@ hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, doubl
     if (P.kb > 0) {
         DLT_TRY(dep(s, sb, L.ev[0]));
         if (P.newton_b == 0 && P.N >= (1 << 16)) {
-            int parts = P.N >> 16;
-            if (parts > NODE_PARTS_MAX) parts = NODE_PARTS_MAX;
+            // about 64 degrees per thread, up to NODE_PARTS_MAX parts per node
+            int parts = P.N / (NODE_PART_THREADS * 64);
+            parts = std::max(1, std::min(parts, NODE_PARTS_MAX));
             traced("k_nodes_bpart", sb, [&] {
-                k_nodes_bpart<<<dim3(P.kb, parts), 1024, 0, sb>>>(P, p.d_guess, parts, scratch);
+                k_nodes_bpart<<<dim3(P.kb, parts), NODE_PART_THREADS, 0, sb>>>(P, p.d_guess, parts, scratch);
             });
             traced("k_nodes_bfin", sb, [&] {
                 k_nodes_bfin<<<P.kb, 64, 0, sb>>>(P, p.d_guess, parts, scratch, theta, w, dth);
