@@ -726,8 +726,10 @@ __global__ void k_far_tables(int N, FarParams F, cplx* __restrict__ amp, cplx* _
         a = cscale(half_shift(n, N), stieltjes_C((double)n) * (F.hK / den));
     }
     amp[n] = a;
+    // row factors by DFT output index m = n (row j(m)), the order in which
+    // the passes read them
     cplx g0, rq;
-    far_row_factors(n, N, g0, rq);
+    far_row_factors(row_of(n, N), N, g0, rq);
     rowf[2 * n] = g0;
     rowf[2 * n + 1] = rq;
 }
@@ -759,8 +761,8 @@ __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __
             const int j = row_of(mo, N);
             const int blk = row_block(F, j, N);
             if (blk >= 0) key[s] = 2 * blk + (2 * mo >= N ? 1 : 0);
-            gm[s] = rowf[2 * j];
-            rq[s] = rowf[2 * j + 1];
+            gm[s] = rowf[2 * mo];
+            rq[s] = rowf[2 * mo + 1];
         }
     }
     int mcur = 0;
@@ -1542,8 +1544,8 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const cplx* _
             const int j = row_of(mo, N);
             const int blk = row_block(F, j, N);
             if (blk >= 0) key[s] = 2 * blk + (2 * mo >= N ? 1 : 0);
-            rq[s] = rowf[2 * j + 1];
-            gm[s] = cscale(rowf[2 * j], ub[j]);
+            rq[s] = rowf[2 * mo + 1];
+            gm[s] = cscale(rowf[2 * mo], ub[j]);
         }
     }
     int mcur = 0;
