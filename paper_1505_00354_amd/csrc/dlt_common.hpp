@@ -308,6 +308,41 @@ __device__ __forceinline__ void twiddle8(cplxT<R>* a, const cplxT<R>* __restrict
     a[7] = cmul(a[7], cmul(w4, w3));
 }
 
+// Last Stockham stage of a compile-time length L (radix 2^RL, p = L /
+// 2^RL) in registers: butterfly index k = i < p with i = i0 + s*STRIDE.
+template <int L, class R>
+__device__ __forceinline__ void tile_last(cplxT<R>* v, const cplxT<R>* __restrict__ tw, int i0) {
+    using TT = Tile<L>;
+    constexpr int ST = TT::STRIDE;
+    constexpr int RL = TT::RL;
+    if constexpr (RL == 3) {
+        twiddle8(v, tw, i0);
+        dft8(v);
+    } else if constexpr (RL == 2) {
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            const int i = i0 + sp * ST;
+            cplxT<R> w1 = tw[i], w2 = tw[2 * i];
+            cplxT<R> w3 = cmul(w1, w2);
+            cplxT<R> x0 = v[sp], x1 = cmul(v[sp + 2], w1), x2 = cmul(v[sp + 4], w2), x3 = cmul(v[sp + 6], w3);
+            cplxT<R> s02 = cadd(x0, x2), d02 = csub(x0, x2);
+            cplxT<R> s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
+            v[sp] = cadd(s02, s13);
+            v[sp + 2] = cadd(d02, d13);
+            v[sp + 4] = csub(s02, s13);
+            v[sp + 6] = csub(d02, d13);
+        }
+    } else {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            cplxT<R> x1 = cmul(v[sp + 4], tw[i0 + sp * ST]);
+            cplxT<R> x0 = v[sp];
+            v[sp] = cadd(x0, x1);
+            v[sp + 4] = csub(x0, x1);
+        }
+    }
+}
+
 // DFT with the + sign of every sequence of the tile, v[s] holding the element
 // (col(s), idx(s)) on entry and the transform at the same position on exit.
 // `buf` is TILE_LDS(L) slots of LDS, `tw` the table e^{2 pi i t/L}, t < L/2,
@@ -331,7 +366,6 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
     } else {
         using TT = Tile<L>;
         constexpr int ST = TT::STRIDE;
-        constexpr int RL = TT::RL;  // log2 of the last radix
         constexpr int NMID = TT::NMID;
         const int cb = T.col_ * L;
         const int i0 = T.i0_;
@@ -362,33 +396,67 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
 #pragma unroll
         for (int s = 0; s < 8; ++s) v[s] = buf[T.rb_ ^ TT::sw(s * ST)];
         __syncthreads();
-        // last stage, p = L / radix: butterfly index k = i < p
-        if constexpr (RL == 3) {
-            twiddle8(v, tw, i0);
-            dft8(v);
-        } else if constexpr (RL == 2) {
+        tile_last<L>(v, tw, i0);
+    }
+}
+
+// tile_fft of two independent tiles (v1 in buf1, v2 in buf2, the same
+// sequence geometry and table): every stage runs for both before its
+// barrier, so a block waits at half the barriers per tile and each wave
+// has two independent streams of butterflies and LDS accesses.
+template <int L, class R>
+__device__ __forceinline__ void tile_fft2(cplxT<R>* v1, cplxT<R>* v2, cplxT<R>* buf1, cplxT<R>* buf2,
+                                          const cplxT<R>* __restrict__ tw, const Tile<L>& T) {
+    if constexpr (L == 0) {
+        tile_fft<L>(v1, buf1, tw, T);
+        tile_fft<L>(v2, buf2, tw, T);
+    } else {
+        using TT = Tile<L>;
+        constexpr int ST = TT::STRIDE;
+        constexpr int NMID = TT::NMID;
+        const int cb = T.col_ * L;
+        const int i0 = T.i0_;
+        dft8(v1);
+        dft8(v2);
+        const int wb = TT::sw(cb + 8 * i0);
 #pragma unroll
-            for (int sp = 0; sp < 2; ++sp) {
-                const int i = i0 + sp * ST;
-                cplxT<R> w1 = tw[i], w2 = tw[2 * i];
-                cplxT<R> w3 = cmul(w1, w2);
-                cplxT<R> x0 = v[sp], x1 = cmul(v[sp + 2], w1), x2 = cmul(v[sp + 4], w2), x3 = cmul(v[sp + 6], w3);
-                cplxT<R> s02 = cadd(x0, x2), d02 = csub(x0, x2);
-                cplxT<R> s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
-                v[sp] = cadd(s02, s13);
-                v[sp + 2] = cadd(d02, d13);
-                v[sp + 4] = csub(s02, s13);
-                v[sp + 6] = csub(d02, d13);
-            }
-        } else {
-#pragma unroll
-            for (int sp = 0; sp < 4; ++sp) {
-                cplxT<R> x1 = cmul(v[sp + 4], tw[i0 + sp * ST]);
-                cplxT<R> x0 = v[sp];
-                v[sp] = cadd(x0, x1);
-                v[sp + 4] = csub(x0, x1);
-            }
+        for (int q = 0; q < 8; ++q) {
+            buf1[wb ^ TT::sw(q)] = v1[q];
+            buf2[wb ^ TT::sw(q)] = v2[q];
         }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < NMID; ++st) {
+            const int p = 8 << (3 * st);
+            const int k = i0 & (p - 1);
+            const cplxT<R>* w4 = tw + L / 2 + tw_mid_off<L>(st) + k;
+            cplxT<R> a1[8], a2[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                a1[j] = buf1[T.rb_ ^ TT::sw(j * ST)];
+                a2[j] = buf2[T.rb_ ^ TT::sw(j * ST)];
+            }
+            twiddle8_tab(a1, w4, p);
+            dft8(a1);
+            twiddle8_tab(a2, w4, p);
+            dft8(a2);
+            __syncthreads();
+            const int db = TT::sw(cb + (i0 - k) * 8 + k);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                buf1[db ^ TT::sw(q * p)] = a1[q];
+                buf2[db ^ TT::sw(q * p)] = a2[q];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            v1[s] = buf1[T.rb_ ^ TT::sw(s * ST)];
+            v2[s] = buf2[T.rb_ ^ TT::sw(s * ST)];
+        }
+        __syncthreads();
+        tile_last<L>(v1, tw, i0);
+        tile_last<L>(v2, tw, i0);
     }
 }
 
@@ -406,11 +474,10 @@ __device__ __forceinline__ const cplxT<R>* stage_twiddles(cplxT<R>* stw, const c
         // stage tables: entry (st, j, k) is e^{2 pi i (j+1) k (L/(8p))/L}, an
         // index below L/2 of the plain table
         for (int i = threadIdx.x; i < tw_mid_size<L>(); i += FFT_THREADS) {
-            int st = 0, p = 8, r = i;
+            int p = 8, r = i;  // stage span p and the index inside its table
             while (r >= 4 * p) {
                 r -= 4 * p;
                 p *= 8;
-                ++st;
             }
             const int j = r / p, k = r % p;
             stw[L / 2 + i] = cto<R>(src[(j + 1) * k * (L / (8 * p))]);

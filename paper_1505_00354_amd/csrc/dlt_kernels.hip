@@ -644,7 +644,11 @@ template <int LA, class R>
 __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __restrict__ amp,
                                                           const double* __restrict__ c, int64_t c_stride,
                                                           cplxT<R>* __restrict__ X, int64_t x_stride) {
-    __shared__ cplxT<R> buf[TILE_LDS(LA)];
+    // FP32 tiles are transformed in pairs of terms (two tiles); FP64 tiles
+    // one at a time (a pair would not fit the registers of two waves per SIMD)
+    constexpr bool PAIRS = sizeof(R) == sizeof(float);
+    __shared__ cplxT<R> buf[TILE_LDS(LA) * (PAIRS ? 2 : 1)];
+    cplxT<R>* const buf2 = buf + TILE_LDS(LA);
     STAGE_TW(stw, LA, R);
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
@@ -668,7 +672,8 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __
         }
     }
     int mcur = F.Mmax - 1;
-    for (int t = F.nterm - 1 - (int)blockIdx.y; t >= 0; t -= G) {
+    // the input of term t at the current m (advanced down to term t's m)
+    auto input = [&](int t, cplxT<R>* v) {
         const int m = FT.m(t);
         for (; mcur > m; --mcur) {
             const double fm = (double)mcur / ((mcur - 0.5) * (mcur - 0.5));
@@ -676,9 +681,24 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __
             for (int s = 0; s < FFT_VPT; ++s) bh[s] = cscale(bh[s], fm * (nn[s] + mcur + 0.5));
         }
         const int nlo = FT.nlo(t);
-        cplxT<R> v[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) v[s] = (nn[s] >= nlo) ? cto<R>(bh[s]) : cplxT<R>{0, 0};
+    };
+    // terms in pairs (t, t - G): two tiles per barrier sequence
+    int t = F.nterm - 1 - (int)blockIdx.y;
+    if constexpr (PAIRS) {
+        for (; t - G >= 0; t -= 2 * G) {
+            cplxT<R> v1[FFT_VPT], v2[FFT_VPT];
+            input(t, v1);
+            input(t - G, v2);
+            tile_fft2<LA>(v1, v2, buf, buf2, twA, T);
+            out.put(g, v1, Xb + (int64_t)t * N, T);
+            out.put(g, v2, Xb + (int64_t)(t - G) * N, T);
+        }
+    }
+    for (; t >= 0; t -= G) {
+        cplxT<R> v[FFT_VPT];
+        input(t, v);
         tile_fft<LA>(v, buf, twA, T);
         out.put(g, v, Xb + (int64_t)t * N, T);
     }
@@ -726,12 +746,11 @@ __global__ void k_far_tables(int N, FarParams F, cplx* __restrict__ amp, cplx* _
         a = cscale(half_shift(n, N), stieltjes_C((double)n) * (F.hK / den));
     }
     amp[n] = a;
-    // row factors by DFT output index m = n (row j(m)), the order in which
-    // the passes read them
+    // row factor by DFT output index m = n (row j(m)), the order in which
+    // the passes read it; the ratio between consecutive m is its square
     cplx g0, rq;
     far_row_factors(row_of(n, N), N, g0, rq);
-    rowf[2 * n] = g0;
-    rowf[2 * n + 1] = rq;
+    rowf[n] = g0;
 }
 
 template <int LB, class R>
@@ -751,24 +770,28 @@ __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __
     cplx gm[FFT_VPT], rq[FFT_VPT];
     double acc[FFT_VPT];
     int key[FFT_VPT];  // 2 * block + (conjugated output), -1 outside
+    int t = grp;
+    // the first tile's loads go out before the row factors', so that
+    // waiting for the tile does not wait for the factors (loads retire in
+    // order)
+    cplxT<R> nx[FFT_VPT] = {};
+    if (t < F.nterm) passB_load<LB, R>(g, jb0, Xb + (int64_t)t * N, nx, T);
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         acc[s] = 0;
         key[s] = -1;
-        gm[s] = rq[s] = {0, 0};
+        gm[s] = {0, 0};
         if (T.live(s)) {
             const int mo = jb0 + T.col(s) + g.N2 * T.idx(s);
             const int j = row_of(mo, N);
             const int blk = row_block(F, j, N);
             if (blk >= 0) key[s] = 2 * blk + (2 * mo >= N ? 1 : 0);
-            gm[s] = rowf[2 * mo];
-            rq[s] = rowf[2 * mo + 1];
+            gm[s] = rowf[mo];
         }
     }
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) rq[s] = cmul(gm[s], gm[s]);
     int mcur = 0;
-    int t = grp;
-    cplxT<R> nx[FFT_VPT] = {};
-    if (t < F.nterm) passB_load<LB, R>(g, jb0, Xb + (int64_t)t * N, nx, T);
     for (; t < F.nterm; t += G) {
         const int m = FT.m(t);
         const int tb = FT.blk(t);
@@ -1544,8 +1567,9 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const cplx* _
             const int j = row_of(mo, N);
             const int blk = row_block(F, j, N);
             if (blk >= 0) key[s] = 2 * blk + (2 * mo >= N ? 1 : 0);
-            rq[s] = rowf[2 * mo + 1];
-            gm[s] = cscale(rowf[2 * mo], ub[j]);
+            const cplx g0 = rowf[mo];
+            rq[s] = cmul(g0, g0);
+            gm[s] = cscale(g0, ub[j]);
         }
     }
     int mcur = 0;
@@ -1979,7 +2003,7 @@ hipError_t plan_prepare(Plan& p) {
     if (p.far.nterm > 0) {
         const int N = (int)p.N;
         hipError_t e = hipMalloc(&p.d_amp, (size_t)N * sizeof(cplx));
-        if (e == hipSuccess) e = hipMalloc(&p.d_rowf, (size_t)N * 2 * sizeof(cplx));
+        if (e == hipSuccess) e = hipMalloc(&p.d_rowf, (size_t)N * sizeof(cplx));
         if (e != hipSuccess) return e;
         k_far_tables<<<(N + 255) / 256, 256, 0, 0>>>(N, p.far, p.d_amp, p.d_rowf);
         e = hipGetLastError();

@@ -129,9 +129,9 @@ struct Plan {
     double* d_near_st = nullptr;
     // far-field tables, input-independent, formed once per plan on the
     // device: amp[n] = C_n h_{Mmax-1,n} e^{i pi n/(2N)} (zero for n < nd) and
-    // rowf[2m], rowf[2m+1] = e^{i(theta_j-pi/2)/2} (2 sin theta_j)^{-1/2},
-    // e^{i(theta_j-pi/2)} / (2 sin theta_j) on the Chebyshev grid, for the
-    // row j = j(m) of DFT output m
+    // rowf[m] = e^{i(theta_j-pi/2)/2} (2 sin theta_j)^{-1/2} on the Chebyshev
+    // grid, for the row j = j(m) of DFT output m (its square is the factor
+    // e^{i(theta_j-pi/2)} / (2 sin theta_j) between consecutive terms m)
     cplx* d_amp = nullptr;
     cplx* d_rowf = nullptr;
     // workspace sizes per transform instance (bytes)
