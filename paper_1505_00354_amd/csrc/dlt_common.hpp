@@ -260,45 +260,33 @@ struct Tile<0> {
 
 // Twiddles of the LDS stages of a compile-time length L, stored after the
 // L/2 entries e^{2 pi i t/L} of the staged table: for the stage with span p,
-// 4p entries [j][k] = e^{2 pi i (j+1) k L/(8p) / L}, j < 4, k < p.  Lanes of
-// a stage read consecutive k, free of bank conflicts (the plain table's
-// indices j k L/(8p) are multiples of a large power of two).
+// p entries [k] = e^{2 pi i k L/(8p) / L}, k < p.  Lanes of a stage read
+// consecutive k, free of bank conflicts (the plain table's indices k L/(8p)
+// are multiples of a large power of two).  The higher powers are formed by
+// products: LDS bandwidth, not arithmetic, bounds the tile transform.
 template <int L>
 constexpr int tw_mid_size() {
     if constexpr (L < 64) {
         return 0;
     } else {
         int n = 0;
-        for (int st = 0, p = 8; st < Tile<L>::NMID; ++st, p *= 8) n += 4 * p;
+        for (int st = 0, p = 8; st < Tile<L>::NMID; ++st, p *= 8) n += p;
         return n;
     }
 }
 template <int L>
 constexpr int tw_mid_off(int st) {
     int n = 0;
-    for (int i = 0, p = 8; i < st; ++i, p *= 8) n += 4 * p;
+    for (int i = 0, p = 8; i < st; ++i, p *= 8) n += p;
     return n;
 }
 
-// Multiplies a[1..7] by w^1..w^7 with w^1..w^4 = w4[0], w4[p], w4[2p], w4[3p]
-// and the rest as w^4 w^j.
+// Multiplies a[1..7] by w^1..w^7, w = *w1 (w^2 = w w, w^3 = w^2 w,
+// w^4 = w^2 w^2, w^{4+j} = w^4 w^j).
 template <class R>
-__device__ __forceinline__ void twiddle8_tab(cplxT<R>* a, const cplxT<R>* __restrict__ w4, int p) {
-    cplxT<R> w1 = w4[0], w2 = w4[p], w3 = w4[2 * p], w4v = w4[3 * p];
-    a[1] = cmul(a[1], w1);
-    a[2] = cmul(a[2], w2);
-    a[3] = cmul(a[3], w3);
-    a[4] = cmul(a[4], w4v);
-    a[5] = cmul(a[5], cmul(w4v, w1));
-    a[6] = cmul(a[6], cmul(w4v, w2));
-    a[7] = cmul(a[7], cmul(w4v, w3));
-}
-
-// Multiplies a[1..7] by w^1..w^7, w = tw[t] (e^{2 pi i t/L}); the powers up to
-// 4 come from the table (indices below L/2), the rest as w^4 w^j.
-template <class R>
-__device__ __forceinline__ void twiddle8(cplxT<R>* a, const cplxT<R>* __restrict__ tw, int t) {
-    cplxT<R> w1 = tw[t], w2 = tw[2 * t], w3 = tw[3 * t], w4 = tw[4 * t];
+__device__ __forceinline__ void twiddle8_tab(cplxT<R>* a, const cplxT<R>* __restrict__ w1p) {
+    const cplxT<R> w1 = *w1p;
+    const cplxT<R> w2 = cmul(w1, w1), w3 = cmul(w2, w1), w4 = cmul(w2, w2);
     a[1] = cmul(a[1], w1);
     a[2] = cmul(a[2], w2);
     a[3] = cmul(a[3], w3);
@@ -306,6 +294,13 @@ __device__ __forceinline__ void twiddle8(cplxT<R>* a, const cplxT<R>* __restrict
     a[5] = cmul(a[5], cmul(w4, w1));
     a[6] = cmul(a[6], cmul(w4, w2));
     a[7] = cmul(a[7], cmul(w4, w3));
+}
+
+// Multiplies a[1..7] by w^1..w^7, w = tw[t] (e^{2 pi i t/L}), the powers
+// formed from w as in twiddle8_tab.
+template <class R>
+__device__ __forceinline__ void twiddle8(cplxT<R>* a, const cplxT<R>* __restrict__ tw, int t) {
+    twiddle8_tab(a, tw + t);
 }
 
 // Last Stockham stage of a compile-time length L (radix 2^RL, p = L /
@@ -322,8 +317,8 @@ __device__ __forceinline__ void tile_last(cplxT<R>* v, const cplxT<R>* __restric
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp) {
             const int i = i0 + sp * ST;
-            cplxT<R> w1 = tw[i], w2 = tw[2 * i];
-            cplxT<R> w3 = cmul(w1, w2);
+            cplxT<R> w1 = tw[i];
+            cplxT<R> w2 = cmul(w1, w1), w3 = cmul(w1, w2);
             cplxT<R> x0 = v[sp], x1 = cmul(v[sp + 2], w1), x2 = cmul(v[sp + 4], w2), x3 = cmul(v[sp + 6], w3);
             cplxT<R> s02 = cadd(x0, x2), d02 = csub(x0, x2);
             cplxT<R> s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3));
@@ -385,7 +380,7 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
             cplxT<R> a[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) a[j] = buf[T.rb_ ^ TT::sw(j * ST)];
-            twiddle8_tab(a, tw + L / 2 + tw_mid_off<L>(st) + k, p);
+            twiddle8_tab(a, tw + L / 2 + tw_mid_off<L>(st) + k);
             dft8(a);
             __syncthreads();
             const int db = TT::sw(cb + (i0 - k) * 8 + k);
@@ -429,16 +424,16 @@ __device__ __forceinline__ void tile_fft2(cplxT<R>* v1, cplxT<R>* v2, cplxT<R>* 
         for (int st = 0; st < NMID; ++st) {
             const int p = 8 << (3 * st);
             const int k = i0 & (p - 1);
-            const cplxT<R>* w4 = tw + L / 2 + tw_mid_off<L>(st) + k;
+            const cplxT<R>* w1p = tw + L / 2 + tw_mid_off<L>(st) + k;
             cplxT<R> a1[8], a2[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 a1[j] = buf1[T.rb_ ^ TT::sw(j * ST)];
                 a2[j] = buf2[T.rb_ ^ TT::sw(j * ST)];
             }
-            twiddle8_tab(a1, w4, p);
+            twiddle8_tab(a1, w1p);
             dft8(a1);
-            twiddle8_tab(a2, w4, p);
+            twiddle8_tab(a2, w1p);
             dft8(a2);
             __syncthreads();
             const int db = TT::sw(cb + (i0 - k) * 8 + k);
@@ -471,16 +466,15 @@ __device__ __forceinline__ const cplxT<R>* stage_twiddles(cplxT<R>* stw, const c
     if constexpr (L > 1) {
 #pragma unroll
         for (int i = threadIdx.x; i < L / 2; i += FFT_THREADS) stw[i] = cto<R>(src[i]);
-        // stage tables: entry (st, j, k) is e^{2 pi i (j+1) k (L/(8p))/L}, an
-        // index below L/2 of the plain table
+        // stage tables: entry (st, k) is e^{2 pi i k (L/(8p))/L}, an index
+        // below L/8 of the plain table
         for (int i = threadIdx.x; i < tw_mid_size<L>(); i += FFT_THREADS) {
-            int p = 8, r = i;  // stage span p and the index inside its table
-            while (r >= 4 * p) {
-                r -= 4 * p;
+            int p = 8, k = i;  // stage span p and the index inside its table
+            while (k >= p) {
+                k -= p;
                 p *= 8;
             }
-            const int j = r / p, k = r % p;
-            stw[L / 2 + i] = cto<R>(src[(j + 1) * k * (L / (8 * p))]);
+            stw[L / 2 + i] = cto<R>(src[k * (L / (8 * p))]);
         }
         __syncthreads();
         return stw;

@@ -28,6 +28,12 @@ __device__ __forceinline__ cplx half_shift(int64_t n, int N) {
     return {c, s};
 }
 
+// e^{i pi n/(2N)}, 0 <= n < 4N, from the plan's tables:
+// e^{2 pi i floor(n/4)/N} e^{i pi (n mod 4)/(2N)}
+__device__ __forceinline__ cplx half_shift_tab(const Geo& g, int n) {
+    return cmul(tw2(g.twHi, g.twLo, n >> 2, g.sh), g.qs[n & 3]);
+}
+
 // ------------------------------------------------------------------ nodes --
 // Interior nodes k in [kb, ceil(N/2)): Newton in delta = theta - theta*_k
 // (theta*_k = (k+1/2)pi/N) on the M-term Stieltjes expansion of P_N(cos theta)
@@ -1089,7 +1095,7 @@ __global__ FFT_BOUNDS void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ 
     for (int s = 0; s < FFT_VPT; ++s) {
         if (T.live(s)) {
             const int n = jb0 + T.col(s) + g.N2 * T.idx(s);
-            const cplx t = half_shift(n, N);
+            const cplx t = half_shift_tab(g, n);
             double val = (t.re * z[s].re - t.im * z[s].im) * ((n == 0) ? 1.0 : 2.0) / N;
             if (n < nd) val += db[n];
             cb[n] = val;
@@ -1133,7 +1139,7 @@ __global__ FFT_BOUNDS void k_ndct_passA(Geo g, int qa, int qb, int QG, const dou
                 if (q0 == 0) Ap[s] = {cb[0], 0};
             } else {
                 const double x = n * invN, y = (N - n) * invN;
-                const cplx e2 = cscale(half_shift(n, N), 0.5);
+                const cplx e2 = cscale(half_shift_tab(g, n), 0.5);
                 double a = 1, bb = 1;
                 for (int q = 0; q < q0; ++q) {
                     a *= x * x;
@@ -1187,6 +1193,16 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
     const cplxT<R>* X1b = X1 + b * x1_stride;
     double acc[FFT_VPT], d[FFT_VPT];
     int kn[FFT_VPT];  // output index: grid row, or the node paired with it (-1: none)
+    // the first tile's loads go out before the node offsets' (loads retire
+    // in order: waiting for the tile then does not wait for them)
+    cplx nx[FFT_VPT] = {};
+    cplxT<R> nxr[FFT_VPT] = {};
+    if constexpr (sizeof(R) == sizeof(double)) {
+        passB_load<LB, double>(g, jb0, X0b + (int64_t)(Q - 1) * N, nx, T);
+    } else {
+        if (Q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(Q - 2) * N, nxr, T);
+        else passB_load<LB, double>(g, jb0, X0b, nx, T);
+    }
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         acc[s] = 0;
@@ -1217,8 +1233,6 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
     };
     if constexpr (sizeof(R) == sizeof(double)) {
         // all pairs FP64 and contiguous (X1 = X0 + N): one prefetch buffer
-        cplx nx[FFT_VPT] = {};
-        passB_load<LB, double>(g, jb0, X0b + (int64_t)(Q - 1) * N, nx, T);
         for (int q = Q - 1; q >= 0; --q) {
             cplx z[FFT_VPT];
 #pragma unroll
@@ -1228,24 +1242,21 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
             horner(q, z);
         }
     } else {
-        cplxT<R> nx[FFT_VPT] = {};
-        cplx n0[FFT_VPT] = {};
-        if (Q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(Q - 2) * N, nx, T);
-        else passB_load<LB, double>(g, jb0, X0b, n0, T);
+        // pairs Q-1..1 in precision R (prefetched into nxr), pair 0 FP64 (nx)
         for (int q = Q - 1; q >= 1; --q) {
             cplxT<R> z[FFT_VPT];
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) z[s] = nx[s];
-            if (q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 2) * N, nx, T);
-            else passB_load<LB, double>(g, jb0, X0b, n0, T);
+            for (int s = 0; s < FFT_VPT; ++s) z[s] = nxr[s];
+            if (q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 2) * N, nxr, T);
+            else passB_load<LB, double>(g, jb0, X0b, nx, T);
             tile_fft<LB>(z, bufr, twr, T);
             cplx U[FFT_VPT];
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
             horner(q, U);
         }
-        tile_fft<LB>(n0, bufd, twd, T);
-        horner(0, n0);
+        tile_fft<LB>(nx, bufd, twd, T);
+        horner(0, nx);
     }
     double* fb = RR.gk ? f + RR.offs[b] : f + b * f_stride;
 #pragma unroll
@@ -1357,7 +1368,7 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
             const int r = actual_row(vb0 + i, N2);
             const int n = r + N2 * ja;
             xs[s] = (double)n / N;
-            en[s] = half_shift(n, N);
+            en[s] = half_shift_tab(g, n);
             int ip, jp;
             if (r == 0) {
                 ip = i;
@@ -1507,7 +1518,7 @@ __global__ FFT_BOUNDS void k_dct3_passA(Geo g, const double* __restrict__ y, int
         if (T.live(s)) {
             const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             const double a = yb[n] * ((n == 0) ? 1.0 : 2.0) / N;
-            x[s] = cscale(half_shift(n, N), a);
+            x[s] = cscale(half_shift_tab(g, n), a);
         }
     }
     tile_fft<LA>(x, buf, twA, T);

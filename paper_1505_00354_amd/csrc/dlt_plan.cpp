@@ -153,6 +153,11 @@ int plan_build(int64_t N, int prec, Plan& p) {
     g.twN2 = p.d_twN2;
     g.twHi = p.d_twHi;
     g.twLo = p.d_twLo;
+    for (int k = 0; k < 4; ++k) {
+        const LD a = PI_L * (LD)k / (2 * (LD)N);
+        g.qs[k].re = (double)cosl(a);
+        g.qs[k].im = (double)sinl(a);
+    }
 
     // ---- Taylor truncation (Corollary 2 with max N|dtheta| <= 0.83845)
     {

@@ -36,6 +36,7 @@ struct Geo {
     const cplx* twN2;  // e^{2 pi i t/N2}
     const cplx* twHi;  // e^{2 pi i (t<<sh)/N}
     const cplx* twLo;  // e^{2 pi i t/N}, t < 2^sh
+    cplx qs[4];        // e^{i pi k/(2N)}, k < 4
 };
 
 // Far-field block b: rows j in [jlo, jhi) and the mirrored rows
