@@ -173,8 +173,13 @@ int plan_build(int64_t N, int prec, Plan& p) {
     }
 
     // ---- low-degree block: dense matrix up to DENSE_MAX columns; for large N
-    // the block n < N/16 is itself converted by this algorithm (sub-plan)
-    p.nd = (N >= RECURSE_FROM) ? (int)(N / 16) : (int)std::min<int64_t>(N, DENSE_MAX);
+    // the block n < N/8 (N/16 at RECURSE_FROM, where that is the dense limit)
+    // is itself converted by this algorithm (sub-plan).  Measured at
+    // N = 2^20: N/8 is fastest (N/16 +2.5%, N/4 +14%, N/32 +11%: a larger
+    // block costs sub-plan work, a smaller one near-field rows and far terms)
+    p.nd = (N >= 2 * RECURSE_FROM) ? (int)(N / 8)
+           : (N >= RECURSE_FROM)   ? (int)(N / 16)
+                                   : (int)std::min<int64_t>(N, DENSE_MAX);
     p.dense_chunk = 512;  // equals DENSE_CH of the dense kernels
     p.dense_nchunk = (p.nd + p.dense_chunk - 1) / p.dense_chunk;
     if (p.nd > DENSE_MAX) {
