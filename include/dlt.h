@@ -33,6 +33,14 @@
  *     until dlt_release() or process exit.  The first call for a given N on
  *     a device builds its plan and synchronises the device (so it must not
  *     be made inside stream capture); later calls never synchronise.
+ *   - Repeated calls: when leg2cheb, cheb_eval_leggrid, dlt_forward or
+ *     dlt_inverse (and their _ex forms) are called again with the same size
+ *     (a power of two), batch, precision, buffers and stream, the second
+ *     call captures its work into a HIP graph (on a library-owned stream)
+ *     and it and later such calls launch that graph on `stream`: the same
+ *     kernels on the buffers' current contents, the same results.  Calls
+ *     made while the kernel trace is on, and the first call, run directly.
+ *     dlt_release() frees the graphs.
  *   - FP64 arithmetic throughout.  Accuracy against the direct O(N^2)
  *     definitions: max_k |f_k - f_k^exact| <= 5e-14 * sum_n |c_n| (DLT, NDCT);
  *     max_n |c_n - c_n^exact| <= 5e-14 * (n+1/2) sum_k w_k |f_k| (IDLT).

@@ -74,6 +74,14 @@ struct Cache {
     std::map<std::tuple<int, int64_t, int64_t, int, int>, std::unique_ptr<SingleEntry>> single;
     std::map<std::vector<int64_t>, std::unique_ptr<BatchEntry>> graphs;  // descriptor -> graph
     std::map<std::tuple<int, int, int64_t, int>, int64_t> tuned;  // (device, direction, P, prec) -> grid
+    // repeated single calls: (device, operation, N, batch, precision, input,
+    // output, stream) -> graph of the call, and the workspace it was captured with
+    struct CallGraph {
+        hipGraphExec_t exec = nullptr;
+        void* ws = nullptr;
+        int seen = 0;
+    };
+    std::map<std::tuple<int, int, int64_t, int64_t, int, const void*, void*, hipStream_t>, CallGraph> calls;
 };
 
 Cache& cache() {
@@ -213,6 +221,65 @@ int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? DLT_OK : DLT_ERR_HIP; }
+
+int capture_stream(hipStream_t user, hipStream_t* out);
+
+// Runs one call: enqueue(cw) puts the call's work on cw.lanes.s (forking to
+// its side streams).  The first call with a given (operation, size, batch,
+// precision, buffers, stream) runs directly; the second is captured into a
+// HIP graph on the private capture stream (the side streams become branches
+// of the graph), and it and every later call replay that graph on the
+// caller's stream with one launch.  A graph is recaptured when the stream's
+// workspace has moved; traced calls always run directly.
+constexpr size_t CALL_GRAPHS_MAX = 256;
+template <class F>
+int run_call(int op, const Plan& p, int64_t batch, const void* in, void* out, hipStream_t stream, F&& enqueue) {
+    CallWS cw;
+    int rc = setup_call(p, batch, stream, cw);
+    if (rc) return rc;
+    if (trace_on()) return enqueue(cw);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    void* ws = (void*)cw.theta;  // base of the stream's workspace
+    const auto key = std::make_tuple(dev, op, (int64_t)p.N, batch, p.prec, in, out, stream);
+    Cache& c = cache();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        Cache::CallGraph& g = c.calls[key];
+        if (g.exec && g.ws == ws) return hip_status(hipGraphLaunch(g.exec, stream));
+        if (++g.seen < 2) return enqueue(cw);
+    }
+    hipStream_t cs;
+    if ((rc = capture_stream(stream, &cs))) return rc;
+    CallWS cc = cw;
+    if ((rc = get_lanes(cs, &cc.lanes))) return rc;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return DLT_ERR_HIP;
+    rc = enqueue(cc);
+    const hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (rc == DLT_OK && ce != hipSuccess) rc = DLT_ERR_HIP;
+    if (rc == DLT_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) rc = DLT_ERR_HIP;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        if (c.calls.size() > CALL_GRAPHS_MAX) {
+            // many distinct calls: drop the graphs of the others (none is in
+            // use by the host; launched replays keep their own references)
+            for (auto& kv : c.calls)
+                if (kv.second.exec && kv.first != key) (void)hipGraphExecDestroy(kv.second.exec);
+            Cache::CallGraph mine = c.calls[key];
+            c.calls.clear();
+            c.calls[key] = mine;
+        }
+        Cache::CallGraph& g = c.calls[key];
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g.exec = exec;
+        g.ws = ws;
+    }
+    return hip_status(hipGraphLaunch(exec, stream));
+}
 
 // ------------------------------------------------------------ ragged sizes --
 // Sizes that are not powers of two, and batches of uneven sizes, run on the
@@ -661,13 +728,14 @@ int leg2cheb_ex(int64_t N, int64_t batch, const double* c, double* chat, int pre
     if (!is_pow2_n(N)) return ragged_equal(N, batch, 2, c, chat, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
-    CallWS cw;
-    if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
-        int64_t nb = std::min(cw.nb, batch - b0);
-        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat + b0 * N, N, cw.work, cw.lanes)))) return rc;
-    }
-    return DLT_OK;
+    return run_call(2, *p, batch, c, chat, stream, [&](CallWS& cw) -> int {
+        for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+            int64_t nb = std::min(cw.nb, batch - b0);
+            int r = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat + b0 * N, N, cw.work, cw.lanes));
+            if (r) return r;
+        }
+        return DLT_OK;
+    });
 }
 
 int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream) {
@@ -683,14 +751,15 @@ int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f
     if (!is_pow2_n(N)) return ragged_equal(N, batch, 3, chat, f, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
-    CallWS cw;
-    if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, cw.lanes)))) return rc;
-    for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
-        int64_t nb = std::min(cw.nb, batch - b0);
-        if ((rc = hip_status(run_ndct(*p, nb, chat + b0 * N, N, cw.dth, f + b0 * N, cw.work, cw.lanes)))) return rc;
-    }
-    return DLT_OK;
+    return run_call(3, *p, batch, chat, f, stream, [&](CallWS& cw) -> int {
+        int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, cw.lanes));
+        if (r) return r;
+        for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+            int64_t nb = std::min(cw.nb, batch - b0);
+            if ((r = hip_status(run_ndct(*p, nb, chat + b0 * N, N, cw.dth, f + b0 * N, cw.work, cw.lanes)))) return r;
+        }
+        return DLT_OK;
+    });
 }
 
 int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream) {
@@ -706,26 +775,27 @@ int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int pre
     if (!is_pow2_n(N)) return ragged_equal(N, batch, 0, c, f, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
-    CallWS cw;
-    if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    // the nodes are needed only by the Taylor evaluation: they run on the
-    // first side stream beside the conversion of the first slice
-    const Lanes& L = cw.lanes;
-    const hipStream_t sn = L.aux(0);
-    const bool fork = sn != stream;
-    if (fork && (hipEventRecord(L.ev[10], stream) != hipSuccess || hipStreamWaitEvent(sn, L.ev[10], 0) != hipSuccess))
-        return DLT_ERR_HIP;
-    if ((rc = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, L.on(sn))))) return rc;
-    if (fork && hipEventRecord(L.ev[11], sn) != hipSuccess) return DLT_ERR_HIP;
-    for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
-        int64_t nb = std::min(cw.nb, batch - b0);
-        // Chebyshev coefficients of the slice, stride N, in the workspace
-        double* chat = cw.work.chat;
-        if ((rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat, cw.work.schat, cw.work, L)))) return rc;
-        if (fork && b0 == 0 && hipStreamWaitEvent(stream, L.ev[11], 0) != hipSuccess) return DLT_ERR_HIP;
-        if ((rc = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, f + b0 * N, cw.work, L)))) return rc;
-    }
-    return DLT_OK;
+    return run_call(0, *p, batch, c, f, stream, [&](CallWS& cw) -> int {
+        // the nodes are needed only by the Taylor evaluation: they run on the
+        // first side stream beside the conversion of the first slice
+        const Lanes& L = cw.lanes;
+        const hipStream_t s0 = L.s, sn = L.aux(0);
+        const bool fork = sn != s0;
+        if (fork && (hipEventRecord(L.ev[10], s0) != hipSuccess || hipStreamWaitEvent(sn, L.ev[10], 0) != hipSuccess))
+            return DLT_ERR_HIP;
+        int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, L.on(sn)));
+        if (r) return r;
+        if (fork && hipEventRecord(L.ev[11], sn) != hipSuccess) return DLT_ERR_HIP;
+        for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+            int64_t nb = std::min(cw.nb, batch - b0);
+            // Chebyshev coefficients of the slice, stride N, in the workspace
+            double* chat = cw.work.chat;
+            if ((r = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat, cw.work.schat, cw.work, L)))) return r;
+            if (fork && b0 == 0 && hipStreamWaitEvent(s0, L.ev[11], 0) != hipSuccess) return DLT_ERR_HIP;
+            if ((r = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, f + b0 * N, cw.work, L)))) return r;
+        }
+        return DLT_OK;
+    });
 }
 
 int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
@@ -741,14 +811,16 @@ int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int pre
     if (!is_pow2_n(N)) return ragged_equal(N, batch, 1, f, c, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
-    CallWS cw;
-    if ((rc = setup_call(*p, batch, stream, cw))) return rc;
-    if ((rc = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes)))) return rc;
-    for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
-        int64_t nb = std::min(cw.nb, batch - b0);
-        if ((rc = hip_status(run_inverse(*p, nb, f + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, cw.lanes)))) return rc;
-    }
-    return DLT_OK;
+    return run_call(1, *p, batch, f, c, stream, [&](CallWS& cw) -> int {
+        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
+        if (r) return r;
+        for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+            int64_t nb = std::min(cw.nb, batch - b0);
+            if ((r = hip_status(run_inverse(*p, nb, f + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, cw.lanes))))
+                return r;
+        }
+        return DLT_OK;
+    });
 }
 
 int dlt_plan_query(int64_t N, int64_t* out, int max_fields) { return dlt_plan_query_ex(N, DLT_PREC_FP64, out, max_fields); }
@@ -813,6 +885,9 @@ int dlt_release(void) {
     }
     c.lanes.clear();
     c.graphs.clear();  // graph executables, their workspaces and descriptors
+    for (auto& kv : c.calls)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    c.calls.clear();
     c.single.clear();
     c.tuned.clear();
     for (auto& kv : c.capture) (void)hipStreamDestroy(kv.second);

@@ -1,0 +1,64 @@
+"""Repeated single calls are replayed from a captured HIP graph (the second
+call with the same operation, size, batch, precision, buffers and stream
+captures it).  Every replay must give the same bits as the direct call on the
+same input, also when the input changes in place between replays, with other
+direct work and synchronisations in between, and with the trace on (direct
+again)."""
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu, say, to_dev, to_host
+from paper_1505_00354_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    need_gpu()
+    import paper_1505_00354_amd as pk
+
+    pk.lib()
+    return pk
+
+
+OPS = ["dlt_forward", "dlt_inverse", "leg2cheb", "cheb_eval_leggrid"]
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("N,batch,prec", [(1 << 16, 1, "fp64"), (1 << 13, 3, "fp64"), (1 << 17, 1, "fp32bulk")])
+def test_replays_match_direct_calls(pk, op, N, batch, prec):
+    import torch
+
+    say("call graph", op, N, batch, prec)
+    fn = getattr(pk, op)
+    x = to_dev(wl.coeffs_algebraic(N, 21, batch=batch))
+    y = torch.empty_like(x)
+    other_in = to_dev(wl.values_normal(N, 22, batch=batch))
+    other_out = torch.empty_like(other_in)
+    ref = to_host(fn(x.clone(), prec=prec))  # direct: fresh buffers
+    for rep in range(5):
+        # the same buffers every time: direct, captured, then replays
+        fn(x, out=y, prec=prec)
+        got = to_host(y)
+        assert np.array_equal(got, ref), (op, rep)
+        # other direct work and host synchronisation between replays
+        pk.dlt_inverse(other_in, out=other_out)
+        other_out.mul_(0.5)
+        torch.cuda.synchronize()
+    # new input in place: the replay reads the buffer's current contents
+    x2 = wl.values_normal(N, 23, batch=batch)
+    x.copy_(to_dev(x2))
+    fn(x, out=y, prec=prec)
+    got = to_host(y)
+    ref2 = to_host(fn(to_dev(x2), prec=prec))
+    assert np.array_equal(got, ref2)
+    # traced calls run directly and agree too
+    pk.trace_enable(True)
+    try:
+        fn(x, out=y, prec=prec)
+        got = to_host(y)
+    finally:
+        pk.trace_enable(False)
+        pk.trace_collect()
+    assert np.array_equal(got, ref2)
