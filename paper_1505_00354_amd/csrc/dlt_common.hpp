@@ -346,13 +346,26 @@ __device__ __forceinline__ void tile_last(cplxT<R>* v, const cplxT<R>* __restric
 // Stockham stages: radix 8 in registers, radix 8 through LDS, and a last
 // radix-8/4/2 stage in registers; all threads of the block must call it.  On
 // return `buf` is free for reuse (the last LDS reads are behind a barrier).
-template <int L, class R>
-__device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT<R>* __restrict__ tw, const Tile<L>& T) {
+// `hook(pt)` runs after the barrier of LDS exchange pt, pt = 0 ..
+// tile_hook_points<L>() - 1 (a place to issue other work, such as the stores
+// of the previous tile, while the exchanges of this one proceed).
+struct NoHook {
+    __device__ __forceinline__ void operator()(int) const {}
+};
+template <int L>
+constexpr int tile_hook_points() {
+    if constexpr (L == 0) return 1;
+    else return Tile<L>::NMID + 1;
+}
+template <int L, class R, class H = NoHook>
+__device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT<R>* __restrict__ tw, const Tile<L>& T,
+                                         const H& hook = H()) {
     if constexpr (L == 0) {
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s)
             if (T.live(s)) buf[T.slot(s)] = v[s];
         __syncthreads();
+        hook(0);
         lds_fft(buf, T.len(), T.cols(), tw);
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s)
@@ -373,6 +386,7 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
 #pragma unroll
         for (int q = 0; q < 8; ++q) buf[wb ^ TT::sw(q)] = v[q];
         __syncthreads();
+        hook(0);
 #pragma unroll
         for (int st = 0; st < NMID; ++st) {
             const int p = 8 << (3 * st);
@@ -387,6 +401,7 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
 #pragma unroll
             for (int q = 0; q < 8; ++q) buf[db ^ TT::sw(q * p)] = a[q];
             __syncthreads();
+            hook(st + 1);
         }
 #pragma unroll
         for (int s = 0; s < 8; ++s) v[s] = buf[T.rb_ ^ TT::sw(s * ST)];

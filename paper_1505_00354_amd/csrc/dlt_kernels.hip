@@ -571,9 +571,9 @@ struct PassAOut {
         p2 = tw2(g.twHi, g.twLo, (int64_t)na * (L / 4), g.sh);
         p4 = tw2(g.twHi, g.twLo, (int64_t)na * (L / 2), g.sh);
     }
+    // o[s] = v[s] times its twiddle
     template <class R>
-    __device__ __forceinline__ void put(const Geo& g, const cplxT<R>* v, cplxT<R>* __restrict__ Xt,
-                                        const Tile<L>& T) const {
+    __device__ __forceinline__ void twid(const cplxT<R>* v, cplxT<R>* o) const {
         cplx w[8];
         w[0] = w0;
         w[1] = cmul(w0, p1);
@@ -584,7 +584,21 @@ struct PassAOut {
         w[6] = cmul(w[2], p4);
         w[7] = cmul(w[3], p4);
 #pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s) Xt[passA_offset(g, na, T.idx(s), VIRT)] = cto<R>(cmul(cwide(v[s]), w[s]));
+        for (int s = 0; s < FFT_VPT; ++s) o[s] = cto<R>(cmul(cwide(v[s]), w[s]));
+    }
+    // stores the twiddled element s
+    template <class R>
+    __device__ __forceinline__ void store(const Geo& g, const cplxT<R>* o, cplxT<R>* __restrict__ Xt,
+                                          const Tile<L>& T, int s) const {
+        Xt[passA_offset(g, na, T.idx(s), VIRT)] = o[s];
+    }
+    template <class R>
+    __device__ __forceinline__ void put(const Geo& g, const cplxT<R>* v, cplxT<R>* __restrict__ Xt,
+                                        const Tile<L>& T) const {
+        cplxT<R> o[FFT_VPT];
+        twid(v, o);
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) store(g, o, Xt, T, s);
     }
 };
 
@@ -598,11 +612,58 @@ struct PassAOut<0, VIRT> {
             if (T.live(s)) w[s] = tw2(g.twHi, g.twLo, (int64_t)(na0 + T.col(s)) * T.idx(s), g.sh);
     }
     template <class R>
+    __device__ __forceinline__ void twid(const cplxT<R>* v, cplxT<R>* o) const {
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) o[s] = cto<R>(cmul(cwide(v[s]), w[s]));
+    }
+    template <class R>
+    __device__ __forceinline__ void store(const Geo& g, const cplxT<R>* o, cplxT<R>* __restrict__ Xt,
+                                          const Tile<0>& T, int s) const {
+        if (T.live(s)) Xt[passA_offset(g, na0 + T.col(s), T.idx(s), VIRT)] = o[s];
+    }
+    template <class R>
     __device__ __forceinline__ void put(const Geo& g, const cplxT<R>* v, cplxT<R>* __restrict__ Xt,
                                         const Tile<0>& T) const {
+        cplxT<R> o[FFT_VPT];
+        twid(v, o);
 #pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s)
-            if (T.live(s)) Xt[passA_offset(g, na0 + T.col(s), T.idx(s), VIRT)] = cto<R>(cmul(cwide(v[s]), w[s]));
+        for (int s = 0; s < FFT_VPT; ++s) store(g, o, Xt, T, s);
+    }
+};
+
+// Pass-A output of one tile held back and stored during the transform of the
+// block's next tile, a few stores after each of its LDS exchanges: the stores
+// of a term then stream out while the next term is transformed, instead of
+// leaving in one burst between two transforms.
+template <int L, bool VIRT, class R>
+struct HeldPut {
+    const PassAOut<L, VIRT>& out;
+    const Geo& g;
+    const Tile<L>& T;
+    cplxT<R> o[FFT_VPT];
+    cplxT<R>* dst = nullptr;
+    __device__ __forceinline__ HeldPut(const PassAOut<L, VIRT>& out_, const Geo& g_, const Tile<L>& T_)
+        : out(out_), g(g_), T(T_) {}
+    // stores the held tile's share of hook point pt (none before the first hold)
+    __device__ __forceinline__ void operator()(int pt) const {
+        constexpr int NP = tile_hook_points<L>();
+        if (dst) {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s)
+                if (s * NP / FFT_VPT == pt) out.store(g, o, dst, T, s);
+        }
+    }
+    // holds the transform v, bound for the slab Xt
+    __device__ __forceinline__ void hold(const cplxT<R>* v, cplxT<R>* Xt) {
+        out.twid(v, o);
+        dst = Xt;
+    }
+    __device__ __forceinline__ void flush() {
+        if (dst) {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) out.store(g, o, dst, T, s);
+        }
+        dst = nullptr;
     }
 };
 
@@ -702,12 +763,14 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __
             out.put(g, v2, Xb + (int64_t)(t - G) * N, T);
         }
     }
+    HeldPut<LA, false, R> held(out, g, T);
     for (; t >= 0; t -= G) {
         cplxT<R> v[FFT_VPT];
         input(t, v);
-        tile_fft<LA>(v, buf, twA, T);
-        out.put(g, v, Xb + (int64_t)t * N, T);
+        tile_fft<LA>(v, buf, twA, T, held);
+        held.hold(v, Xb + (int64_t)t * N);
     }
+    held.flush();
 }
 
 // ---------------------------------------------------------- far field B --
@@ -1125,6 +1188,7 @@ __global__ FFT_BOUNDS void k_ndct_passA(Geo g, int qa, int qb, int QG, const dou
     const double* cb = chat + b * chat_stride;
     cplxT<R>* Xb = X + b * x_stride;
     const PassAOut<LA, false> out(g, T, na0);
+    HeldPut<LA, false, R> held(out, g, T);
     const double invN = 1.0 / N;
     // W = A x^{2q} + B y^{2q} with A = e (1+x) chat_n / 2, B = -i e x chat_{N-n} / 2;
     // Ap = A x^{2q} and Bp = B y^{2q} are carried from pair to pair
@@ -1160,9 +1224,10 @@ __global__ FFT_BOUNDS void k_ndct_passA(Geo g, int qa, int qb, int QG, const dou
             Ap[s] = cscale(Ap[s], (n == 0) ? 0.0 : x * x);
             Bp[s] = cscale(Bp[s], y * y);
         }
-        tile_fft<LA>(v, buf, twA, T);
-        out.put(g, v, Xb + (int64_t)(q - qa) * N, T);
+        tile_fft<LA>(v, buf, twA, T, held);
+        held.hold(v, Xb + (int64_t)(q - qa) * N);
     }
+    held.flush();
 }
 
 // f_k = sum_l s_l d_k^l/l! F_l[k], s_l = (-1)^floor((l+1)/2), d_k = N dtheta_k,
@@ -1289,6 +1354,7 @@ __global__ FFT_BOUNDS void k_tndct_passA(Geo g, int qa, int qb, int QG, const do
     const double* fb = fv + b * f_stride;
     cplxT<R>* Xb = X + b * x_stride;
     const PassAOut<LA, true> out(g, T, na0);
+    HeldPut<LA, true, R> held(out, g, T);
     double gv[FFT_VPT], dv[FFT_VPT], d2[FFT_VPT];
     const int q0 = qa + ((qb - qa) * grp) / QG, q1 = qa + ((qb - qa) * (grp + 1)) / QG;
 #pragma unroll
@@ -1319,9 +1385,10 @@ __global__ FFT_BOUNDS void k_tndct_passA(Geo g, int qa, int qb, int QG, const do
             v[s] = cto<R>(cplx{gv[s], gv[s] * dv[s]});
             gv[s] *= d2[s];
         }
-        tile_fft<LA>(v, buf, twA, T);
-        out.put(g, v, Xb + (int64_t)(q - qa) * N, T);
+        tile_fft<LA>(v, buf, twA, T, held);
+        held.hold(v, Xb + (int64_t)(q - qa) * N);
     }
+    held.flush();
 }
 
 // y_n = sum_l s_l (n/N)^l / l! Z_l[n]; Z_{2q} = Re(e_n A_n), Z_{2q+1} = Im(e_n B_n),
