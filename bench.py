@@ -228,6 +228,60 @@ def ragged_runs(pk, wl, torch, np, dev, with_oracle=True):
     return res
 
 
+WS_CAP = 6 << 30  # the library's per-stream workspace bound: larger batches run in slices
+
+
+def rooflines(pk, kern, N, B, prec):
+    """Per-kernel rooflines from a kernel trace ({name: (ms, launches)}) of
+    steps at size N, batch B, precision prec: algorithmic bytes (or flops)
+    per launch over the average launch time.  A batch whose workspace
+    exceeds the library's bound runs in slices, so a launch covers B/slices
+    instances on average.  Returns (dominant kernel's roofline, all,
+    dominant kernel name); the dominant kernel has the largest share of the
+    traced time."""
+    infos = {}
+
+    def info(n):
+        if n not in infos:
+            infos[n] = pk.plan_info(n, prec)
+        return infos[n]
+
+    per_inst = max(1, info(N)["ws_bytes"])
+    nb = max(1, min(B, WS_CAP // per_inst))
+    slices = -(-B // nb)
+    inst_per_launch = B / slices
+    tot = sum(v[0] for v in kern.values())
+    ranked = sorted(kern.items(), key=lambda kv: -kv[1][0])
+    per_kernel = {}
+    for key, (ms, cnt) in ranked:
+        name, n = key.split("/")
+        n = int(n)
+        m = kernel_model(name.replace("_f32", ""), n, info(n), f32=name.endswith("_f32"), bulk=(prec == "fp32bulk"))
+        if m is None:
+            continue
+        bound, work = m
+        avg_s = ms / cnt / 1000.0
+        wl = work * inst_per_launch
+        if bound == "hbm":
+            ach, peak, unit = wl / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            ach, peak, unit = wl / avg_s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+        per_kernel[key] = {"bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit,
+                           "frac": round(ach / peak, 4), "work_per_launch": int(wl),
+                           "instances_per_launch": round(inst_per_launch, 3),
+                           "avg_launch_us": round(avg_s * 1e6, 2), "share_of_step": round(ms / tot, 4)}
+    dominant = ranked[0][0] if ranked else None
+    roof = None
+    if dominant in per_kernel:
+        r = per_kernel[dominant]
+        roof = {"kernel": dominant, "bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"],
+                "unit": r["unit"], "frac": r["frac"], "traffic": None,
+                ("bytes_per_launch" if r["bound"] == "hbm" else "flops_per_launch"): r["work_per_launch"],
+                "instances_per_launch": r["instances_per_launch"],
+                "avg_launch_us": r["avg_launch_us"], "share_of_step": r["share_of_step"]}
+    return roof, per_kernel, dominant
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,42 +383,9 @@ def main():
     for k, (ms, cnt) in sorted(kern.items(), key=lambda kv: -kv[1][0]):
         log(f"  {k:26s} {ms / cnt * 1000:10.2f} us/launch  x{cnt:4d}  {100 * ms / tot:5.1f}%")
 
-    # roofline of the dominant kernel (largest share of the step): its
-    # algorithmic bytes or flops per launch over its average launch time
-    infos = {}
-
-    def model(key):
-        name, n = key.split("/")
-        n = int(n)
-        if n not in infos:
-            infos[n] = pk.plan_info(n, prec)
-        return kernel_model(name.replace("_f32", ""), n, infos[n], f32=name.endswith("_f32"),
-                            bulk=(prec == "fp32bulk"))
-
-    ranked = sorted(kern.items(), key=lambda kv: -kv[1][0])
-    per_kernel = {}
-    for key, (ms, cnt) in ranked:
-        m = model(key)
-        if m is None:
-            continue
-        bound, work = m
-        avg_s = ms / cnt / 1000.0
-        if bound == "hbm":
-            ach, peak, unit = work * B / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
-        else:
-            ach, peak, unit = work * B / avg_s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
-        per_kernel[key] = {"bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit,
-                           "frac": round(ach / peak, 4), "work_per_launch": work * B,
-                           "avg_launch_us": round(avg_s * 1e6, 2), "share_of_step": round(ms / tot, 4)}
-    dominant = ranked[0][0] if ranked else None
-    roof = None
-    if dominant in per_kernel:
-        r = per_kernel[dominant]
-        traffic = stored_traffic(dominant) if B == 1 else None
-        roof = {"kernel": dominant, "bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"],
-                "unit": r["unit"], "frac": r["frac"], "traffic": traffic,
-                ("bytes_per_launch" if r["bound"] == "hbm" else "flops_per_launch"): r["work_per_launch"],
-                "avg_launch_us": r["avg_launch_us"], "share_of_step": r["share_of_step"]}
+    roof, per_kernel, dominant = rooflines(pk, kern, N, B, prec)
+    if roof is not None and B == 1:
+        roof["traffic"] = stored_traffic(dominant)
 
     out = {
         "metric": "DLT transforms/s + HBM GB/s at N=2^16..2^20, plain FP64 vs batched/FP32-bulk",
@@ -423,10 +444,22 @@ def main():
                 b2.record()
                 torch.cuda.synchronize()
                 bms = a.elapsed_time(b2) / 3
+                # the same steps with the kernel trace: rooflines of the batched form
+                pk.trace_enable(True)
+                for _ in range(3):
+                    bstep()
+                torch.cuda.synchronize()
+                pk.trace_enable(False)
+                broof, bper, _ = rooflines(pk, pk.trace_collect(), N, BB, m)
+                top = sorted(bper.items(), key=lambda kv: -kv[1]["share_of_step"])[:8]
                 modes[m + "_batch64"] = {"ms_per_step": round(bms, 3), "transforms_per_s": round(2 * BB * 1000.0 / bms, 2),
                                          "step": "forward DLT + inverse DLT of 64 instances (c_n = N(0,1)/(n+1), "
-                                                 "seeds 100..163)"}
-                log(f"{m} batch 64: {bms:.3f} ms per forward+inverse")
+                                                 "seeds 100..163)",
+                                         "roofline": broof,
+                                         "roofline_by_kernel": {k: {f: v[f] for f in ("frac", "avg_launch_us",
+                                                                                      "instances_per_launch")}
+                                                                for k, v in top}}
+                log(f"{m} batch 64: {bms:.3f} ms per forward+inverse; dominant kernel {broof}")
             modes["fp32bulk_batch64"]["speedup_vs_fp64relaxed_equal_accuracy"] = round(
                 modes["fp64relaxed_batch64"]["ms_per_step"] / modes["fp32bulk_batch64"]["ms_per_step"], 3)
             del cb, fb, cb2
