@@ -1943,19 +1943,21 @@ __global__ void k_idlt_final(int N, int nd, int nrg, const int* __restrict__ rg_
 }  // namespace dlt
 
 // ================================================================ host ====
+#include <hip/hip_ext.h>
+
 // Launch a length-templated pass kernel: the compile-time length is used
 // when the tile is full (N >= FFT_CAP), the run-time path otherwise.
 #define LEN_LAUNCH(FULL, LEN, KER, GRID, BLK, SHM, STR, ...)                      \
     do {                                                                          \
         int L_ = (FULL) ? (LEN) : 0;                                              \
         switch (L_) {                                                             \
-            case 64: KER<64><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;         \
-            case 128: KER<128><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;       \
-            case 256: KER<256><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;       \
-            case 512: KER<512><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;       \
-            case 1024: KER<1024><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;     \
-            case 2048: KER<2048><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;     \
-            default: KER<0><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;          \
+            case 64: launch(KER<64>, GRID, BLK, SHM, STR, __VA_ARGS__); break;         \
+            case 128: launch(KER<128>, GRID, BLK, SHM, STR, __VA_ARGS__); break;       \
+            case 256: launch(KER<256>, GRID, BLK, SHM, STR, __VA_ARGS__); break;       \
+            case 512: launch(KER<512>, GRID, BLK, SHM, STR, __VA_ARGS__); break;       \
+            case 1024: launch(KER<1024>, GRID, BLK, SHM, STR, __VA_ARGS__); break;     \
+            case 2048: launch(KER<2048>, GRID, BLK, SHM, STR, __VA_ARGS__); break;     \
+            default: launch(KER<0>, GRID, BLK, SHM, STR, __VA_ARGS__); break;          \
         }                                                                         \
     } while (0)
 // The same for kernels with a precision parameter R (double or float).
@@ -1963,13 +1965,13 @@ __global__ void k_idlt_final(int N, int nd, int nrg, const int* __restrict__ rg_
     do {                                                                          \
         int L_ = (FULL) ? (LEN) : 0;                                              \
         switch (L_) {                                                             \
-            case 64: KER<64, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;      \
-            case 128: KER<128, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;    \
-            case 256: KER<256, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;    \
-            case 512: KER<512, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;    \
-            case 1024: KER<1024, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;  \
-            case 2048: KER<2048, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;  \
-            default: KER<0, R><<<GRID, BLK, SHM, STR>>>(__VA_ARGS__); break;       \
+            case 64: launch(KER<64, R>, GRID, BLK, SHM, STR, __VA_ARGS__); break;      \
+            case 128: launch(KER<128, R>, GRID, BLK, SHM, STR, __VA_ARGS__); break;    \
+            case 256: launch(KER<256, R>, GRID, BLK, SHM, STR, __VA_ARGS__); break;    \
+            case 512: launch(KER<512, R>, GRID, BLK, SHM, STR, __VA_ARGS__); break;    \
+            case 1024: launch(KER<1024, R>, GRID, BLK, SHM, STR, __VA_ARGS__); break;  \
+            case 2048: launch(KER<2048, R>, GRID, BLK, SHM, STR, __VA_ARGS__); break;  \
+            default: launch(KER<0, R>, GRID, BLK, SHM, STR, __VA_ARGS__); break;       \
         }                                                                         \
     } while (0)
 namespace dlt {
@@ -1984,6 +1986,10 @@ static std::mutex mu;
 static bool on = false;
 static std::vector<Rec> recs;
 static std::vector<hipEvent_t> pool;
+// events of the launch being traced (null outside traced launches), and
+// whether a kernel took them
+static thread_local hipEvent_t cur_a = nullptr, cur_b = nullptr;
+static thread_local bool used = false;
 
 static hipEvent_t take() {
     if (!pool.empty()) {
@@ -1999,14 +2005,29 @@ static hipEvent_t take() {
 
 bool trace_on() { return trace::on; }
 
+// Kernel launch.  Inside a traced launch the kernel takes the trace's events
+// itself (hipExtLaunchKernel binds them to the dispatch), so they hold the
+// kernel's own start and end, not the stream's progress before and after it.
+template <class... P, class... A>
+static inline void launch(void (*k)(P...), dim3 g, dim3 b, size_t shm, hipStream_t s, A&&... a) {
+    if (trace::cur_a) {
+        trace::used = true;
+        hipExtLaunchKernelGGL(k, g, b, (std::uint32_t)shm, s, trace::cur_a, trace::cur_b, 0, static_cast<P>(a)...);
+    } else {
+        k<<<g, b, shm, s>>>(static_cast<P>(a)...);
+    }
+}
+
 void trace_set(bool enable) {
     std::lock_guard<std::mutex> lk(trace::mu);
     trace::on = enable;
 }
 
-// launches `fn` bracketed by events when tracing
 // current transform size, appended to trace names ("kernel/N")
 static thread_local int64_t trace_n = 0;
+
+// runs `fn` (one kernel launch); when tracing, the kernel records a start and
+// an end event of its own
 
 template <class F>
 static void traced(const char* name, hipStream_t s, F&& fn) {
@@ -2016,10 +2037,18 @@ static void traced(const char* name, hipStream_t s, F&& fn) {
     }
     std::lock_guard<std::mutex> lk(trace::mu);
     trace::Rec r{std::string(name) + "/" + std::to_string(trace_n), trace::take(), trace::take()};
-    (void)hipEventRecord(r.a, s);
+    (void)s;
+    trace::cur_a = r.a;
+    trace::cur_b = r.b;
+    trace::used = false;
     fn();
-    (void)hipEventRecord(r.b, s);
-    trace::recs.push_back(r);
+    trace::cur_a = trace::cur_b = nullptr;
+    if (trace::used) {
+        trace::recs.push_back(r);
+    } else {  // nothing launched
+        trace::pool.push_back(r.a);
+        trace::pool.push_back(r.b);
+    }
 }
 
 int trace_collect(std::vector<std::pair<std::string, std::pair<double, int64_t>>>& out) {
@@ -2083,7 +2112,7 @@ hipError_t plan_prepare(Plan& p) {
         hipError_t e = hipMalloc(&p.d_amp, (size_t)N * sizeof(cplx));
         if (e == hipSuccess) e = hipMalloc(&p.d_rowf, (size_t)N * sizeof(cplx));
         if (e != hipSuccess) return e;
-        k_far_tables<<<(N + 255) / 256, 256, 0, 0>>>(N, p.far, p.d_amp, p.d_rowf);
+        launch(k_far_tables, (N + 255) / 256, 256, 0, 0, N, p.far, p.d_amp, p.d_rowf);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) return e;
@@ -2098,9 +2127,9 @@ hipError_t plan_prepare(Plan& p) {
     double* st1 = items + (size_t)NP.nitems * 8;
     e = hipMalloc(&p.d_near_st, (size_t)NP.nitems * 2 * NEAR_NSUB * sizeof(double));
     if (e == hipSuccess) {
-        k_near_items<<<dim3(p.tn_wg, 1, 1), 64, 0, 0>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, items);
-        k_tnear_scan<<<dim3(NP.jnear, 1, 1), 64, 0, 0>>>(NP, items, 0, st1, 0);
-        k_near_substates<<<dim3(p.tn_wg, 1, 1), 64, 0, 0>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, st1,
+        launch(k_near_items, dim3(p.tn_wg, 1, 1), 64, 0, 0, N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, items);
+        launch(k_tnear_scan, dim3(NP.jnear, 1, 1), 64, 0, 0, NP, items, 0, st1, 0);
+        launch(k_near_substates, dim3(p.tn_wg, 1, 1), 64, 0, 0, N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, st1,
                                                            p.d_near_st);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -2138,20 +2167,20 @@ hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, doubl
             int parts = P.N / (NODE_PART_THREADS * 64);
             parts = std::max(1, std::min(parts, NODE_PARTS_MAX));
             traced("k_nodes_bpart", sb, [&] {
-                k_nodes_bpart<<<dim3(P.kb, parts), NODE_PART_THREADS, 0, sb>>>(P, p.d_guess, parts, scratch);
+                launch(k_nodes_bpart, dim3(P.kb, parts), NODE_PART_THREADS, 0, sb, P, p.d_guess, parts, scratch);
             });
             traced("k_nodes_bfin", sb, [&] {
-                k_nodes_bfin<<<P.kb, 64, 0, sb>>>(P, p.d_guess, parts, scratch, theta, w, dth);
+                launch(k_nodes_bfin, P.kb, 64, 0, sb, P, p.d_guess, parts, scratch, theta, w, dth);
             });
         } else {
             int T = 64;
             while (T < 1024 && T * 256 < P.N) T *= 2;
             size_t shm = (size_t)7 * T * sizeof(double);
-            traced("k_nodes_boundary", sb, [&] { k_nodes_boundary<<<P.kb, T, shm, sb>>>(P, p.d_guess, theta, w, dth); });
+            traced("k_nodes_boundary", sb, [&] { launch(k_nodes_boundary, P.kb, T, shm, sb, P, p.d_guess, theta, w, dth); });
         }
     }
     if (ni > 0)
-        traced("k_nodes_interior", s, [&] { k_nodes_interior<<<(ni + 255) / 256, 256, 0, s>>>(P, theta, w, dth); });
+        traced("k_nodes_interior", s, [&] { launch(k_nodes_interior, (ni + 255) / 256, 256, 0, s, P, theta, w, dth); });
     if (P.kb > 0) DLT_TRY(dep(sb, s, L.ev[1]));
     return hipGetLastError();
 }
@@ -2182,11 +2211,11 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
     DLT_TRY(dep(s, sl, L.ev[2]));
     if (!p.sub) {
         dim3 gd(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb);
-        traced("k_dense", sl, [&] { k_dense<<<gd, 256, 0, sl>>>(N, nd, p.dense_chunk, p.d_lam, c, cs, w.dense, w.sdense); });
+        traced("k_dense", sl, [&] { launch(k_dense, gd, 256, 0, sl, N, nd, p.dense_chunk, p.d_lam, c, cs, w.dense, w.sdense); });
         double* dst = last ? chat : dense_out;
         int64_t ds = last ? hs : w.sdense;
         traced("k_dense_reduce", sl, [&] {
-            k_dense_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, sl>>>(nd, p.dense_nchunk, p.dense_chunk,
+            launch(k_dense_reduce, dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, sl, nd, p.dense_nchunk, p.dense_chunk,
                                                                                 w.dense, w.sdense, dst, ds);
         });
         if (last) return hipGetLastError();
@@ -2200,12 +2229,12 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
     DLT_TRY(dep(s, sn, L.ev[3]));
     if (NP.nitems > 0)
         traced("k_near_sums", sn, [&] {
-            k_near_sums<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, sn>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp,
+            launch(k_near_sums, dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, sn, N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp,
                                                                       p.d_near_st, c, cs, w.items, w.sitems);
         });
     if (NP.jnear > 0)
         traced("k_near_reduce", sn, [&] {
-            k_near_reduce<<<dim3(NP.jnear, 1, (unsigned)nb), 64, 0, sn>>>(NP, w.items, w.sitems, w.near, w.snear);
+            launch(k_near_reduce, dim3(NP.jnear, 1, (unsigned)nb), 64, 0, sn, NP, w.items, w.sitems, w.near, w.snear);
         });
     // far field
     const FarParams& F = p.far;
@@ -2259,14 +2288,14 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     DLT_TRY(dep(s, sl, L.ev[6]));
     if (!p.sub) {
         traced("k_dense_t", sl, [&] {
-            k_dense_t<<<dim3(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb), 256, 0, sl>>>(nd, p.dense_chunk, p.d_lam,
+            launch(k_dense_t, dim3(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb), 256, 0, sl, nd, p.dense_chunk, p.d_lam,
                                                                                           y, ys, w.dense, w.sdense);
         });
         double* dst = last ? out : dense_out;
         int64_t ds = last ? os : w.sdense;
         int hf = last ? half : 0;
         traced("k_dense_t_reduce", sl, [&] {
-            k_dense_t_reduce<<<dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, sl>>>(nd, p.dense_nchunk, p.dense_chunk,
+            launch(k_dense_t_reduce, dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, sl, nd, p.dense_nchunk, p.dense_chunk,
                                                                                   w.dense, w.sdense, dst, ds, hf);
         });
         if (last) return hipGetLastError();
@@ -2288,7 +2317,7 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     DLT_TRY(dep(s, sn, L.ev[7]));
     if (NP.nitems > 0) {
         traced("k_tnear_accum", sn, [&] {
-            k_tnear_accum<<<dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, sn>>>(N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, u,
+            launch(k_tnear_accum, dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, sn, N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp, u,
                                                                         w.svec, p.d_near_st, w.part, w.spart);
         });
     }
@@ -2314,7 +2343,7 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     DLT_TRY(dep(sn, s, L.ev[8]));
     DLT_TRY(dep(sl, s, L.ev[9]));
     traced("k_idlt_final", s, [&] {
-        k_idlt_final<<<dim3((N + 255) / 256, 1, (unsigned)nb), 256, 0, s>>>(N, nd, (NP.nitems > 0) ? p.tn_nrg : 0,
+        launch(k_idlt_final, dim3((N + 255) / 256, 1, (unsigned)nb), 256, 0, s, N, nd, (NP.nitems > 0) ? p.tn_nrg : 0,
                                                                           p.d_tn_rgnend, dense_out, w.sdense, p.tgB, w.v,
                                                                           w.sv, w.part, w.spart, out, os, half);
     });
@@ -2402,15 +2431,15 @@ hipError_t run_rnodes(const RaggedNodes& rn, int Ng, int* gk, double* dg, double
     trace_n = Ng;
     if (gk) {
         const int64_t n = (int64_t)rn.nb * Ng;
-        traced("k_fill_int", s, [&] { k_fill_int<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(gk, n, -1); });
+        traced("k_fill_int", s, [&] { launch(k_fill_int, (unsigned)((n + 255) / 256), 256, 0, s, gk, n, -1); });
     }
     if (rn.nbnd_total > 0)
         traced("k_rnodes_boundary", s, [&] {
-            k_rnodes_boundary<<<rn.nbnd_total, 256, 0, s>>>(rn.R, rn.boff, rn.nb, Ng, gk, dg, wg, theta, w, dth);
+            launch(k_rnodes_boundary, rn.nbnd_total, 256, 0, s, rn.R, rn.boff, rn.nb, Ng, gk, dg, wg, theta, w, dth);
         });
     if (rn.ni_total > 0)
         traced("k_rnodes_interior", s, [&] {
-            k_rnodes_interior<<<(rn.ni_total + 255) / 256, 256, 0, s>>>(rn.R, rn.ioff, rn.nb, Ng, gk, dg, wg, theta, w,
+            launch(k_rnodes_interior, (rn.ni_total + 255) / 256, 256, 0, s, rn.R, rn.ioff, rn.nb, Ng, gk, dg, wg, theta, w,
                                                                        dth);
         });
     return hipGetLastError();
@@ -2419,14 +2448,14 @@ hipError_t run_rnodes(const RaggedNodes& rn, int Ng, int* gk, double* dg, double
 hipError_t run_rgather(const double* in, const RNode* R, const int64_t* offs, int nb, int Ng, int64_t stride,
                        double* out, hipStream_t s) {
     trace_n = Ng;
-    traced("k_rgather", s, [&] { k_rgather<<<dim3((Ng + 255) / 256, nb), 256, 0, s>>>(in, R, offs, Ng, stride, out); });
+    traced("k_rgather", s, [&] { launch(k_rgather, dim3((Ng + 255) / 256, nb), 256, 0, s, in, R, offs, Ng, stride, out); });
     return hipGetLastError();
 }
 
 hipError_t run_rscatter(const double* in, int64_t stride, const RNode* R, const int64_t* offs, int nb, int Ng,
                         double* out, hipStream_t s) {
     trace_n = Ng;
-    traced("k_rscatter", s, [&] { k_rscatter<<<dim3((Ng + 255) / 256, nb), 256, 0, s>>>(in, stride, R, offs, out); });
+    traced("k_rscatter", s, [&] { launch(k_rscatter, dim3((Ng + 255) / 256, nb), 256, 0, s, in, stride, R, offs, out); });
     return hipGetLastError();
 }
 
