@@ -364,10 +364,10 @@ def main():
     ms_step = e0.elapsed_time(e1) / args.steps
     value = 3 * B * 1000.0 / ms_step
     log(f"ms/step {ms_step:.4f} (wall {1000 * wall / args.steps:.4f})")
-    # the same K steps again with the library's kernel trace on: HIP events
-    # around every launch, on the stream it is launched on.  The events hold
-    # each launch until the previous one has finished, so this region runs
-    # slower; it gives the per-kernel launch times only.
+    # the same K steps again with the library's kernel trace on: every
+    # kernel runs alone on the caller's stream and takes a start and an end
+    # event bound to its own dispatch (its duration, as rocprofv3 reports
+    # it).  This region runs slower; it gives the per-kernel times only.
     pk.trace_enable(True)
     torch.cuda.synchronize()
     e0.record()
