@@ -2207,26 +2207,23 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
     const bool last = (N <= nd);  // the dense block is the whole conversion
     const hipStream_t sl = last ? s : L.aux(1), sn = L.aux(2);
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
-    // low block
-    DLT_TRY(dep(s, sl, L.ev[2]));
-    if (!p.sub) {
+    auto dense_block = [&](hipStream_t st, double* dst, int64_t ds) {
         dim3 gd(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb);
-        traced("k_dense", sl, [&] { launch(k_dense, gd, 256, 0, sl, N, nd, p.dense_chunk, p.d_lam, c, cs, w.dense, w.sdense); });
-        double* dst = last ? chat : dense_out;
-        int64_t ds = last ? hs : w.sdense;
-        traced("k_dense_reduce", sl, [&] {
-            launch(k_dense_reduce, dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, sl, nd, p.dense_nchunk, p.dense_chunk,
-                                                                                w.dense, w.sdense, dst, ds);
+        traced("k_dense", st, [&] { launch(k_dense, gd, 256, 0, st, N, nd, p.dense_chunk, p.d_lam, c, cs, w.dense, w.sdense); });
+        traced("k_dense_reduce", st, [&] {
+            launch(k_dense_reduce, dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, st, nd, p.dense_nchunk, p.dense_chunk,
+                   w.dense, w.sdense, dst, ds);
         });
-        if (last) return hipGetLastError();
-    } else {
-        Work sw = sub_work(*p.sub, nb, w);
-        DLT_TRY(run_leg2cheb(*p.sub, nb, c, cs, dense_out, w.sdense, sw, L.on(sl)));
-        trace_n = p.N;
+    };
+    if (last) {
+        dense_block(s, chat, hs);
+        return hipGetLastError();
     }
-    // near field
+    // near field (reads only c).  It is enqueued first and its end recorded
+    // at once, so that a nested low-degree run can queue its own near field
+    // behind it on the same stream without delaying this run's DCT.
     const NearParams& NP = p.near;
-    DLT_TRY(dep(s, sn, L.ev[3]));
+    if (!L.near_inline) DLT_TRY(dep(s, sn, L.ev[3]));
     if (NP.nitems > 0)
         traced("k_near_sums", sn, [&] {
             launch(k_near_sums, dim3(p.tn_wg, 1, (unsigned)nb), 64, 0, sn, N, NP, p.d_tn_wgseg, p.d_tn_segoff, p.d_rcp,
@@ -2236,6 +2233,16 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
         traced("k_near_reduce", sn, [&] {
             launch(k_near_reduce, dim3(NP.jnear, 1, (unsigned)nb), 64, 0, sn, NP, w.items, w.sitems, w.near, w.snear);
         });
+    if (sn != s) DLT_TRY(hipEventRecord(L.ev[4], sn));
+    // low block: the dense block, or the whole method at size nd
+    DLT_TRY(dep(s, sl, L.ev[2]));
+    if (!p.sub) {
+        dense_block(sl, dense_out, w.sdense);
+    } else {
+        Work sw = sub_work(*p.sub, nb, w);
+        DLT_TRY(run_leg2cheb(*p.sub, nb, c, cs, dense_out, w.sdense, sw, L.nested_leg2cheb(sl)));
+        trace_n = p.N;
+    }
     // far field
     const FarParams& F = p.far;
     const dim3 gA(g.N1 / g.colsA, p.tgA, (unsigned)nb), gB(g.N2 / g.rowsB, p.tgB, (unsigned)nb);
@@ -2257,7 +2264,7 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
         });
     }
     // values on the grid -> coefficients
-    DLT_TRY(dep(sn, s, L.ev[4]));
+    if (sn != s) DLT_TRY(hipStreamWaitEvent(s, L.ev[4], 0));
     traced("k_dct2_passA", s, [&] {
         LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_dct2_passA, (dim3(g.N1 / g.colsA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, p.tgB, w.v, w.sv, w.near, w.snear,
                                                                                 NP.jnear, w.X, w.sX);

@@ -33,12 +33,27 @@ struct Lanes {
     hipStream_t s = nullptr;
     hipStream_t side[LANE_SIDES] = {};
     hipEvent_t ev[LANE_EVENTS] = {};
-    bool forks() const { return side[0] != nullptr; }
+    // the near field goes on side[2] directly, after work already ordered
+    // there (no fork from s)
+    bool near_inline = false;
     hipStream_t aux(int i) const { return side[i] ? side[i] : s; }
     // the same call on one stream only (used for nested runs)
     Lanes on(hipStream_t st) const {
         Lanes l;
         l.s = st;
+        return l;
+    }
+    // the low-degree conversion nested in a Legendre-to-Chebyshev run: its
+    // own work on st, its near field queued on this run's near-field stream
+    // behind this run's near field (events 14, 15 are reserved for it)
+    Lanes nested_leg2cheb(hipStream_t st) const {
+        if (!side[2] || !ev[14]) return on(st);
+        Lanes l;
+        l.s = st;
+        l.side[2] = side[2];
+        l.near_inline = true;
+        l.ev[4] = ev[14];
+        l.ev[14] = ev[15];
         return l;
     }
 };
