@@ -151,9 +151,11 @@ int dlt_plan_query(int64_t N, int64_t* out, int max_fields);
 /* The same for the plan of precision mode `prec` (DLT_PREC_*). */
 int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields);
 
-/* Kernel trace.  While enabled, every kernel the library launches is
- * bracketed by two hipEvents recorded on the launch stream (no host
- * synchronisation at launch time).  dlt_trace_collect waits for the recorded
+/* Kernel trace.  While enabled, every kernel the library launches in a
+ * transform is given a start and an end hipEvent bound to its own dispatch
+ * (hipExtLaunchKernel; no host synchronisation at launch time), so the time
+ * between them is the kernel's execution, without the dispatch around it
+ * (plan set-up kernels are not traced).  dlt_trace_collect waits for the
  * events, writes at most max_kernels entries -- kernel name (NUL-terminated,
  * truncated to name_len-1 bytes, at names + i*name_len), total milliseconds
  * and launch count, summed over launches -- clears the record and returns the
