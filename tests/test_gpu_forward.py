@@ -147,3 +147,42 @@ def test_traced_calls_match_untraced(pk, N):
     assert np.array_equal(got_c, ref_c)
     names = " ".join(kern)
     assert "far_pass" in names and "tfar_pass" in names
+
+
+@pytest.mark.parametrize("N", [1 << 12, 1 << 20])
+def test_trace_times_are_kernel_durations(pk, N):
+    # traced kernels run one after another on the caller's stream, so their
+    # own durations (events bound to each launch) are positive and add up to
+    # no more than the elapsed time of the traced region; the Chebyshev
+    # evaluation and the conversion give the same bits traced and untraced
+    import torch
+
+    say("trace times", N)
+    c = to_dev(wl.coeffs_algebraic(N, 11)[0])
+    f = to_dev(wl.values_normal(N, 12)[0])
+    ref_g, ref_h = to_host(pk.cheb_eval_leggrid(c)), to_host(pk.leg2cheb(c))
+    torch.cuda.synchronize()
+    pk.trace_collect()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pk.trace_enable(True)
+    try:
+        e0.record()
+        g = pk.cheb_eval_leggrid(c)
+        h = pk.leg2cheb(c)
+        pk.dlt_forward(c)
+        pk.dlt_inverse(f)
+        e1.record()
+        torch.cuda.synchronize()
+    finally:
+        pk.trace_enable(False)
+    kern = pk.trace_collect()
+    elapsed_ms = e0.elapsed_time(e1)
+    assert np.array_equal(to_host(g), ref_g)
+    assert np.array_equal(to_host(h), ref_h)
+    assert kern, "no kernel traced"
+    total = 0.0
+    for name, (ms, cnt) in kern.items():
+        assert cnt >= 1 and ms > 0, name
+        total += ms
+    say("  traced kernels", len(kern), "sum ms", total, "region ms", elapsed_ms)
+    assert total <= elapsed_ms * 1.001 + 1e-3
