@@ -49,6 +49,7 @@ def _load():
                                                       _i64p, _f64p]
             getattr(lib, f"orc_leg2cheb_{p}").argtypes = [ctypes.c_int64, _f64p, _f64p]
             getattr(lib, f"orc_leg2cheb_t_{p}").argtypes = [ctypes.c_int64, _f64p, _f64p]
+            getattr(lib, f"orc_leg2cheb_rows_{p}").argtypes = [ctypes.c_int64, _f64p, ctypes.c_int64, _i64p, _f64p]
             getattr(lib, f"orc_legendre_{p}").argtypes = [ctypes.c_int64, ctypes.c_double, _f64p]
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         lib.orc_set_threads.restype = ctypes.c_int
@@ -131,6 +132,16 @@ def leg2cheb(c, prec="d"):
     c, cp = _d(c)
     out = np.empty(len(c))
     _check(getattr(_load(), f"orc_leg2cheb_{prec}")(len(c), cp, out.ctypes.data_as(_f64p)))
+    return out
+
+
+def leg2cheb_rows(c, idx, prec="d"):
+    """(M c)_k for the rows k in idx (Sec. 3, eq. (9)), O(N) per row."""
+    c, cp = _d(c)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(len(idx))
+    _check(getattr(_load(), f"orc_leg2cheb_rows_{prec}")(len(c), cp, len(idx), idx.ctypes.data_as(_i64p),
+                                                        out.ctypes.data_as(_f64p)))
     return out
 
 

@@ -26,6 +26,7 @@
  *             lack one Gamma-ratio factor; the reading used here is
  *             M_kn = (eps_k/pi) Lam((n-k)/2) Lam((n+k)/2), n>=k, n+k even,
  *             Lam(z) = Gamma(z+1/2)/Gamma(z+1), eps_0 = 1, eps_k = 2.
+ *             (leg2cheb_rows: the same for a given set of rows.)
  *
  * Recurrences are evaluated for theta' = min(theta, pi - theta) <= pi/2 and
  * mirrored with P_n(-x) = (-1)^n P_n(x), T_n(-x) = (-1)^n T_n(x).  For
@@ -253,6 +254,29 @@ int FN(orc_leg2cheb)(int64_t N, const double *c, double *chat) {
             acc += (REAL)(L[(n - k) / 2] * L[(n + k) / 2]) * (REAL)c[n];
         REAL e = (k == 0) ? 1 : 2;
         chat[k] = (double)(e / PI_R * acc);
+    }
+    free(L);
+    return 0;
+}
+
+/* chat_k = (M c)_k for the cnt rows k = idx[i] only, the same definition as
+ * orc_leg2cheb (Sec. 3, eq. (9)) restricted to those rows: O(N) per row, so
+ * that large N can be checked on a sample of outputs. */
+int FN(orc_leg2cheb_rows)(int64_t N, const double *c, int64_t cnt, const int64_t *idx, double *chat) {
+    if (N < 1 || cnt < 0 || (cnt > 0 && !idx)) return -1;
+    for (int64_t i = 0; i < cnt; ++i)
+        if (idx[i] < 0 || idx[i] >= N) return -1;
+    long double *L = (long double *)malloc((size_t)N * sizeof(long double));
+    if (!L) return -4;
+    FN(lam_table)(N, L);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < cnt; ++i) {
+        const int64_t k = idx[i];
+        REAL acc = 0;
+        for (int64_t n = k; n < N; n += 2)
+            acc += (REAL)(L[(n - k) / 2] * L[(n + k) / 2]) * (REAL)c[n];
+        REAL e = (k == 0) ? 1 : 2;
+        chat[i] = (double)(e / PI_R * acc);
     }
     free(L);
     return 0;

@@ -56,6 +56,23 @@ def test_leg2cheb(pk, orc, N):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("N", [1 << 18, 1 << 20])
+def test_leg2cheb_sampled(pk, orc, N):
+    # sampled rows of M c against the oracle's row-sampled definition; the
+    # rows around nd are where the exact low block meets the near and far
+    # fields
+    nd = pk.plan_info(N)["nd"]
+    edge = {0, 1, 2, nd - 2, nd - 1, nd, nd + 1, N // 2, N - 2, N - 1}
+    idx = np.array(sorted(set(int(i) for i in wl.sample_indices(N, 512, 13)) | edge), dtype=np.int64)
+    say("leg2cheb sampled", N, "nd", nd, "rows", len(idx))
+    for fam, c in (("A", wl.coeffs_algebraic(N, 2)[0]), ("B", wl.coeffs_analytic(N, 3)[0])):
+        chat = to_host(pk.leg2cheb(to_dev(c)))
+        ref = orc.leg2cheb_rows(c, idx, prec="l")
+        err = np.max(np.abs(chat[idx] - ref)) / np.sum(np.abs(c))
+        say("  family", fam, "err", err)
+        assert err <= TOL
+
+
 @pytest.mark.parametrize("N", [1, 2, 4, 16, 256, 1024, 4096, 16384])
 def test_cheb_eval_leggrid(pk, orc, N):
     say("ndct", N)

@@ -345,6 +345,30 @@ def test_leg2cheb_vs_numpy_conversion(orc, N):
         assert np.all(col[n + 1:] == 0)  # upper triangular
 
 
+@pytest.mark.parametrize("prec", ["d", "l"])
+def test_leg2cheb_rows_match_dense(orc, prec):
+    # the row-sampled conversion is the dense one restricted to the rows
+    from paper_1505_00354_amd import workloads as wl
+
+    N = 777
+    c = wl.coeffs_algebraic(N, 23)[0]
+    idx = np.array([0, 1, 2, 100, 387, 388, 775, 776, 5, 5])
+    assert np.array_equal(orc.leg2cheb_rows(c, idx, prec=prec), orc.leg2cheb(c, prec=prec)[idx])
+    assert orc.leg2cheb_rows(c, np.array([], dtype=np.int64)).shape == (0,)
+
+
+def test_leg2cheb_rows_column_sums_large_n(orc):
+    # P_n(+-1) = (+-1)^n: column n of M sums to 1 and alternates to (-1)^n,
+    # here at N = 2^16 through the row-sampled routine (all rows k <= n)
+    N, n = 1 << 16, 4097
+    e = np.zeros(N)
+    e[n] = 1
+    col = orc.leg2cheb_rows(e, np.arange(n + 1), prec="l")
+    assert abs(col.sum() - 1) <= 1e-13
+    assert abs(np.sum(col * (-1.0) ** np.arange(n + 1)) - (-1) ** n) <= 1e-13
+    assert np.all(col[(np.arange(n + 1) + n) % 2 == 1] == 0)
+
+
 def test_leg2cheb_composes_to_dlt(orc):
     # eq. (9): sum c_n P_n(x_k) = sum chat_n T_n(x_k), chat = M c
     from paper_1505_00354_amd import workloads as wl
