@@ -1976,7 +1976,7 @@ __global__ void k_idlt_final(int N, int nd, int nrg, const int* __restrict__ rg_
     } while (0)
 namespace dlt {
 
-// ---- kernel trace: start/stop events around every launch while enabled
+// ---- kernel trace: a start and an end event bound to every traced launch
 namespace trace {
 struct Rec {
     std::string name;
@@ -2037,7 +2037,7 @@ static void traced(const char* name, hipStream_t s, F&& fn) {
     }
     std::lock_guard<std::mutex> lk(trace::mu);
     trace::Rec r{std::string(name) + "/" + std::to_string(trace_n), trace::take(), trace::take()};
-    (void)s;
+    (void)s;  // the launch itself names its stream
     trace::cur_a = r.a;
     trace::cur_b = r.b;
     trace::used = false;

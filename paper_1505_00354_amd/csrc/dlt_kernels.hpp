@@ -102,7 +102,7 @@ hipError_t run_rgather(const double* in, const RNode* R, const int64_t* offs, in
 hipError_t run_rscatter(const double* in, int64_t stride, const RNode* R, const int64_t* offs, int nb, int Ng,
                         double* out, hipStream_t s);
 
-// kernel trace (events around every launch while enabled)
+// kernel trace (start and end events bound to every traced launch)
 bool trace_on();
 void trace_set(bool enable);
 int trace_collect(std::vector<std::pair<std::string, std::pair<double, int64_t>>>& out);
