@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace dlt {
 
 // Complex value in precision R (double, or float for the FP32-bulk passes).
@@ -408,6 +410,50 @@ __device__ __forceinline__ void tile_fft(cplxT<R>* v, cplxT<R>* buf, const cplxT
         __syncthreads();
         tile_last<L>(v, tw, i0);
     }
+}
+
+// tile_fft for a compile-time length that also returns, in vp, the outputs
+// of another thread's position (column colp, first index i0p: vp[s] is the
+// output at i0p + s L/8 of that column), by reading that thread's inputs to
+// the last stage as well and repeating its last stage in registers.
+template <int L, class R>
+__device__ __forceinline__ void tile_fft_with(cplxT<R>* v, cplxT<R>* vp, cplxT<R>* buf,
+                                              const cplxT<R>* __restrict__ tw, const Tile<L>& T, int colp, int i0p) {
+    static_assert(L > 0, "compile-time tile lengths only");
+    using TT = Tile<L>;
+    constexpr int ST = TT::STRIDE;
+    constexpr int NMID = TT::NMID;
+    const int cb = T.col_ * L;
+    const int i0 = T.i0_;
+    dft8(v);
+    const int wb = TT::sw(cb + 8 * i0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) buf[wb ^ TT::sw(q)] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < NMID; ++st) {
+        const int p = 8 << (3 * st);
+        const int k = i0 & (p - 1);
+        cplxT<R> a[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = buf[T.rb_ ^ TT::sw(j * ST)];
+        twiddle8_tab(a, tw + L / 2 + tw_mid_off<L>(st) + k);
+        dft8(a);
+        __syncthreads();
+        const int db = TT::sw(cb + (i0 - k) * 8 + k);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) buf[db ^ TT::sw(q * p)] = a[q];
+        __syncthreads();
+    }
+    const int rbp = TT::sw(colp * L + i0p);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        v[s] = buf[T.rb_ ^ TT::sw(s * ST)];
+        vp[s] = buf[rbp ^ TT::sw(s * ST)];
+    }
+    __syncthreads();
+    tile_last<L>(v, tw, i0);
+    tile_last<L>(vp, tw, i0p);
 }
 
 // tile_fft of two independent tiles (v1 in buf1, v2 in buf2, the same

@@ -1450,28 +1450,58 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
             part[s] = Tile<LB>::sw(ip * N1 + jp);
         }
     }
-    // transformed tile in buffer `bb` (precision P): pair each value with its
-    // partner and take one Horner step
+    // one Horner step from each value u and its partner's value V
+    auto horner = [&](int q, int s, const cplx u, const cplx V) {
+        const double sc = (q & 1) ? -1.0 : 1.0;
+        const double r1 = 1.0 / (2 * q + 1), r2 = 1.0 / (2 * q + 2);
+        const cplx A = {0.5 * (u.re + V.re), 0.5 * (u.im - V.im)};
+        const cplx Bm = {0.5 * (u.im + V.im), -0.5 * (u.re - V.re)};  // (U - conj V)/(2i)
+        const double Zc = en[s].re * A.re - en[s].im * A.im;
+        const double Zs = en[s].re * Bm.im + en[s].im * Bm.re;
+        const double inner = fma(xs[s] * r2, acc[s], -sc * Zs);
+        acc[s] = fma(xs[s] * r1, inner, sc * Zc);
+    };
+    // run-time length: the transformed tile in buffer `bb` (precision P)
+    // goes through LDS once more to pair each value with its partner
     auto combine = [&](int q, auto* bb, const auto* U) {
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s)
             if (T.live(s)) bb[T.slot(s)] = U[s];
         __syncthreads();
-        const double sc = (q & 1) ? -1.0 : 1.0;
-        const double r1 = 1.0 / (2 * q + 1), r2 = 1.0 / (2 * q + 2);
 #pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s) {
-            if (T.live(s)) {
-                const cplx u = cwide(U[s]), V = cwide(bb[part[s]]);
-                const cplx A = {0.5 * (u.re + V.re), 0.5 * (u.im - V.im)};
-                const cplx Bm = {0.5 * (u.im + V.im), -0.5 * (u.re - V.re)};  // (U - conj V)/(2i)
-                const double Zc = en[s].re * A.re - en[s].im * A.im;
-                const double Zs = en[s].re * Bm.im + en[s].im * Bm.re;
-                const double inner = fma(xs[s] * r2, acc[s], -sc * Zs);
-                acc[s] = fma(xs[s] * r1, inner, sc * Zc);
-            }
-        }
+        for (int s = 0; s < FFT_VPT; ++s)
+            if (T.live(s)) horner(q, s, cwide(U[s]), cwide(bb[part[s]]));
         __syncthreads();
+    };
+    // compile-time length: the partner of output (col, i0 + s L/8) is output
+    // (colp, i0p + sp L/8) with sp = 7 - s, or (8 - s) mod 8 for row 0 at
+    // i0 = 0; the transform computes the partner thread's outputs as well
+    int colp = 0, i0p = 0;
+    bool z = false;
+    if constexpr (LB > 0) {
+        constexpr int ST = Tile<LB>::STRIDE;
+        const int i = T.col_, i0 = T.i0_;
+        const int r = actual_row(vb0 + i, N2);
+        if (r == 0) {
+            colp = i;
+            i0p = (ST - i0) & (ST - 1);
+            z = (i0 == 0);
+        } else {
+            colp = (2 * r == N2) ? i : (i ^ 1);
+            i0p = ST - 1 - i0;
+        }
+    }
+    auto transform_combine = [&](int q, auto* U, auto* bb, const auto* twb) {
+        if constexpr (LB > 0) {
+            using V_t = std::remove_reference_t<decltype(U[0])>;
+            V_t VP[FFT_VPT];
+            tile_fft_with<LB>(U, VP, bb, twb, T, colp, i0p);
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) horner(q, s, cwide(U[s]), cwide(z ? VP[(8 - s) & 7] : VP[7 - s]));
+        } else {
+            tile_fft<LB>(U, bb, twb, T);
+            combine(q, bb, U);
+        }
     };
     if constexpr (sizeof(R) == sizeof(double)) {
         // all pairs FP64 and contiguous (X1 = X0 + N): one prefetch buffer
@@ -1482,8 +1512,7 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
             if (q > 0) passB_load<LB, double>(g, vb0, X0b + (int64_t)(q - 1) * N, nx, T);
-            tile_fft<LB>(U, bufd, twd, T);
-            combine(q, bufd, U);
+            transform_combine(q, U, bufd, twd);
         }
     } else {
         cplxT<R> nx[FFT_VPT] = {};
@@ -1496,11 +1525,9 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
             for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
             if (q > 1) passB_load<LB, R>(g, vb0, X1b + (int64_t)(q - 2) * N, nx, T);
             else passB_load<LB, double>(g, vb0, X0b, n0, T);
-            tile_fft<LB>(U, bufr, twr, T);
-            combine(q, bufr, U);
+            transform_combine(q, U, bufr, twr);
         }
-        tile_fft<LB>(n0, bufd, twd, T);
-        combine(0, bufd, n0);
+        transform_combine(0, n0, bufd, twd);
     }
     double* yb = y + b * y_stride;
 #pragma unroll
