@@ -228,9 +228,6 @@ def ragged_runs(pk, wl, torch, np, dev, with_oracle=True):
     return res
 
 
-WS_CAP = 6 << 30  # the library's per-stream workspace bound: larger batches run in slices
-
-
 def rooflines(pk, kern, N, B, prec):
     """Per-kernel rooflines from a kernel trace ({name: (ms, launches)}) of
     steps at size N, batch B, precision prec: algorithmic bytes (or flops)
@@ -247,7 +244,7 @@ def rooflines(pk, kern, N, B, prec):
         return infos[n]
 
     per_inst = max(1, info(N)["ws_bytes"])
-    nb = max(1, min(B, WS_CAP // per_inst))
+    nb = max(1, min(B, info(N)["ws_cap"] // per_inst))
     slices = -(-B // nb)
     inst_per_launch = B / slices
     tot = sum(v[0] for v in kern.values())

@@ -199,7 +199,7 @@ def release():
 
 PLAN_FIELDS = ("L", "nd", "far_terms", "far_blocks", "far_mmax", "near_items", "near_rows", "N1", "N2",
                "colsA", "rowsB", "tgB", "tnear_wg", "tnear_rg", "near_steps", "boundary_nodes", "ws_bytes",
-               "near_work", "tgA")
+               "near_work", "tgA", "ws_cap")
 
 
 def plan_info(N, prec="fp64"):

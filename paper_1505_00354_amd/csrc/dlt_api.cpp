@@ -840,7 +840,7 @@ int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields) {
     }
     const int64_t v[] = {p->L, p->nd, p->far.nterm, p->far.nblk, p->far.Mmax, p->near.nitems, p->near.jnear,
                          p->geo.N1, p->geo.N2, p->geo.colsA, p->geo.rowsB, p->tgB, p->tn_wg, p->tn_nrg, steps,
-                         p->nodes.kb, (int64_t)p->ws_per_inst, work, p->tgA};
+                         p->nodes.kb, (int64_t)p->ws_per_inst, work, p->tgA, (int64_t)WS_CAP};
     int n = (int)(sizeof(v) / sizeof(v[0]));
     for (int i = 0; i < n && i < max_fields; ++i) out[i] = v[i];
     return n;

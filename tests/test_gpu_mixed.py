@@ -44,6 +44,11 @@ def test_plan_parameters(pk):
     assert p64["L"] == 16 and p32["L"] == 10 and prl["L"] == 10
     # each mode picks its own cheapest term count for the 5e-6 budget
     assert p32["far_terms"] < p64["far_terms"] and prl["far_terms"] < p64["far_terms"]
+    # FP32 intermediates take less workspace; a batch of 64 at N = 2^20 runs
+    # in slices of the per-stream workspace bound
+    assert p32["ws_bytes"] < p64["ws_bytes"]
+    for p in (p64, p32, prl):
+        assert 1 <= p["ws_cap"] // p["ws_bytes"] < 64
 
 
 @pytest.mark.parametrize("mode", MODES)
