@@ -34,7 +34,7 @@
  *     a device builds its plan and synchronises the device (so it must not
  *     be made inside stream capture); later calls never synchronise.
  *   - Repeated calls: when leg2cheb, cheb_eval_leggrid, dlt_forward or
- *     dlt_inverse (and their _ex forms) are called again with the same size
+ *     dlt_inverse (and their _ex and _tol forms) are called again with the same size
  *     (a power of two), batch, precision, buffers and stream, the second
  *     call captures its work into a HIP graph (on a library-owned stream)
  *     and it and later such calls launch that graph on `stream`: the same
@@ -114,6 +114,22 @@ int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f
 int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int prec, hipStream_t stream);
 int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int prec, hipStream_t stream);
 
+/* The same four operations for a working tolerance eps (Sec. 3: every
+ * parameter of the method follows from the accuracy goal; Sec. 2, Cor. 1 and
+ * Table 1 for the Taylor terms).  FP64 arithmetic; the Taylor length and the
+ * far-field terms, blocks and rows (hence the near field) are chosen for eps
+ * instead of the fixed 5e-14 / 5e-6 budgets of the precision modes, so the
+ * accuracy statements at the top of this file hold with eps in place of
+ * 5e-14.  eps is rounded down to the steps 1, 2, 5 x 10^e from 5e-14 to 1e-1
+ * (one cached plan per step and N).  N must be a power of two
+ * (DLT_ERR_UNSUPPORTED otherwise); eps outside [5e-14, 1e-1] or NaN gives
+ * DLT_ERR_INVALID_ARG; arguments, layout, ownership and the other errors as
+ * for the plain entry points. */
+int leg2cheb_tol(int64_t N, int64_t batch, const double* c, double* chat, double eps, hipStream_t stream);
+int cheb_eval_leggrid_tol(int64_t N, int64_t batch, const double* chat, double* f, double eps, hipStream_t stream);
+int dlt_forward_tol(int64_t N, int64_t batch, const double* c, double* f, double eps, hipStream_t stream);
+int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double eps, hipStream_t stream);
+
 /* Ragged batch: `count` independent transforms of uneven sizes in one call
  * (many transforms of different N, forward and inverse mixed).
  *   Ns[i]       size of instance i (1 <= Ns[i] <= DLT_MAX_N), host array
@@ -152,6 +168,8 @@ const char* dlt_status_string(int status);
 int dlt_plan_query(int64_t N, int64_t* out, int max_fields);
 /* The same for the plan of precision mode `prec` (DLT_PREC_*). */
 int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields);
+/* The same for the plan of working tolerance eps (see the _tol entry points). */
+int dlt_plan_query_tol(int64_t N, double eps, int64_t* out, int max_fields);
 
 /* Kernel trace.  While enabled, every kernel the library launches in a
  * transform is given a start and an end hipEvent bound to its own dispatch

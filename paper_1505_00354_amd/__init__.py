@@ -53,8 +53,13 @@ def lib():
         for name in ("leg2cheb_ex", "cheb_eval_leggrid_ex", "dlt_forward_ex", "dlt_inverse_ex"):
             getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_int, vp]
             getattr(L, name).restype = ctypes.c_int
+        for name in ("leg2cheb_tol", "cheb_eval_leggrid_tol", "dlt_forward_tol", "dlt_inverse_tol"):
+            getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_double, vp]
+            getattr(L, name).restype = ctypes.c_int
         L.dlt_plan_query_ex.argtypes = [i64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         L.dlt_plan_query_ex.restype = ctypes.c_int
+        L.dlt_plan_query_tol.argtypes = [i64, ctypes.c_double, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        L.dlt_plan_query_tol.restype = ctypes.c_int
         L.dlt_batch_ex.argtypes = [i64, vp, vp, vp, vp, vp, ctypes.c_int, vp]
         L.dlt_batch_ex.restype = ctypes.c_int
         L.dlt_status_string.argtypes = [ctypes.c_int]
@@ -117,39 +122,45 @@ def _prec(prec):
     return PRECISIONS[prec]
 
 
-def _unary(name, x, out, prec="fp64"):
+def _unary(name, x, out, prec="fp64", tol=None):
     import torch
 
     N, batch, out = _vec_args(x, out)
     args = (N, batch, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()))
     with torch.cuda.device(x.device):
-        if prec == "fp64":
+        if tol is not None:
+            if prec != "fp64":
+                raise ValueError("a working tolerance runs in FP64 (prec must be 'fp64')")
+            _check(getattr(lib(), name + "_tol")(*args, float(tol), _stream(x.device)), name + "_tol")
+        elif prec == "fp64":
             _check(getattr(lib(), name)(*args, _stream(x.device)), name)
         else:
             _check(getattr(lib(), name + "_ex")(*args, _prec(prec), _stream(x.device)), name + "_ex")
     return out
 
 
-def leg2cheb(c, out=None, prec="fp64"):
+def leg2cheb(c, out=None, prec="fp64", tol=None):
     """Chebyshev coefficients of sum_n c_n P_n (chat = M c)."""
-    return _unary("leg2cheb", c, out, prec)
+    return _unary("leg2cheb", c, out, prec, tol)
 
 
-def cheb_eval_leggrid(chat, out=None, prec="fp64"):
+def cheb_eval_leggrid(chat, out=None, prec="fp64", tol=None):
     """sum_n chat_n T_n at the N Legendre nodes."""
-    return _unary("cheb_eval_leggrid", chat, out, prec)
+    return _unary("cheb_eval_leggrid", chat, out, prec, tol)
 
 
-def dlt_forward(c, out=None, prec="fp64"):
+def dlt_forward(c, out=None, prec="fp64", tol=None):
     """Discrete Legendre transform f_k = sum_n c_n P_n(x_k).  prec: "fp64",
     "fp32bulk" (FP32 bulk transforms, 5e-6 budget) or "fp64relaxed" (FP64
-    with the 5e-6 parameters)."""
-    return _unary("dlt_forward", c, out, prec)
+    with the 5e-6 parameters).  tol: a working tolerance instead (FP64,
+    parameters chosen for eps = tol, 5e-14 <= tol <= 0.1; the other entry
+    points take it too)."""
+    return _unary("dlt_forward", c, out, prec, tol)
 
 
-def dlt_inverse(f, out=None, prec="fp64"):
+def dlt_inverse(f, out=None, prec="fp64", tol=None):
     """Inverse transform c_n = (n+1/2) sum_k w_k f_k P_n(x_k)."""
-    return _unary("dlt_inverse", f, out, prec)
+    return _unary("dlt_inverse", f, out, prec, tol)
 
 
 def dlt_batch(x, sizes, offsets=None, inverse=None, out=None, prec="fp64"):
@@ -202,12 +213,16 @@ PLAN_FIELDS = ("L", "nd", "far_terms", "far_blocks", "far_mmax", "near_items", "
                "near_work", "tgA", "ws_cap")
 
 
-def plan_info(N, prec="fp64"):
-    """The library's plan parameters for size N (and precision), as a dict."""
+def plan_info(N, prec="fp64", tol=None):
+    """The library's plan parameters for size N (and precision, or working
+    tolerance), as a dict."""
     buf = (ctypes.c_int64 * 32)()
-    n = lib().dlt_plan_query_ex(N, _prec(prec), buf, 32)
+    if tol is not None:
+        n = lib().dlt_plan_query_tol(N, float(tol), buf, 32)
+    else:
+        n = lib().dlt_plan_query_ex(N, _prec(prec), buf, 32)
     if n < 0:
-        _check(n, "dlt_plan_query_ex")
+        _check(n, "dlt_plan_query")
     return {k: int(buf[i]) for i, k in enumerate(PLAN_FIELDS[:n])}
 
 

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -61,7 +62,9 @@ struct SingleEntry {
 
 struct Cache {
     std::mutex mu;
-    std::map<std::tuple<int, int64_t, int>, std::unique_ptr<Plan>> plans;  // (device, N, precision)
+    // (device, N, precision), or (device, N, TOL_KEY + tolerance step) for
+    // the plans of a working tolerance
+    std::map<std::tuple<int, int64_t, int>, std::unique_ptr<Plan>> plans;
     struct WS {
         void* ptr = nullptr;
         size_t bytes = 0;
@@ -74,14 +77,14 @@ struct Cache {
     std::map<std::tuple<int, int64_t, int64_t, int, int>, std::unique_ptr<SingleEntry>> single;
     std::map<std::vector<int64_t>, std::unique_ptr<BatchEntry>> graphs;  // descriptor -> graph
     std::map<std::tuple<int, int, int64_t, int>, int64_t> tuned;  // (device, direction, P, prec) -> grid
-    // repeated single calls: (device, operation, N, batch, precision, input,
+    // repeated single calls: (device, operation, N, batch, plan, input,
     // output, stream) -> graph of the call, and the workspace it was captured with
     struct CallGraph {
         hipGraphExec_t exec = nullptr;
         void* ws = nullptr;
         int seen = 0;
     };
-    std::map<std::tuple<int, int, int64_t, int64_t, int, const void*, void*, hipStream_t>, CallGraph> calls;
+    std::map<std::tuple<int, int, int64_t, int64_t, const void*, const void*, void*, hipStream_t>, CallGraph> calls;
 };
 
 Cache& cache() {
@@ -126,6 +129,59 @@ int get_plan(int64_t N, int prec, Plan** out) {
                         : prec == DLT_PREC_FP64_RELAXED ? PREC_FP64_RELAXED
                                                         : PREC_FP64,
                         *p);
+    if (rc == DLT_OK && plan_prepare(*p) != hipSuccess) rc = DLT_ERR_HIP;
+    if (rc != DLT_OK) {
+        plan_free(*p);
+        return rc;
+    }
+    *out = p.get();
+    c.plans[key] = std::move(p);
+    return DLT_OK;
+}
+
+// Working tolerances: the steps 1, 2, 5 x 10^e from TOL_MIN to TOL_MAX; a
+// requested eps is served by the largest step not above it (its accuracy is
+// then at least the requested one).
+constexpr double TOL_MIN = 5e-14, TOL_MAX = 1e-1;
+constexpr int TOL_KEY = 1000;
+int tol_step(double eps, double* val, int* index) {
+    if (!(eps >= TOL_MIN && eps <= TOL_MAX)) return DLT_ERR_INVALID_ARG;  // NaN too
+    int idx = -1;
+    double best = 0;
+    int k = 0;
+    for (int e = -14; e <= -1; ++e) {
+        for (double m : {1.0, 2.0, 5.0}) {
+            const double v = m * std::pow(10.0, e);
+            if (v < TOL_MIN * (1 - 1e-9) || v > TOL_MAX * (1 + 1e-9)) continue;
+            if (v <= eps * (1 + 1e-12)) {
+                best = v;
+                idx = k;
+            }
+            ++k;
+        }
+    }
+    if (idx < 0) return DLT_ERR_INVALID_ARG;
+    *val = best;
+    *index = idx;
+    return DLT_OK;
+}
+
+int get_plan_tol(int64_t N, double eps, Plan** out) {
+    double tv;
+    int ti, rc;
+    if ((rc = tol_step(eps, &tv, &ti))) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto key = std::make_tuple(dev, N, TOL_KEY + ti);
+    auto it = c.plans.find(key);
+    if (it != c.plans.end()) {
+        *out = it->second.get();
+        return DLT_OK;
+    }
+    std::unique_ptr<Plan> p(new Plan());
+    rc = plan_build(N, PREC_FP64, *p, tv);
     if (rc == DLT_OK && plan_prepare(*p) != hipSuccess) rc = DLT_ERR_HIP;
     if (rc != DLT_OK) {
         plan_free(*p);
@@ -241,7 +297,7 @@ int run_call(int op, const Plan& p, int64_t batch, const void* in, void* out, hi
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
     void* ws = (void*)cw.theta;  // base of the stream's workspace
-    const auto key = std::make_tuple(dev, op, (int64_t)p.N, batch, p.prec, in, out, stream);
+    const auto key = std::make_tuple(dev, op, (int64_t)p.N, batch, (const void*)&p, in, out, stream);
     Cache& c = cache();
     {
         std::lock_guard<std::mutex> lk(c.mu);
@@ -719,15 +775,9 @@ int leg2cheb(int64_t N, int64_t batch, const double* c, double* chat, hipStream_
     return leg2cheb_ex(N, batch, c, chat, DLT_PREC_FP64, stream);
 }
 
-int leg2cheb_ex(int64_t N, int64_t batch, const double* c, double* chat, int prec, hipStream_t stream) {
-    int rc = check_any_size(N, batch);
-    if (rc) return rc;
-    if ((rc = check_prec(prec))) return rc;
-    if (batch == 0) return DLT_OK;
-    if (!c || !chat || overlap(c, chat, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
-    if (!is_pow2_n(N)) return ragged_equal(N, batch, 2, c, chat, prec, stream);
-    Plan* p;
-    if ((rc = get_plan(N, prec, &p))) return rc;
+// leg2cheb for nb instances on plan P (any precision mode or tolerance)
+static int leg2cheb_on(Plan& P, int64_t N, int64_t batch, const double* c, double* chat, hipStream_t stream) {
+    Plan* p = &P;
     return run_call(2, *p, batch, c, chat, stream, [&](CallWS& cw) -> int {
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
@@ -738,19 +788,38 @@ int leg2cheb_ex(int64_t N, int64_t batch, const double* c, double* chat, int pre
     });
 }
 
-int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream) {
-    return cheb_eval_leggrid_ex(N, batch, chat, f, DLT_PREC_FP64, stream);
-}
-
-int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f, int prec, hipStream_t stream) {
+int leg2cheb_ex(int64_t N, int64_t batch, const double* c, double* chat, int prec, hipStream_t stream) {
     int rc = check_any_size(N, batch);
     if (rc) return rc;
     if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
-    if (!chat || !f || overlap(chat, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
-    if (!is_pow2_n(N)) return ragged_equal(N, batch, 3, chat, f, prec, stream);
+    if (!c || !chat || overlap(c, chat, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    if (!is_pow2_n(N)) return ragged_equal(N, batch, 2, c, chat, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
+    return leg2cheb_on(*p, N, batch, c, chat, stream);
+}
+
+int leg2cheb_tol(int64_t N, int64_t batch, const double* c, double* chat, double eps, hipStream_t stream) {
+    int rc = check_size(N, batch);  // power-of-two sizes
+    if (rc) return rc;
+    double tv;
+    int ti;
+    if ((rc = tol_step(eps, &tv, &ti))) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!c || !chat || overlap(c, chat, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan_tol(N, eps, &p))) return rc;
+    return leg2cheb_on(*p, N, batch, c, chat, stream);
+}
+
+int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream) {
+    return cheb_eval_leggrid_ex(N, batch, chat, f, DLT_PREC_FP64, stream);
+}
+
+// cheb_eval_leggrid for nb instances on plan P (any precision mode or tolerance)
+static int cheb_eval_leggrid_on(Plan& P, int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream) {
+    Plan* p = &P;
     return run_call(3, *p, batch, chat, f, stream, [&](CallWS& cw) -> int {
         int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, cw.lanes));
         if (r) return r;
@@ -762,19 +831,38 @@ int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f
     });
 }
 
-int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream) {
-    return dlt_forward_ex(N, batch, c, f, DLT_PREC_FP64, stream);
-}
-
-int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int prec, hipStream_t stream) {
+int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f, int prec, hipStream_t stream) {
     int rc = check_any_size(N, batch);
     if (rc) return rc;
     if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
-    if (!c || !f || overlap(c, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
-    if (!is_pow2_n(N)) return ragged_equal(N, batch, 0, c, f, prec, stream);
+    if (!chat || !f || overlap(chat, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    if (!is_pow2_n(N)) return ragged_equal(N, batch, 3, chat, f, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
+    return cheb_eval_leggrid_on(*p, N, batch, chat, f, stream);
+}
+
+int cheb_eval_leggrid_tol(int64_t N, int64_t batch, const double* chat, double* f, double eps, hipStream_t stream) {
+    int rc = check_size(N, batch);  // power-of-two sizes
+    if (rc) return rc;
+    double tv;
+    int ti;
+    if ((rc = tol_step(eps, &tv, &ti))) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!chat || !f || overlap(chat, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan_tol(N, eps, &p))) return rc;
+    return cheb_eval_leggrid_on(*p, N, batch, chat, f, stream);
+}
+
+int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream) {
+    return dlt_forward_ex(N, batch, c, f, DLT_PREC_FP64, stream);
+}
+
+// dlt_forward for nb instances on plan P (any precision mode or tolerance)
+static int dlt_forward_on(Plan& P, int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream) {
+    Plan* p = &P;
     return run_call(0, *p, batch, c, f, stream, [&](CallWS& cw) -> int {
         // the nodes are needed only by the Taylor evaluation: they run on the
         // first side stream beside the conversion of the first slice
@@ -798,19 +886,38 @@ int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int pre
     });
 }
 
-int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
-    return dlt_inverse_ex(N, batch, f, c, DLT_PREC_FP64, stream);
-}
-
-int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int prec, hipStream_t stream) {
+int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int prec, hipStream_t stream) {
     int rc = check_any_size(N, batch);
     if (rc) return rc;
     if ((rc = check_prec(prec))) return rc;
     if (batch == 0) return DLT_OK;
-    if (!f || !c || overlap(f, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
-    if (!is_pow2_n(N)) return ragged_equal(N, batch, 1, f, c, prec, stream);
+    if (!c || !f || overlap(c, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    if (!is_pow2_n(N)) return ragged_equal(N, batch, 0, c, f, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
+    return dlt_forward_on(*p, N, batch, c, f, stream);
+}
+
+int dlt_forward_tol(int64_t N, int64_t batch, const double* c, double* f, double eps, hipStream_t stream) {
+    int rc = check_size(N, batch);  // power-of-two sizes
+    if (rc) return rc;
+    double tv;
+    int ti;
+    if ((rc = tol_step(eps, &tv, &ti))) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!c || !f || overlap(c, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan_tol(N, eps, &p))) return rc;
+    return dlt_forward_on(*p, N, batch, c, f, stream);
+}
+
+int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
+    return dlt_inverse_ex(N, batch, f, c, DLT_PREC_FP64, stream);
+}
+
+// dlt_inverse for nb instances on plan P (any precision mode or tolerance)
+static int dlt_inverse_on(Plan& P, int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
+    Plan* p = &P;
     return run_call(1, *p, batch, f, c, stream, [&](CallWS& cw) -> int {
         int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
         if (r) return r;
@@ -823,15 +930,34 @@ int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int pre
     });
 }
 
-int dlt_plan_query(int64_t N, int64_t* out, int max_fields) { return dlt_plan_query_ex(N, DLT_PREC_FP64, out, max_fields); }
-
-int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields) {
-    int rc = check_size(N, 1);
+int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int prec, hipStream_t stream) {
+    int rc = check_any_size(N, batch);
     if (rc) return rc;
     if ((rc = check_prec(prec))) return rc;
-    if (!out || max_fields < 0) return DLT_ERR_INVALID_ARG;
+    if (batch == 0) return DLT_OK;
+    if (!f || !c || overlap(f, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    if (!is_pow2_n(N)) return ragged_equal(N, batch, 1, f, c, prec, stream);
     Plan* p;
     if ((rc = get_plan(N, prec, &p))) return rc;
+    return dlt_inverse_on(*p, N, batch, f, c, stream);
+}
+
+int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double eps, hipStream_t stream) {
+    int rc = check_size(N, batch);  // power-of-two sizes
+    if (rc) return rc;
+    double tv;
+    int ti;
+    if ((rc = tol_step(eps, &tv, &ti))) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!f || !c || overlap(f, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan_tol(N, eps, &p))) return rc;
+    return dlt_inverse_on(*p, N, batch, f, c, stream);
+}
+
+int dlt_plan_query(int64_t N, int64_t* out, int max_fields) { return dlt_plan_query_ex(N, DLT_PREC_FP64, out, max_fields); }
+
+static int plan_fields(const Plan* p, int64_t* out, int max_fields) {
     int64_t steps = 0, work = 0;
     for (int s = 0; s < p->near.nseg; ++s) {
         const int64_t rows = p->near.seg[s].jhi - p->near.seg[s].jlo;
@@ -844,6 +970,28 @@ int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields) {
     int n = (int)(sizeof(v) / sizeof(v[0]));
     for (int i = 0; i < n && i < max_fields; ++i) out[i] = v[i];
     return n;
+}
+
+int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields) {
+    int rc = check_size(N, 1);
+    if (rc) return rc;
+    if ((rc = check_prec(prec))) return rc;
+    if (!out || max_fields < 0) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan(N, prec, &p))) return rc;
+    return plan_fields(p, out, max_fields);
+}
+
+int dlt_plan_query_tol(int64_t N, double eps, int64_t* out, int max_fields) {
+    int rc = check_size(N, 1);
+    if (rc) return rc;
+    double tv;
+    int ti;
+    if ((rc = tol_step(eps, &tv, &ti))) return rc;
+    if (!out || max_fields < 0) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan_tol(N, eps, &p))) return rc;
+    return plan_fields(p, out, max_fields);
 }
 
 int dlt_trace_enable(int on) {

@@ -124,10 +124,12 @@ void rnode_build(int64_t N, RNode& r) {
     }
 }
 
-int plan_build(int64_t N, int prec, Plan& p) {
+int plan_build(int64_t N, int prec, Plan& p, double tol) {
     memset(&p.geo, 0, sizeof(p.geo));
     p.N = N;
     p.prec = prec;
+    if (tol > 0 && prec != PREC_FP64) return DLT_ERR_INVALID_ARG;
+    p.tol = tol;
     const bool bulk = (prec != PREC_FP64);  // parameters for the 5e-6 budget
     const bool f32 = (prec == PREC_FP32_BULK);
     // ---- FFT geometry
@@ -161,8 +163,9 @@ int plan_build(int64_t N, int prec, Plan& p) {
 
     // ---- Taylor truncation (Corollary 2 with max N|dtheta| <= 0.83845)
     {
-        // 10% of the budget: 5e-14 (FP64) or 5e-6 (FP32-bulk)
-        const double tolT = bulk ? 5e-7 : 5e-15;
+        // 10% of the budget: 5e-14 (FP64), 5e-6 (FP32-bulk, relaxed FP64) or
+        // the working tolerance
+        const double tolT = (tol > 0) ? tol / 10 : bulk ? 5e-7 : 5e-15;
         int L = 1;
         double f = 0.83845;
         while (f > tolT) {
@@ -184,7 +187,7 @@ int plan_build(int64_t N, int prec, Plan& p) {
     p.dense_nchunk = (p.nd + p.dense_chunk - 1) / p.dense_chunk;
     if (p.nd > DENSE_MAX) {
         p.sub = new Plan();
-        if ((rc = plan_build(p.nd, prec, *p.sub))) return rc;
+        if ((rc = plan_build(p.nd, prec, *p.sub, tol))) return rc;
         p.dense_nchunk = 0;
     } else {
         std::vector<double> lam(p.nd);
@@ -201,7 +204,10 @@ int plan_build(int64_t N, int prec, Plan& p) {
     Nr.nd = p.nd;
     if (N > p.nd) {
         // truncation of the asymptotic series per row, relative to ||c||_1
-        const LD eps = bulk ? 5e-7L : 1e-15L;
+        // (a working tolerance: 1/50 of it below 1e-11, where rounding takes
+        // a share of the budget as in the FP64 mode, else 1/10 as in the
+        // 5e-6 modes)
+        const LD eps = (tol > 0) ? (LD)tol / (tol < 1e-11 ? 50 : 10) : bulk ? 5e-7L : 1e-15L;
         // cost model (forward + inverse, calibrated on MI355X at N = 2^20):
         // one far term (both passes) ~ 24 us per 2^20 points in FP64, 3/4 of
         // that with FP32 storage; the near field runs 64 rows per wave, so it
@@ -216,7 +222,8 @@ int plan_build(int64_t N, int prec, Plan& p) {
         int M1 = 12;
         {
             double best = 1e300;
-            for (int m = bulk ? 3 : 8; m <= (bulk ? 12 : 16); ++m) {
+            const int mlo = (tol > 0) ? 2 : bulk ? 3 : 8, mhi = (tol > 0) ? 16 : bulk ? 12 : 16;
+            for (int m = mlo; m <= mhi; ++m) {
                 int j = first_row(N, far_smin(m, p.nd, eps));
                 double cost = m * far_term_s + near_cost(j, N - p.nd);
                 if (cost < best) {

@@ -106,6 +106,9 @@ constexpr int PREC_FP64_RELAXED = 2;
 struct Plan {
     int64_t N = 0;
     int prec = PREC_FP64;
+    // working tolerance of a tolerance plan (FP64 arithmetic, parameters for
+    // ||error|| <= tol ||c||_1); 0 for the fixed budgets of the precision modes
+    double tol = 0;
     int L = 16;        // Taylor terms (even)
     int nd = 0;        // columns n < nd handled by the dense block
     int dense_chunk = 1024, dense_nchunk = 0;
@@ -148,7 +151,9 @@ struct Plan {
 
 // Builds the plan for size N (power of two, 1 <= N <= MAX_N) and precision
 // `prec`; returns 0 or a DLT status code.  Allocates the device tables.
-int plan_build(int64_t N, int prec, Plan& p);
+// With tol > 0 (PREC_FP64 only) the Taylor and far-field truncations are
+// set for the working tolerance tol instead of the mode's fixed budget.
+int plan_build(int64_t N, int prec, Plan& p, double tol = 0);
 void plan_free(Plan& p);
 
 }  // namespace dlt

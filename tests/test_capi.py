@@ -96,3 +96,20 @@ def test_batch_rejects_bad_descriptors(L):
     assert f(3, i64p(Ns), i64p(offs), i64p(inv), x, ctypes.c_void_p(0x1000 + 8 * 50), 0, None) == -1
     a = ctypes.c_void_p(0x1000)
     assert L.leg_nodes_weights(16, 1, a, a, None, None) == -1        # overlapping outputs
+
+
+@pytest.mark.parametrize("fn", ["leg2cheb_tol", "cheb_eval_leggrid_tol", "dlt_forward_tol", "dlt_inverse_tol"])
+def test_tol_rejects_before_device_work(L, fn):
+    f = getattr(L, fn)
+    f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
+    p, q = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000)
+    for eps in (0.0, -1e-6, 1e-15, 4.9e-14, 0.2, float("nan"), float("inf")):
+        assert f(16, 1, p, q, eps, None) == -1, eps
+    assert f(24, 1, p, q, 1e-6, None) == -2          # power-of-two sizes only
+    assert f(0, 1, p, q, 1e-6, None) == -1
+    assert f(16, -1, p, q, 1e-6, None) == -1
+    assert f(16, 0, p, q, 1e-6, None) == 0           # empty batch is a no-op
+    assert f(16, 1, None, q, 1e-6, None) == -1
+    assert f(16, 1, p, ctypes.c_void_p(0x1000 + 8), 1e-6, None) == -1   # overlap
+    L.dlt_plan_query_tol.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int]
+    assert L.dlt_plan_query_tol(16, 1e-20, None, 4) == -1
