@@ -26,7 +26,8 @@ Prints one JSON line; diagnostics go to stderr.  Options:
                 inverse, with errors per octave against the oracle)
   --no-modes    skip the short runs of the other modes (reported under
                 "modes": step time, speedup at equal stated accuracy,
-                FP32-bulk at batch 64, error against the oracle)
+                FP32-bulk at batch 64, the step at working tolerances
+                1e-12 ... 1e-3, errors against the oracle)
   --copy-probe BYTES  only run one plain copy kernel (read BYTES, write
                 BYTES) and exit: the reference for calibrating the HBM byte
                 counters FETCH_SIZE / WRITE_SIZE
@@ -331,6 +332,23 @@ def main():
         pk.dlt_inverse(fin, out=c2, prec=mode)
         pk.cheb_eval_leggrid(chat, out=g, prec=mode)
 
+    def step_tol(eps, c=c, fin=fin, chat=chat, f=f, c2=c2, g=g):
+        pk.dlt_forward(c, out=f, tol=eps)
+        pk.dlt_inverse(fin, out=c2, tol=eps)
+        pk.cheb_eval_leggrid(chat, out=g, tol=eps)
+
+    def timed_tol(eps, steps):
+        for _ in range(2):
+            step_tol(eps)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            step_tol(eps)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
     def timed(mode, steps, **kw):
         for _ in range(2):
             step(mode, **kw)
@@ -460,6 +478,17 @@ def main():
             modes["fp32bulk_batch64"]["speedup_vs_fp64relaxed_equal_accuracy"] = round(
                 modes["fp64relaxed_batch64"]["ms_per_step"] / modes["fp32bulk_batch64"]["ms_per_step"], 3)
             del cb, fb, cb2
+        # working tolerances (the *_tol entry points, FP64): the same step
+        # with the parameters chosen for eps
+        tols = {}
+        for eps in (1e-12, 1e-9, 1e-6, 1e-3):
+            ms = timed_tol(eps, args.steps)
+            pi = pk.plan_info(N, tol=eps)
+            tols[f"{eps:g}"] = {"ms_per_step": round(ms, 5), "transforms_per_s": round(3 * B * 1000.0 / ms, 2),
+                                "L": pi["L"], "far_terms": pi["far_terms"], "near_rows": pi["near_rows"],
+                                "speedup_vs_fp64": round(ms_step / ms, 3) if prec == "fp64" else None}
+            log(f"tolerance {eps:g}: {ms:.4f} ms/step")
+        modes["tolerance"] = tols
         out["modes"] = modes
 
     if not args.no_ragged and B == 1:
@@ -490,6 +519,11 @@ def main():
                 fg = pk.dlt_forward(c1, prec=m).cpu().numpy()[0]
                 modes[m]["forward_error_vs_oracle"] = float(np.max(np.abs(fg[idx] - fo)) / np.sum(np.abs(cc)))
             log("errors", {m: modes[m]["forward_error_vs_oracle"] for m in ("fp64", "fp32bulk", "fp64relaxed")})
+            for key in modes.get("tolerance", {}):
+                fg = pk.dlt_forward(c1, tol=float(key)).cpu().numpy()[0]
+                modes["tolerance"][key]["forward_error_vs_oracle"] = float(
+                    np.max(np.abs(fg[idx] - fo)) / np.sum(np.abs(cc)))
+            log("tolerance errors", {k: v.get("forward_error_vs_oracle") for k, v in modes.get("tolerance", {}).items()})
     print(json.dumps(out), flush=True)
 
 
