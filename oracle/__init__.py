@@ -50,6 +50,7 @@ def _load():
             getattr(lib, f"orc_leg2cheb_{p}").argtypes = [ctypes.c_int64, _f64p, _f64p]
             getattr(lib, f"orc_leg2cheb_t_{p}").argtypes = [ctypes.c_int64, _f64p, _f64p]
             getattr(lib, f"orc_leg2cheb_rows_{p}").argtypes = [ctypes.c_int64, _f64p, ctypes.c_int64, _i64p, _f64p]
+            getattr(lib, f"orc_cheb2leg_{p}").argtypes = [ctypes.c_int64, _f64p, _f64p]
             getattr(lib, f"orc_legendre_{p}").argtypes = [ctypes.c_int64, ctypes.c_double, _f64p]
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         lib.orc_set_threads.restype = ctypes.c_int
@@ -142,6 +143,14 @@ def leg2cheb_rows(c, idx, prec="d"):
     out = np.empty(len(idx))
     _check(getattr(_load(), f"orc_leg2cheb_rows_{prec}")(len(c), cp, len(idx), idx.ctypes.data_as(_i64p),
                                                         out.ctypes.data_as(_f64p)))
+    return out
+
+
+def cheb2leg(chat, prec="d"):
+    """Legendre coefficients c = M^{-1} chat (back substitution, Sec. 3)."""
+    chat, hp = _d(chat)
+    out = np.empty(len(chat))
+    _check(getattr(_load(), f"orc_cheb2leg_{prec}")(len(chat), hp, out.ctypes.data_as(_f64p)))
     return out
 
 

@@ -26,7 +26,8 @@
  *             lack one Gamma-ratio factor; the reading used here is
  *             M_kn = (eps_k/pi) Lam((n-k)/2) Lam((n+k)/2), n>=k, n+k even,
  *             Lam(z) = Gamma(z+1/2)/Gamma(z+1), eps_0 = 1, eps_k = 2.
- *             (leg2cheb_rows: the same for a given set of rows.)
+ *             (leg2cheb_rows: the same for a given set of rows;
+ *             cheb2leg: c = M^{-1} chat by back substitution.)
  *
  * Recurrences are evaluated for theta' = min(theta, pi - theta) <= pi/2 and
  * mirrored with P_n(-x) = (-1)^n P_n(x), T_n(-x) = (-1)^n T_n(x).  For
@@ -279,6 +280,32 @@ int FN(orc_leg2cheb_rows)(int64_t N, const double *c, int64_t cnt, const int64_t
         chat[i] = (double)(e / PI_R * acc);
     }
     free(L);
+    return 0;
+}
+
+/* c = M^{-1} chat (Chebyshev to Legendre coefficients): the solution of
+ * M c = chat by back substitution, M upper triangular with nonzero diagonal
+ * M_kk = (eps_k/pi) Lam(0) Lam(k) (Sec. 3, eq. (9)).  O(N^2). */
+int FN(orc_cheb2leg)(int64_t N, const double *chat, double *c) {
+    if (N < 1) return -1;
+    long double *L = (long double *)malloc((size_t)N * sizeof(long double));
+    REAL *x = (REAL *)malloc((size_t)N * sizeof(REAL));
+    if (!L || !x) {
+        free(L);
+        free(x);
+        return -4;
+    }
+    FN(lam_table)(N, L);
+    for (int64_t k = N - 1; k >= 0; --k) {
+        REAL acc = 0;
+        for (int64_t n = k + 2; n < N; n += 2) acc += (REAL)(L[(n - k) / 2] * L[(n + k) / 2]) * x[n];
+        REAL e = (k == 0) ? 1 : 2;
+        REAL diag = e / PI_R * (REAL)(L[0] * L[k]);
+        x[k] = ((REAL)chat[k] - e / PI_R * acc) / diag;
+    }
+    for (int64_t k = 0; k < N; ++k) c[k] = (double)x[k];
+    free(L);
+    free(x);
     return 0;
 }
 

@@ -369,6 +369,31 @@ def test_leg2cheb_rows_column_sums_large_n(orc):
     assert np.all(col[(np.arange(n + 1) + n) % 2 == 1] == 0)
 
 
+@pytest.mark.parametrize("N", [1, 2, 9, 12])
+def test_cheb2leg_vs_numpy(orc, N):
+    # Chebyshev to Legendre through the monomial basis (numpy); that route
+    # loses accuracy quickly with N (5e-11 at N = 24), so small N only
+    from numpy.polynomial import chebyshev as C
+    from numpy.polynomial import legendre as L
+    from paper_1505_00354_amd import workloads as wl
+
+    chat = wl.coeffs_algebraic(N, 25)[0]
+    ref = L.poly2leg(C.cheb2poly(chat))
+    assert np.max(np.abs(orc.cheb2leg(chat) - ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("N", [300, 2048])
+def test_cheb2leg_inverts_leg2cheb(orc, N):
+    from paper_1505_00354_amd import workloads as wl
+
+    c = wl.coeffs_algebraic(N, 26)[0]
+    back = orc.cheb2leg(orc.leg2cheb(c, prec="l"), prec="l")
+    assert np.max(np.abs(back - c)) <= 1e-14 * np.sum(np.abs(c))
+    chat = wl.coeffs_algebraic(N, 27)[0]
+    again = orc.leg2cheb(orc.cheb2leg(chat, prec="l"), prec="l")
+    assert np.max(np.abs(again - chat)) <= 1e-14 * np.sum(np.abs(chat))
+
+
 def test_leg2cheb_composes_to_dlt(orc):
     # eq. (9): sum c_n P_n(x_k) = sum chat_n T_n(x_k), chat = M c
     from paper_1505_00354_amd import workloads as wl
