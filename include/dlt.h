@@ -87,6 +87,17 @@ int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_
 /* Inverse discrete Legendre transform, eq. (2) (Sec. 4). */
 int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream);
 
+/* Chebyshev-to-Legendre coefficients c = M^{-1} chat (the inverse of
+ * leg2cheb, Sec. 3): the Chebyshev expansion is evaluated at the Legendre
+ * nodes (as cheb_eval_leggrid) and the inverse transform (as dlt_inverse)
+ * is applied to those values, which is exact for degree < N because the
+ * Gauss-Legendre rule integrates P_n T_m exactly for n + m <= 2N - 1
+ * (Sec. 4, eq. (10)).  c is used as the intermediate for the values.
+ * Accuracy: max_n |c_n - c_n^exact| / ((n+1/2) ||chat||_1) <= 2e-13 (the
+ * evaluation's and the inverse's errors added).  Arguments, layout, sizes
+ * and errors as for leg2cheb. */
+int cheb2leg(int64_t N, int64_t batch, const double* chat, double* c, hipStream_t stream);
+
 /* Arithmetic of the _ex entry points (FP64 inputs and outputs in both).
  *   DLT_PREC_FP64       the plain method in FP64 (what the entry points above
  *                       use): accuracy as stated at the top of this file.
@@ -107,14 +118,15 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
 #define DLT_PREC_FP32_BULK 1
 #define DLT_PREC_FP64_RELAXED 2
 
-/* leg2cheb, cheb_eval_leggrid, dlt_forward and dlt_inverse with a precision
- * mode (DLT_PREC_*); same arguments and behaviour otherwise. */
+/* leg2cheb, cheb_eval_leggrid, dlt_forward, dlt_inverse and cheb2leg with a
+ * precision mode (DLT_PREC_*); same arguments and behaviour otherwise. */
 int leg2cheb_ex(int64_t N, int64_t batch, const double* c, double* chat, int prec, hipStream_t stream);
 int cheb_eval_leggrid_ex(int64_t N, int64_t batch, const double* chat, double* f, int prec, hipStream_t stream);
 int dlt_forward_ex(int64_t N, int64_t batch, const double* c, double* f, int prec, hipStream_t stream);
 int dlt_inverse_ex(int64_t N, int64_t batch, const double* f, double* c, int prec, hipStream_t stream);
+int cheb2leg_ex(int64_t N, int64_t batch, const double* chat, double* c, int prec, hipStream_t stream);
 
-/* The same four operations for a working tolerance eps (Sec. 3: every
+/* The same five operations for a working tolerance eps (Sec. 3: every
  * parameter of the method follows from the accuracy goal; Sec. 2, Cor. 1 and
  * Table 1 for the Taylor terms).  FP64 arithmetic; the Taylor length and the
  * far-field terms, blocks and rows (hence the near field) are chosen for eps
@@ -129,6 +141,7 @@ int leg2cheb_tol(int64_t N, int64_t batch, const double* c, double* chat, double
 int cheb_eval_leggrid_tol(int64_t N, int64_t batch, const double* chat, double* f, double eps, hipStream_t stream);
 int dlt_forward_tol(int64_t N, int64_t batch, const double* c, double* f, double eps, hipStream_t stream);
 int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double eps, hipStream_t stream);
+int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double eps, hipStream_t stream);
 
 /* Ragged batch: `count` independent transforms of uneven sizes in one call
  * (many transforms of different N, forward and inverse mixed).

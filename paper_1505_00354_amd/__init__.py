@@ -50,10 +50,11 @@ def lib():
         L.cheb_eval_leggrid.argtypes = [i64, i64, vp, vp, vp]
         L.dlt_forward.argtypes = [i64, i64, vp, vp, vp]
         L.dlt_inverse.argtypes = [i64, i64, vp, vp, vp]
-        for name in ("leg2cheb_ex", "cheb_eval_leggrid_ex", "dlt_forward_ex", "dlt_inverse_ex"):
+        L.cheb2leg.argtypes = [i64, i64, vp, vp, vp]
+        for name in ("leg2cheb_ex", "cheb_eval_leggrid_ex", "dlt_forward_ex", "dlt_inverse_ex", "cheb2leg_ex"):
             getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_int, vp]
             getattr(L, name).restype = ctypes.c_int
-        for name in ("leg2cheb_tol", "cheb_eval_leggrid_tol", "dlt_forward_tol", "dlt_inverse_tol"):
+        for name in ("leg2cheb_tol", "cheb_eval_leggrid_tol", "dlt_forward_tol", "dlt_inverse_tol", "cheb2leg_tol"):
             getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_double, vp]
             getattr(L, name).restype = ctypes.c_int
         L.dlt_plan_query_ex.argtypes = [i64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
@@ -69,7 +70,7 @@ def lib():
         L.dlt_trace_enable.argtypes = [ctypes.c_int]
         L.dlt_trace_collect.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
-        for name in ("leg_nodes_weights", "leg2cheb", "cheb_eval_leggrid", "dlt_forward", "dlt_inverse",
+        for name in ("leg_nodes_weights", "leg2cheb", "cheb_eval_leggrid", "dlt_forward", "dlt_inverse", "cheb2leg",
                      "dlt_release", "dlt_plan_query", "dlt_trace_enable", "dlt_trace_collect"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -161,6 +162,12 @@ def dlt_forward(c, out=None, prec="fp64", tol=None):
 def dlt_inverse(f, out=None, prec="fp64", tol=None):
     """Inverse transform c_n = (n+1/2) sum_k w_k f_k P_n(x_k)."""
     return _unary("dlt_inverse", f, out, prec, tol)
+
+
+def cheb2leg(chat, out=None, prec="fp64", tol=None):
+    """Legendre coefficients c = M^{-1} chat of a Chebyshev expansion (the
+    inverse of leg2cheb)."""
+    return _unary("cheb2leg", chat, out, prec, tol)
 
 
 def dlt_batch(x, sizes, offsets=None, inverse=None, out=None, prec="fp64"):

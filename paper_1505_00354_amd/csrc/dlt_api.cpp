@@ -955,6 +955,56 @@ int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double
     return dlt_inverse_on(*p, N, batch, f, c, stream);
 }
 
+// Chebyshev to Legendre coefficients on plan P: the expansion's values at
+// the Legendre nodes (written into c), then the inverse transform of them in
+// place (its input is read only by its first pass, before c is written)
+static int cheb2leg_on(Plan& P, int64_t N, int64_t batch, const double* chat, double* c, hipStream_t stream) {
+    Plan* p = &P;
+    return run_call(4, *p, batch, chat, c, stream, [&](CallWS& cw) -> int {
+        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
+        if (r) return r;
+        for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+            int64_t nb = std::min(cw.nb, batch - b0);
+            if ((r = hip_status(run_ndct(*p, nb, chat + b0 * N, N, cw.dth, c + b0 * N, cw.work, cw.lanes)))) return r;
+            if ((r = hip_status(run_inverse(*p, nb, c + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, cw.lanes))))
+                return r;
+        }
+        return DLT_OK;
+    });
+}
+
+int cheb2leg(int64_t N, int64_t batch, const double* chat, double* c, hipStream_t stream) {
+    return cheb2leg_ex(N, batch, chat, c, DLT_PREC_FP64, stream);
+}
+
+int cheb2leg_ex(int64_t N, int64_t batch, const double* chat, double* c, int prec, hipStream_t stream) {
+    int rc = check_any_size(N, batch);
+    if (rc) return rc;
+    if ((rc = check_prec(prec))) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!chat || !c || overlap(chat, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    if (!is_pow2_n(N)) {
+        if ((rc = ragged_equal(N, batch, 3, chat, c, prec, stream))) return rc;
+        return ragged_equal(N, batch, 1, c, c, prec, stream);
+    }
+    Plan* p;
+    if ((rc = get_plan(N, prec, &p))) return rc;
+    return cheb2leg_on(*p, N, batch, chat, c, stream);
+}
+
+int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double eps, hipStream_t stream) {
+    int rc = check_size(N, batch);  // power-of-two sizes
+    if (rc) return rc;
+    double tv;
+    int ti;
+    if ((rc = tol_step(eps, &tv, &ti))) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!chat || !c || overlap(chat, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan_tol(N, eps, &p))) return rc;
+    return cheb2leg_on(*p, N, batch, chat, c, stream);
+}
+
 int dlt_plan_query(int64_t N, int64_t* out, int max_fields) { return dlt_plan_query_ex(N, DLT_PREC_FP64, out, max_fields); }
 
 static int plan_fields(const Plan* p, int64_t* out, int max_fields) {

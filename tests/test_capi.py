@@ -37,7 +37,7 @@ def test_status_strings(L):
     assert L.dlt_status_string(7) == b"unknown status"
 
 
-@pytest.mark.parametrize("fn", ["leg2cheb", "cheb_eval_leggrid", "dlt_forward", "dlt_inverse"])
+@pytest.mark.parametrize("fn", ["leg2cheb", "cheb_eval_leggrid", "dlt_forward", "dlt_inverse", "cheb2leg"])
 def test_rejects_bad_sizes_before_device_work(L, fn):
     f = getattr(L, fn)
     p = ctypes.c_void_p(0x1000)
@@ -60,7 +60,7 @@ def test_nodes_rejects(L):
     assert L.leg_nodes_weights(24, 1, None, None, None, None) == 0   # any size; nothing requested
 
 
-@pytest.mark.parametrize("fn", ["leg2cheb_ex", "cheb_eval_leggrid_ex", "dlt_forward_ex", "dlt_inverse_ex"])
+@pytest.mark.parametrize("fn", ["leg2cheb_ex", "cheb_eval_leggrid_ex", "dlt_forward_ex", "dlt_inverse_ex", "cheb2leg_ex"])
 def test_ex_rejects_bad_precision(L, fn):
     f = getattr(L, fn)
     p, q = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000)
@@ -98,7 +98,7 @@ def test_batch_rejects_bad_descriptors(L):
     assert L.leg_nodes_weights(16, 1, a, a, None, None) == -1        # overlapping outputs
 
 
-@pytest.mark.parametrize("fn", ["leg2cheb_tol", "cheb_eval_leggrid_tol", "dlt_forward_tol", "dlt_inverse_tol"])
+@pytest.mark.parametrize("fn", ["leg2cheb_tol", "cheb_eval_leggrid_tol", "dlt_forward_tol", "dlt_inverse_tol", "cheb2leg_tol"])
 def test_tol_rejects_before_device_work(L, fn):
     f = getattr(L, fn)
     f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
