@@ -27,7 +27,8 @@ Prints one JSON line; diagnostics go to stderr.  Options:
   --no-modes    skip the short runs of the other modes (reported under
                 "modes": step time, speedup at equal stated accuracy,
                 FP32-bulk at batch 64, the step at working tolerances
-                1e-12 ... 1e-3, errors against the oracle)
+                1e-12 ... 1e-3, errors against the oracle; and under
+                "sizes" the FP64 step at N = 2^12, 2^14, 2^16, 2^18)
   --copy-probe BYTES  only run one plain copy kernel (read BYTES, write
                 BYTES) and exit: the reference for calibrating the HBM byte
                 counters FETCH_SIZE / WRITE_SIZE
@@ -490,6 +491,20 @@ def main():
             log(f"tolerance {eps:g}: {ms:.4f} ms/step")
         modes["tolerance"] = tols
         out["modes"] = modes
+
+    # the same step at the smaller sizes of the metric's range (FP64, one
+    # instance): these are bound by the chain of dependent launches
+    if not args.no_modes and B == 1 and prec == "fp64":
+        sizes = {}
+        for n in (1 << 12, 1 << 14, 1 << 16, 1 << 18):
+            cn = torch.from_numpy(wl.coeffs_algebraic(n, 2)).to(dev)
+            fn_ = torch.from_numpy(wl.values_normal(n, 4)).to(dev)
+            hn = torch.from_numpy(wl.coeffs_algebraic(n, 3)).to(dev)
+            a1, a2, a3 = torch.empty_like(cn), torch.empty_like(cn), torch.empty_like(cn)
+            ms = timed("fp64", args.steps, c=cn, fin=fn_, chat=hn, f=a1, c2=a2, g=a3)
+            sizes[str(n)] = {"ms_per_step": round(ms, 5), "transforms_per_s": round(3000.0 / ms, 2)}
+            log(f"N={n}: {ms:.4f} ms/step")
+        out["sizes"] = sizes
 
     if not args.no_ragged and B == 1:
         out["ragged"] = ragged_runs(pk, wl, torch, np, dev, with_oracle=not args.no_cpu)
