@@ -87,6 +87,20 @@ int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_
 /* Inverse discrete Legendre transform, eq. (2) (Sec. 4). */
 int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream);
 
+/* Chebyshev expansion at near-Chebyshev points (the NDCT of Sec. 2, eq. (3),
+ * at theta_k = (k+1/2) pi/N + dtheta_k): f_k = sum_n chat_n cos(n theta_k),
+ * by the same Taylor series in the offsets (Sec. 2.1, Cor. 1) as
+ * cheb_eval_leggrid, for points such as Gauss-Jacobi nodes (Sec. 1 names the
+ * Hankel-transform analogue).  dtheta: N offsets (device, shared by every
+ * batch instance), same convention as leg_nodes_weights's dtheta.
+ * Precondition: |N dtheta_k| <= pi/2 for every k; the Taylor length (L = 20)
+ * is chosen for that bound, so the error is at most 5e-14 ||chat||_1 as for
+ * cheb_eval_leggrid; larger offsets are not detected and give larger
+ * errors.  N must be a power of two (DLT_ERR_UNSUPPORTED otherwise); dtheta
+ * must not overlap f.  Calls are never captured into a graph. */
+int cheb_eval_nodes(int64_t N, int64_t batch, const double* chat, const double* dtheta, double* f,
+                    hipStream_t stream);
+
 /* Chebyshev-to-Legendre coefficients c = M^{-1} chat (the inverse of
  * leg2cheb, Sec. 3): the Chebyshev expansion is evaluated at the Legendre
  * nodes (as cheb_eval_leggrid) and the inverse transform (as dlt_inverse)

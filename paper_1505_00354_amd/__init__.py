@@ -51,6 +51,8 @@ def lib():
         L.dlt_forward.argtypes = [i64, i64, vp, vp, vp]
         L.dlt_inverse.argtypes = [i64, i64, vp, vp, vp]
         L.cheb2leg.argtypes = [i64, i64, vp, vp, vp]
+        L.cheb_eval_nodes.argtypes = [i64, i64, vp, vp, vp, vp]
+        L.cheb_eval_nodes.restype = ctypes.c_int
         for name in ("leg2cheb_ex", "cheb_eval_leggrid_ex", "dlt_forward_ex", "dlt_inverse_ex", "cheb2leg_ex"):
             getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_int, vp]
             getattr(L, name).restype = ctypes.c_int
@@ -162,6 +164,21 @@ def dlt_forward(c, out=None, prec="fp64", tol=None):
 def dlt_inverse(f, out=None, prec="fp64", tol=None):
     """Inverse transform c_n = (n+1/2) sum_k w_k f_k P_n(x_k)."""
     return _unary("dlt_inverse", f, out, prec, tol)
+
+
+def cheb_eval_nodes(chat, dtheta, out=None):
+    """sum_n chat_n cos(n theta_k) at theta_k = (k+1/2) pi/N + dtheta_k
+    (|N dtheta_k| <= pi/2); dtheta: float64 CUDA tensor of N offsets."""
+    import torch
+
+    N, batch, out = _vec_args(chat, out)
+    d = dtheta.contiguous()
+    if d.dtype != torch.float64 or d.device != chat.device or d.numel() != N:
+        raise ValueError("dtheta must be N float64 values on the device of chat")
+    with torch.cuda.device(chat.device):
+        _check(lib().cheb_eval_nodes(N, batch, ctypes.c_void_p(chat.data_ptr()), ctypes.c_void_p(d.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), _stream(chat.device)), "cheb_eval_nodes")
+    return out
 
 
 def cheb2leg(chat, out=None, prec="fp64", tol=None):

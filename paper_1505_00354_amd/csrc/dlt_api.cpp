@@ -93,6 +93,11 @@ Cache& cache() {
 }
 
 const size_t WS_CAP = size_t(6) << 30;  // per-stream workspace bound; larger batches run in slices
+// Taylor pairs of cheb_eval_nodes: L = 20 gives (pi/2)^20 / 20! = 3.4e-15, within
+// the FP64 Taylor budget for offsets |N dtheta| <= pi/2 (the workspace holds
+// RAGGED_Q_MAX pairs)
+constexpr int NODES_Q = 10;
+static_assert(NODES_Q <= RAGGED_Q_MAX, "workspace");
 
 bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
 
@@ -105,6 +110,12 @@ int check_size(int64_t N, int64_t batch) {
 bool overlap(const void* a, const void* b, size_t bytes) {
     uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
     return x < y + bytes && y < x + bytes;
+}
+
+// [a, a + abytes) and [b, b + bbytes) intersect
+bool overlap2(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bbytes && y < x + abytes;
 }
 
 int check_prec(int prec) {
@@ -1003,6 +1014,28 @@ int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double
     Plan* p;
     if ((rc = get_plan_tol(N, eps, &p))) return rc;
     return cheb2leg_on(*p, N, batch, chat, c, stream);
+}
+
+int cheb_eval_nodes(int64_t N, int64_t batch, const double* chat, const double* dtheta, double* f,
+                    hipStream_t stream) {
+    int rc = check_size(N, batch);  // power-of-two sizes
+    if (rc) return rc;
+    if (batch == 0) return DLT_OK;
+    const size_t bytes = (size_t)N * batch * sizeof(double);
+    if (!chat || !dtheta || !f || overlap(chat, f, bytes) || overlap2(dtheta, (size_t)N * sizeof(double), f, bytes))
+        return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
+    // enqueued directly (no cached graph: the offsets are an input of their own)
+    CallWS cw;
+    if ((rc = setup_call(*p, batch, stream, cw))) return rc;
+    for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+        int64_t nb = std::min(cw.nb, batch - b0);
+        if ((rc = hip_status(run_ndct(*p, nb, chat + b0 * N, N, dtheta, f + b0 * N, cw.work, cw.lanes, nullptr,
+                                      NODES_Q))))
+            return rc;
+    }
+    return DLT_OK;
 }
 
 int dlt_plan_query(int64_t N, int64_t* out, int max_fields) { return dlt_plan_query_ex(N, DLT_PREC_FP64, out, max_fields); }

@@ -113,3 +113,17 @@ def test_tol_rejects_before_device_work(L, fn):
     assert f(16, 1, p, ctypes.c_void_p(0x1000 + 8), 1e-6, None) == -1   # overlap
     L.dlt_plan_query_tol.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int]
     assert L.dlt_plan_query_tol(16, 1e-20, None, 4) == -1
+
+
+def test_cheb_eval_nodes_rejects(L):
+    f = L.cheb_eval_nodes
+    f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    a, d, o = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000)
+    assert f(24, 1, a, d, o, None) == -2                 # power-of-two sizes only
+    assert f(0, 1, a, d, o, None) == -1
+    assert f(16, 0, a, d, o, None) == 0                  # empty batch
+    assert f(16, 1, None, d, o, None) == -1
+    assert f(16, 1, a, None, o, None) == -1
+    assert f(16, 1, a, d, None, None) == -1
+    assert f(16, 1, a, ctypes.c_void_p(0x200000 + 8), o, None) == -1   # offsets overlap the output
+    assert f(16, 1, a, d, ctypes.c_void_p(0x1000 + 8), None) == -1     # output overlaps the input
