@@ -101,6 +101,26 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
 int cheb_eval_nodes(int64_t N, int64_t batch, const double* chat, const double* dtheta, double* f,
                     hipStream_t stream);
 
+/* Legendre coefficients <-> values at the Chebyshev points x_j =
+ * cos((j+1/2) pi/N), j = 0..N-1 (decreasing x, the order of the Legendre
+ * outputs) (Sec. 1, the arcs of Fig. 1 between Legendre coefficients and
+ * values on a Chebyshev grid):
+ *   leg2chebvals  v_j = sum_n c_n P_n(x_j): leg2cheb, then the Chebyshev
+ *                 expansion on the grid (a DCT-III);
+ *   chebvals2leg  c = the Legendre coefficients of the polynomial of degree
+ *                 < N through the values v_j: the Chebyshev coefficients of
+ *                 the interpolant (a DCT-II, chat_n = (eps_n/N) sum_j v_j
+ *                 cos(n theta_j)), then cheb2leg; c is used as the
+ *                 intermediate for the values at the Legendre nodes.
+ * Accuracy: leg2chebvals as dlt_forward, ||v - v^exact||_inf <= 5e-14
+ * ||c||_1; chebvals2leg as cheb2leg applied to the exact Chebyshev
+ * coefficients chat of the interpolant, max_n |c_n - c_n^exact| /
+ * ((n+1/2) ||chat||_1) <= 2e-13.  FP64; N must be a power of two
+ * (DLT_ERR_UNSUPPORTED otherwise); other arguments and errors as for
+ * leg2cheb. */
+int leg2chebvals(int64_t N, int64_t batch, const double* c, double* v, hipStream_t stream);
+int chebvals2leg(int64_t N, int64_t batch, const double* v, double* c, hipStream_t stream);
+
 /* Chebyshev-to-Legendre coefficients c = M^{-1} chat (the inverse of
  * leg2cheb, Sec. 3): the Chebyshev expansion is evaluated at the Legendre
  * nodes (as cheb_eval_leggrid) and the inverse transform (as dlt_inverse)

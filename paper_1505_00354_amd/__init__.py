@@ -53,6 +53,9 @@ def lib():
         L.cheb2leg.argtypes = [i64, i64, vp, vp, vp]
         L.cheb_eval_nodes.argtypes = [i64, i64, vp, vp, vp, vp]
         L.cheb_eval_nodes.restype = ctypes.c_int
+        for name in ("leg2chebvals", "chebvals2leg"):
+            getattr(L, name).argtypes = [i64, i64, vp, vp, vp]
+            getattr(L, name).restype = ctypes.c_int
         for name in ("leg2cheb_ex", "cheb_eval_leggrid_ex", "dlt_forward_ex", "dlt_inverse_ex", "cheb2leg_ex"):
             getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_int, vp]
             getattr(L, name).restype = ctypes.c_int
@@ -179,6 +182,17 @@ def cheb_eval_nodes(chat, dtheta, out=None):
         _check(lib().cheb_eval_nodes(N, batch, ctypes.c_void_p(chat.data_ptr()), ctypes.c_void_p(d.data_ptr()),
                                      ctypes.c_void_p(out.data_ptr()), _stream(chat.device)), "cheb_eval_nodes")
     return out
+
+
+def leg2chebvals(c, out=None):
+    """Values of sum_n c_n P_n at the Chebyshev points cos((j+1/2) pi/N)."""
+    return _unary("leg2chebvals", c, out)
+
+
+def chebvals2leg(v, out=None):
+    """Legendre coefficients of the degree < N interpolant of values v at the
+    Chebyshev points cos((j+1/2) pi/N)."""
+    return _unary("chebvals2leg", v, out)
 
 
 def cheb2leg(chat, out=None, prec="fp64", tol=None):

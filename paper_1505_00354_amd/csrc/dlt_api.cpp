@@ -1038,6 +1038,54 @@ int cheb_eval_nodes(int64_t N, int64_t batch, const double* chat, const double* 
     return DLT_OK;
 }
 
+int chebvals2leg(int64_t N, int64_t batch, const double* v, double* c, hipStream_t stream) {
+    int rc = check_size(N, batch);  // power-of-two sizes
+    if (rc) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!v || !c || overlap(v, c, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
+    // Chebyshev coefficients of the interpolant (workspace), their expansion's
+    // values at the Legendre nodes (into c), the inverse transform in place
+    return run_call(5, *p, batch, v, c, stream, [&](CallWS& cw) -> int {
+        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
+        if (r) return r;
+        for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+            int64_t nb = std::min(cw.nb, batch - b0);
+            double* chat = cw.work.chat;
+            if ((r = hip_status(run_chebvals2cheb(*p, nb, v + b0 * N, N, chat, cw.work.schat, cw.work, cw.lanes))))
+                return r;
+            if ((r = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, c + b0 * N, cw.work, cw.lanes)))) return r;
+            if ((r = hip_status(run_inverse(*p, nb, c + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, cw.lanes))))
+                return r;
+        }
+        return DLT_OK;
+    });
+}
+
+int leg2chebvals(int64_t N, int64_t batch, const double* c, double* v, hipStream_t stream) {
+    int rc = check_size(N, batch);  // power-of-two sizes
+    if (rc) return rc;
+    if (batch == 0) return DLT_OK;
+    if (!c || !v || overlap(c, v, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p;
+    if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
+    // Chebyshev coefficients (workspace), then the Taylor evaluation with all
+    // offsets zero and one term pair: exactly the DCT-III onto the grid
+    return run_call(6, *p, batch, c, v, stream, [&](CallWS& cw) -> int {
+        int r = hip_status(run_fill_zero(cw.dth, N, cw.lanes.s));
+        if (r) return r;
+        for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
+            int64_t nb = std::min(cw.nb, batch - b0);
+            double* chat = cw.work.chat;
+            if ((r = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat, cw.work.schat, cw.work, cw.lanes)))) return r;
+            if ((r = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, v + b0 * N, cw.work, cw.lanes, nullptr, 1))))
+                return r;
+        }
+        return DLT_OK;
+    });
+}
+
 int dlt_plan_query(int64_t N, int64_t* out, int max_fields) { return dlt_plan_query_ex(N, DLT_PREC_FP64, out, max_fields); }
 
 static int plan_fields(const Plan* p, int64_t* out, int max_fields) {

@@ -2308,6 +2308,29 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
 // conversion (dense or recursive), rows n >= nd as P^T C D_eps y on the grid.
 // With side streams the low block runs beside everything else and the
 // transposed near field beside the transposed far field.
+hipError_t run_chebvals2cheb(const Plan& p, int64_t nb, const double* v, int64_t vs, double* chat, int64_t hs,
+                             Work& w, const Lanes& L) {
+    trace_n = p.N;
+    const Geo& g = p.geo;
+    const hipStream_t s = L.s;
+    // one slab of values, no near-field rows (never read), no low block
+    traced("k_dct2_passA", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_dct2_passA, (dim3(g.N1 / g.colsA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, 1,
+                   v, vs, v, vs, 0, w.X, w.sX);
+    });
+    traced("k_dct2_passB", s, [&] {
+        LEN_LAUNCH(g.N >= FFT_CAP, g.N1, k_dct2_passB, (dim3(g.N2 / g.rowsB, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, 0,
+                   w.X, w.sX, v, vs, chat, hs);
+    });
+    return hipGetLastError();
+}
+
+hipError_t run_fill_zero(double* x, int64_t n, hipStream_t s) {
+    // zero bits are 0.0: a fill kernel (no memset node in a captured graph)
+    traced("k_fill_int", s, [&] { launch(k_fill_int, (unsigned)((2 * n + 255) / 256), 256, 0, s, (int*)x, 2 * n, 0); });
+    return hipGetLastError();
+}
+
 hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys, double* out, int64_t os, int half,
                           Work& w, const Lanes& L) {
     trace_n = p.N;

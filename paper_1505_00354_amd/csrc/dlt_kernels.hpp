@@ -71,6 +71,13 @@ hipError_t plan_prepare(Plan& p);
 // chat = M c for nb instances (batch strides cs, hs in elements)
 hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, double* chat, int64_t hs, Work& w,
                         const Lanes& L);
+// chat_n = (eps_n/N) sum_j v_j cos(n theta_j), theta_j = (j+1/2) pi/N: the
+// Chebyshev coefficients of the interpolant of values v on the grid (the
+// conversion's DCT-II passes alone)
+hipError_t run_chebvals2cheb(const Plan& p, int64_t nb, const double* v, int64_t vs, double* chat, int64_t hs,
+                             Work& w, const Lanes& L);
+// x[0..n) = 0 on stream s
+hipError_t run_fill_zero(double* x, int64_t n, hipStream_t s);
 // out = M^T y (times n + 1/2 when half != 0)
 hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys, double* out, int64_t os, int half,
                           Work& w, const Lanes& L);

@@ -37,7 +37,8 @@ def test_status_strings(L):
     assert L.dlt_status_string(7) == b"unknown status"
 
 
-@pytest.mark.parametrize("fn", ["leg2cheb", "cheb_eval_leggrid", "dlt_forward", "dlt_inverse", "cheb2leg"])
+@pytest.mark.parametrize("fn", ["leg2cheb", "cheb_eval_leggrid", "dlt_forward", "dlt_inverse", "cheb2leg",
+                                "leg2chebvals", "chebvals2leg"])
 def test_rejects_bad_sizes_before_device_work(L, fn):
     f = getattr(L, fn)
     p = ctypes.c_void_p(0x1000)
