@@ -32,9 +32,13 @@
  *     and a per-stream workspace; both are created on first use and live
  *     until dlt_release() or process exit.  The first call for a given N on
  *     a device builds its plan and synchronises the device (so it must not
- *     be made inside stream capture); later calls never synchronise.
- *   - Repeated calls: when leg2cheb, cheb_eval_leggrid, dlt_forward or
- *     dlt_inverse (and their _ex and _tol forms) are called again with the same size
+ *     be made inside stream capture); a call that needs a larger workspace
+ *     than its stream holds synchronises that stream before replacing it;
+ *     other calls never synchronise.  Calls on different streams use
+ *     different workspaces and may run at the same time.
+ *   - Repeated calls: when leg2cheb, cheb_eval_leggrid, dlt_forward,
+ *     dlt_inverse, cheb2leg (and their _ex and _tol forms), leg2chebvals or
+ *     chebvals2leg are called again with the same size
  *     (a power of two), batch, precision, buffers and stream, the second
  *     call captures its work into a HIP graph (on a library-owned stream)
  *     and it and later such calls launch that graph on `stream`: the same

@@ -62,3 +62,34 @@ def test_replays_match_direct_calls(pk, op, N, batch, prec):
         pk.trace_enable(False)
         pk.trace_collect()
     assert np.array_equal(got, ref2)
+
+
+@pytest.mark.parametrize("op", OPS + ["cheb2leg", "leg2chebvals", "chebvals2leg"])
+@pytest.mark.parametrize("Na,Nb", [(1 << 16, 1 << 16), (1 << 16, 1 << 13)])
+def test_two_streams_at_once(pk, op, Na, Nb):
+    """Calls on two streams (each with its own workspace, side streams and
+    graphs) run at the same time, direct, captured and replayed, and give the
+    bits of the same calls made alone."""
+    import torch
+
+    say("two streams", op, Na, Nb)
+    fn = getattr(pk, op)
+    xa = to_dev(wl.coeffs_algebraic(Na, 31))
+    xb = to_dev(wl.coeffs_algebraic(Nb, 32))
+    ref_a = to_host(fn(xa.clone()))
+    ref_b = to_host(fn(xb.clone()))
+    ya, yb = torch.empty_like(xa), torch.empty_like(xb)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        ya.fill_(np.nan)
+        yb.fill_(np.nan)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            with torch.cuda.stream(s1):
+                fn(xa, out=ya)
+            with torch.cuda.stream(s2):
+                fn(xb, out=yb)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(ya), ref_a), (op, rep, "stream 1")
+        assert np.array_equal(to_host(yb), ref_b), (op, rep, "stream 2")
