@@ -332,8 +332,12 @@ int run_call(int op, const Plan& p, int64_t batch, const void* in, void* out, hi
     {
         std::lock_guard<std::mutex> lk(c.mu);
         if (c.calls.size() > CALL_GRAPHS_MAX) {
-            // many distinct calls: drop the graphs of the others (none is in
-            // use by the host; launched replays keep their own references)
+            // many distinct calls: drop the graphs of the others, once the
+            // device has drained (a replay may still run on another stream)
+            if (hipDeviceSynchronize() != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                return DLT_ERR_HIP;
+            }
             for (auto& kv : c.calls)
                 if (kv.second.exec && kv.first != key) (void)hipGraphExecDestroy(kv.second.exec);
             Cache::CallGraph mine = c.calls[key];

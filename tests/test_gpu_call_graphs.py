@@ -93,3 +93,25 @@ def test_two_streams_at_once(pk, op, Na, Nb):
         torch.cuda.synchronize()
         assert np.array_equal(to_host(ya), ref_a), (op, rep, "stream 1")
         assert np.array_equal(to_host(yb), ref_b), (op, rep, "stream 2")
+
+
+def test_more_distinct_calls_than_kept_graphs(pk):
+    """300 distinct repeated calls (one output buffer each), three rounds:
+    more than the library keeps graphs for, so graphs are dropped (after the
+    device drains) while others are queued; every call still gives the
+    bits of the direct call."""
+    import torch
+
+    N = 256
+    say("many call graphs", N)
+    x = to_dev(wl.coeffs_algebraic(N, 41))
+    ref = to_host(pk.dlt_forward(x.clone()))
+    outs = [torch.empty_like(x) for _ in range(300)]
+    for rep in range(3):
+        for y in outs:
+            y.fill_(np.nan)
+        for y in outs:
+            pk.dlt_forward(x, out=y)
+        torch.cuda.synchronize()
+        for i, y in enumerate(outs):
+            assert np.array_equal(to_host(y), ref), (rep, i)
