@@ -166,3 +166,28 @@ def test_ragged_graph_replay_and_single_calls(pk):
     assert np.allclose(second, -0.5 * first, rtol=0, atol=1e-13 * np.max(np.abs(first)))
     pk.dlt_batch(xd, sizes, offs, inv, out=out)
     assert np.array_equal(to_host(out), second)  # replays are deterministic
+
+
+def test_ragged_graph_cache_bound(pk):
+    """70 distinct layouts (the library keeps 64 ragged graphs): each call and
+    its replay agree bit for bit, and the earliest layouts, whose graphs were
+    dropped, are rebuilt on the same grids with the same bits."""
+    import torch
+
+    sizes = np.array([100, 37, 64], dtype=np.int64)
+    n = 70
+    say("ragged graph cache bound", n)
+    xd = to_dev(wl.coeffs_algebraic(int(sizes.sum()) + n, 61)[0])
+    base = np.concatenate(([0], np.cumsum(sizes)[:-1]))
+    outs = [torch.zeros_like(xd) for _ in range(n)]
+    first = []
+    for k in range(n):
+        pk.dlt_batch(xd, sizes, base + k, out=outs[k])
+        first.append(to_host(outs[k]))
+        outs[k].zero_()
+        pk.dlt_batch(xd, sizes, base + k, out=outs[k])
+        assert np.array_equal(to_host(outs[k]), first[k]), k
+    for k in range(3):
+        outs[k].zero_()
+        pk.dlt_batch(xd, sizes, base + k, out=outs[k])
+        assert np.array_equal(to_host(outs[k]), first[k]), ("rebuilt", k)
