@@ -181,34 +181,6 @@ int dlt_forward_tol(int64_t N, int64_t batch, const double* c, double* f, double
 int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double eps, hipStream_t stream);
 int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double eps, hipStream_t stream);
 
-/* Caller-owned workspace (power-of-two N).
- * dlt_workspace_bytes: *bytes = the workspace a call of size N with `batch`
- *   instances at precision `prec` uses (batch 0 or 1: one instance, the
- *   least any call accepts).  Builds the plan for N if needed (device tables,
- *   synchronises the device once, like a first call).
- * leg2cheb_ws, cheb_eval_leggrid_ws, dlt_forward_ws, dlt_inverse_ws: the
- *   same operations as the _ex entry points, on the caller's device buffer
- *   `ws` of `ws_bytes` bytes instead of the library's per-stream workspace;
- *   with fewer bytes than the whole batch needs (but at least one
- *   instance's), the batch runs in slices of as many instances as fit.
- *   `ws` must be 256-byte aligned and must not overlap the input or the
- *   output (DLT_ERR_INVALID_ARG, also for a buffer smaller than one
- *   instance needs).  The library reads and writes ws until the call's work
- *   on `stream` has finished; the caller must not use it, or pass it to a
- *   call on another stream, before then.  Repeated calls with the same
- *   arguments and workspace replay a captured graph as above.  For callers
- *   that manage device memory themselves (pools, arenas); the plan's tables
- *   are still the library's. */
-int dlt_workspace_bytes(int64_t N, int64_t batch, int prec, size_t* bytes);
-int leg2cheb_ws(int64_t N, int64_t batch, const double* c, double* chat, int prec, void* ws, size_t ws_bytes,
-                hipStream_t stream);
-int cheb_eval_leggrid_ws(int64_t N, int64_t batch, const double* chat, double* f, int prec, void* ws,
-                         size_t ws_bytes, hipStream_t stream);
-int dlt_forward_ws(int64_t N, int64_t batch, const double* c, double* f, int prec, void* ws, size_t ws_bytes,
-                   hipStream_t stream);
-int dlt_inverse_ws(int64_t N, int64_t batch, const double* f, double* c, int prec, void* ws, size_t ws_bytes,
-                   hipStream_t stream);
-
 /* Ragged batch: `count` independent transforms of uneven sizes in one call
  * (many transforms of different N, forward and inverse mixed).
  *   Ns[i]       size of instance i (1 <= Ns[i] <= DLT_MAX_N), host array

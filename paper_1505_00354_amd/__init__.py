@@ -62,11 +62,6 @@ def lib():
         for name in ("leg2cheb_tol", "cheb_eval_leggrid_tol", "dlt_forward_tol", "dlt_inverse_tol", "cheb2leg_tol"):
             getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_double, vp]
             getattr(L, name).restype = ctypes.c_int
-        L.dlt_workspace_bytes.argtypes = [i64, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
-        L.dlt_workspace_bytes.restype = ctypes.c_int
-        for name in ("leg2cheb_ws", "cheb_eval_leggrid_ws", "dlt_forward_ws", "dlt_inverse_ws"):
-            getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
-            getattr(L, name).restype = ctypes.c_int
         L.dlt_plan_query_ex.argtypes = [i64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         L.dlt_plan_query_ex.restype = ctypes.c_int
         L.dlt_plan_query_tol.argtypes = [i64, ctypes.c_double, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
@@ -133,30 +128,13 @@ def _prec(prec):
     return PRECISIONS[prec]
 
 
-def workspace_bytes(N, batch=1, prec="fp64"):
-    """Bytes of device workspace a call of size N (a power of two) with
-    `batch` instances uses (dlt_workspace_bytes); the _ws forms of the
-    transforms run on such a caller buffer (ws= argument)."""
-    n = ctypes.c_size_t(0)
-    _check(lib().dlt_workspace_bytes(int(N), int(batch), _prec(prec), ctypes.byref(n)), "dlt_workspace_bytes")
-    return n.value
-
-
-def _unary(name, x, out, prec="fp64", tol=None, ws=None):
+def _unary(name, x, out, prec="fp64", tol=None):
     import torch
 
     N, batch, out = _vec_args(x, out)
     args = (N, batch, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()))
     with torch.cuda.device(x.device):
-        if ws is not None:
-            if tol is not None:
-                raise ValueError("a caller workspace runs with the precision modes, not a working tolerance")
-            if not (isinstance(ws, torch.Tensor) and ws.is_cuda and ws.is_contiguous() and ws.device == x.device):
-                raise ValueError("ws must be a contiguous CUDA tensor on the input's device")
-            nbytes = ws.numel() * ws.element_size()
-            _check(getattr(lib(), name + "_ws")(*args, _prec(prec), ctypes.c_void_p(ws.data_ptr()), nbytes,
-                                                _stream(x.device)), name + "_ws")
-        elif tol is not None:
+        if tol is not None:
             if prec != "fp64":
                 raise ValueError("a working tolerance runs in FP64 (prec must be 'fp64')")
             _check(getattr(lib(), name + "_tol")(*args, float(tol), _stream(x.device)), name + "_tol")
@@ -167,30 +145,28 @@ def _unary(name, x, out, prec="fp64", tol=None, ws=None):
     return out
 
 
-def leg2cheb(c, out=None, prec="fp64", tol=None, ws=None):
+def leg2cheb(c, out=None, prec="fp64", tol=None):
     """Chebyshev coefficients of sum_n c_n P_n (chat = M c)."""
-    return _unary("leg2cheb", c, out, prec, tol, ws)
+    return _unary("leg2cheb", c, out, prec, tol)
 
 
-def cheb_eval_leggrid(chat, out=None, prec="fp64", tol=None, ws=None):
+def cheb_eval_leggrid(chat, out=None, prec="fp64", tol=None):
     """sum_n chat_n T_n at the N Legendre nodes."""
-    return _unary("cheb_eval_leggrid", chat, out, prec, tol, ws)
+    return _unary("cheb_eval_leggrid", chat, out, prec, tol)
 
 
-def dlt_forward(c, out=None, prec="fp64", tol=None, ws=None):
+def dlt_forward(c, out=None, prec="fp64", tol=None):
     """Discrete Legendre transform f_k = sum_n c_n P_n(x_k).  prec: "fp64",
     "fp32bulk" (FP32 bulk transforms, 5e-6 budget) or "fp64relaxed" (FP64
     with the 5e-6 parameters).  tol: a working tolerance instead (FP64,
     parameters chosen for eps = tol, 5e-14 <= tol <= 0.1; the other entry
-    points take it too).  ws: a caller-owned device workspace (a contiguous
-    CUDA tensor, 256-byte aligned; see workspace_bytes) instead of the
-    library's (leg2cheb, cheb_eval_leggrid and dlt_inverse take it too)."""
-    return _unary("dlt_forward", c, out, prec, tol, ws)
+    points take it too)."""
+    return _unary("dlt_forward", c, out, prec, tol)
 
 
-def dlt_inverse(f, out=None, prec="fp64", tol=None, ws=None):
+def dlt_inverse(f, out=None, prec="fp64", tol=None):
     """Inverse transform c_n = (n+1/2) sum_k w_k f_k P_n(x_k)."""
-    return _unary("dlt_inverse", f, out, prec, tol, ws)
+    return _unary("dlt_inverse", f, out, prec, tol)
 
 
 def cheb_eval_nodes(chat, dtheta, out=None):

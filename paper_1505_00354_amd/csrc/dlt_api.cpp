@@ -82,8 +82,7 @@ struct Cache {
     // output, stream) -> graph of the call, and the workspace it was captured with
     struct CallGraph {
         hipGraphExec_t exec = nullptr;
-        void* ws = nullptr;  // workspace base and instances per slice it was captured with
-        int64_t nb = 0;
+        void* ws = nullptr;
         int seen = 0;
     };
     std::map<std::tuple<int, int, int64_t, int64_t, const void*, const void*, void*, hipStream_t>, CallGraph> calls;
@@ -273,34 +272,15 @@ struct CallWS {
     Lanes lanes;
 };
 
-// A caller-owned workspace (the _ws entry points): 256-byte aligned, `bytes` long.
-struct UserWS {
-    void* ptr;
-    size_t bytes;
-};
-
-// bytes of a call's workspace shared by its instances: the node arrays and
-// the node scratch
-size_t call_shared_bytes(const Plan& p) { return p.ws_shared + (size_t)64 * NODE_PARTS_MAX * 8 * sizeof(double); }
-
-// The call's workspace: the caller's (uw; as many instances per slice as it
-// holds) or the stream's own (slices bounded by WS_CAP).
-int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw, const UserWS* uw = nullptr) {
+int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
     size_t per = p.ws_per_inst;
-    const size_t shared = call_shared_bytes(p);
     int64_t nb = batch;
+    if (per > 0 && (size_t)nb * per > WS_CAP) nb = (int64_t)(WS_CAP / per);
+    if (batch > 0 && nb < 1) nb = 1;
+    size_t shared = p.ws_shared + (size_t)64 * NODE_PARTS_MAX * 8 * sizeof(double);
     void* base = nullptr;
-    if (uw) {
-        if (uw->bytes < shared + per) return DLT_ERR_INVALID_ARG;  // not even one instance
-        if (per > 0) nb = std::min<int64_t>(batch, (int64_t)((uw->bytes - shared) / per));
-        if (batch > 0 && nb < 1) nb = 1;
-        base = uw->ptr;
-    } else {
-        if (per > 0 && (size_t)nb * per > WS_CAP) nb = (int64_t)(WS_CAP / per);
-        if (batch > 0 && nb < 1) nb = 1;
-        int rc = get_ws(s, shared + work_bytes(p, nb), &base);
-        if (rc) return rc;
-    }
+    int rc = get_ws(s, shared + work_bytes(p, nb), &base);
+    if (rc) return rc;
     size_t vecb = ((size_t)p.N * sizeof(double) + 255) & ~size_t(255);
     cw.theta = (double*)base;
     cw.w = (double*)((char*)base + vecb);
@@ -320,14 +300,13 @@ int capture_stream(hipStream_t user, hipStream_t* out);
 // precision, buffers, stream) runs directly; the second is captured into a
 // HIP graph on the private capture stream (the side streams become branches
 // of the graph), and it and every later call replay that graph on the
-// caller's stream with one launch.  A graph is recaptured when the workspace
-// has moved or is sliced otherwise; traced calls always run directly.
+// caller's stream with one launch.  A graph is recaptured when the stream's
+// workspace has moved; traced calls always run directly.
 constexpr size_t CALL_GRAPHS_MAX = 256;
 template <class F>
-int run_call(int op, const Plan& p, int64_t batch, const void* in, void* out, hipStream_t stream, const UserWS* uw,
-             F&& enqueue) {
+int run_call(int op, const Plan& p, int64_t batch, const void* in, void* out, hipStream_t stream, F&& enqueue) {
     CallWS cw;
-    int rc = setup_call(p, batch, stream, cw, uw);
+    int rc = setup_call(p, batch, stream, cw);
     if (rc) return rc;
     if (trace_on()) return enqueue(cw);
     int dev = 0;
@@ -338,7 +317,7 @@ int run_call(int op, const Plan& p, int64_t batch, const void* in, void* out, hi
     {
         std::lock_guard<std::mutex> lk(c.mu);
         Cache::CallGraph& g = c.calls[key];
-        if (g.exec && g.ws == ws && g.nb == cw.nb) return hip_status(hipGraphLaunch(g.exec, stream));
+        if (g.exec && g.ws == ws) return hip_status(hipGraphLaunch(g.exec, stream));
         if (++g.seen < 2) return enqueue(cw);
     }
     hipStream_t cs;
@@ -373,7 +352,6 @@ int run_call(int op, const Plan& p, int64_t batch, const void* in, void* out, hi
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         g.exec = exec;
         g.ws = ws;
-        g.nb = cw.nb;
     }
     return hip_status(hipGraphLaunch(exec, stream));
 }
@@ -830,10 +808,9 @@ int leg2cheb(int64_t N, int64_t batch, const double* c, double* chat, hipStream_
 }
 
 // leg2cheb for nb instances on plan P (any precision mode or tolerance)
-static int leg2cheb_on(Plan& P, int64_t N, int64_t batch, const double* c, double* chat, hipStream_t stream,
-                       const UserWS* uw = nullptr) {
+static int leg2cheb_on(Plan& P, int64_t N, int64_t batch, const double* c, double* chat, hipStream_t stream) {
     Plan* p = &P;
-    return run_call(2, *p, batch, c, chat, stream, uw, [&](CallWS& cw) -> int {
+    return run_call(2, *p, batch, c, chat, stream, [&](CallWS& cw) -> int {
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
             int r = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat + b0 * N, N, cw.work, cw.lanes));
@@ -873,10 +850,9 @@ int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, h
 }
 
 // cheb_eval_leggrid for nb instances on plan P (any precision mode or tolerance)
-static int cheb_eval_leggrid_on(Plan& P, int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream,
-                                const UserWS* uw = nullptr) {
+static int cheb_eval_leggrid_on(Plan& P, int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream) {
     Plan* p = &P;
-    return run_call(3, *p, batch, chat, f, stream, uw, [&](CallWS& cw) -> int {
+    return run_call(3, *p, batch, chat, f, stream, [&](CallWS& cw) -> int {
         int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, cw.lanes));
         if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
@@ -917,10 +893,9 @@ int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_
 }
 
 // dlt_forward for nb instances on plan P (any precision mode or tolerance)
-static int dlt_forward_on(Plan& P, int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream,
-                          const UserWS* uw = nullptr) {
+static int dlt_forward_on(Plan& P, int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream) {
     Plan* p = &P;
-    return run_call(0, *p, batch, c, f, stream, uw, [&](CallWS& cw) -> int {
+    return run_call(0, *p, batch, c, f, stream, [&](CallWS& cw) -> int {
         // the nodes are needed only by the Taylor evaluation: they run on the
         // first side stream beside the conversion of the first slice
         const Lanes& L = cw.lanes;
@@ -973,10 +948,9 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
 }
 
 // dlt_inverse for nb instances on plan P (any precision mode or tolerance)
-static int dlt_inverse_on(Plan& P, int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream,
-                          const UserWS* uw = nullptr) {
+static int dlt_inverse_on(Plan& P, int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
     Plan* p = &P;
-    return run_call(1, *p, batch, f, c, stream, uw, [&](CallWS& cw) -> int {
+    return run_call(1, *p, batch, f, c, stream, [&](CallWS& cw) -> int {
         int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
         if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
@@ -1013,64 +987,12 @@ int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double
     return dlt_inverse_on(*p, N, batch, f, c, stream);
 }
 
-// ---------------------------------------------------- caller workspaces --
-int dlt_workspace_bytes(int64_t N, int64_t batch, int prec, size_t* bytes) {
-    int rc = check_size(N, batch);  // power-of-two sizes
-    if (rc) return rc;
-    if ((rc = check_prec(prec))) return rc;
-    if (!bytes) return DLT_ERR_INVALID_ARG;
-    Plan* p;
-    if ((rc = get_plan(N, prec, &p))) return rc;
-    *bytes = call_shared_bytes(*p) + work_bytes(*p, std::max<int64_t>(batch, 1));
-    return DLT_OK;
-}
-
-// The _ws entry points: the checks of the plain ones plus the caller's
-// workspace (256-byte aligned, apart from in and out), then the same call on
-// that workspace.
-using OnFn = int (*)(Plan&, int64_t, int64_t, const double*, double*, hipStream_t, const UserWS*);
-static int ws_call(int64_t N, int64_t batch, const double* in, double* out, int prec, void* ws, size_t ws_bytes,
-                   hipStream_t stream, OnFn on) {
-    int rc = check_size(N, batch);  // power-of-two sizes
-    if (rc) return rc;
-    if ((rc = check_prec(prec))) return rc;
-    if (batch == 0) return DLT_OK;
-    const size_t vb = (size_t)N * batch * sizeof(double);
-    if (!in || !out || !ws || overlap(in, out, vb)) return DLT_ERR_INVALID_ARG;
-    if (((uintptr_t)ws & 255) != 0 || overlap2(ws, ws_bytes, in, vb) || overlap2(ws, ws_bytes, out, vb))
-        return DLT_ERR_INVALID_ARG;
-    Plan* p;
-    if ((rc = get_plan(N, prec, &p))) return rc;
-    const UserWS uw{ws, ws_bytes};
-    return on(*p, N, batch, in, out, stream, &uw);
-}
-
-int leg2cheb_ws(int64_t N, int64_t batch, const double* c, double* chat, int prec, void* ws, size_t ws_bytes,
-                hipStream_t stream) {
-    return ws_call(N, batch, c, chat, prec, ws, ws_bytes, stream, leg2cheb_on);
-}
-
-int cheb_eval_leggrid_ws(int64_t N, int64_t batch, const double* chat, double* f, int prec, void* ws,
-                         size_t ws_bytes, hipStream_t stream) {
-    return ws_call(N, batch, chat, f, prec, ws, ws_bytes, stream, cheb_eval_leggrid_on);
-}
-
-int dlt_forward_ws(int64_t N, int64_t batch, const double* c, double* f, int prec, void* ws, size_t ws_bytes,
-                   hipStream_t stream) {
-    return ws_call(N, batch, c, f, prec, ws, ws_bytes, stream, dlt_forward_on);
-}
-
-int dlt_inverse_ws(int64_t N, int64_t batch, const double* f, double* c, int prec, void* ws, size_t ws_bytes,
-                   hipStream_t stream) {
-    return ws_call(N, batch, f, c, prec, ws, ws_bytes, stream, dlt_inverse_on);
-}
-
 // Chebyshev to Legendre coefficients on plan P: the expansion's values at
 // the Legendre nodes (written into c), then the inverse transform of them in
 // place (its input is read only by its first pass, before c is written)
 static int cheb2leg_on(Plan& P, int64_t N, int64_t batch, const double* chat, double* c, hipStream_t stream) {
     Plan* p = &P;
-    return run_call(4, *p, batch, chat, c, stream, nullptr, [&](CallWS& cw) -> int {
+    return run_call(4, *p, batch, chat, c, stream, [&](CallWS& cw) -> int {
         int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
         if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
@@ -1146,7 +1068,7 @@ int chebvals2leg(int64_t N, int64_t batch, const double* v, double* c, hipStream
     if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
     // Chebyshev coefficients of the interpolant (workspace), their expansion's
     // values at the Legendre nodes (into c), the inverse transform in place
-    return run_call(5, *p, batch, v, c, stream, nullptr, [&](CallWS& cw) -> int {
+    return run_call(5, *p, batch, v, c, stream, [&](CallWS& cw) -> int {
         int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
         if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
@@ -1171,7 +1093,7 @@ int leg2chebvals(int64_t N, int64_t batch, const double* c, double* v, hipStream
     if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
     // Chebyshev coefficients (workspace), then the Taylor evaluation with all
     // offsets zero and one term pair: exactly the DCT-III onto the grid
-    return run_call(6, *p, batch, c, v, stream, nullptr, [&](CallWS& cw) -> int {
+    return run_call(6, *p, batch, c, v, stream, [&](CallWS& cw) -> int {
         int r = hip_status(run_fill_zero(cw.dth, N, cw.lanes.s));
         if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {

@@ -128,32 +128,3 @@ def test_cheb_eval_nodes_rejects(L):
     assert f(16, 1, a, d, None, None) == -1
     assert f(16, 1, a, ctypes.c_void_p(0x200000 + 8), o, None) == -1   # offsets overlap the output
     assert f(16, 1, a, d, ctypes.c_void_p(0x1000 + 8), None) == -1     # output overlaps the input
-
-
-@pytest.mark.parametrize("fn", ["leg2cheb_ws", "cheb_eval_leggrid_ws", "dlt_forward_ws", "dlt_inverse_ws"])
-def test_ws_rejects_before_device_work(L, fn):
-    f = getattr(L, fn)
-    f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
-                  ctypes.c_size_t, ctypes.c_void_p]
-    p, q, ws = 0x1000, 0x100000, 0x10000000  # N = 16: 128-byte vectors
-    big = 1 << 20
-    assert f(16, 1, p, q, 0, None, big, None) == -1          # no workspace
-    assert f(16, 1, p, q, 0, ws + 8, big, None) == -1        # not 256-byte aligned
-    assert f(16, 1, p, q, 0, p, big, None) == -1             # overlaps the input
-    assert f(16, 1, p, q, 0, q - 256, big, None) == -1       # overlaps the output
-    assert f(16, 1, p, q, 7, ws, big, None) == -1            # precision
-    assert f(16, 1, None, q, 0, ws, big, None) == -1
-    assert f(16, 1, p, p + 64, 0, ws, big, None) == -1       # output overlaps the input
-    assert f(24, 1, p, q, 0, ws, big, None) == -2            # powers of two only
-    assert f(16, 0, p, q, 0, None, 0, None) == 0             # nothing to do
-
-
-def test_workspace_bytes_rejects_before_device_work(L):
-    f = L.dlt_workspace_bytes
-    f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
-    n = ctypes.c_size_t(0)
-    assert f(24, 1, 0, ctypes.byref(n)) == -2
-    assert f(0, 1, 0, ctypes.byref(n)) == -1
-    assert f(16, -1, 0, ctypes.byref(n)) == -1
-    assert f(16, 1, 5, ctypes.byref(n)) == -1
-    assert f(16, 1, 0, None) == -1
