@@ -525,6 +525,17 @@ def main():
             "value": round(1.0 / per_transform, 6), "unit": "transforms/s", "cores": cores, "kind": "oracle",
             "sample": f"forward DLT at N={N}: {len(idx)} of {N} outputs (Newton nodes + direct recurrence sum, "
                       f"FP64 build) in {dt:.2f} s, extrapolated x{N / len(idx):.0f} to one transform"}
+        # the same oracle on one host core, on a 16x smaller sample
+        oracle.set_threads(1)
+        idx1 = wl.sample_indices(N, max(8, K // 16), 5)
+        t0 = time.perf_counter()
+        th1, _ = oracle.nodes(N, idx=idx1)
+        oracle.dlt(cc, th1)
+        dt1 = time.perf_counter() - t0
+        oracle.set_threads(cores)
+        out["cpu_baseline"]["one_core"] = {
+            "value": round(len(idx1) / (dt1 * N), 7), "unit": "transforms/s", "cores": 1,
+            "sample": f"{len(idx1)} of {N} outputs in {dt1:.2f} s, extrapolated x{N / len(idx1):.0f}"}
         log("cpu baseline", out["cpu_baseline"])
         # end-to-end error of every mode against the FP64 oracle on the same
         # sampled outputs (the oracle with its own nodes), in ||.||_inf/||c||_1
