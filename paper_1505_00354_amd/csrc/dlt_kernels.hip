@@ -546,6 +546,16 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
     if (ntiles & 7) return bid;
     return (bid & 7) * (ntiles >> 3) + (bid >> 3);
 }
+// the same with each XCD's range split into a run from the front and its
+// mirror image from the back (tiles t and ntiles - 1 - t on one XCD): the
+// Taylor pass B stores grid rows 2m and 2m + 1 from the tiles of columns
+// m mod N2 and N2 - 1 - m mod N2, so each output line is then completed in
+// one L2
+__device__ __forceinline__ int xcd_tile_mirror(int bid, int ntiles) {
+    if (ntiles & 15) return xcd_tile(bid, ntiles);
+    const int half = ntiles >> 4, x = bid & 7, k = bid >> 3;
+    return (k < half) ? x * half + k : ntiles - 1 - (x * half + (k - half));
+}
 
 // Pass A: the block owns columns n_a in [na0, na0+colsA) and runs the
 // length-N2 DFTs over n_b (element (col, idx) of the tile is n_a = na0 + col,
@@ -1252,7 +1262,7 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
     }
     const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
-    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int jb0 = xcd_tile_mirror(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const cplx* X0b = X0 + b * x0_stride;
     const cplxT<R>* X1b = X1 + b * x1_stride;
