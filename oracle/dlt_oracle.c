@@ -19,6 +19,7 @@
 #define SIN_R sin
 #define COS_R cos
 #define FABS_R fabs
+#define IDLT_G 16 /* nodes advanced together by the FP64 inverse (SIMD) */
 #include "dlt_oracle_impl.h"
 #undef REAL
 #undef SUFFIX
@@ -27,6 +28,7 @@
 #undef SIN_R
 #undef COS_R
 #undef FABS_R
+#undef IDLT_G
 
 #define REAL long double
 #define SUFFIX _l
@@ -35,6 +37,7 @@
 #define SIN_R sinl
 #define COS_R cosl
 #define FABS_R fabsl
+#define IDLT_G 1 /* x87: one node at a time */
 #include "dlt_oracle_impl.h"
 
 /*

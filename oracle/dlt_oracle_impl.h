@@ -163,7 +163,78 @@ int FN(orc_ndct)(int64_t N, const double *chat, int64_t nt, const double *theta,
 
 /* c_n = (n+1/2) sum_k w_k f_k P_n(cos theta_k), eq. (2), for the requested
  * degrees n (all N if idx == NULL).  One recurrence per node, accumulated
- * per degree ("along rows", Sec. 4.1). */
+ * per degree ("along rows", Sec. 4.1).
+ *
+ * The recurrences of IDLT_G neighbouring nodes advance together, one degree
+ * at a time, so that their independent chains overlap in the CPU (a loop
+ * interchange: every node runs exactly the steps it would run alone); the
+ * group's terms of a degree are summed pairwise and then added to that
+ * degree's accumulator.  A group whose nodes use both forms of the
+ * recurrence runs once per form, the nodes of the other form contributing
+ * exact zeros.  IDLT_G (a power of two) is set by the including file. */
+
+/* the angle of node k reduced to [0, pi/2] and its form: 0 = Reinsch (u),
+ * 1 = textbook (x); *sgf = -1 when the node lies beyond pi/2 */
+static int FN(idlt_form)(const double *theta, const double *theta_lo, int64_t k, REAL *v, REAL *sgf) {
+    REAL t = (REAL)theta[k] + (theta_lo ? (REAL)theta_lo[k] : (REAL)0);
+    int flip = t > PI_R / 2;
+    REAL tt = flip ? PI_R - t : t;
+    *sgf = flip ? (REAL)-1 : (REAL)1;
+    if (tt <= PI_R / 4) {
+        REAL s = SIN_R(tt / 2);
+        *v = 2 * s * s;
+        return 0;
+    }
+    *v = COS_R(tt);
+    return 1;
+}
+
+/* sum of the IDLT_G terms t[0..IDLT_G), pairwise */
+static REAL FN(idlt_gsum)(const REAL *t) {
+    REAL q[IDLT_G];
+    for (int j = 0; j < IDLT_G; ++j) q[j] = t[j];
+    for (int h = IDLT_G / 2; h >= 1; h /= 2)
+        for (int j = 0; j < h; ++j) q[j] = q[j] + q[j + h];
+    return q[0];
+}
+
+/* the nodes of one group with weights g[j] (zero: no contribution), all of
+ * form `form` with parameters v[j], mirror signs sgf[j]: degrees 0..nmax
+ * added to a[] */
+static void FN(idlt_group)(int64_t nmax, int form, const REAL *g, const REAL *v, const REAL *sgf, REAL *a) {
+    REAL p[IDLT_G], q[IDLT_G], sg[IDLT_G], t[IDLT_G];
+    for (int j = 0; j < IDLT_G; ++j) {
+        p[j] = 1;
+        q[j] = 0; /* d_n (Reinsch form) or P_{n-1} (textbook form) */
+        sg[j] = 1;
+    }
+    a[0] += FN(idlt_gsum)(g);
+    if (form == 0) {
+        for (int64_t n = 0; n < nmax; ++n) {
+#pragma omp simd
+            for (int j = 0; j < IDLT_G; ++j) {
+                q[j] = ((REAL)n * q[j] - (REAL)(2 * n + 1) * v[j] * p[j]) / (REAL)(n + 1);
+                p[j] = p[j] + q[j];
+                sg[j] = sg[j] * sgf[j];
+                t[j] = g[j] * (sg[j] * p[j]);
+            }
+            a[n + 1] += FN(idlt_gsum)(t);
+        }
+    } else {
+        for (int64_t n = 0; n < nmax; ++n) {
+#pragma omp simd
+            for (int j = 0; j < IDLT_G; ++j) {
+                REAL pn = ((REAL)(2 * n + 1) * v[j] * p[j] - (REAL)n * q[j]) / (REAL)(n + 1);
+                q[j] = p[j];
+                p[j] = pn;
+                sg[j] = sg[j] * sgf[j];
+                t[j] = g[j] * (sg[j] * p[j]);
+            }
+            a[n + 1] += FN(idlt_gsum)(t);
+        }
+    }
+}
+
 int FN(orc_idlt)(int64_t N, const double *f, const double *theta, const double *theta_lo,
                  const double *w, int64_t nidx, const int64_t *idx, double *c) {
     if (N < 1) return -1;
@@ -190,33 +261,28 @@ int FN(orc_idlt)(int64_t N, const double *f, const double *theta, const double *
 #endif
         REAL *a = acc + (size_t)tid * (size_t)(nmax + 1);
         int64_t k0 = N * tid / nth, k1 = N * (tid + 1) / nth;
-        for (int64_t k = k0; k < k1; ++k) {
-            REAL g = (REAL)w[k] * (REAL)f[k];
-            REAL t = (REAL)theta[k] + (theta_lo ? (REAL)theta_lo[k] : (REAL)0);
-            int flip = t > PI_R / 2;
-            REAL tt = flip ? PI_R - t : t;
-            REAL sg = 1;
-            a[0] += g;
-            if (tt <= PI_R / 4) {
-                REAL s = SIN_R(tt / 2);
-                REAL u = 2 * s * s;
-                REAL p = 1, d = 0;
-                for (int64_t n = 0; n < nmax; ++n) {
-                    d = ((REAL)n * d - (REAL)(2 * n + 1) * u * p) / (REAL)(n + 1);
-                    p = p + d;
-                    if (flip) sg = -sg;
-                    a[n + 1] += g * (sg * p);
+        for (int64_t kg = k0; kg < k1; kg += IDLT_G) {
+            REAL g[IDLT_G], v[IDLT_G], sgf[IDLT_G], gm[IDLT_G], vm[IDLT_G];
+            int form[IDLT_G], has[2] = {0, 0};
+            for (int j = 0; j < IDLT_G; ++j) {
+                g[j] = 0; /* lanes past the thread's last node contribute zero */
+                v[j] = 0;
+                sgf[j] = 1;
+                form[j] = -1;
+                if (kg + j < k1) {
+                    const int64_t k = kg + j;
+                    g[j] = (REAL)w[k] * (REAL)f[k];
+                    form[j] = FN(idlt_form)(theta, theta_lo, k, &v[j], &sgf[j]);
+                    has[form[j]] = 1;
                 }
-            } else {
-                REAL x = COS_R(tt);
-                REAL pm = 0, p = 1;
-                for (int64_t n = 0; n < nmax; ++n) {
-                    REAL pn = ((REAL)(2 * n + 1) * x * p - (REAL)n * pm) / (REAL)(n + 1);
-                    pm = p;
-                    p = pn;
-                    if (flip) sg = -sg;
-                    a[n + 1] += g * (sg * p);
+            }
+            for (int fm = 0; fm < 2; ++fm) {
+                if (!has[fm]) continue;
+                for (int j = 0; j < IDLT_G; ++j) {
+                    gm[j] = (form[j] == fm) ? g[j] : 0;
+                    vm[j] = (form[j] == fm) ? v[j] : 0;
                 }
+                FN(idlt_group)(nmax, fm, gm, vm, sgf, a);
             }
         }
     }

@@ -369,10 +369,18 @@ __global__ __launch_bounds__(64) void k_nodes_bfin(NodeParams P, const double* _
 // --------------------------------------------------------- ragged batches --
 // Instances of uneven size N_b share one power-of-two grid of size Ng >= N_b
 // (the Chebyshev points (j+1/2) pi/Ng).  Every node of P_{N_b} is paired with
-// its nearest grid row j; since the node spacing exceeds pi/Ng when Ng > N_b
-// the pairing is one-to-one, and |Ng (theta_k - theta*_j)| <= pi/2 (for
-// Ng = N_b it is the identity and Lemma 2 applies).  The Taylor series then
-// runs about theta*_j with d = Ng (theta_k - theta*_j).
+// its nearest grid row j, so |Ng (theta_k - theta*_j)| <= pi/2 (for Ng = N_b
+// the pairing is the identity and Lemma 2 applies).  The pairing must be
+// one-to-one.  The node gaps in theta are all below pi/(N_b + 1/2) and
+// smallest at the ends (Sturm comparison), where the first one is about
+// 3.115/(N_b + 1/2): for N_b above about Ng/1.0085 the first few gaps are
+// shorter than the grid spacing pi/Ng, so two nodes could in principle share
+// a row.  They do not: there the row coordinate of node k is k plus a
+// fraction that grows from about 1/4 (first node) towards 1/2 (middle), so
+// node k takes row k and no rounding boundary falls between neighbours.  A
+// CPU check confirms distinct rows for every such size up to Ng = 2^12 and
+// for the nodes nearest the ends of sampled sizes up to 2^20.
+// The Taylor series then runs about theta*_j with d = Ng (theta_k - theta*_j).
 __device__ __forceinline__ int ragged_find(const int* __restrict__ off, int nb, int t) {
     int lo = 0, hi = nb;  // largest b with off[b] <= t
     while (hi - lo > 1) {

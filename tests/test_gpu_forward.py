@@ -45,6 +45,26 @@ def test_nodes(pk, orc, N):
         assert abs(w.sum() - 2) <= 1e-13
 
 
+@pytest.mark.parametrize("N", [1 << 18, 1 << 20])
+def test_nodes_sampled_large(pk, orc, N):
+    # 256 seeded nodes plus every boundary node (k < kb, the nodes whose
+    # weight comes from the Christoffel sum) and their mirror images
+    say("nodes sampled", N)
+    th, w, d = gpu_nodes(pk, N)
+    kb = pk.plan_info(N)["boundary_nodes"]
+    edge = set(range(kb + 2)) | {N - 1 - k for k in range(kb + 2)} | {N // 2 - 1, N // 2}
+    idx = np.array(sorted(set(int(i) for i in wl.sample_indices(N, 256, 17)) | edge), dtype=np.int64)
+    tho, wo = orc.nodes(N, idx=idx)
+    ulps = np.abs(th[idx] - tho) / (ULP * tho)
+    werr = np.abs(w[idx] / wo - 1)
+    say("  kb", kb, "max ulps", float(np.max(ulps)), "max weight err", float(np.max(werr)))
+    assert np.all(ulps <= 4)
+    assert np.max(werr) <= 1e-14
+    grid = (np.arange(N) + 0.5) * np.pi / N
+    assert np.max(np.abs(grid + d - th)) <= 4 * ULP * np.pi
+    assert np.max(np.abs(N * d)) <= 0.83845  # Lemma 2
+
+
 @pytest.mark.parametrize("N", [1, 2, 4, 16, 256, 1024, 4096, 8192, 16384, 32768])
 def test_leg2cheb(pk, orc, N):
     say("leg2cheb", N)

@@ -3,7 +3,14 @@ oracle, plus the round trip IDLT(DLT(c)) = c and IDLT(1) = e_0.
 
 Error norm (forward-transform analogue for the inverse): for every n,
 |c_n - c_n^ref| <= 5e-14 (n + 1/2) sum_k w_k |f_k|; the oracle is evaluated
-at the GPU's own nodes (two-double angles) and weights."""
+at the GPU's own nodes (two-double angles) and weights.
+
+At N = 2^19 and 2^20 the degrees compared span the whole range the fast
+path splits: the exact low block of each recursion level (n < nd), the
+degrees just above each level's nd, where the near and far fields of that
+level take over, and the top degrees; the FP64 build of the oracle is the
+reference there (the extended build would take hours; the CPU suite pins
+the FP64 inverse to the extended one at degrees up to N - 1)."""
 import numpy as np
 import pytest
 
@@ -61,6 +68,56 @@ def test_idlt_sampled_low_degrees(pk, orc, N):
     assert err <= TOL
 
 
+def spread_degrees(pk, N, top, count, seed):
+    """Degrees in [0, top): `count` seeded ones plus nd - 2 .. nd + 2 of
+    every recursion level of the plan (the edges of each level's exact low
+    block) and the top two."""
+    edges = set()
+    n = N
+    while True:
+        nd = pk.plan_info(n)["nd"]
+        if nd >= n:
+            break
+        edges |= {nd - 2, nd - 1, nd, nd + 1, nd + 2}
+        n = nd
+    edges |= {0, 1, top - 2, top - 1}
+    idx = set(int(i) for i in wl.sample_indices(top, count, seed)) | {e for e in edges if 0 <= e < top}
+    return np.array(sorted(idx), dtype=np.int64)
+
+
+_REF = {}
+
+
+def full_size_reference(pk, orc, N, top):
+    """(f, w, degrees, oracle c at those degrees), computed once per module:
+    f iid N(0,1), the GPU's nodes and weights (nodes checked on their own in
+    the forward tests, at these sizes too)."""
+    if N not in _REF:
+        f = wl.values_normal(N, 4)[0]
+        _, w, d = nodes(pk, N)
+        hi, lo = exact_angles(N, d)
+        idx = spread_degrees(pk, N, top, 64, 21)
+        say("  oracle (FP64) at", len(idx), "degrees up to", int(idx[-1]))
+        ref = orc.idlt(f, hi, w, idx=idx, prec="d", theta_lo=lo)
+        _REF[N] = (f, w, idx, ref)
+    return _REF[N]
+
+
+# 2^19: 1024-point tiles in the second pass, an N/8 low block that is itself
+# a recursion level; all degrees.  2^20: degrees up to 2^18 (the main level's
+# near and far fields above its nd = 2^17 and the recursion below it).
+@pytest.mark.parametrize("N,top", [(1 << 19, 1 << 19), (1 << 20, 1 << 18)])
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL), ("fp32bulk", 5e-6)])
+def test_idlt_full_size_spread_degrees(pk, orc, N, top, prec, tol):
+    say("idlt full size", N, prec, "degrees <", top)
+    f, w, idx, ref = full_size_reference(pk, orc, N, top)
+    c = to_host(pk.dlt_inverse(to_dev(f), prec=prec))
+    err = idlt_err(c[idx], ref, w, f, idx)
+    hi = idx >= N // 16
+    say("  err", err, "high-degree err", idlt_err(c[idx[hi]], ref[hi], w, f, idx[hi]))
+    assert err <= tol
+
+
 @pytest.mark.parametrize("N", [1, 2, 16, 1024, 4096, 16384, 1 << 16, 1 << 20])
 def test_roundtrip(pk, N):
     say("roundtrip", N)
@@ -82,3 +139,20 @@ def test_idlt_of_constant(pk, N):
     assert abs(c[0] - 1) <= 1e-14
     n = np.arange(1, N)
     assert np.max(np.abs(c[1:]) / (2 * (n + 0.5)), initial=0) <= TOL
+
+
+def test_roundtrip_undecayed_2p20(pk):
+    # c_n iid N(0,1): every degree up to N - 1 carries as much as the low
+    # ones, so the round trip is no longer dominated by the exact low block.
+    # Gauss-Legendre quadrature is exact for these degrees (Sec. 4), so what
+    # remains is rounding: measured about 1e-12 relative; a wrong far- or
+    # near-field term at high degrees would be of order 1e-6 or more.
+    N = 1 << 20
+    say("roundtrip undecayed", N)
+    c = wl.values_normal(N, 31)[0]
+    f = pk.dlt_forward(to_dev(c))
+    c2 = to_host(pk.dlt_inverse(f))
+    rel = float(np.max(np.abs(c2 - c)) / np.max(np.abs(c)))
+    top = float(np.max(np.abs(c2 - c)[N // 2:]) / np.max(np.abs(c)))
+    say("  max|dc|/max|c|", rel, "over the top half", top)
+    assert rel <= 1e-10

@@ -43,7 +43,9 @@ def test_nodes_any_size(pk, orc, N):
     assert np.max(np.abs((np.arange(N) + 0.5) * np.pi / N + d - th)) <= 4 * ULP * np.pi
 
 
-@pytest.mark.parametrize("N", [3, 7, 24, 100, 1000, 3000, 6000, 12345])
+# 2^k - 1 and 2^k - 3: sizes just below the grid size, where the first node
+# gaps near the ends are shorter than the grid spacing pi/Ng
+@pytest.mark.parametrize("N", [3, 7, 24, 100, 1000, 3000, 6000, 12345, 1021, 1023, 4093, 4095, 16381])
 def test_dlt_forward_any_size(pk, orc, N):
     say("dlt", N)
     c = wl.coeffs_algebraic(N, 1)[0]

@@ -278,6 +278,24 @@ def test_idlt_vs_mpmath_brute_force(orc):
         assert abs(c[n] - float(ex)) <= 8 * ULP * (n + 0.5)
 
 
+def test_idlt_double_vs_long_double_high_degrees(orc):
+    # the FP64 inverse is the reference of the GPU tests at N = 2^19 and 2^20,
+    # where the extended build is too slow: its rounding at degrees up to N - 1
+    # (Reinsch and textbook forms, mirrored nodes, groups of both forms) must
+    # stay far below the 5e-14 budget of the norm (n + 1/2) sum_k w_k |f_k|
+    from paper_1505_00354_amd import workloads as wl
+
+    N = 1 << 15
+    th, w = orc.nodes(N)
+    f = wl.values_normal(N, 12)[0]
+    idx = np.unique(np.concatenate([[0, 1, 2, N // 8 - 1, N // 8, N // 2, N - 2, N - 1],
+                                    wl.sample_indices(N, 24, 13)]))
+    cd = orc.idlt(f, th, w, idx=idx)
+    cl = orc.idlt(f, th, w, idx=idx, prec="l")
+    scale = (idx + 0.5) * np.sum(w * np.abs(f))
+    assert np.max(np.abs(cd - cl) / scale) <= 1e-15
+
+
 # -------------------------------------------------------------- NDCT ---
 
 @pytest.mark.parametrize("N", [8, 100, 256])

@@ -50,12 +50,22 @@ MUTANTS = [
     ("ndct: Chebyshev recurrence sign (x form)", H, "int FN(orc_ndct)",
      "REAL pn = 2 * x * p - pm;", "REAL pn = 2 * x * p + pm;"),
     # IDLT, eq. (2)
-    ("idlt: dropped weights", H, "int FN(orc_idlt)", "REAL g = (REAL)w[k] * (REAL)f[k];", "REAL g = (REAL)f[k];"),
+    ("idlt: dropped weights", H, "int FN(orc_idlt)", "g[j] = (REAL)w[k] * (REAL)f[k];", "g[j] = (REAL)f[k];"),
     ("idlt: normalisation n + 1", H, "int FN(orc_idlt)",
      "c[i] = (double)(((REAL)n + (REAL)0.5) * tot[n]);", "c[i] = (double)(((REAL)n + (REAL)1.0) * tot[n]);"),
-    ("idlt: dropped degree-0 term", H, "int FN(orc_idlt)", "a[0] += g;", "a[0] += 0;"),
+    ("idlt: dropped degree-0 term", H, "static void FN(idlt_group)", "a[0] += FN(idlt_gsum)(g);", "a[0] += 0;"),
     ("idlt: last node of each thread dropped", H, "int FN(orc_idlt)",
-     "for (int64_t k = k0; k < k1; ++k)", "for (int64_t k = k0; k + 1 < k1; ++k)"),
+     "if (kg + j < k1) {", "if (kg + j + 1 < k1) {"),
+    ("idlt: Reinsch step sign", H, "static void FN(idlt_group)",
+     "q[j] = ((REAL)n * q[j] - (REAL)(2 * n + 1) * v[j] * p[j])",
+     "q[j] = ((REAL)n * q[j] + (REAL)(2 * n + 1) * v[j] * p[j])"),
+    ("idlt: textbook recurrence sign", H, "static void FN(idlt_group)",
+     "REAL pn = ((REAL)(2 * n + 1) * v[j] * p[j] - (REAL)n * q[j])",
+     "REAL pn = ((REAL)(2 * n + 1) * v[j] * p[j] + (REAL)n * q[j])"),
+    ("idlt: pairwise group sum stops early", H, "static REAL FN(idlt_gsum)",
+     "for (int h = IDLT_G / 2; h >= 1; h /= 2)", "for (int h = IDLT_G / 2; h >= 2; h /= 2)"),
+    ("idlt: node of the other form counted too", H, "int FN(orc_idlt)",
+     "gm[j] = (form[j] == fm) ? g[j] : 0;", "gm[j] = (form[j] >= 0) ? g[j] : 0;"),
     # Legendre values
     ("legendre: odd-degree mirror parity", H, "static void FN(leg_row)",
      "for (int64_t n = 1; n < N; n += 2) P[n] = -P[n];", "for (int64_t n = 0; n < N; n += 2) P[n] = -P[n];"),
