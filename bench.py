@@ -34,6 +34,7 @@ Prints one JSON line; diagnostics go to stderr.  Options:
                 counters FETCH_SIZE / WRITE_SIZE
 """
 import argparse
+import faulthandler
 import json
 import os
 import sys
@@ -282,6 +283,7 @@ def rooflines(pk, kern, N, B, prec):
 
 
 def main():
+    faulthandler.enable()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)

@@ -43,8 +43,9 @@
  *     call captures its work into a HIP graph (on a library-owned stream)
  *     and it and later such calls launch that graph on `stream`: the same
  *     kernels on the buffers' current contents, the same results.  Calls
- *     made while the kernel trace is on, and the first call, run directly.
- *     dlt_release() frees the graphs.
+ *     made while the kernel trace is on, and the first call, run directly;
+ *     with DLT_CALL_GRAPHS=0 in the environment (read at the first call)
+ *     every call runs directly.  dlt_release() frees the graphs.
  *   - FP64 arithmetic throughout.  Accuracy against the direct O(N^2)
  *     definitions: max_k |f_k - f_k^exact| <= 5e-14 * sum_n |c_n| (DLT, NDCT);
  *     max_n |c_n - c_n^exact| <= 5e-14 * (n+1/2) sum_k w_k |f_k| (IDLT).

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -267,7 +268,6 @@ struct CallWS {
     double* theta;
     double* w;
     double* dth;
-    double* nscr;  // node scratch
     int64_t nb;  // instances per slice
     Lanes lanes;
 };
@@ -277,7 +277,7 @@ int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
     int64_t nb = batch;
     if (per > 0 && (size_t)nb * per > WS_CAP) nb = (int64_t)(WS_CAP / per);
     if (batch > 0 && nb < 1) nb = 1;
-    size_t shared = p.ws_shared + (size_t)64 * NODE_PARTS_MAX * 8 * sizeof(double);
+    size_t shared = p.ws_shared;
     void* base = nullptr;
     int rc = get_ws(s, shared + work_bytes(p, nb), &base);
     if (rc) return rc;
@@ -285,7 +285,6 @@ int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
     cw.theta = (double*)base;
     cw.w = (double*)((char*)base + vecb);
     cw.dth = (double*)((char*)base + 2 * vecb);
-    cw.nscr = (double*)((char*)base + 3 * vecb);
     work_carve(p, nb, (char*)base + shared, cw.work);
     cw.nb = nb;
     return get_lanes(s, &cw.lanes);
@@ -303,12 +302,20 @@ int capture_stream(hipStream_t user, hipStream_t* out);
 // caller's stream with one launch.  A graph is recaptured when the stream's
 // workspace has moved; traced calls always run directly.
 constexpr size_t CALL_GRAPHS_MAX = 256;
+// DLT_CALL_GRAPHS=0 in the environment (read once) runs every call directly
+bool call_graphs_on() {
+    static const bool on = [] {
+        const char* v = std::getenv("DLT_CALL_GRAPHS");
+        return !(v && v[0] == '0' && v[1] == 0);
+    }();
+    return on;
+}
 template <class F>
 int run_call(int op, const Plan& p, int64_t batch, const void* in, void* out, hipStream_t stream, F&& enqueue) {
     CallWS cw;
     int rc = setup_call(p, batch, stream, cw);
     if (rc) return rc;
-    if (trace_on()) return enqueue(cw);
+    if (trace_on() || !call_graphs_on()) return enqueue(cw);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
     void* ws = (void*)cw.theta;  // base of the stream's workspace
@@ -791,7 +798,7 @@ int leg_nodes_weights(int64_t N, int64_t batch, double* theta, double* w, double
         if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
         CallWS cw;
         if ((rc = setup_call(*p, 0, stream, cw))) return rc;
-        if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, cw.nscr, cw.lanes)))) return rc;
+        if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, cw.lanes)))) return rc;
     }
     for (int64_t b = 1; b < batch; ++b) {
         size_t vb = (size_t)N * sizeof(double);
@@ -853,7 +860,7 @@ int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, h
 static int cheb_eval_leggrid_on(Plan& P, int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream) {
     Plan* p = &P;
     return run_call(3, *p, batch, chat, f, stream, [&](CallWS& cw) -> int {
-        int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, cw.lanes));
+        int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.lanes));
         if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
@@ -903,7 +910,7 @@ static int dlt_forward_on(Plan& P, int64_t N, int64_t batch, const double* c, do
         const bool fork = sn != s0;
         if (fork && (hipEventRecord(L.ev[10], s0) != hipSuccess || hipStreamWaitEvent(sn, L.ev[10], 0) != hipSuccess))
             return DLT_ERR_HIP;
-        int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.nscr, L.on(sn)));
+        int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, L.on(sn)));
         if (r) return r;
         if (fork && hipEventRecord(L.ev[11], sn) != hipSuccess) return DLT_ERR_HIP;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
@@ -951,7 +958,7 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
 static int dlt_inverse_on(Plan& P, int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
     Plan* p = &P;
     return run_call(1, *p, batch, f, c, stream, [&](CallWS& cw) -> int {
-        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
+        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.lanes));
         if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
@@ -993,7 +1000,7 @@ int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double
 static int cheb2leg_on(Plan& P, int64_t N, int64_t batch, const double* chat, double* c, hipStream_t stream) {
     Plan* p = &P;
     return run_call(4, *p, batch, chat, c, stream, [&](CallWS& cw) -> int {
-        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
+        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.lanes));
         if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
@@ -1069,7 +1076,7 @@ int chebvals2leg(int64_t N, int64_t batch, const double* v, double* c, hipStream
     // Chebyshev coefficients of the interpolant (workspace), their expansion's
     // values at the Legendre nodes (into c), the inverse transform in place
     return run_call(5, *p, batch, v, c, stream, [&](CallWS& cw) -> int {
-        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.nscr, cw.lanes));
+        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.lanes));
         if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);

@@ -126,14 +126,21 @@ __device__ __forceinline__ void emit_node(int N, int k, double delta, double wk,
     }
 }
 
+// Interior nodes k >= kb, one thread each; with the closed-form boundary
+// nodes (P.closed_b) also the nodes k < kb, from the plan's values.
 __global__ void k_nodes_interior(NodeParams P, double* __restrict__ theta, double* __restrict__ w,
                                  double* __restrict__ dth) {
     const int N = P.N;
     const int nh = (N + 1) / 2;
-    int k = P.kb + blockIdx.x * blockDim.x + threadIdx.x;
+    int k = (P.closed_b ? 0 : P.kb) + blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nh) return;
     double delta, wk;
-    node_interior(P, k, delta, wk);
+    if (k < P.kb) {
+        delta = P.bd[k];
+        wk = P.bw[k];
+    } else {
+        node_interior(P, k, delta, wk);
+    }
     emit_node(N, k, delta, wk, theta, w, dth);
 }
 
@@ -275,97 +282,6 @@ __global__ __launch_bounds__(1024) void k_nodes_boundary(NodeParams P, const dou
     if (threadIdx.x == 0) emit_node(P.N, k, delta, wk, theta, w, dth);
 }
 
-// Boundary nodes for large N (no Newton step: the Bessel-zero start is
-// within an ulp): block (k, part) produces the transfer data of degrees
-// [part*N/P, (part+1)*N/P) at theta_k; k_nodes_bfin chains the P parts.
-constexpr int NODE_PART_THREADS = 256;
-__global__ __launch_bounds__(NODE_PART_THREADS) void k_nodes_bpart(NodeParams P, const double* __restrict__ guess,
-                                                                  int parts, double* __restrict__ scratch) {
-    __shared__ double sh[7 * NODE_PART_THREADS];
-    const int N = P.N;
-    const int k = blockIdx.x, part = blockIdx.y;
-    const double pi = 3.141592653589793;
-    const double t = (k + 0.5) * pi / N + guess[k];
-    const int T = NODE_PART_THREADS, tid = threadIdx.x;
-    const int lo = (int)((int64_t)N * part / parts), hi = (int)((int64_t)N * (part + 1) / parts);
-    double s = sin(0.5 * t);
-    double u = 2.0 * s * s;
-    int C = (hi - lo + T - 1) / T;
-    int n0 = lo + tid * C, n1 = min(hi, n0 + C);
-    double pa = 1, da = 0, pb = 0, db = 1;
-    double saa = 0, sab = 0, sbb = 0;
-    for (int n = n0; n < n1; ++n) {
-        double wgt = 2.0 * n + 1.0;
-        saa = fma(wgt * pa, pa, saa);
-        sab = fma(wgt * pa, pb, sab);
-        sbb = fma(wgt * pb, pb, sbb);
-        double r = recip_np1(n);
-        reinsch_step(u, r, pa, da);
-        reinsch_step(u, r, pb, db);
-    }
-    Xfer x{pa, da, pb, db, saa, sab, sbb};
-    for (int span = 1; span < T; span *= 2) {
-        double* q = sh + 7 * tid;
-        q[0] = x.a; q[1] = x.b; q[2] = x.c; q[3] = x.d; q[4] = x.qaa; q[5] = x.qab; q[6] = x.qbb;
-        __syncthreads();
-        if ((tid & (2 * span - 1)) == 0 && tid + span < T) {
-            const double* r = sh + 7 * (tid + span);
-            Xfer y{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
-            x = xfer_then(x, y);
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        double* o = scratch + ((int64_t)k * parts + part) * 8;
-        o[0] = x.a; o[1] = x.b; o[2] = x.c; o[3] = x.d; o[4] = x.qaa; o[5] = x.qab; o[6] = x.qbb;
-    }
-}
-
-// One wave per boundary node: lane i takes the transfer data of part i
-// (parts <= 64), and a shuffle tree combines them in order (each level joins
-// a run with the run after it).
-__global__ __launch_bounds__(64) void k_nodes_bfin(NodeParams P, const double* __restrict__ guess, int parts,
-                                                   const double* __restrict__ scratch, double* __restrict__ theta,
-                                                   double* __restrict__ w, double* __restrict__ dth) {
-    const int N = P.N;
-    const int k = blockIdx.x;
-    const int lane = threadIdx.x;
-    const double pi = 3.141592653589793;
-    Xfer x{1, 0, 0, 1, 0, 0, 0};
-    if (lane < parts) {
-        const double* o = scratch + ((int64_t)k * parts + lane) * 8;
-        x = Xfer{o[0], o[1], o[2], o[3], o[4], o[5], o[6]};
-    }
-    for (int span = 1; span < 64; span *= 2) {
-        Xfer y;
-        y.a = __shfl_down(x.a, span);
-        y.b = __shfl_down(x.b, span);
-        y.c = __shfl_down(x.c, span);
-        y.d = __shfl_down(x.d, span);
-        y.qaa = __shfl_down(x.qaa, span);
-        y.qab = __shfl_down(x.qab, span);
-        y.qbb = __shfl_down(x.qbb, span);
-        if ((lane & (2 * span - 1)) == 0) x = xfer_then(x, y);
-    }
-    if (lane != 0) return;
-    double delta = guess[k];
-    double th = (k + 0.5) * pi / N + delta;
-    double wk = 2.0 / x.qaa;  // Christoffel number from the true start (1, 0)
-    int k2 = N - 1 - k;
-    if (theta) {
-        theta[k] = th;
-        if (k2 != k) theta[k2] = pi - th;
-    }
-    if (w) {
-        w[k] = wk;
-        if (k2 != k) w[k2] = wk;
-    }
-    if (dth) {
-        dth[k] = delta;
-        if (k2 != k) dth[k2] = -delta;
-    }
-}
-
 // --------------------------------------------------------- ragged batches --
 // Instances of uneven size N_b share one power-of-two grid of size Ng >= N_b
 // (the Chebyshev points (j+1/2) pi/Ng).  Every node of P_{N_b} is paired with
@@ -436,7 +352,12 @@ __global__ __launch_bounds__(256) void k_rnodes_boundary(const RNode* __restrict
     const int b = ragged_find(boff, nb, t);
     const int k = t - boff[b];
     double delta, wk;
-    node_boundary(R[b].P, R[b].guess[k], k, sh, delta, wk);
+    if (R[b].P.closed_b) {  // uniform per block
+        delta = R[b].P.bd[k];
+        wk = R[b].P.bw[k];
+    } else {
+        node_boundary(R[b].P, R[b].guess[k], k, sh, delta, wk);
+    }
     if (threadIdx.x == 0) {
         const int N = R[b].P.N;
         if (gk) map_node(N, Ng, k, delta, wk, gk + (int64_t)b * Ng, dg + (int64_t)b * Ng, wg ? wg + (int64_t)b * Ng : nullptr);
@@ -2199,34 +2120,22 @@ static hipError_t dep(hipStream_t from, hipStream_t to, hipEvent_t e) {
 
 // Boundary nodes (few, recurrence-based) and interior nodes (one thread
 // each) are independent: with side streams they run side by side.
-hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, const Lanes& L) {
+hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, const Lanes& L) {
     trace_n = p.N;
     const NodeParams& P = p.nodes;
     const hipStream_t s = L.s, sb = L.aux(0);
     int nh = (P.N + 1) / 2;
-    int ni = nh - P.kb;
-    if (P.kb > 0) {
+    int ni = P.closed_b ? nh : nh - P.kb;
+    if (P.kb > 0 && !P.closed_b) {
         DLT_TRY(dep(s, sb, L.ev[0]));
-        if (P.newton_b == 0 && P.N >= (1 << 16)) {
-            // about 64 degrees per thread, up to NODE_PARTS_MAX parts per node
-            int parts = P.N / (NODE_PART_THREADS * 64);
-            parts = std::max(1, std::min(parts, NODE_PARTS_MAX));
-            traced("k_nodes_bpart", sb, [&] {
-                launch(k_nodes_bpart, dim3(P.kb, parts), NODE_PART_THREADS, 0, sb, P, p.d_guess, parts, scratch);
-            });
-            traced("k_nodes_bfin", sb, [&] {
-                launch(k_nodes_bfin, P.kb, 64, 0, sb, P, p.d_guess, parts, scratch, theta, w, dth);
-            });
-        } else {
-            int T = 64;
-            while (T < 1024 && T * 256 < P.N) T *= 2;
-            size_t shm = (size_t)7 * T * sizeof(double);
-            traced("k_nodes_boundary", sb, [&] { launch(k_nodes_boundary, P.kb, T, shm, sb, P, p.d_guess, theta, w, dth); });
-        }
+        int T = 64;
+        while (T < 1024 && T * 256 < P.N) T *= 2;
+        size_t shm = (size_t)7 * T * sizeof(double);
+        traced("k_nodes_boundary", sb, [&] { launch(k_nodes_boundary, P.kb, T, shm, sb, P, p.d_guess, theta, w, dth); });
     }
     if (ni > 0)
         traced("k_nodes_interior", s, [&] { launch(k_nodes_interior, (ni + 255) / 256, 256, 0, s, P, theta, w, dth); });
-    if (P.kb > 0) DLT_TRY(dep(sb, s, L.ev[1]));
+    if (P.kb > 0 && !P.closed_b) DLT_TRY(dep(sb, s, L.ev[1]));
     return hipGetLastError();
 }
 

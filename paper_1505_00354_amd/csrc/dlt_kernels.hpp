@@ -61,9 +61,7 @@ size_t work_bytes(const Plan& p, int64_t nb);
 void work_carve(const Plan& p, int64_t nb, void* base, Work& w);
 
 // theta, w, dtheta (any may be null) for the plan's N
-// `scratch` holds kb * NODE_PARTS_MAX * 8 doubles
-constexpr int NODE_PARTS_MAX = 64;
-hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, double* scratch, const Lanes& L);
+hipError_t run_nodes(const Plan& p, double* theta, double* w, double* dth, const Lanes& L);
 // Input-independent plan data formed on the device once per plan (and its
 // sub-plans): the far-field amplitude and row-factor tables and the
 // near-field states at every chunk start.  Synchronous.

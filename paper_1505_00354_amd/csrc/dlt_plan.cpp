@@ -95,6 +95,35 @@ static double bessel_j0_zero(int k) {
     return x;
 }
 
+// Zeros j_{0,k} of J0 (k = 1..8) and J1 at them.
+static const LD BESSEL_J0_ZERO_J1[NODE_CLOSED_KB][2] = {
+    {2.404825557695772768622L, 0.5191474972894667881402L},  {5.520078110286310649597L, -0.3402648065583681485649L},
+    {8.653727912911012216954L, 0.2714522999283819203881L},  {11.79153443901428161374L, -0.232459831364724778856L},
+    {14.93091770848778594776L, 0.2065464330779960268291L},  {18.07106396791092254315L, -0.1877288030404394320809L},
+    {21.21163662987925895908L, 0.1732658942292298697358L},  {24.35247153074930273706L, -0.1617015506892500044539L},
+};
+
+// Boundary nodes in closed form for N >= NODE_CLOSED_MIN.  u = sqrt(sin t)
+// P_N(cos t) solves u'' + (rho^2 + 1/(4 sin^2 t)) u = 0 with rho = N + 1/2,
+// and 1/(4 sin^2 t) = 1/(4 t^2) + 1/12 + t^2/60 + ...; dropping the t^2/60
+// term leaves Bessel's equation of order 0 in rho' t, rho'^2 = rho^2 + 1/12,
+// whose solution regular at 0 with P_N(1) = 1 is sqrt(t) J0(rho' t).  So
+// P_N(cos t) = sqrt(t / sin t) J0(rho' t) up to a relative change of order
+// t^3 / rho' from the dropped term, below 1e-17 for the first eight nodes
+// once N >= 8192: theta_k = j_{0,k+1} / rho' and
+// w_k = 2 / (dP_N/dt)^2 = 2 sin(theta_k) / (theta_k rho'^2 J1(j_{0,k+1})^2).
+constexpr int64_t NODE_CLOSED_MIN = 8192;
+static void closed_boundary_nodes(int64_t N, NodeParams& P) {
+    const LD rho2 = ((LD)N + 0.5L) * ((LD)N + 0.5L) + 1.0L / 12;
+    const LD rho = sqrtl(rho2);
+    for (int k = 0; k < P.kb; ++k) {
+        const LD j = BESSEL_J0_ZERO_J1[k][0], J1 = BESSEL_J0_ZERO_J1[k][1];
+        const LD t = j / rho;
+        P.bd[k] = (double)(t - ((LD)k + 0.5L) * PI_L / (LD)N);
+        P.bw[k] = (double)(2 * sinl(t) / (t * rho2 * J1 * J1));
+    }
+}
+
 void rnode_build(int64_t N, RNode& r) {
     memset(&r, 0, sizeof(r));
     NodeParams& ndp = r.P;
@@ -121,6 +150,11 @@ void rnode_build(int64_t N, RNode& r) {
             th = ((LD)k + 0.75L) * PI_L / nu;
         }
         r.guess[k] = (double)(th - ((LD)k + 0.5L) * PI_L / (LD)N);
+    }
+    if (N >= NODE_CLOSED_MIN && ndp.kb <= NODE_CLOSED_KB) {
+        ndp.closed_b = 1;
+        closed_boundary_nodes(N, ndp);
+        for (int k = 0; k < ndp.kb; ++k) r.guess[k] = ndp.bd[k];
     }
 }
 

@@ -67,10 +67,14 @@ struct NearParams {
     Seg seg[MAX_SEGS];
 };
 
+constexpr int NODE_CLOSED_KB = 8;  // boundary nodes the closed form may cover
 struct NodeParams {
     int N, kb, Ms, newton_b;   // boundary nodes k < kb use the recurrence
+    int closed_b;              // 1: boundary nodes k < kb from the closed form (bd, bw)
     double C;                  // C_N of the Stieltjes series
     double h[MAX_NODE_M];      // h_{m,N}
+    double bd[NODE_CLOSED_KB]; // closed form: theta_k - (k+1/2) pi/N
+    double bw[NODE_CLOSED_KB]; // closed form: w_k
 };
 
 // Node parameters of one instance of a ragged batch: its NodeParams and the
