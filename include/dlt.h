@@ -68,6 +68,7 @@ extern "C" {
 #define DLT_ERR_UNSUPPORTED (-2) /* N > DLT_MAX_N (plan queries: N not a power of two) */
 #define DLT_ERR_HIP (-3)         /* a HIP runtime call or kernel launch failed */
 #define DLT_ERR_NOMEM (-4)       /* device workspace or plan tables could not be allocated */
+#define DLT_ERR_NOT_PREPARED (-5) /* dlt_forward_noalloc: the size's plan has not been built */
 
 #define DLT_MAX_N (1LL << 20)
 
@@ -204,6 +205,25 @@ int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double
  * the device and drops the cached ones. */
 int dlt_batch_ex(int64_t count, const int64_t* Ns, const int64_t* offsets, const int8_t* inverse,
                  const double* in, double* out, int prec, hipStream_t stream);
+
+/* dlt_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * The same transform and kernels as dlt_forward (the same bits), but the call
+ * allocates nothing: every buffer beyond c and f lives in one static device
+ * array of the library (32 MiB per GPU, held until the process ends), it
+ * creates no stream, event or graph and never synchronises; all kernels run
+ * in order on `stream`, so the call may be captured into the caller's graph.
+ *   N      a power of two, 1 <= N <= 65536 (DLT_ERR_UNSUPPORTED otherwise)
+ *   c, f   device arrays of N*batch doubles, as for dlt_forward; batches
+ *          larger than the scratch holds run in slices inside the call
+ * The plan of size N must exist beforehand: any FP64 call of size N (for
+ * example dlt_forward, or dlt_plan_query(N, ...)) builds it, and that call
+ * may allocate; otherwise DLT_ERR_NOT_PREPARED.  Every call on one GPU uses
+ * that GPU's one scratch array: calls that may overlap in time on that GPU
+ * (different streams with no ordering between them) race and give wrong
+ * results; order them on one stream.  The kernel trace does not record these
+ * calls. */
+int dlt_forward_noalloc(int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream);
 
 /* Human-readable text of a status code (static storage). */
 const char* dlt_status_string(int status);

@@ -19,6 +19,7 @@ DLT_ERR_INVALID_ARG = -1
 DLT_ERR_UNSUPPORTED = -2
 DLT_ERR_HIP = -3
 DLT_ERR_NOMEM = -4
+DLT_ERR_NOT_PREPARED = -5
 DLT_MAX_N = 1 << 20
 DLT_PREC_FP64 = 0
 DLT_PREC_FP32_BULK = 1
@@ -66,6 +67,8 @@ def lib():
         L.dlt_plan_query_ex.restype = ctypes.c_int
         L.dlt_plan_query_tol.argtypes = [i64, ctypes.c_double, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         L.dlt_plan_query_tol.restype = ctypes.c_int
+        L.dlt_forward_noalloc.argtypes = [i64, i64, vp, vp, vp]
+        L.dlt_forward_noalloc.restype = ctypes.c_int
         L.dlt_batch_ex.argtypes = [i64, vp, vp, vp, vp, vp, ctypes.c_int, vp]
         L.dlt_batch_ex.restype = ctypes.c_int
         L.dlt_status_string.argtypes = [ctypes.c_int]
@@ -162,6 +165,19 @@ def dlt_forward(c, out=None, prec="fp64", tol=None):
     parameters chosen for eps = tol, 5e-14 <= tol <= 0.1; the other entry
     points take it too)."""
     return _unary("dlt_forward", c, out, prec, tol)
+
+
+def dlt_forward_noalloc(c, out=None):
+    """dlt_forward (FP64) on the library's static scratch: allocates nothing
+    (N a power of two <= 65536; the plan of size N must have been built by an
+    earlier call of that size)."""
+    import torch
+
+    N, batch, out = _vec_args(c, out)
+    with torch.cuda.device(c.device):
+        _check(lib().dlt_forward_noalloc(N, batch, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                         _stream(c.device)), "dlt_forward_noalloc")
+    return out
 
 
 def dlt_inverse(f, out=None, prec="fp64", tol=None):

@@ -155,6 +155,16 @@ int get_plan(int64_t N, int prec, Plan** out) {
     return DLT_OK;
 }
 
+// the plan of (current device, N, prec) if it has been built, else null
+Plan* find_plan(int64_t N, int prec) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.plans.find(std::make_tuple(dev, N, prec));
+    return it == c.plans.end() ? nullptr : it->second.get();
+}
+
 // Working tolerances: the steps 1, 2, 5 x 10^e from TOL_MIN to TOL_MAX; a
 // requested eps is served by the largest step not above it (its accuracy is
 // then at least the requested one).
@@ -670,6 +680,31 @@ int check_any_size(int64_t N, int64_t batch) {
     return DLT_OK;
 }
 
+// ------------------------------------------------ allocation-free forward --
+// Device scratch of dlt_forward_noalloc: one array per GPU, held until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address (per device) comes from hipGetSymbolAddress.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+constexpr int64_t NOALLOC_MAX_N = int64_t(1) << 16;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// the current device's address of `scratch` (looked up once per device)
+int scratch_address(void** out) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DLT_ERR_HIP;
+        it = addr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return DLT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -775,6 +810,7 @@ const char* dlt_status_string(int st) {
         case DLT_ERR_UNSUPPORTED: return "unsupported size";
         case DLT_ERR_HIP: return "HIP runtime error";
         case DLT_ERR_NOMEM: return "out of device memory";
+        case DLT_ERR_NOT_PREPARED: return "plan not prepared (dlt_forward_noalloc: build the size's plan first)";
         default: return "unknown status";
     }
 }
@@ -948,6 +984,42 @@ int dlt_forward_tol(int64_t N, int64_t batch, const double* c, double* f, double
     Plan* p;
     if ((rc = get_plan_tol(N, eps, &p))) return rc;
     return dlt_forward_on(*p, N, batch, c, f, stream);
+}
+
+// dlt_forward with every buffer beyond c and f in the library's static
+// device scratch: no allocation, no side stream, no event, no graph; every
+// kernel on `stream` in order.  The scratch needs no clearing (every pass
+// writes what a later pass reads before it is read).
+int dlt_forward_noalloc(int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream) {
+    int rc = check_any_size(N, batch);
+    if (rc) return rc;
+    if (N > NOALLOC_MAX_N || (N & (N - 1)) != 0) return DLT_ERR_UNSUPPORTED;
+    if (batch == 0) return DLT_OK;
+    if (!c || !f || overlap(c, f, (size_t)N * batch * sizeof(double))) return DLT_ERR_INVALID_ARG;
+    Plan* p = find_plan(N, DLT_PREC_FP64);
+    if (!p) return DLT_ERR_NOT_PREPARED;
+    void* base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    const size_t shared = p->ws_shared;
+    if (shared + p->ws_per_inst > NOALLOC_SCRATCH_BYTES) return DLT_ERR_UNSUPPORTED;
+    const int64_t per_slice =
+        p->ws_per_inst ? (int64_t)((NOALLOC_SCRATCH_BYTES - shared) / p->ws_per_inst) : batch;
+    const int64_t nbmax = std::min<int64_t>(batch, per_slice);
+    const size_t vecb = ((size_t)N * sizeof(double) + 255) & ~size_t(255);
+    double* dth = (double*)((char*)base + 2 * vecb);  // the layout of setup_call
+    Work work;
+    work_carve(*p, nbmax, (char*)base + shared, work);
+    Lanes L;  // the caller's stream only
+    L.s = stream;
+    trace_hold(true);
+    rc = hip_status(run_nodes(*p, nullptr, nullptr, dth, L));
+    for (int64_t b0 = 0; rc == DLT_OK && b0 < batch; b0 += nbmax) {
+        const int64_t nb = std::min(nbmax, batch - b0);
+        rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, work.chat, work.schat, work, L));
+        if (rc == DLT_OK) rc = hip_status(run_ndct(*p, nb, work.chat, work.schat, dth, f + b0 * N, work, L));
+    }
+    trace_hold(false);
+    return rc;
 }
 
 int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {

@@ -1991,13 +1991,15 @@ void trace_set(bool enable) {
 
 // current transform size, appended to trace names ("kernel/N")
 static thread_local int64_t trace_n = 0;
+static thread_local bool trace_held = false;
+void trace_hold(bool hold) { trace_held = hold; }
 
 // runs `fn` (one kernel launch); when tracing, the kernel records a start and
 // an end event of its own
 
 template <class F>
 static void traced(const char* name, hipStream_t s, F&& fn) {
-    if (!trace::on) {
+    if (!trace::on || trace_held) {
         fn();
         return;
     }

@@ -110,6 +110,9 @@ hipError_t run_rscatter(const double* in, int64_t stride, const RNode* R, const 
 // kernel trace (start and end events bound to every traced launch)
 bool trace_on();
 void trace_set(bool enable);
+// while held (this thread), launches are never traced (no trace events are
+// created or recorded)
+void trace_hold(bool hold);
 int trace_collect(std::vector<std::pair<std::string, std::pair<double, int64_t>>>& out);
 
 }  // namespace dlt

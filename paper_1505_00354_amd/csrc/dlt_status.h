@@ -5,3 +5,4 @@
 #define DLT_ERR_UNSUPPORTED (-2)
 #define DLT_ERR_HIP (-3)
 #define DLT_ERR_NOMEM (-4)
+#define DLT_ERR_NOT_PREPARED (-5)

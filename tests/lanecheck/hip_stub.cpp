@@ -110,6 +110,9 @@ struct State {
     int call_first_node = 0;
     long n_launch = 0, n_capture = 0, n_graph_launch = 0, n_record = 0, n_wait = 0;
     long n_side_to_side = 0;  // captured waits of one side stream on another's record
+    long n_alloc = 0, n_free = 0, n_stream_create = 0, n_event_create = 0, n_sync = 0;
+    std::map<const void*, size_t> vars;        // registered device variables: size
+    std::map<const void*, void*> var_addr;     // their stand-in device addresses
 };
 
 State& st() {
@@ -179,6 +182,7 @@ bool reaches(int a, int b) {
 }
 
 void sync_point(const char* what, int s) {
+    ++st().n_sync;
     const int ac = active_capture();
     if (ac && (s < 0 || st().streams[s].capture == ac))
         violate("sync-in-capture: %s during capture %d", what, ac);
@@ -216,6 +220,16 @@ int stub_call_end(hipStream_t user) {
     }
     return bad;
 }
+// resource counters: allocations, frees, streams and events created,
+// synchronising calls
+void stub_resource_counts(long* out) {
+    State& S = st();
+    out[0] = S.n_alloc;
+    out[1] = S.n_free;
+    out[2] = S.n_stream_create;
+    out[3] = S.n_event_create;
+    out[4] = S.n_sync;
+}
 // counters: launches, captures, graph launches, event records, waits, and
 // waits inside a capture of one side stream on an event recorded on another
 // (not an error; a topology that is not a plain fork from and join to the
@@ -236,6 +250,20 @@ void** __hipRegisterFatBinary(const void*) {
     return &mod;
 }
 void __hipUnregisterFatBinary(void**) {}
+void __hipRegisterVar(void**, void* var, char*, char*, int, size_t size, int, int) { st().vars[var] = size; }
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+    State& S = st();
+    auto it = S.vars.find(symbol);
+    if (!p || it == S.vars.end()) return hipErrorInvalidSymbol;
+    auto a = S.var_addr.find(symbol);
+    if (a == S.var_addr.end()) {
+        void* q = mmap(nullptr, it->second, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1, 0);
+        if (q == MAP_FAILED) return hipErrorOutOfMemory;
+        a = S.var_addr.emplace(symbol, q).first;
+    }
+    *p = a->second;
+    return hipSuccess;
+}
 void __hipRegisterFunction(void**, const void* hostFunction, char*, const char* deviceName, unsigned int, uint3*,
                            uint3*, dim3*, dim3*, int*) {
     st().kernels[hostFunction] = deviceName ? deviceName : "?";
@@ -284,6 +312,7 @@ hipError_t hipGetDevice(int* d) {
 // ---------------------------------------------------------------- memory --
 hipError_t hipMalloc(void** p, size_t bytes) {
     if (!p) return hipErrorInvalidValue;
+    ++st().n_alloc;
     size_t n = bytes ? bytes : 1;
     void* q = mmap(nullptr, n, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1, 0);
     if (q == MAP_FAILED) return hipErrorOutOfMemory;
@@ -293,6 +322,7 @@ hipError_t hipMalloc(void** p, size_t bytes) {
 }
 hipError_t hipFree(void* p) {
     if (!p) return hipSuccess;
+    ++st().n_free;
     sync_point("hipFree", -1);
     auto it = st().allocs.find(p);
     if (it == st().allocs.end()) {
@@ -320,6 +350,7 @@ hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKin
 
 // ------------------------------------------------------- streams, events --
 hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned int) {
+    ++st().n_stream_create;
     const int id = st().next_id++;
     st().streams[id] = Stream();
     *s = make_handle<hipStream_t>(id);
@@ -340,6 +371,7 @@ hipError_t hipDeviceSynchronize() {
     return hipSuccess;
 }
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) {
+    ++st().n_event_create;
     const int id = st().next_id++;
     st().events[id] = Event();
     *e = make_handle<hipEvent_t>(id);

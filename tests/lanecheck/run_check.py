@@ -142,6 +142,32 @@ def main(argv):
             calls.append("dlt_batch_ex distinct descriptors")
             if rc:
                 errors.append(f"dlt_batch_ex distinct descriptor {i}: status {rc}")
+    # the allocation-free forward: once its size's plan exists, no allocation,
+    # free, stream, event, synchronisation, capture, record or wait at all
+    L.dlt_forward_noalloc.argtypes = [i64, i64, vp, vp, vp]
+    res0, res1 = (ctypes.c_long * 5)(), (ctypes.c_long * 5)()
+    cnt0, cnt1 = (ctypes.c_long * 6)(), (ctypes.c_long * 6)()
+    noalloc = {}
+    for N, batch in ((1 << 16, 3), (4096, 500), (1024, 2), (1, 4)):
+        unary("dlt_forward", N, 1)  # builds the plan
+        x, y = buf("in", N * batch), buf("out", N * batch)
+        stub.stub_resource_counts(res0)
+        stub.stub_counts(cnt0)
+        for s in streams:
+            for rep in range(2):
+                stub.stub_call_begin()
+                rc = L.dlt_forward_noalloc(N, batch, x, y, s)
+                stub.stub_call_end(s)
+                calls.append(f"dlt_forward_noalloc N={N} b={batch}")
+                if rc:
+                    errors.append(f"dlt_forward_noalloc N={N} b={batch}: status {rc}")
+        stub.stub_resource_counts(res1)
+        stub.stub_counts(cnt1)
+        noalloc[f"{N}x{batch}"] = {
+            "resources": [res1[i] - res0[i] for i in range(5)],
+            "launches": cnt1[0] - cnt0[0],
+            "captures_graphs_records_waits": [cnt1[i] - cnt0[i] for i in (1, 2, 3, 4)],
+        }
     # the kernel trace: every kernel on the caller's stream
     L.dlt_trace_enable.argtypes = [ctypes.c_int]
     L.dlt_trace_enable(1)
@@ -158,7 +184,7 @@ def main(argv):
         "calls": len(calls),
         "launches": counts[0], "captures": counts[1], "graph_launches": counts[2],
         "event_records": counts[3], "event_waits": counts[4], "side_to_side_waits": counts[5],
-        "errors": errors, "violations": viol[:50], "violation_count": len(viol),
+        "errors": errors, "violations": viol[:50], "violation_count": len(viol), "noalloc": noalloc,
     }))
 
 

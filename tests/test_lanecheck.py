@@ -79,3 +79,10 @@ def test_library_stream_orderings(built):
     assert out["calls"] > 3000 and out["launches"] > 10000
     assert out["captures"] > 1000 and out["graph_launches"] > 1500
     assert out["event_waits"] > 1000
+    # the allocation-free forward allocates, frees, creates and synchronises
+    # nothing, and neither captures nor records nor waits on events
+    assert len(out["noalloc"]) == 4
+    for case, r in out["noalloc"].items():
+        assert r["launches"] > 0, case
+        assert r["resources"] == [0, 0, 0, 0, 0], case
+        assert r["captures_graphs_records_waits"] == [0, 0, 0, 0], case
