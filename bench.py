@@ -137,8 +137,9 @@ def stored_traffic(kernel):
     return rows[kernel]
 
 
-def ragged_runs(pk, wl, torch, np, dev, with_oracle=True):
-    """The two ragged-batch workloads; see --no-ragged."""
+def ragged_runs(pk, wl, torch, np, dev, checks=None):
+    """The two ragged-batch workloads; see --no-ragged.  Error checks
+    against the oracle are appended to `checks` (run later, in the CPU leg)."""
     res = {}
 
     def timed_calls(fn, reps):
@@ -200,31 +201,41 @@ def ragged_runs(pk, wl, torch, np, dev, with_oracle=True):
              "gbytes_in_out": round(2 * 8 * int(sizes.sum()) / 1e9, 2), "first_call_s": round(setup_s, 2),
              "inputs": "sizes round(exp(U[ln 256, ln 2^18])) seed 7; odd instances inverse (values N(0,1)); "
                        "10% of forward instances c_n = 0.99^n N(0,1), others N(0,1)/(n+1); values seed 9"}
-    if with_oracle:
-        import oracle
-
+    if checks is not None:
         yh = y.cpu().numpy()
-        errs = {}
-        for octave in range(8, 18):
-            lo, hi = 1 << octave, 1 << (octave + 1)
-            members = [i for i in range(cnt) if lo <= sizes[i] < hi]
-            worst = 0.0
-            for i in members[:2] + [i for i in members if inv[i]][:1]:
-                n, o = int(sizes[i]), int(offs[i])
-                xi, yi = xh[o:o + n], yh[o:o + n]
-                th, w, d = (t.cpu().numpy()[0] for t in pk.leg_nodes_weights(n))
-                if inv[i]:
-                    idx = np.arange(min(n, 64))
-                    ref = oracle.idlt(xi, th, w, idx=idx)
-                    err = np.max(np.abs(yi[idx] - ref) / ((idx + 0.5) * np.sum(w * np.abs(xi))))
-                else:
-                    idx = wl.sample_indices(n, 64, 10 + i)
-                    ref = oracle.dlt(xi, th[idx])
-                    err = np.max(np.abs(yi[idx] - ref)) / np.sum(np.abs(xi))
-                worst = max(worst, float(err))
-            errs[f"[2^{octave}, 2^{octave + 1})"] = worst
-        entry["max_error_vs_oracle_by_octave"] = errs
-        entry["error_budget"] = 5e-6
+
+        def check(entry=entry, yh=yh, xh=xh, sizes=sizes, offs=offs, inv=inv):
+            import oracle
+
+            errs = {}
+            for octave in range(8, 18):
+                lo, hi = 1 << octave, 1 << (octave + 1)
+                fwd = [i for i in range(cnt) if lo <= sizes[i] < hi and not inv[i]]
+                bwd = [i for i in range(cnt) if lo <= sizes[i] < hi and inv[i]]
+                worst = {"forward": 0.0, "inverse": 0.0}
+                # two forward instances on 64 sampled outputs; one inverse
+                # instance on 64 degrees spread over [0, N), both ends included
+                for i in fwd[:2] + bwd[:1]:
+                    n, o = int(sizes[i]), int(offs[i])
+                    xi, yi = xh[o:o + n], yh[o:o + n]
+                    th, w, d = (t.cpu().numpy()[0] for t in pk.leg_nodes_weights(n))
+                    if inv[i]:
+                        idx = np.unique(np.concatenate([wl.sample_indices(n, 62, 20 + i), [0, n - 1]]))
+                        ref = oracle.idlt(xi, th, w, idx=idx)
+                        err = np.max(np.abs(yi[idx] - ref) / ((idx + 0.5) * np.sum(w * np.abs(xi))))
+                        worst["inverse"] = max(worst["inverse"], float(err))
+                    else:
+                        idx = wl.sample_indices(n, 64, 10 + i)
+                        ref = oracle.dlt(xi, th[idx])
+                        err = np.max(np.abs(yi[idx] - ref)) / np.sum(np.abs(xi))
+                        worst["forward"] = max(worst["forward"], float(err))
+                errs[f"[2^{octave}, 2^{octave + 1})"] = worst
+            entry["max_error_vs_oracle_by_octave"] = errs
+            entry["error_budget"] = 5e-6
+            entry["error_check"] = ("per octave of N: two forward instances on 64 sampled outputs, one inverse "
+                                    "instance on 64 degrees spread over [0, N); the oracle at the GPU's nodes")
+
+        checks.append(check)
     res["fp32bulk_16384_sizes_256_262144_mixed"] = entry
     log("ragged fp32bulk 16384:", {k: v for k, v in entry.items() if k != "max_error_vs_oracle_by_octave"})
     del x, y
@@ -282,6 +293,42 @@ def rooflines(pk, kern, N, B, prec):
     return roof, per_kernel, dominant
 
 
+def step_bytes(pk, kern, steps, N, B, prec):
+    """Algorithmic HBM bytes of one step from a kernel trace of `steps`
+    steps at size N, batch B: each modelled HBM-bound kernel's bytes per
+    instance and launch, times the instances a launch covers (B / slices,
+    as in rooflines()), times its launches per step.  Kernels without a byte
+    model (nodes, dense and near-field blocks, reductions) add nothing."""
+    infos = {}
+
+    def info(n):
+        if n not in infos:
+            infos[n] = pk.plan_info(n, prec)
+        return infos[n]
+
+    per_inst = max(1, info(N)["ws_bytes"])
+    nb = max(1, min(B, info(N)["ws_cap"] // per_inst))
+    inst_per_launch = B / -(-B // nb)
+    tot = 0.0
+    for key, (ms, cnt) in kern.items():
+        name, n = key.split("/")
+        n = int(n)
+        m = kernel_model(name.replace("_f32", ""), n, info(n), f32=name.endswith("_f32"), bulk=(prec == "fp32bulk"))
+        if m is not None and m[0] == "hbm":
+            tot += m[1] * inst_per_launch * cnt / steps
+    return tot
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def main():
     faulthandler.enable()
     ap = argparse.ArgumentParser()
@@ -290,7 +337,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--batch", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32bulk", "fp64relaxed"])
@@ -321,14 +368,28 @@ def main():
     N, B = args.n, args.batch
     pk.lib()
     prec = args.prec
-    info = pk.plan_info(N, prec)
-    log("plan", prec, info)
     c = torch.from_numpy(wl.coeffs_algebraic(N, 2, batch=B)).to(dev)
     fin = torch.from_numpy(wl.values_normal(N, 4, batch=B)).to(dev)
     chat = torch.from_numpy(wl.coeffs_algebraic(N, 3, batch=B)).to(dev)
     f = torch.empty_like(c)
     c2 = torch.empty_like(c)
     g = torch.empty_like(c)
+    checks = []  # error checks against the oracle, run in the CPU leg
+
+    # first calls of a fresh process: the forward call builds the size's plan
+    # (tables formed on the device, synchronous) and the stream's workspace
+    first = {}
+    torch.cuda.synchronize()
+    for name, fn in (("dlt_forward", lambda: pk.dlt_forward(c, out=f, prec=prec)),
+                     ("dlt_inverse", lambda: pk.dlt_inverse(fin, out=c2, prec=prec)),
+                     ("cheb_eval_leggrid", lambda: pk.cheb_eval_leggrid(chat, out=g, prec=prec))):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        first[name] = round(1000 * (time.perf_counter() - t0), 3)
+    log("first calls (ms, host wall clock)", first)
+    info = pk.plan_info(N, prec)
+    log("plan", prec, info)
 
     def step(mode=prec, c=c, fin=fin, chat=chat, f=f, c2=c2, g=g):
         pk.dlt_forward(c, out=f, prec=mode)
@@ -404,6 +465,33 @@ def main():
     roof, per_kernel, dominant = rooflines(pk, kern, N, B, prec)
     if roof is not None and B == 1:
         roof["traffic"] = stored_traffic(dominant)
+    sb = step_bytes(pk, kern, args.steps, N, B, prec)
+    step_hbm = {"algorithmic_bytes_per_step": int(sb), "achieved": round(sb / ms_step / 1e6, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(sb / ms_step / 1e6 / HBM_PEAK_GBS, 4),
+                "note": "byte model of the FFT passes only (nodes, dense and near blocks add none), over the "
+                        "untraced step time"}
+    log("step-level HBM", step_hbm)
+
+    # each transform of the step alone, K calls back to back
+    def timed_fn(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    per_transform = {}
+    for name, fn in (("dlt_forward", lambda: pk.dlt_forward(c, out=f, prec=prec)),
+                     ("dlt_inverse", lambda: pk.dlt_inverse(fin, out=c2, prec=prec)),
+                     ("cheb_eval_leggrid", lambda: pk.cheb_eval_leggrid(chat, out=g, prec=prec))):
+        ms1 = timed_fn(fn, args.steps)
+        per_transform[name] = {"ms": round(ms1, 5), "transforms_per_s": round(B * 1000.0 / ms1, 2),
+                               "first_call_ms": first[name]}
+    log("per transform", per_transform)
 
     out = {
         "metric": "DLT transforms/s + HBM GB/s at N=2^16..2^20, plain FP64 vs batched/FP32-bulk",
@@ -425,6 +513,8 @@ def main():
                    "inputs": "c_n=N(0,1)/(n+1) seed 2; IDLT f_k=N(0,1) seed 4; chat_n=N(0,1)/(n+1) seed 3"},
         "dominant_kernel": dominant,
         "roofline": roof,
+        "step_hbm": step_hbm,
+        "per_transform": per_transform,
         "roofline_by_kernel": per_kernel,
         "kernel_us": {k: round(v[0] / v[1] * 1000, 2) for k, v in kern.items()},
     }
@@ -468,16 +558,48 @@ def main():
                     bstep()
                 torch.cuda.synchronize()
                 pk.trace_enable(False)
-                broof, bper, _ = rooflines(pk, pk.trace_collect(), N, BB, m)
+                bk = pk.trace_collect()
+                broof, bper, _ = rooflines(pk, bk, N, BB, m)
+                bsb = step_bytes(pk, bk, 3, N, BB, m)
                 top = sorted(bper.items(), key=lambda kv: -kv[1]["share_of_step"])[:8]
                 modes[m + "_batch64"] = {"ms_per_step": round(bms, 3), "transforms_per_s": round(2 * BB * 1000.0 / bms, 2),
                                          "step": "forward DLT + inverse DLT of 64 instances (c_n = N(0,1)/(n+1), "
                                                  "seeds 100..163)",
                                          "roofline": broof,
+                                         "step_hbm": {"algorithmic_bytes_per_step": int(bsb),
+                                                      "achieved": round(bsb / bms / 1e6, 2), "unit": "GB/s",
+                                                      "frac": round(bsb / bms / 1e6 / HBM_PEAK_GBS, 4)},
                                          "roofline_by_kernel": {k: {f: v[f] for f in ("frac", "avg_launch_us",
                                                                                       "instances_per_launch")}
                                                                 for k, v in top}}
                 log(f"{m} batch 64: {bms:.3f} ms per forward+inverse; dominant kernel {broof}")
+                # errors: the forward output of four instances on 4096 sampled
+                # outputs against the oracle, and the round trip of all 64
+                fbh, cbh = fb.cpu().numpy().reshape(BB, N), cb2.cpu().numpy().reshape(BB, N)
+                cbin = cb.cpu().numpy().reshape(BB, N)
+                entry = modes[m + "_batch64"]
+                # round trip in the inverse transform's norm: |c2_n - c_n| /
+                # ((n + 1/2) sum_k w_k |f_k|), max over n and the 64 instances
+                wN = pk.leg_nodes_weights(N, theta=False, dtheta=False)[1].cpu().numpy()[0]
+                scale = (np.arange(N) + 0.5)[None, :] * np.sum(wN[None, :] * np.abs(fbh), axis=1, keepdims=True)
+                entry["roundtrip_error"] = float(np.max(np.abs(cbh - cbin) / scale))
+                entry["roundtrip_error_relative"] = float(np.max(np.abs(cbh - cbin)) / np.max(np.abs(cbin)))
+                if not args.no_cpu:
+                    def check(entry=entry, fbh=fbh, cbin=cbin):
+                        import oracle
+
+                        idx = wl.sample_indices(N, 4096, 11)
+                        th, _ = oracle.nodes(N, idx=idx)
+                        worst = 0.0
+                        for i in (0, 21, 42, 63):
+                            ref = oracle.dlt(cbin[i], th)
+                            worst = max(worst, float(np.max(np.abs(fbh[i][idx] - ref)) / np.sum(np.abs(cbin[i]))))
+                        entry["forward_error_vs_oracle"] = worst
+                        entry["error_budget"] = 5e-6
+                        entry["error_check"] = ("instances 0, 21, 42, 63 on 4096 sampled outputs; the oracle with "
+                                                "its own nodes; max |f - f_oracle| / ||c||_1")
+
+                    checks.append(check)
             modes["fp32bulk_batch64"]["speedup_vs_fp64relaxed_equal_accuracy"] = round(
                 modes["fp64relaxed_batch64"]["ms_per_step"] / modes["fp32bulk_batch64"]["ms_per_step"], 3)
             del cb, fb, cb2
@@ -504,12 +626,23 @@ def main():
             hn = torch.from_numpy(wl.coeffs_algebraic(n, 3)).to(dev)
             a1, a2, a3 = torch.empty_like(cn), torch.empty_like(cn), torch.empty_like(cn)
             ms = timed("fp64", args.steps, c=cn, fin=fn_, chat=hn, f=a1, c2=a2, g=a3)
-            sizes[str(n)] = {"ms_per_step": round(ms, 5), "transforms_per_s": round(3000.0 / ms, 2)}
-            log(f"N={n}: {ms:.4f} ms/step")
+            pk.trace_enable(True)
+            for _ in range(3):
+                step("fp64", c=cn, fin=fn_, chat=hn, f=a1, c2=a2, g=a3)
+            torch.cuda.synchronize()
+            pk.trace_enable(False)
+            kn = pk.trace_collect()
+            sbn = step_bytes(pk, kn, 3, n, 1, "fp64")
+            sizes[str(n)] = {"ms_per_step": round(ms, 5), "transforms_per_s": round(3000.0 / ms, 2),
+                             "kernels_per_step": int(round(sum(v[1] for v in kn.values()) / 3)),
+                             "step_hbm": {"algorithmic_bytes_per_step": int(sbn),
+                                          "achieved": round(sbn / ms / 1e6, 2), "unit": "GB/s",
+                                          "frac": round(sbn / ms / 1e6 / HBM_PEAK_GBS, 4)}}
+            log(f"N={n}: {ms:.4f} ms/step", sizes[str(n)])
         out["sizes"] = sizes
 
     if not args.no_ragged and B == 1:
-        out["ragged"] = ragged_runs(pk, wl, torch, np, dev, with_oracle=not args.no_cpu)
+        out["ragged"] = ragged_runs(pk, wl, torch, np, dev, checks=None if args.no_cpu else checks)
 
     if not args.no_cpu:
         import oracle
@@ -538,7 +671,10 @@ def main():
         out["cpu_baseline"]["one_core"] = {
             "value": round(len(idx1) / (dt1 * N), 7), "unit": "transforms/s", "cores": 1,
             "sample": f"{len(idx1)} of {N} outputs in {dt1:.2f} s, extrapolated x{N / len(idx1):.0f}"}
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
         log("cpu baseline", out["cpu_baseline"])
+        for chk in checks:
+            chk()
         # end-to-end error of every mode against the FP64 oracle on the same
         # sampled outputs (the oracle with its own nodes), in ||.||_inf/||c||_1
         if modes:
