@@ -444,6 +444,100 @@ __global__ void k_dense_reduce(int nd, int nchunk, int chunk, const double* __re
     out[b * out_stride + k] = s;
 }
 
+// ---------------------------------------------- batched dense block --
+// The exact low block of the conversion for a batch of instances, as one
+// contraction on the FP64 matrix cores.  Rows k and columns n of M pair up
+// by parity p (k = 2i + p, n = 2j + p), and for each parity
+//   forward:    out[b][2i+p]  = (eps_k/pi) sum_{j >= i} Lam(j-i) Lam(i+j+p) x[b][2j+p]
+//   transposed: out[b][2i+p]  = h_n sum_{j <= i} Lam(i-j) Lam(i+j+p) (eps_k/pi) x[b][2j+p]
+// (h_n = n + 1/2 when `half`, else 1): a Toeplitz-times-Hankel matrix that
+// is the same for every instance, so each block forms its tile of it once
+// (from two LDS windows of Lam) and applies it to DMM_B instances.
+// Block: 4 waves; wave w takes parity w >> 1 and rows i0 + 32 (w & 1) + [0, 32)
+// of tile i0 = DMM_I * blockIdx.x, instances b0 = DMM_B * blockIdx.y + [0, 32).
+// Each wave accumulates a 32 x 32 tile as 2 x 2 v_mfma_f64_16x16x4f64
+// (operand lanes: A row l%16, inner l/16; B column l%16, inner l/16; result
+// lane l, register r -> row l/16 + 4r, column l%16), over chunks of DMM_J
+// inner indices staged in LDS.
+constexpr int DMM_I = 64, DMM_B = 32, DMM_J = 32, DMM_PB = DMM_B + 8;
+typedef double dmm_v4 __attribute__((ext_vector_type(4)));
+
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restrict__ lam, const double* __restrict__ x,
+                                                  int64_t xs, int nb, double* __restrict__ out, int64_t os,
+                                                  int half) {
+    __shared__ double sx[2 * DMM_J][DMM_PB];           // x[b0 + bb][2 j0 + t] at [t][bb]
+    __shared__ double slm[DMM_I + DMM_J];               // Lam(|j - i|) window
+    __shared__ double slp[2][DMM_I + DMM_J];            // Lam(i + j + p) windows
+    const int i0 = blockIdx.x * DMM_I, b0 = blockIdx.y * DMM_B;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int p = w >> 1, iw = i0 + 32 * (w & 1);
+    const int ndp = (nd + 1 - p) >> 1;                 // rows (and columns) of parity p
+    const int ndp0 = (nd + 1) >> 1;
+    const int lr = l & 15, lk = l >> 4;
+    // inner range of the tile: forward j >= i0, transposed j <= i0 + DMM_I - 1
+    const int jlo = TRANS ? 0 : i0;
+    const int jhi = TRANS ? min(ndp0, i0 + DMM_I) : ndp0;
+    dmm_v4 acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[u][t] = dmm_v4{0, 0, 0, 0};
+    for (int j0 = jlo; j0 < jhi; j0 += DMM_J) {
+        __syncthreads();  // the previous chunk's reads are done
+        for (int q = tid; q < 2 * DMM_J * DMM_B; q += 256) {
+            const int bb = q / (2 * DMM_J), t = q % (2 * DMM_J);
+            const int n = 2 * j0 + t, b = b0 + bb;
+            double v = 0.0;
+            if (n < nd && b < nb) {
+                v = x[(int64_t)b * xs + n];
+                if (TRANS) v *= (n == 0) ? 0.3183098861837907 : 0.6366197723675814;  // eps_n / pi
+            }
+            sx[t][bb] = v;
+        }
+        for (int q = tid; q < DMM_I + DMM_J; q += 256) {
+            // forward: j - i = j0 - i0 - (DMM_I - 1) + q; transposed: i - j = i0 - j0 - (DMM_J - 1) + q
+            const int zm = TRANS ? i0 - j0 - (DMM_J - 1) + q : j0 - i0 - (DMM_I - 1) + q;
+            slm[q] = (zm >= 0 && zm < nd) ? lam[zm] : 0.0;
+            const int zp = i0 + j0 + q;
+            slp[0][q] = (zp < nd) ? lam[zp] : 0.0;
+            slp[1][q] = (zp + 1 < nd) ? lam[zp + 1] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int s4 = 0; s4 < DMM_J; s4 += 4) {
+            const int jj = s4 + lk;  // inner index within the chunk
+            double a[2], bv[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int ii = iw - i0 + 16 * u + lr;  // row within the tile
+                const double lm = TRANS ? slm[ii - jj + (DMM_J - 1)] : slm[jj - ii + (DMM_I - 1)];
+                a[u] = lm * slp[p][ii + jj];
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t) bv[t] = sx[2 * jj + p][16 * t + lr];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bv[t], acc[u][t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = iw + 16 * u + lk + 4 * r, b = b0 + 16 * t + lr;
+                if (i < ndp && b < nb) {
+                    const int k = 2 * i + p;
+                    const double sc = TRANS ? (half ? k + 0.5 : 1.0)
+                                            : ((k == 0) ? 0.3183098861837907 : 0.6366197723675814);
+                    out[(int64_t)b * os + k] = sc * acc[u][t][r];
+                }
+            }
+}
+
 // ------------------------------------------------------ FFT pass helpers --
 // Every FFT-carrying kernel: FFT_THREADS threads, and registers capped so that
 // FFT_WAVES waves of it share a SIMD (the LDS tile allows three blocks per CU)
@@ -2106,6 +2200,11 @@ hipError_t plan_prepare(Plan& p) {
     return (e != hipSuccess) ? e : e2;
 }
 
+// The batched dense block pays on the matrix cores once a tile of it is
+// shared by enough instances (a block's 32 instance columns are then mostly
+// live); single instances keep the one-instance kernel.
+static bool dense_mm_pays(int nd, int64_t nb) { return nb >= 8 && nd >= 64; }
+
 // Makes `to` wait for everything enqueued on `from` so far.
 static hipError_t dep(hipStream_t from, hipStream_t to, hipEvent_t e) {
     if (from == to) return hipSuccess;
@@ -2164,6 +2263,11 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
     const hipStream_t sl = last ? s : L.aux(1), sn = L.aux(2);
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
     auto dense_block = [&](hipStream_t st, double* dst, int64_t ds) {
+        if (dense_mm_pays(nd, nb)) {  // one contraction on the matrix cores
+            const dim3 gm((unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I), (unsigned)((nb + DMM_B - 1) / DMM_B));
+            traced("k_dense_mm", st, [&] { launch(k_dense_mm<false>, gm, 256, 0, st, nd, p.d_lam, c, cs, (int)nb, dst, ds, 0); });
+            return;
+        }
         dim3 gd(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb);
         traced("k_dense", st, [&] { launch(k_dense, gd, 256, 0, st, N, nd, p.dense_chunk, p.d_lam, c, cs, w.dense, w.sdense); });
         traced("k_dense_reduce", st, [&] {
@@ -2272,7 +2376,15 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     const hipStream_t sl = last ? s : L.aux(1), sn = L.aux(2);
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
     DLT_TRY(dep(s, sl, L.ev[6]));
-    if (!p.sub) {
+    if (!p.sub && dense_mm_pays(nd, nb)) {  // one contraction on the matrix cores
+        double* dst = last ? out : dense_out;
+        const int64_t ds = last ? os : w.sdense;
+        const dim3 gm((unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I), (unsigned)((nb + DMM_B - 1) / DMM_B));
+        traced("k_dense_mm_t", sl, [&] {
+            launch(k_dense_mm<true>, gm, 256, 0, sl, nd, p.d_lam, y, ys, (int)nb, dst, ds, last ? half : 0);
+        });
+        if (last) return hipGetLastError();
+    } else if (!p.sub) {
         traced("k_dense_t", sl, [&] {
             launch(k_dense_t, dim3(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb), 256, 0, sl, nd, p.dense_chunk, p.d_lam,
                                                                                           y, ys, w.dense, w.sdense);
