@@ -428,7 +428,8 @@ int rdesc_build(const int64_t* Ns, const int64_t* offs, const std::vector<int64_
             R[b] = rnode_of(c, Ns[idx[b]]);
             o[b] = offs[idx[b]];
             const int nh = (int)((Ns[idx[b]] + 1) / 2);
-            io[b + 1] = io[b] + (nh - R[b].P.kb);
+            const int ni = nh - R[b].P.kb;  // rounded up: a wave serves one instance
+            io[b + 1] = io[b] + (ni + RNODE_INTERIOR_ALIGN - 1) / RNODE_INTERIOR_ALIGN * RNODE_INTERIOR_ALIGN;
             bo[b + 1] = bo[b] + R[b].P.kb;
         }
     }

@@ -272,6 +272,45 @@ __device__ void node_boundary(const NodeParams& P, double guess0, int k, double*
     w_out = 2.0 / kc;
 }
 
+// The same for one thread alone (small N): P_N, P_{N-1} and the Christoffel
+// sum by the recurrence in order, Newton steps as above.
+__device__ void node_boundary_thread(const NodeParams& P, double guess0, int k, double& delta_out, double& w_out) {
+    const int N = P.N;
+    const double pi = 3.141592653589793;
+    const double ts = (k + 0.5) * pi / N;
+    auto pair = [&](double t, double& pN, double& pN1, double& kc) {
+        const double sh = sin(0.5 * t);
+        const double u = 2.0 * sh * sh;
+        double Pn = 1, Dn = 0, K = 0, Pm = 1;
+        for (int n = 0; n < N; ++n) {
+            K = fma((2.0 * n + 1.0) * Pn, Pn, K);
+            Pm = Pn;
+            reinsch_step(u, recip_np1(n), Pn, Dn);
+        }
+        pN = Pn;
+        pN1 = Pm;
+        kc = K;
+    };
+    double delta = guess0;
+    double pN, pN1, kc;
+    if ((N & 1) && (k == (N - 1) / 2)) {
+        delta = 0;  // x = 0 is a root of odd-degree P_N and theta*_k = pi/2 there
+    } else {
+        for (int it = 0; it < P.newton_b; ++it) {
+            const double th = ts + delta;
+            pair(th, pN, pN1, kc);
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            const double step = pN / (N * (cs * pN - pN1) / sn);
+            delta -= step;
+            if (fabs(step) <= 2.2e-16 * th) break;
+        }
+    }
+    pair(ts + delta, pN, pN1, kc);
+    delta_out = delta;
+    w_out = 2.0 / kc;
+}
+
 __global__ __launch_bounds__(1024) void k_nodes_boundary(NodeParams P, const double* __restrict__ guess,
                                                         double* __restrict__ theta, double* __restrict__ w,
                                                         double* __restrict__ dth) {
@@ -330,9 +369,12 @@ __global__ void k_rnodes_interior(const RNode* __restrict__ R, const int* __rest
                                   double* __restrict__ theta, double* __restrict__ w, double* __restrict__ dth) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ioff[nb]) return;
-    const int b = ragged_find(ioff, nb, t);
+    // each instance's range starts at a multiple of 64, so a wave serves one
+    // instance and its parameters are read once per wave (scalar loads)
+    const int b = __builtin_amdgcn_readfirstlane(ragged_find(ioff, nb, t));
     const NodeParams& P = R[b].P;
     const int k = P.kb + (t - ioff[b]);
+    if (k >= (P.N + 1) / 2) return;
     double delta, wk;
     node_interior(P, k, delta, wk);
     if (gk) map_node(P.N, Ng, k, delta, wk, gk + (int64_t)b * Ng, dg + (int64_t)b * Ng, wg ? wg + (int64_t)b * Ng : nullptr);
@@ -363,6 +405,27 @@ __global__ __launch_bounds__(256) void k_rnodes_boundary(const RNode* __restrict
         if (gk) map_node(N, Ng, k, delta, wk, gk + (int64_t)b * Ng, dg + (int64_t)b * Ng, wg ? wg + (int64_t)b * Ng : nullptr);
         if (theta || w || dth) emit_node(N, k, delta, wk, theta, w, dth);
     }
+}
+
+// Boundary nodes of every instance of a small grid, one thread each.
+__global__ __launch_bounds__(256) void k_rnodes_bthread(const RNode* __restrict__ R, const int* __restrict__ boff, int nb,
+                                                        int Ng, int* __restrict__ gk, double* __restrict__ dg,
+                                                        double* __restrict__ wg, double* __restrict__ theta,
+                                                        double* __restrict__ w, double* __restrict__ dth) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= boff[nb]) return;
+    const int b = ragged_find(boff, nb, t);
+    const int k = t - boff[b];
+    double delta, wk;
+    if (R[b].P.closed_b) {
+        delta = R[b].P.bd[k];
+        wk = R[b].P.bw[k];
+    } else {
+        node_boundary_thread(R[b].P, R[b].guess[k], k, delta, wk);
+    }
+    const int N = R[b].P.N;
+    if (gk) map_node(N, Ng, k, delta, wk, gk + (int64_t)b * Ng, dg + (int64_t)b * Ng, wg ? wg + (int64_t)b * Ng : nullptr);
+    if (theta || w || dth) emit_node(N, k, delta, wk, theta, w, dth);
 }
 
 __global__ void k_fill_int(int* __restrict__ p, int64_t n, int v) {
@@ -458,34 +521,36 @@ __global__ void k_dense_reduce(int nd, int nchunk, int chunk, const double* __re
 // Each wave accumulates a 32 x 32 tile as 2 x 2 v_mfma_f64_16x16x4f64
 // (operand lanes: A row l%16, inner l/16; B column l%16, inner l/16; result
 // lane l, register r -> row l/16 + 4r, column l%16), over chunks of DMM_J
-// inner indices staged in LDS.
-constexpr int DMM_I = 64, DMM_B = 32, DMM_J = 32, DMM_PB = DMM_B + 8;
+// inner indices staged in LDS; each chunk's global loads are issued into
+// registers while the previous chunk is multiplied.
+constexpr int DMM_I = 64, DMM_B = 32, DMM_J = 64, DMM_PB = DMM_B + 4;
+constexpr int DMM_XPT = 2 * DMM_J * DMM_B / 256;  // x values each thread stages per chunk
+constexpr int DMM_W = DMM_I + DMM_J;              // Lam window length
 typedef double dmm_v4 __attribute__((ext_vector_type(4)));
 
 template <bool TRANS>
 __global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restrict__ lam, const double* __restrict__ x,
                                                   int64_t xs, int nb, double* __restrict__ out, int64_t os,
                                                   int half) {
-    __shared__ double sx[2 * DMM_J][DMM_PB];           // x[b0 + bb][2 j0 + t] at [t][bb]
-    __shared__ double slm[DMM_I + DMM_J];               // Lam(|j - i|) window
-    __shared__ double slp[2][DMM_I + DMM_J];            // Lam(i + j + p) windows
+    __shared__ double sx[2 * DMM_J][DMM_PB];  // x[b0 + bb][2 j0 + t] at [t][bb]
+    __shared__ double slm[DMM_W];             // Lam(|j - i|) window
+    __shared__ double slp[2][DMM_W];          // Lam(i + j + p) windows
     const int i0 = blockIdx.x * DMM_I, b0 = blockIdx.y * DMM_B;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int p = w >> 1, iw = i0 + 32 * (w & 1);
-    const int ndp = (nd + 1 - p) >> 1;                 // rows (and columns) of parity p
+    const int ndp = (nd + 1 - p) >> 1;  // rows (and columns) of parity p
     const int ndp0 = (nd + 1) >> 1;
     const int lr = l & 15, lk = l >> 4;
     // inner range of the tile: forward j >= i0, transposed j <= i0 + DMM_I - 1
     const int jlo = TRANS ? 0 : i0;
     const int jhi = TRANS ? min(ndp0, i0 + DMM_I) : ndp0;
-    dmm_v4 acc[2][2];
+    // chunk data staged through registers: the next chunk's global loads are
+    // issued before the current chunk's products
+    double rx[DMM_XPT], rm = 0, rp0 = 0, rp1 = 0;
+    auto fetch = [&](int j0) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int t = 0; t < 2; ++t) acc[u][t] = dmm_v4{0, 0, 0, 0};
-    for (int j0 = jlo; j0 < jhi; j0 += DMM_J) {
-        __syncthreads();  // the previous chunk's reads are done
-        for (int q = tid; q < 2 * DMM_J * DMM_B; q += 256) {
+        for (int e = 0; e < DMM_XPT; ++e) {
+            const int q = tid + 256 * e;
             const int bb = q / (2 * DMM_J), t = q % (2 * DMM_J);
             const int n = 2 * j0 + t, b = b0 + bb;
             double v = 0.0;
@@ -493,18 +558,41 @@ __global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restri
                 v = x[(int64_t)b * xs + n];
                 if (TRANS) v *= (n == 0) ? 0.3183098861837907 : 0.6366197723675814;  // eps_n / pi
             }
-            sx[t][bb] = v;
+            rx[e] = v;
         }
-        for (int q = tid; q < DMM_I + DMM_J; q += 256) {
+        if (tid < DMM_W) {
             // forward: j - i = j0 - i0 - (DMM_I - 1) + q; transposed: i - j = i0 - j0 - (DMM_J - 1) + q
-            const int zm = TRANS ? i0 - j0 - (DMM_J - 1) + q : j0 - i0 - (DMM_I - 1) + q;
-            slm[q] = (zm >= 0 && zm < nd) ? lam[zm] : 0.0;
-            const int zp = i0 + j0 + q;
-            slp[0][q] = (zp < nd) ? lam[zp] : 0.0;
-            slp[1][q] = (zp + 1 < nd) ? lam[zp + 1] : 0.0;
+            const int zm = TRANS ? i0 - j0 - (DMM_J - 1) + tid : j0 - i0 - (DMM_I - 1) + tid;
+            rm = (zm >= 0 && zm < nd) ? lam[zm] : 0.0;
+            const int zp = i0 + j0 + tid;
+            rp0 = (zp < nd) ? lam[zp] : 0.0;
+            rp1 = (zp + 1 < nd) ? lam[zp + 1] : 0.0;
         }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int e = 0; e < DMM_XPT; ++e) {
+            const int q = tid + 256 * e;
+            sx[q % (2 * DMM_J)][q / (2 * DMM_J)] = rx[e];
+        }
+        if (tid < DMM_W) {
+            slm[tid] = rm;
+            slp[0][tid] = rp0;
+            slp[1][tid] = rp1;
+        }
+    };
+    dmm_v4 acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[u][t] = dmm_v4{0, 0, 0, 0};
+    if (jlo < jhi) fetch(jlo);
+    for (int j0 = jlo; j0 < jhi; j0 += DMM_J) {
+        __syncthreads();  // the previous chunk's reads are done
+        stage();
         __syncthreads();
-#pragma unroll 2
+        if (j0 + DMM_J < jhi) fetch(j0 + DMM_J);
+#pragma unroll 4
         for (int s4 = 0; s4 < DMM_J; s4 += 4) {
             const int jj = s4 + lk;  // inner index within the chunk
             double a[2], bv[2];
@@ -2531,10 +2619,18 @@ hipError_t run_rnodes(const RaggedNodes& rn, int Ng, int* gk, double* dg, double
         const int64_t n = (int64_t)rn.nb * Ng;
         traced("k_fill_int", s, [&] { launch(k_fill_int, (unsigned)((n + 255) / 256), 256, 0, s, gk, n, -1); });
     }
-    if (rn.nbnd_total > 0)
-        traced("k_rnodes_boundary", s, [&] {
-            launch(k_rnodes_boundary, rn.nbnd_total, 256, 0, s, rn.R, rn.boff, rn.nb, Ng, gk, dg, wg, theta, w, dth);
-        });
+    if (rn.nbnd_total > 0) {
+        if (Ng <= RNODE_THREAD_MAX_NG) {  // short recurrences: one thread per node
+            traced("k_rnodes_bthread", s, [&] {
+                launch(k_rnodes_bthread, (rn.nbnd_total + 255) / 256, 256, 0, s, rn.R, rn.boff, rn.nb, Ng, gk, dg, wg,
+                       theta, w, dth);
+            });
+        } else {
+            traced("k_rnodes_boundary", s, [&] {
+                launch(k_rnodes_boundary, rn.nbnd_total, 256, 0, s, rn.R, rn.boff, rn.nb, Ng, gk, dg, wg, theta, w, dth);
+            });
+        }
+    }
     if (rn.ni_total > 0)
         traced("k_rnodes_interior", s, [&] {
             launch(k_rnodes_interior, (rn.ni_total + 255) / 256, 256, 0, s, rn.R, rn.ioff, rn.nb, Ng, gk, dg, wg, theta, w,

@@ -94,6 +94,10 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
 // Ragged batches: node tables on the grid of size Ng for nb instances
 // (R, ioff, boff device arrays; totals of interior and boundary nodes), and
 // the zero-padded gather / scatter between the caller's layout and the grid.
+// grids up to this size compute boundary nodes one thread per node
+constexpr int RNODE_THREAD_MAX_NG = 1024;
+// interior-node ranges of the instances start at multiples of this
+constexpr int RNODE_INTERIOR_ALIGN = 64;
 struct RaggedNodes {
     const RNode* R;
     const int* ioff;
