@@ -199,7 +199,8 @@ int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double
  * per group shape), builds the device descriptors and captures the whole
  * sequence into a HIP graph; it synchronises the device.  Later calls with the
  * same descriptor launch the cached graph on `stream` and do not
- * synchronise.  Graphs, descriptors and their workspaces live until
+ * synchronise; while the kernel trace is on they run its kernels directly
+ * on `stream` instead, each traced.  Graphs, descriptors and their workspaces live until
  * dlt_release(), or until a new descriptor would bring the cached graphs
  * beyond 64 or their workspaces beyond 16 GiB: that call then synchronises
  * the device and drops the cached ones. */

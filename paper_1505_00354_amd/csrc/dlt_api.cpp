@@ -741,11 +741,24 @@ int dlt_batch_ex(int64_t count, const int64_t* Ns, const int64_t* offsets, const
         key.push_back(offsets[i]);
         key.push_back(inverse ? inverse[i] : 0);
     }
+    // a cached batch: its graph, or with the kernel trace on its kernels
+    // directly on `stream` (each traced, none on a side stream)
+    // (called with the cache lock held: the lanes are taken before)
+    const bool traced_run = trace_on();
+    Lanes TL;
+    if (traced_run && (rc = get_lanes(stream, &TL))) return rc;
+    auto launch_entry = [&](BatchEntry* E) -> int {
+        if (!traced_run) return hip_status(hipGraphLaunch(E->exec, stream));
+        int r = DLT_OK;
+        for (auto& S : E->slices)
+            if (r == DLT_OK) r = hip_status(rslice_run(S, in, out, E->ws, TL));
+        return r;
+    };
     {
         Cache& c = cache();
         std::lock_guard<std::mutex> lk(c.mu);
         auto it = c.graphs.find(key);
-        if (it != c.graphs.end()) return hip_status(hipGraphLaunch(it->second->exec, stream));
+        if (it != c.graphs.end()) return launch_entry(it->second.get());
     }
     {
         std::unique_ptr<BatchEntry> e(new BatchEntry());
@@ -798,7 +811,7 @@ int dlt_batch_ex(int64_t count, const int64_t* Ns, const int64_t* offsets, const
         Cache& c = cache();
         std::lock_guard<std::mutex> lk(c.mu);
         BatchEntry* E = c.graphs.emplace(key, std::move(e)).first->second.get();
-        return hip_status(hipGraphLaunch(E->exec, stream));
+        return launch_entry(E);
     }
 }
 

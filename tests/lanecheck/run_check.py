@@ -173,6 +173,9 @@ def main(argv):
     L.dlt_trace_enable(1)
     unary("dlt_forward", 1 << 18, 1)
     unary("dlt_inverse", 1 << 18, 1)
+    # a cached ragged batch runs its kernels directly while traced
+    call(f"dlt_batch_ex traced count={len(Ns)}", L.dlt_batch_ex, len(Ns), vp(Ns.ctypes.data),
+         vp(offs.ctypes.data), vp(inv.ctypes.data), buf("in", tot), buf("out", tot), PREC["fp64"])
     L.dlt_trace_enable(0)
     L.dlt_release()
     unary("dlt_inverse", 1 << 20, 1)

@@ -193,3 +193,22 @@ def test_ragged_graph_cache_bound(pk):
         outs[k].zero_()
         pk.dlt_batch(xd, sizes, base + k, out=outs[k])
         assert np.array_equal(to_host(outs[k]), first[k]), ("rebuilt", k)
+
+
+def test_ragged_traced_run_matches_graph(pk):
+    """With the kernel trace on, a cached batch runs its kernels directly
+    (each traced) instead of its graph: the same bits, and the trace names
+    the batched dense block of the classes of eight or more instances."""
+    sizes, offs, inv, x = ragged_case(300, 64, 9000, 41, mixed=True)
+    say("ragged traced", int(sizes.min()), int(sizes.max()), int(inv.sum()))
+    xd = to_dev(x)
+    ref = to_host(pk.dlt_batch(xd, sizes, offs, inv))
+    ref2 = to_host(pk.dlt_batch(xd, sizes, offs, inv))  # replay
+    pk.trace_enable(True)
+    got = to_host(pk.dlt_batch(xd, sizes, offs, inv))
+    pk.trace_enable(False)
+    kern = pk.trace_collect(128)
+    assert np.array_equal(ref, ref2)
+    assert np.array_equal(got, ref)
+    assert any(k.startswith("k_dense_mm/") for k in kern), sorted(kern)
+    assert any(k.startswith("k_dense_mm_t/") for k in kern), sorted(kern)
