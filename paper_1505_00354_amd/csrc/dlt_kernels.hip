@@ -517,7 +517,7 @@ __global__ void k_dense_reduce(int nd, int nchunk, int chunk, const double* __re
 // is the same for every instance, so each block forms its tile of it once
 // (from two LDS windows of Lam) and applies it to DMM_B instances.
 // Block: 4 waves; wave w takes parity w >> 1 and rows i0 + 32 (w & 1) + [0, 32)
-// of tile i0 = DMM_I * blockIdx.x, instances b0 = DMM_B * blockIdx.y + [0, 32).
+// of tile i0 = DMM_I * blockIdx.y, instances b0 = DMM_B * blockIdx.x + [0, 32).
 // Each wave accumulates a 32 x 32 tile as 2 x 2 v_mfma_f64_16x16x4f64
 // (operand lanes: A row l%16, inner l/16; B column l%16, inner l/16; result
 // lane l, register r -> row l/16 + 4r, column l%16), over chunks of DMM_J
@@ -535,7 +535,9 @@ __global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restri
     __shared__ double sx[2 * DMM_J][DMM_PB];  // x[b0 + bb][2 j0 + t] at [t][bb]
     __shared__ double slm[DMM_W];             // Lam(|j - i|) window
     __shared__ double slp[2][DMM_W];          // Lam(i + j + p) windows
-    const int i0 = blockIdx.x * DMM_I, b0 = blockIdx.y * DMM_B;
+    // blocks are dispatched in x-major order: the instance tiles of one row
+    // tile go together, the longest rows (the first tiles) first
+    const int i0 = blockIdx.y * DMM_I, b0 = blockIdx.x * DMM_B;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int p = w >> 1, iw = i0 + 32 * (w & 1);
     const int ndp = (nd + 1 - p) >> 1;  // rows (and columns) of parity p
@@ -2352,7 +2354,7 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
     auto dense_block = [&](hipStream_t st, double* dst, int64_t ds) {
         if (dense_mm_pays(nd, nb)) {  // one contraction on the matrix cores
-            const dim3 gm((unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I), (unsigned)((nb + DMM_B - 1) / DMM_B));
+            const dim3 gm((unsigned)((nb + DMM_B - 1) / DMM_B), (unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I));
             traced("k_dense_mm", st, [&] { launch(k_dense_mm<false>, gm, 256, 0, st, nd, p.d_lam, c, cs, (int)nb, dst, ds, 0); });
             return;
         }
@@ -2467,7 +2469,7 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     if (!p.sub && dense_mm_pays(nd, nb)) {  // one contraction on the matrix cores
         double* dst = last ? out : dense_out;
         const int64_t ds = last ? os : w.sdense;
-        const dim3 gm((unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I), (unsigned)((nb + DMM_B - 1) / DMM_B));
+        const dim3 gm((unsigned)((nb + DMM_B - 1) / DMM_B), (unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I));
         traced("k_dense_mm_t", sl, [&] {
             launch(k_dense_mm<true>, gm, 256, 0, sl, nd, p.d_lam, y, ys, (int)nb, dst, ds, last ? half : 0);
         });
