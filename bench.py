@@ -19,6 +19,8 @@ Prints one JSON line; diagnostics go to stderr.  Options:
   --prec P      arithmetic of the headline run: fp64 (default), fp32bulk
                 (FP32 bulk transforms, 5e-6 budget) or fp64relaxed (FP64 with
                 the 5e-6 parameters)
+  --ragged-only run only the ragged-batch workloads (no oracle checks) and
+                print their results
   --no-ragged   skip the ragged-batch runs (reported under "ragged": 4096
                 FP64 DLTs of sizes log-uniform in [64, 16384] as one cached
                 graph launch against one call per transform; 16384 FP32-bulk
@@ -292,8 +294,8 @@ def rooflines(pk, kern, N, B, prec):
         return infos[n]
 
     per_inst = max(1, info(N)["ws_bytes"])
-    nb = max(1, min(B, info(N)["ws_cap"] // per_inst))
-    slices = -(-B // nb)
+    nbmax = max(1, min(B, info(N)["ws_cap"] // per_inst))
+    slices = -(-B // nbmax)  # the library splits a batch into equal slices
     inst_per_launch = B / slices
     tot = sum(v[0] for v in kern.values())
     ranked = sorted(kern.items(), key=lambda kv: -kv[1][0])
@@ -341,8 +343,8 @@ def step_bytes(pk, kern, steps, N, B, prec):
         return infos[n]
 
     per_inst = max(1, info(N)["ws_bytes"])
-    nb = max(1, min(B, info(N)["ws_cap"] // per_inst))
-    inst_per_launch = B / -(-B // nb)
+    nbmax = max(1, min(B, info(N)["ws_cap"] // per_inst))
+    inst_per_launch = B / -(-B // nbmax)
     tot = 0.0
     for key, (ms, cnt) in kern.items():
         name, n = key.split("/")
@@ -377,6 +379,7 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32bulk", "fp64relaxed"])
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--ragged-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py: this build runs on a single GPU; --gpus must be 1 "
@@ -402,6 +405,9 @@ def main():
     N, B = args.n, args.batch
     pk.lib()
     prec = args.prec
+    if args.ragged_only:  # the two ragged-batch workloads alone (for profiling them)
+        print(json.dumps({"ragged": ragged_runs(pk, wl, torch, np, dev, checks=None)}), flush=True)
+        return
     c = torch.from_numpy(wl.coeffs_algebraic(N, 2, batch=B)).to(dev)
     fin = torch.from_numpy(wl.values_normal(N, 4, batch=B)).to(dev)
     chat = torch.from_numpy(wl.coeffs_algebraic(N, 3, batch=B)).to(dev)

@@ -237,8 +237,9 @@ const char* dlt_status_string(int status);
  * recurrence steps (rows x degrees, one end), boundary nodes, workspace bytes
  * per instance, near-field steps that carry weights (rows x degrees >= nd),
  * pass-A term groups, and the per-stream workspace bound in bytes (a batch
- * whose workspace, instances x bytes per instance, exceeds it runs in slices
- * of floor(bound / bytes per instance) instances).  Returns the number of
+ * whose workspace, instances x bytes per instance, exceeds it runs in the
+ * fewest slices of at most floor(bound / bytes per instance) instances, of
+ * equal size up to one instance).  Returns the number of
  * fields available or a status < 0. */
 int dlt_plan_query(int64_t N, int64_t* out, int max_fields);
 /* The same for the plan of precision mode `prec` (DLT_PREC_*). */

@@ -285,7 +285,13 @@ struct CallWS {
 int setup_call(const Plan& p, int64_t batch, hipStream_t s, CallWS& cw) {
     size_t per = p.ws_per_inst;
     int64_t nb = batch;
-    if (per > 0 && (size_t)nb * per > WS_CAP) nb = (int64_t)(WS_CAP / per);
+    if (per > 0 && (size_t)nb * per > WS_CAP) {
+        // as few slices as the bound allows, of equal size (the last one no
+        // smaller than the others by more than one instance)
+        const int64_t nbmax = std::max<int64_t>(1, (int64_t)(WS_CAP / per));
+        const int64_t slices = (batch + nbmax - 1) / nbmax;
+        nb = (batch + slices - 1) / slices;
+    }
     if (batch > 0 && nb < 1) nb = 1;
     size_t shared = p.ws_shared;
     void* base = nullptr;
