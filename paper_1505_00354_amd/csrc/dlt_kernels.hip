@@ -528,6 +528,12 @@ constexpr int DMM_XPT = 2 * DMM_J * DMM_B / 256;  // x values each thread stages
 constexpr int DMM_W = DMM_I + DMM_J;              // Lam window length
 typedef double dmm_v4 __attribute__((ext_vector_type(4)));
 
+// With gridDim.z > 1 the inner range is split: block z covers the columns
+// n of chunk z (DMM_CH of them) and writes its partial sums, scaled as the
+// one-instance kernels' partials, at out[b * os + z * nd + k] for the
+// reduction of those kernels (rows whose chunk lies wholly on the zero side
+// of the triangle are neither written nor read).
+constexpr int DMM_CH = DENSE_CH;  // columns per split chunk
 template <bool TRANS>
 __global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restrict__ lam, const double* __restrict__ x,
                                                   int64_t xs, int nb, double* __restrict__ out, int64_t os,
@@ -536,16 +542,27 @@ __global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restri
     __shared__ double slm[DMM_W];             // Lam(|j - i|) window
     __shared__ double slp[2][DMM_W];          // Lam(i + j + p) windows
     // blocks are dispatched in x-major order: the instance tiles of one row
-    // tile go together, the longest rows (the first tiles) first
-    const int i0 = blockIdx.y * DMM_I, b0 = blockIdx.x * DMM_B;
+    // tile go together, the longest rows first (the first tiles forward,
+    // the last ones transposed)
+    const int ty = TRANS ? (int)(gridDim.y - 1 - blockIdx.y) : (int)blockIdx.y;
+    const int i0 = ty * DMM_I, b0 = blockIdx.x * DMM_B;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int p = w >> 1, iw = i0 + 32 * (w & 1);
     const int ndp = (nd + 1 - p) >> 1;  // rows (and columns) of parity p
     const int ndp0 = (nd + 1) >> 1;
     const int lr = l & 15, lk = l >> 4;
     // inner range of the tile: forward j >= i0, transposed j <= i0 + DMM_I - 1
-    const int jlo = TRANS ? 0 : i0;
-    const int jhi = TRANS ? min(ndp0, i0 + DMM_I) : ndp0;
+    int jlo = TRANS ? 0 : i0;
+    int jhi = TRANS ? min(ndp0, i0 + DMM_I) : ndp0;
+    const bool split = gridDim.z > 1;
+    if (split) {
+        const int c0 = (int)blockIdx.z * (DMM_CH / 2), c1 = c0 + DMM_CH / 2;  // chunk's inner indices
+        // chunks the reduction never reads: forward, wholly left of the
+        // tile's first row (c1 <= i0); transposed, wholly right of its last
+        if (TRANS ? (c0 >= i0 + DMM_I) : (c1 <= i0)) return;
+        jlo = max(jlo, c0);
+        jhi = min(jhi, c1);
+    }
     // chunk data staged through registers: the next chunk's global loads are
     // issued before the current chunk's products
     double rx[DMM_XPT], rm = 0, rp0 = 0, rp1 = 0;
@@ -621,9 +638,9 @@ __global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restri
                 const int i = iw + 16 * u + lk + 4 * r, b = b0 + 16 * t + lr;
                 if (i < ndp && b < nb) {
                     const int k = 2 * i + p;
-                    const double sc = TRANS ? (half ? k + 0.5 : 1.0)
+                    const double sc = TRANS ? ((half && !split) ? k + 0.5 : 1.0)
                                             : ((k == 0) ? 0.3183098861837907 : 0.6366197723675814);
-                    out[(int64_t)b * os + k] = sc * acc[u][t][r];
+                    out[(int64_t)b * os + (split ? (int64_t)blockIdx.z * nd : 0) + k] = sc * acc[u][t][r];
                 }
             }
 }
@@ -2294,6 +2311,14 @@ hipError_t plan_prepare(Plan& p) {
 // shared by enough instances (a block's 32 instance columns are then mostly
 // live); single instances keep the one-instance kernel.
 static bool dense_mm_pays(int nd, int64_t nb) { return nb >= 8 && nd >= 64; }
+// Splits of the batched dense block's inner range: one (sums written
+// directly) once the row and instance tiles alone give 512 blocks, else one
+// per chunk of the one-instance kernels, whose partial buffer and reduction
+// it then shares.
+static int dense_mm_splits(int nd, int64_t nb, int nchunk) {
+    const int64_t tiles = ((nb + DMM_B - 1) / DMM_B) * (((nd + 1) / 2 + DMM_I - 1) / DMM_I);
+    return (tiles >= 512 || nchunk <= 1) ? 1 : nchunk;
+}
 
 // Makes `to` wait for everything enqueued on `from` so far.
 static hipError_t dep(hipStream_t from, hipStream_t to, hipEvent_t e) {
@@ -2354,8 +2379,20 @@ hipError_t run_leg2cheb(const Plan& p, int64_t nb, const double* c, int64_t cs, 
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
     auto dense_block = [&](hipStream_t st, double* dst, int64_t ds) {
         if (dense_mm_pays(nd, nb)) {  // one contraction on the matrix cores
-            const dim3 gm((unsigned)((nb + DMM_B - 1) / DMM_B), (unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I));
-            traced("k_dense_mm", st, [&] { launch(k_dense_mm<false>, gm, 256, 0, st, nd, p.d_lam, c, cs, (int)nb, dst, ds, 0); });
+            const int zs = dense_mm_splits(nd, nb, p.dense_nchunk);
+            const dim3 gm((unsigned)((nb + DMM_B - 1) / DMM_B), (unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I),
+                          (unsigned)zs);
+            if (zs == 1) {
+                traced("k_dense_mm", st, [&] { launch(k_dense_mm<false>, gm, 256, 0, st, nd, p.d_lam, c, cs, (int)nb, dst, ds, 0); });
+            } else {  // chunk partials, then the one-instance kernels' reduction
+                traced("k_dense_mm", st, [&] {
+                    launch(k_dense_mm<false>, gm, 256, 0, st, nd, p.d_lam, c, cs, (int)nb, w.dense, w.sdense, 0);
+                });
+                traced("k_dense_reduce", st, [&] {
+                    launch(k_dense_reduce, dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, st, nd, p.dense_nchunk,
+                           p.dense_chunk, w.dense, w.sdense, dst, ds);
+                });
+            }
             return;
         }
         dim3 gd(2 * ((nd + 511) / 512), p.dense_nchunk, (unsigned)nb);
@@ -2469,10 +2506,21 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     if (!p.sub && dense_mm_pays(nd, nb)) {  // one contraction on the matrix cores
         double* dst = last ? out : dense_out;
         const int64_t ds = last ? os : w.sdense;
-        const dim3 gm((unsigned)((nb + DMM_B - 1) / DMM_B), (unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I));
-        traced("k_dense_mm_t", sl, [&] {
-            launch(k_dense_mm<true>, gm, 256, 0, sl, nd, p.d_lam, y, ys, (int)nb, dst, ds, last ? half : 0);
-        });
+        const int zs = dense_mm_splits(nd, nb, p.dense_nchunk);
+        const dim3 gm((unsigned)((nb + DMM_B - 1) / DMM_B), (unsigned)(((nd + 1) / 2 + DMM_I - 1) / DMM_I), (unsigned)zs);
+        if (zs == 1) {
+            traced("k_dense_mm_t", sl, [&] {
+                launch(k_dense_mm<true>, gm, 256, 0, sl, nd, p.d_lam, y, ys, (int)nb, dst, ds, last ? half : 0);
+            });
+        } else {  // chunk partials, then the one-instance kernels' reduction
+            traced("k_dense_mm_t", sl, [&] {
+                launch(k_dense_mm<true>, gm, 256, 0, sl, nd, p.d_lam, y, ys, (int)nb, w.dense, w.sdense, 0);
+            });
+            traced("k_dense_t_reduce", sl, [&] {
+                launch(k_dense_t_reduce, dim3((nd + 255) / 256, 1, (unsigned)nb), 256, 0, sl, nd, p.dense_nchunk,
+                       p.dense_chunk, w.dense, w.sdense, dst, ds, last ? half : 0);
+            });
+        }
         if (last) return hipGetLastError();
     } else if (!p.sub) {
         traced("k_dense_t", sl, [&] {
