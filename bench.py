@@ -181,29 +181,38 @@ def ragged_runs(pk, wl, torch, np, dev, checks=None):
         pk.dlt_batch(x, sizes, offs, out=y)
     torch.cuda.synchronize()
     pk.trace_enable(False)
-    kern = pk.trace_collect(128)
+    kern = pk.trace_collect()
     tot_ms = sum(v[0] for v in kern.values()) / 2
     ranked = sorted(kern.items(), key=lambda kv: -kv[1][0])
+    # instances per grid: each size class (padded power of two P) runs on
+    # the grid the batch's first call timed fastest, P or 2P; classes of 8 or
+    # more instances take the batched dense block
     classes = {}
     for n in sizes.tolist():
         P = 1 << max(0, (int(n) - 1).bit_length())
         classes[P] = classes.get(P, 0) + 1
+    on_grid = {}
+    for P, cnt in classes.items():
+        if cnt >= 8:
+            G = pk.batch_grid(P)
+            on_grid[G] = on_grid.get(G, 0) + cnt
     roof3 = None
     mm = {k: v for k, v in kern.items() if k.startswith("k_dense_mm/")}
-    if mm and all(int(k.split("/")[1]) in classes for k in mm):
+    if mm and set(int(k.split("/")[1]) for k in mm) == set(on_grid):
         flops = 0.0
-        for k in mm:
-            P = int(k.split("/")[1])
-            nd = pk.plan_info(P)["nd"]
+        for G, cnt in on_grid.items():
+            nd = pk.plan_info(G)["nd"]
             h0, h1 = (nd + 1) // 2, nd // 2
-            flops += classes[P] * (h0 * (h0 + 1) + h1 * (h1 + 1))
+            flops += cnt * (h0 * (h0 + 1) + h1 * (h1 + 1))
         mm_s = sum(v[0] for v in mm.values()) / 2 / 1000.0
         ach = flops / mm_s / 1e12
         roof3 = {"kernel": "k_dense_mm", "bound": "mfma", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
                  "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "flops_per_batch": int(flops),
                  "ms_per_batch": round(mm_s * 1000, 3), "share_of_traced_batch": round(mm_s * 1000 / tot_ms, 4),
-                 "model": "2 (h0 (h0+1) + h1 (h1+1)) flops per instance of the dense block, h0, h1 = rows of each "
-                          "parity below nd (classes of 8 or more instances; grids taken as the padded sizes)"}
+                 "instances_per_grid": {str(G): c for G, c in sorted(on_grid.items())},
+                 "model": "h0 (h0+1) + h1 (h1+1) flops per instance of the dense block (a multiply-add on each of "
+                          "the h (h+1)/2 entries of each parity's triangle), h0, h1 = rows of each parity below nd "
+                          "of the grid the instance runs on (classes of 8 or more instances)"}
     res["fp64_4096_sizes_64_16384"] = {
         "transforms": 4096, "ms_per_batch_graph": round(ms_graph, 3),
         "transforms_per_s_graph": round(4096 * 1000.0 / ms_graph, 1),

@@ -207,6 +207,20 @@ int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double
 int dlt_batch_ex(int64_t count, const int64_t* Ns, const int64_t* offsets, const int8_t* inverse,
                  const double* in, double* out, int prec, hipStream_t stream);
 
+/* The grid size on which dlt_batch_ex runs instances of size N in direction
+ * `inverse` (0: DLT, 1: IDLT) and precision mode prec (DLT_PREC_*) on the
+ * current device: the padded power of two P >= N, or 2P when the timing of
+ * both at the first dlt_batch_ex call holding such instances found 2P faster
+ * (on the finer grid the nodes lie closer to grid points, so the evaluation
+ * needs fewer Taylor terms, which can outweigh the larger FFTs).
+ * Writes it to *grid: P when 2P > DLT_MAX_N (no other candidate), 0 when no
+ * dlt_batch_ex call on this device has held such instances since the last
+ * dlt_release().  Host-side lookup only: no device work, no allocation, no
+ * synchronisation.  Status: DLT_ERR_INVALID_ARG (N < 1, inverse not 0 or 1,
+ * grid NULL, prec not a DLT_PREC_* value), DLT_ERR_UNSUPPORTED (N >
+ * DLT_MAX_N). */
+int dlt_batch_grid(int64_t N, int inverse, int prec, int64_t* grid);
+
 /* dlt_forward for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation).
  * The same transform and kernels as dlt_forward (the same bits), but the call

@@ -71,6 +71,8 @@ def lib():
         L.dlt_forward_noalloc.restype = ctypes.c_int
         L.dlt_batch_ex.argtypes = [i64, vp, vp, vp, vp, vp, ctypes.c_int, vp]
         L.dlt_batch_ex.restype = ctypes.c_int
+        L.dlt_batch_grid.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+        L.dlt_batch_grid.restype = ctypes.c_int
         L.dlt_status_string.argtypes = [ctypes.c_int]
         L.dlt_status_string.restype = ctypes.c_char_p
         L.dlt_release.argtypes = []
@@ -280,11 +282,21 @@ def plan_info(N, prec="fp64", tol=None):
     return {k: int(buf[i]) for i, k in enumerate(PLAN_FIELDS[:n])}
 
 
+def batch_grid(N, inverse=False, prec="fp64"):
+    """Grid size dlt_batch runs instances of size N on (direction, precision)
+    on the current device: the padded power of two or twice it, as timed at
+    the first batch holding such instances; 0 before any such batch
+    (dlt_batch_grid)."""
+    g = ctypes.c_int64(0)
+    _check(lib().dlt_batch_grid(int(N), 1 if inverse else 0, _prec(prec), ctypes.byref(g)), "dlt_batch_grid")
+    return int(g.value)
+
+
 def trace_enable(on=True):
     _check(lib().dlt_trace_enable(1 if on else 0), "dlt_trace_enable")
 
 
-def trace_collect(max_kernels=64):
+def trace_collect(max_kernels=4096):
     """{kernel name: (total ms, launches)} since the last collect; waits for
     the recorded events."""
     names = ctypes.create_string_buffer(max_kernels * 48)

@@ -1233,6 +1233,25 @@ int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields) {
     return plan_fields(p, out, max_fields);
 }
 
+int dlt_batch_grid(int64_t N, int inverse, int prec, int64_t* grid) {
+    if (N < 1 || (inverse != 0 && inverse != 1) || !grid) return DLT_ERR_INVALID_ARG;
+    if (N > DLT_MAX_N) return DLT_ERR_UNSUPPORTED;
+    int rc;
+    if ((rc = check_prec(prec))) return rc;
+    const int64_t P = next_pow2(N);
+    if (2 * P > DLT_MAX_N) {  // no larger candidate: never timed
+        *grid = P;
+        return DLT_OK;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.tuned.find(std::make_tuple(dev, inverse, P, prec));
+    *grid = it == c.tuned.end() ? 0 : it->second;
+    return DLT_OK;
+}
+
 int dlt_plan_query_tol(int64_t N, double eps, int64_t* out, int max_fields) {
     int rc = check_size(N, 1);
     if (rc) return rc;

@@ -111,9 +111,35 @@ def main(argv):
     inv = (np.arange(len(Ns)) % 2).astype(np.int8)
     tot = int(Ns.sum())
     L.dlt_batch_ex.argtypes = [i64, vp, vp, vp, vp, vp, ctypes.c_int, vp]
+    L.dlt_batch_grid.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(i64)]
+    max_n = 1 << 20
+
+    def grids():
+        # (status, grid, padded size) of every instance of the batch
+        out = []
+        for n, d in zip(Ns.tolist(), inv.tolist()):
+            g = i64(-7)
+            rc = L.dlt_batch_grid(int(n), int(d), PREC["fp64"], ctypes.byref(g))
+            out.append((rc, g.value, 1 << max(0, (int(n) - 1).bit_length())))
+        return out
+
+    before = grids()
     for prec in ("fp64", "fp32bulk"):
         call(f"dlt_batch_ex count={len(Ns)} {prec}", L.dlt_batch_ex, len(Ns), vp(Ns.ctypes.data),
              vp(offs.ctypes.data), vp(inv.ctypes.data), buf("in", tot), buf("out", tot), PREC[prec])
+    after = grids()
+    # the grid query: 0 before a batch held the size class (the padded size
+    # when there is no larger candidate), the padded size or twice it after;
+    # bad arguments refused
+    g = i64(0)
+    bad = [L.dlt_batch_grid(0, 0, 0, ctypes.byref(g)), L.dlt_batch_grid(5, 2, 0, ctypes.byref(g)),
+           L.dlt_batch_grid(5, 0, 9, ctypes.byref(g)), L.dlt_batch_grid(5, 0, 0, None),
+           L.dlt_batch_grid(max_n + 1, 0, 0, ctypes.byref(g))]
+    batch_grid = {
+        "before_ok": all(rc == 0 and gr == (P if 2 * P > max_n else 0) for rc, gr, P in before),
+        "after_ok": all(rc == 0 and gr in (P, 2 * P) for rc, gr, P in after),
+        "bad_status": bad,
+    }
     # more distinct calls than the call-graph cache keeps (its eviction
     # destroys the other graphs), then the first ones again
     N = 1024
@@ -188,6 +214,7 @@ def main(argv):
         "launches": counts[0], "captures": counts[1], "graph_launches": counts[2],
         "event_records": counts[3], "event_waits": counts[4], "side_to_side_waits": counts[5],
         "errors": errors, "violations": viol[:50], "violation_count": len(viol), "noalloc": noalloc,
+        "batch_grid": batch_grid,
     }))
 
 

@@ -207,8 +207,18 @@ def test_ragged_traced_run_matches_graph(pk):
     pk.trace_enable(True)
     got = to_host(pk.dlt_batch(xd, sizes, offs, inv))
     pk.trace_enable(False)
-    kern = pk.trace_collect(128)
+    kern = pk.trace_collect()
     assert np.array_equal(ref, ref2)
     assert np.array_equal(got, ref)
     assert any(k.startswith("k_dense_mm/") for k in kern), sorted(kern)
     assert any(k.startswith("k_dense_mm_t/") for k in kern), sorted(kern)
+    # every class ran on the grid dlt_batch_grid reports (its padded size or
+    # twice it), and the trace names kernels on those grids only
+    grids = set()
+    for n, d in zip(sizes.tolist(), inv.tolist()):
+        P = 1 << max(0, (int(n) - 1).bit_length())
+        G = pk.batch_grid(int(n), bool(d))
+        assert G in (P, 2 * P), (n, d, G)
+        grids.add(G)
+    for k in kern:
+        assert int(k.split("/")[1]) in grids, (k, sorted(grids))

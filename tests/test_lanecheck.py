@@ -79,6 +79,9 @@ def test_library_stream_orderings(built):
     assert out["calls"] > 3000 and out["launches"] > 10000
     assert out["captures"] > 1000 and out["graph_launches"] > 1500
     assert out["event_waits"] > 1000
+    # the ragged batch's grid query
+    assert out["batch_grid"]["before_ok"] and out["batch_grid"]["after_ok"], out["batch_grid"]
+    assert out["batch_grid"]["bad_status"] == [-1, -1, -1, -1, -2]
     # the allocation-free forward allocates, frees, creates and synchronises
     # nothing, and neither captures nor records nor waits on events
     assert len(out["noalloc"]) == 4
