@@ -29,8 +29,11 @@ Prints one JSON line; diagnostics go to stderr.  Options:
   --no-modes    skip the short runs of the other modes (reported under
                 "modes": step time, speedup at equal stated accuracy,
                 FP32-bulk at batch 64, the step at working tolerances
-                1e-12 ... 1e-3, errors against the oracle; and under
-                "sizes" the FP64 step at N = 2^12, 2^14, 2^16, 2^18)
+                1e-12 ... 1e-3, errors against the oracle; under
+                "sizes" the FP64 step at N = 2^12, 2^14, 2^16, 2^18; and
+                under "grids" the evaluation and the DLT with the Taylor
+                series about theta^cheb* against theta^cheb1: time per
+                call, the theta^cheb* kernels' rooflines, the error)
   --copy-probe BYTES  only run one plain copy kernel (read BYTES, write
                 BYTES) and exit: the reference for calibrating the HBM byte
                 counters FETCH_SIZE / WRITE_SIZE
@@ -73,6 +76,11 @@ def kernel_model(name, N, info, f32=False, bulk=False):
         "k_dct3_passA": 8 * N + 16 * N,
         "k_dct3_passB": 16 * N + 8 * N,
     }
+    # evaluation about theta^cheb*: LS slabs of M = 2N complex values
+    LS, M = info.get("chebstar_L", 0), 2 * N
+    hbm["k_star_passA"] = 8 * N + 16 * M * LS
+    hbm["k_star_passB"] = 2 * 16 * M * LS + 16 * M
+    hbm["k_star_passC"] = 16 * M * LS + 8 * N + 8 * N
     # near field: per (row, degree >= nd) one recurrence step (3 FMA + 1 add
     # = 7 flops) and one weighted accumulation (FMA, or multiply + add)
     alu = {
@@ -137,6 +145,72 @@ def stored_traffic(kernel):
     if digest != source_digest() or kernel not in rows:
         return None
     return rows[kernel]
+
+
+def grid_runs(pk, wl, torch, np, dev, N, reps, checks=None):
+    """cheb_eval_leggrid and dlt_forward (FP64) with the Taylor series about
+    theta^cheb1 and about theta^cheb*, K calls each; the theta^cheb* kernels'
+    rooflines from 3 traced calls; the theta^cheb* forward's error against the
+    oracle (appended to `checks`, run in the CPU leg)."""
+    c = torch.from_numpy(wl.coeffs_algebraic(N, 2)[0]).to(dev)
+    chat = torch.from_numpy(wl.coeffs_algebraic(N, 3)[0]).to(dev)
+    f = torch.empty_like(c)
+
+    def timed_fn(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {"N": N}
+    for op, x in (("cheb_eval_leggrid", chat), ("dlt_forward", c)):
+        fn = getattr(pk, op)
+        t1 = timed_fn(lambda: fn(x, out=f))
+        ts = timed_fn(lambda: fn(x, out=f, grid="chebstar"))
+        res[op] = {"ms_cheb1": round(t1, 4), "ms_chebstar": round(ts, 4), "chebstar_over_cheb1": round(ts / t1, 3)}
+    info = pk.plan_info(N)
+    res["taylor_terms"] = {"cheb1": info["L"], "chebstar": info["chebstar_L"]}
+    pk.trace_enable(True)
+    for _ in range(3):
+        pk.cheb_eval_leggrid(chat, out=f, grid="chebstar")
+    torch.cuda.synchronize()
+    pk.trace_enable(False)
+    kern = pk.trace_collect()
+    kr = {}
+    for key, (ms, cnt) in sorted(kern.items()):
+        name, n = key.split("/")
+        m = kernel_model(name, int(n), info)
+        if m is None or m[0] != "hbm":
+            continue
+        us = ms / cnt * 1000
+        kr[key] = {"avg_launch_us": round(us, 2), "bytes_per_launch": int(m[1]),
+                   "achieved": round(m[1] / us / 1e3, 2), "unit": "GB/s",
+                   "frac": round(m[1] / us / 1e3 / HBM_PEAK_GBS, 4)}
+    res["chebstar_kernels"] = kr
+    res["bytes_per_evaluation"] = {
+        "cheb1": int(sum(kernel_model(k, N, info)[1] for k in ("k_ndct_passA", "k_ndct_passB"))),
+        "chebstar": int(sum(v["bytes_per_launch"] for v in kr.values()))}
+    log("grids", res)
+    if checks is not None:
+        fh = pk.dlt_forward(c, grid="chebstar").cpu().numpy()
+        ch = c.cpu().numpy()
+
+        def check(res=res, fh=fh, ch=ch):
+            import oracle
+
+            idx = wl.sample_indices(N, 4096, 11)
+            th, _ = oracle.nodes(N, idx=idx)
+            ref = oracle.dlt(ch, th)
+            res["chebstar_forward_error_vs_oracle"] = float(np.max(np.abs(fh[idx] - ref)) / np.sum(np.abs(ch)))
+            res["error_check"] = "4096 sampled outputs; the oracle with its own nodes; max |f - f_oracle| / ||c||_1"
+
+        checks.append(check)
+    return res
 
 
 def ragged_runs(pk, wl, torch, np, dev, checks=None):
@@ -689,6 +763,11 @@ def main():
                                           "frac": round(sbn / ms / 1e6 / HBM_PEAK_GBS, 4)}}
             log(f"N={n}: {ms:.4f} ms/step", sizes[str(n)])
         out["sizes"] = sizes
+
+    # the evaluation about the other grid theta^cheb* against theta^cheb1:
+    # time per call, the kernels' rooflines, and the forward error
+    if not args.no_modes and B == 1 and prec == "fp64":
+        out["grids"] = grid_runs(pk, wl, torch, np, dev, N, args.steps, checks=None if args.no_cpu else checks)
 
     if not args.no_ragged and B == 1:
         out["ragged"] = ragged_runs(pk, wl, torch, np, dev, checks=None if args.no_cpu else checks)

@@ -183,6 +183,34 @@ int dlt_forward_tol(int64_t N, int64_t batch, const double* c, double* f, double
 int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double eps, hipStream_t stream);
 int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double eps, hipStream_t stream);
 
+/* cheb_eval_leggrid (eq. (3)) and dlt_forward (eq. (1)) with the Taylor
+ * series of Sec. 2.3 taken about another equispaced grid, chosen by `grid`:
+ *   DLT_GRID_CHEB1     theta^cheb1_k = (k+1/2) pi/N: the same calls as the
+ *                      plain entry points;
+ *   DLT_GRID_CHEBSTAR  theta^cheb*_k = (k+3/4) pi/(N+1/2), the zeros of the
+ *                      leading term of the Stieltjes asymptotic form (Sec. 2.2).
+ *                      The nodes lie within 1/(6 pi N) of them (Lemma 2), so
+ *                      8 Taylor terms meet the FP64 budget (Cor. 2, second
+ *                      bound) against 16 about theta^cheb1; but the sums of
+ *                      each term are odd outputs of transforms of length
+ *                      2N+1 (Remark 1), computed as chirp-z transforms
+ *                      (cyclic convolutions of length 2N): three passes over
+ *                      8 slabs of 2N complex values, about 1050 N bytes of
+ *                      intermediates against about 280 N for the Taylor
+ *                      passes about theta^cheb1.
+ * FP64 arithmetic; accuracy as stated at the top of this file.  N must be a
+ * power of two for DLT_GRID_CHEBSTAR (DLT_ERR_UNSUPPORTED otherwise); other
+ * values of grid give DLT_ERR_INVALID_ARG; arguments, layout and ownership as
+ * for the plain entry points.  DLT_GRID_CHEBSTAR calls run every kernel
+ * directly on `stream` (no side streams, no graph capture); the first call
+ * for a size builds its tables (and the size's FP64 plan if needed) and
+ * synchronises the device; the stream's workspace grows by 8 x 2N complex
+ * values per instance (batches beyond the workspace bound run in slices). */
+#define DLT_GRID_CHEB1 0
+#define DLT_GRID_CHEBSTAR 1
+int cheb_eval_leggrid_grid(int64_t N, int64_t batch, const double* chat, double* f, int grid, hipStream_t stream);
+int dlt_forward_grid(int64_t N, int64_t batch, const double* c, double* f, int grid, hipStream_t stream);
+
 /* Ragged batch: `count` independent transforms of uneven sizes in one call
  * (many transforms of different N, forward and inverse mixed).
  *   Ns[i]       size of instance i (1 <= Ns[i] <= DLT_MAX_N), host array
@@ -253,8 +281,9 @@ const char* dlt_status_string(int status);
  * pass-A term groups, and the per-stream workspace bound in bytes (a batch
  * whose workspace, instances x bytes per instance, exceeds it runs in the
  * fewest slices of at most floor(bound / bytes per instance) instances, of
- * equal size up to one instance).  Returns the number of
- * fields available or a status < 0. */
+ * equal size up to one instance), and the Taylor terms of the evaluation
+ * about theta^cheb* (DLT_GRID_CHEBSTAR; FP64 plans of the fixed budget, 0
+ * for the others).  Returns the number of fields available or a status < 0. */
 int dlt_plan_query(int64_t N, int64_t* out, int max_fields);
 /* The same for the plan of precision mode `prec` (DLT_PREC_*). */
 int dlt_plan_query_ex(int64_t N, int prec, int64_t* out, int max_fields);

@@ -25,6 +25,9 @@ DLT_PREC_FP64 = 0
 DLT_PREC_FP32_BULK = 1
 DLT_PREC_FP64_RELAXED = 2
 PRECISIONS = {"fp64": DLT_PREC_FP64, "fp32bulk": DLT_PREC_FP32_BULK, "fp64relaxed": DLT_PREC_FP64_RELAXED}
+DLT_GRID_CHEB1 = 0
+DLT_GRID_CHEBSTAR = 1
+GRIDS = {"cheb1": DLT_GRID_CHEB1, "chebstar": DLT_GRID_CHEBSTAR}
 
 _lib = None
 
@@ -73,6 +76,9 @@ def lib():
         L.dlt_batch_ex.restype = ctypes.c_int
         L.dlt_batch_grid.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
         L.dlt_batch_grid.restype = ctypes.c_int
+        for name in ("cheb_eval_leggrid_grid", "dlt_forward_grid"):
+            getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_int, vp]
+            getattr(L, name).restype = ctypes.c_int
         L.dlt_status_string.argtypes = [ctypes.c_int]
         L.dlt_status_string.restype = ctypes.c_char_p
         L.dlt_release.argtypes = []
@@ -133,13 +139,19 @@ def _prec(prec):
     return PRECISIONS[prec]
 
 
-def _unary(name, x, out, prec="fp64", tol=None):
+def _unary(name, x, out, prec="fp64", tol=None, grid="cheb1"):
     import torch
 
     N, batch, out = _vec_args(x, out)
     args = (N, batch, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()))
+    if grid not in GRIDS:
+        raise ValueError(f"grid must be one of {sorted(GRIDS)}")
     with torch.cuda.device(x.device):
-        if tol is not None:
+        if grid != "cheb1":
+            if prec != "fp64" or tol is not None:
+                raise ValueError("the cheb* grid runs in FP64 at the fixed budget (prec 'fp64', no tol)")
+            _check(getattr(lib(), name + "_grid")(*args, GRIDS[grid], _stream(x.device)), name + "_grid")
+        elif tol is not None:
             if prec != "fp64":
                 raise ValueError("a working tolerance runs in FP64 (prec must be 'fp64')")
             _check(getattr(lib(), name + "_tol")(*args, float(tol), _stream(x.device)), name + "_tol")
@@ -155,18 +167,20 @@ def leg2cheb(c, out=None, prec="fp64", tol=None):
     return _unary("leg2cheb", c, out, prec, tol)
 
 
-def cheb_eval_leggrid(chat, out=None, prec="fp64", tol=None):
-    """sum_n chat_n T_n at the N Legendre nodes."""
-    return _unary("cheb_eval_leggrid", chat, out, prec, tol)
+def cheb_eval_leggrid(chat, out=None, prec="fp64", tol=None, grid="cheb1"):
+    """sum_n chat_n T_n at the N Legendre nodes.  grid: the Taylor expansion
+    point, "cheb1" ((k+1/2) pi/N) or "chebstar" ((k+3/4) pi/(N+1/2))."""
+    return _unary("cheb_eval_leggrid", chat, out, prec, tol, grid)
 
 
-def dlt_forward(c, out=None, prec="fp64", tol=None):
+def dlt_forward(c, out=None, prec="fp64", tol=None, grid="cheb1"):
     """Discrete Legendre transform f_k = sum_n c_n P_n(x_k).  prec: "fp64",
     "fp32bulk" (FP32 bulk transforms, 5e-6 budget) or "fp64relaxed" (FP64
     with the 5e-6 parameters).  tol: a working tolerance instead (FP64,
     parameters chosen for eps = tol, 5e-14 <= tol <= 0.1; the other entry
-    points take it too)."""
-    return _unary("dlt_forward", c, out, prec, tol)
+    points take it too).  grid: the Taylor expansion point of the evaluation,
+    "cheb1" or "chebstar" (FP64, N a power of two)."""
+    return _unary("dlt_forward", c, out, prec, tol, grid)
 
 
 def dlt_forward_noalloc(c, out=None):
@@ -266,7 +280,7 @@ def release():
 
 PLAN_FIELDS = ("L", "nd", "far_terms", "far_blocks", "far_mmax", "near_items", "near_rows", "N1", "N2",
                "colsA", "rowsB", "tgB", "tnear_wg", "tnear_rg", "near_steps", "boundary_nodes", "ws_bytes",
-               "near_work", "tgA", "ws_cap")
+               "near_work", "tgA", "ws_cap", "chebstar_L")
 
 
 def plan_info(N, prec="fp64", tol=None):

@@ -1042,6 +1042,90 @@ int dlt_forward_noalloc(int64_t N, int64_t batch, const double* c, double* f, hi
     return rc;
 }
 
+// ------------------------------------------------------ theta^cheb* grid --
+// the theta^cheb* plan of an FP64 plan (built on first use)
+static int get_star(Plan* p, StarPlan** out) {
+    Cache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (!p->star) {
+        std::unique_ptr<StarPlan> s(new StarPlan());
+        int rc = star_plan_build(p->N, *s);
+        if (rc == DLT_OK && star_prepare(*s) != hipSuccess) rc = DLT_ERR_HIP;
+        if (rc != DLT_OK) {
+            star_plan_free(*s);
+            return rc;
+        }
+        p->star = s.release();
+    }
+    *out = p->star;
+    return DLT_OK;
+}
+
+// cheb_eval_leggrid (from_leg false) or dlt_forward (true) about theta^cheb*,
+// every kernel on `stream`, in slices that keep the workspace within WS_CAP
+static int star_call(int64_t N, int64_t batch, const double* in, double* f, bool from_leg, hipStream_t stream) {
+    Plan* p;
+    int rc;
+    if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
+    StarPlan* sp;
+    if ((rc = get_star(p, &sp))) return rc;
+    const size_t per = sp->ws_per_inst + (from_leg ? p->ws_per_inst : 0);
+    int64_t nb = batch;
+    if ((size_t)nb * per > WS_CAP) {
+        const int64_t nbmax = std::max<int64_t>(1, (int64_t)(WS_CAP / per));
+        const int64_t slices = (batch + nbmax - 1) / nbmax;
+        nb = (batch + slices - 1) / slices;
+    }
+    void* base = nullptr;
+    if ((rc = get_ws(stream, p->ws_shared + (size_t)nb * per, &base))) return rc;
+    const size_t vecb = ((size_t)N * sizeof(double) + 255) & ~size_t(255);
+    double* dth = (double*)((char*)base + 2 * vecb);  // the layout of setup_call
+    char* q = (char*)base + p->ws_shared;
+    cplx* X = (cplx*)q;  // nb x L slabs of 2N values
+    Work work;
+    if (from_leg) work_carve(*p, nb, q + (size_t)nb * sp->ws_per_inst, work);
+    Lanes L;  // the caller's stream only
+    L.s = stream;
+    rc = hip_status(run_nodes(*p, nullptr, nullptr, dth, L));
+    for (int64_t b0 = 0; rc == DLT_OK && b0 < batch; b0 += nb) {
+        const int64_t n = std::min(nb, batch - b0);
+        const double* chat = in + b0 * N;
+        int64_t hs = N;
+        if (from_leg) {
+            rc = hip_status(run_leg2cheb(*p, n, in + b0 * N, N, work.chat, work.schat, work, L));
+            chat = work.chat;
+            hs = work.schat;
+        }
+        if (rc == DLT_OK) rc = hip_status(run_star(*sp, n, chat, hs, dth, f + b0 * N, N, X, stream));
+    }
+    return rc;
+}
+
+static int grid_args(int64_t N, int64_t batch, const double* in, const double* out) {
+    int rc = check_any_size(N, batch);
+    if (rc) return rc;
+    if (!is_pow2_n(N)) return DLT_ERR_UNSUPPORTED;
+    if (batch > 0 && (!in || !out || overlap(in, out, (size_t)N * batch * sizeof(double))))
+        return DLT_ERR_INVALID_ARG;
+    return DLT_OK;
+}
+
+int cheb_eval_leggrid_grid(int64_t N, int64_t batch, const double* chat, double* f, int grid, hipStream_t stream) {
+    if (grid == DLT_GRID_CHEB1) return cheb_eval_leggrid(N, batch, chat, f, stream);
+    if (grid != DLT_GRID_CHEBSTAR) return DLT_ERR_INVALID_ARG;
+    int rc = grid_args(N, batch, chat, f);
+    if (rc || batch == 0) return rc;
+    return star_call(N, batch, chat, f, false, stream);
+}
+
+int dlt_forward_grid(int64_t N, int64_t batch, const double* c, double* f, int grid, hipStream_t stream) {
+    if (grid == DLT_GRID_CHEB1) return dlt_forward(N, batch, c, f, stream);
+    if (grid != DLT_GRID_CHEBSTAR) return DLT_ERR_INVALID_ARG;
+    int rc = grid_args(N, batch, c, f);
+    if (rc || batch == 0) return rc;
+    return star_call(N, batch, c, f, true, stream);
+}
+
 int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
     return dlt_inverse_ex(N, batch, f, c, DLT_PREC_FP64, stream);
 }
@@ -1217,7 +1301,8 @@ static int plan_fields(const Plan* p, int64_t* out, int max_fields) {
     }
     const int64_t v[] = {p->L, p->nd, p->far.nterm, p->far.nblk, p->far.Mmax, p->near.nitems, p->near.jnear,
                          p->geo.N1, p->geo.N2, p->geo.colsA, p->geo.rowsB, p->tgB, p->tn_wg, p->tn_nrg, steps,
-                         p->nodes.kb, (int64_t)p->ws_per_inst, work, p->tgA, (int64_t)WS_CAP};
+                         p->nodes.kb, (int64_t)p->ws_per_inst, work, p->tgA, (int64_t)WS_CAP,
+                         (p->prec == PREC_FP64 && p->tol == 0) ? star_terms(5e-15) : 0};
     int n = (int)(sizeof(v) / sizeof(v[0]));
     for (int i = 0; i < n && i < max_fields; ++i) out[i] = v[i];
     return n;

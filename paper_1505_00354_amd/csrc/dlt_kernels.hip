@@ -1470,6 +1470,215 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
 }
 
 
+// ===================================================== theta^cheb* grid ===
+// f_k = sum_n chat_n cos(n theta_k) with theta_k = theta*_k + delta_k,
+// theta*_k = (k+3/4) alpha, alpha = 2 pi/(2N+1) (Sec. 2.2), by the Taylor
+// series of Sec. 2.3 about theta*_k:
+//   f_k = Re sum_l (d_k^l/l!) i^l E_l(k),  d_k = N delta_k,
+//   E_l(k) = sum_{n<N} (n/N)^l chat_n e^{i n theta*_k}.
+// Each E_l is a chirp-z transform, e^{i alpha k^2/2} (u_l * h)(k) with
+// u_l[n] = (n/N)^l chat_n e^{i alpha (n^2/2 + 3n/4)} and h[m] = e^{-i alpha m^2/2},
+// a cyclic convolution of length M = 2N computed as F^-(F^+ u_l . F^+ h)/M.
+// Three passes over L slabs of M values: pass A of F^+ u_l (k_star_passA),
+// pass B of F^+, the product with H = F^+ h/M and pass B of the conjugate
+// transform in place (k_star_passB), pass A of the conjugate transform with
+// the Horner sum over l and the output chirp (k_star_passC).  Between the
+// passes the data keep the blocked layout of the other transforms.
+
+// e^{i pi r/den} for 0 <= r < 2 den (r an exact integer reduction)
+__device__ __forceinline__ cplx cispi_frac(int64_t r, int64_t den) {
+    double sn, cs;
+    sincospi((double)r / (double)den, &sn, &cs);
+    return {cs, sn};
+}
+// the input chirp e^{i alpha (n^2/2 + 3n/4)} = e^{i pi (2n^2 + 3n)/(2P)}, P = 2N+1
+__device__ __forceinline__ cplx star_chirp_in(int64_t n, int64_t P) {
+    return cispi_frac((2 * n * n + 3 * n) % (4 * P), 2 * P);
+}
+// the output chirp e^{i alpha k^2/2} = e^{i pi k^2/P}
+__device__ __forceinline__ cplx star_chirp_out(int64_t k, int64_t P) {
+    return cispi_frac((k * k) % (2 * P), P);
+}
+
+// Pass A of F^+ over M = 2N for the terms [qa, qb) (slab l - qa of X; block
+// row blockIdx.y takes an equal share of them), inputs zero for n >= N.
+// With table = 1 it forms instead the cyclic chirp h~[j] = h[j] (j < N),
+// h[2N - j] (j > N), 0 (j = N), into slab 0.
+template <int LA>
+__global__ FFT_BOUNDS void k_star_passA(Geo g, int N, int qa, int qb, int QG, int table,
+                                        const double* __restrict__ chat, int64_t chat_stride, cplx* __restrict__ X,
+                                        int64_t x_stride) {
+    __shared__ cplx buf[TILE_LDS(LA)];
+    STAGE_TW(stw, LA, double);
+    const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
+    const Tile<LA> T(g.colsA, g.N2);
+    const int M = g.N;
+    const int64_t P = 2 * (int64_t)N + 1;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int b = blockIdx.z;
+    const double* cb = chat + b * chat_stride;
+    cplx* Xb = X + b * x_stride;
+    const PassAOut<LA, false> out(g, T, na0);
+    HeldPut<LA, false, double> held(out, g, T);
+    if (table) {
+        cplx v[FFT_VPT];
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            v[s] = {0, 0};
+            const int j = na0 + T.col(s) + g.N1 * T.idx(s);
+            if (T.live(s) && j != N) v[s] = cconj(star_chirp_out(j < N ? j : M - j, P));
+        }
+        tile_fft<LA>(v, buf, twA, T, held);
+        held.hold(v, Xb);
+        held.flush();
+        return;
+    }
+    const double invN = 1.0 / N;
+    const int q0 = qa + ((qb - qa) * (int)blockIdx.y) / QG, q1 = qa + ((qb - qa) * ((int)blockIdx.y + 1)) / QG;
+    cplx A[FFT_VPT];  // (n/N)^l chat_n e^{i alpha (n^2/2 + 3n/4)}, carried from term to term
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        A[s] = {0, 0};
+        const int n = na0 + T.col(s) + g.N1 * T.idx(s);
+        if (T.live(s) && n < N) {
+            double a = cb[n];
+            for (int l = 0; l < q0; ++l) a *= n * invN;
+            A[s] = cscale(star_chirp_in(n, P), a);
+        }
+    }
+    for (int l = q0; l < q1; ++l) {
+        cplx v[FFT_VPT];
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            const int n = na0 + T.col(s) + g.N1 * T.idx(s);
+            v[s] = A[s];
+            A[s] = cscale(A[s], n * invN);
+        }
+        tile_fft<LA>(v, buf, twA, T, held);
+        held.hold(v, Xb + (int64_t)(l - qa) * M);
+    }
+    held.flush();
+}
+
+// Pass B of F^+ over the nterm slabs of X in place; then, unless fwd_only,
+// the product with H and pass B of the conjugate transform: the slab holds
+// Y = F+_B(conj(F+_B(x) H)), the conjugate of the inverse pass B output.
+// With fwd_only the transform is scaled by 1/M instead (forming H).
+template <int LB>
+__global__ FFT_BOUNDS void k_star_passB(Geo g, int nterm, int fwd_only, const cplx* __restrict__ H,
+                                        cplx* __restrict__ X, int64_t x_stride) {
+    __shared__ cplx buf[TILE_LDS(LB)];
+    STAGE_TW(stw, LB, double);
+    const cplx* tw = stage_twiddles<LB, double>(stw, g.twN1, g.N1);
+    const Tile<LB> T(g.rowsB, g.N1);
+    const int M = g.N;
+    const int vb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int64_t off = (int64_t)(vb0 >> g.lrB) * ((int64_t)g.N1 << g.lrB);
+    cplx* Xb = X + blockIdx.z * x_stride + off;
+    cplx h[FFT_VPT];
+    if (!fwd_only) passB_load<LB, double>(g, vb0, H, h, T);
+    const double invM = 1.0 / M;
+    cplx nx[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s)
+        if (T.live(s)) nx[s] = Xb[threadIdx.x + s * FFT_THREADS];
+    for (int t = 0; t < nterm; ++t) {
+        cplx v[FFT_VPT];
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) v[s] = nx[s];
+        if (t + 1 < nterm) {  // the next slab's tile loads while this one is transformed
+            const cplx* src = Xb + (int64_t)(t + 1) * M;
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s)
+                if (T.live(s)) nx[s] = src[threadIdx.x + s * FFT_THREADS];
+        }
+        tile_fft<LB>(v, buf, tw, T);
+        if (fwd_only) {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) v[s] = cscale(v[s], invM);
+        } else {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) v[s] = cconj(cmul(v[s], h[s]));
+            tile_fft<LB>(v, buf, tw, T);
+        }
+        cplx* dst = Xb + (int64_t)t * M;
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s)
+            if (T.live(s)) dst[threadIdx.x + s * FFT_THREADS] = v[s];
+    }
+}
+
+// Pass A of the conjugate transform for the L slabs (term l in slab l), from
+// the highest term down, with the Horner sum
+//   S = a_{L-1};  S = a_l + (d_k/(l+1)) S,  a_l = i^l conj(F+_A(Y_l twiddled)),
+// then f_k = Re(e^{i alpha k^2/2} S) for the outputs k < N;
+// d_k = N (theta_k - theta*_k) = N dth_k + pi (2k - N + 1)/(2(2N+1)), dth
+// the node offsets from theta^cheb1.
+template <int LA>
+__global__ FFT_BOUNDS void k_star_passC(Geo g, int N, int L, const cplx* __restrict__ X, int64_t x_stride,
+                                        const double* __restrict__ dth, double* __restrict__ f, int64_t f_stride) {
+    __shared__ cplx buf[TILE_LDS(LA)];
+    STAGE_TW(stw, LA, double);
+    const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
+    const Tile<LA> T(g.colsA, g.N2);
+    const int M = g.N;
+    const int64_t P = 2 * (int64_t)N + 1;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int b = blockIdx.z;
+    const cplx* Xb = X + b * x_stride;
+    const PassAOut<LA, false> tw(g, T, na0);
+    int off[FFT_VPT];
+    double d[FFT_VPT];
+    bool out[FFT_VPT];
+    const double dsh = M_PI / (2.0 * (double)P);
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        const int na = na0 + T.col(s), k = na + g.N1 * T.idx(s);
+        off[s] = passA_offset(g, na, T.idx(s), false);
+        out[s] = T.live(s) && k < N;
+        d[s] = out[s] ? (double)N * dth[k] + dsh * (double)(2 * k - N + 1) : 0.0;
+    }
+    cplx S[FFT_VPT], nx[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        S[s] = {0, 0};
+        nx[s] = T.live(s) ? Xb[(int64_t)(L - 1) * M + off[s]] : cplx{0, 0};
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        cplx v[FFT_VPT];
+        tw.twid(nx, v);
+        if (l > 0) {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s)
+                if (T.live(s)) nx[s] = Xb[(int64_t)(l - 1) * M + off[s]];
+        }
+        tile_fft<LA>(v, buf, twA, T);
+        const double r = 1.0 / (l + 1);
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            const cplx z = cconj(v[s]);
+            cplx a;  // i^l z
+            switch (l & 3) {
+                case 0: a = z; break;
+                case 1: a = {-z.im, z.re}; break;
+                case 2: a = {-z.re, -z.im}; break;
+                default: a = {z.im, -z.re}; break;
+            }
+            const double c = d[s] * r;
+            S[s] = {fma(c, S[s].re, a.re), fma(c, S[s].im, a.im)};
+        }
+    }
+    double* fb = f + b * f_stride;
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        if (out[s]) {
+            const int k = na0 + T.col(s) + g.N1 * T.idx(s);
+            const cplx c2 = star_chirp_out(k, P);
+            fb[k] = c2.re * S[s].re - c2.im * S[s].im;
+        }
+    }
+}
+
 // ============================================================== inverse ===
 // c = D_s M^T T^T D_w f (Sec. 4): g = w f; y = T^T g by the transposed Taylor
 // series; c_n = (n+1/2) (M^T y)_n with M^T = P^T C D_eps on the grid.
@@ -2621,6 +2830,49 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_ndct_passB, double, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, w.X + N, w.sX, dth, f, p.N, RR);
         });
     }
+    return hipGetLastError();
+}
+
+// H = F^+(cyclic chirp)/M of the theta^cheb* plan, formed once on the device
+hipError_t star_prepare(StarPlan& sp) {
+    const Geo& g = sp.geo;
+    const int M = g.N;
+    hipError_t e = hipMalloc(&sp.d_H, (size_t)M * sizeof(cplx));
+    if (e != hipSuccess) return e;
+    const int tilesA = g.N1 / g.colsA, tilesB = g.N2 / g.rowsB;
+    LEN_LAUNCH(M >= FFT_CAP, g.N2, k_star_passA, dim3(tilesA, 1, 1), FFT_THREADS, 0, 0, g, (int)sp.N, 0, 1, 1, 1,
+               (const double*)nullptr, (int64_t)0, sp.d_H, (int64_t)0);
+    LEN_LAUNCH(M >= FFT_CAP, g.N1, k_star_passB, dim3(tilesB, 1, 1), FFT_THREADS, 0, 0, g, 1, 1, (const cplx*)nullptr,
+               sp.d_H, (int64_t)0);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return e;
+}
+
+// f = the expansions chat (nb instances, stride hs) at the Legendre nodes by
+// the Taylor series about theta^cheb*; X: nb x L slabs of M values
+hipError_t run_star(const StarPlan& sp, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
+                    int64_t fs, cplx* X, hipStream_t s) {
+    trace_n = sp.N;
+    const Geo& g = sp.geo;
+    const int M = g.N;
+    const int L = sp.L;
+    const int tilesA = g.N1 / g.colsA, tilesB = g.N2 / g.rowsB;
+    // small transforms: split the terms over blocks for parallelism
+    const int QG = (tilesA * nb >= 256) ? 1 : L;
+    const int64_t xs = (int64_t)L * M;
+    traced("k_star_passA", s, [&] {
+        LEN_LAUNCH(M >= FFT_CAP, g.N2, k_star_passA, dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s, g, (int)sp.N, 0,
+                   L, QG, 0, chat, hs, X, xs);
+    });
+    traced("k_star_passB", s, [&] {
+        LEN_LAUNCH(M >= FFT_CAP, g.N1, k_star_passB, dim3(tilesB, 1, (unsigned)nb), FFT_THREADS, 0, s, g, L, 0,
+                   (const cplx*)sp.d_H, X, xs);
+    });
+    traced("k_star_passC", s, [&] {
+        LEN_LAUNCH(M >= FFT_CAP, g.N2, k_star_passC, dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s, g, (int)sp.N, L,
+                   (const cplx*)X, xs, dth, f, fs);
+    });
     return hipGetLastError();
 }
 

@@ -158,20 +158,12 @@ void rnode_build(int64_t N, RNode& r) {
     }
 }
 
-int plan_build(int64_t N, int prec, Plan& p, double tol) {
-    memset(&p.geo, 0, sizeof(p.geo));
-    p.N = N;
-    p.prec = prec;
-    if (tol > 0 && prec != PREC_FP64) return DLT_ERR_INVALID_ARG;
-    p.tol = tol;
-    const bool bulk = (prec != PREC_FP64);  // parameters for the 5e-6 budget
-    const bool f32 = (prec == PREC_FP32_BULK);
-    // ---- FFT geometry
+// Geometry and twiddle tables of the length-N DFT (N a power of two)
+static int geo_build(int64_t N, Geo& g, cplx** twN1, cplx** twN2, cplx** twHi, cplx** twLo) {
     int lg = 0;
     while ((int64_t(1) << lg) < N) ++lg;
     int l2 = lg / 2, l1 = lg - l2;  // N1 = 2^l1 >= N2 = 2^l2
     int N1 = 1 << l1, N2 = 1 << l2;
-    Geo& g = p.geo;
     g.N = (int)N;
     g.N1 = N1;
     g.N2 = N2;
@@ -181,19 +173,33 @@ int plan_build(int64_t N, int prec, Plan& p, double tol) {
     while ((1 << g.lrB) < g.rowsB) ++g.lrB;
     g.sh = (lg + 1) / 2;
     int rc;
-    if ((rc = twiddle_table(N1, N1, 1, &p.d_twN1))) return rc;
-    if ((rc = twiddle_table(N2, N2, 1, &p.d_twN2))) return rc;
-    if ((rc = twiddle_table((int)(N >> g.sh) + 1, (LD)N, 1 << g.sh, &p.d_twHi))) return rc;
-    if ((rc = twiddle_table(1 << g.sh, (LD)N, 1, &p.d_twLo))) return rc;
-    g.twN1 = p.d_twN1;
-    g.twN2 = p.d_twN2;
-    g.twHi = p.d_twHi;
-    g.twLo = p.d_twLo;
+    if ((rc = twiddle_table(N1, N1, 1, twN1))) return rc;
+    if ((rc = twiddle_table(N2, N2, 1, twN2))) return rc;
+    if ((rc = twiddle_table((int)(N >> g.sh) + 1, (LD)N, 1 << g.sh, twHi))) return rc;
+    if ((rc = twiddle_table(1 << g.sh, (LD)N, 1, twLo))) return rc;
+    g.twN1 = *twN1;
+    g.twN2 = *twN2;
+    g.twHi = *twHi;
+    g.twLo = *twLo;
     for (int k = 0; k < 4; ++k) {
         const LD a = PI_L * (LD)k / (2 * (LD)N);
         g.qs[k].re = (double)cosl(a);
         g.qs[k].im = (double)sinl(a);
     }
+    return 0;
+}
+
+int plan_build(int64_t N, int prec, Plan& p, double tol) {
+    memset(&p.geo, 0, sizeof(p.geo));
+    p.N = N;
+    p.prec = prec;
+    if (tol > 0 && prec != PREC_FP64) return DLT_ERR_INVALID_ARG;
+    p.tol = tol;
+    const bool bulk = (prec != PREC_FP64);  // parameters for the 5e-6 budget
+    const bool f32 = (prec == PREC_FP32_BULK);
+    // ---- FFT geometry
+    int rc;
+    if ((rc = geo_build(N, p.geo, &p.d_twN1, &p.d_twN2, &p.d_twHi, &p.d_twLo))) return rc;
 
     // ---- Taylor truncation (Corollary 2 with max N|dtheta| <= 0.83845)
     {
@@ -377,6 +383,7 @@ int plan_build(int64_t N, int prec, Plan& p, double tol) {
         // staging, amplitude or row-factor reads, the first tile), so more
         // groups than needed to fill the GPU cost time (measured at N = 2^20:
         // one group per pass is fastest)
+        const Geo& g = p.geo;
         int tilesA = g.N1 / g.colsA, tilesB = g.N2 / g.rowsB;
         int nt = std::max(F.nterm, 1);
         p.tgA = std::min({nt, 16, std::max(1, (512 + tilesA - 1) / tilesA)});
@@ -402,11 +409,47 @@ int plan_build(int64_t N, int prec, Plan& p, double tol) {
     return 0;
 }
 
+// Taylor terms on the theta^cheb* grid: N |theta_k - theta^cheb*_k| <=
+// N/(3 pi (2N+1)) < 1/(6 pi) (Lemma 2), so the truncation error is at most
+// ||c||_1 / ((6 pi)^L L!) (Corollary 2, second bound); L is the smallest
+// with that factor within a tenth of the FP64 budget, 5e-15 (L = 8).
+int star_terms(double tolT) {
+    int L = 1;
+    double f = 1.0 / (6 * M_PI);
+    while (f > tolT) {
+        ++L;
+        f /= 6 * M_PI * L;
+    }
+    return L;
+}
+
+int star_plan_build(int64_t N, StarPlan& s) {
+    s = StarPlan();
+    s.N = N;
+    s.L = star_terms(5e-15);
+    int rc;
+    if ((rc = geo_build(2 * N, s.geo, &s.d_twN1, &s.d_twN2, &s.d_twHi, &s.d_twLo))) return rc;
+    s.ws_per_inst = ((size_t)s.L * 2 * (size_t)N * sizeof(cplx) + 255) & ~size_t(255);
+    return 0;
+}
+
+void star_plan_free(StarPlan& s) {
+    void* ptrs[] = {s.d_twN1, s.d_twN2, s.d_twHi, s.d_twLo, s.d_H};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    s = StarPlan();
+}
+
 void plan_free(Plan& p) {
     if (p.sub) {
         plan_free(*p.sub);
         delete p.sub;
         p.sub = nullptr;
+    }
+    if (p.star) {
+        star_plan_free(*p.star);
+        delete p.star;
+        p.star = nullptr;
     }
     void* ptrs[] = {p.d_twN1,  p.d_twN2,     p.d_twHi,      p.d_twLo,     p.d_lam,
                     p.d_rcp,   p.d_guess,    p.d_tn_wgseg,  p.d_tn_segoff, p.d_tn_rgnend, p.d_near_st,

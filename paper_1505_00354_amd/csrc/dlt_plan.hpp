@@ -107,6 +107,22 @@ constexpr int PREC_FP64 = 0;
 constexpr int PREC_FP32_BULK = 1;
 constexpr int PREC_FP64_RELAXED = 2;
 
+// Evaluation on the grid theta^cheb*_k = (k+3/4) pi/(N+1/2) (Sec. 2.2): at
+// these points the sums of Sec. 2.3 are odd outputs of length-(2N+1)
+// transforms.  Each Taylor term runs as a chirp-z transform: with
+// alpha = 2 pi/(2N+1), sum_{n<N} x_n e^{i n (k+3/4) alpha} equals
+// e^{i alpha k^2/2} sum_n [x_n e^{i alpha (n^2/2 + 3n/4)}] e^{-i alpha (k-n)^2/2},
+// a cyclic convolution of power-of-two length M = 2N (inputs n < N, outputs
+// k < N, lags |k - n| < N), done with length-M DFTs.
+struct StarPlan {
+    int64_t N = 0;
+    int L = 8;               // Taylor terms: smallest L with 1/((6 pi)^L L!) <= 5e-15
+    Geo geo{};               // the length-M DFT (M = 2N)
+    cplx *d_twN1 = nullptr, *d_twN2 = nullptr, *d_twHi = nullptr, *d_twLo = nullptr;
+    cplx* d_H = nullptr;     // (1/M) DFT of the cyclic chirp, in the blocked layout
+    size_t ws_per_inst = 0;  // L slabs of M complex values
+};
+
 struct Plan {
     int64_t N = 0;
     int prec = PREC_FP64;
@@ -151,6 +167,8 @@ struct Plan {
     // low-degree block n < nd when nd exceeds the dense limit: the same
     // transform at size nd (owned)
     Plan* sub = nullptr;
+    // theta^cheb* evaluation of this size (FP64 plans; built on first use, owned)
+    StarPlan* star = nullptr;
 };
 
 // Builds the plan for size N (power of two, 1 <= N <= MAX_N) and precision
@@ -159,5 +177,12 @@ struct Plan {
 // set for the working tolerance tol instead of the mode's fixed budget.
 int plan_build(int64_t N, int prec, Plan& p, double tol = 0);
 void plan_free(Plan& p);
+// Host part of the theta^cheb* plan of size N (power of two): geometry,
+// twiddle tables, term count and workspace; d_H is formed on the device
+// (star_prepare).  Returns 0 or a DLT status code.
+int star_plan_build(int64_t N, StarPlan& s);
+// Taylor terms about theta^cheb* for a truncation budget tolT (times ||c||_1)
+int star_terms(double tolT);
+void star_plan_free(StarPlan& s);
 
 }  // namespace dlt

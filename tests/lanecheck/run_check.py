@@ -95,6 +95,13 @@ def main(argv):
     # a batch that runs in several workspace slices
     for name in ("dlt_forward", "dlt_inverse"):
         unary(name, 1 << 20, 64, prec="fp32bulk")
+    # the evaluation about theta^cheb* (every kernel on the caller's stream),
+    # and a batch of it in slices
+    for name in ("cheb_eval_leggrid_grid", "dlt_forward_grid"):
+        f = getattr(L, name)
+        f.argtypes = [i64, i64, vp, vp, ctypes.c_int, vp]
+        for N, batch in ((1, 2), (1024, 2), (1 << 16, 3), (1 << 20, 2), (1 << 20, 14)):
+            call(f"{name} N={N} b={batch}", f, N, batch, buf("in", N * batch), buf("out", N * batch), 1)
     for name in ("leg2chebvals", "chebvals2leg"):
         f = getattr(L, name)
         f.argtypes = [i64, i64, vp, vp, vp]
