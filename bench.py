@@ -148,10 +148,11 @@ def stored_traffic(kernel):
 
 
 def grid_runs(pk, wl, torch, np, dev, N, reps, checks=None):
-    """cheb_eval_leggrid and dlt_forward (FP64) with the Taylor series about
-    theta^cheb1 and about theta^cheb*, K calls each; the theta^cheb* kernels'
-    rooflines from 3 traced calls; the theta^cheb* forward's error against the
-    oracle (appended to `checks`, run in the CPU leg)."""
+    """cheb_eval_leggrid, dlt_forward and dlt_inverse (FP64) with the Taylor
+    series about theta^cheb1 and about theta^cheb*, K calls each; the
+    theta^cheb* kernels' rooflines from 3 traced evaluations; the
+    theta^cheb* forward's error against the oracle (appended to `checks`,
+    run in the CPU leg)."""
     c = torch.from_numpy(wl.coeffs_algebraic(N, 2)[0]).to(dev)
     chat = torch.from_numpy(wl.coeffs_algebraic(N, 3)[0]).to(dev)
     f = torch.empty_like(c)
@@ -167,8 +168,9 @@ def grid_runs(pk, wl, torch, np, dev, N, reps, checks=None):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
+    fin = torch.from_numpy(wl.values_normal(N, 4)[0]).to(dev)
     res = {"N": N}
-    for op, x in (("cheb_eval_leggrid", chat), ("dlt_forward", c)):
+    for op, x in (("cheb_eval_leggrid", chat), ("dlt_forward", c), ("dlt_inverse", fin)):
         fn = getattr(pk, op)
         t1 = timed_fn(lambda: fn(x, out=f))
         ts = timed_fn(lambda: fn(x, out=f, grid="chebstar"))

@@ -183,8 +183,10 @@ int dlt_forward_tol(int64_t N, int64_t batch, const double* c, double* f, double
 int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double eps, hipStream_t stream);
 int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double eps, hipStream_t stream);
 
-/* cheb_eval_leggrid (eq. (3)) and dlt_forward (eq. (1)) with the Taylor
- * series of Sec. 2.3 taken about another equispaced grid, chosen by `grid`:
+/* cheb_eval_leggrid (eq. (3)), dlt_forward (eq. (1)) and dlt_inverse (eq.
+ * (2), through eq. (10): the transposed evaluation y = T^T D_w f about the
+ * grid) with the Taylor series of Sec. 2.3 taken about another equispaced
+ * grid, chosen by `grid`:
  *   DLT_GRID_CHEB1     theta^cheb1_k = (k+1/2) pi/N: the same calls as the
  *                      plain entry points;
  *   DLT_GRID_CHEBSTAR  theta^cheb*_k = (k+3/4) pi/(N+1/2), the zeros of the
@@ -210,6 +212,7 @@ int cheb2leg_tol(int64_t N, int64_t batch, const double* chat, double* c, double
 #define DLT_GRID_CHEBSTAR 1
 int cheb_eval_leggrid_grid(int64_t N, int64_t batch, const double* chat, double* f, int grid, hipStream_t stream);
 int dlt_forward_grid(int64_t N, int64_t batch, const double* c, double* f, int grid, hipStream_t stream);
+int dlt_inverse_grid(int64_t N, int64_t batch, const double* f, double* c, int grid, hipStream_t stream);
 
 /* Ragged batch: `count` independent transforms of uneven sizes in one call
  * (many transforms of different N, forward and inverse mixed).

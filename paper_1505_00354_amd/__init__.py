@@ -76,7 +76,7 @@ def lib():
         L.dlt_batch_ex.restype = ctypes.c_int
         L.dlt_batch_grid.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
         L.dlt_batch_grid.restype = ctypes.c_int
-        for name in ("cheb_eval_leggrid_grid", "dlt_forward_grid"):
+        for name in ("cheb_eval_leggrid_grid", "dlt_forward_grid", "dlt_inverse_grid"):
             getattr(L, name).argtypes = [i64, i64, vp, vp, ctypes.c_int, vp]
             getattr(L, name).restype = ctypes.c_int
         L.dlt_status_string.argtypes = [ctypes.c_int]
@@ -196,9 +196,11 @@ def dlt_forward_noalloc(c, out=None):
     return out
 
 
-def dlt_inverse(f, out=None, prec="fp64", tol=None):
-    """Inverse transform c_n = (n+1/2) sum_k w_k f_k P_n(x_k)."""
-    return _unary("dlt_inverse", f, out, prec, tol)
+def dlt_inverse(f, out=None, prec="fp64", tol=None, grid="cheb1"):
+    """Inverse transform c_n = (n+1/2) sum_k w_k f_k P_n(x_k).  grid: the
+    Taylor expansion point of its transposed evaluation, "cheb1" or
+    "chebstar" (FP64, N a power of two)."""
+    return _unary("dlt_inverse", f, out, prec, tol, grid)
 
 
 def cheb_eval_nodes(chat, dtheta, out=None):

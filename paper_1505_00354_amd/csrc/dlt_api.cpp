@@ -1061,15 +1061,17 @@ static int get_star(Plan* p, StarPlan** out) {
     return DLT_OK;
 }
 
-// cheb_eval_leggrid (from_leg false) or dlt_forward (true) about theta^cheb*,
-// every kernel on `stream`, in slices that keep the workspace within WS_CAP
-static int star_call(int64_t N, int64_t batch, const double* in, double* f, bool from_leg, hipStream_t stream) {
+// cheb_eval_leggrid (op 0), dlt_forward (op 1) or dlt_inverse (op 2) about
+// theta^cheb*, every kernel on `stream`, in slices that keep the workspace
+// within WS_CAP
+static int star_call(int64_t N, int64_t batch, const double* in, double* f, int op, hipStream_t stream) {
+    const bool from_leg = op == 1, inverse = op == 2;
     Plan* p;
     int rc;
     if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
     StarPlan* sp;
     if ((rc = get_star(p, &sp))) return rc;
-    const size_t per = sp->ws_per_inst + (from_leg ? p->ws_per_inst : 0);
+    const size_t per = sp->ws_per_inst + (op != 0 ? p->ws_per_inst : 0);
     int64_t nb = batch;
     if ((size_t)nb * per > WS_CAP) {
         const int64_t nbmax = std::max<int64_t>(1, (int64_t)(WS_CAP / per));
@@ -1079,16 +1081,23 @@ static int star_call(int64_t N, int64_t batch, const double* in, double* f, bool
     void* base = nullptr;
     if ((rc = get_ws(stream, p->ws_shared + (size_t)nb * per, &base))) return rc;
     const size_t vecb = ((size_t)N * sizeof(double) + 255) & ~size_t(255);
-    double* dth = (double*)((char*)base + 2 * vecb);  // the layout of setup_call
+    double* wts = (double*)((char*)base + vecb);  // the layout of setup_call
+    double* dth = (double*)((char*)base + 2 * vecb);
     char* q = (char*)base + p->ws_shared;
     cplx* X = (cplx*)q;  // nb x L slabs of 2N values
     Work work;
-    if (from_leg) work_carve(*p, nb, q + (size_t)nb * sp->ws_per_inst, work);
+    if (op != 0) work_carve(*p, nb, q + (size_t)nb * sp->ws_per_inst, work);
     Lanes L;  // the caller's stream only
     L.s = stream;
-    rc = hip_status(run_nodes(*p, nullptr, nullptr, dth, L));
+    rc = hip_status(run_nodes(*p, nullptr, inverse ? wts : nullptr, dth, L));
     for (int64_t b0 = 0; rc == DLT_OK && b0 < batch; b0 += nb) {
         const int64_t n = std::min(nb, batch - b0);
+        if (inverse) {
+            // y = T^T D_w f about theta^cheb*, then c = D_s M^T y (Sec. 4)
+            rc = hip_status(run_star(*sp, n, in + b0 * N, N, wts, dth, work.chat, work.schat, X, stream));
+            if (rc == DLT_OK) rc = hip_status(run_leg2cheb_t(*p, n, work.chat, work.schat, f + b0 * N, N, 1, work, L));
+            continue;
+        }
         const double* chat = in + b0 * N;
         int64_t hs = N;
         if (from_leg) {
@@ -1096,7 +1105,7 @@ static int star_call(int64_t N, int64_t batch, const double* in, double* f, bool
             chat = work.chat;
             hs = work.schat;
         }
-        if (rc == DLT_OK) rc = hip_status(run_star(*sp, n, chat, hs, dth, f + b0 * N, N, X, stream));
+        if (rc == DLT_OK) rc = hip_status(run_star(*sp, n, chat, hs, nullptr, dth, f + b0 * N, N, X, stream));
     }
     return rc;
 }
@@ -1115,7 +1124,7 @@ int cheb_eval_leggrid_grid(int64_t N, int64_t batch, const double* chat, double*
     if (grid != DLT_GRID_CHEBSTAR) return DLT_ERR_INVALID_ARG;
     int rc = grid_args(N, batch, chat, f);
     if (rc || batch == 0) return rc;
-    return star_call(N, batch, chat, f, false, stream);
+    return star_call(N, batch, chat, f, 0, stream);
 }
 
 int dlt_forward_grid(int64_t N, int64_t batch, const double* c, double* f, int grid, hipStream_t stream) {
@@ -1123,7 +1132,15 @@ int dlt_forward_grid(int64_t N, int64_t batch, const double* c, double* f, int g
     if (grid != DLT_GRID_CHEBSTAR) return DLT_ERR_INVALID_ARG;
     int rc = grid_args(N, batch, c, f);
     if (rc || batch == 0) return rc;
-    return star_call(N, batch, c, f, true, stream);
+    return star_call(N, batch, c, f, 1, stream);
+}
+
+int dlt_inverse_grid(int64_t N, int64_t batch, const double* f, double* c, int grid, hipStream_t stream) {
+    if (grid == DLT_GRID_CHEB1) return dlt_inverse(N, batch, f, c, stream);
+    if (grid != DLT_GRID_CHEBSTAR) return DLT_ERR_INVALID_ARG;
+    int rc = grid_args(N, batch, f, c);
+    if (rc || batch == 0) return rc;
+    return star_call(N, batch, f, c, 2, stream);
 }
 
 int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {

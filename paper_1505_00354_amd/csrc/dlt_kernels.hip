@@ -1484,6 +1484,12 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
 // transform in place (k_star_passB), pass A of the conjugate transform with
 // the Horner sum over l and the output chirp (k_star_passC).  Between the
 // passes the data keep the blocked layout of the other transforms.
+// The transposed evaluation of the inverse transform (Sec. 4),
+//   y_n = sum_k g_k cos(n theta_k) = Re sum_l (n/N)^l i^l G_l(n),
+//   G_l(n) = sum_{k<N} (g_k d_k^l/l!) e^{i n theta*_k},
+// is the same convolution with the chirps' roles exchanged: the input
+// chirp e^{i alpha k^2/2} on g_k d_k^l/l!, the output chirp
+// e^{i alpha (n^2/2 + 3n/4)}, and the Horner sum in n/N.
 
 // e^{i pi r/den} for 0 <= r < 2 den (r an exact integer reduction)
 __device__ __forceinline__ cplx cispi_frac(int64_t r, int64_t den) {
@@ -1502,12 +1508,16 @@ __device__ __forceinline__ cplx star_chirp_out(int64_t k, int64_t P) {
 
 // Pass A of F^+ over M = 2N for the terms [qa, qb) (slab l - qa of X; block
 // row blockIdx.y takes an equal share of them), inputs zero for n >= N.
-// With table = 1 it forms instead the cyclic chirp h~[j] = h[j] (j < N),
-// h[2N - j] (j > N), 0 (j = N), into slab 0.
+// mode 0: the terms (n/N)^l chat_n of the evaluation (`in` = chat);
+// mode 2: the terms g_k d_k^l/l! of the transposed evaluation, g = wts * in
+// (`in` = f), d_k from the node offsets dth;
+// mode 1: the cyclic chirp h~[j] = h[j] (j < N), h[2N - j] (j > N), 0
+// (j = N), into slab 0.
 template <int LA>
-__global__ FFT_BOUNDS void k_star_passA(Geo g, int N, int qa, int qb, int QG, int table,
-                                        const double* __restrict__ chat, int64_t chat_stride, cplx* __restrict__ X,
-                                        int64_t x_stride) {
+__global__ FFT_BOUNDS void k_star_passA(Geo g, int N, int qa, int qb, int QG, int mode,
+                                        const double* __restrict__ chat, int64_t chat_stride,
+                                        const double* __restrict__ wts, const double* __restrict__ dth,
+                                        cplx* __restrict__ X, int64_t x_stride) {
     __shared__ cplx buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, double);
     const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
@@ -1520,7 +1530,7 @@ __global__ FFT_BOUNDS void k_star_passA(Geo g, int N, int qa, int qb, int QG, in
     cplx* Xb = X + b * x_stride;
     const PassAOut<LA, false> out(g, T, na0);
     HeldPut<LA, false, double> held(out, g, T);
-    if (table) {
+    if (mode == 1) {
         cplx v[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
@@ -1534,25 +1544,39 @@ __global__ FFT_BOUNDS void k_star_passA(Geo g, int N, int qa, int qb, int QG, in
         return;
     }
     const double invN = 1.0 / N;
+    const double dsh = M_PI / (2.0 * (double)P);
     const int q0 = qa + ((qb - qa) * (int)blockIdx.y) / QG, q1 = qa + ((qb - qa) * ((int)blockIdx.y + 1)) / QG;
-    cplx A[FFT_VPT];  // (n/N)^l chat_n e^{i alpha (n^2/2 + 3n/4)}, carried from term to term
+    // A: the term-l input times the input chirp, carried from term to term
+    // by the factor r: (n/N)^l chat_n e^{i alpha (n^2/2 + 3n/4)}, r = n/N
+    // (mode 0); g_k d_k^l/l! e^{i alpha k^2/2}, r = d_k/(l+1) (mode 2)
+    cplx A[FFT_VPT];
+    double r[FFT_VPT];
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         A[s] = {0, 0};
+        r[s] = 0;
         const int n = na0 + T.col(s) + g.N1 * T.idx(s);
         if (T.live(s) && n < N) {
-            double a = cb[n];
-            for (int l = 0; l < q0; ++l) a *= n * invN;
-            A[s] = cscale(star_chirp_in(n, P), a);
+            if (mode == 0) {
+                r[s] = n * invN;
+                double a = cb[n];
+                for (int l = 0; l < q0; ++l) a *= r[s];
+                A[s] = cscale(star_chirp_in(n, P), a);
+            } else {
+                r[s] = (double)N * dth[n] + dsh * (double)(2 * n - N + 1);
+                double a = wts[n] * cb[n];
+                for (int l = 0; l < q0; ++l) a *= r[s] / (l + 1);
+                A[s] = cscale(star_chirp_out(n, P), a);
+            }
         }
     }
     for (int l = q0; l < q1; ++l) {
         cplx v[FFT_VPT];
+        const double fl = (mode == 0) ? 1.0 : 1.0 / (l + 1);
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
-            const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             v[s] = A[s];
-            A[s] = cscale(A[s], n * invN);
+            A[s] = cscale(A[s], r[s] * fl);
         }
         tile_fft<LA>(v, buf, twA, T, held);
         held.hold(v, Xb + (int64_t)(l - qa) * M);
@@ -1613,9 +1637,10 @@ __global__ FFT_BOUNDS void k_star_passB(Geo g, int nterm, int fwd_only, const cp
 //   S = a_{L-1};  S = a_l + (d_k/(l+1)) S,  a_l = i^l conj(F+_A(Y_l twiddled)),
 // then f_k = Re(e^{i alpha k^2/2} S) for the outputs k < N;
 // d_k = N (theta_k - theta*_k) = N dth_k + pi (2k - N + 1)/(2(2N+1)), dth
-// the node offsets from theta^cheb1.
+// the node offsets from theta^cheb1.  With trans (the transposed
+// evaluation): S = a_l + (n/N) S and y_n = Re(e^{i alpha (n^2/2 + 3n/4)} S).
 template <int LA>
-__global__ FFT_BOUNDS void k_star_passC(Geo g, int N, int L, const cplx* __restrict__ X, int64_t x_stride,
+__global__ FFT_BOUNDS void k_star_passC(Geo g, int N, int L, int trans, const cplx* __restrict__ X, int64_t x_stride,
                                         const double* __restrict__ dth, double* __restrict__ f, int64_t f_stride) {
     __shared__ cplx buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, double);
@@ -1636,7 +1661,7 @@ __global__ FFT_BOUNDS void k_star_passC(Geo g, int N, int L, const cplx* __restr
         const int na = na0 + T.col(s), k = na + g.N1 * T.idx(s);
         off[s] = passA_offset(g, na, T.idx(s), false);
         out[s] = T.live(s) && k < N;
-        d[s] = out[s] ? (double)N * dth[k] + dsh * (double)(2 * k - N + 1) : 0.0;
+        d[s] = !out[s] ? 0.0 : trans ? (double)k / N : (double)N * dth[k] + dsh * (double)(2 * k - N + 1);
     }
     cplx S[FFT_VPT], nx[FFT_VPT];
 #pragma unroll
@@ -1653,7 +1678,7 @@ __global__ FFT_BOUNDS void k_star_passC(Geo g, int N, int L, const cplx* __restr
                 if (T.live(s)) nx[s] = Xb[(int64_t)(l - 1) * M + off[s]];
         }
         tile_fft<LA>(v, buf, twA, T);
-        const double r = 1.0 / (l + 1);
+        const double r = trans ? 1.0 : 1.0 / (l + 1);
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
             const cplx z = cconj(v[s]);
@@ -1673,7 +1698,7 @@ __global__ FFT_BOUNDS void k_star_passC(Geo g, int N, int L, const cplx* __restr
     for (int s = 0; s < FFT_VPT; ++s) {
         if (out[s]) {
             const int k = na0 + T.col(s) + g.N1 * T.idx(s);
-            const cplx c2 = star_chirp_out(k, P);
+            const cplx c2 = trans ? star_chirp_in(k, P) : star_chirp_out(k, P);
             fb[k] = c2.re * S[s].re - c2.im * S[s].im;
         }
     }
@@ -2841,7 +2866,7 @@ hipError_t star_prepare(StarPlan& sp) {
     if (e != hipSuccess) return e;
     const int tilesA = g.N1 / g.colsA, tilesB = g.N2 / g.rowsB;
     LEN_LAUNCH(M >= FFT_CAP, g.N2, k_star_passA, dim3(tilesA, 1, 1), FFT_THREADS, 0, 0, g, (int)sp.N, 0, 1, 1, 1,
-               (const double*)nullptr, (int64_t)0, sp.d_H, (int64_t)0);
+               (const double*)nullptr, (int64_t)0, (const double*)nullptr, (const double*)nullptr, sp.d_H, (int64_t)0);
     LEN_LAUNCH(M >= FFT_CAP, g.N1, k_star_passB, dim3(tilesB, 1, 1), FFT_THREADS, 0, 0, g, 1, 1, (const cplx*)nullptr,
                sp.d_H, (int64_t)0);
     e = hipGetLastError();
@@ -2850,9 +2875,10 @@ hipError_t star_prepare(StarPlan& sp) {
 }
 
 // f = the expansions chat (nb instances, stride hs) at the Legendre nodes by
-// the Taylor series about theta^cheb*; X: nb x L slabs of M values
-hipError_t run_star(const StarPlan& sp, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
-                    int64_t fs, cplx* X, hipStream_t s) {
+// the Taylor series about theta^cheb*, or with wts (the transposed
+// evaluation) y = T^T (wts * in) into f; X: nb x L slabs of M values
+hipError_t run_star(const StarPlan& sp, int64_t nb, const double* chat, int64_t hs, const double* wts,
+                    const double* dth, double* f, int64_t fs, cplx* X, hipStream_t s) {
     trace_n = sp.N;
     const Geo& g = sp.geo;
     const int M = g.N;
@@ -2863,7 +2889,7 @@ hipError_t run_star(const StarPlan& sp, int64_t nb, const double* chat, int64_t 
     const int64_t xs = (int64_t)L * M;
     traced("k_star_passA", s, [&] {
         LEN_LAUNCH(M >= FFT_CAP, g.N2, k_star_passA, dim3(tilesA, QG, (unsigned)nb), FFT_THREADS, 0, s, g, (int)sp.N, 0,
-                   L, QG, 0, chat, hs, X, xs);
+                   L, QG, wts ? 2 : 0, chat, hs, wts, dth, X, xs);
     });
     traced("k_star_passB", s, [&] {
         LEN_LAUNCH(M >= FFT_CAP, g.N1, k_star_passB, dim3(tilesB, 1, (unsigned)nb), FFT_THREADS, 0, s, g, L, 0,
@@ -2871,7 +2897,7 @@ hipError_t run_star(const StarPlan& sp, int64_t nb, const double* chat, int64_t 
     });
     traced("k_star_passC", s, [&] {
         LEN_LAUNCH(M >= FFT_CAP, g.N2, k_star_passC, dim3(tilesA, 1, (unsigned)nb), FFT_THREADS, 0, s, g, (int)sp.N, L,
-                   (const cplx*)X, xs, dth, f, fs);
+                   wts ? 1 : 0, (const cplx*)X, xs, dth, f, fs);
     });
     return hipGetLastError();
 }

@@ -88,10 +88,12 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
 // theta^cheb* evaluation: star_prepare forms the plan's H table (allocates,
 // synchronises the device); run_star evaluates nb expansions chat (stride hs)
 // at the Legendre nodes (dth: offsets from theta^cheb1) into f (stride fs),
-// on stream s only, with X holding nb x L slabs of 2N complex values.
+// or, given the weights wts, the transposed evaluation y_n = sum_k wts_k
+// in_k T_n(x_k) of in = chat into f; on stream s only, with X holding
+// nb x L slabs of 2N complex values.
 hipError_t star_prepare(StarPlan& sp);
-hipError_t run_star(const StarPlan& sp, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
-                    int64_t fs, cplx* X, hipStream_t s);
+hipError_t run_star(const StarPlan& sp, int64_t nb, const double* chat, int64_t hs, const double* wts,
+                    const double* dth, double* f, int64_t fs, cplx* X, hipStream_t s);
 
 // c = D_s M^T T^T D_w f (inverse transform), wts/dth from the nodes; with
 // `rr` the inputs are f + rr->offs[b] paired through rr (wts, dth unused) and

@@ -97,7 +97,7 @@ def main(argv):
         unary(name, 1 << 20, 64, prec="fp32bulk")
     # the evaluation about theta^cheb* (every kernel on the caller's stream),
     # and a batch of it in slices
-    for name in ("cheb_eval_leggrid_grid", "dlt_forward_grid"):
+    for name in ("cheb_eval_leggrid_grid", "dlt_forward_grid", "dlt_inverse_grid"):
         f = getattr(L, name)
         f.argtypes = [i64, i64, vp, vp, ctypes.c_int, vp]
         for N, batch in ((1, 2), (1024, 2), (1 << 16, 3), (1 << 20, 2), (1 << 20, 14)):

@@ -3,9 +3,12 @@
 theta^cheb*_k = (k+3/4) pi/(N+1/2) (Sec. 2.2, Lemma 2; Remark 1), against the
 oracle at the points the GPU path evaluates at: the full vector up to 16384,
 sampled outputs (both ends included) at 2^16 and 2^20; the DLT up to 2^18;
-batches, including one that runs in workspace slices; the same results as
-about theta^cheb1 to the same bar; the argument checks; the kernel names in
-the trace.  Bar: the FP64 target 5e-14 * ||c||_1."""
+the IDLT (its transposed evaluation about theta^cheb*, eq. (10)) on every
+degree up to 2^16 and on sampled degrees up to 2^18 at N = 2^20, and the
+round trip; batches, including one that runs in workspace slices; the same
+results as about theta^cheb1 to the same bar; the argument checks; the
+kernel names in the trace.  Bars: the FP64 targets 5e-14 * ||c||_1 (DLT,
+evaluation) and 5e-14 (n+1/2) sum_k w_k |f_k| (IDLT)."""
 import ctypes
 
 import numpy as np
@@ -69,6 +72,54 @@ def test_chebstar_forward(pk, orc, N):
         assert err <= TOL
 
 
+def _idlt_err(c, ref, w, f, idx):
+    return float(np.max(np.abs(c - ref) / ((idx + 0.5) * np.sum(w * np.abs(f)))))
+
+
+@pytest.mark.parametrize("N,top", [(1, 1), (2, 2), (16, 16), (1024, 1024), (16384, 16384), (1 << 16, 4096),
+                                   (1 << 20, 16384)])
+def test_chebstar_inverse(pk, orc, N, top):
+    # the inverse transform with its transposed evaluation about theta^cheb*
+    # (eq. (10)), against the oracle's IDLT at the GPU's nodes and weights on
+    # every degree up to 16384 and on sampled degrees below `top` beyond
+    # (the oracle's cost grows with the top degree; the evaluation feeds
+    # every degree alike); on every degree against the inverse about
+    # theta^cheb1
+    say("chebstar idlt", N)
+    f = wl.values_normal(N, 33)[0]
+    c = to_host(pk.dlt_inverse(to_dev(f), grid="chebstar"))
+    _, w, d = (to_host(t)[0] for t in pk.leg_nodes_weights(N))
+    hi, lo = exact_angles(N, d)
+    if N <= 16384:
+        idx = np.arange(top)
+    else:
+        idx = np.array(sorted(set(int(i) for i in wl.sample_indices(top, 96, 34)) | {0, 1, top - 2, top - 1}),
+                       dtype=np.int64)
+    ref = orc.idlt(f, hi, w, idx=idx, prec="d", theta_lo=lo)
+    err = _idlt_err(c[idx], ref, w, f, idx)
+    say("  err", err)
+    assert err <= TOL
+    c1 = to_host(pk.dlt_inverse(to_dev(f)))
+    n = np.arange(N)
+    dd = _idlt_err(c, c1, w, f, n)
+    say("  vs cheb1, every degree", dd)
+    assert dd <= TOL
+
+
+def test_chebstar_roundtrip(pk):
+    # dlt_inverse(dlt_forward(c)) about theta^cheb* returns c (2^16, family A)
+    N = 1 << 16
+    c = wl.coeffs_algebraic(N, 35)[0]
+    f = pk.dlt_forward(to_dev(c), grid="chebstar")
+    c2 = to_host(pk.dlt_inverse(f, grid="chebstar"))
+    fh = to_host(f)
+    w = to_host(pk.leg_nodes_weights(N)[1])[0]
+    n = np.arange(N)
+    err = float(np.max(np.abs(c2 - c) / ((n + 0.5) * np.sum(w * np.abs(fh)))))
+    say("chebstar roundtrip", N, err)
+    assert err <= TOL
+
+
 def test_chebstar_batches(pk, orc):
     # batch 3 at 4096 (full vectors), and 14 instances at 2^20, which the
     # workspace bound splits into slices (the forward's own work plus 8 x 2N
@@ -108,6 +159,8 @@ def test_chebstar_arguments(pk):
     assert L.cheb_eval_leggrid_grid(1024, 1, vp(x), vp(y), 7, s) == pk.DLT_ERR_INVALID_ARG
     assert L.dlt_forward_grid(1024, 1, vp(x), vp(x), pk.DLT_GRID_CHEBSTAR, s) == pk.DLT_ERR_INVALID_ARG
     assert L.dlt_forward_grid(1024, 0, vp(x), vp(y), pk.DLT_GRID_CHEBSTAR, s) == pk.DLT_OK
+    assert L.dlt_inverse_grid(3000, 1, vp(x), vp(y), pk.DLT_GRID_CHEBSTAR, s) == pk.DLT_ERR_UNSUPPORTED
+    assert L.dlt_inverse_grid(1024, 1, vp(x), vp(y), -1, s) == pk.DLT_ERR_INVALID_ARG
     with pytest.raises(ValueError):
         pk.dlt_forward(x[:1024], grid="chebstar", prec="fp32bulk")
     with pytest.raises(ValueError):
