@@ -484,13 +484,20 @@ __global__ __launch_bounds__(256) void k_dense(int N, int nd, int chunk, const d
     }
     __syncthreads();
     if (k >= nd) return;
-    double acc = 0;
     int n = max(n0, k);
     if ((n - k) & 1) ++n;
-    for (; n < n1; n += 2) {
-        int im = ((n - k) >> 1) - zm0, ip = ((n + k) >> 1) - zp0;
-        acc = fma(slm[im] * slp[ip], sc[n - n0], acc);
+    // four columns per step into four sums: the LDS reads of a step are
+    // independent, so they overlap instead of each waiting for the last
+    int im = ((n - k) >> 1) - zm0, ip = ((n + k) >> 1) - zp0, ic = n - n0;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (; n + 6 < n1; n += 8, im += 4, ip += 4, ic += 8) {
+        a0 = fma(slm[im] * slp[ip], sc[ic], a0);
+        a1 = fma(slm[im + 1] * slp[ip + 1], sc[ic + 2], a1);
+        a2 = fma(slm[im + 2] * slp[ip + 2], sc[ic + 4], a2);
+        a3 = fma(slm[im + 3] * slp[ip + 3], sc[ic + 6], a3);
     }
+    for (; n < n1; n += 2, ++im, ++ip, ic += 2) a0 = fma(slm[im] * slp[ip], sc[ic], a0);
+    const double acc = (a0 + a1) + (a2 + a3);
     double e = (k == 0) ? 0.3183098861837907 : 0.6366197723675814;  // eps_k / pi
     pb[(int64_t)ch * nd + k] = e * acc;
 }
@@ -1943,15 +1950,20 @@ __global__ __launch_bounds__(256) void k_dense_t(int nd, int chunk, const double
     }
     __syncthreads();
     if (n >= nd) return;
-    double acc = 0;
     int kk = k0;
     if ((n - kk) & 1) ++kk;
-    int kend = min(k1, n + 1);
-    for (; kk < kend; kk += 2) {
-        int im = ((n - kk) >> 1) - zm0, ip = ((n + kk) >> 1) - zp0;
-        acc = fma(slm[im] * slp[ip], sy[kk - k0], acc);
+    const int kend = min(k1, n + 1);
+    // four rows per step into four sums (as in k_dense)
+    int im = ((n - kk) >> 1) - zm0, ip = ((n + kk) >> 1) - zp0, iy = kk - k0;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (; kk + 6 < kend; kk += 8, im -= 4, ip += 4, iy += 8) {
+        a0 = fma(slm[im] * slp[ip], sy[iy], a0);
+        a1 = fma(slm[im - 1] * slp[ip + 1], sy[iy + 2], a1);
+        a2 = fma(slm[im - 2] * slp[ip + 2], sy[iy + 4], a2);
+        a3 = fma(slm[im - 3] * slp[ip + 3], sy[iy + 6], a3);
     }
-    part[b * part_stride + (int64_t)ch * nd + n] = acc;
+    for (; kk < kend; kk += 2, --im, ++ip, iy += 2) a0 = fma(slm[im] * slp[ip], sy[iy], a0);
+    part[b * part_stride + (int64_t)ch * nd + n] = (a0 + a1) + (a2 + a3);
 }
 
 __global__ void k_dense_t_reduce(int nd, int nchunk, int chunk, const double* __restrict__ part,
