@@ -28,7 +28,10 @@ struct Work {
 // the side streams (default priority) and are joined back through events.
 // With no side streams everything runs on `s`.
 constexpr int LANE_SIDES = 3;
-constexpr int LANE_EVENTS = 16;
+constexpr int LANE_EVENTS = 18;
+// largest size whose inverse runs its nested transposed conversion's low
+// block on a side stream of its own
+constexpr int64_t NESTED_LOW_MAX_N = int64_t(1) << 18;
 struct Lanes {
     hipStream_t s = nullptr;
     hipStream_t side[LANE_SIDES] = {};
@@ -36,6 +39,10 @@ struct Lanes {
     // the near field goes on side[2] directly, after work already ordered
     // there (no fork from s)
     bool near_inline = false;
+    // the low block goes on side[1] directly: the caller of a nested run
+    // forked that stream from its own stream (so no side stream waits on
+    // another that also waits on it)
+    bool low_inline = false;
     hipStream_t aux(int i) const { return side[i] ? side[i] : s; }
     // the same call on one stream only (used for nested runs)
     Lanes on(hipStream_t st) const {
@@ -54,6 +61,19 @@ struct Lanes {
         l.near_inline = true;
         l.ev[4] = ev[14];
         l.ev[14] = ev[15];
+        return l;
+    }
+    // the transposed conversion nested in the inverse's: its low block on
+    // this run's first side stream (forked by the caller with event 16,
+    // joined into st with event 17), the rest on st
+    Lanes nested_leg2cheb_t(hipStream_t st) const {
+        Lanes l;
+        l.s = st;
+        if (side[0] && ev[16] && ev[17]) {
+            l.side[1] = side[0];
+            l.low_inline = true;
+            l.ev[9] = ev[17];
+        }
         return l;
     }
 };
