@@ -685,9 +685,9 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
 }
 // the same with each XCD's range split into a run from the front and its
 // mirror image from the back (tiles t and ntiles - 1 - t on one XCD): the
-// Taylor pass B stores grid rows 2m and 2m + 1 from the tiles of columns
-// m mod N2 and N2 - 1 - m mod N2, so each output line is then completed in
-// one L2
+// passes that store or load vectors in grid-row order (rows 2m and 2m + 1
+// come from the tiles of m and N - 1 - m, which are mirror tiles) then
+// complete or consume each line in one L2
 __device__ __forceinline__ int xcd_tile_mirror(int bid, int ntiles) {
     if (ntiles & 15) return xcd_tile(bid, ntiles);
     const int half = ntiles >> 4, x = bid & 7, k = bid >> 3;
@@ -979,7 +979,7 @@ __global__ FFT_BOUNDS void k_far_passB(Geo g, FarParams F, int G, const cplx* __
     const Tile<LB> T(g.rowsB, g.N1);
     const FarTerms FT(F);
     const int N = g.N;
-    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int jb0 = xcd_tile_mirror(blockIdx.x, gridDim.x) * T.cols();
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const cplxT<R>* Xb = X + b * x_stride;
@@ -1262,7 +1262,7 @@ __global__ FFT_BOUNDS void k_dct2_passA(Geo g, int G, const double* __restrict__
     const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
-    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int na0 = xcd_tile_mirror(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const double* vb = v + b * v_stride;
     const double* nb = near + b * near_stride;
@@ -1729,7 +1729,7 @@ __global__ FFT_BOUNDS void k_tndct_passA(Geo g, int qa, int qb, int QG, const do
     const cplxT<R>* twA = stage_twiddles<LA, R>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
-    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int na0 = xcd_tile_mirror(blockIdx.x, gridDim.x) * T.cols();
     const int grp = blockIdx.y;
     const int b = blockIdx.z;
     const double* fb = fv + b * f_stride;
@@ -2013,7 +2013,7 @@ __global__ FFT_BOUNDS void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64
     const cplx* twB = stage_twiddles<LB, double>(stw, g.twN1, g.N1);
     const Tile<LB> T(g.rowsB, g.N1);
     const int N = g.N;
-    const int jb0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int jb0 = xcd_tile_mirror(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     cplx z[FFT_VPT];
     passB_load<LB, double>(g, jb0, X + b * x_stride, z, T);
@@ -2042,7 +2042,7 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const cplx* _
     const Tile<LA> T(g.colsA, g.N2);
     const FarTerms FT(F);
     const int N = g.N;
-    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int na0 = xcd_tile_mirror(blockIdx.x, gridDim.x) * T.cols();
     const int b = blockIdx.z;
     const double* ub = u + b * u_stride;
     cplxT<R>* Xb = X + b * x_stride;
