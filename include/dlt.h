@@ -27,8 +27,9 @@
  *     same size; other N run on the next power-of-two grid, with the inputs
  *     zero-padded and every Legendre node paired with its nearest grid point
  *     (more Taylor terms, same accuracy).
- *   - The library keeps per-N plans (twiddle and coefficient tables, and the
- *     input-independent near-field recurrence states, formed on the device)
+ *   - The library keeps per-N plans (twiddle and coefficient tables, the
+ *     input-independent near-field recurrence states, and the nodes, weights
+ *     and offsets theta_k - (k+1/2) pi/N, all formed on the device)
  *     and a per-stream workspace; both are created on first use and live
  *     until dlt_release() or process exit.  The first call for a given N on
  *     a device builds its plan and synchronises the device (so it must not

@@ -128,6 +128,19 @@ int check_prec(int prec) {
                                                                                                 : DLT_ERR_INVALID_ARG;
 }
 
+// the plan's node arrays (theta, w, dtheta), formed once on the device
+static int plan_nodes(Plan& p) {
+    const size_t vb = (size_t)p.N * sizeof(double);
+    if (hipMalloc(&p.d_theta, vb) != hipSuccess || hipMalloc(&p.d_w, vb) != hipSuccess ||
+        hipMalloc(&p.d_dth, vb) != hipSuccess)
+        return DLT_ERR_NOMEM;
+    Lanes L;
+    L.s = nullptr;
+    if (run_nodes(p, p.d_theta, p.d_w, p.d_dth, L) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return DLT_ERR_HIP;
+    return DLT_OK;
+}
+
 int get_plan(int64_t N, int prec, Plan** out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return DLT_ERR_HIP;
@@ -146,6 +159,7 @@ int get_plan(int64_t N, int prec, Plan** out) {
                                                         : PREC_FP64,
                         *p);
     if (rc == DLT_OK && plan_prepare(*p) != hipSuccess) rc = DLT_ERR_HIP;
+    if (rc == DLT_OK) rc = plan_nodes(*p);
     if (rc != DLT_OK) {
         plan_free(*p);
         return rc;
@@ -209,6 +223,7 @@ int get_plan_tol(int64_t N, double eps, Plan** out) {
     std::unique_ptr<Plan> p(new Plan());
     rc = plan_build(N, PREC_FP64, *p, tv);
     if (rc == DLT_OK && plan_prepare(*p) != hipSuccess) rc = DLT_ERR_HIP;
+    if (rc == DLT_OK) rc = plan_nodes(*p);
     if (rc != DLT_OK) {
         plan_free(*p);
         return rc;
@@ -852,9 +867,10 @@ int leg_nodes_weights(int64_t N, int64_t batch, double* theta, double* w, double
     } else {
         Plan* p;
         if ((rc = get_plan(N, DLT_PREC_FP64, &p))) return rc;
-        CallWS cw;
-        if ((rc = setup_call(*p, 0, stream, cw))) return rc;
-        if ((rc = hip_status(run_nodes(*p, theta, w, dtheta, cw.lanes)))) return rc;
+        const size_t vb = (size_t)N * sizeof(double);
+        if (theta && hipMemcpyAsync(theta, p->d_theta, vb, hipMemcpyDeviceToDevice, stream)) return DLT_ERR_HIP;
+        if (w && hipMemcpyAsync(w, p->d_w, vb, hipMemcpyDeviceToDevice, stream)) return DLT_ERR_HIP;
+        if (dtheta && hipMemcpyAsync(dtheta, p->d_dth, vb, hipMemcpyDeviceToDevice, stream)) return DLT_ERR_HIP;
     }
     for (int64_t b = 1; b < batch; ++b) {
         size_t vb = (size_t)N * sizeof(double);
@@ -916,11 +932,10 @@ int cheb_eval_leggrid(int64_t N, int64_t batch, const double* chat, double* f, h
 static int cheb_eval_leggrid_on(Plan& P, int64_t N, int64_t batch, const double* chat, double* f, hipStream_t stream) {
     Plan* p = &P;
     return run_call(3, *p, batch, chat, f, stream, [&](CallWS& cw) -> int {
-        int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, cw.lanes));
-        if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
-            if ((r = hip_status(run_ndct(*p, nb, chat + b0 * N, N, cw.dth, f + b0 * N, cw.work, cw.lanes)))) return r;
+            int r = hip_status(run_ndct(*p, nb, chat + b0 * N, N, p->d_dth, f + b0 * N, cw.work, cw.lanes));
+            if (r) return r;
         }
         return DLT_OK;
     });
@@ -959,23 +974,14 @@ int dlt_forward(int64_t N, int64_t batch, const double* c, double* f, hipStream_
 static int dlt_forward_on(Plan& P, int64_t N, int64_t batch, const double* c, double* f, hipStream_t stream) {
     Plan* p = &P;
     return run_call(0, *p, batch, c, f, stream, [&](CallWS& cw) -> int {
-        // the nodes are needed only by the Taylor evaluation: they run on the
-        // first side stream beside the conversion of the first slice
         const Lanes& L = cw.lanes;
-        const hipStream_t s0 = L.s, sn = L.aux(0);
-        const bool fork = sn != s0;
-        if (fork && (hipEventRecord(L.ev[10], s0) != hipSuccess || hipStreamWaitEvent(sn, L.ev[10], 0) != hipSuccess))
-            return DLT_ERR_HIP;
-        int r = hip_status(run_nodes(*p, nullptr, nullptr, cw.dth, L.on(sn)));
-        if (r) return r;
-        if (fork && hipEventRecord(L.ev[11], sn) != hipSuccess) return DLT_ERR_HIP;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
             // Chebyshev coefficients of the slice, stride N, in the workspace
             double* chat = cw.work.chat;
-            if ((r = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat, cw.work.schat, cw.work, L)))) return r;
-            if (fork && b0 == 0 && hipStreamWaitEvent(s0, L.ev[11], 0) != hipSuccess) return DLT_ERR_HIP;
-            if ((r = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, f + b0 * N, cw.work, L)))) return r;
+            int r = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, chat, cw.work.schat, cw.work, L));
+            if (r) return r;
+            if ((r = hip_status(run_ndct(*p, nb, chat, cw.work.schat, p->d_dth, f + b0 * N, cw.work, L)))) return r;
         }
         return DLT_OK;
     });
@@ -1025,18 +1031,15 @@ int dlt_forward_noalloc(int64_t N, int64_t batch, const double* c, double* f, hi
     const int64_t per_slice =
         p->ws_per_inst ? (int64_t)((NOALLOC_SCRATCH_BYTES - shared) / p->ws_per_inst) : batch;
     const int64_t nbmax = std::min<int64_t>(batch, per_slice);
-    const size_t vecb = ((size_t)N * sizeof(double) + 255) & ~size_t(255);
-    double* dth = (double*)((char*)base + 2 * vecb);  // the layout of setup_call
-    Work work;
+    Work work;  // after the node-array region of setup_call's layout (unused: the plan holds the nodes)
     work_carve(*p, nbmax, (char*)base + shared, work);
     Lanes L;  // the caller's stream only
     L.s = stream;
     trace_hold(true);
-    rc = hip_status(run_nodes(*p, nullptr, nullptr, dth, L));
     for (int64_t b0 = 0; rc == DLT_OK && b0 < batch; b0 += nbmax) {
         const int64_t nb = std::min(nbmax, batch - b0);
         rc = hip_status(run_leg2cheb(*p, nb, c + b0 * N, N, work.chat, work.schat, work, L));
-        if (rc == DLT_OK) rc = hip_status(run_ndct(*p, nb, work.chat, work.schat, dth, f + b0 * N, work, L));
+        if (rc == DLT_OK) rc = hip_status(run_ndct(*p, nb, work.chat, work.schat, p->d_dth, f + b0 * N, work, L));
     }
     trace_hold(false);
     return rc;
@@ -1089,7 +1092,8 @@ static int star_call(int64_t N, int64_t batch, const double* in, double* f, int 
     if (op != 0) work_carve(*p, nb, q + (size_t)nb * sp->ws_per_inst, work);
     Lanes L;  // the caller's stream only
     L.s = stream;
-    rc = hip_status(run_nodes(*p, nullptr, inverse ? wts : nullptr, dth, L));
+    wts = p->d_w;
+    dth = p->d_dth;
     for (int64_t b0 = 0; rc == DLT_OK && b0 < batch; b0 += nb) {
         const int64_t n = std::min(nb, batch - b0);
         if (inverse) {
@@ -1151,12 +1155,10 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
 static int dlt_inverse_on(Plan& P, int64_t N, int64_t batch, const double* f, double* c, hipStream_t stream) {
     Plan* p = &P;
     return run_call(1, *p, batch, f, c, stream, [&](CallWS& cw) -> int {
-        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.lanes));
-        if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
-            if ((r = hip_status(run_inverse(*p, nb, f + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, cw.lanes))))
-                return r;
+            int r = hip_status(run_inverse(*p, nb, f + b0 * N, p->d_w, p->d_dth, c + b0 * N, cw.work, cw.lanes));
+            if (r) return r;
         }
         return DLT_OK;
     });
@@ -1193,12 +1195,11 @@ int dlt_inverse_tol(int64_t N, int64_t batch, const double* f, double* c, double
 static int cheb2leg_on(Plan& P, int64_t N, int64_t batch, const double* chat, double* c, hipStream_t stream) {
     Plan* p = &P;
     return run_call(4, *p, batch, chat, c, stream, [&](CallWS& cw) -> int {
-        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.lanes));
-        if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
-            if ((r = hip_status(run_ndct(*p, nb, chat + b0 * N, N, cw.dth, c + b0 * N, cw.work, cw.lanes)))) return r;
-            if ((r = hip_status(run_inverse(*p, nb, c + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, cw.lanes))))
+            int r = hip_status(run_ndct(*p, nb, chat + b0 * N, N, p->d_dth, c + b0 * N, cw.work, cw.lanes));
+            if (r) return r;
+            if ((r = hip_status(run_inverse(*p, nb, c + b0 * N, p->d_w, p->d_dth, c + b0 * N, cw.work, cw.lanes))))
                 return r;
         }
         return DLT_OK;
@@ -1269,15 +1270,13 @@ int chebvals2leg(int64_t N, int64_t batch, const double* v, double* c, hipStream
     // Chebyshev coefficients of the interpolant (workspace), their expansion's
     // values at the Legendre nodes (into c), the inverse transform in place
     return run_call(5, *p, batch, v, c, stream, [&](CallWS& cw) -> int {
-        int r = hip_status(run_nodes(*p, nullptr, cw.w, cw.dth, cw.lanes));
-        if (r) return r;
         for (int64_t b0 = 0; b0 < batch; b0 += cw.nb) {
             int64_t nb = std::min(cw.nb, batch - b0);
             double* chat = cw.work.chat;
-            if ((r = hip_status(run_chebvals2cheb(*p, nb, v + b0 * N, N, chat, cw.work.schat, cw.work, cw.lanes))))
-                return r;
-            if ((r = hip_status(run_ndct(*p, nb, chat, cw.work.schat, cw.dth, c + b0 * N, cw.work, cw.lanes)))) return r;
-            if ((r = hip_status(run_inverse(*p, nb, c + b0 * N, cw.w, cw.dth, c + b0 * N, cw.work, cw.lanes))))
+            int r = hip_status(run_chebvals2cheb(*p, nb, v + b0 * N, N, chat, cw.work.schat, cw.work, cw.lanes));
+            if (r) return r;
+            if ((r = hip_status(run_ndct(*p, nb, chat, cw.work.schat, p->d_dth, c + b0 * N, cw.work, cw.lanes)))) return r;
+            if ((r = hip_status(run_inverse(*p, nb, c + b0 * N, p->d_w, p->d_dth, c + b0 * N, cw.work, cw.lanes))))
                 return r;
         }
         return DLT_OK;

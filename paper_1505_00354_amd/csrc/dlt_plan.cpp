@@ -453,7 +453,7 @@ void plan_free(Plan& p) {
     }
     void* ptrs[] = {p.d_twN1,  p.d_twN2,     p.d_twHi,      p.d_twLo,     p.d_lam,
                     p.d_rcp,   p.d_guess,    p.d_tn_wgseg,  p.d_tn_segoff, p.d_tn_rgnend, p.d_near_st,
-                    p.d_amp,   p.d_rowf};
+                    p.d_amp,   p.d_rowf,     p.d_theta,     p.d_w,        p.d_dth};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p = Plan();

@@ -169,6 +169,10 @@ struct Plan {
     Plan* sub = nullptr;
     // theta^cheb* evaluation of this size (FP64 plans; built on first use, owned)
     StarPlan* star = nullptr;
+    // the Legendre nodes theta_k, weights w_k and offsets theta_k - (k+1/2) pi/N
+    // (input-independent: formed on the device once, when a plan that
+    // evaluates at the nodes is built; null in sub-plans)
+    double *d_theta = nullptr, *d_w = nullptr, *d_dth = nullptr;
 };
 
 // Builds the plan for size N (power of two, 1 <= N <= MAX_N) and precision
