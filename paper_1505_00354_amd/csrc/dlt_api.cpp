@@ -30,8 +30,14 @@ struct RDesc {
     int* ioff = nullptr;
     int* boff = nullptr;
     int nb = 0, ni = 0, nbd = 0;
+    // the node tables of the slice (grid row -> node, its offset and weight),
+    // input-independent: formed once when the slice is built, if small enough
+    // (null: formed in the workspace by every run)
+    int* gk = nullptr;
+    double* dg = nullptr;
+    double* wg = nullptr;
     ~RDesc() {
-        void* q[] = {R, offs, ioff, boff};
+        void* q[] = {R, offs, ioff, boff, gk, dg, wg};
         for (void* x : q)
             if (x) (void)hipFree(x);
     }
@@ -50,6 +56,7 @@ struct BatchEntry {
     std::vector<RSlice> slices;
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    size_t tab_bytes = 0;  // node tables held by the slices
     hipGraphExec_t exec = nullptr;
     ~BatchEntry() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -60,6 +67,7 @@ struct BatchEntry {
 struct SingleEntry {
     std::vector<RSlice> slices;
     size_t ws_bytes = 0;
+    size_t tab_bytes = 0;
 };
 
 struct Cache {
@@ -493,9 +501,20 @@ hipError_t rslice_run(const RSlice& S, const double* in, double* out, void* ws, 
     q += al256z(v * sizeof(double));
     double* wg = (double*)q;
     const RaggedNodes rn{S.d->R, S.d->ioff, S.d->boff, nb, S.d->ni, S.d->nbd};
+    const bool cached = S.d->gk != nullptr;  // the slice's own node tables
+    if (cached) {
+        gk = S.d->gk;
+        dg = S.d->dg;
+        wg = S.d->wg;
+    }
     const RaggedRows rr{gk, dg, wg, S.d->offs};
     hipError_t e;
     if (S.dir == 0) {
+        if (cached) {
+            if ((e = run_rgather(in, S.d->R, S.d->offs, nb, Ng, Ng, stage, L.s)) != hipSuccess) return e;
+            if ((e = run_leg2cheb(p, nb, stage, Ng, w.chat, w.schat, w, L)) != hipSuccess) return e;
+            return run_ndct(p, nb, w.chat, w.schat, nullptr, out, w, L, &rr, S.Q);
+        }
         // nodes on the first side stream, beside the conversion
         const hipStream_t sn = L.aux(0);
         if (sn != L.s) {
@@ -515,19 +534,45 @@ hipError_t rslice_run(const RSlice& S, const double* in, double* out, void* ws, 
         return run_rscatter(w.chat, w.schat, S.d->R, S.d->offs, nb, Ng, out, L.s);
     }
     if (S.dir == 3) {  // Chebyshev expansion (zero-padded) at the Legendre nodes
-        if ((e = run_rnodes(rn, Ng, gk, dg, nullptr, nullptr, nullptr, nullptr, L.s)) != hipSuccess) return e;
+        if (!cached && (e = run_rnodes(rn, Ng, gk, dg, nullptr, nullptr, nullptr, nullptr, L.s)) != hipSuccess)
+            return e;
         if ((e = run_rgather(in, S.d->R, S.d->offs, nb, Ng, Ng, stage, L.s)) != hipSuccess) return e;
         return run_ndct(p, nb, stage, Ng, nullptr, out, w, L, &rr, S.Q);
     }
-    if ((e = run_rnodes(rn, Ng, gk, dg, wg, nullptr, nullptr, nullptr, L.s)) != hipSuccess) return e;
+    if (!cached && (e = run_rnodes(rn, Ng, gk, dg, wg, nullptr, nullptr, nullptr, L.s)) != hipSuccess) return e;
     if ((e = run_inverse(p, nb, in, nullptr, nullptr, stage, w, L, &rr, S.Q)) != hipSuccess) return e;
     return run_rscatter(stage, Ng, S.d->R, S.d->offs, nb, Ng, out, L.s);
 }
 
+// The node tables of a slice of the evaluating directions (0, 1, 3), formed
+// once on the device (the null stream, then a device synchronisation: slices
+// are built by first calls, which synchronise anyway) while the batch's
+// tables (running total *held) stay within RTABLE_MAX bytes; the slices
+// beyond form them in every run.
+constexpr size_t RTABLE_MAX = size_t(1) << 30;
+int rdesc_tables(RSlice& S, size_t* held) {
+    if (S.dir != 0 && S.dir != 1 && S.dir != 3) return DLT_OK;
+    RDesc& d = *S.d;
+    const size_t v = (size_t)d.nb * (size_t)S.Ng;
+    const bool inv = S.dir == 1;
+    const size_t need = v * (sizeof(int) + sizeof(double) * (inv ? 2 : 1));
+    if (*held + need > RTABLE_MAX) return DLT_OK;
+    *held += need;
+    if (hipMalloc(&d.gk, v * sizeof(int)) != hipSuccess || hipMalloc(&d.dg, v * sizeof(double)) != hipSuccess ||
+        (inv && hipMalloc(&d.wg, v * sizeof(double)) != hipSuccess))
+        return DLT_ERR_NOMEM;
+    const RaggedNodes rn{d.R, d.ioff, d.boff, d.nb, d.ni, d.nbd};
+    if (run_rnodes(rn, (int)S.Ng, d.gk, d.dg, d.wg, nullptr, nullptr, nullptr, nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+        return DLT_ERR_HIP;
+    return DLT_OK;
+}
+
 // Splits instances idx (one direction, one grid) into slices whose
-// workspace fits WS_CAP; builds their descriptors.
+// workspace fits WS_CAP; builds their descriptors (and node tables, adding
+// their bytes to *tab).
 int rslices_build(int dir, int64_t Ng, int prec, const int64_t* Ns, const int64_t* offs,
-                  const std::vector<int64_t>& idx, std::vector<RSlice>& out, size_t* ws_max) {
+                  const std::vector<int64_t>& idx, std::vector<RSlice>& out, size_t* ws_max, size_t* tab) {
     Plan* p;
     int rc;
     if ((rc = get_plan(Ng, prec, &p))) return rc;
@@ -542,6 +587,7 @@ int rslices_build(int dir, int64_t Ng, int prec, const int64_t* Ns, const int64_
         S.Q = ragged_Q(prec, Ns, part, Ng);
         S.d.reset(new RDesc());
         if ((rc = rdesc_build(Ns, offs, part, *S.d))) return rc;
+        if ((rc = rdesc_tables(S, tab))) return rc;
         *ws_max = std::max(*ws_max, rslice_bytes(*p, (int64_t)part.size()));
         out.push_back(std::move(S));
     }
@@ -585,7 +631,8 @@ int single_entry(int64_t N, int64_t batch, int dir, int prec, SingleEntry** out)
             offs[b] = b * N;
             idx[b] = b;
         }
-        if ((rc = rslices_build(dir, next_pow2(N), prec, Ns.data(), offs.data(), idx, e->slices, &e->ws_bytes)))
+        if ((rc = rslices_build(dir, next_pow2(N), prec, Ns.data(), offs.data(), idx, e->slices, &e->ws_bytes,
+                                &e->tab_bytes)))
             return rc;
         Cache& c = cache();
         std::lock_guard<std::mutex> lk(c.mu);
@@ -662,8 +709,8 @@ int tune_grid(int dir, int64_t P, int prec, const int64_t* Ns, const int64_t* of
     if (rc == DLT_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = DLT_ERR_HIP;
     for (int64_t cand = P; cand <= 2 * P && rc == DLT_OK; cand *= 2) {
         std::vector<RSlice> sl;
-        size_t wmax = 0;
-        if ((rc = rslices_build(dir, cand, prec, sN.data(), so.data(), sidx, sl, &wmax))) break;
+        size_t wmax = 0, tab = 0;
+        if ((rc = rslices_build(dir, cand, prec, sN.data(), so.data(), sidx, sl, &wmax, &tab))) break;
         void* ws = nullptr;
         if ((rc = get_ws(s, wmax, &ws))) break;
         float ms = 0;
@@ -791,16 +838,18 @@ int dlt_batch_ex(int64_t count, const int64_t* Ns, const int64_t* offsets, const
             int64_t Ng = kv.first.second;
             if ((rc = tune_grid(kv.first.first, kv.first.second, prec, Ns, offsets, kv.second, in, stream, &Ng)))
                 return rc;
-            if ((rc = rslices_build(kv.first.first, Ng, prec, Ns, offsets, kv.second, e->slices, &wmax))) return rc;
+            if ((rc = rslices_build(kv.first.first, Ng, prec, Ns, offsets, kv.second, e->slices, &wmax,
+                                    &e->tab_bytes)))
+                return rc;
         }
         {
-            // each cached graph owns a workspace: beyond BATCH_GRAPHS_MAX graphs
-            // or BATCH_WS_MAX bytes of them, drop the cached ones (once the
-            // device has drained: a replay may still run)
+            // each cached graph owns a workspace and node tables: beyond
+            // BATCH_GRAPHS_MAX graphs or BATCH_WS_MAX bytes of them, drop the
+            // cached ones (once the device has drained: a replay may still run)
             Cache& c = cache();
             std::lock_guard<std::mutex> lk(c.mu);
-            size_t held = wmax;
-            for (auto& kv : c.graphs) held += kv.second->ws_bytes;
+            size_t held = wmax + e->tab_bytes;
+            for (auto& kv : c.graphs) held += kv.second->ws_bytes + kv.second->tab_bytes;
             if (!c.graphs.empty() && (c.graphs.size() >= BATCH_GRAPHS_MAX || held > BATCH_WS_MAX)) {
                 if (hipDeviceSynchronize() != hipSuccess) return DLT_ERR_HIP;
                 c.graphs.clear();

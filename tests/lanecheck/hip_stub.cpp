@@ -31,7 +31,9 @@
 //                      possibly through others);
 //   call-unjoined      (checked at stub_call_end) work enqueued during one
 //                      library call on any stream other than the caller's is
-//                      not an ancestor of the caller's stream's last node;
+//                      not an ancestor of the caller's stream's last node
+//                      (work that a later hipDeviceSynchronize in the call
+//                      waited for has completed and is exempt);
 //   dead-handle        a graph executable, stream or event is used after it
 //                      was destroyed, or a pointer is freed that is not a
 //                      live allocation.
@@ -108,6 +110,7 @@ struct State {
     std::vector<std::string> violations;
     int next_id = 1;
     int call_first_node = 0;
+    int done_upto = 0;  // nodes below this had completed at a device synchronisation
     long n_launch = 0, n_capture = 0, n_graph_launch = 0, n_record = 0, n_wait = 0;
     long n_side_to_side = 0;  // captured waits of one side stream on another's record
     long n_alloc = 0, n_free = 0, n_stream_create = 0, n_event_create = 0, n_sync = 0;
@@ -211,7 +214,7 @@ int stub_call_end(hipStream_t user) {
     int bad = 0;
     for (int i = S.call_first_node; i < (int)S.nodes.size(); ++i) {
         const Node& n = S.nodes[i];
-        if (n.stream == u || n.capture) continue;
+        if (n.stream == u || n.capture || i < S.done_upto) continue;
         if (!reaches(i, last)) {
             violate("call-unjoined: %s on stream %d (node %d) is not ordered before the caller's stream %d",
                     n.what.c_str(), n.stream, i, u);
@@ -368,6 +371,8 @@ hipError_t hipStreamSynchronize(hipStream_t s) {
 }
 hipError_t hipDeviceSynchronize() {
     sync_point("hipDeviceSynchronize", -1);
+    // every node enqueued outside a capture so far has completed
+    if (!active_capture()) st().done_upto = (int)st().nodes.size();
     return hipSuccess;
 }
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) {
