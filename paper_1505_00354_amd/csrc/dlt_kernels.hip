@@ -1444,14 +1444,24 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
         }
     };
     if constexpr (sizeof(R) == sizeof(double)) {
-        // all pairs FP64 and contiguous (X1 = X0 + N): one prefetch buffer
-        for (int q = Q - 1; q >= 0; --q) {
+        // all pairs FP64 and contiguous (X1 = X0 + N): two prefetch buffers
+        // taken in turn, so two tiles are in flight while one is transformed
+        // (nx holds pair q, ny pair q - 1)
+        cplx ny[FFT_VPT] = {};
+        if (Q > 1) passB_load<LB, double>(g, jb0, X0b + (int64_t)(Q - 2) * N, ny, T);
+        for (int q = Q - 1; q >= 0; q -= 2) {
             cplx z[FFT_VPT];
 #pragma unroll
             for (int s = 0; s < FFT_VPT; ++s) z[s] = nx[s];
-            if (q > 0) passB_load<LB, double>(g, jb0, X0b + (int64_t)(q - 1) * N, nx, T);
+            if (q > 1) passB_load<LB, double>(g, jb0, X0b + (int64_t)(q - 2) * N, nx, T);
             tile_fft<LB>(z, bufd, twd, T);
             horner(q, z);
+            if (q == 0) break;
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) z[s] = ny[s];
+            if (q > 2) passB_load<LB, double>(g, jb0, X0b + (int64_t)(q - 3) * N, ny, T);
+            tile_fft<LB>(z, bufd, twd, T);
+            horner(q - 1, z);
         }
     } else {
         // pairs Q-1..1 in precision R (prefetched into nxr), pair 0 FP64 (nx)
@@ -1884,8 +1894,9 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
             combine(q, bb, U);
         }
     };
-    if constexpr (sizeof(R) == sizeof(double)) {
-        // all pairs FP64 and contiguous (X1 = X0 + N): one prefetch buffer
+    if constexpr (sizeof(R) == sizeof(double) && LB == 0) {
+        // all pairs FP64 and contiguous (X1 = X0 + N); run-time length (short
+        // transforms): one prefetch buffer, within the registers
         cplx nx[FFT_VPT] = {};
         passB_load<LB, double>(g, vb0, X0b + (int64_t)(Q - 1) * N, nx, T);
         for (int q = Q - 1; q >= 0; --q) {
@@ -1894,6 +1905,24 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
             for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
             if (q > 0) passB_load<LB, double>(g, vb0, X0b + (int64_t)(q - 1) * N, nx, T);
             transform_combine(q, U, bufd, twd);
+        }
+    } else if constexpr (sizeof(R) == sizeof(double)) {
+        // all pairs FP64 and contiguous: two prefetch buffers taken in turn
+        // (nx holds pair q, ny pair q - 1)
+        cplx nx[FFT_VPT] = {}, ny[FFT_VPT] = {};
+        passB_load<LB, double>(g, vb0, X0b + (int64_t)(Q - 1) * N, nx, T);
+        if (Q > 1) passB_load<LB, double>(g, vb0, X0b + (int64_t)(Q - 2) * N, ny, T);
+        for (int q = Q - 1; q >= 0; q -= 2) {
+            cplx U[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) U[s] = nx[s];
+            if (q > 1) passB_load<LB, double>(g, vb0, X0b + (int64_t)(q - 2) * N, nx, T);
+            transform_combine(q, U, bufd, twd);
+            if (q == 0) break;
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) U[s] = ny[s];
+            if (q > 2) passB_load<LB, double>(g, vb0, X0b + (int64_t)(q - 3) * N, ny, T);
+            transform_combine(q - 1, U, bufd, twd);
         }
     } else {
         cplxT<R> nx[FFT_VPT] = {};
