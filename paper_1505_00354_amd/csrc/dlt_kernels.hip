@@ -1464,18 +1464,48 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
             horner(q - 1, z);
         }
     } else {
-        // pairs Q-1..1 in precision R (prefetched into nxr), pair 0 FP64 (nx)
-        for (int q = Q - 1; q >= 1; --q) {
-            cplxT<R> z[FFT_VPT];
+        // pairs Q-1..1 in precision R, pair 0 FP64 (nx)
+        if constexpr (LB > 0) {
+            // two prefetch buffers taken in turn: nxr holds pairs Q-1, Q-3,
+            // ..., nyr pairs Q-2, Q-4, ... (pair 0 goes to nx)
+            cplxT<R> nyr[FFT_VPT] = {};
+            if (Q > 2) passB_load<LB, R>(g, jb0, X1b + (int64_t)(Q - 3) * N, nyr, T);
+            else if (Q == 2) passB_load<LB, double>(g, jb0, X0b, nx, T);
+            for (int q = Q - 1; q >= 1; q -= 2) {
+                cplxT<R> z[FFT_VPT];
+                cplx U[FFT_VPT];
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) z[s] = nxr[s];
-            if (q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 2) * N, nxr, T);
-            else passB_load<LB, double>(g, jb0, X0b, nx, T);
-            tile_fft<LB>(z, bufr, twr, T);
-            cplx U[FFT_VPT];
+                for (int s = 0; s < FFT_VPT; ++s) z[s] = nxr[s];
+                if (q > 2) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 3) * N, nxr, T);
+                else if (q == 2) passB_load<LB, double>(g, jb0, X0b, nx, T);
+                tile_fft<LB>(z, bufr, twr, T);
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
-            horner(q, U);
+                for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
+                horner(q, U);
+                if (q == 1) break;
+#pragma unroll
+                for (int s = 0; s < FFT_VPT; ++s) z[s] = nyr[s];
+                if (q > 3) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 4) * N, nyr, T);
+                else if (q == 3) passB_load<LB, double>(g, jb0, X0b, nx, T);
+                tile_fft<LB>(z, bufr, twr, T);
+#pragma unroll
+                for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
+                horner(q - 1, U);
+            }
+        } else {
+            // run-time length (short transforms): one prefetch buffer (nxr)
+            for (int q = Q - 1; q >= 1; --q) {
+                cplxT<R> z[FFT_VPT];
+#pragma unroll
+                for (int s = 0; s < FFT_VPT; ++s) z[s] = nxr[s];
+                if (q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 2) * N, nxr, T);
+                else passB_load<LB, double>(g, jb0, X0b, nx, T);
+                tile_fft<LB>(z, bufr, twr, T);
+                cplx U[FFT_VPT];
+#pragma unroll
+                for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
+                horner(q, U);
+            }
         }
         tile_fft<LB>(nx, bufd, twd, T);
         horner(0, nx);
