@@ -2897,6 +2897,18 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     return hipGetLastError();
 }
 
+// Pair groups of an FP64 Taylor pass A (grid rows, each taking an equal
+// share of the pairs) over `tiles` tile blocks: the fewest that give the
+// launch 256 blocks.  Measured on one box, pass A and its transpose at
+// N = 2^20 (512 tiles) are fastest with one group (two and four groups:
+// 20% and 60% slower), at 2^18 (128 tiles) with two (eight: 23% slower),
+// at 2^16 and below with one pair per group.
+static int pass_a_groups(int64_t tiles, int npairs) {
+    int qg = 1;
+    while (qg < npairs && tiles * qg < 256) ++qg;
+    return qg;
+}
+
 hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, const double* dth, double* f,
                     Work& w, const Lanes& L, const RaggedRows* rr, int Qo) {
     trace_n = p.N;
@@ -2923,8 +2935,7 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_ndct_passB, float, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, X1, s1, dth, f, p.N, RR);
         });
     } else {
-        // small transforms: split the Taylor pairs over blocks for parallelism
-        const int QG = (tilesA * nb >= 256) ? 1 : Q;
+        const int QG = pass_a_groups(tilesA * nb, Q);
         traced("k_ndct_passA", s, [&] {
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_ndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, chat, hs, w.X, w.sX);
         });
@@ -3006,7 +3017,7 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tndct_passB, float, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, X1, s1, y, w.schat);
         });
     } else {
-        const int QG = (tilesA * nb >= 256) ? 1 : Q;
+        const int QG = pass_a_groups(tilesA * nb, Q);
         traced("k_tndct_passA", s, [&] {
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, f, N, wts, dth, w.X, w.sX, RR);
         });
