@@ -659,6 +659,10 @@ __global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restri
 #define FFT_WAVES 2
 #endif
 #define FFT_BOUNDS __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES)))
+// the same for a kernel whose FP32 tiles (half the LDS) of compile-time
+// length L fit the registers of three waves per SIMD
+#define FFT_BOUNDS_R(R, L) \
+    __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && (L) > 0) ? 3 : FFT_WAVES)))
 // Intermediate layout between the passes ("blocked"): DFT output (n_a, j_b)
 // of pass A sits at X[(v >> lrB) * (N1 << lrB) + n_a * rowsB + (v & (rowsB-1))]
 // with v = j_b, or for kernels whose pass B pairs row r with N2 - r, the
@@ -1760,7 +1764,7 @@ __global__ FFT_BOUNDS void k_star_passC(Geo g, int N, int L, int trans, const cp
 // One launch covers the pairs [qa, qb) (slab q - qa of X, precision R);
 // block row blockIdx.y takes an equal share of them.
 template <int LA, class R>
-__global__ FFT_BOUNDS void k_tndct_passA(Geo g, int qa, int qb, int QG, const double* __restrict__ fv,
+__global__ FFT_BOUNDS_R(R, LA) void k_tndct_passA(Geo g, int qa, int qb, int QG, const double* __restrict__ fv,
                                          int64_t f_stride, const double* __restrict__ wts,
                                          const double* __restrict__ dth, cplxT<R>* __restrict__ X, int64_t x_stride,
                                          RaggedRows RR) {
