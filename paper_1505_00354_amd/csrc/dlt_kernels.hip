@@ -2809,7 +2809,12 @@ hipError_t run_leg2cheb_t(const Plan& p, int64_t nb, const double* y, int64_t ys
     const int tilesA = g.N1 / g.colsA;
     const hipStream_t s = L.s;
     const bool last = (N <= nd);
-    const hipStream_t sl = last ? s : L.aux(1), sn = L.aux(2);
+    // the transposed near field beside the transposed far field up to
+    // TNEAR_SIDE_MAX_N; above it on s, before the far field (measured on one
+    // box at 2^20: the far-field passes lose more to sharing the CUs with it
+    // than the overlap saves, the inverse 3% faster in sequence; at 2^18 the
+    // overlap is 1% faster)
+    const hipStream_t sl = last ? s : L.aux(1), sn = (p.N <= TNEAR_SIDE_MAX_N) ? L.aux(2) : s;
     double* dense_out = w.dense + (int64_t)p.dense_nchunk * nd;
     if (!L.low_inline) DLT_TRY(dep(s, sl, L.ev[6]));
     if (!p.sub && dense_mm_pays(nd, nb)) {  // one contraction on the matrix cores

@@ -32,6 +32,9 @@ constexpr int LANE_EVENTS = 18;
 // largest size whose inverse runs its nested transposed conversion's low
 // block on a side stream of its own
 constexpr int64_t NESTED_LOW_MAX_N = int64_t(1) << 18;
+// largest size whose transposed near field runs on a side stream beside the
+// transposed far field (larger sizes run it in sequence)
+constexpr int64_t TNEAR_SIDE_MAX_N = int64_t(1) << 18;
 struct Lanes {
     hipStream_t s = nullptr;
     hipStream_t side[LANE_SIDES] = {};
