@@ -722,10 +722,8 @@ struct PassAOut {
         p2 = tw2(g.twHi, g.twLo, (int64_t)na * (L / 4), g.sh);
         p4 = tw2(g.twHi, g.twLo, (int64_t)na * (L / 2), g.sh);
     }
-    // o[s] = v[s] times its twiddle
-    template <class R>
-    __device__ __forceinline__ void twid(const cplxT<R>* v, cplxT<R>* o) const {
-        cplx w[8];
+    // the thread's twiddles w[s] (element s)
+    __device__ __forceinline__ void twiddles(cplx* w) const {
         w[0] = w0;
         w[1] = cmul(w0, p1);
         w[2] = cmul(w0, p2);
@@ -734,6 +732,12 @@ struct PassAOut {
         w[5] = cmul(w[1], p4);
         w[6] = cmul(w[2], p4);
         w[7] = cmul(w[3], p4);
+    }
+    // o[s] = v[s] times its twiddle
+    template <class R>
+    __device__ __forceinline__ void twid(const cplxT<R>* v, cplxT<R>* o) const {
+        cplx w[8];
+        twiddles(w);
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) o[s] = cto<R>(cmul(cwide(v[s]), w[s]));
     }
@@ -788,13 +792,25 @@ struct PassAOut<0, VIRT> {
 // leaving in one burst between two transforms.
 template <int L, bool VIRT, class R>
 struct HeldPut {
+    // FP32 tiles of compile-time length: the thread's twiddles are rounded
+    // to FP32 once and applied in FP32 (the FP32 terms' own rounding is of
+    // that order), instead of widening every product to FP64
+    static constexpr bool F32 = (sizeof(R) < sizeof(double)) && (L > 0);
     const PassAOut<L, VIRT>& out;
     const Geo& g;
     const Tile<L>& T;
     cplxT<R> o[FFT_VPT];
+    cplxT<R> wr[F32 ? FFT_VPT : 1];
     cplxT<R>* dst = nullptr;
     __device__ __forceinline__ HeldPut(const PassAOut<L, VIRT>& out_, const Geo& g_, const Tile<L>& T_)
-        : out(out_), g(g_), T(T_) {}
+        : out(out_), g(g_), T(T_) {
+        if constexpr (F32) {
+            cplx w[FFT_VPT];
+            out.twiddles(w);
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) wr[s] = cto<R>(w[s]);
+        }
+    }
     // stores the held tile's share of hook point pt (none before the first hold)
     __device__ __forceinline__ void operator()(int pt) const {
         constexpr int NP = tile_hook_points<L>();
@@ -806,7 +822,12 @@ struct HeldPut {
     }
     // holds the transform v, bound for the slab Xt
     __device__ __forceinline__ void hold(const cplxT<R>* v, cplxT<R>* Xt) {
-        out.twid(v, o);
+        if constexpr (F32) {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) o[s] = cmul(v[s], wr[s]);
+        } else {
+            out.twid(v, o);
+        }
         dst = Xt;
     }
     __device__ __forceinline__ void flush() {
