@@ -660,7 +660,9 @@ __global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restri
 #endif
 #define FFT_BOUNDS __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES)))
 // the same for a kernel whose FP32 tiles (half the LDS) of compile-time
-// length L fit the registers of three waves per SIMD
+// length L fit the registers of three waves per SIMD without spilling (the
+// FP32 Taylor passes A and the FP32 transposed far-field pass A; the FP32
+// far-field pass A spills under it)
 #define FFT_BOUNDS_R(R, L) \
     __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && (L) > 0) ? 3 : FFT_WAVES)))
 // Intermediate layout between the passes ("blocked"): DFT output (n_a, j_b)
@@ -830,6 +832,18 @@ struct HeldPut {
         }
         dst = Xt;
     }
+    // twiddles the transform v and stores it at once (nothing is held)
+    __device__ __forceinline__ void put(const cplxT<R>* v, cplxT<R>* Xt) const {
+        cplxT<R> t[FFT_VPT];
+        if constexpr (F32) {
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) t[s] = cmul(v[s], wr[s]);
+        } else {
+            out.twid(v, t);
+        }
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) out.store(g, t, Xt, T, s);
+    }
     __device__ __forceinline__ void flush() {
         if (dst) {
 #pragma unroll
@@ -925,17 +939,17 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __
     };
     // terms in pairs (t, t - G): two tiles per barrier sequence
     int t = F.nterm - 1 - (int)blockIdx.y;
+    HeldPut<LA, false, R> held(out, g, T);
     if constexpr (PAIRS) {
         for (; t - G >= 0; t -= 2 * G) {
             cplxT<R> v1[FFT_VPT], v2[FFT_VPT];
             input(t, v1);
             input(t - G, v2);
             tile_fft2<LA>(v1, v2, buf, buf2, twA, T);
-            out.put(g, v1, Xb + (int64_t)t * N, T);
-            out.put(g, v2, Xb + (int64_t)(t - G) * N, T);
+            held.put(v1, Xb + (int64_t)t * N);
+            held.put(v2, Xb + (int64_t)(t - G) * N);
         }
     }
-    HeldPut<LA, false, R> held(out, g, T);
     for (; t >= 0; t -= G) {
         cplxT<R> v[FFT_VPT];
         input(t, v);
@@ -1347,7 +1361,7 @@ __global__ FFT_BOUNDS void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ 
 // One launch covers the pairs [qa, qb) (slab q - qa of X, precision R);
 // block row blockIdx.y takes an equal share of them.
 template <int LA, class R>
-__global__ FFT_BOUNDS void k_ndct_passA(Geo g, int qa, int qb, int QG, const double* __restrict__ chat,
+__global__ FFT_BOUNDS_R(R, LA) void k_ndct_passA(Geo g, int qa, int qb, int QG, const double* __restrict__ chat,
                                         int64_t chat_stride, cplxT<R>* __restrict__ X, int64_t x_stride) {
     __shared__ cplxT<R> buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, R);
@@ -1386,18 +1400,45 @@ __global__ FFT_BOUNDS void k_ndct_passA(Geo g, int qa, int qb, int QG, const dou
             }
         }
     }
-    for (int q = q0; q < q1; ++q) {
-        cplxT<R> v[FFT_VPT];
+    if constexpr (sizeof(R) < sizeof(double)) {
+        // FP32 terms: the carried products and the squares in FP32 (their
+        // rounding is that of the FP32 terms themselves)
+        cplxT<R> Af[FFT_VPT], Bf[FFT_VPT];
+        R xx[FFT_VPT], yy[FFT_VPT];
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s) {
             const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             const double x = n * invN, y = (N - n) * invN;
-            v[s] = cto<R>(cadd(Ap[s], Bp[s]));
-            Ap[s] = cscale(Ap[s], (n == 0) ? 0.0 : x * x);
-            Bp[s] = cscale(Bp[s], y * y);
+            Af[s] = cto<R>(Ap[s]);
+            Bf[s] = cto<R>(Bp[s]);
+            xx[s] = (R)((n == 0) ? 0.0 : x * x);
+            yy[s] = (R)(y * y);
         }
-        tile_fft<LA>(v, buf, twA, T, held);
-        held.hold(v, Xb + (int64_t)(q - qa) * N);
+        for (int q = q0; q < q1; ++q) {
+            cplxT<R> v[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) {
+                v[s] = cadd(Af[s], Bf[s]);
+                Af[s] = cscale(Af[s], xx[s]);
+                Bf[s] = cscale(Bf[s], yy[s]);
+            }
+            tile_fft<LA>(v, buf, twA, T, held);
+            held.hold(v, Xb + (int64_t)(q - qa) * N);
+        }
+    } else {
+        for (int q = q0; q < q1; ++q) {
+            cplxT<R> v[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) {
+                const int n = na0 + T.col(s) + g.N1 * T.idx(s);
+                const double x = n * invN, y = (N - n) * invN;
+                v[s] = cto<R>(cadd(Ap[s], Bp[s]));
+                Ap[s] = cscale(Ap[s], (n == 0) ? 0.0 : x * x);
+                Bp[s] = cscale(Bp[s], y * y);
+            }
+            tile_fft<LA>(v, buf, twA, T, held);
+            held.hold(v, Xb + (int64_t)(q - qa) * N);
+        }
     }
     held.flush();
 }
@@ -2117,7 +2158,7 @@ __global__ FFT_BOUNDS void k_dct3_passB(Geo g, const cplx* __restrict__ X, int64
 //   rho_j = u_j e^{i (m+1/2)(theta_j - pi/2)} (2 sin theta_j)^{-m-1/2} [j in block b].
 // Term group blockIdx.y takes the terms y, y + G, ...
 template <int LA, class R>
-__global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const cplx* __restrict__ rowf,
+__global__ FFT_BOUNDS_R(R, LA) void k_tfar_passA(Geo g, FarParams F, int G, const cplx* __restrict__ rowf,
                                                            const double* __restrict__ u, int64_t u_stride,
                                                            cplxT<R>* __restrict__ X, int64_t x_stride) {
     __shared__ cplxT<R> buf[TILE_LDS(LA)];
@@ -2131,6 +2172,7 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const cplx* _
     const double* ub = u + b * u_stride;
     cplxT<R>* Xb = X + b * x_stride;
     const PassAOut<LA, false> out(g, T, na0);
+    const HeldPut<LA, false, R> put(out, g, T);  // stores only (no tile held)
     cplx gm[FFT_VPT], rq[FFT_VPT];
     int key[FFT_VPT];  // 2 * block + (conjugated input), -1 outside
 #pragma unroll
@@ -2162,7 +2204,7 @@ __global__ FFT_BOUNDS void k_tfar_passA(Geo g, FarParams F, int G, const cplx* _
             if (key[s] & 1) v[s].im = -v[s].im;
         }
         tile_fft<LA>(v, buf, twA, T);
-        out.put(g, v, Xb + (int64_t)t * N, T);
+        put.put(v, Xb + (int64_t)t * N);
     }
 }
 
