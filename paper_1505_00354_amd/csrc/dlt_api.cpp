@@ -547,16 +547,18 @@ hipError_t rslice_run(const RSlice& S, const double* in, double* out, void* ws, 
 // The node tables of a slice of the evaluating directions (0, 1, 3), formed
 // once on the device (the null stream, then a device synchronisation: slices
 // are built by first calls, which synchronise anyway) while the batch's
-// tables (running total *held) stay within RTABLE_MAX bytes; the slices
-// beyond form them in every run.
+// tables (running total *held) stay within `cap` bytes; the slices beyond
+// form them in every run.  A cached batch holds at most RTABLE_MAX bytes of
+// tables, the cached equal-size batches together at most SINGLE_TABLES_MAX.
 constexpr size_t RTABLE_MAX = size_t(1) << 30;
-int rdesc_tables(RSlice& S, size_t* held) {
+constexpr size_t SINGLE_TABLES_MAX = size_t(4) << 30;
+int rdesc_tables(RSlice& S, size_t* held, size_t cap) {
     if (S.dir != 0 && S.dir != 1 && S.dir != 3) return DLT_OK;
     RDesc& d = *S.d;
     const size_t v = (size_t)d.nb * (size_t)S.Ng;
     const bool inv = S.dir == 1;
     const size_t need = v * (sizeof(int) + sizeof(double) * (inv ? 2 : 1));
-    if (*held + need > RTABLE_MAX) return DLT_OK;
+    if (*held + need > cap) return DLT_OK;
     *held += need;
     if (hipMalloc(&d.gk, v * sizeof(int)) != hipSuccess || hipMalloc(&d.dg, v * sizeof(double)) != hipSuccess ||
         (inv && hipMalloc(&d.wg, v * sizeof(double)) != hipSuccess))
@@ -569,10 +571,11 @@ int rdesc_tables(RSlice& S, size_t* held) {
 }
 
 // Splits instances idx (one direction, one grid) into slices whose
-// workspace fits WS_CAP; builds their descriptors (and node tables, adding
-// their bytes to *tab).
+// workspace fits WS_CAP; builds their descriptors (and node tables while
+// *tab, to which their bytes are added, stays within tab_cap).
 int rslices_build(int dir, int64_t Ng, int prec, const int64_t* Ns, const int64_t* offs,
-                  const std::vector<int64_t>& idx, std::vector<RSlice>& out, size_t* ws_max, size_t* tab) {
+                  const std::vector<int64_t>& idx, std::vector<RSlice>& out, size_t* ws_max, size_t* tab,
+                  size_t tab_cap) {
     Plan* p;
     int rc;
     if ((rc = get_plan(Ng, prec, &p))) return rc;
@@ -587,7 +590,7 @@ int rslices_build(int dir, int64_t Ng, int prec, const int64_t* Ns, const int64_
         S.Q = ragged_Q(prec, Ns, part, Ng);
         S.d.reset(new RDesc());
         if ((rc = rdesc_build(Ns, offs, part, *S.d))) return rc;
-        if ((rc = rdesc_tables(S, tab))) return rc;
+        if ((rc = rdesc_tables(S, tab, tab_cap))) return rc;
         *ws_max = std::max(*ws_max, rslice_bytes(*p, (int64_t)part.size()));
         out.push_back(std::move(S));
     }
@@ -631,8 +634,16 @@ int single_entry(int64_t N, int64_t batch, int dir, int prec, SingleEntry** out)
             offs[b] = b * N;
             idx[b] = b;
         }
+        size_t cap = 0;  // what the cached equal-size batches leave of their table bound
+        {
+            Cache& c = cache();
+            std::lock_guard<std::mutex> lk(c.mu);
+            size_t used = 0;
+            for (auto& kv : c.single) used += kv.second->tab_bytes;
+            if (used < SINGLE_TABLES_MAX) cap = std::min(RTABLE_MAX, SINGLE_TABLES_MAX - used);
+        }
         if ((rc = rslices_build(dir, next_pow2(N), prec, Ns.data(), offs.data(), idx, e->slices, &e->ws_bytes,
-                                &e->tab_bytes)))
+                                &e->tab_bytes, cap)))
             return rc;
         Cache& c = cache();
         std::lock_guard<std::mutex> lk(c.mu);
@@ -710,7 +721,7 @@ int tune_grid(int dir, int64_t P, int prec, const int64_t* Ns, const int64_t* of
     for (int64_t cand = P; cand <= 2 * P && rc == DLT_OK; cand *= 2) {
         std::vector<RSlice> sl;
         size_t wmax = 0, tab = 0;
-        if ((rc = rslices_build(dir, cand, prec, sN.data(), so.data(), sidx, sl, &wmax, &tab))) break;
+        if ((rc = rslices_build(dir, cand, prec, sN.data(), so.data(), sidx, sl, &wmax, &tab, RTABLE_MAX))) break;
         void* ws = nullptr;
         if ((rc = get_ws(s, wmax, &ws))) break;
         float ms = 0;
@@ -839,7 +850,7 @@ int dlt_batch_ex(int64_t count, const int64_t* Ns, const int64_t* offsets, const
             if ((rc = tune_grid(kv.first.first, kv.first.second, prec, Ns, offsets, kv.second, in, stream, &Ng)))
                 return rc;
             if ((rc = rslices_build(kv.first.first, Ng, prec, Ns, offsets, kv.second, e->slices, &wmax,
-                                    &e->tab_bytes)))
+                                    &e->tab_bytes, RTABLE_MAX)))
                 return rc;
         }
         {
