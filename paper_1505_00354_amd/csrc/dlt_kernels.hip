@@ -1532,6 +1532,27 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
     } else {
         // pairs Q-1..1 in precision R, pair 0 FP64 (nx)
         if constexpr (LB > 0) {
+            // The Horner steps of the pairs in R run in R into a partial sum
+            // accr, widened once before pair 0 (its rounding, relative to a
+            // partial sum that pair 0 weights by at most 0.84^2/2, is that of
+            // the R terms themselves).
+            R accr[FFT_VPT], dr[FFT_VPT], sg[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) {
+                const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
+                accr[s] = 0;
+                dr[s] = (R)d[s];
+                sg[s] = (2 * m >= N) ? (R)-1 : (R)1;
+            }
+            auto horner_r = [&](int q, const cplxT<R>* U) {
+                const R sc = (q & 1) ? (R)-1 : (R)1;
+                const R r1 = (R)1 / (R)(2 * q + 1), r2 = (R)1 / (R)(2 * q + 2);
+#pragma unroll
+                for (int s = 0; s < FFT_VPT; ++s) {
+                    const R inner = fmaf(dr[s] * r2, accr[s], -sc * sg[s] * U[s].im);
+                    accr[s] = fmaf(dr[s] * r1, inner, sc * U[s].re);
+                }
+            };
             // two prefetch buffers taken in turn: nxr holds pairs Q-1, Q-3,
             // ..., nyr pairs Q-2, Q-4, ... (pair 0 goes to nx)
             cplxT<R> nyr[FFT_VPT] = {};
@@ -1539,25 +1560,22 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
             else if (Q == 2) passB_load<LB, double>(g, jb0, X0b, nx, T);
             for (int q = Q - 1; q >= 1; q -= 2) {
                 cplxT<R> z[FFT_VPT];
-                cplx U[FFT_VPT];
 #pragma unroll
                 for (int s = 0; s < FFT_VPT; ++s) z[s] = nxr[s];
                 if (q > 2) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 3) * N, nxr, T);
                 else if (q == 2) passB_load<LB, double>(g, jb0, X0b, nx, T);
                 tile_fft<LB>(z, bufr, twr, T);
-#pragma unroll
-                for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
-                horner(q, U);
+                horner_r(q, z);
                 if (q == 1) break;
 #pragma unroll
                 for (int s = 0; s < FFT_VPT; ++s) z[s] = nyr[s];
                 if (q > 3) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 4) * N, nyr, T);
                 else if (q == 3) passB_load<LB, double>(g, jb0, X0b, nx, T);
                 tile_fft<LB>(z, bufr, twr, T);
-#pragma unroll
-                for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
-                horner(q - 1, U);
+                horner_r(q - 1, z);
             }
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) acc[s] = (double)accr[s];
         } else {
             // run-time length (short transforms): one prefetch buffer (nxr)
             for (int q = Q - 1; q >= 1; --q) {
