@@ -1448,7 +1448,7 @@ __global__ FFT_BOUNDS_R(R, LA) void k_ndct_passA(Geo g, int qa, int qb, int QG, 
 // (slab q - 1, precision R), pair 0 from X0 (FP64); the next pair's tile is
 // loaded while the current one is transformed.
 template <int LB, class R>
-__global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X0, int64_t x0_stride,
+__global__ FFT_BOUNDS_R(R, LB) void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X0, int64_t x0_stride,
                                         const cplxT<R>* __restrict__ X1, int64_t x1_stride,
                                         const double* __restrict__ dth, double* __restrict__ f, int64_t f_stride,
                                         RaggedRows RR) {
@@ -1469,6 +1469,84 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
     const int b = blockIdx.z;
     const cplx* X0b = X0 + b * x0_stride;
     const cplxT<R>* X1b = X1 + b * x1_stride;
+    if constexpr (sizeof(R) < sizeof(double) && LB > 0) {
+        // Pairs Q-1..1 in R from two prefetch buffers taken in turn (nxr
+        // holds pairs Q-1, Q-3, ..., nyr pairs Q-2, Q-4, ...); their Horner
+        // steps run in R into a partial sum accr, widened once before pair 0
+        // (its rounding, relative to a partial sum that pair 0 weights by at
+        // most 0.84^2/2, is that of the R terms themselves).  Pair 0 (FP64)
+        // and its node offsets in FP64 are read only after the loop, so the
+        // loop's registers fit three waves per SIMD.
+        cplxT<R> nxr[FFT_VPT] = {}, nyr[FFT_VPT] = {};
+        if (Q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(Q - 2) * N, nxr, T);
+        if (Q > 2) passB_load<LB, R>(g, jb0, X1b + (int64_t)(Q - 3) * N, nyr, T);
+        R accr[FFT_VPT], dr[FFT_VPT], sg[FFT_VPT];
+        int kn[FFT_VPT];  // output index: grid row, or the node paired with it (-1: none)
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
+            const int r = row_of(m, N);
+            double dd;
+            if (RR.gk) {
+                kn[s] = RR.gk[(int64_t)b * N + r];
+                dd = (kn[s] >= 0) ? RR.dg[(int64_t)b * N + r] : 0.0;
+            } else {
+                kn[s] = r;
+                dd = (double)N * dth[r];
+            }
+            accr[s] = 0;
+            dr[s] = (R)dd;
+            sg[s] = (2 * m >= N) ? (R)-1 : (R)1;
+        }
+        auto horner_r = [&](int q, const cplxT<R>* U) {
+            const R sc = (q & 1) ? (R)-1 : (R)1;
+            const R r1 = (R)1 / (R)(2 * q + 1), r2 = (R)1 / (R)(2 * q + 2);
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) {
+                const R inner = fmaf(dr[s] * r2, accr[s], -sc * sg[s] * U[s].im);
+                accr[s] = fmaf(dr[s] * r1, inner, sc * U[s].re);
+            }
+        };
+        for (int q = Q - 1; q >= 1; q -= 2) {
+            cplxT<R> z[FFT_VPT];
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) z[s] = nxr[s];
+            if (q > 2) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 3) * N, nxr, T);
+            tile_fft<LB>(z, bufr, twr, T);
+            horner_r(q, z);
+            if (q == 1) break;
+#pragma unroll
+            for (int s = 0; s < FFT_VPT; ++s) z[s] = nyr[s];
+            if (q > 3) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 4) * N, nyr, T);
+            tile_fft<LB>(z, bufr, twr, T);
+            horner_r(q - 1, z);
+        }
+        // pair 0 in FP64
+        cplx z0[FFT_VPT];
+        passB_load<LB, double>(g, jb0, X0b, z0, T);
+        double acc[FFT_VPT], d[FFT_VPT];
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
+            const int r = row_of(m, N);
+            acc[s] = (double)accr[s];
+            if (RR.gk) d[s] = (kn[s] >= 0) ? RR.dg[(int64_t)b * N + r] : 0.0;
+            else d[s] = (double)N * dth[r];
+        }
+        tile_fft<LB>(z0, bufd, twd, T);
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s) {
+            const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
+            const double Fs = (2 * m >= N) ? -z0[s].im : z0[s].im;
+            const double inner = fma(d[s] * 0.5, acc[s], -Fs);
+            acc[s] = fma(d[s], inner, z0[s].re);
+        }
+        double* fb = RR.gk ? f + RR.offs[b] : f + b * f_stride;
+#pragma unroll
+        for (int s = 0; s < FFT_VPT; ++s)
+            if (kn[s] >= 0) fb[kn[s]] = acc[s];
+        return;
+    }
     double acc[FFT_VPT], d[FFT_VPT];
     int kn[FFT_VPT];  // output index: grid row, or the node paired with it (-1: none)
     // the first tile's loads go out before the node offsets' (loads retire
@@ -1530,66 +1608,19 @@ __global__ FFT_BOUNDS void k_ndct_passB(Geo g, int Q, const cplx* __restrict__ X
             horner(q - 1, z);
         }
     } else {
-        // pairs Q-1..1 in precision R, pair 0 FP64 (nx)
-        if constexpr (LB > 0) {
-            // The Horner steps of the pairs in R run in R into a partial sum
-            // accr, widened once before pair 0 (its rounding, relative to a
-            // partial sum that pair 0 weights by at most 0.84^2/2, is that of
-            // the R terms themselves).
-            R accr[FFT_VPT], dr[FFT_VPT], sg[FFT_VPT];
+        // pairs Q-1..1 in precision R (run-time length: one prefetch buffer,
+        // nxr), pair 0 FP64 (nx)
+        for (int q = Q - 1; q >= 1; --q) {
+            cplxT<R> z[FFT_VPT];
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) {
-                const int m = jb0 + T.col(s) + g.N2 * T.idx(s);
-                accr[s] = 0;
-                dr[s] = (R)d[s];
-                sg[s] = (2 * m >= N) ? (R)-1 : (R)1;
-            }
-            auto horner_r = [&](int q, const cplxT<R>* U) {
-                const R sc = (q & 1) ? (R)-1 : (R)1;
-                const R r1 = (R)1 / (R)(2 * q + 1), r2 = (R)1 / (R)(2 * q + 2);
+            for (int s = 0; s < FFT_VPT; ++s) z[s] = nxr[s];
+            if (q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 2) * N, nxr, T);
+            else passB_load<LB, double>(g, jb0, X0b, nx, T);
+            tile_fft<LB>(z, bufr, twr, T);
+            cplx U[FFT_VPT];
 #pragma unroll
-                for (int s = 0; s < FFT_VPT; ++s) {
-                    const R inner = fmaf(dr[s] * r2, accr[s], -sc * sg[s] * U[s].im);
-                    accr[s] = fmaf(dr[s] * r1, inner, sc * U[s].re);
-                }
-            };
-            // two prefetch buffers taken in turn: nxr holds pairs Q-1, Q-3,
-            // ..., nyr pairs Q-2, Q-4, ... (pair 0 goes to nx)
-            cplxT<R> nyr[FFT_VPT] = {};
-            if (Q > 2) passB_load<LB, R>(g, jb0, X1b + (int64_t)(Q - 3) * N, nyr, T);
-            else if (Q == 2) passB_load<LB, double>(g, jb0, X0b, nx, T);
-            for (int q = Q - 1; q >= 1; q -= 2) {
-                cplxT<R> z[FFT_VPT];
-#pragma unroll
-                for (int s = 0; s < FFT_VPT; ++s) z[s] = nxr[s];
-                if (q > 2) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 3) * N, nxr, T);
-                else if (q == 2) passB_load<LB, double>(g, jb0, X0b, nx, T);
-                tile_fft<LB>(z, bufr, twr, T);
-                horner_r(q, z);
-                if (q == 1) break;
-#pragma unroll
-                for (int s = 0; s < FFT_VPT; ++s) z[s] = nyr[s];
-                if (q > 3) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 4) * N, nyr, T);
-                else if (q == 3) passB_load<LB, double>(g, jb0, X0b, nx, T);
-                tile_fft<LB>(z, bufr, twr, T);
-                horner_r(q - 1, z);
-            }
-#pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) acc[s] = (double)accr[s];
-        } else {
-            // run-time length (short transforms): one prefetch buffer (nxr)
-            for (int q = Q - 1; q >= 1; --q) {
-                cplxT<R> z[FFT_VPT];
-#pragma unroll
-                for (int s = 0; s < FFT_VPT; ++s) z[s] = nxr[s];
-                if (q > 1) passB_load<LB, R>(g, jb0, X1b + (int64_t)(q - 2) * N, nxr, T);
-                else passB_load<LB, double>(g, jb0, X0b, nx, T);
-                tile_fft<LB>(z, bufr, twr, T);
-                cplx U[FFT_VPT];
-#pragma unroll
-                for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
-                horner(q, U);
-            }
+            for (int s = 0; s < FFT_VPT; ++s) U[s] = cwide(z[s]);
+            horner(q, U);
         }
         tile_fft<LB>(nx, bufd, twd, T);
         horner(0, nx);
