@@ -894,7 +894,7 @@ struct FarTerms {
 // goes through pass A of the length-N DFT.  Term group blockIdx.y takes the
 // terms nterm-1-y, nterm-1-y-G, ...
 template <int LA, class R>
-__global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __restrict__ amp,
+__global__ FFT_BOUNDS_R(R, LA) void k_far_passA(Geo g, FarParams F, int G, const cplx* __restrict__ amp,
                                                           const double* __restrict__ c, int64_t c_stride,
                                                           cplxT<R>* __restrict__ X, int64_t x_stride) {
     // FP32 tiles are transformed in pairs of terms (two tiles); FP64 tiles
@@ -912,7 +912,11 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __
     const double* cb = c + b * c_stride;
     cplxT<R>* Xb = X + b * x_stride;
     const PassAOut<LA, false> out(g, T, na0);
-    cplx bh[FFT_VPT];  // C_n h_{m,n} c_n e^{i pi n/(2N)} at the current m
+    // C_n h_{m,n} c_n e^{i pi n/(2N)} at the current m, carried in the
+    // precision of the terms (FP32 terms: its FP32 rounding per step is that
+    // of the terms themselves)
+    using BT = typename std::conditional<PAIRS, R, double>::type;
+    cplxT<BT> bh[FFT_VPT];
     int nn[FFT_VPT];
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
@@ -921,7 +925,7 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __
         if (T.live(s)) {
             const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             nn[s] = n;
-            if (n >= F.nd) bh[s] = cscale(amp[n], cb[n]);
+            if (n >= F.nd) bh[s] = cto<BT>(cscale(amp[n], cb[n]));
         }
     }
     int mcur = F.Mmax - 1;
@@ -931,11 +935,14 @@ __global__ FFT_BOUNDS void k_far_passA(Geo g, FarParams F, int G, const cplx* __
         for (; mcur > m; --mcur) {
             const double fm = (double)mcur / ((mcur - 0.5) * (mcur - 0.5));
 #pragma unroll
-            for (int s = 0; s < FFT_VPT; ++s) bh[s] = cscale(bh[s], fm * (nn[s] + mcur + 0.5));
+            for (int s = 0; s < FFT_VPT; ++s) bh[s] = cscale(bh[s], (BT)(fm * (nn[s] + mcur + 0.5)));
         }
         const int nlo = FT.nlo(t);
 #pragma unroll
-        for (int s = 0; s < FFT_VPT; ++s) v[s] = (nn[s] >= nlo) ? cto<R>(bh[s]) : cplxT<R>{0, 0};
+        for (int s = 0; s < FFT_VPT; ++s) {
+            if constexpr (PAIRS) v[s] = (nn[s] >= nlo) ? bh[s] : cplxT<R>{0, 0};
+            else v[s] = (nn[s] >= nlo) ? cto<R>(bh[s]) : cplxT<R>{0, 0};
+        }
     };
     // terms in pairs (t, t - G): two tiles per barrier sequence
     int t = F.nterm - 1 - (int)blockIdx.y;
