@@ -1450,6 +1450,44 @@ __global__ FFT_BOUNDS_R(R, LA) void k_ndct_passA(Geo g, int qa, int qb, int QG, 
     held.flush();
 }
 
+// The first Taylor pair alone, in FP64, for the FP32-bulk mode (whose other
+// pairs are FP32 and go through k_ndct_passA<LA, float>): the input of pass A
+// at q = 0, one transform, the stores at once.  Without the carried powers
+// and the held stores of the multi-pair pass its registers fit three waves
+// per SIMD.  Same values as k_ndct_passA<LA, double> over [0, 1).
+template <int LA>
+__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(LA > 0 ? 3 : FFT_WAVES)))
+void k_ndct_pair0(Geo g, const double* __restrict__ chat, int64_t chat_stride, cplx* __restrict__ X,
+                  int64_t x_stride) {
+    __shared__ cplx buf[TILE_LDS(LA)];
+    STAGE_TW(stw, LA, double);
+    const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
+    const Tile<LA> T(g.colsA, g.N2);
+    const int N = g.N;
+    const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int b = blockIdx.z;
+    const double* cb = chat + b * chat_stride;
+    const PassAOut<LA, false> out(g, T, na0);
+    const double invN = 1.0 / N;
+    cplx v[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        v[s] = {0, 0};
+        if (T.live(s)) {
+            const int n = na0 + T.col(s) + g.N1 * T.idx(s);
+            if (n == 0) {
+                v[s] = {cb[0], 0};
+            } else {
+                const double x = n * invN;
+                const cplx e2 = cscale(half_shift_tab(g, n), 0.5);
+                v[s] = cadd(cscale(e2, (1.0 + x) * cb[n]), cscale(cmuli(e2), -x * cb[N - n]));
+            }
+        }
+    }
+    tile_fft<LA>(v, buf, twA, T);
+    out.put(g, v, X + b * x_stride, T);
+}
+
 // f_k = sum_l s_l d_k^l/l! F_l[k], s_l = (-1)^floor((l+1)/2), d_k = N dtheta_k,
 // by Horner from the highest pair down, in FP64.  Pairs q >= 1 come from X1
 // (slab q - 1, precision R), pair 0 from X0 (FP64); the next pair's tile is
@@ -1932,6 +1970,46 @@ __global__ FFT_BOUNDS_R(R, LA) void k_tndct_passA(Geo g, int qa, int qb, int QG,
         held.hold(v, Xb + (int64_t)(q - qa) * N);
     }
     held.flush();
+}
+
+// The first transposed Taylor pair alone, in FP64, for the FP32-bulk mode
+// (as k_ndct_pair0 for the forward evaluation): the input of the transposed
+// pass A at q = 0, one transform, the stores at once.  Same values as
+// k_tndct_passA<LA, double> over [0, 1).
+template <int LA>
+__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(LA > 0 ? 3 : FFT_WAVES)))
+void k_tndct_pair0(Geo g, const double* __restrict__ fv, int64_t f_stride, const double* __restrict__ wts,
+                   const double* __restrict__ dth, cplx* __restrict__ X, int64_t x_stride, RaggedRows RR) {
+    __shared__ cplx buf[TILE_LDS(LA)];
+    STAGE_TW(stw, LA, double);
+    const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
+    const Tile<LA> T(g.colsA, g.N2);
+    const int N = g.N;
+    const int na0 = xcd_tile_mirror(blockIdx.x, gridDim.x) * T.cols();
+    const int b = blockIdx.z;
+    const double* fb = fv + b * f_stride;
+    const PassAOut<LA, true> out(g, T, na0);
+    cplx v[FFT_VPT];
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) {
+        v[s] = {0, 0};
+        if (T.live(s)) {
+            const int m = na0 + T.col(s) + g.N1 * T.idx(s);
+            const int r = row_of(m, N);
+            double d, p;
+            if (RR.gk) {
+                const int kk = RR.gk[(int64_t)b * N + r];
+                d = (kk >= 0) ? RR.dg[(int64_t)b * N + r] : 0.0;
+                p = (kk >= 0) ? RR.wg[(int64_t)b * N + r] * fv[RR.offs[b] + kk] : 0.0;
+            } else {
+                d = (double)N * dth[r];
+                p = wts[r] * fb[r];
+            }
+            v[s] = cplx{p, p * ((2 * m < N) ? d : -d)};  // g_k, g_k sigma_m d_k
+        }
+    }
+    tile_fft<LA>(v, buf, twA, T);
+    out.put(g, v, X + b * x_stride, T);
 }
 
 // y_n = sum_l s_l (n/N)^l / l! Z_l[n]; Z_{2q} = Re(e_n A_n), Z_{2q+1} = Im(e_n B_n),
@@ -3059,7 +3137,7 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
         const hipStream_t s0 = L.aux(0);
         DLT_TRY(dep(s, s0, L.ev[10]));
         traced("k_ndct_passA", s0, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_ndct_passA, double, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s0, g, 0, 1, 1, chat, hs, w.X, w.sX);
+            LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_ndct_pair0, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s0, g, chat, hs, w.X, w.sX);
         });
         if (Q > 1)
             traced("k_ndct_passA_f32", s, [&] {
@@ -3142,7 +3220,7 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
         const int64_t s1 = 2 * w.sX;
         const int QG = (tilesA * nb >= 256) ? 1 : std::max(Q - 1, 1);
         traced("k_tndct_passA", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, 1, 1, f, N, wts, dth, w.X, w.sX, RR);
+            LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_tndct_pair0, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, f, N, wts, dth, w.X, w.sX, RR);
         });
         if (Q > 1)
             traced("k_tndct_passA_f32", s, [&] {
