@@ -1450,21 +1450,24 @@ __global__ FFT_BOUNDS_R(R, LA) void k_ndct_passA(Geo g, int qa, int qb, int QG, 
     held.flush();
 }
 
-// The first Taylor pair alone, in FP64, for the FP32-bulk mode (whose other
-// pairs are FP32 and go through k_ndct_passA<LA, float>): the input of pass A
-// at q = 0, one transform, the stores at once.  Without the carried powers
-// and the held stores of the multi-pair pass its registers fit three waves
-// per SIMD.  Same values as k_ndct_passA<LA, double> over [0, 1).
+// One Taylor pair per block, in FP64: pair q = qa + blockIdx.y into slab
+// blockIdx.y of X.  Used where every group of the pairs holds one pair (small
+// transforms, and the FP64 first pair of the FP32-bulk mode, whose other pairs
+// go through k_ndct_passA<LA, float>): the input of pass A for pair q, one
+// transform, the stores at once.  Without the carried powers and the held
+// stores of the multi-pair pass its registers fit three or four waves per
+// SIMD.  Same values as k_ndct_passA<LA, double> with one pair per group.
 template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(LA > 0 ? 3 : FFT_WAVES)))
-void k_ndct_pair0(Geo g, const double* __restrict__ chat, int64_t chat_stride, cplx* __restrict__ X,
-                  int64_t x_stride) {
+void k_ndct_pair(Geo g, int qa, const double* __restrict__ chat, int64_t chat_stride, cplx* __restrict__ X,
+                 int64_t x_stride) {
     __shared__ cplx buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, double);
     const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
     const int na0 = xcd_tile(blockIdx.x, gridDim.x) * T.cols();
+    const int q = qa + (int)blockIdx.y;
     const int b = blockIdx.z;
     const double* cb = chat + b * chat_stride;
     const PassAOut<LA, false> out(g, T, na0);
@@ -1476,16 +1479,21 @@ void k_ndct_pair0(Geo g, const double* __restrict__ chat, int64_t chat_stride, c
         if (T.live(s)) {
             const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             if (n == 0) {
-                v[s] = {cb[0], 0};
+                if (q == 0) v[s] = {cb[0], 0};
             } else {
-                const double x = n * invN;
+                const double x = n * invN, y = (N - n) * invN;
+                double a = 1, bb = 1;  // x^{2q}, y^{2q}
+                for (int k = 0; k < q; ++k) {
+                    a *= x * x;
+                    bb *= y * y;
+                }
                 const cplx e2 = cscale(half_shift_tab(g, n), 0.5);
-                v[s] = cadd(cscale(e2, (1.0 + x) * cb[n]), cscale(cmuli(e2), -x * cb[N - n]));
+                v[s] = cadd(cscale(e2, (1.0 + x) * cb[n] * a), cscale(cmuli(e2), -x * cb[N - n] * bb));
             }
         }
     }
     tile_fft<LA>(v, buf, twA, T);
-    out.put(g, v, X + b * x_stride, T);
+    out.put(g, v, X + b * x_stride + (int64_t)blockIdx.y * N, T);
 }
 
 // f_k = sum_l s_l d_k^l/l! F_l[k], s_l = (-1)^floor((l+1)/2), d_k = N dtheta_k,
@@ -1972,20 +1980,20 @@ __global__ FFT_BOUNDS_R(R, LA) void k_tndct_passA(Geo g, int qa, int qb, int QG,
     held.flush();
 }
 
-// The first transposed Taylor pair alone, in FP64, for the FP32-bulk mode
-// (as k_ndct_pair0 for the forward evaluation): the input of the transposed
-// pass A at q = 0, one transform, the stores at once.  Same values as
-// k_tndct_passA<LA, double> over [0, 1).
+// One transposed Taylor pair per block, in FP64 (as k_ndct_pair for the
+// forward evaluation): pair q = qa + blockIdx.y into slab blockIdx.y of X.
+// Same values as k_tndct_passA<LA, double> with one pair per group.
 template <int LA>
 __global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(LA > 0 ? 3 : FFT_WAVES)))
-void k_tndct_pair0(Geo g, const double* __restrict__ fv, int64_t f_stride, const double* __restrict__ wts,
-                   const double* __restrict__ dth, cplx* __restrict__ X, int64_t x_stride, RaggedRows RR) {
+void k_tndct_pair(Geo g, int qa, const double* __restrict__ fv, int64_t f_stride, const double* __restrict__ wts,
+                  const double* __restrict__ dth, cplx* __restrict__ X, int64_t x_stride, RaggedRows RR) {
     __shared__ cplx buf[TILE_LDS(LA)];
     STAGE_TW(stw, LA, double);
     const cplx* twA = stage_twiddles<LA, double>(stw, g.twN2, g.N2);
     const Tile<LA> T(g.colsA, g.N2);
     const int N = g.N;
     const int na0 = xcd_tile_mirror(blockIdx.x, gridDim.x) * T.cols();
+    const int q = qa + (int)blockIdx.y;
     const int b = blockIdx.z;
     const double* fb = fv + b * f_stride;
     const PassAOut<LA, true> out(g, T, na0);
@@ -2005,11 +2013,12 @@ void k_tndct_pair0(Geo g, const double* __restrict__ fv, int64_t f_stride, const
                 d = (double)N * dth[r];
                 p = wts[r] * fb[r];
             }
-            v[s] = cplx{p, p * ((2 * m < N) ? d : -d)};  // g_k, g_k sigma_m d_k
+            for (int k = 0; k < q; ++k) p *= d * d;     // g_k d_k^{2q}
+            v[s] = cplx{p, p * ((2 * m < N) ? d : -d)};  // and times sigma_m d_k
         }
     }
     tile_fft<LA>(v, buf, twA, T);
-    out.put(g, v, X + b * x_stride, T);
+    out.put(g, v, X + b * x_stride + (int64_t)blockIdx.y * N, T);
 }
 
 // y_n = sum_l s_l (n/N)^l / l! Z_l[n]; Z_{2q} = Re(e_n A_n), Z_{2q+1} = Im(e_n B_n),
@@ -3137,7 +3146,7 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
         const hipStream_t s0 = L.aux(0);
         DLT_TRY(dep(s, s0, L.ev[10]));
         traced("k_ndct_passA", s0, [&] {
-            LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_ndct_pair0, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s0, g, chat, hs, w.X, w.sX);
+            LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_ndct_pair, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s0, g, 0, chat, hs, w.X, w.sX);
         });
         if (Q > 1)
             traced("k_ndct_passA_f32", s, [&] {
@@ -3150,7 +3159,10 @@ hipError_t run_ndct(const Plan& p, int64_t nb, const double* chat, int64_t hs, c
     } else {
         const int QG = pass_a_groups(tilesA * nb, Q);
         traced("k_ndct_passA", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_ndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, chat, hs, w.X, w.sX);
+            if (QG == Q)  // one pair per group
+                LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_ndct_pair, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, chat, hs, w.X, w.sX);
+            else
+                LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_ndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, chat, hs, w.X, w.sX);
         });
         traced("k_ndct_passB", s, [&] {
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_ndct_passB, double, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, w.X + N, w.sX, dth, f, p.N, RR);
@@ -3220,7 +3232,7 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
         const int64_t s1 = 2 * w.sX;
         const int QG = (tilesA * nb >= 256) ? 1 : std::max(Q - 1, 1);
         traced("k_tndct_passA", s, [&] {
-            LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_tndct_pair0, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, f, N, wts, dth, w.X, w.sX, RR);
+            LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_tndct_pair, (dim3(tilesA, 1, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, f, N, wts, dth, w.X, w.sX, RR);
         });
         if (Q > 1)
             traced("k_tndct_passA_f32", s, [&] {
@@ -3232,7 +3244,10 @@ hipError_t run_inverse(const Plan& p, int64_t nb, const double* f, const double*
     } else {
         const int QG = pass_a_groups(tilesA * nb, Q);
         traced("k_tndct_passA", s, [&] {
-            LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, f, N, wts, dth, w.X, w.sX, RR);
+            if (QG == Q)  // one pair per group
+                LEN_LAUNCH(g.N >= FFT_CAP, g.N2, k_tndct_pair, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, f, N, wts, dth, w.X, w.sX, RR);
+            else
+                LEN_LAUNCH_R(g.N >= FFT_CAP, g.N2, k_tndct_passA, double, (dim3(tilesA, QG, (unsigned)nb)), FFT_THREADS, 0, s, g, 0, Q, QG, f, N, wts, dth, w.X, w.sX, RR);
         });
         traced("k_tndct_passB", s, [&] {
             LEN_LAUNCH_R(g.N >= FFT_CAP, g.N1, k_tndct_passB, double, gB, FFT_THREADS, 0, s, g, Q, w.X, w.sX, w.X + N, w.sX, y, w.schat);
