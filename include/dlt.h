@@ -102,9 +102,11 @@ int dlt_inverse(int64_t N, int64_t batch, const double* f, double* c, hipStream_
  * batch instance), same convention as leg_nodes_weights's dtheta.
  * Precondition: |N dtheta_k| <= pi/2 for every k; the Taylor length (L = 20)
  * is chosen for that bound, so the error is at most 5e-14 ||chat||_1 as for
- * cheb_eval_leggrid; larger offsets are not detected and give larger
- * errors.  N must be a power of two (DLT_ERR_UNSUPPORTED otherwise); dtheta
- * must not overlap f.  Calls are never captured into a graph. */
+ * cheb_eval_leggrid.  An output f_k whose offset exceeds the bound
+ * (|N dtheta_k| > (pi/2)(1 + 1e-12)) is NaN; the call still returns DLT_OK
+ * (the offsets are device data, read only by the kernels).  N must be a
+ * power of two (DLT_ERR_UNSUPPORTED otherwise); dtheta must not overlap f.
+ * Calls are never captured into a graph. */
 int cheb_eval_nodes(int64_t N, int64_t batch, const double* chat, const double* dtheta, double* f,
                     hipStream_t stream);
 

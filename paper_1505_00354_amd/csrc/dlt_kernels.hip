@@ -1496,6 +1496,12 @@ void k_ndct_pair(Geo g, int qa, const double* __restrict__ chat, int64_t chat_st
     out.put(g, v, X + b * x_stride + (int64_t)blockIdx.y * N, T);
 }
 
+// Largest |d_k| = |N dtheta_k| the Taylor lengths are chosen for (pi/2, with
+// room for rounding): outputs at points beyond it are NaN instead of values
+// with an error above the stated bound (caller-given offsets of
+// cheb_eval_nodes; the Legendre nodes and the ragged pairing stay within it).
+constexpr double TAYLOR_D_MAX = 1.5707963267948966 * (1.0 + 1e-12);
+
 // f_k = sum_l s_l d_k^l/l! F_l[k], s_l = (-1)^floor((l+1)/2), d_k = N dtheta_k,
 // by Horner from the highest pair down, in FP64.  Pairs q >= 1 come from X1
 // (slab q - 1, precision R), pair 0 from X0 (FP64); the next pair's tile is
@@ -1597,7 +1603,7 @@ __global__ FFT_BOUNDS_R(R, LB) void k_ndct_passB(Geo g, int Q, const cplx* __res
         double* fb = RR.gk ? f + RR.offs[b] : f + b * f_stride;
 #pragma unroll
         for (int s = 0; s < FFT_VPT; ++s)
-            if (kn[s] >= 0) fb[kn[s]] = acc[s];
+            if (kn[s] >= 0) fb[kn[s]] = (fabs(d[s]) <= TAYLOR_D_MAX) ? acc[s] : __builtin_nan("");
         return;
     }
     double acc[FFT_VPT], d[FFT_VPT];
@@ -1681,7 +1687,7 @@ __global__ FFT_BOUNDS_R(R, LB) void k_ndct_passB(Geo g, int Q, const cplx* __res
     double* fb = RR.gk ? f + RR.offs[b] : f + b * f_stride;
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s)
-        if (kn[s] >= 0) fb[kn[s]] = acc[s];
+        if (kn[s] >= 0) fb[kn[s]] = (fabs(d[s]) <= TAYLOR_D_MAX) ? acc[s] : __builtin_nan("");
 }
 
 

@@ -68,3 +68,24 @@ def test_cheb_eval_nodes_legendre_matches(pk):
     a = to_host(pk.cheb_eval_nodes(chat, d[0]))
     b = to_host(pk.cheb_eval_leggrid(chat))
     assert np.max(np.abs(a - b)) / np.sum(np.abs(to_host(chat))) <= 1e-15
+
+
+def test_cheb_eval_nodes_offsets_beyond_bound(pk, orc):
+    # offsets with |N dtheta_k| > pi/2 (outside the precondition the Taylor
+    # length is chosen for) give NaN at exactly those outputs; the other
+    # outputs keep the bar, and offsets at the bound itself are accepted
+    N = 1024
+    d = offsets("random", N)
+    bad = np.array([0, 5, 300, 511, 512, N - 1])
+    d[bad] = np.where(np.arange(bad.size) % 2 == 0, 1, -1) * 0.6 * np.pi / N
+    d[7] = 0.5 * np.pi / N  # the bound itself
+    chat = wl.coeffs_algebraic(N, 54)[0]
+    f = to_host(pk.cheb_eval_nodes(to_dev(chat), to_dev(d)))
+    say("beyond bound: NaN at", np.flatnonzero(np.isnan(f)))
+    assert np.array_equal(np.flatnonzero(np.isnan(f)), bad)
+    good = np.setdiff1d(np.arange(N), bad)
+    hi, lo = exact_angles(N, d, good)
+    ref = orc.ndct(chat, hi, prec="l", theta_lo=lo)
+    err = dlt_err(f[good], ref, chat)
+    say("  err at the other points", err)
+    assert err <= TOL
