@@ -33,6 +33,28 @@ __device__ __forceinline__ cplx half_shift(int64_t n, int N) {
 __device__ __forceinline__ cplx half_shift_tab(const Geo& g, int n) {
     return cmul(tw2(g.twHi, g.twLo, n >> 2, g.sh), g.qs[n & 3]);
 }
+// e^{i pi s/16}, s = 0..7: in a tile of compile-time length L the thread's
+// elements are n0 + s N/8 (pass A: n = n_a + N1 (i0 + s L/8) with L = N2,
+// N1 L = N; pass B: n = j_b + N2 (i0 + s L/8) with L = N1), so
+// e^{i pi n/(2N)} = e^{i pi n0/(2N)} e^{i pi s/16}
+__device__ constexpr cplx HALF_SHIFT_STEP[8] = {
+    {1.0, 0.0},
+    {0.9807852804032304, 0.19509032201612825},
+    {0.9238795325112867, 0.3826834323650898},
+    {0.8314696123025452, 0.5555702330196022},
+    {0.7071067811865476, 0.7071067811865475},
+    {0.5555702330196023, 0.8314696123025452},
+    {0.38268343236508984, 0.9238795325112867},
+    {0.19509032201612833, 0.9807852804032304}
+};
+// e^{i pi n/(2N)} of the elements n0 + s N/8, s = 0..7 (a thread's elements
+// in a tile of compile-time length, in either pass): one table value times
+// the constants above
+__device__ __forceinline__ void half_shift_eighths(const Geo& g, int n0, cplx* e) {
+    const cplx e0 = half_shift_tab(g, n0);
+#pragma unroll
+    for (int s = 0; s < FFT_VPT; ++s) e[s] = (s == 0) ? e0 : cmul(e0, HALF_SHIFT_STEP[s]);
+}
 
 // ------------------------------------------------------------------ nodes --
 // Interior nodes k in [kb, ceil(N/2)): Newton in delta = theta - theta*_k
@@ -1344,6 +1366,8 @@ __global__ FFT_BOUNDS void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ 
     const int b = blockIdx.z;
     cplx z[FFT_VPT];
     passB_load<LB, double>(g, jb0, X + b * x_stride, z, T);
+    cplx eh[FFT_VPT];  // e^{i pi n/(2N)} of the thread's elements
+    if constexpr (LB > 0) half_shift_eighths(g, jb0 + T.col(0) + g.N2 * T.idx(0), eh);
     tile_fft<LB>(z, buf, twB, T);
     const double* db = dense + b * dense_stride;
     double* cb = chat + b * chat_stride;
@@ -1351,7 +1375,7 @@ __global__ FFT_BOUNDS void k_dct2_passB(Geo g, int nd, const cplx* __restrict__ 
     for (int s = 0; s < FFT_VPT; ++s) {
         if (T.live(s)) {
             const int n = jb0 + T.col(s) + g.N2 * T.idx(s);
-            const cplx t = half_shift_tab(g, n);
+            const cplx t = (LB > 0) ? eh[s] : half_shift_tab(g, n);
             double val = (t.re * z[s].re - t.im * z[s].im) * ((n == 0) ? 1.0 : 2.0) / N;
             if (n < nd) val += db[n];
             cb[n] = val;
@@ -1387,6 +1411,8 @@ __global__ FFT_BOUNDS_R(R, LA) void k_ndct_passA(Geo g, int qa, int qb, int QG, 
     // Ap = A x^{2q} and Bp = B y^{2q} are carried from pair to pair
     cplx Ap[FFT_VPT], Bp[FFT_VPT];
     const int q0 = qa + ((qb - qa) * grp) / QG, q1 = qa + ((qb - qa) * (grp + 1)) / QG;
+    cplx eh[FFT_VPT];  // e^{i pi n/(2N)} of the thread's elements
+    if constexpr (LA > 0) half_shift_eighths(g, na0 + T.col(0) + g.N1 * T.idx(0), eh);
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         Ap[s] = Bp[s] = {0, 0};
@@ -1396,7 +1422,7 @@ __global__ FFT_BOUNDS_R(R, LA) void k_ndct_passA(Geo g, int qa, int qb, int QG, 
                 if (q0 == 0) Ap[s] = {cb[0], 0};
             } else {
                 const double x = n * invN, y = (N - n) * invN;
-                const cplx e2 = cscale(half_shift_tab(g, n), 0.5);
+                const cplx e2 = cscale((LA > 0) ? eh[s] : half_shift_tab(g, n), 0.5);
                 double a = 1, bb = 1;
                 for (int q = 0; q < q0; ++q) {
                     a *= x * x;
@@ -1472,6 +1498,8 @@ void k_ndct_pair(Geo g, int qa, const double* __restrict__ chat, int64_t chat_st
     const double* cb = chat + b * chat_stride;
     const PassAOut<LA, false> out(g, T, na0);
     const double invN = 1.0 / N;
+    cplx eh[FFT_VPT];  // e^{i pi n/(2N)} of the thread's elements
+    if constexpr (LA > 0) half_shift_eighths(g, na0 + T.col(0) + g.N1 * T.idx(0), eh);
     cplx v[FFT_VPT];
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
@@ -1487,7 +1515,7 @@ void k_ndct_pair(Geo g, int qa, const double* __restrict__ chat, int64_t chat_st
                     a *= x * x;
                     bb *= y * y;
                 }
-                const cplx e2 = cscale(half_shift_tab(g, n), 0.5);
+                const cplx e2 = cscale((LA > 0) ? eh[s] : half_shift_tab(g, n), 0.5);
                 v[s] = cadd(cscale(e2, (1.0 + x) * cb[n] * a), cscale(cmuli(e2), -x * cb[N - n] * bb));
             }
         }
@@ -2060,18 +2088,19 @@ __global__ FFT_BOUNDS void k_tndct_passB(Geo g, int Q, const cplx* __restrict__ 
     double acc[FFT_VPT], xs[FFT_VPT];
     cplx en[FFT_VPT];
     int part[FFT_VPT];
+    if constexpr (LB > 0) half_shift_eighths(g, actual_row(vb0 + T.col(0), N2) + N2 * T.idx(0), en);
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         acc[s] = 0;
         xs[s] = 0;
-        en[s] = {0, 0};
+        if constexpr (LB == 0) en[s] = {0, 0};
         part[s] = 0;
         if (T.live(s)) {
             const int i = T.col(s), ja = T.idx(s);
             const int r = actual_row(vb0 + i, N2);
             const int n = r + N2 * ja;
             xs[s] = (double)n / N;
-            en[s] = half_shift_tab(g, n);
+            if constexpr (LB == 0) en[s] = half_shift_tab(g, n);
             int ip, jp;
             if (r == 0) {
                 ip = i;
@@ -2266,13 +2295,15 @@ __global__ FFT_BOUNDS void k_dct3_passA(Geo g, const double* __restrict__ y, int
     const int b = blockIdx.z;
     const double* yb = y + b * y_stride;
     const PassAOut<LA, false> out(g, T, na0);
+    cplx eh[FFT_VPT];  // e^{i pi n/(2N)} of the thread's elements
+    if constexpr (LA > 0) half_shift_eighths(g, na0 + T.col(0) + g.N1 * T.idx(0), eh);
     cplx x[FFT_VPT];
 #pragma unroll
     for (int s = 0; s < FFT_VPT; ++s) {
         if (T.live(s)) {
             const int n = na0 + T.col(s) + g.N1 * T.idx(s);
             const double a = yb[n] * ((n == 0) ? 1.0 : 2.0) / N;
-            x[s] = cscale(half_shift_tab(g, n), a);
+            x[s] = cscale((LA > 0) ? eh[s] : half_shift_tab(g, n), a);
         }
     }
     tile_fft<LA>(x, buf, twA, T);
