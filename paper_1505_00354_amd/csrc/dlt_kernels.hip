@@ -683,8 +683,8 @@ __global__ __launch_bounds__(256) void k_dense_mm(int nd, const double* __restri
 #define FFT_BOUNDS __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(FFT_WAVES)))
 // the same for a kernel whose FP32 tiles (half the LDS) of compile-time
 // length L fit the registers of three waves per SIMD without spilling (the
-// FP32 Taylor passes A and the FP32 transposed far-field pass A; the FP32
-// far-field pass A spills under it)
+// FP32 passes A of the far field and of the Taylor terms, both directions,
+// and the FP32 Taylor pass B)
 #define FFT_BOUNDS_R(R, L) \
     __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && (L) > 0) ? 3 : FFT_WAVES)))
 // Intermediate layout between the passes ("blocked"): DFT output (n_a, j_b)
